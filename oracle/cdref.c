@@ -1,0 +1,1030 @@
+/* cdref.c - FP64 CPU oracle of the Contact Dynamics contact-force solve.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  Written to be
+ * read against the paper (Shojaaee et al., Sec. 2-3): plain loops, no
+ * blocking, no fusion, every step in the paper's order.  Built with
+ * -O2 -ffp-contract=off so that every floating-point operation is the IEEE
+ * operation written here.
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *  - the gap entering the force law is max(g, 0) unless overlap_mode = 1
+ *    (initial overlaps are not pushed apart in one step);
+ *  - the order inside a domain is a greedy colouring in canonical order
+ *    (instead of a random order), which is an exact sequential order;
+ *  - |R| is the Euclidean norm of the contact force and R_avg the mean of
+ *    |R| over all listed contacts; a relative test with 0/0 passes;
+ *  - bisection cuts are placed by contact count at the k-th smallest
+ *    contact position, k = floor(n L_left / (L_left + L_right)), with the
+ *    cut axis along the longest side of the node's region.
+ */
+#include "cdref.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* small vector helpers (component order fixed: 0, 1, 2)               */
+/* ------------------------------------------------------------------ */
+
+/* Tangent basis (t1, t2) of a unit normal in 3D, right-handed with
+ * t1 x t2 = n.  Construction of Duff et al., "Building an orthonormal
+ * basis, revisited", JCGT 6(1), 2017.  In 2D the tangent is t = z x n. */
+static void tangent_basis3(const double n[3], double t1[3], double t2[3]) {
+  double sign = copysign(1.0, n[2]);
+  double a = -1.0 / (sign + n[2]);
+  double b = n[0] * n[1] * a;
+  t1[0] = 1.0 + sign * n[0] * n[0] * a;
+  t1[1] = sign * b;
+  t1[2] = -sign * n[0];
+  t2[0] = b;
+  t2[1] = sign + n[1] * n[1] * a;
+  t2[2] = -n[1];
+}
+
+static void contact_frame(int dim, const double* normal, int64_t nc, int64_t c,
+                          double n[3], double t1[3], double t2[3]) {
+  for (int k = 0; k < 3; ++k) n[k] = t1[k] = t2[k] = 0.0;
+  for (int k = 0; k < dim; ++k) n[k] = normal[k * nc + c];
+  if (dim == 2) {
+    t1[0] = -n[1];
+    t1[1] = n[0];
+    t2[2] = 1.0;
+  } else {
+    tangent_basis3(n, t1, t2);
+  }
+}
+
+/* gap between particle i and body j (particle or wall), Sec. 2.1 / Fig. 1 */
+static double pair_gap(int dim, int64_t n, const double* x, const double* r,
+                       const double* wall_normal, const double* wall_offset,
+                       int64_t i, int64_t j, double nrm[3]) {
+  if (j < n) {
+    double delta[3] = {0, 0, 0};
+    double d2 = 0.0;
+    for (int k = 0; k < dim; ++k) {
+      delta[k] = x[k * n + j] - x[k * n + i];
+      d2 = d2 + delta[k] * delta[k];
+    }
+    double dist = sqrt(d2);
+    if (nrm) for (int k = 0; k < dim; ++k) nrm[k] = delta[k] / dist;
+    return (dist - r[i]) - r[j];
+  } else {
+    int64_t w = j - n;
+    double proj = 0.0;
+    for (int k = 0; k < dim; ++k) proj = proj + wall_normal[w * dim + k] * x[k * n + i];
+    if (nrm) for (int k = 0; k < dim; ++k) nrm[k] = -wall_normal[w * dim + k];
+    return (proj - wall_offset[w]) - r[i];
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* contact detection (Sec. 3.1 boundary width, Sec. 3.2 cell method)   */
+/* ------------------------------------------------------------------ */
+
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+int cdref_detect(int dim, int64_t n, const double* x, const double* r,
+                 int n_walls, const double* wall_normal, const double* wall_offset,
+                 double skin, int use_cells, const double* box_lo, const double* box_hi,
+                 int64_t cap, int32_t* ci, int32_t* cj, int64_t* nc) {
+  int64_t count = 0;
+  if (dim != 2 && dim != 3) return CDREF_EINVAL;
+  if (!use_cells) {
+    for (int64_t i = 0; i < n; ++i) {
+      for (int64_t j = i + 1; j < n; ++j) {
+        if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, j, NULL) <= skin) {
+          if (count < cap) { ci[count] = (int32_t)i; cj[count] = (int32_t)j; }
+          ++count;
+        }
+      }
+      for (int w = 0; w < n_walls; ++w) {
+        if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, n + w, NULL) <= skin) {
+          if (count < cap) { ci[count] = (int32_t)i; cj[count] = (int32_t)(n + w); }
+          ++count;
+        }
+      }
+    }
+    *nc = count;
+    return count > cap ? CDREF_ECAPACITY : CDREF_OK;
+  }
+  /* cell method: mesh >= 2.2 r_max and >= the largest possible centre distance */
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) if (r[i] > rmax) rmax = r[i];
+  double a = 2.2 * rmax;
+  if (2.0 * rmax + skin > a) a = 2.0 * rmax + skin;
+  int64_t ncell[3] = {1, 1, 1};
+  double width[3] = {1, 1, 1};
+  for (int k = 0; k < dim; ++k) {
+    double len = box_hi[k] - box_lo[k];
+    int64_t m = (int64_t)floor(len / a);
+    if (m < 1) m = 1;
+    if (m > 4096) m = 4096;
+    ncell[k] = m;
+    width[k] = len / (double)m;
+  }
+  int64_t total = ncell[0] * ncell[1] * ncell[2];
+  int64_t* cell = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* start = (int64_t*)calloc((size_t)(total + 1), sizeof(int64_t));
+  int64_t* members = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(total + 1));
+  int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!cell || !start || !members || !fill || !cand) {
+    free(cell); free(start); free(members); free(fill); free(cand);
+    return CDREF_ENOMEM;
+  }
+  int64_t ic[3];
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < 3; ++k) ic[k] = 0;
+    for (int k = 0; k < dim; ++k) {
+      double q = floor((x[k * n + i] - box_lo[k]) / width[k]);
+      int64_t m = q < 0.0 ? 0 : (q > (double)(ncell[k] - 1) ? ncell[k] - 1 : (int64_t)q);
+      ic[k] = m;
+    }
+    cell[i] = (ic[2] * ncell[1] + ic[1]) * ncell[0] + ic[0];
+    start[cell[i] + 1] += 1;
+  }
+  for (int64_t c = 0; c < total; ++c) start[c + 1] += start[c];
+  memcpy(fill, start, sizeof(int64_t) * (size_t)(total + 1));
+  for (int64_t i = 0; i < n; ++i) members[fill[cell[i]]++] = i;
+
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t c = cell[i];
+    int64_t cx = c % ncell[0], cy = (c / ncell[0]) % ncell[1], cz = c / (ncell[0] * ncell[1]);
+    int ncand = 0;
+    for (int64_t dz = -1; dz <= 1; ++dz) {
+      for (int64_t dy = -1; dy <= 1; ++dy) {
+        for (int64_t dx = -1; dx <= 1; ++dx) {
+          int64_t qx = cx + dx, qy = cy + dy, qz = cz + dz;
+          if (qx < 0 || qy < 0 || qz < 0 || qx >= ncell[0] || qy >= ncell[1] || qz >= ncell[2])
+            continue;
+          int64_t q = (qz * ncell[1] + qy) * ncell[0] + qx;
+          for (int64_t s = start[q]; s < start[q + 1]; ++s) {
+            int64_t j = members[s];
+            if (j <= i) continue;
+            if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, j, NULL) <= skin)
+              cand[ncand++] = (int32_t)j;
+          }
+        }
+      }
+    }
+    qsort(cand, (size_t)ncand, sizeof(int32_t), cmp_i32);
+    for (int s = 0; s < ncand; ++s) {
+      if (count < cap) { ci[count] = (int32_t)i; cj[count] = cand[s]; }
+      ++count;
+    }
+    for (int w = 0; w < n_walls; ++w) {
+      if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, n + w, NULL) <= skin) {
+        if (count < cap) { ci[count] = (int32_t)i; cj[count] = (int32_t)(n + w); }
+        ++count;
+      }
+    }
+  }
+  free(cell); free(start); free(members); free(fill); free(cand);
+  *nc = count;
+  return count > cap ? CDREF_ECAPACITY : CDREF_OK;
+}
+
+void cdref_geometry(int dim, int64_t n, const double* x, const double* r,
+                    int n_walls, const double* wall_normal, const double* wall_offset,
+                    int64_t nc, const int32_t* ci, const int32_t* cj,
+                    double* normal, double* gap, double* xmid) {
+  (void)n_walls;
+  for (int64_t c = 0; c < nc; ++c) {
+    double nrm[3];
+    int64_t i = ci[c], j = cj[c];
+    double g = pair_gap(dim, n, x, r, wall_normal, wall_offset, i, j, nrm);
+    gap[c] = g;
+    double lever = r[i] + 0.5 * g;   /* middle of the gap, Sec. 3.1 */
+    for (int k = 0; k < dim; ++k) {
+      normal[k * nc + c] = nrm[k];
+      xmid[k * nc + c] = x[k * n + i] + lever * nrm[k];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* hierarchical domain tree (Sec. 3.2, Fig. 8)                          */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  int count;
+  int32_t* child;   /* 2 per node */
+  int32_t* leaf;    /* domain id or -1 */
+  int32_t* leaves;  /* leaf count below the node */
+} tree_shape;
+
+static int tree_shape_build(int P, tree_shape* t) {
+  int total = 2 * P - 1;
+  t->count = total;
+  t->child = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)total);
+  t->leaf = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  t->leaves = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  if (!t->child || !t->leaf || !t->leaves) return CDREF_ENOMEM;
+  for (int k = 0; k < 2 * total; ++k) t->child[k] = -1;
+  /* level by level: branch every node of a level until 2^l < P <= 2^(l+1),
+     then branch only the first P - 2^l nodes of level l, left to right */
+  int created = 1;
+  int level_begin = 0, level_size = 1;
+  if (P > 1) {
+    int l = 0;
+    while ((1 << (l + 1)) < P) ++l;      /* now 2^l < P <= 2^(l+1) */
+    for (int m = 0; m < l; ++m) {
+      for (int q = 0; q < level_size; ++q) {
+        int node = level_begin + q;
+        t->child[2 * node] = created++;
+        t->child[2 * node + 1] = created++;
+      }
+      level_begin += level_size;
+      level_size *= 2;
+    }
+    int extra = P - (1 << l);
+    for (int q = 0; q < extra; ++q) {
+      int node = level_begin + q;
+      t->child[2 * node] = created++;
+      t->child[2 * node + 1] = created++;
+    }
+  }
+  if (created != total) return CDREF_EINVAL;
+  /* leaves numbered left to right by a depth-first walk */
+  int* stack = (int*)malloc(sizeof(int) * (size_t)total);
+  int* post = (int*)malloc(sizeof(int) * (size_t)total);
+  if (!stack || !post) { free(stack); free(post); return CDREF_ENOMEM; }
+  int sp = 0, next_leaf = 0, npost = 0;
+  stack[sp++] = 0;
+  while (sp > 0) {
+    int node = stack[--sp];
+    post[npost++] = node;
+    if (t->child[2 * node] < 0) {
+      t->leaf[node] = next_leaf++;
+    } else {
+      t->leaf[node] = -1;
+      stack[sp++] = t->child[2 * node + 1];   /* right pushed first: left visited first */
+      stack[sp++] = t->child[2 * node];
+    }
+  }
+  /* leaf counts: children are always created after their parent */
+  for (int node = total - 1; node >= 0; --node) {
+    if (t->child[2 * node] < 0) t->leaves[node] = 1;
+    else t->leaves[node] = t->leaves[t->child[2 * node]] + t->leaves[t->child[2 * node + 1]];
+  }
+  free(stack); free(post);
+  return CDREF_OK;
+}
+
+static void tree_shape_free(tree_shape* t) {
+  free(t->child); free(t->leaf); free(t->leaves);
+}
+
+int cdref_tree_leaves(int P, int32_t* node_leaves) {
+  if (P < 1) return CDREF_EINVAL;
+  tree_shape t;
+  int st = tree_shape_build(P, &t);
+  if (st == CDREF_OK) memcpy(node_leaves, t.leaves, sizeof(int32_t) * (size_t)t.count);
+  tree_shape_free(&t);
+  return st;
+}
+
+static int cmp_f64(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+/* split `node` owning contacts ids[0..cnt) in region [lo, hi] */
+static void orb_split(int dim, const tree_shape* t, int node, const double* lo,
+                      const double* hi, int64_t nc, const double* xmid, int32_t* ids,
+                      int64_t cnt, int32_t* node_axis, double* node_cut, int32_t* dom,
+                      double* scratch, int32_t* tmp_ids) {
+  if (t->child[2 * node] < 0) {
+    node_axis[node] = -1;
+    node_cut[node] = 0.0;
+    for (int64_t s = 0; s < cnt; ++s) dom[ids[s]] = t->leaf[node];
+    return;
+  }
+  /* cut perpendicular to the longest side (shortest interface), ties to x,y,z */
+  int axis = 0;
+  double best = hi[0] - lo[0];
+  for (int k = 1; k < dim; ++k) {
+    if (hi[k] - lo[k] > best) { best = hi[k] - lo[k]; axis = k; }
+  }
+  int left = t->child[2 * node], right = t->child[2 * node + 1];
+  int64_t ll = t->leaves[left], lr = t->leaves[right];
+  double cut;
+  if (cnt > 0) {
+    for (int64_t s = 0; s < cnt; ++s) scratch[s] = xmid[(int64_t)axis * nc + ids[s]];
+    qsort(scratch, (size_t)cnt, sizeof(double), cmp_f64);
+    int64_t k = (cnt * ll) / (ll + lr);   /* share of contacts ~ share of leaves */
+    cut = scratch[k];
+  } else {
+    cut = 0.5 * (lo[axis] + hi[axis]);
+  }
+  node_axis[node] = axis;
+  node_cut[node] = cut;
+  /* stable partition: coordinate < cut goes left, ties go right */
+  int64_t nl = 0, nr = 0;
+  for (int64_t s = 0; s < cnt; ++s) {
+    if (xmid[(int64_t)axis * nc + ids[s]] < cut) ids[nl++] = ids[s];
+    else tmp_ids[nr++] = ids[s];
+  }
+  memcpy(ids + nl, tmp_ids, sizeof(int32_t) * (size_t)nr);
+  double llo[3], lhi[3], rlo[3], rhi[3];
+  for (int k = 0; k < dim; ++k) { llo[k] = rlo[k] = lo[k]; lhi[k] = rhi[k] = hi[k]; }
+  lhi[axis] = cut;
+  rlo[axis] = cut;
+  orb_split(dim, t, left, llo, lhi, nc, xmid, ids, nl, node_axis, node_cut, dom, scratch, tmp_ids);
+  orb_split(dim, t, right, rlo, rhi, nc, xmid, ids + nl, nr, node_axis, node_cut, dom, scratch,
+            tmp_ids);
+}
+
+int cdref_orb(int dim, int P, const double* box_lo, const double* box_hi,
+              int64_t nc, const double* xmid,
+              int32_t* node_axis, double* node_cut, int32_t* node_child,
+              int32_t* node_leaf, int32_t* node_leaves, int32_t* dom) {
+  if (P < 1 || (dim != 2 && dim != 3)) return CDREF_EINVAL;
+  tree_shape t;
+  int st = tree_shape_build(P, &t);
+  if (st != CDREF_OK) { tree_shape_free(&t); return st; }
+  int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+  int32_t* tmp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+  double* scratch = (double*)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+  if (!ids || !tmp || !scratch) {
+    free(ids); free(tmp); free(scratch); tree_shape_free(&t);
+    return CDREF_ENOMEM;
+  }
+  for (int64_t c = 0; c < nc; ++c) ids[c] = (int32_t)c;
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int k = 0; k < dim; ++k) { lo[k] = box_lo[k]; hi[k] = box_hi[k]; }
+  orb_split(dim, &t, 0, lo, hi, nc, xmid, ids, nc, node_axis, node_cut, dom, scratch, tmp);
+  memcpy(node_child, t.child, sizeof(int32_t) * 2 * (size_t)t.count);
+  memcpy(node_leaf, t.leaf, sizeof(int32_t) * (size_t)t.count);
+  if (node_leaves) memcpy(node_leaves, t.leaves, sizeof(int32_t) * (size_t)t.count);
+  free(ids); free(tmp); free(scratch); tree_shape_free(&t);
+  return CDREF_OK;
+}
+
+void cdref_descend(int dim, int P, const int32_t* node_axis, const double* node_cut,
+                   const int32_t* node_child, const int32_t* node_leaf,
+                   int64_t nc, const double* xmid, int32_t* dom) {
+  (void)dim; (void)P;
+  for (int64_t c = 0; c < nc; ++c) {
+    int node = 0;
+    while (node_leaf[node] < 0) {
+      int axis = node_axis[node];
+      node = xmid[(int64_t)axis * nc + c] < node_cut[node] ? node_child[2 * node]
+                                                            : node_child[2 * node + 1];
+    }
+    dom[c] = node_leaf[node];
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* update order inside a domain                                         */
+/* ------------------------------------------------------------------ */
+
+#define CDREF_MAX_COLORS 256
+
+int cdref_order(int64_t n, int64_t nc, const int32_t* ci, const int32_t* cj,
+                int P, const int32_t* dom, int32_t* color, int32_t* slot_contact,
+                int64_t* dom_start) {
+  const int words = CDREF_MAX_COLORS / 64;
+  uint64_t* used = (uint64_t*)calloc((size_t)(n > 0 ? n : 1) * words, sizeof(uint64_t));
+  int64_t* count = (int64_t*)calloc((size_t)P + 1, sizeof(int64_t));
+  int64_t* members_start = (int64_t*)calloc((size_t)P + 1, sizeof(int64_t));
+  int32_t* members = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+  if (!used || !count || !members_start || !members) {
+    free(used); free(count); free(members_start); free(members);
+    return CDREF_ENOMEM;
+  }
+  /* contacts of each domain in canonical order */
+  for (int64_t c = 0; c < nc; ++c) members_start[dom[c] + 1] += 1;
+  for (int d = 0; d < P; ++d) members_start[d + 1] += members_start[d];
+  for (int d = 0; d <= P; ++d) count[d] = members_start[d];
+  for (int64_t c = 0; c < nc; ++c) members[count[dom[c]]++] = (int32_t)c;
+
+  int status = CDREF_OK;
+  int64_t slot = 0;
+  for (int d = 0; d < P; ++d) {
+    dom_start[d] = slot;
+    int maxcol = -1;
+    /* greedy first-fit colouring in canonical order */
+    for (int64_t s = members_start[d]; s < members_start[d + 1]; ++s) {
+      int32_t c = members[s];
+      int64_t a = ci[c], b = cj[c];
+      int k = 0;
+      for (; k < CDREF_MAX_COLORS; ++k) {
+        uint64_t bit = 1ull << (k % 64);
+        int in_a = (used[a * words + k / 64] & bit) != 0;
+        int in_b = b < n ? (used[b * words + k / 64] & bit) != 0 : 0;
+        if (!in_a && !in_b) break;
+      }
+      if (k == CDREF_MAX_COLORS) { status = CDREF_ECAPACITY; k = CDREF_MAX_COLORS - 1; }
+      color[c] = k;
+      used[a * words + k / 64] |= 1ull << (k % 64);
+      if (b < n) used[b * words + k / 64] |= 1ull << (k % 64);
+      if (k > maxcol) maxcol = k;
+    }
+    /* order by (colour, canonical id) */
+    for (int k = 0; k <= maxcol; ++k)
+      for (int64_t s = members_start[d]; s < members_start[d + 1]; ++s)
+        if (color[members[s]] == k) slot_contact[slot++] = members[s];
+    /* clear the colour sets of this domain's particles */
+    for (int64_t s = members_start[d]; s < members_start[d + 1]; ++s) {
+      int32_t c = members[s];
+      for (int w = 0; w < words; ++w) {
+        used[(int64_t)ci[c] * words + w] = 0;
+        if (cj[c] < n) used[(int64_t)cj[c] * words + w] = 0;
+      }
+    }
+  }
+  dom_start[P] = slot;
+  free(used); free(count); free(members_start); free(members);
+  return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* velocities from forces: Eq. (1) and its rotational analogue          */
+/* ------------------------------------------------------------------ */
+
+/* V = v + dt/m (F + sum of contact forces), W = w + dt/I (T + sum of torques),
+ * the sums taken over the particle's contacts in ascending contact id. */
+void cdref_velocities(int dim, int64_t n, double dt, const double* v, const double* w,
+                      const double* m, const double* inertia, const double* r,
+                      const double* f, const double* t, int64_t nc,
+                      const int32_t* ci, const int32_t* cj, const double* normal,
+                      const double* R, double* V, double* W) {
+  int dr = dim == 2 ? 1 : 3;
+  double* acc = (double*)malloc(sizeof(double) * (size_t)(dim * (n > 0 ? n : 1)));
+  double* tacc = (double*)malloc(sizeof(double) * (size_t)(dr * (n > 0 ? n : 1)));
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < dim; ++k) acc[k * n + i] = f[k * n + i];
+    for (int k = 0; k < dr; ++k) tacc[k * n + i] = t[k * n + i];
+  }
+  for (int64_t c = 0; c < nc; ++c) {
+    double nv[3], t1[3], t2[3];
+    contact_frame(dim, normal, nc, c, nv, t1, t2);
+    double rn = R[c], rt1 = R[nc + c], rt2 = dim == 3 ? R[2 * nc + c] : 0.0;
+    double force[3], q[3];
+    for (int k = 0; k < dim; ++k) {
+      force[k] = rn * nv[k] + rt1 * t1[k];
+      if (dim == 3) force[k] = force[k] + rt2 * t2[k];
+    }
+    /* n x R: the torque of the force about a lever along n, per unit lever */
+    if (dim == 2) {
+      q[0] = rt1;
+    } else {
+      for (int k = 0; k < 3; ++k) q[k] = rt1 * t2[k] - rt2 * t1[k];
+    }
+    int64_t a = ci[c], b = cj[c];
+    /* body 1 receives -R at lever r_a n; body 2 receives R at lever -r_b n;
+       both torques are -r (n x R) */
+    for (int k = 0; k < dim; ++k) acc[k * n + a] = acc[k * n + a] - force[k];
+    for (int k = 0; k < dr; ++k) tacc[k * n + a] = tacc[k * n + a] - r[a] * q[k];
+    if (b < n) {
+      for (int k = 0; k < dim; ++k) acc[k * n + b] = acc[k * n + b] + force[k];
+      for (int k = 0; k < dr; ++k) tacc[k * n + b] = tacc[k * n + b] - r[b] * q[k];
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    double dtim = dt * (1.0 / m[i]);
+    double dtii = dt * (1.0 / inertia[i]);
+    for (int k = 0; k < dim; ++k) V[k * n + i] = v[k * n + i] + dtim * acc[k * n + i];
+    for (int k = 0; k < dr; ++k) W[k * n + i] = w[k * n + i] + dtii * tacc[k * n + i];
+  }
+  free(acc); free(tacc);
+}
+
+/* ------------------------------------------------------------------ */
+/* single-contact force law: Sec. 2.1, Eqs. (3)-(9), Fig. 2             */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  double gdt;        /* g_e / dt */
+  double dwn, dwt;   /* dt w_n, dt w_t : M^-1 = w_n nn + w_t (1 - nn) */
+  double kn, kt;     /* 1/(dt w_n), 1/(dt w_t) */
+  double mu;
+} contact_consts;
+
+/* Given the velocities of both bodies (with every current force applied,
+ * including this contact's own R), return the new force R' in the contact
+ * frame.  Rold and Rnew: (R_n, R_t1[, R_t2]). */
+static void local_force(int dim, const double n[3], const double t1[3], const double t2[3],
+                        const contact_consts* k, double ra, double rb,
+                        const double Va[3], const double Wa[3], const double Vb[3],
+                        const double Wb[3], const double Rold[3], double Rnew[3]) {
+  double dV[3] = {0, 0, 0};
+  for (int q = 0; q < dim; ++q) dV[q] = Vb[q] - Va[q];
+  double vn = 0.0, vt1 = 0.0, vt2 = 0.0;
+  for (int q = 0; q < dim; ++q) vn = vn + dV[q] * n[q];
+  if (dim == 2) {
+    /* relative velocity of the contact points projected on t = z x n */
+    double dvt = dV[0] * t1[0] + dV[1] * t1[1];
+    double spin = ra * Wa[0] + rb * Wb[0];
+    vt1 = dvt - spin;
+  } else {
+    double spin[3];
+    for (int q = 0; q < 3; ++q) spin[q] = ra * Wa[q] + rb * Wb[q];
+    double dvt1 = 0.0, dvt2 = 0.0, s2 = 0.0, s1 = 0.0;
+    for (int q = 0; q < 3; ++q) {
+      dvt1 = dvt1 + dV[q] * t1[q];
+      dvt2 = dvt2 + dV[q] * t2[q];
+      s2 = s2 + spin[q] * t2[q];
+      s1 = s1 + spin[q] * t1[q];
+    }
+    vt1 = dvt1 - s2;
+    vt2 = dvt2 + s1;
+  }
+  /* hypothetical relative velocity without this contact's force (R = 0) */
+  double un = vn - k->dwn * Rold[0];
+  double ut1 = vt1 - k->dwt * Rold[1];
+  double ut2 = dim == 3 ? vt2 - k->dwt * Rold[2] : 0.0;
+  /* predicted gap g + dt u_n (Eq. 3), divided by dt */
+  double s = k->gdt + un;
+  Rnew[0] = Rnew[1] = Rnew[2] = 0.0;
+  if (s >= 0.0) return;                 /* contact stays open: R = 0 */
+  /* sticking force from g(t+dt) = 0 and v_t(t+dt) = 0 (Eqs. 4-5) */
+  double rn = -s * k->kn;
+  double T1 = -ut1 * k->kt;
+  double T2 = dim == 3 ? -ut2 * k->kt : 0.0;
+  double lim = k->mu * rn;              /* Coulomb bound (Eq. 7) */
+  Rnew[0] = rn;
+  if (dim == 2) {
+    if (fabs(T1) <= lim) Rnew[1] = T1;
+    else Rnew[1] = T1 > 0.0 ? lim : -lim;   /* sliding (Eqs. 8-9) */
+  } else {
+    double tn = sqrt(T1 * T1 + T2 * T2);
+    if (tn <= lim) {
+      Rnew[1] = T1;
+      Rnew[2] = T2;
+    } else {
+      /* sliding: R_t = -mu R_n v_t/|v_t|; with M diagonal in the contact
+         frame the slip is parallel to the sticking force (Eqs. 8-9) */
+      double fac = lim / tn;
+      Rnew[1] = T1 * fac;
+      Rnew[2] = T2 * fac;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* convergence tests (I) and (II), Sec. 2.1                             */
+/* ------------------------------------------------------------------ */
+
+int cdref_criterion(int dim, int64_t nc, const double* Rprev, const double* R, double ravg_prev,
+                    double alpha, int criterion, int64_t* n_pass, double* max_d_fail,
+                    double* r_avg, int* finite) {
+  int64_t npass = 0;
+  double maxd = 0.0, sum = 0.0;
+  int any_fail = 0, ok = 1;
+  for (int64_t c = 0; c < nc; ++c) {
+    double d2 = 0.0, s2 = 0.0, q = 0.0;
+    for (int k = 0; k < dim; ++k) {
+      double a1 = R[k * nc + c], a0 = Rprev[k * nc + c];
+      d2 = d2 + (a1 - a0) * (a1 - a0);
+      s2 = s2 + (a1 + a0) * (a1 + a0);
+      q = q + a1 * a1;
+    }
+    if (!isfinite(q)) ok = 0;
+    sum = sum + sqrt(q);
+    /* relative change (R^j - R^j-1)^2 / (R^j + R^j-1)^2 < alpha; 0/0 passes */
+    if (d2 < alpha * s2 || d2 == 0.0) {
+      ++npass;
+    } else {
+      if (!any_fail || d2 > maxd) maxd = d2;
+      any_fail = 1;
+    }
+  }
+  double ravg = nc > 0 ? sum / (double)nc : 0.0;
+  int conv;
+  if (criterion == 0) {
+    /* (I): at least 90% pass the relative test and every other contact has
+       (R^j - R^j-1)^2 < alpha R_avg^(j-1)^2 */
+    conv = (10 * npass >= 9 * nc) && (!any_fail || maxd < alpha * (ravg_prev * ravg_prev));
+  } else {
+    /* (II): relative change of the average force */
+    double dd = (ravg - ravg_prev) * (ravg - ravg_prev);
+    double ss = (ravg + ravg_prev) * (ravg + ravg_prev);
+    conv = dd < alpha * ss || dd == 0.0;
+  }
+  if (n_pass) *n_pass = npass;
+  if (max_d_fail) *max_d_fail = maxd;
+  if (r_avg) *r_avg = ravg;
+  if (finite) *finite = ok;
+  return conv;
+}
+
+/* ------------------------------------------------------------------ */
+/* iterative solve with domain-wise sweeps (Sec. 2.1, Sec. 3.1)         */
+/* ------------------------------------------------------------------ */
+
+int cdref_solve(const cdref_params* p, int64_t n, const double* v, const double* w,
+                const double* r, const double* m, const double* inertia,
+                const double* f, const double* t, const double* wall_velocity,
+                int64_t nc, const int32_t* ci, const int32_t* cj,
+                const double* normal, const double* gap, const double* mu_c,
+                int P, const int64_t* dom_start, const int32_t* slot_contact,
+                double* R, cdref_info* info, double* history) {
+  int dim = p->dim, dr = dim == 2 ? 1 : 3;
+  int64_t nn = n > 0 ? n : 1, ncc = nc > 0 ? nc : 1;
+  memset(info, 0, sizeof(*info));
+  info->n_contacts = nc;
+  if (nc == 0) return CDREF_OK;
+  double dt = p->dt;
+  contact_consts* cc = (contact_consts*)malloc(sizeof(contact_consts) * (size_t)ncc);
+  double* Rprev = (double*)malloc(sizeof(double) * (size_t)(dim * ncc));
+  double* Vg = (double*)malloc(sizeof(double) * (size_t)(dim * nn));
+  double* Wg = (double*)malloc(sizeof(double) * (size_t)(dr * nn));
+  double* Vd = (double*)malloc(sizeof(double) * (size_t)(dim * nn));
+  double* Wd = (double*)malloc(sizeof(double) * (size_t)(dr * nn));
+  double* dtim = (double*)malloc(sizeof(double) * (size_t)nn);
+  double* dtii = (double*)malloc(sizeof(double) * (size_t)nn);
+  if (!cc || !Rprev || !Vg || !Wg || !Vd || !Wd || !dtim || !dtii) {
+    free(cc); free(Rprev); free(Vg); free(Wg); free(Vd); free(Wd); free(dtim); free(dtii);
+    return CDREF_ENOMEM;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    dtim[i] = dt * (1.0 / m[i]);
+    dtii[i] = dt * (1.0 / inertia[i]);
+  }
+  /* per-contact constants of this step: the pair's inverse mass matrix in
+     the contact frame (Eq. 5) and the (clamped) gap */
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t a = ci[c], b = cj[c];
+    double wn = 1.0 / m[a] + (b < n ? 1.0 / m[b] : 0.0);
+    double wt = wn + (r[a] * r[a]) * (1.0 / inertia[a]);
+    wt = wt + (b < n ? (r[b] * r[b]) * (1.0 / inertia[b]) : 0.0);
+    double ge = gap[c];
+    if (p->overlap_mode == 0 && ge < 0.0) ge = 0.0;
+    cc[c].gdt = ge / dt;
+    cc[c].dwn = dt * wn;
+    cc[c].dwt = dt * wt;
+    cc[c].kn = 1.0 / cc[c].dwn;
+    cc[c].kt = 1.0 / cc[c].dwt;
+    cc[c].mu = mu_c ? mu_c[c] : p->mu;
+  }
+  int limit = p->fixed_iters > 0 ? p->fixed_iters : p->max_iter;
+  double alpha = p->alpha;
+  /* R_avg of the starting forces */
+  double sum = 0.0;
+  for (int64_t c = 0; c < nc; ++c) {
+    double q = 0.0;
+    for (int k = 0; k < dim; ++k) q = q + R[k * nc + c] * R[k * nc + c];
+    sum = sum + sqrt(q);
+  }
+  double ravg_prev = sum / (double)nc;
+  int status = CDREF_MAXITER;
+  int j = 0;
+  while (j < limit) {
+    ++j;
+    memcpy(Rprev, R, sizeof(double) * (size_t)(dim * nc));
+    /* exchange: every particle's velocity from the forces of sweep j-1 */
+    cdref_velocities(dim, n, dt, v, w, m, inertia, r, f, t, nc, ci, cj, normal, Rprev, Vg, Wg);
+    memcpy(Vd, Vg, sizeof(double) * (size_t)(dim * n));
+    memcpy(Wd, Wg, sizeof(double) * (size_t)(dr * n));
+    /* each domain sweeps its native contacts sequentially on a private copy
+       of the velocities; other domains' contacts keep their sweep j-1 value */
+    for (int d = 0; d < P; ++d) {
+      for (int64_t s = dom_start[d]; s < dom_start[d + 1]; ++s) {
+        int64_t c = slot_contact[s];
+        int64_t a = ci[c], b = cj[c];
+        double nv[3], t1[3], t2[3];
+        contact_frame(dim, normal, nc, c, nv, t1, t2);
+        double Va[3] = {0, 0, 0}, Wa[3] = {0, 0, 0}, Vb[3] = {0, 0, 0}, Wb[3] = {0, 0, 0};
+        for (int k = 0; k < dim; ++k) Va[k] = Vd[k * n + a];
+        for (int k = 0; k < dr; ++k) Wa[k] = Wd[k * n + a];
+        double rb = 0.0;
+        if (b < n) {
+          for (int k = 0; k < dim; ++k) Vb[k] = Vd[k * n + b];
+          for (int k = 0; k < dr; ++k) Wb[k] = Wd[k * n + b];
+          rb = r[b];
+        } else {
+          for (int k = 0; k < dim; ++k) Vb[k] = wall_velocity[(b - n) * dim + k];
+        }
+        double Rold[3] = {0, 0, 0}, Rnew[3];
+        for (int k = 0; k < dim; ++k) Rold[k] = R[k * nc + c];
+        local_force(dim, nv, t1, t2, &cc[c], r[a], rb, Va, Wa, Vb, Wb, Rold, Rnew);
+        double dRn = Rnew[0] - Rold[0], dR1 = Rnew[1] - Rold[1];
+        double dR2 = dim == 3 ? Rnew[2] - Rold[2] : 0.0;
+        for (int k = 0; k < dim; ++k) R[k * nc + c] = Rnew[k];
+        /* apply the change to both bodies' private velocities */
+        double dF[3], dq[3];
+        for (int k = 0; k < dim; ++k) {
+          dF[k] = dRn * nv[k] + dR1 * t1[k];
+          if (dim == 3) dF[k] = dF[k] + dR2 * t2[k];
+        }
+        if (dim == 2) dq[0] = dR1;
+        else for (int k = 0; k < 3; ++k) dq[k] = dR1 * t2[k] - dR2 * t1[k];
+        for (int k = 0; k < dim; ++k) Vd[k * n + a] = Vd[k * n + a] - dtim[a] * dF[k];
+        for (int k = 0; k < dr; ++k) Wd[k * n + a] = Wd[k * n + a] - dtii[a] * (r[a] * dq[k]);
+        if (b < n) {
+          for (int k = 0; k < dim; ++k) Vd[k * n + b] = Vd[k * n + b] + dtim[b] * dF[k];
+          for (int k = 0; k < dr; ++k) Wd[k * n + b] = Wd[k * n + b] - dtii[b] * (r[b] * dq[k]);
+        }
+      }
+      /* the domain's private copy ends with the sweep: restore from Vg */
+      for (int64_t s = dom_start[d]; s < dom_start[d + 1]; ++s) {
+        int64_t c = slot_contact[s];
+        int64_t ends[2] = {ci[c], cj[c]};
+        for (int e = 0; e < 2; ++e) {
+          int64_t q = ends[e];
+          if (q >= n) continue;
+          for (int k = 0; k < dim; ++k) Vd[k * n + q] = Vg[k * n + q];
+          for (int k = 0; k < dr; ++k) Wd[k * n + q] = Wg[k * n + q];
+        }
+      }
+    }
+    /* convergence tests (Sec. 2.1) */
+    int64_t npass = 0;
+    double maxd = 0.0, ravg = 0.0;
+    int finite = 1;
+    int conv = cdref_criterion(dim, nc, Rprev, R, ravg_prev, alpha, p->criterion, &npass, &maxd,
+                               &ravg, &finite);
+    if (history) {
+      history[0 * (int64_t)limit + (j - 1)] = (double)npass;
+      history[1 * (int64_t)limit + (j - 1)] = maxd;
+      history[2 * (int64_t)limit + (j - 1)] = ravg;
+      history[3 * (int64_t)limit + (j - 1)] = (double)conv;
+    }
+    info->n_pass = npass;
+    info->max_d_fail = maxd;
+    info->r_avg = ravg;
+    info->r_avg_prev = ravg_prev;
+    info->iterations = j;
+    ravg_prev = ravg;
+    if (!finite) { status = CDREF_ENONFINITE; break; }
+    if (p->fixed_iters > 0) {
+      if (j == p->fixed_iters) { status = CDREF_OK; break; }
+      continue;
+    }
+    if (conv) { status = CDREF_OK; break; }
+  }
+  info->status = status;
+  free(cc); free(Rprev); free(Vg); free(Wg); free(Vd); free(Wd); free(dtim); free(dtii);
+  return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* whole time steps (Fig. 3 and Fig. 7)                                 */
+/* ------------------------------------------------------------------ */
+
+struct cdref_sim {
+  cdref_params p;
+  int64_t n;
+  int dr;
+  double *x, *v, *w, *r, *m, *I, *f, *t;
+  double *wn, *wo, *wu;
+  double lo[3], hi[3];
+  int64_t step;
+  /* tree */
+  int32_t *axis, *child, *leaf;
+  double* cut;
+  int have_tree;
+  /* contacts of the last step */
+  int64_t nc, cap;
+  int32_t *ci, *cj, *dom, *color, *slot;
+  double *normal, *gap, *xmid, *R;
+};
+
+static double* dup_array(const double* a, int64_t count) {
+  double* b = (double*)malloc(sizeof(double) * (size_t)(count > 0 ? count : 1));
+  if (b && count > 0) memcpy(b, a, sizeof(double) * (size_t)count);
+  return b;
+}
+
+cdref_sim* cdref_sim_create(const cdref_params* p, int64_t n, const double* x,
+                            const double* v, const double* w, const double* r,
+                            const double* m, const double* inertia, const double* f,
+                            const double* t, const double* wall_normal,
+                            const double* wall_offset, const double* wall_velocity,
+                            const double* box_lo, const double* box_hi) {
+  if (p->dim != 2 && p->dim != 3) return NULL;
+  if (p->n_domains < 1 || n < 1) return NULL;
+  cdref_sim* s = (cdref_sim*)calloc(1, sizeof(cdref_sim));
+  if (!s) return NULL;
+  s->p = *p;
+  if (s->p.repartition_every < 1) s->p.repartition_every = 1;
+  s->n = n;
+  int dim = p->dim;
+  s->dr = dim == 2 ? 1 : 3;
+  s->x = dup_array(x, dim * n);
+  s->v = dup_array(v, dim * n);
+  s->w = dup_array(w, s->dr * n);
+  s->r = dup_array(r, n);
+  s->m = dup_array(m, n);
+  s->I = dup_array(inertia, n);
+  s->f = dup_array(f, dim * n);
+  s->t = dup_array(t, s->dr * n);
+  s->wn = dup_array(wall_normal, (int64_t)p->n_walls * dim);
+  s->wo = dup_array(wall_offset, p->n_walls);
+  s->wu = dup_array(wall_velocity, (int64_t)p->n_walls * dim);
+  for (int k = 0; k < 3; ++k) { s->lo[k] = k < dim ? box_lo[k] : 0.0; s->hi[k] = k < dim ? box_hi[k] : 0.0; }
+  int nodes = 2 * p->n_domains - 1;
+  s->axis = (int32_t*)calloc((size_t)nodes, sizeof(int32_t));
+  s->child = (int32_t*)calloc(2 * (size_t)nodes, sizeof(int32_t));
+  s->leaf = (int32_t*)calloc((size_t)nodes, sizeof(int32_t));
+  s->cut = (double*)calloc((size_t)nodes, sizeof(double));
+  return s;
+}
+
+void cdref_sim_destroy(cdref_sim* s) {
+  if (!s) return;
+  free(s->x); free(s->v); free(s->w); free(s->r); free(s->m); free(s->I); free(s->f);
+  free(s->t); free(s->wn); free(s->wo); free(s->wu);
+  free(s->axis); free(s->child); free(s->leaf); free(s->cut);
+  free(s->ci); free(s->cj); free(s->dom); free(s->color); free(s->slot);
+  free(s->normal); free(s->gap); free(s->xmid); free(s->R);
+  free(s);
+}
+
+static int ensure_capacity(cdref_sim* s, int64_t need) {
+  if (need <= s->cap) return CDREF_OK;
+  int64_t cap = need + need / 4 + 64;
+  int dim = s->p.dim;
+  free(s->ci); free(s->cj); free(s->dom); free(s->color); free(s->slot);
+  free(s->normal); free(s->gap); free(s->xmid);
+  s->ci = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+  s->cj = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+  s->dom = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+  s->color = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+  s->slot = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+  s->normal = (double*)malloc(sizeof(double) * (size_t)(dim * cap));
+  s->gap = (double*)malloc(sizeof(double) * (size_t)cap);
+  s->xmid = (double*)malloc(sizeof(double) * (size_t)(dim * cap));
+  if (!s->ci || !s->cj || !s->dom || !s->color || !s->slot || !s->normal || !s->gap || !s->xmid)
+    return CDREF_ENOMEM;
+  s->cap = cap;
+  return CDREF_OK;
+}
+
+int cdref_sim_step(cdref_sim* s, cdref_info* info) {
+  cdref_params* p = &s->p;
+  int dim = p->dim, dr = s->dr;
+  int64_t n = s->n;
+  memset(info, 0, sizeof(*info));
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(s->r[i] > 0.0) || !(s->m[i] > 0.0) || !(s->I[i] > 0.0)) return CDREF_EINVAL;
+    for (int k = 0; k < dim; ++k)
+      if (!isfinite(s->x[k * n + i]) || !isfinite(s->v[k * n + i])) return CDREF_ENONFINITE;
+  }
+  /* boundary width: two particles can touch within dt if their gap is below
+     2 vmax dt (Sec. 3.1) */
+  double vmax = 0.0, rmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double q = 0.0;
+    for (int k = 0; k < dim; ++k) q = q + s->v[k * n + i] * s->v[k * n + i];
+    double sp = sqrt(q);
+    if (sp > vmax) vmax = sp;
+    if (s->r[i] > rmax) rmax = s->r[i];
+  }
+  for (int wi = 0; wi < p->n_walls; ++wi) {
+    double q = 0.0;
+    for (int k = 0; k < dim; ++k) q = q + s->wu[wi * dim + k] * s->wu[wi * dim + k];
+    double sp = sqrt(q);
+    if (sp > vmax) vmax = sp;
+  }
+  double skin = p->skin >= 0.0 ? p->skin : 2.0 * vmax * p->dt;
+  info->skin = skin;
+  if (skin > 0.2 * rmax) return CDREF_EINVAL;   /* displacement bound 0.1 r_max */
+
+  /* previous contacts for the warm start */
+  int64_t old_nc = s->nc;
+  int32_t* old_ci = s->ci;
+  int32_t* old_cj = s->cj;
+  double* old_R = s->R;
+  s->ci = NULL; s->cj = NULL; s->R = NULL;
+  /* detection */
+  int64_t nc = 0;
+  int st;
+  {
+    int64_t guess = s->cap > 0 ? s->cap : 4 * n + 64;
+    int32_t* ci = (int32_t*)malloc(sizeof(int32_t) * (size_t)guess);
+    int32_t* cj = (int32_t*)malloc(sizeof(int32_t) * (size_t)guess);
+    st = cdref_detect(dim, n, s->x, s->r, p->n_walls, s->wn, s->wo, skin, 1, s->lo, s->hi,
+                      guess, ci, cj, &nc);
+    if (st == CDREF_ECAPACITY) {
+      free(ci); free(cj);
+      ci = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+      cj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+      st = cdref_detect(dim, n, s->x, s->r, p->n_walls, s->wn, s->wo, skin, 1, s->lo, s->hi,
+                        nc, ci, cj, &nc);
+    }
+    if (st != CDREF_OK) { free(ci); free(cj); free(old_ci); free(old_cj); free(old_R); return st; }
+    int64_t keep_cap = s->cap;
+    free(s->dom); free(s->color); free(s->slot); free(s->normal); free(s->gap); free(s->xmid);
+    s->dom = NULL; s->color = NULL; s->slot = NULL; s->normal = NULL; s->gap = NULL; s->xmid = NULL;
+    s->cap = 0;
+    st = ensure_capacity(s, nc > keep_cap ? nc : keep_cap);
+    if (st != CDREF_OK) { free(ci); free(cj); return st; }
+    memcpy(s->ci, ci, sizeof(int32_t) * (size_t)nc);
+    memcpy(s->cj, cj, sizeof(int32_t) * (size_t)nc);
+    free(ci); free(cj);
+  }
+  s->nc = nc;
+  info->n_contacts = nc;
+  cdref_geometry(dim, n, s->x, s->r, p->n_walls, s->wn, s->wo, nc, s->ci, s->cj, s->normal,
+                 s->gap, s->xmid);
+  /* warm start: forces of the same pair in the previous step, else zero */
+  s->R = (double*)calloc((size_t)(dim * (nc > 0 ? nc : 1)), sizeof(double));
+  if (p->warm_start && old_R) {
+    for (int64_t c = 0; c < nc; ++c) {
+      int64_t lo = 0, hi = old_nc;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (old_ci[mid] < s->ci[c] || (old_ci[mid] == s->ci[c] && old_cj[mid] < s->cj[c]))
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo < old_nc && old_ci[lo] == s->ci[c] && old_cj[lo] == s->cj[c])
+        for (int k = 0; k < dim; ++k) s->R[k * nc + c] = old_R[k * old_nc + lo];
+    }
+  }
+  free(old_ci); free(old_cj); free(old_R);
+  /* partition: rebuild the tree every repartition_every steps, otherwise
+     descend the existing one (Sec. 3.2) */
+  int P = p->n_domains;
+  if (!s->have_tree || s->step % p->repartition_every == 0) {
+    st = cdref_orb(dim, P, s->lo, s->hi, nc, s->xmid, s->axis, s->cut, s->child, s->leaf, NULL,
+                   s->dom);
+    if (st != CDREF_OK) return st;
+    s->have_tree = 1;
+  } else {
+    cdref_descend(dim, P, s->axis, s->cut, s->child, s->leaf, nc, s->xmid, s->dom);
+  }
+  int64_t* dom_start = (int64_t*)malloc(sizeof(int64_t) * ((size_t)P + 1));
+  st = cdref_order(n, nc, s->ci, s->cj, P, s->dom, s->color, s->slot, dom_start);
+  if (st != CDREF_OK) { free(dom_start); return st; }
+  st = cdref_solve(p, n, s->v, s->w, s->r, s->m, s->I, s->f, s->t, s->wu, nc, s->ci, s->cj,
+                   s->normal, s->gap, NULL, P, dom_start, s->slot, s->R, info, NULL);
+  info->skin = skin;
+  info->n_contacts = nc;
+  free(dom_start);
+  if (st < 0) return st;
+  /* time stepping: Eqs. (1)-(2) with the final forces */
+  double* V = (double*)malloc(sizeof(double) * (size_t)(dim * n));
+  double* W = (double*)malloc(sizeof(double) * (size_t)(dr * n));
+  cdref_velocities(dim, n, p->dt, s->v, s->w, s->m, s->I, s->r, s->f, s->t, nc, s->ci, s->cj,
+                   s->normal, s->R, V, W);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < dim; ++k) {
+      s->v[k * n + i] = V[k * n + i];
+      s->x[k * n + i] = s->x[k * n + i] + V[k * n + i] * p->dt;
+    }
+    for (int k = 0; k < dr; ++k) s->w[k * n + i] = W[k * n + i];
+  }
+  free(V); free(W);
+  /* walls translate; a box face follows the wall lying on it */
+  for (int wi = 0; wi < p->n_walls; ++wi) {
+    double un = 0.0;
+    for (int k = 0; k < dim; ++k) un = un + s->wn[wi * dim + k] * s->wu[wi * dim + k];
+    s->wo[wi] = s->wo[wi] + p->dt * un;
+    for (int k = 0; k < dim; ++k) {
+      int unit = 1;
+      for (int q = 0; q < dim; ++q)
+        if (q != k && s->wn[wi * dim + q] != 0.0) unit = 0;
+      if (!unit) continue;
+      if (s->wn[wi * dim + k] == 1.0) s->lo[k] = s->wo[wi];
+      if (s->wn[wi * dim + k] == -1.0) s->hi[k] = -s->wo[wi];
+    }
+  }
+  s->step += 1;
+  return st;
+}
+
+void cdref_sim_state(const cdref_sim* s, double* x, double* v, double* w, double* wall_offset) {
+  int dim = s->p.dim;
+  if (x) memcpy(x, s->x, sizeof(double) * (size_t)(dim * s->n));
+  if (v) memcpy(v, s->v, sizeof(double) * (size_t)(dim * s->n));
+  if (w) memcpy(w, s->w, sizeof(double) * (size_t)(s->dr * s->n));
+  if (wall_offset && s->p.n_walls > 0)
+    memcpy(wall_offset, s->wo, sizeof(double) * (size_t)s->p.n_walls);
+}
+
+int64_t cdref_sim_contacts(const cdref_sim* s, int64_t cap, int32_t* ci, int32_t* cj,
+                           double* normal, double* gap, double* R, int32_t* dom,
+                           int32_t* color, int32_t* slot_contact) {
+  int64_t nc = s->nc;
+  if (cap < nc) return nc;
+  int dim = s->p.dim;
+  if (ci) memcpy(ci, s->ci, sizeof(int32_t) * (size_t)nc);
+  if (cj) memcpy(cj, s->cj, sizeof(int32_t) * (size_t)nc);
+  if (normal) memcpy(normal, s->normal, sizeof(double) * (size_t)(dim * nc));
+  if (gap) memcpy(gap, s->gap, sizeof(double) * (size_t)nc);
+  if (R) memcpy(R, s->R, sizeof(double) * (size_t)(dim * nc));
+  if (dom) memcpy(dom, s->dom, sizeof(int32_t) * (size_t)nc);
+  if (color) memcpy(color, s->color, sizeof(int32_t) * (size_t)nc);
+  if (slot_contact) memcpy(slot_contact, s->slot, sizeof(int32_t) * (size_t)nc);
+  return nc;
+}
+
+void cdref_sim_tree(const cdref_sim* s, int32_t* node_axis, double* node_cut,
+                    int32_t* node_child, int32_t* node_leaf) {
+  int nodes = 2 * s->p.n_domains - 1;
+  memcpy(node_axis, s->axis, sizeof(int32_t) * (size_t)nodes);
+  memcpy(node_cut, s->cut, sizeof(double) * (size_t)nodes);
+  memcpy(node_child, s->child, sizeof(int32_t) * 2 * (size_t)nodes);
+  memcpy(node_leaf, s->leaf, sizeof(int32_t) * (size_t)nodes);
+}
