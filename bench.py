@@ -1,0 +1,174 @@
+"""Benchmark of the contact-force solve on one MI355X.
+
+Workload (the headline configuration): 2D disks, N = 262,144 on a 512x512
+jittered triangular lattice (spacing 2.05, radii U[0.8, 1.2], jitter +-0.05),
+rigid box walls, gravity 1, mass ~ r^2, mu = 0.3, dt = 1e-3, initial
+velocities N(0, 0.01^2), hierarchical bisection into 4,096 domains balanced
+by contact count, repartition every 10 steps, tolerance alpha = 1e-6 on the
+local test (I), at most 2,000 sweeps per step, 100 time steps of settling
+under gravity.  A "step" is one full time step: detection, warm start,
+partition, order, the sweeps to convergence and the Euler update.
+
+The JSON line reports whole-step contact updates/s (sum over steps of sweeps
+x contacts, divided by the timed wall-clock), the milliseconds per step, the
+roofline of the sweep kernel (algorithmic bytes per sweep over the summed
+durations of the sweep launches that did work, from HIP events on the
+library's stream) and the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "contact updates/sec and ms per converged time step at tol 1e-6 (FP64), % HBM peak"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes a streaming sweep must move (2D): per contact the pair
+# indices, normal, gap, force read and force write; per particle the base
+# velocities and the mass, inertia and radius terms
+BYTES_PER_CONTACT_2D = 64
+BYTES_PER_PARTICLE_2D = 48
+
+WORKLOAD = ("disks_262k: 2D disks N=262144 (512x512 jittered triangular lattice), mu=0.3, "
+            "dt=1e-3, gravity 1, 4096 contact-count-balanced bisection domains, repartition "
+            "every 10 steps, alpha=1e-6 local test, max 2000 sweeps, gravity settling")
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_ctx(pk, binding, timing=True):
+    params = binding.make_params(2, pk.n_walls, mu=0.3, dt=1e-3, alpha=1e-6, criterion=0,
+                                 max_iter=2000, n_domains=4096, repartition_every=10,
+                                 warm_start=1)
+    return binding.Context(params, pk, timing=timing)
+
+
+def cpu_baseline(pk, sweeps: int) -> dict:
+    """The oracle as it is, single-threaded, on the first time step of the
+    same workload with the sweep count capped."""
+    from oracle import cdref
+    cdref.build(force=False)
+    p = cdref.make_params(2, pk.n_walls, mu=0.3, dt=1e-3, alpha=1e-6, criterion=0,
+                          max_iter=sweeps, n_domains=4096, repartition_every=10)
+    sim = cdref.Sim(p, pk)
+    t0 = time.perf_counter()
+    info = sim.step()
+    dt = time.perf_counter() - t0
+    updates = info.iterations * info.n_contacts
+    return {"value": updates / dt, "unit": "contact updates/s", "cores": 1, "kind": "oracle",
+            "sample": (f"first time step of the same workload (N=262144, 4096 domains), "
+                       f"sweeps capped at {sweeps} ({info.iterations} run, "
+                       f"{info.n_contacts} contacts), whole step incl. detection and "
+                       f"partition, {dt:.1f} s single-threaded")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sweeps", type=int, default=200,
+                    help="sweep cap of the CPU-oracle sample (0 skips it)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles",
+                                                          "sweep_disks_262k_traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              f"(the path shards by subtrees of the bisection tree, see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1104_3516_amd import binding, inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        return 1
+    pk = inputs.config("disks_262k")
+
+    # warm-up on a throwaway context (kernels loaded, allocations made)
+    if args.warmup > 0:
+        ctx = make_ctx(pk, binding)
+        for s in range(args.warmup):
+            r = ctx.step()
+            log(f"warmup step {s}: {r.iterations} sweeps, {r.n_contacts} contacts")
+        ctx.close()
+        del ctx
+
+    ctx = make_ctx(pk, binding)
+    torch.cuda.synchronize()
+    sweeps = 0
+    updates = 0
+    sweep_kernel_ms = 0.0
+    solve_ms = 0.0
+    bytes_sweeps = 0.0
+    maxiter_steps = 0
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        r = ctx.step()
+        tm = ctx.timing()
+        sweeps += r.iterations
+        updates += r.iterations * r.n_contacts
+        sweep_kernel_ms += tm.sweep_kernel_ms
+        solve_ms += tm.solve_ms
+        bytes_sweeps += r.iterations * (BYTES_PER_CONTACT_2D * r.n_contacts +
+                                        BYTES_PER_PARTICLE_2D * pk.n)
+        maxiter_steps += int(r.status == binding.MAXITER)
+        if s % 10 == 0 or s == args.steps - 1:
+            log(f"step {s}: {r.iterations} sweeps, {r.n_contacts} contacts, status {r.status}, "
+                f"solve {tm.solve_ms:.2f} ms, sweep kernels {tm.sweep_kernel_ms:.2f} ms "
+                f"({tm.sweep_launches} launches)")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    avg_sweep_s = (sweep_kernel_ms / 1e3) / max(sweeps, 1)
+    bytes_per_sweep = bytes_sweeps / max(sweeps, 1)
+    achieved = bytes_per_sweep / avg_sweep_s / 1e9 if sweeps else 0.0
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            traffic = json.load(open(args.traffic_json)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    out = {
+        "metric": METRIC,
+        "value": updates / elapsed,
+        "unit": "contact updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n_particles": pk.n, "n_domains": 4096,
+                   "time_steps": args.steps},
+        "sweeps_total": sweeps,
+        "sweeps_per_step": sweeps / args.steps,
+        "steps_at_sweep_cap": maxiter_steps,
+        "solve_ms_per_step": solve_ms / args.steps,
+        "solve_contact_updates_per_s": updates / (solve_ms / 1e3) if solve_ms > 0 else None,
+        "sweep_kernel_us": 1e6 * avg_sweep_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sweep<2>", "bytes_per_launch": bytes_per_sweep},
+    }
+    if args.cpu_sweeps > 0:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(pk, args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

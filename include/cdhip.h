@@ -1,0 +1,166 @@
+/* cdhip.h - C ABI of the MI355X (gfx950) Contact Dynamics force solver.
+ *
+ * The library computes time steps of the non-smooth Contact Dynamics method
+ * for rigid frictional disks (2D) and spheres (3D) as described by Shojaaee
+ * et al., "An adaptive hierarchical domain decomposition method for parallel
+ * contact dynamics simulations of granular materials":
+ *   - contact detection with the cell method and a boundary width of
+ *     2 vmax dt (Sec. 3.1 and 3.2);
+ *   - assignment of contacts to P domains of a hierarchical bisection tree
+ *     built for an arbitrary P (Sec. 3.2, Fig. 8), with cuts placed by contact
+ *     count (the balancing by contact number named in Sec. 5);
+ *   - the iterative force solve: each contact's force is computed with all
+ *     other forces fixed (Sec. 2.1, Eqs. 3-9 and Fig. 2); native contacts of a
+ *     domain are updated sequentially, other domains' contacts keep the value
+ *     of the previous sweep and are exchanged after every sweep (Sec. 3.1);
+ *     sweeps stop on the local (I) or global (II) convergence test (Sec. 2.1);
+ *   - the semi-implicit Euler update of velocities and positions (Eqs. 1-2).
+ *
+ * Conventions
+ *   - FP64 throughout.  Arrays are structure-of-arrays, component-major:
+ *     a[k * n + i].  dim = 2 or 3; dr = 1 (2D) or 3 (3D) rotational components.
+ *   - Unless stated otherwise pointers are DEVICE pointers (HIP global memory
+ *     on the context's device) owned by the caller; the library copies what it
+ *     needs during the call and keeps no caller pointer after it returns.
+ *   - Bodies 0..N-1 are particles; a contact partner j >= N is wall j-N.  A
+ *     wall is the plane {x : nu.x = o} whose unit normal nu points into the
+ *     box.  Contact c joins body 1 = ci[c] < body 2 = cj[c]; its normal n
+ *     points from body 1 to body 2 and R is the force on body 2, stored in the
+ *     contact frame: (R_n, R_t) in 2D with t = z x n, (R_n, R_t1, R_t2) in 3D.
+ *   - All work of a context is enqueued on the stream given at creation.
+ *     Calls that return results on the host synchronise that stream.
+ *   - Return codes: CD_OK (0); CD_MAXITER (1, a valid but unconverged solve);
+ *     negative values are errors, described by cd_last_error().  No C++
+ *     exception crosses the ABI.  A context is not thread-safe.
+ */
+#ifndef CDHIP_H
+#define CDHIP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CD_OK = 0,
+  CD_MAXITER = 1,        /* sweep cap reached before the convergence test held */
+  CD_EINVAL = -1,        /* bad argument (sizes, radii/masses <= 0, skin > 0.2 r_max, P < 1) */
+  CD_ENOMEM = -2,        /* device allocation failed */
+  CD_ECAPACITY = -3,     /* a domain exceeds the per-domain limits (contacts, colours) */
+  CD_ENONFINITE = -4,    /* non-finite input or force */
+  CD_EHIP = -5,          /* HIP runtime error; cd_last_error() gives the detail */
+  CD_ENOTREADY = -6      /* particles not set yet */
+};
+
+/* Solver parameters (host struct, copied at cd_create). */
+typedef struct cd_params {
+  int dim;               /* 2 or 3 */
+  int n_walls;           /* walls are set with cd_set_walls */
+  double dt;             /* time step */
+  double alpha;          /* convergence threshold on squared relative changes (paper: 1e-6) */
+  double mu;             /* Coulomb friction coefficient, all contacts */
+  int criterion;         /* 0: local test (I); 1: global test (II) (Sec. 2.1) */
+  int max_iter;          /* sweep cap in tolerance mode */
+  int fixed_iters;       /* > 0: exactly this many sweeps per step, no convergence stop */
+  int overlap_mode;      /* 0: gap clamped at zero in the force law; 1: signed gap */
+  int n_domains;         /* P >= 1 domains of the bisection tree */
+  int repartition_every; /* rebuild the tree every this many steps (>= 1) */
+  int warm_start;        /* 1: start each step from the previous forces of the same pairs */
+  double skin;           /* < 0: boundary width 2 vmax dt; >= 0: this fixed width */
+} cd_params;
+
+/* Outcome of one step (host struct). */
+typedef struct cd_result {
+  int status;            /* CD_OK or CD_MAXITER */
+  int iterations;        /* sweeps performed */
+  int64_t n_contacts;    /* contacts in the list of this step */
+  int64_t n_pass;        /* contacts passing the relative test in the last sweep */
+  double max_d_fail;     /* largest |dR|^2 among the others (0 if none) */
+  double r_avg;          /* mean |R| after the last sweep */
+  double r_avg_prev;     /* mean |R| before the last sweep */
+  double skin;           /* boundary width used */
+  int max_colors;        /* largest number of colours in a domain */
+  int max_domain_contacts;  /* largest domain (contacts) */
+} cd_result;
+
+/* Time spent in each phase of the last step, milliseconds, from HIP events
+ * on the context's stream (host struct). */
+typedef struct cd_timing {
+  double detect_ms;      /* boundary width, cell binning, pair search, geometry, warm start */
+  double partition_ms;   /* tree build or descent */
+  double order_ms;       /* per-domain colouring and slot layout */
+  double solve_ms;       /* all sweeps, exchange and convergence tests */
+  double update_ms;      /* Euler update */
+  double sweep_kernel_ms;  /* summed durations of the sweep launches that did work */
+  int sweep_launches;    /* sweep kernel launches in the last step (including idle ones) */
+} cd_timing;
+
+typedef struct cd_ctx cd_ctx;
+
+/* Create a context for n_particles bodies on the current HIP device.
+ * stream: a hipStream_t (NULL = the null stream) on which all work runs.
+ * The context owns its workspace and frees it in cd_destroy. */
+int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* stream);
+int cd_destroy(cd_ctx* ctx);
+
+/* Particle state and properties (device pointers, copied in):
+ * x, v (dim x N); w (dr x N); radius, mass, inertia (N), all > 0. */
+int cd_set_particles(cd_ctx* ctx, const double* x, const double* v, const double* w,
+                     const double* radius, const double* mass, const double* inertia);
+
+/* External forces (dim x N) and torques (dr x N, NULL = zero); device pointers. */
+int cd_set_external(cd_ctx* ctx, const double* force, const double* torque);
+
+/* Walls (HOST pointers): normal (W x dim, unit, into the box), offset (W),
+ * velocity (W x dim).  W must equal params.n_walls. */
+int cd_set_walls(cd_ctx* ctx, const double* normal, const double* offset, const double* velocity);
+
+/* Simulation box (HOST pointers, dim each): the root region of the
+ * bisection tree and the extent of the cell grid.  Box faces lying on an
+ * axis-aligned wall move with that wall. */
+int cd_set_box(cd_ctx* ctx, const double* lo, const double* hi);
+
+/* One time step: detection, warm start, partition, order, force solve,
+ * Euler update (Fig. 7).  Positions and velocities are updated in place in
+ * the context.  out (host, may be NULL) receives the outcome.  Returns
+ * CD_OK, CD_MAXITER or an error. */
+int cd_step(cd_ctx* ctx, cd_result* out);
+
+/* Copy the state out (device pointers, NULL skips): x, v (dim x N), w (dr x N). */
+int cd_get_state(cd_ctx* ctx, double* x, double* v, double* w);
+
+/* Wall offsets after the steps so far (HOST pointer, W entries). */
+int cd_get_walls(cd_ctx* ctx, double* offset);
+
+/* Number of contacts of the last step (host value, no device work). */
+int64_t cd_num_contacts(const cd_ctx* ctx);
+
+/* The contacts of the last step in canonical (ci, cj) order (device
+ * pointers, NULL skips): ci, cj (nc), normal (dim x nc), gap (nc),
+ * R (dim x nc, contact frame), dom (nc), color (nc) and slot_contact (nc:
+ * the contact at each position of the domain-major update order).
+ * cap must be >= cd_num_contacts(). */
+int cd_get_contacts(cd_ctx* ctx, int64_t cap, int32_t* ci, int32_t* cj, double* normal,
+                    double* gap, double* R, int32_t* dom, int32_t* color,
+                    int32_t* slot_contact);
+
+/* The current bisection tree, 2P-1 nodes in creation order (HOST pointers):
+ * axis (-1 for leaves), cut, child (2 per node, -1 for leaves), leaf domain
+ * id (-1 for inner nodes). */
+int cd_get_tree(cd_ctx* ctx, int32_t* axis, double* cut, int32_t* child, int32_t* leaf);
+
+/* per_sweep_events != 0: bracket every sweep launch with HIP events so that
+ * cd_timing.sweep_kernel_ms holds the summed kernel durations (default on). */
+int cd_set_timing(cd_ctx* ctx, int per_sweep_events);
+
+/* Phase timings of the last step (host struct). */
+int cd_get_timing(cd_ctx* ctx, cd_timing* out);
+
+/* Static description of a status code, and the last error of a context. */
+const char* cd_status_string(int status);
+const char* cd_last_error(const cd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

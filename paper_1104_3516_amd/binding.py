@@ -1,0 +1,225 @@
+"""ctypes binding of libcdhip (include/cdhip.h): argument marshalling only.
+
+PyTorch provides device memory and the stream; every step of the solve runs
+in the library's HIP kernels.  There is no CPU fallback: without the built
+library or without a GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcdhip.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "cdhip.h")
+
+OK, MAXITER, EINVAL, ENOMEM, ECAPACITY, ENONFINITE, EHIP, ENOTREADY = 0, 1, -1, -2, -3, -4, -5, -6
+
+
+class Params(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_walls", C.c_int), ("dt", C.c_double),
+                ("alpha", C.c_double), ("mu", C.c_double), ("criterion", C.c_int),
+                ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("overlap_mode", C.c_int),
+                ("n_domains", C.c_int), ("repartition_every", C.c_int),
+                ("warm_start", C.c_int), ("skin", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("n_contacts", C.c_int64),
+                ("n_pass", C.c_int64), ("max_d_fail", C.c_double), ("r_avg", C.c_double),
+                ("r_avg_prev", C.c_double), ("skin", C.c_double), ("max_colors", C.c_int),
+                ("max_domain_contacts", C.c_int)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("detect_ms", C.c_double), ("partition_ms", C.c_double),
+                ("order_ms", C.c_double), ("solve_ms", C.c_double), ("update_ms", C.c_double),
+                ("sweep_kernel_ms", C.c_double), ("sweep_launches", C.c_int)]
+
+
+def make_params(dim: int, n_walls: int, *, dt=1e-3, alpha=1e-6, mu=0.3, criterion=0,
+                max_iter=2000, fixed_iters=0, overlap_mode=0, n_domains=1,
+                repartition_every=1, warm_start=1, skin=-1.0) -> Params:
+    return Params(dim, n_walls, dt, alpha, mu, criterion, max_iter, fixed_iters, overlap_mode,
+                  n_domains, repartition_every, warm_start, skin)
+
+
+def declared_symbols() -> list:
+    """Function names declared in include/cdhip.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(cd_\w+)\s*\(", text,
+                                 re.MULTILINE)))
+
+
+_lib = None
+
+
+def lib():
+    """Load libcdhip.so (after torch, whose HIP runtime it shares)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (loads libamdhip64 first)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        i64 = C.c_int64
+        L.cd_create.argtypes = [C.POINTER(P), C.POINTER(Params), i64, P]
+        L.cd_destroy.argtypes = [P]
+        L.cd_set_particles.argtypes = [P, P, P, P, P, P, P]
+        L.cd_set_external.argtypes = [P, P, P]
+        L.cd_set_walls.argtypes = [P, P, P, P]
+        L.cd_set_box.argtypes = [P, P, P]
+        L.cd_set_timing.argtypes = [P, C.c_int]
+        L.cd_step.argtypes = [P, C.POINTER(Result)]
+        L.cd_get_state.argtypes = [P, P, P, P]
+        L.cd_get_walls.argtypes = [P, P]
+        L.cd_num_contacts.argtypes = [P]
+        L.cd_num_contacts.restype = i64
+        L.cd_get_contacts.argtypes = [P, i64, P, P, P, P, P, P, P, P]
+        L.cd_get_tree.argtypes = [P, P, P, P, P]
+        L.cd_get_timing.argtypes = [P, C.POINTER(Timing)]
+        L.cd_status_string.argtypes = [C.c_int]
+        L.cd_status_string.restype = C.c_char_p
+        L.cd_last_error.argtypes = [P]
+        L.cd_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class CDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libcdhip error {code}: {msg}")
+        self.code = code
+
+
+class Context:
+    """One simulation on one GPU.  `packing` is a paper_1104_3516_amd.inputs.Packing."""
+
+    def __init__(self, params: Params, packing, device: str = "cuda:0", timing: bool = True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libcdhip needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.L = lib()
+        self.device = torch.device(device)
+        self.params = params
+        self.dim = packing.dim
+        self.dr = 1 if self.dim == 2 else 3
+        self.n = packing.n
+        self.W = packing.n_walls
+        if params.n_walls != self.W or params.dim != self.dim:
+            raise ValueError("params do not match the packing")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            h = C.c_void_p()
+            self._check(self.L.cd_create(C.byref(h), C.byref(params), self.n,
+                                         C.c_void_p(self.stream.cuda_stream)), None)
+            self.h = h
+            dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64),
+                                            device=self.device)
+            x, v, w = dev(packing.x), dev(packing.v), dev(packing.w)
+            r, m, inertia = dev(packing.r), dev(packing.m), dev(packing.inertia)
+            f, t = dev(packing.f), dev(packing.t)
+            self._check(self.L.cd_set_particles(self.h, _ptr(x), _ptr(v), _ptr(w), _ptr(r),
+                                                _ptr(m), _ptr(inertia)))
+            self._check(self.L.cd_set_external(self.h, _ptr(f), _ptr(t)))
+            wn = np.ascontiguousarray(packing.wall_normal, dtype=np.float64)
+            wo = np.ascontiguousarray(packing.wall_offset, dtype=np.float64)
+            wv = np.ascontiguousarray(packing.wall_velocity, dtype=np.float64)
+            self._check(self.L.cd_set_walls(self.h, wn.ctypes.data_as(C.c_void_p),
+                                            wo.ctypes.data_as(C.c_void_p),
+                                            wv.ctypes.data_as(C.c_void_p)))
+            lo = np.ascontiguousarray(packing.box_lo, dtype=np.float64)
+            hi = np.ascontiguousarray(packing.box_hi, dtype=np.float64)
+            self._check(self.L.cd_set_box(self.h, lo.ctypes.data_as(C.c_void_p),
+                                          hi.ctypes.data_as(C.c_void_p)))
+            self._check(self.L.cd_set_timing(self.h, 1 if timing else 0))
+            torch.cuda.synchronize(self.device)
+
+    def _check(self, code: int, h="self"):
+        if code < 0:
+            msg = self.L.cd_last_error(self.h if h == "self" else None)
+            raise CDError(code, (msg or b"").decode())
+        return code
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.cd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self) -> Result:
+        res = Result()
+        self._check(self.L.cd_step(self.h, C.byref(res)))
+        return res
+
+    def state(self):
+        torch = self.torch
+        x = torch.empty((self.dim, self.n), dtype=torch.float64, device=self.device)
+        v = torch.empty_like(x)
+        w = torch.empty((self.dr, self.n), dtype=torch.float64, device=self.device)
+        self._check(self.L.cd_get_state(self.h, _ptr(x), _ptr(v), _ptr(w)))
+        return x, v, w
+
+    def wall_offsets(self) -> np.ndarray:
+        out = np.zeros(max(self.W, 1))
+        self._check(self.L.cd_get_walls(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out[:self.W]
+
+    def num_contacts(self) -> int:
+        return int(self.L.cd_num_contacts(self.h))
+
+    def contacts(self) -> Dict[str, "object"]:
+        torch = self.torch
+        nc = self.num_contacts()
+        cap = max(nc, 1)
+        i32 = dict(dtype=torch.int32, device=self.device)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        out = dict(ci=torch.empty(cap, **i32), cj=torch.empty(cap, **i32),
+                   normal=torch.empty((self.dim, cap), **f64), gap=torch.empty(cap, **f64),
+                   R=torch.empty((self.dim, cap), **f64), dom=torch.empty(cap, **i32),
+                   color=torch.empty(cap, **i32), slot=torch.empty(cap, **i32))
+        if nc > 0:
+            # (dim x nc) arrays are written with stride nc
+            normal = torch.empty(self.dim * nc, **f64)
+            R = torch.empty(self.dim * nc, **f64)
+            self._check(self.L.cd_get_contacts(self.h, cap, _ptr(out["ci"]), _ptr(out["cj"]),
+                                               _ptr(normal), _ptr(out["gap"]), _ptr(R),
+                                               _ptr(out["dom"]), _ptr(out["color"]),
+                                               _ptr(out["slot"])))
+            out["normal"] = normal.view(self.dim, nc)
+            out["R"] = R.view(self.dim, nc)
+        return {k: (v[..., :nc] if v.dim() == 1 or k in ("normal", "R") else v)
+                for k, v in out.items()}
+
+    def tree(self):
+        P = self.params.n_domains
+        nodes = 2 * P - 1
+        axis = np.zeros(nodes, np.int32)
+        cut = np.zeros(nodes)
+        child = np.zeros(2 * nodes, np.int32)
+        leaf = np.zeros(nodes, np.int32)
+        self._check(self.L.cd_get_tree(self.h, axis.ctypes.data_as(C.c_void_p),
+                                       cut.ctypes.data_as(C.c_void_p),
+                                       child.ctypes.data_as(C.c_void_p),
+                                       leaf.ctypes.data_as(C.c_void_p)))
+        return dict(axis=axis, cut=cut, child=child, leaf=leaf)
+
+    def timing(self) -> Timing:
+        t = Timing()
+        self._check(self.L.cd_get_timing(self.h, C.byref(t)))
+        return t

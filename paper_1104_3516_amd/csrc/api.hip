@@ -1,0 +1,657 @@
+// api.hip - host driver of libcdhip: the C ABI declared in include/cdhip.h.
+//
+// One time step (the parallel CD scheme of Fig. 7, on one device):
+//   boundary width (vmax) -> cell binning -> pair search (canonical list)
+//   -> geometry -> warm start -> tree build or descent -> per-domain order
+//   -> sweeps until the convergence test holds -> Euler update.
+// Host/device synchronisation per step: the vmax readback (the boundary
+// width decides the cell search), the contact count (capacity), the domain
+// statistics (launch shape), and one state readback per chunk of sweep
+// launches (the stop decision itself is taken on the device).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+
+#include "cd_internal.h"
+
+#define CD_TRY(expr)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      c->err = std::string(#expr) + ": " + hipGetErrorString(e_);                  \
+      return e_ == hipErrorOutOfMemory ? CD_ENOMEM : CD_EHIP;                      \
+    }                                                                              \
+  } while (0)
+
+namespace {
+
+template <typename T>
+hipError_t grow(T** p, int64_t count) {
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  if (count < 1) count = 1;
+  return hipMalloc((void**)p, sizeof(T) * (size_t)count);
+}
+
+template <typename T>
+void release(T** p) {
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+}
+
+int fail(cd_ctx* c, int code, const std::string& msg) {
+  c->err = msg;
+  return code;
+}
+
+// tree shape of Sec. 3.2 / Fig. 8 for P leaves
+void build_tree_shape(cd_ctx* c) {
+  const int P = c->P;
+  const int nodes = 2 * P - 1;
+  c->t_child.assign(2 * nodes, -1);
+  c->t_parent.assign(nodes, -1);
+  c->t_leaf.assign(nodes, -1);
+  c->t_leaves.assign(nodes, 1);
+  c->t_level_first.clear();
+  c->t_level_count.clear();
+  int created = 1;
+  if (P > 1) {
+    int l = 0;
+    while ((1 << (l + 1)) < P) ++l;   // 2^l < P <= 2^(l+1)
+    int begin = 0, size = 1;
+    auto branch = [&](int node) {
+      c->t_child[2 * node] = created;
+      c->t_child[2 * node + 1] = created + 1;
+      c->t_parent[created] = node;
+      c->t_parent[created + 1] = node;
+      created += 2;
+    };
+    for (int m = 0; m < l; ++m) {
+      c->t_level_first.push_back(begin);
+      c->t_level_count.push_back(size);
+      for (int q = 0; q < size; ++q) branch(begin + q);
+      begin += size;
+      size *= 2;
+    }
+    int extra = P - (1 << l);
+    c->t_level_first.push_back(begin);
+    c->t_level_count.push_back(extra);
+    for (int q = 0; q < extra; ++q) branch(begin + q);
+  }
+  // leaves left to right
+  std::vector<int> stack;
+  stack.push_back(0);
+  int next = 0;
+  while (!stack.empty()) {
+    int node = stack.back();
+    stack.pop_back();
+    if (c->t_child[2 * node] < 0) {
+      c->t_leaf[node] = next++;
+    } else {
+      stack.push_back(c->t_child[2 * node + 1]);
+      stack.push_back(c->t_child[2 * node]);
+    }
+  }
+  for (int node = nodes - 1; node >= 0; --node)
+    if (c->t_child[2 * node] >= 0)
+      c->t_leaves[node] = c->t_leaves[c->t_child[2 * node]] + c->t_leaves[c->t_child[2 * node + 1]];
+  c->h_axis.assign(nodes, -1);
+  c->h_cut.assign(nodes, 0.0);
+}
+
+int alloc_tree(cd_ctx* c) {
+  const int nodes = 2 * c->P - 1;
+  CD_TRY(grow(&c->d_child, 2 * nodes));
+  CD_TRY(grow(&c->d_leaf, nodes));
+  CD_TRY(grow(&c->d_leaves, nodes));
+  CD_TRY(grow(&c->d_parent, nodes));
+  CD_TRY(grow(&c->d_axis, nodes));
+  CD_TRY(grow(&c->d_cut, nodes));
+  CD_TRY(grow(&c->d_seg_start, nodes));
+  CD_TRY(grow(&c->d_seg_end, nodes));
+  CD_TRY(grow(&c->d_nl, nodes));
+  CD_TRY(grow(&c->d_region, 6 * (int64_t)(nodes + 1)));
+  CD_TRY(hipMemcpy(c->d_child, c->t_child.data(), sizeof(int) * 2 * nodes, hipMemcpyHostToDevice));
+  CD_TRY(hipMemcpy(c->d_leaf, c->t_leaf.data(), sizeof(int) * nodes, hipMemcpyHostToDevice));
+  CD_TRY(hipMemcpy(c->d_leaves, c->t_leaves.data(), sizeof(int) * nodes, hipMemcpyHostToDevice));
+  CD_TRY(hipMemcpy(c->d_parent, c->t_parent.data(), sizeof(int) * nodes, hipMemcpyHostToDevice));
+  // per-domain arrays
+  const int P = c->P;
+  CD_TRY(grow(&c->dom_count, P + 1));
+  CD_TRY(grow(&c->dom_start, P + 1));
+  CD_TRY(grow(&c->dom_cursor, P + 1));
+  CD_TRY(grow(&c->dcol, (int64_t)P * (CD_MAX_COLORS + 1)));
+  CD_TRY(grow(&c->dncol, P));
+  CD_TRY(grow(&c->dp_count, P));
+  int grid = 8 * ((P + 7) / 8);
+  CD_TRY(grow(&c->partial, grid));
+  c->partial_cap = grid;
+  return CD_OK;
+}
+
+// capacity of every contact-sized array except the (ci, cj, R) pair lists
+int ensure_capacity(cd_ctx* c, int64_t need) {
+  if (need <= c->cap && c->cap > 0) return CD_OK;
+  int64_t cap = need + need / 4 + 1024;
+  const int rec = c->dim == 2 ? 4 : 12;
+  CD_TRY(grow(&c->dom, cap));
+  CD_TRY(grow(&c->color, cap));
+  CD_TRY(grow(&c->nrm, c->dim * cap));
+  CD_TRY(grow(&c->gap, cap));
+  CD_TRY(grow(&c->xmid, c->dim * cap));
+  for (int k = 0; k < 2; ++k) {
+    CD_TRY(grow(&c->sort_keys[k], cap));
+    CD_TRY(grow(&c->sort_vals[k], cap));
+    CD_TRY(grow(&c->rec[k], rec * cap));
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (k < c->dim) CD_TRY(grow(&c->perm[k], cap));
+  }
+  CD_TRY(grow(&c->perm_tmp, cap));
+  CD_TRY(grow(&c->cnode, cap));
+  CD_TRY(grow(&c->side, cap));
+  CD_TRY(grow(&c->flag, cap));
+  CD_TRY(grow(&c->flag_scan, cap + 1));
+  CD_TRY(grow(&c->bucket, cap));
+  CD_TRY(grow(&c->slot_contact, cap));
+  CD_TRY(grow(&c->contact_slot, cap));
+  CD_TRY(grow(&c->slot_ab, cap));
+  CD_TRY(grow(&c->geo, (int64_t)G_COUNT * cap));
+  CD_TRY(grow(&c->dp, 2 * cap));
+  CD_TRY(grow(&c->inc, 2 * cap));
+  c->cap = cap;
+  return CD_OK;
+}
+
+int ensure_list(cd_ctx* c, int64_t need, int64_t* cap, int** ci, int** cj, double** R) {
+  if (need <= *cap && *cap > 0) return CD_OK;
+  int64_t nc = need + need / 4 + 1024;
+  CD_TRY(grow(ci, nc));
+  CD_TRY(grow(cj, nc));
+  CD_TRY(grow(R, c->dim * nc));
+  *cap = nc;
+  return CD_OK;
+}
+
+int setup_grid(cd_ctx* c) {
+  double a = 2.2 * c->rmax;
+  int64_t total = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (k < c->dim) {
+      double len = c->hi[k] - c->lo[k];
+      int64_t m = (int64_t)floor(len / a);
+      if (m < 1) m = 1;
+      if (m > 4096) m = 4096;
+      c->ncell[k] = (int)m;
+      c->cwidth[k] = len / (double)m;
+    } else {
+      c->ncell[k] = 1;
+      c->cwidth[k] = 1.0;
+    }
+    total *= c->ncell[k];
+  }
+  if (total > c->cells_cap) {
+    CD_TRY(grow(&c->cell_count, total + 1));
+    CD_TRY(grow(&c->cell_start, total + 1));
+    c->cells_cap = total;
+  }
+  c->ncells = total;
+  return CD_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0f;
+  return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cd_status_string(int s) {
+  switch (s) {
+    case CD_OK: return "ok";
+    case CD_MAXITER: return "sweep cap reached before convergence";
+    case CD_EINVAL: return "invalid argument";
+    case CD_ENOMEM: return "device allocation failed";
+    case CD_ECAPACITY: return "per-domain capacity exceeded";
+    case CD_ENONFINITE: return "non-finite value";
+    case CD_EHIP: return "HIP runtime error";
+    case CD_ENOTREADY: return "particles not set";
+    default: return "unknown status";
+  }
+}
+
+const char* cd_last_error(const cd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* stream) {
+  if (!out || !params) return CD_EINVAL;
+  *out = nullptr;
+  if ((params->dim != 2 && params->dim != 3) || n_particles < 1 || params->n_domains < 1 ||
+      params->n_walls < 0 || params->n_walls > CD_MAX_WALLS || !(params->dt > 0.0) ||
+      n_particles > (int64_t)1 << 30)
+    return CD_EINVAL;
+  cd_ctx* c = new cd_ctx();
+  c->p = *params;
+  if (c->p.repartition_every < 1) c->p.repartition_every = 1;
+  c->dim = params->dim;
+  c->dr = c->dim == 2 ? 1 : 3;
+  c->n = n_particles;
+  c->W = params->n_walls;
+  c->P = params->n_domains;
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return CD_EHIP;
+  }
+  const int64_t n = c->n;
+  int st = CD_OK;
+  auto alloc = [&](double** p, int64_t k) {
+    if (st == CD_OK && grow(p, k) != hipSuccess) st = CD_ENOMEM;
+  };
+  auto alloci = [&](int** p, int64_t k) {
+    if (st == CD_OK && grow(p, k) != hipSuccess) st = CD_ENOMEM;
+  };
+  alloc(&c->x, c->dim * n);
+  alloc(&c->v, c->dim * n);
+  alloc(&c->w, c->dr * n);
+  alloc(&c->r, n);
+  alloc(&c->m, n);
+  alloc(&c->I, n);
+  alloc(&c->f, c->dim * n);
+  alloc(&c->t, c->dr * n);
+  alloc(&c->inv_m, n);
+  alloc(&c->inv_I, n);
+  alloc(&c->dtim, n);
+  alloc(&c->dtii, n);
+  alloc(&c->d_wall, (int64_t)CD_MAX_WALLS * 7);
+  alloci(&c->cell_of, n);
+  alloci(&c->cell_members, n);
+  alloci(&c->pair_count, n + 1);
+  alloci(&c->pair_off, n + 1);
+  alloci(&c->inc_count, n + 1);
+  alloci(&c->inc_ptr, n + 1);
+  alloci(&c->inc_cursor, n + 1);
+  if (st == CD_OK && hipMalloc((void**)&c->d_state, sizeof(SolveState)) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK && hipMalloc((void**)&c->d_stats, sizeof(DomainStats)) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK && hipMalloc((void**)&c->d_vmax, sizeof(unsigned long long)) != hipSuccess)
+    st = CD_ENOMEM;
+  if (st == CD_OK && hipHostMalloc((void**)&c->h_state, sizeof(SolveState)) != hipSuccess)
+    st = CD_ENOMEM;
+  if (st == CD_OK && hipHostMalloc((void**)&c->h_scratch, 64) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK) {
+    build_tree_shape(c);
+    st = alloc_tree(c);
+  }
+  for (int k = 0; k < 8 && st == CD_OK; ++k)
+    if (hipEventCreate(&c->ev[k]) != hipSuccess) st = CD_EHIP;
+  if (st == CD_OK && hipMemset(c->t, 0, sizeof(double) * c->dr * n) != hipSuccess) st = CD_EHIP;
+  if (st == CD_OK && hipMemset(c->f, 0, sizeof(double) * c->dim * n) != hipSuccess) st = CD_EHIP;
+  if (st != CD_OK) {
+    cd_destroy(c);
+    return st;
+  }
+  *out = c;
+  return CD_OK;
+}
+
+int cd_destroy(cd_ctx* c) {
+  if (!c) return CD_OK;
+  (void)hipDeviceSynchronize();
+  double** dbl[] = {&c->x, &c->v, &c->w, &c->r, &c->m, &c->I, &c->f, &c->t, &c->inv_m,
+                    &c->inv_I, &c->dtim, &c->dtii, &c->d_wall, &c->nrm, &c->gap, &c->xmid,
+                    &c->R, &c->R_prev, &c->d_cut, &c->d_region, &c->geo, &c->rec[0],
+                    &c->rec[1]};
+  for (auto p : dbl) release(p);
+  int** ints[] = {&c->cell_of, &c->cell_count, &c->cell_start, &c->cell_members,
+                  &c->pair_count, &c->pair_off, &c->ci, &c->cj, &c->dom, &c->color,
+                  &c->ci_prev, &c->cj_prev, &c->d_child, &c->d_leaf, &c->d_leaves,
+                  &c->d_parent, &c->d_axis, &c->d_seg_start, &c->d_seg_end, &c->d_nl,
+                  &c->sort_vals[0], &c->sort_vals[1], &c->perm[0], &c->perm[1], &c->perm[2],
+                  &c->perm_tmp, &c->cnode, &c->side, &c->flag, &c->flag_scan, &c->dom_count,
+                  &c->dom_start, &c->dom_cursor, &c->bucket, &c->slot_contact,
+                  &c->contact_slot, &c->dcol, &c->dncol, &c->dp, &c->dp_count, &c->inc_count,
+                  &c->inc_ptr, &c->inc_cursor, &c->inc, &c->scan_tmp};
+  for (auto p : ints) release(p);
+  release(&c->sort_keys[0]);
+  release(&c->sort_keys[1]);
+  release(&c->sort_hist);
+  release(&c->slot_ab);
+  release(&c->d_state);
+  release(&c->d_stats);
+  release(&c->partial);
+  release(&c->d_vmax);
+  if (c->h_state) (void)hipHostFree(c->h_state);
+  if (c->h_scratch) (void)hipHostFree(c->h_scratch);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->sweep_ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+  return CD_OK;
+}
+
+int cd_set_particles(cd_ctx* c, const double* x, const double* v, const double* w,
+                     const double* radius, const double* mass, const double* inertia) {
+  if (!c || !x || !v || !radius || !mass || !inertia) return CD_EINVAL;
+  const int64_t n = c->n;
+  auto cp = [&](double* dst, const double* src, int64_t k) {
+    return hipMemcpyAsync(dst, src, sizeof(double) * (size_t)k, hipMemcpyDeviceToDevice, c->stream);
+  };
+  CD_TRY(cp(c->x, x, c->dim * n));
+  CD_TRY(cp(c->v, v, c->dim * n));
+  if (w) CD_TRY(cp(c->w, w, c->dr * n));
+  else CD_TRY(hipMemsetAsync(c->w, 0, sizeof(double) * c->dr * n, c->stream));
+  CD_TRY(cp(c->r, radius, n));
+  CD_TRY(cp(c->m, mass, n));
+  CD_TRY(cp(c->I, inertia, n));
+  // radii, masses and moments of inertia must be positive and finite
+  std::vector<double> h(3 * n);
+  CD_TRY(hipMemcpyAsync(h.data(), radius, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  CD_TRY(hipMemcpyAsync(h.data() + n, mass, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  CD_TRY(hipMemcpyAsync(h.data() + 2 * n, inertia, sizeof(double) * n, hipMemcpyDeviceToHost,
+                        c->stream));
+  CD_TRY(hipStreamSynchronize(c->stream));
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(h[i] > 0.0) || !(h[n + i] > 0.0) || !(h[2 * n + i] > 0.0) || !isfinite(h[i]) ||
+        !isfinite(h[n + i]) || !isfinite(h[2 * n + i]))
+      return fail(c, CD_EINVAL, "radius, mass and inertia must be positive and finite");
+    if (h[i] > rmax) rmax = h[i];
+  }
+  c->rmax = rmax;
+  CD_TRY(cd_launch_derived(c));
+  c->have_particles = true;
+  c->have_tree = false;
+  c->step = 0;
+  c->nc_prev = 0;
+  return CD_OK;
+}
+
+int cd_set_external(cd_ctx* c, const double* force, const double* torque) {
+  if (!c) return CD_EINVAL;
+  const int64_t n = c->n;
+  if (force)
+    CD_TRY(hipMemcpyAsync(c->f, force, sizeof(double) * c->dim * n, hipMemcpyDeviceToDevice,
+                          c->stream));
+  else
+    CD_TRY(hipMemsetAsync(c->f, 0, sizeof(double) * c->dim * n, c->stream));
+  if (torque)
+    CD_TRY(hipMemcpyAsync(c->t, torque, sizeof(double) * c->dr * n, hipMemcpyDeviceToDevice,
+                          c->stream));
+  else
+    CD_TRY(hipMemsetAsync(c->t, 0, sizeof(double) * c->dr * n, c->stream));
+  return CD_OK;
+}
+
+static int upload_walls(cd_ctx* c) {
+  double buf[CD_MAX_WALLS * 7];
+  const int W = c->W, dim = c->dim;
+  for (int k = 0; k < W * dim; ++k) buf[k] = c->wn[k];
+  for (int k = 0; k < W; ++k) buf[W * dim + k] = c->wo[k];
+  for (int k = 0; k < W * dim; ++k) buf[W * dim + W + k] = c->wu[k];
+  if (W > 0)
+    CD_TRY(hipMemcpyAsync(c->d_wall, buf, sizeof(double) * (size_t)(W * (2 * dim + 1)),
+                          hipMemcpyHostToDevice, c->stream));
+  // the host buffer must outlive the copy
+  CD_TRY(hipStreamSynchronize(c->stream));
+  return CD_OK;
+}
+
+int cd_set_walls(cd_ctx* c, const double* normal, const double* offset, const double* velocity) {
+  if (!c) return CD_EINVAL;
+  const int W = c->W, dim = c->dim;
+  if (W > 0 && (!normal || !offset)) return CD_EINVAL;
+  for (int k = 0; k < W * dim; ++k) {
+    c->wn[k] = normal[k];
+    c->wu[k] = velocity ? velocity[k] : 0.0;
+  }
+  for (int k = 0; k < W; ++k) c->wo[k] = offset[k];
+  return upload_walls(c);
+}
+
+int cd_set_box(cd_ctx* c, const double* lo, const double* hi) {
+  if (!c || !lo || !hi) return CD_EINVAL;
+  for (int k = 0; k < 3; ++k) {
+    c->lo[k] = k < c->dim ? lo[k] : 0.0;
+    c->hi[k] = k < c->dim ? hi[k] : 0.0;
+    if (k < c->dim && !(hi[k] > lo[k])) return fail(c, CD_EINVAL, "box must have hi > lo");
+  }
+  c->have_box = true;
+  return CD_OK;
+}
+
+int cd_set_timing(cd_ctx* c, int per_sweep_events) {
+  if (!c) return CD_EINVAL;
+  c->time_sweeps = per_sweep_events != 0;
+  return CD_OK;
+}
+
+int cd_step(cd_ctx* c, cd_result* out) {
+  if (!c) return CD_EINVAL;
+  if (!c->have_particles || !c->have_box) return fail(c, CD_ENOTREADY, "particles or box not set");
+  const int dim = c->dim;
+  const double dt = c->p.dt;
+  CD_TRY(hipEventRecord(c->ev[0], c->stream));
+  // ---- boundary width: 2 vmax dt (Sec. 3.1)
+  CD_TRY(cd_launch_vmax(c));
+  CD_TRY(hipMemcpyAsync(c->h_scratch, c->d_vmax, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                        c->stream));
+  CD_TRY(hipStreamSynchronize(c->stream));
+  double vmax;
+  {
+    unsigned long long bits = (unsigned long long)c->h_scratch[0];
+    memcpy(&vmax, &bits, sizeof(double));
+  }
+  for (int wi = 0; wi < c->W; ++wi) {
+    double q = 0.0;
+    for (int k = 0; k < dim; ++k) q = q + c->wu[wi * dim + k] * c->wu[wi * dim + k];
+    double sp = sqrt(q);
+    if (sp > vmax) vmax = sp;
+  }
+  if (!isfinite(vmax)) return fail(c, CD_ENONFINITE, "non-finite velocity");
+  const double skin = c->p.skin >= 0.0 ? c->p.skin : 2.0 * vmax * dt;
+  if (!(skin <= 0.2 * c->rmax))
+    return fail(c, CD_EINVAL, "boundary width exceeds 0.2 r_max (displacement bound)");
+  // ---- the previous step's list becomes the warm-start source
+  std::swap(c->ci, c->ci_prev);
+  std::swap(c->cj, c->cj_prev);
+  std::swap(c->R, c->R_prev);
+  std::swap(c->cap_prev, c->cap_list);
+  c->nc_prev = c->step > 0 ? c->nc : 0;
+  // ---- cells and pair search
+  int st = setup_grid(c);
+  if (st != CD_OK) return st;
+  CD_TRY(cd_launch_cells(c));
+  CD_TRY(cd_launch_pair_count(c, skin));
+  CD_TRY(hipMemcpyAsync(c->h_scratch, c->pair_off + c->n, sizeof(int), hipMemcpyDeviceToHost,
+                        c->stream));
+  CD_TRY(hipStreamSynchronize(c->stream));
+  const int64_t nc = (int64_t)((int*)c->h_scratch)[0];
+  if (nc < 0 || nc > ((int64_t)1 << 30)) return fail(c, CD_ECAPACITY, "too many contacts");
+  st = ensure_capacity(c, nc);
+  if (st != CD_OK) return st;
+  st = ensure_list(c, nc, &c->cap_list, &c->ci, &c->cj, &c->R);
+  if (st != CD_OK) return st;
+  c->nc = nc;
+  CD_TRY(cd_launch_pair_fill(c, skin));
+  CD_TRY(cd_launch_geometry(c));
+  CD_TRY(cd_launch_warm_start(c));
+  CD_TRY(hipEventRecord(c->ev[1], c->stream));
+  // ---- partition (Sec. 3.2)
+  if (!c->have_tree || c->step % c->p.repartition_every == 0) {
+    CD_TRY(cd_launch_orb(c));
+    c->have_tree = true;
+  } else {
+    CD_TRY(cd_launch_descend(c));
+  }
+  CD_TRY(hipEventRecord(c->ev[2], c->stream));
+  // ---- order
+  CD_TRY(cd_launch_order(c));
+  CD_TRY(hipMemcpyAsync(c->h_scratch, c->d_stats, sizeof(DomainStats), hipMemcpyDeviceToHost,
+                        c->stream));
+  CD_TRY(hipStreamSynchronize(c->stream));
+  DomainStats ds;
+  memcpy(&ds, c->h_scratch, sizeof(DomainStats));
+  if (ds.overflow)
+    return fail(c, CD_ECAPACITY,
+                ds.overflow == 1 ? "a domain has more than 1024 contacts"
+                                 : "a domain needs more than 64 colours");
+  const int dr = c->dr;
+  const size_t per_particle = (size_t)(dim + dr + 3) * sizeof(double);
+  const size_t lds = per_particle * (size_t)std::max(ds.max_particles, 1);
+  if (lds > 64 * 1024) return fail(c, CD_ECAPACITY, "domain particle set exceeds 64 KiB of LDS");
+  c->sweep_lds = lds;
+  c->sweep_threads = ds.max_contacts > 512 ? 256 : (ds.max_contacts > 128 ? 128 : 64);
+  CD_TRY(hipEventRecord(c->ev[3], c->stream));
+  // ---- iterative solve
+  const int limit = c->p.fixed_iters > 0 ? c->p.fixed_iters : c->p.max_iter;
+  CD_TRY(cd_launch_solve_init(c, limit));
+  int launched = 0;
+  int chunk = c->last.iterations > 8 ? c->last.iterations - 2 : 16;
+  if (c->p.fixed_iters > 0) chunk = limit;
+  if (c->time_sweeps && (int)c->sweep_ev.size() < 2 * limit) {
+    size_t old = c->sweep_ev.size();
+    c->sweep_ev.resize(2 * (size_t)limit, nullptr);
+    for (size_t k = old; k < c->sweep_ev.size(); ++k) CD_TRY(hipEventCreate(&c->sweep_ev[k]));
+  }
+  c->h_state->done = nc == 0 || limit <= 0;
+  while (!c->h_state->done && launched < limit) {
+    int k = std::min(chunk, limit - launched);
+    for (int q = 0; q < k; ++q) {
+      if (c->time_sweeps) CD_TRY(hipEventRecord(c->sweep_ev[2 * (launched + q)], c->stream));
+      CD_TRY(cd_launch_sweep(c));
+      if (c->time_sweeps) CD_TRY(hipEventRecord(c->sweep_ev[2 * (launched + q) + 1], c->stream));
+    }
+    launched += k;
+    CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
+                          c->stream));
+    CD_TRY(hipStreamSynchronize(c->stream));
+    chunk = 16;
+  }
+  if (nc == 0 || limit <= 0) {
+    CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
+                          c->stream));
+    CD_TRY(hipStreamSynchronize(c->stream));
+  }
+  SolveState s;
+  memcpy(&s, c->h_state, sizeof(SolveState));
+  CD_TRY(hipEventRecord(c->ev[4], c->stream));
+  // ---- Euler update and canonical forces
+  CD_TRY(cd_launch_unslot(c, s.iter));
+  CD_TRY(cd_launch_update(c, s.iter));
+  CD_TRY(hipEventRecord(c->ev[5], c->stream));
+  CD_TRY(hipStreamSynchronize(c->stream));
+  // walls move; a box face follows the axis-aligned wall lying on it
+  for (int wi = 0; wi < c->W; ++wi) {
+    double un = 0.0;
+    for (int k = 0; k < dim; ++k) un = un + c->wn[wi * dim + k] * c->wu[wi * dim + k];
+    c->wo[wi] = c->wo[wi] + dt * un;
+    for (int k = 0; k < dim; ++k) {
+      bool unit = true;
+      for (int q = 0; q < dim; ++q)
+        if (q != k && c->wn[wi * dim + q] != 0.0) unit = false;
+      if (!unit) continue;
+      if (c->wn[wi * dim + k] == 1.0) c->lo[k] = c->wo[wi];
+      if (c->wn[wi * dim + k] == -1.0) c->hi[k] = -c->wo[wi];
+    }
+  }
+  st = upload_walls(c);
+  if (st != CD_OK) return st;
+  c->step += 1;
+  // ---- result and timings
+  cd_result res{};
+  res.status = nc == 0 ? CD_OK : s.status;
+  res.iterations = s.iter;
+  res.n_contacts = nc;
+  res.n_pass = s.n_pass;
+  res.max_d_fail = s.max_d_fail;
+  res.r_avg = s.r_avg;
+  res.r_avg_prev = s.r_avg_prev;
+  res.skin = skin;
+  res.max_colors = ds.max_colors;
+  res.max_domain_contacts = ds.max_contacts;
+  c->last = res;
+  cd_timing tm{};
+  tm.detect_ms = elapsed(c->ev[0], c->ev[1]);
+  tm.partition_ms = elapsed(c->ev[1], c->ev[2]);
+  tm.order_ms = elapsed(c->ev[2], c->ev[3]);
+  tm.solve_ms = elapsed(c->ev[3], c->ev[4]);
+  tm.update_ms = elapsed(c->ev[4], c->ev[5]);
+  tm.sweep_launches = launched;
+  double sk = 0.0;
+  if (c->time_sweeps)
+    for (int q = 0; q < std::min(launched, s.iter); ++q)
+      sk += elapsed(c->sweep_ev[2 * q], c->sweep_ev[2 * q + 1]);
+  tm.sweep_kernel_ms = sk;
+  c->timing = tm;
+  if (out) *out = res;
+  if (res.status == CD_ENONFINITE) return fail(c, CD_ENONFINITE, "non-finite contact force");
+  return res.status;
+}
+
+int cd_get_state(cd_ctx* c, double* x, double* v, double* w) {
+  if (!c) return CD_EINVAL;
+  const int64_t n = c->n;
+  if (x) CD_TRY(hipMemcpyAsync(x, c->x, sizeof(double) * c->dim * n, hipMemcpyDeviceToDevice, c->stream));
+  if (v) CD_TRY(hipMemcpyAsync(v, c->v, sizeof(double) * c->dim * n, hipMemcpyDeviceToDevice, c->stream));
+  if (w) CD_TRY(hipMemcpyAsync(w, c->w, sizeof(double) * c->dr * n, hipMemcpyDeviceToDevice, c->stream));
+  CD_TRY(hipStreamSynchronize(c->stream));
+  return CD_OK;
+}
+
+int cd_get_walls(cd_ctx* c, double* offset) {
+  if (!c || (!offset && c->W > 0)) return CD_EINVAL;
+  for (int k = 0; k < c->W; ++k) offset[k] = c->wo[k];
+  return CD_OK;
+}
+
+int64_t cd_num_contacts(const cd_ctx* c) { return c ? c->nc : 0; }
+
+int cd_get_contacts(cd_ctx* c, int64_t cap, int32_t* ci, int32_t* cj, double* normal, double* gap,
+                    double* R, int32_t* dom, int32_t* color, int32_t* slot_contact) {
+  if (!c) return CD_EINVAL;
+  const int64_t nc = c->nc;
+  if (cap < nc) return fail(c, CD_EINVAL, "output capacity below the contact count");
+  if (nc == 0) return CD_OK;
+  auto cpi = [&](int32_t* d, const int* s) {
+    return d ? hipMemcpyAsync(d, s, sizeof(int) * nc, hipMemcpyDeviceToDevice, c->stream)
+             : hipSuccess;
+  };
+  auto cpd = [&](double* d, const double* s, int64_t k) {
+    return d ? hipMemcpyAsync(d, s, sizeof(double) * k, hipMemcpyDeviceToDevice, c->stream)
+             : hipSuccess;
+  };
+  CD_TRY(cpi(ci, c->ci));
+  CD_TRY(cpi(cj, c->cj));
+  CD_TRY(cpd(normal, c->nrm, c->dim * nc));
+  CD_TRY(cpd(gap, c->gap, nc));
+  CD_TRY(cpd(R, c->R, c->dim * nc));
+  CD_TRY(cpi(dom, c->dom));
+  CD_TRY(cpi(color, c->color));
+  CD_TRY(cpi(slot_contact, c->slot_contact));
+  CD_TRY(hipStreamSynchronize(c->stream));
+  return CD_OK;
+}
+
+int cd_get_tree(cd_ctx* c, int32_t* axis, double* cut, int32_t* child, int32_t* leaf) {
+  if (!c) return CD_EINVAL;
+  const int nodes = 2 * c->P - 1;
+  if (axis) CD_TRY(hipMemcpyAsync(axis, c->d_axis, sizeof(int) * nodes, hipMemcpyDeviceToHost, c->stream));
+  if (cut) CD_TRY(hipMemcpyAsync(cut, c->d_cut, sizeof(double) * nodes, hipMemcpyDeviceToHost, c->stream));
+  CD_TRY(hipStreamSynchronize(c->stream));
+  if (child) memcpy(child, c->t_child.data(), sizeof(int) * 2 * nodes);
+  if (leaf) memcpy(leaf, c->t_leaf.data(), sizeof(int) * nodes);
+  return CD_OK;
+}
+
+int cd_get_timing(cd_ctx* c, cd_timing* out) {
+  if (!c || !out) return CD_EINVAL;
+  *out = c->timing;
+  return CD_OK;
+}
+
+}  // extern "C"

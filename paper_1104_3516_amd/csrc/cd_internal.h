@@ -1,0 +1,241 @@
+// cd_internal.h - context layout and kernel launch wrappers of libcdhip.
+//
+// Data layout in device memory (FP64 structure-of-arrays unless noted):
+//   particles (canonical order i = 0..N-1): x, v (dim x N), w (dr x N), r, m,
+//     inertia, f (dim x N), t (dr x N), and the derived 1/m, 1/I, dt/m, dt/I;
+//   contacts in canonical (i, j) order: ci, cj, normal (dim x nc), gap,
+//     xmid (dim x nc), R (dim x nc, contact frame), dom;
+//   contacts in domain-major update order ("slots"): each domain d owns the
+//     slot range [dom_start[d], dom_start[d+1]) sorted by (colour, contact id);
+//     per slot: local body indices (a, b), frame (n, and t1, t2 in 3D) and the
+//     constants of the force law; forces live in two ping-pong record arrays
+//     rec[0], rec[1] of REC doubles per slot:
+//       2D: (R_n, R_t, F_x, F_y)  with F = R_n n + R_t t the world force,
+//       3D: (R_n, R_t1, R_t2, 0, F_x, F_y, F_z, 0, q_x, q_y, q_z, 0) with
+//           q = n x R (torque per unit lever);
+//   per domain: its particles (ascending id) and colour offsets;
+//   per particle: incident slots in ascending contact id (sign bit = body 2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cdhip.h"
+
+#define CD_MAX_COLORS 64     // colours per domain (64-bit masks)
+#define CD_MAX_DC 1024       // contacts per domain
+#define CD_MAX_DP 2048       // particles per domain
+#define CD_MAX_WALLS 8
+
+struct SolveState {
+  int iter;           // sweeps completed
+  int done;           // 1 once converged, capped or failed
+  int status;         // CD_OK, CD_MAXITER or CD_ENONFINITE
+  unsigned arrive;    // blocks arrived in the current sweep
+  long long n_pass;
+  double max_d_fail;
+  double r_avg;
+  double r_avg_prev;
+  int conv;
+  int pad;
+};
+
+struct DomainStats {
+  int max_colors;
+  int max_contacts;
+  int max_particles;
+  int overflow;       // a domain exceeded CD_MAX_DC / CD_MAX_DP / CD_MAX_COLORS
+};
+
+struct BlockPartial {
+  long long n_pass;
+  double max_d_fail;
+  double sum_r;
+  long long pad;
+};
+
+// Arguments of the sweep kernels (passed by value).
+struct SweepArgs {
+  // domains
+  const int* dom_start;     // P+1 slot offsets
+  const int* dcol;          // P x (CD_MAX_COLORS+1) colour offsets inside the domain
+  const int* dncol;         // P colours per domain
+  const int* dp;            // domain particles, 2 entries reserved per slot
+  const int* dp_count;      // P
+  // particles
+  const double* v;
+  const double* w;
+  const double* f;
+  const double* t;
+  const double* r;
+  const double* dtim;
+  const double* dtii;
+  const int* inc_ptr;       // N+1
+  const int* inc;           // incident slots * 2 + (1 if body 2)
+  // slots
+  const int2* ab;           // local body indices; b < 0: wall -1-b
+  const double* geo;        // per-slot constants, SoA with stride cap
+  const double* walls_u;    // W x dim wall velocities
+  double* rec[2];
+  // convergence
+  SolveState* state;
+  BlockPartial* partial;
+  int P;
+  int n;                    // particles (SoA stride)
+  int cap;                  // slot capacity (SoA stride of geo)
+  int grid;                 // blocks in the launch
+  int per_xcd;              // domains per XCD in the block -> domain map
+  long long nc;
+  double alpha;
+  double mu;
+  int criterion;
+  int fixed_iters;
+  int max_iter;
+};
+
+// Per-slot constants, index k of geo (each block of `cap` doubles):
+enum {
+  G_N0 = 0,     // normal, dim components
+  G_T10 = 3,    // t1 (3D only)
+  G_T20 = 6,    // t2 (3D only)
+  G_GDT = 9,    // g_e / dt
+  G_DWN = 10,   // dt w_n
+  G_DWT = 11,   // dt w_t
+  G_KN = 12,    // 1 / (dt w_n)
+  G_KT = 13,    // 1 / (dt w_t)
+  G_COUNT = 14
+};
+
+struct cd_ctx {
+  cd_params p{};
+  int dim = 2, dr = 1;
+  int64_t n = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  bool have_particles = false;
+  double rmax = 0.0;
+  int64_t step = 0;
+
+  // particles
+  double *x = nullptr, *v = nullptr, *w = nullptr, *r = nullptr, *m = nullptr, *I = nullptr;
+  double *f = nullptr, *t = nullptr, *inv_m = nullptr, *inv_I = nullptr, *dtim = nullptr,
+         *dtii = nullptr;
+  // walls (host copies, and a device copy of the velocities)
+  int W = 0;
+  double wn[CD_MAX_WALLS * 3] = {0}, wo[CD_MAX_WALLS] = {0}, wu[CD_MAX_WALLS * 3] = {0};
+  double* d_wall = nullptr;     // normals (W x dim), offsets (W), velocities (W x dim)
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  bool have_box = false;
+
+  // cells
+  int ncell[3] = {1, 1, 1};
+  double cwidth[3] = {1, 1, 1};
+  int64_t ncells = 0, cells_cap = 0;
+  int *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_members = nullptr;
+
+  // contacts (canonical)
+  int64_t cap = 0, nc = 0;
+  int *pair_count = nullptr, *pair_off = nullptr;
+  int *ci = nullptr, *cj = nullptr, *dom = nullptr, *color = nullptr;
+  double *nrm = nullptr, *gap = nullptr, *xmid = nullptr, *R = nullptr;
+  int64_t cap_list = 0, cap_prev = 0, nc_prev = 0;
+  int *ci_prev = nullptr, *cj_prev = nullptr;
+  double* R_prev = nullptr;
+
+  // tree (host shape + device arrays)
+  int P = 1;
+  std::vector<int> t_child, t_leaf, t_leaves, t_parent, t_level_first, t_level_count;
+  std::vector<int> h_axis;
+  std::vector<double> h_cut;
+  int* d_child = nullptr;
+  int* d_leaf = nullptr;
+  int* d_leaves = nullptr;
+  int* d_parent = nullptr;
+  int* d_axis = nullptr;
+  double* d_cut = nullptr;
+  int *d_seg_start = nullptr, *d_seg_end = nullptr, *d_nl = nullptr;
+  double* d_region = nullptr;   // (2P-1) x 6: lo[3], hi[3]
+  bool have_tree = false;
+  // ORB workspace (cap-sized)
+  unsigned long long* sort_keys[2] = {nullptr, nullptr};
+  int* sort_vals[2] = {nullptr, nullptr};
+  int* perm[3] = {nullptr, nullptr, nullptr};
+  int* perm_tmp = nullptr;
+  int* cnode = nullptr;
+  int* side = nullptr;
+  int* flag = nullptr;
+  int* flag_scan = nullptr;
+  unsigned* sort_hist = nullptr;
+  int64_t sort_hist_cap = 0;
+
+  // order / slots
+  int *dom_count = nullptr, *dom_start = nullptr, *dom_cursor = nullptr, *bucket = nullptr;
+  int *slot_contact = nullptr, *contact_slot = nullptr;
+  int2* slot_ab = nullptr;
+  double* geo = nullptr;
+  double* rec[2] = {nullptr, nullptr};
+  int *dcol = nullptr, *dncol = nullptr, *dp = nullptr, *dp_count = nullptr;
+  int *inc_count = nullptr, *inc_ptr = nullptr, *inc_cursor = nullptr, *inc = nullptr;
+  DomainStats* d_stats = nullptr;
+
+  // solve
+  SolveState* d_state = nullptr;
+  SolveState* h_state = nullptr;   // pinned
+  BlockPartial* partial = nullptr;
+  int partial_cap = 0;
+  unsigned long long* d_vmax = nullptr;
+  long long* h_scratch = nullptr;  // pinned small readbacks
+
+  // scan workspace
+  int* scan_tmp = nullptr;
+  int64_t scan_tmp_cap = 0;
+
+  // sweep launch shape
+  int sweep_threads = 64;
+  size_t sweep_lds = 0;
+
+  // timing
+  hipEvent_t ev[8] = {};
+  std::vector<hipEvent_t> sweep_ev;
+  bool time_sweeps = true;
+  cd_timing timing{};
+  cd_result last{};
+};
+
+// ---- launch wrappers (each enqueues on ctx->stream) -----------------------
+// scan.hip
+hipError_t cd_scan_exclusive(cd_ctx* c, const int* in, int* out, int64_t n);
+// sort.hip: stable LSD radix sort of (key, value) pairs, `bits` low key bits
+hipError_t cd_radix_sort(cd_ctx* c, unsigned long long* keys, int* vals, unsigned long long* keys_tmp,
+                         int* vals_tmp, int64_t n, int bits, unsigned long long** keys_out,
+                         int** vals_out);
+// detect.hip
+hipError_t cd_launch_vmax(cd_ctx* c);
+hipError_t cd_launch_cells(cd_ctx* c);
+hipError_t cd_launch_pair_count(cd_ctx* c, double skin);
+hipError_t cd_launch_pair_fill(cd_ctx* c, double skin);
+hipError_t cd_launch_geometry(cd_ctx* c);
+hipError_t cd_launch_warm_start(cd_ctx* c);
+// partition.hip
+hipError_t cd_launch_orb(cd_ctx* c);
+hipError_t cd_launch_descend(cd_ctx* c);
+// order.hip
+hipError_t cd_launch_order(cd_ctx* c);
+// sweep.hip
+hipError_t cd_launch_solve_init(cd_ctx* c, int limit);
+hipError_t cd_launch_sweep(cd_ctx* c);
+hipError_t cd_launch_unslot(cd_ctx* c, int final_iter);
+// update.hip
+hipError_t cd_launch_update(cd_ctx* c, int final_iter);
+hipError_t cd_launch_derived(cd_ctx* c);
+SweepArgs cd_sweep_args(cd_ctx* c);
+
+// helpers
+static inline int cd_blocks(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  return (int)b;
+}

@@ -1,0 +1,87 @@
+// update.hip - per-particle derived constants and the semi-implicit Euler
+// step (Eqs. 1-2 and the rotational analogue): the new velocity is the old
+// one plus dt/m times the external force and every contact force of the
+// final sweep (summed in ascending contact id), and the position moves with
+// the new velocity.
+#include "cd_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ __launch_bounds__(kThreads) void k_derived(const double* m, const double* inertia,
+                                                     int64_t n, double dt, double* inv_m,
+                                                     double* inv_I, double* dtim, double* dtii) {
+  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  double im = 1.0 / m[i], ii = 1.0 / inertia[i];
+  inv_m[i] = im;
+  inv_I[i] = ii;
+  dtim[i] = dt * im;
+  dtii[i] = dt * ii;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_update(double* x, double* v, double* w,
+                                                    const double* f, const double* t,
+                                                    const double* r, const double* dtim,
+                                                    const double* dtii, const int* inc_ptr,
+                                                    const int* inc, const double* rec, int64_t n,
+                                                    double dt) {
+  constexpr int DR = DIM == 2 ? 1 : 3;
+  constexpr int REC = DIM == 2 ? 4 : 12;
+  int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  double acc[DIM], tacc[DR];
+  for (int k = 0; k < DIM; ++k) acc[k] = f[k * n + p];
+  for (int k = 0; k < DR; ++k) tacc[k] = t[k * n + p];
+  const double rp = r[p];
+  for (int e = inc_ptr[p]; e < inc_ptr[p + 1]; ++e) {
+    const int ent = inc[e];
+    const double* rc = rec + (int64_t)(ent >> 1) * REC;
+    if (DIM == 2) {
+      double F0 = rc[2], F1 = rc[3], q = rc[1];
+      if (ent & 1) {
+        acc[0] = acc[0] + F0;
+        acc[1] = acc[1] + F1;
+      } else {
+        acc[0] = acc[0] - F0;
+        acc[1] = acc[1] - F1;
+      }
+      tacc[0] = tacc[0] - rp * q;
+    } else {
+      for (int k = 0; k < 3; ++k) {
+        double F = rc[4 + k];
+        acc[k] = (ent & 1) ? acc[k] + F : acc[k] - F;
+      }
+      for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * rc[8 + k];
+    }
+  }
+  const double dm = dtim[p], di = dtii[p];
+  for (int k = 0; k < DIM; ++k) {
+    double V = v[k * n + p] + dm * acc[k];
+    v[k * n + p] = V;
+    x[k * n + p] = x[k * n + p] + V * dt;
+  }
+  for (int k = 0; k < DR; ++k) w[k * n + p] = w[k * n + p] + di * tacc[k];
+}
+
+}  // namespace
+
+hipError_t cd_launch_derived(cd_ctx* c) {
+  hipLaunchKernelGGL(k_derived, dim3(cd_blocks(c->n, kThreads)), dim3(kThreads), 0, c->stream,
+                     c->m, c->I, c->n, c->p.dt, c->inv_m, c->inv_I, c->dtim, c->dtii);
+  return hipGetLastError();
+}
+
+hipError_t cd_launch_update(cd_ctx* c, int final_iter) {
+  const double* rec = c->rec[final_iter & 1];
+  int nb = cd_blocks(c->n, kThreads);
+  if (c->dim == 2)
+    hipLaunchKernelGGL(k_update<2>, dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->v, c->w, c->f,
+                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->n, c->p.dt);
+  else
+    hipLaunchKernelGGL(k_update<3>, dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->v, c->w, c->f,
+                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->n, c->p.dt);
+  return hipGetLastError();
+}

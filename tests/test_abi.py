@@ -1,0 +1,48 @@
+"""The C-ABI library builds, loads and exports every entry point that
+include/cdhip.h declares (CPU only: no compute calls)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_1104_3516_amd import binding
+
+
+def test_header_declares_the_boundary():
+    names = binding.declared_symbols()
+    for required in ("cd_create", "cd_destroy", "cd_set_particles", "cd_set_external",
+                     "cd_set_walls", "cd_set_box", "cd_step", "cd_get_state",
+                     "cd_get_contacts", "cd_get_tree", "cd_get_timing", "cd_status_string",
+                     "cd_last_error", "cd_num_contacts", "cd_get_walls", "cd_set_timing"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libcdhip.so is not built (run __graft_entry__.build())")
+    L = binding.lib()
+    for name in binding.declared_symbols():
+        assert hasattr(L, name), name
+    # status strings need no device
+    assert L.cd_status_string(0) == b"ok"
+    assert L.cd_status_string(1).startswith(b"sweep cap")
+
+
+def test_struct_layouts_match_header():
+    # the ctypes mirrors have the C sizes of the header structs
+    assert ctypes.sizeof(binding.Params) == 4 * 2 + 8 * 3 + 4 * 8 + 8
+    assert ctypes.sizeof(binding.Result) == 4 * 2 + 8 * 2 + 8 * 4 + 4 * 2
+    assert ctypes.sizeof(binding.Timing) == 8 * 6 + 8
+
+
+def test_product_package_does_not_import_the_oracle():
+    import re
+
+    import paper_1104_3516_amd
+    root = os.path.dirname(paper_1104_3516_amd.__file__)
+    for dirpath, _, files in os.walk(root):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), f
+                assert "cdref" not in text, f
