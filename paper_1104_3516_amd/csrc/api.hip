@@ -124,7 +124,8 @@ int alloc_tree(cd_ctx* c) {
   CD_TRY(grow(&c->dom_cursor, P + 1));
   CD_TRY(grow(&c->dcol, (int64_t)P * (CD_MAX_COLORS + 1)));
   CD_TRY(grow(&c->dncol, P));
-  CD_TRY(grow(&c->dp_count, P));
+  CD_TRY(grow(&c->dp_count, P + 1));
+  CD_TRY(grow(&c->dp_start, P + 1));
   int grid = 8 * ((P + 7) / 8);
   CD_TRY(grow(&c->partial, grid));
   c->partial_cap = grid;
@@ -142,18 +143,25 @@ int ensure_capacity(cd_ctx* c, int64_t need) {
   CD_TRY(grow(&c->gap, cap));
   CD_TRY(grow(&c->xmid, c->dim * cap));
   for (int k = 0; k < 2; ++k) {
-    CD_TRY(grow(&c->sort_keys[k], cap));
-    CD_TRY(grow(&c->sort_vals[k], cap));
+    CD_TRY(grow(&c->sort_keys[k], 2 * cap));
+    CD_TRY(grow(&c->sort_vals[k], 2 * cap));
     CD_TRY(grow(&c->rec[k], rec * cap));
   }
+  CD_TRY(grow(&c->q_la, cap));
+  CD_TRY(grow(&c->q_lb, cap));
+  CD_TRY(grow(&c->q_col, cap));
+  CD_TRY(grow(&c->q_pos, cap));
+  CD_TRY(grow(&c->g_mask, 2 * cap));
+  CD_TRY(grow(&c->dpb, (int64_t)(2 * c->dim + 2 * c->dr + 3) * 2 * cap));
+  CD_TRY(grow(&c->dinc_ptr, 2 * cap + 1));
   for (int k = 0; k < 3; ++k) {
     if (k < c->dim) CD_TRY(grow(&c->perm[k], cap));
   }
   CD_TRY(grow(&c->perm_tmp, cap));
   CD_TRY(grow(&c->cnode, cap));
   CD_TRY(grow(&c->side, cap));
-  CD_TRY(grow(&c->flag, cap));
-  CD_TRY(grow(&c->flag_scan, cap + 1));
+  CD_TRY(grow(&c->flag, 2 * cap));
+  CD_TRY(grow(&c->flag_scan, 2 * cap + 1));
   CD_TRY(grow(&c->bucket, cap));
   CD_TRY(grow(&c->slot_contact, cap));
   CD_TRY(grow(&c->contact_slot, cap));
@@ -247,6 +255,13 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
     delete c;
     return CD_EHIP;
   }
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) ==
+            hipSuccess &&
+        lds > 0)
+      c->max_lds = (size_t)lds;
+  }
   const int64_t n = c->n;
   int st = CD_OK;
   auto alloc = [&](double** p, int64_t k) {
@@ -314,12 +329,18 @@ int cd_destroy(cd_ctx* c) {
                   &c->perm_tmp, &c->cnode, &c->side, &c->flag, &c->flag_scan, &c->dom_count,
                   &c->dom_start, &c->dom_cursor, &c->bucket, &c->slot_contact,
                   &c->contact_slot, &c->dcol, &c->dncol, &c->dp, &c->dp_count, &c->inc_count,
-                  &c->inc_ptr, &c->inc_cursor, &c->inc, &c->scan_tmp};
+                  &c->inc_ptr, &c->inc_cursor, &c->inc, &c->scan_tmp,
+                  &c->dp_start, &c->q_la, &c->q_lb, &c->q_col, &c->q_pos};
   for (auto p : ints) release(p);
   release(&c->sort_keys[0]);
   release(&c->sort_keys[1]);
   release(&c->sort_hist);
   release(&c->slot_ab);
+  release(&c->g_mask);
+  release(&c->gscr);
+  release(&c->dpb);
+  release(&c->dinc_ptr);
+  release(&c->dinc);
   release(&c->d_state);
   release(&c->d_stats);
   release(&c->partial);
@@ -501,10 +522,25 @@ int cd_step(cd_ctx* c, cd_result* out) {
                 ds.overflow == 1 ? "a domain has more than 1024 contacts"
                                  : "a domain needs more than 64 colours");
   const int dr = c->dr;
-  const size_t per_particle = (size_t)(dim + dr + 3) * sizeof(double);
-  const size_t lds = per_particle * (size_t)std::max(ds.max_particles, 1);
-  if (lds > 64 * 1024) return fail(c, CD_ECAPACITY, "domain particle set exceeds 64 KiB of LDS");
-  c->sweep_lds = lds;
+  if (ds.dinc_total > c->dinc_cap || !c->dinc) {
+    int64_t cap = (int64_t)ds.dinc_total + ds.dinc_total / 4 + 1024;
+    CD_TRY(grow(&c->dinc, cap));
+    c->dinc_cap = cap;
+  }
+  CD_TRY(cd_launch_order_entries(c));
+  const size_t lds = (size_t)std::max(ds.max_lds, 8);
+  // static LDS of the sweep kernel (reduction scratch) stays below 1 KiB
+  c->sweep_global = lds + 1024 > c->max_lds;
+  c->sweep_lds = c->sweep_global ? 0 : lds;
+  if (c->sweep_global) {
+    // domains too large for LDS stage their data in global memory
+    const int sd = (dim == 2 ? 2 : 9) + 5 + dim;
+    int64_t need = (int64_t)(dim + dr + 3) * 2 * c->cap + (int64_t)(sd + 1) * c->cap;
+    if (need > c->gscr_cap) {
+      CD_TRY(grow(&c->gscr, need));
+      c->gscr_cap = need;
+    }
+  }
   c->sweep_threads = ds.max_contacts > 512 ? 256 : (ds.max_contacts > 128 ? 128 : 64);
   CD_TRY(hipEventRecord(c->ev[3], c->stream));
   // ---- iterative solve
@@ -522,9 +558,11 @@ int cd_step(cd_ctx* c, cd_result* out) {
   while (!c->h_state->done && launched < limit) {
     int k = std::min(chunk, limit - launched);
     for (int q = 0; q < k; ++q) {
-      if (c->time_sweeps) CD_TRY(hipEventRecord(c->sweep_ev[2 * (launched + q)], c->stream));
-      CD_TRY(cd_launch_sweep(c));
-      if (c->time_sweeps) CD_TRY(hipEventRecord(c->sweep_ev[2 * (launched + q) + 1], c->stream));
+      if (c->time_sweeps)
+        CD_TRY(cd_launch_sweep(c, c->sweep_ev[2 * (launched + q)],
+                               c->sweep_ev[2 * (launched + q) + 1]));
+      else
+        CD_TRY(cd_launch_sweep(c, nullptr, nullptr));
     }
     launched += k;
     CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,

@@ -46,7 +46,11 @@ struct DomainStats {
   int max_colors;
   int max_contacts;
   int max_particles;
-  int overflow;       // a domain exceeded CD_MAX_DC / CD_MAX_DP / CD_MAX_COLORS
+  int overflow;       // 2: a domain needs more than CD_MAX_COLORS colours
+  int max_lds;        // largest per-domain staging size of the sweep, bytes
+  int dinc_total;     // incidences summed over all domain particle entries
+  int dp_total;       // domain particle entries
+  int pad;
 };
 
 struct BlockPartial {
@@ -62,18 +66,13 @@ struct SweepArgs {
   const int* dom_start;     // P+1 slot offsets
   const int* dcol;          // P x (CD_MAX_COLORS+1) colour offsets inside the domain
   const int* dncol;         // P colours per domain
-  const int* dp;            // domain particles, 2 entries reserved per slot
-  const int* dp_count;      // P
-  // particles
-  const double* v;
-  const double* w;
-  const double* f;
-  const double* t;
-  const double* r;
-  const double* dtim;
-  const double* dtii;
-  const int* inc_ptr;       // N+1
-  const int* inc;           // incident slots * 2 + (1 if body 2)
+  const int* dp_start;      // P+1 offsets of the domain particle entries
+  double* gscr;             // global stand-in for LDS when a domain does not fit
+  // domain particle entries (SoA, stride dpe): v, w, f, t, dt/m, dt/I, r
+  const double* dpb;
+  int64_t dpe;
+  const int* dinc_ptr;      // per entry: incident slots, ascending contact id
+  const int* dinc;          // slot * 2 + (1 if body 2)
   // slots
   const int2* ab;           // local body indices; b < 0: wall -1-b
   const double* geo;        // per-slot constants, SoA with stride cap
@@ -177,7 +176,17 @@ struct cd_ctx {
   int2* slot_ab = nullptr;
   double* geo = nullptr;
   double* rec[2] = {nullptr, nullptr};
-  int *dcol = nullptr, *dncol = nullptr, *dp = nullptr, *dp_count = nullptr;
+  int *dcol = nullptr, *dncol = nullptr, *dp = nullptr, *dp_count = nullptr, *dp_start = nullptr;
+  int *q_la = nullptr, *q_lb = nullptr, *q_col = nullptr, *q_pos = nullptr;
+  unsigned long long* g_mask = nullptr;
+  double* gscr = nullptr;
+  int64_t gscr_cap = 0;
+  double* dpb = nullptr;         // domain particle entries, SoA with stride 2 cap
+  int* dinc_ptr = nullptr;       // 2 cap + 1
+  int* dinc = nullptr;
+  int64_t dinc_cap = 0;
+  bool sweep_global = false;
+  size_t max_lds = 65536;
   int *inc_count = nullptr, *inc_ptr = nullptr, *inc_cursor = nullptr, *inc = nullptr;
   DomainStats* d_stats = nullptr;
 
@@ -224,9 +233,10 @@ hipError_t cd_launch_orb(cd_ctx* c);
 hipError_t cd_launch_descend(cd_ctx* c);
 // order.hip
 hipError_t cd_launch_order(cd_ctx* c);
+hipError_t cd_launch_order_entries(cd_ctx* c);   // after the stats readback
 // sweep.hip
 hipError_t cd_launch_solve_init(cd_ctx* c, int limit);
-hipError_t cd_launch_sweep(cd_ctx* c);
+hipError_t cd_launch_sweep(cd_ctx* c, hipEvent_t before, hipEvent_t after);  // sweep + decision
 hipError_t cd_launch_unslot(cd_ctx* c, int final_iter);
 // update.hip
 hipError_t cd_launch_update(cd_ctx* c, int final_iter);

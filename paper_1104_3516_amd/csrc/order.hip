@@ -8,56 +8,72 @@
 // different lanes gives exactly the result of updating them one after the
 // other: the colour-major sweep is an exact sequential sweep.
 //
-// One workgroup per domain sorts its contacts, builds its particle list
-// (ascending id), colours, and writes the slot arrays: local body indices,
-// the contact frame and force-law constants, and the initial force records.
-// The particle incidence lists (ascending contact id) are built beside it.
+// Steps (no limit on the domain size):
+//   1. contacts grouped by domain, canonical order kept: stable radix sort of
+//      (domain, contact id);
+//   2. each domain's particles, ascending: radix sort of (domain, particle)
+//      keys of all contact ends, then unique;
+//   3. local body indices of every contact (binary search in its domain's
+//      particle list);
+//   4. one workgroup per domain colours serially (first fit, the order is
+//      the definition) with the per-particle colour masks in LDS when the
+//      domain fits, and writes the slot arrays: local body indices, contact
+//      frame, force-law constants and the initial force records;
+//   5. per-particle incidence lists in ascending contact id.
 #include "cd_internal.h"
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kBuild = 256;
+constexpr int kBuild = 64;
+constexpr int kSmall = 2048;   // LDS staging limit (contacts and particles of a domain)
 
 __global__ __launch_bounds__(kThreads) void k_dom_count(const int* dom, int64_t nc, int* count) {
   int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (c < nc) atomicAdd(&count[dom[c]], 1);
 }
 
-__global__ __launch_bounds__(kThreads) void k_dom_scatter(const int* dom, int64_t nc,
-                                                         const int* start, int* cursor,
-                                                         int* bucket) {
+__global__ __launch_bounds__(kThreads) void k_dom_keys(const int* dom, int64_t nc,
+                                                      unsigned long long* keys, int* vals) {
   int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (c >= nc) return;
-  int d = dom[c];
-  int pos = atomicAdd(&cursor[d], 1);
-  bucket[start[d] + pos] = (int)c;
+  keys[c] = (unsigned long long)dom[c];
+  vals[c] = (int)c;
 }
 
-// in-place ascending bitonic sort of n_pow2 ints in shared memory
-__device__ void bitonic_sort(int* a, int n_pow2) {
-  for (int k = 2; k <= n_pow2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n_pow2; i += blockDim.x) {
-        int l = i ^ j;
-        if (l > i) {
-          bool up = (i & k) == 0;
-          int x = a[i], y = a[l];
-          if ((x > y) == up) {
-            a[i] = y;
-            a[l] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
+__global__ __launch_bounds__(kThreads) void k_end_keys(const int* bucket, const int* dom,
+                                                      const int* ci, const int* cj, int64_t nc,
+                                                      int64_t n, unsigned long long* keys,
+                                                      int* vals) {
+  int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (q >= nc) return;
+  int c = bucket[q];
+  unsigned long long d = (unsigned long long)dom[c];
+  keys[2 * q] = d * (unsigned long long)n + (unsigned long long)ci[c];
+  int b = cj[c];
+  keys[2 * q + 1] = b < n ? d * (unsigned long long)n + (unsigned long long)b : ~0ull;
+  vals[2 * q] = 0;
+  vals[2 * q + 1] = 0;
 }
 
-__device__ inline int pow2_at_least(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
+__global__ __launch_bounds__(kThreads) void k_unique_flags(const unsigned long long* keys,
+                                                          int64_t m, int* flag) {
+  int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= m) return;
+  unsigned long long v = keys[k];
+  flag[k] = (v != ~0ull) && (k == 0 || keys[k - 1] != v);
+}
+
+__global__ __launch_bounds__(kThreads) void k_unique_compact(const unsigned long long* keys,
+                                                            int64_t m, const int* flag,
+                                                            const int* pos, int64_t n, int* dp,
+                                                            int* dp_count) {
+  int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= m || !flag[k]) return;
+  unsigned long long v = keys[k];
+  unsigned long long d = v / (unsigned long long)n;
+  dp[pos[k]] = (int)(v - d * (unsigned long long)n);
+  atomicAdd(&dp_count[d], 1);
 }
 
 __device__ inline int lower_bound_i(const int* a, int n, int v) {
@@ -70,9 +86,30 @@ __device__ inline int lower_bound_i(const int* a, int n, int v) {
   return lo;
 }
 
+__global__ __launch_bounds__(kThreads) void k_local_index(const int* bucket, const int* dom,
+                                                         const int* ci, const int* cj,
+                                                         int64_t nc, int64_t n, const int* dp,
+                                                         const int* dp_start, int* qla,
+                                                         int* qlb) {
+  int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (q >= nc) return;
+  int c = bucket[q];
+  int d = dom[c];
+  int ps = dp_start[d], np = dp_start[d + 1] - ps;
+  qla[q] = lower_bound_i(dp + ps, np, ci[c]);
+  int b = cj[c];
+  qlb[q] = b < n ? lower_bound_i(dp + ps, np, b) : -1 - (int)(b - n);
+}
+
 struct BuildArgs {
   const int* dom_start;
   const int* bucket;
+  const int* dp_start;
+  const int* qla;
+  const int* qlb;
+  int* qcol;              // scratch, per bucket position
+  int* qpos;              // scratch, per bucket position
+  unsigned long long* gmask;   // scratch, per domain particle
   const int* ci;
   const int* cj;
   const double* nrm;
@@ -94,92 +131,64 @@ struct BuildArgs {
   double* rec0;
   int* dcol;
   int* dncol;
-  int* dp;
-  int* dp_count;
   DomainStats* stats;
 };
 
 template <int DIM>
 __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   constexpr int REC = DIM == 2 ? 4 : 12;
-  __shared__ int s_cid[CD_MAX_DC];
-  __shared__ int s_ep[CD_MAX_DP];
-  __shared__ int s_pos[CD_MAX_DC];
-  __shared__ unsigned long long s_mask[CD_MAX_DP];
-  __shared__ short s_col[CD_MAX_DC];
+  __shared__ unsigned long long s_mask[kSmall];
+  __shared__ int s_la[kSmall], s_lb[kSmall];
+  __shared__ short s_col[kSmall];
+  __shared__ int s_pos[kSmall];
   __shared__ int s_coloff[CD_MAX_COLORS + 1];
-  __shared__ int s_np, s_ncol, s_bad;
+  __shared__ int s_ncol, s_bad;
 
   const int d = blockIdx.x;
-  const int cs = a.dom_start[d], ce = a.dom_start[d + 1];
-  const int nct = ce - cs;
-  if (threadIdx.x == 0) s_bad = 0;
-  if (nct > CD_MAX_DC) {
-    if (threadIdx.x == 0) atomicMax(&a.stats->overflow, 1);
-    return;
-  }
-  // 1. the domain's contacts in canonical order
-  const int pc = pow2_at_least(nct > 0 ? nct : 1);
-  for (int k = threadIdx.x; k < pc; k += blockDim.x) s_cid[k] = k < nct ? a.bucket[cs + k] : 0x7fffffff;
-  __syncthreads();
-  bitonic_sort(s_cid, pc);
-  // 2. its particles: sorted unique finite-mass endpoints
-  const int ne = 2 * nct;
-  const int pe = pow2_at_least(ne > 0 ? ne : 1);
-  for (int k = threadIdx.x; k < pe; k += blockDim.x) {
-    int v = 0x7fffffff;
-    if (k < ne) {
-      int c = s_cid[k >> 1];
-      int b = (k & 1) ? a.cj[c] : a.ci[c];
-      if (b < a.n) v = b;
+  const int cs = a.dom_start[d], nct = a.dom_start[d + 1] - cs;
+  const int ps = a.dp_start[d], np = a.dp_start[d + 1] - ps;
+  const bool small = nct <= kSmall && np <= kSmall;
+  // generic pointers: LDS when the domain fits, global scratch otherwise
+  unsigned long long* mask = small ? s_mask : a.gmask + ps;
+  int* la_s = small ? s_la : (int*)a.qla + cs;
+  int* lb_s = small ? s_lb : (int*)a.qlb + cs;
+  int* pos = small ? s_pos : a.qpos + cs;
+  for (int k = threadIdx.x; k < np; k += blockDim.x) mask[k] = 0ull;
+  if (small) {
+    for (int k = threadIdx.x; k < nct; k += blockDim.x) {
+      s_la[k] = a.qla[cs + k];
+      s_lb[k] = a.qlb[cs + k];
     }
-    s_ep[k] = v;
   }
   __syncthreads();
-  bitonic_sort(s_ep, pe);
+  // greedy first-fit colouring in canonical order (serial by definition)
   if (threadIdx.x == 0) {
-    // compact in place (serial; at most 2 CD_MAX_DC entries)
-    int np = 0;
-    for (int k = 0; k < ne; ++k) {
-      int v = s_ep[k];
-      if (v == 0x7fffffff) break;
-      if (np == 0 || s_ep[np - 1] != v) s_ep[np++] = v;
-    }
-    s_np = np;
-  }
-  __syncthreads();
-  const int np = s_np;
-  for (int k = threadIdx.x; k < np; k += blockDim.x) s_mask[k] = 0ull;
-  __syncthreads();
-  // 3. greedy first-fit colouring in canonical order (serial by design)
-  if (threadIdx.x == 0) {
-    int ncol = 0;
+    int ncol = 0, bad = 0;
     for (int k = 0; k < nct; ++k) {
-      int c = s_cid[k];
-      int la = lower_bound_i(s_ep, np, a.ci[c]);
-      int bj = a.cj[c];
-      int lb = bj < a.n ? lower_bound_i(s_ep, np, bj) : -1;
-      unsigned long long used = s_mask[la] | (lb >= 0 ? s_mask[lb] : 0ull);
+      int la = la_s[k], lb = lb_s[k];
+      unsigned long long used = mask[la] | (lb >= 0 ? mask[lb] : 0ull);
       if (used == ~0ull) {
-        s_bad = 1;
+        bad = 1;
         break;
       }
       int col = __ffsll((long long)~used) - 1;
-      s_col[k] = (short)col;
-      s_mask[la] |= 1ull << col;
-      if (lb >= 0) s_mask[lb] |= 1ull << col;
+      if (small) s_col[k] = (short)col;
+      else a.qcol[cs + k] = col;
+      mask[la] |= 1ull << col;
+      if (lb >= 0) mask[lb] |= 1ull << col;
       if (col + 1 > ncol) ncol = col + 1;
     }
-    // stable counting sort by colour
     for (int q = 0; q <= CD_MAX_COLORS; ++q) s_coloff[q] = 0;
-    if (!s_bad) {
-      for (int k = 0; k < nct; ++k) s_coloff[s_col[k] + 1] += 1;
+    if (!bad) {
+      // stable counting sort by colour
+      for (int k = 0; k < nct; ++k) s_coloff[(small ? s_col[k] : a.qcol[cs + k]) + 1] += 1;
       for (int q = 0; q < ncol; ++q) s_coloff[q + 1] += s_coloff[q];
       int run[CD_MAX_COLORS];
       for (int q = 0; q < ncol; ++q) run[q] = s_coloff[q];
-      for (int k = 0; k < nct; ++k) s_pos[k] = run[s_col[k]]++;
+      for (int k = 0; k < nct; ++k) pos[k] = run[small ? s_col[k] : a.qcol[cs + k]]++;
     }
     s_ncol = ncol;
+    s_bad = bad;
   }
   __syncthreads();
   if (s_bad) {
@@ -191,25 +200,26 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     atomicMax(&a.stats->max_colors, ncol);
     atomicMax(&a.stats->max_contacts, nct);
     atomicMax(&a.stats->max_particles, np);
+    // sweep staging: per particle V, W, dt/m, dt/I, r; per slot frame,
+    // five constants, the old force and the body pair
+    constexpr int PD = DIM + (DIM == 2 ? 1 : 3) + 3;
+    constexpr int SD = (DIM == 2 ? 2 : 9) + 5 + DIM;
+    long long bytes = 8ll * PD * np + (8ll * SD + 8ll) * nct;
+    atomicMax(&a.stats->max_lds, (int)(bytes < 0x7fffffffll ? bytes : 0x7fffffffll));
     a.dncol[d] = ncol;
   }
   for (int q = threadIdx.x; q <= CD_MAX_COLORS; q += blockDim.x)
     a.dcol[(int64_t)d * (CD_MAX_COLORS + 1) + q] = q <= ncol ? s_coloff[q] : nct;
-  const int64_t dp0 = 2 * (int64_t)cs;
-  for (int k = threadIdx.x; k < np; k += blockDim.x) a.dp[dp0 + k] = s_ep[k];
-  if (threadIdx.x == 0) a.dp_count[d] = np;
-  // 4. slot arrays
+  // slot arrays
   const int64_t nc = a.nc, cap = a.cap, nn = a.n;
   for (int k = threadIdx.x; k < nct; k += blockDim.x) {
-    const int c = s_cid[k];
-    const int64_t s = cs + s_pos[k];
+    const int c = a.bucket[cs + k];
+    const int64_t s = cs + pos[k];
     const int i = a.ci[c], j = a.cj[c];
     a.slot_contact[s] = c;
     a.contact_slot[c] = (int)s;
-    a.color[c] = s_col[k];
-    int la = lower_bound_i(s_ep, np, i);
-    int lb = j < nn ? lower_bound_i(s_ep, np, j) : -1 - (int)(j - nn);
-    a.ab[s] = make_int2(la, lb);
+    a.color[c] = small ? s_col[k] : a.qcol[cs + k];
+    a.ab[s] = make_int2(la_s[k], lb_s[k]);
     double n3[3] = {0.0, 0.0, 0.0};
     for (int q = 0; q < DIM; ++q) n3[q] = a.nrm[q * nc + c];
     double t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
@@ -312,29 +322,120 @@ __global__ __launch_bounds__(kThreads) void k_inc_finish(int64_t n, const int* p
   }
 }
 
+// domain particle entries in domain order: base data (SoA, stride E) and
+// the incidence count of the particle
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_dp_entries(const int* dp, const int* dp_start, int P,
+                                                        int64_t E, const double* v,
+                                                        const double* w, const double* f,
+                                                        const double* t, const double* dtim,
+                                                        const double* dtii, const double* r,
+                                                        const int* inc_ptr, int64_t n,
+                                                        double* dpb, int* count,
+                                                        DomainStats* stats) {
+  constexpr int DR = DIM == 2 ? 1 : 3;
+  int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= E) return;
+  const int total = dp_start[P];
+  if (e == 0) stats->dp_total = total;
+  if (e >= total) {
+    count[e] = 0;
+    return;
+  }
+  const int p = dp[e];
+  int q = 0;
+  for (int k = 0; k < DIM; ++k) dpb[(q++) * E + e] = v[k * n + p];
+  for (int k = 0; k < DR; ++k) dpb[(q++) * E + e] = w[k * n + p];
+  for (int k = 0; k < DIM; ++k) dpb[(q++) * E + e] = f[k * n + p];
+  for (int k = 0; k < DR; ++k) dpb[(q++) * E + e] = t[k * n + p];
+  dpb[(q++) * E + e] = dtim[p];
+  dpb[(q++) * E + e] = dtii[p];
+  dpb[(q++) * E + e] = r[p];
+  count[e] = inc_ptr[p + 1] - inc_ptr[p];
+}
+
+__global__ void k_dinc_total(const int* dinc_ptr, int64_t E, DomainStats* stats) {
+  stats->dinc_total = dinc_ptr[E];
+}
+
+__global__ __launch_bounds__(kThreads) void k_dinc_fill(const int* dp, const int* dp_start, int P,
+                                                       int64_t E, const int* inc_ptr,
+                                                       const int* inc, const int* dinc_ptr,
+                                                       int* dinc) {
+  int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= E || e >= dp_start[P]) return;
+  const int p = dp[e];
+  const int s0 = inc_ptr[p], s1 = inc_ptr[p + 1];
+  int o = dinc_ptr[e];
+  for (int k = s0; k < s1; ++k) dinc[o++] = inc[k];
+}
+
+int bits_for(unsigned long long maxval) {
+  int b = 0;
+  while (b < 64 && (maxval >> b) != 0ull) ++b;
+  return ((b + 7) / 8) * 8;
+}
+
 }  // namespace
 
 hipError_t cd_launch_order(cd_ctx* c) {
   const int64_t nc = c->nc;
+  const int64_t n = c->n;
   const int P = c->P;
   hipError_t e;
   e = hipMemsetAsync(c->dom_count, 0, sizeof(int) * (size_t)(P + 1), c->stream);
   if (e != hipSuccess) return e;
   e = hipMemsetAsync(c->d_stats, 0, sizeof(DomainStats), c->stream);
   if (e != hipSuccess) return e;
+  e = hipMemsetAsync(c->dp_count, 0, sizeof(int) * (size_t)(P + 1), c->stream);
+  if (e != hipSuccess) return e;
   if (nc > 0)
     hipLaunchKernelGGL(k_dom_count, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
                        c->dom, nc, c->dom_count);
   e = cd_scan_exclusive(c, c->dom_count, c->dom_start, P);
   if (e != hipSuccess) return e;
-  e = hipMemsetAsync(c->dom_cursor, 0, sizeof(int) * (size_t)(P + 1), c->stream);
+  if (nc > 0) {
+    // 1. contacts by domain, canonical order kept (stable sort)
+    hipLaunchKernelGGL(k_dom_keys, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
+                       c->dom, nc, c->sort_keys[0], c->sort_vals[0]);
+    unsigned long long* ko;
+    int* vo;
+    e = cd_radix_sort(c, c->sort_keys[0], c->sort_vals[0], c->sort_keys[1], c->sort_vals[1], nc,
+                      bits_for((unsigned long long)(P - 1)), &ko, &vo);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(c->bucket, vo, sizeof(int) * (size_t)nc, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    // 2. each domain's particles: sorted unique (domain, particle) keys
+    const int64_t m = 2 * nc;
+    hipLaunchKernelGGL(k_end_keys, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
+                       c->bucket, c->dom, c->ci, c->cj, nc, n, c->sort_keys[0], c->sort_vals[0]);
+    e = cd_radix_sort(c, c->sort_keys[0], c->sort_vals[0], c->sort_keys[1], c->sort_vals[1], m,
+                      bits_for((unsigned long long)P * (unsigned long long)n), &ko, &vo);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_unique_flags, dim3(cd_blocks(m, kThreads)), dim3(kThreads), 0, c->stream,
+                       ko, m, c->flag);
+    e = cd_scan_exclusive(c, c->flag, c->flag_scan, m);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_unique_compact, dim3(cd_blocks(m, kThreads)), dim3(kThreads), 0,
+                       c->stream, ko, m, c->flag, c->flag_scan, n, c->dp, c->dp_count);
+  }
+  e = cd_scan_exclusive(c, c->dp_count, c->dp_start, P);
   if (e != hipSuccess) return e;
+  // 3. local body indices
   if (nc > 0)
-    hipLaunchKernelGGL(k_dom_scatter, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
-                       c->dom, nc, c->dom_start, c->dom_cursor, c->bucket);
+    hipLaunchKernelGGL(k_local_index, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
+                       c->bucket, c->dom, c->ci, c->cj, nc, n, c->dp, c->dp_start, c->q_la,
+                       c->q_lb);
+  // 4. colouring and slots
   BuildArgs a;
   a.dom_start = c->dom_start;
   a.bucket = c->bucket;
+  a.dp_start = c->dp_start;
+  a.qla = c->q_la;
+  a.qlb = c->q_lb;
+  a.qcol = c->q_col;
+  a.qpos = c->q_pos;
+  a.gmask = c->g_mask;
   a.ci = c->ci;
   a.cj = c->cj;
   a.nrm = c->nrm;
@@ -343,7 +444,7 @@ hipError_t cd_launch_order(cd_ctx* c) {
   a.r = c->r;
   a.inv_m = c->inv_m;
   a.inv_I = c->inv_I;
-  a.n = c->n;
+  a.n = n;
   a.nc = nc;
   a.cap = c->cap;
   a.dt = c->p.dt;
@@ -356,8 +457,6 @@ hipError_t cd_launch_order(cd_ctx* c) {
   a.rec0 = c->rec[0];
   a.dcol = c->dcol;
   a.dncol = c->dncol;
-  a.dp = c->dp;
-  a.dp_count = c->dp_count;
   a.stats = c->d_stats;
   if (c->dim == 2)
     hipLaunchKernelGGL(k_dom_build<2>, dim3(P), dim3(kBuild), 0, c->stream, a);
@@ -365,20 +464,40 @@ hipError_t cd_launch_order(cd_ctx* c) {
     hipLaunchKernelGGL(k_dom_build<3>, dim3(P), dim3(kBuild), 0, c->stream, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // incidence lists
-  e = hipMemsetAsync(c->inc_count, 0, sizeof(int) * (size_t)(c->n + 1), c->stream);
+  // 5. incidence lists
+  e = hipMemsetAsync(c->inc_count, 0, sizeof(int) * (size_t)(n + 1), c->stream);
   if (e != hipSuccess) return e;
   if (nc > 0)
     hipLaunchKernelGGL(k_inc_count, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
-                       c->ci, c->cj, nc, c->n, c->inc_count);
-  e = cd_scan_exclusive(c, c->inc_count, c->inc_ptr, c->n);
+                       c->ci, c->cj, nc, n, c->inc_count);
+  e = cd_scan_exclusive(c, c->inc_count, c->inc_ptr, n);
   if (e != hipSuccess) return e;
-  e = hipMemsetAsync(c->inc_cursor, 0, sizeof(int) * (size_t)(c->n + 1), c->stream);
+  e = hipMemsetAsync(c->inc_cursor, 0, sizeof(int) * (size_t)(n + 1), c->stream);
   if (e != hipSuccess) return e;
   if (nc > 0)
     hipLaunchKernelGGL(k_inc_fill, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
-                       c->ci, c->cj, nc, c->n, c->inc_ptr, c->inc_cursor, c->inc);
-  hipLaunchKernelGGL(k_inc_finish, dim3(cd_blocks(c->n, kThreads)), dim3(kThreads), 0, c->stream,
-                     c->n, c->inc_ptr, c->contact_slot, c->inc);
+                       c->ci, c->cj, nc, n, c->inc_ptr, c->inc_cursor, c->inc);
+  hipLaunchKernelGGL(k_inc_finish, dim3(cd_blocks(n, kThreads)), dim3(kThreads), 0, c->stream, n,
+                     c->inc_ptr, c->contact_slot, c->inc);
+  // 6. domain particle entries and their incidence counts
+  const int64_t E = 2 * c->cap;
+  if (c->dim == 2)
+    hipLaunchKernelGGL(k_dp_entries<2>, dim3(cd_blocks(E, kThreads)), dim3(kThreads), 0, c->stream,
+                       c->dp, c->dp_start, P, E, c->v, c->w, c->f, c->t, c->dtim, c->dtii, c->r,
+                       c->inc_ptr, n, c->dpb, c->flag, c->d_stats);
+  else
+    hipLaunchKernelGGL(k_dp_entries<3>, dim3(cd_blocks(E, kThreads)), dim3(kThreads), 0, c->stream,
+                       c->dp, c->dp_start, P, E, c->v, c->w, c->f, c->t, c->dtim, c->dtii, c->r,
+                       c->inc_ptr, n, c->dpb, c->flag, c->d_stats);
+  e = cd_scan_exclusive(c, c->flag, c->dinc_ptr, E);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dinc_total, dim3(1), dim3(1), 0, c->stream, c->dinc_ptr, E, c->d_stats);
+  return hipGetLastError();
+}
+
+hipError_t cd_launch_order_entries(cd_ctx* c) {
+  const int64_t E = 2 * c->cap;
+  hipLaunchKernelGGL(k_dinc_fill, dim3(cd_blocks(E, kThreads)), dim3(kThreads), 0, c->stream,
+                     c->dp, c->dp_start, c->P, E, c->inc_ptr, c->inc, c->dinc_ptr, c->dinc);
   return hipGetLastError();
 }

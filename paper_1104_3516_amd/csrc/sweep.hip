@@ -1,21 +1,27 @@
 // sweep.hip - the domain-wise iterative force solve (Sec. 2.1 and 3.1).
 //
-// One sweep = one kernel launch; one workgroup per domain.
-//  1. Exchange: the workgroup recomputes the velocities of its particles
-//     from their base velocities and external forces plus every incident
-//     contact force of the previous sweep (own and foreign contacts), into
-//     LDS.  This is the per-sweep exchange of boundary contact forces: other
-//     domains' forces are read from the previous sweep's record array.
-//  2. Sequential update: colours in order; in a colour, lanes update
-//     contacts that share no particle, each solving its own force law with
-//     all other forces fixed (Eqs. 3-9, Fig. 2) and applying the change to
-//     both bodies' LDS velocities.  New forces go to the other record array,
-//     so no domain ever sees a force of the current sweep from another
-//     domain (foreign contacts stay frozen for the sweep).
-//  3. Convergence: every workgroup reduces its contacts' test values; the
-//     last workgroup to finish reduces all of them in a fixed order and
-//     decides (criterion I or II), advancing the sweep counter.  Later
-//     launches of the same solve return at once after the stop decision.
+// One sweep = one launch of k_sweep (one workgroup per domain) followed by
+// one launch of k_decide (one workgroup).
+//  k_sweep
+//   0. Stage the domain's slot data in LDS with coalesced loads: contact
+//      frame, force-law constants, the previous sweep's force and the body
+//      pair of every native contact.
+//   1. Exchange: recompute the velocities of the domain's particles from
+//      their base velocities and external forces plus every incident contact
+//      force of the previous sweep (native and foreign), into LDS.  This is
+//      the per-sweep exchange of boundary contact forces: other domains'
+//      forces are read from the previous sweep's record array.
+//   2. Sequential update: colours in order; in a colour, lanes update
+//      contacts that share no particle, each solving its own force law with
+//      all other forces fixed (Eqs. 3-9, Fig. 2) and applying the change to
+//      both bodies' LDS velocities.  New forces go to the other record array,
+//      so no domain sees a force of the current sweep from another domain
+//      (foreign contacts stay frozen for the sweep).
+//   3. The workgroup's convergence test values (count passing the relative
+//      test, largest change of the others, sum of |R|) go to its partial.
+//  k_decide reduces the partials in a fixed order, applies test (I) or (II)
+//  and advances the sweep counter; after a stop every later launch of the
+//  solve returns at once.
 //
 // Blocks are mapped to domains so that each of the 8 XCDs (blocks are
 // dispatched round-robin over them) works on a contiguous run of domains,
@@ -25,14 +31,16 @@
 
 namespace {
 
-constexpr int kInitThreads = 1024;
+constexpr int kDecideThreads = 1024;
 
-__device__ inline void store_rel(long long* p, long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline long long load_rel(const long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+template <int DIM>
+struct Layout {
+  static constexpr int DR = DIM == 2 ? 1 : 3;
+  static constexpr int REC = DIM == 2 ? 4 : 12;
+  static constexpr int NG = DIM == 2 ? 2 : 9;      // frame doubles per slot
+  static constexpr int PD = DIM + DR + 3;          // staged doubles per particle
+  static constexpr int SD = NG + 5 + DIM;          // staged doubles per slot
+};
 
 template <int DIM>
 __device__ inline void local_force(const double* n, const double* t1, const double* t2, double gdt,
@@ -92,18 +100,17 @@ __device__ inline void local_force(const double* n, const double* t1, const doub
   }
 }
 
-template <int DIM>
+template <int DIM, bool GLOB>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
-  constexpr int DR = DIM == 2 ? 1 : 3;
-  constexpr int REC = DIM == 2 ? 4 : 12;
+  using L = Layout<DIM>;
+  constexpr int DR = L::DR, REC = L::REC, NG = L::NG, PD = L::PD, SD = L::SD;
   extern __shared__ double lds[];
   __shared__ long long sh_np[4];
   __shared__ double sh_md[4], sh_sr[4];
-  __shared__ int sh_last;
 
-  SolveState* st = a.state;
-  if (*(volatile int*)&st->done) return;
-  const int j = *(volatile int*)&st->iter + 1;
+  const SolveState* st = a.state;
+  if (*(volatile const int*)&st->done) return;
+  const int j = *(volatile const int*)&st->iter + 1;
   const double* rin = a.rec[(j - 1) & 1];
   double* rout = a.rec[j & 1];
   const int b = blockIdx.x;
@@ -114,37 +121,55 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
   double maxd = 0.0, sumr = 0.0;
 
   if (d < a.P) {
-    const int cs = a.dom_start[d];
-    const int np = a.dp_count[d];
-    const int* dpl = a.dp + 2 * (int64_t)cs;
-    const int stride = np;   // LDS arrays are [component][local particle]
-    double* sV = lds;
-    double* sW = sV + DIM * stride;
-    double* sdm = sW + DR * stride;
-    double* sdi = sdm + stride;
-    double* sr = sdi + stride;
-    const int64_t n = a.n;
+    const int cs = a.dom_start[d], nct = a.dom_start[d + 1] - cs;
+    const int ps = a.dp_start[d], np = a.dp_start[d + 1] - ps;
+    // staging: particles [PD][np], slots [SD][nct], body pairs [nct]
+    double* sp = GLOB ? a.gscr + (int64_t)PD * ps : lds;
+    double* ss = GLOB ? a.gscr + (int64_t)PD * 2 * a.cap + (int64_t)SD * cs : sp + PD * np;
+    int2* sab = GLOB ? (int2*)(a.gscr + (int64_t)PD * 2 * a.cap + (int64_t)SD * a.cap) + cs
+                     : (int2*)(ss + SD * nct);
+    double* sV = sp;
+    double* sW = sV + DIM * np;
+    double* sdm = sW + DR * np;
+    double* sdi = sdm + np;
+    double* sr = sdi + np;
+    // 0. stage the native contacts
+    const int64_t cap = a.cap;
+    const double* g = a.geo;
+    for (int k = tid; k < nct; k += nthr) {
+      const int s = cs + k;
+      for (int q = 0; q < NG; ++q) ss[q * nct + k] = g[q * cap + s];
+      for (int q = 0; q < 5; ++q) ss[(NG + q) * nct + k] = g[(G_GDT + q) * cap + s];
+      const double* ri = rin + (int64_t)s * REC;
+      for (int q = 0; q < DIM; ++q) ss[(NG + 5 + q) * nct + k] = ri[q];
+      sab[k] = a.ab[s];
+    }
     // 1. exchange: velocities from the previous sweep's forces
+    const int64_t E = a.dpe;
     for (int l = tid; l < np; l += nthr) {
-      const int p = dpl[l];
+      const int64_t e = ps + l;
       double acc[DIM], tacc[DR];
-      for (int k = 0; k < DIM; ++k) acc[k] = a.f[k * n + p];
-      for (int k = 0; k < DR; ++k) tacc[k] = a.t[k * n + p];
-      const double rp = a.r[p];
-      const int e1 = a.inc_ptr[p + 1];
-      for (int e = a.inc_ptr[p]; e < e1; ++e) {
-        const int ent = a.inc[e];
+      int q = DIM + DR;
+      for (int k = 0; k < DIM; ++k) acc[k] = a.dpb[(q + k) * E + e];
+      q += DIM;
+      for (int k = 0; k < DR; ++k) tacc[k] = a.dpb[(q + k) * E + e];
+      q += DR;
+      const double dm = a.dpb[q * E + e], di = a.dpb[(q + 1) * E + e];
+      const double rp = a.dpb[(q + 2) * E + e];
+      const int e1 = a.dinc_ptr[e + 1];
+      for (int x = a.dinc_ptr[e]; x < e1; ++x) {
+        const int ent = a.dinc[x];
         const double* rc = rin + (int64_t)(ent >> 1) * REC;
         if (DIM == 2) {
-          double F0 = rc[2], F1 = rc[3], q = rc[1];
+          const double4 r4 = *(const double4*)rc;
           if (ent & 1) {
-            acc[0] = acc[0] + F0;
-            acc[1] = acc[1] + F1;
+            acc[0] = acc[0] + r4.z;
+            acc[1] = acc[1] + r4.w;
           } else {
-            acc[0] = acc[0] - F0;
-            acc[1] = acc[1] - F1;
+            acc[0] = acc[0] - r4.z;
+            acc[1] = acc[1] - r4.w;
           }
-          tacc[0] = tacc[0] - rp * q;
+          tacc[0] = tacc[0] - rp * r4.y;
         } else {
           for (int k = 0; k < 3; ++k) {
             double F = rc[4 + k];
@@ -153,76 +178,74 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
           for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * rc[8 + k];
         }
       }
-      const double dm = a.dtim[p], di = a.dtii[p];
-      for (int k = 0; k < DIM; ++k) sV[k * stride + l] = a.v[k * n + p] + dm * acc[k];
-      for (int k = 0; k < DR; ++k) sW[k * stride + l] = a.w[k * n + p] + di * tacc[k];
+      for (int k = 0; k < DIM; ++k) sV[k * np + l] = a.dpb[k * E + e] + dm * acc[k];
+      for (int k = 0; k < DR; ++k) sW[k * np + l] = a.dpb[(DIM + k) * E + e] + di * tacc[k];
       sdm[l] = dm;
       sdi[l] = di;
       sr[l] = rp;
     }
     __syncthreads();
-    // 2. colour-major sequential update
+    // 2. colour-major sequential update, from the staged data
     const int ncol = a.dncol[d];
     const int* co = a.dcol + (int64_t)d * (CD_MAX_COLORS + 1);
-    const int64_t cap = a.cap;
-    const double* g = a.geo;
     for (int col = 0; col < ncol; ++col) {
-      const int s0 = cs + co[col], s1 = cs + co[col + 1];
-      for (int s = s0 + tid; s < s1; s += nthr) {
-        const int2 ab = a.ab[s];
+      const int k0 = co[col], k1 = co[col + 1];
+      for (int k = k0 + tid; k < k1; k += nthr) {
+        const int2 ab = sab[k];
         double nv[3] = {0.0, 0.0, 0.0}, t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < DIM; ++q) nv[q] = g[(G_N0 + q) * cap + s];
+        for (int q = 0; q < DIM; ++q) nv[q] = ss[q * nct + k];
         if (DIM == 2) {
           t1[0] = -nv[1];
           t1[1] = nv[0];
         } else {
           for (int q = 0; q < 3; ++q) {
-            t1[q] = g[(G_T10 + q) * cap + s];
-            t2[q] = g[(G_T20 + q) * cap + s];
+            t1[q] = ss[(3 + q) * nct + k];
+            t2[q] = ss[(6 + q) * nct + k];
           }
         }
-        const double gdt = g[G_GDT * cap + s], dwn = g[G_DWN * cap + s];
-        const double dwt = g[G_DWT * cap + s], kn = g[G_KN * cap + s], kt = g[G_KT * cap + s];
-        const double* ri = rin + (int64_t)s * REC;
-        double Rold[3] = {ri[0], ri[1], DIM == 3 ? ri[2] : 0.0};
+        const double gdt = ss[NG * nct + k], dwn = ss[(NG + 1) * nct + k];
+        const double dwt = ss[(NG + 2) * nct + k], kn = ss[(NG + 3) * nct + k];
+        const double kt = ss[(NG + 4) * nct + k];
+        double Rold[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < DIM; ++q) Rold[q] = ss[(NG + 5 + q) * nct + k];
         const int la = ab.x, lb = ab.y;
         double Va[3] = {0, 0, 0}, Wa[3] = {0, 0, 0}, Vb[3] = {0, 0, 0}, Wb[3] = {0, 0, 0};
-        for (int k = 0; k < DIM; ++k) Va[k] = sV[k * stride + la];
-        for (int k = 0; k < DR; ++k) Wa[k] = sW[k * stride + la];
+        for (int q = 0; q < DIM; ++q) Va[q] = sV[q * np + la];
+        for (int q = 0; q < DR; ++q) Wa[q] = sW[q * np + la];
         const double ra = sr[la];
         double rb = 0.0;
         if (lb >= 0) {
-          for (int k = 0; k < DIM; ++k) Vb[k] = sV[k * stride + lb];
-          for (int k = 0; k < DR; ++k) Wb[k] = sW[k * stride + lb];
+          for (int q = 0; q < DIM; ++q) Vb[q] = sV[q * np + lb];
+          for (int q = 0; q < DR; ++q) Wb[q] = sW[q * np + lb];
           rb = sr[lb];
         } else {
           const double* u = a.walls_u + (-1 - lb) * DIM;
-          for (int k = 0; k < DIM; ++k) Vb[k] = u[k];
+          for (int q = 0; q < DIM; ++q) Vb[q] = u[q];
         }
         double Rn[3] = {0.0, 0.0, 0.0};
         local_force<DIM>(nv, t1, t2, gdt, dwn, dwt, kn, kt, a.mu, ra, rb, Va, Wa, Vb, Wb, Rold, Rn);
         const double dRn = Rn[0] - Rold[0], dR1 = Rn[1] - Rold[1];
         const double dR2 = DIM == 3 ? Rn[2] - Rold[2] : 0.0;
         double dF[3], dq[3];
-        for (int k = 0; k < DIM; ++k) {
-          dF[k] = dRn * nv[k] + dR1 * t1[k];
-          if (DIM == 3) dF[k] = dF[k] + dR2 * t2[k];
+        for (int q = 0; q < DIM; ++q) {
+          dF[q] = dRn * nv[q] + dR1 * t1[q];
+          if (DIM == 3) dF[q] = dF[q] + dR2 * t2[q];
         }
         if (DIM == 2) {
           dq[0] = dR1;
         } else {
-          for (int k = 0; k < 3; ++k) dq[k] = dR1 * t2[k] - dR2 * t1[k];
+          for (int q = 0; q < 3; ++q) dq[q] = dR1 * t2[q] - dR2 * t1[q];
         }
         const double dma = sdm[la], dia = sdi[la];
-        for (int k = 0; k < DIM; ++k) sV[k * stride + la] = Va[k] - dma * dF[k];
-        for (int k = 0; k < DR; ++k) sW[k * stride + la] = Wa[k] - dia * (ra * dq[k]);
+        for (int q = 0; q < DIM; ++q) sV[q * np + la] = Va[q] - dma * dF[q];
+        for (int q = 0; q < DR; ++q) sW[q * np + la] = Wa[q] - dia * (ra * dq[q]);
         if (lb >= 0) {
           const double dmb = sdm[lb], dib = sdi[lb];
-          for (int k = 0; k < DIM; ++k) sV[k * stride + lb] = Vb[k] + dmb * dF[k];
-          for (int k = 0; k < DR; ++k) sW[k * stride + lb] = Wb[k] - dib * (rb * dq[k]);
+          for (int q = 0; q < DIM; ++q) sV[q * np + lb] = Vb[q] + dmb * dF[q];
+          for (int q = 0; q < DR; ++q) sW[q * np + lb] = Wb[q] - dib * (rb * dq[q]);
         }
         // new record: frame force, world force, torque per unit lever
-        double* ro = rout + (int64_t)s * REC;
+        double* ro = rout + (int64_t)(cs + k) * REC;
         if (DIM == 2) {
           double4 rec4;
           rec4.x = Rn[0];
@@ -231,22 +254,20 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
           rec4.w = Rn[0] * nv[1] + Rn[1] * t1[1];
           *(double4*)ro = rec4;
         } else {
-          ro[0] = Rn[0];
-          ro[1] = Rn[1];
-          ro[2] = Rn[2];
-          ro[3] = 0.0;
-          for (int k = 0; k < 3; ++k) {
-            double fk = Rn[0] * nv[k] + Rn[1] * t1[k];
-            ro[4 + k] = fk + Rn[2] * t2[k];
-            ro[8 + k] = Rn[1] * t2[k] - Rn[2] * t1[k];
+          double F[3], Q[3];
+          for (int q = 0; q < 3; ++q) {
+            double fk = Rn[0] * nv[q] + Rn[1] * t1[q];
+            F[q] = fk + Rn[2] * t2[q];
+            Q[q] = Rn[1] * t2[q] - Rn[2] * t1[q];
           }
-          ro[7] = 0.0;
-          ro[11] = 0.0;
+          *(double4*)ro = make_double4(Rn[0], Rn[1], Rn[2], 0.0);
+          *(double4*)(ro + 4) = make_double4(F[0], F[1], F[2], 0.0);
+          *(double4*)(ro + 8) = make_double4(Q[0], Q[1], Q[2], 0.0);
         }
         // convergence test values (Sec. 2.1)
         double d2 = 0.0, s2 = 0.0, qq = 0.0;
-        for (int k = 0; k < DIM; ++k) {
-          double a1 = Rn[k], a0 = Rold[k];
+        for (int q = 0; q < DIM; ++q) {
+          double a1 = Rn[q], a0 = Rold[q];
           d2 = d2 + (a1 - a0) * (a1 - a0);
           s2 = s2 + (a1 + a0) * (a1 + a0);
           qq = qq + a1 * a1;
@@ -258,7 +279,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
       __syncthreads();
     }
   }
-  // 3. block reduction (fixed order), partial store, arrival
+  // 3. block reduction in a fixed order; the partial is read by k_decide
   for (int off = 32; off > 0; off >>= 1) {
     npass += __shfl_xor(npass, off, 64);
     double o = __shfl_xor(maxd, off, 64);
@@ -278,26 +299,29 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
       if (sh_md[k] > maxd || sh_md[k] != sh_md[k]) maxd = sh_md[k];
       sumr += sh_sr[k];
     }
-    BlockPartial* bp = a.partial + b;
-    store_rel(&bp->n_pass, npass);
-    store_rel((long long*)&bp->max_d_fail, __double_as_longlong(maxd));
-    store_rel((long long*)&bp->sum_r, __double_as_longlong(sumr));
-    __threadfence();
-    unsigned prev = atomicAdd(&st->arrive, 1u);
-    sh_last = prev == (unsigned)(a.grid - 1);
+    BlockPartial p;
+    p.n_pass = npass;
+    p.max_d_fail = maxd;
+    p.sum_r = sumr;
+    p.pad = 0;
+    a.partial[b] = p;
   }
-  __syncthreads();
-  if (!sh_last) return;
-  __threadfence();
-  // last block: reduce every block's partial in a fixed order and decide
+}
+
+// stop decision of the sweep just done: one workgroup, fixed reduction order
+__global__ __launch_bounds__(kDecideThreads) void k_decide(SweepArgs a) {
+  __shared__ long long sh_np[kDecideThreads / 64];
+  __shared__ double sh_md[kDecideThreads / 64], sh_sr[kDecideThreads / 64];
+  SolveState* st = a.state;
+  if (st->done) return;
+  const int tid = threadIdx.x;
   long long tn = 0;
   double tm = 0.0, ts = 0.0;
-  for (int q = tid; q < a.grid; q += nthr) {
-    const BlockPartial* bp = a.partial + q;
-    tn += load_rel(&bp->n_pass);
-    double m = __longlong_as_double(load_rel((const long long*)&bp->max_d_fail));
-    if (m > tm || m != m) tm = m;
-    ts += __longlong_as_double(load_rel((const long long*)&bp->sum_r));
+  for (int q = tid; q < a.grid; q += kDecideThreads) {
+    const BlockPartial p = a.partial[q];
+    tn += p.n_pass;
+    if (p.max_d_fail > tm || p.max_d_fail != p.max_d_fail) tm = p.max_d_fail;
+    ts += p.sum_r;
   }
   for (int off = 32; off > 0; off >>= 1) {
     tn += __shfl_xor(tn, off, 64);
@@ -305,65 +329,62 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     if (o > tm || o != o) tm = o;
     ts += __shfl_xor(ts, off, 64);
   }
-  __syncthreads();
+  const int wave = tid >> 6;
   if ((tid & 63) == 0) {
     sh_np[wave] = tn;
     sh_md[wave] = tm;
     sh_sr[wave] = ts;
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int k = 1; k < nw; ++k) {
-      tn += sh_np[k];
-      if (sh_md[k] > tm || sh_md[k] != sh_md[k]) tm = sh_md[k];
-      ts += sh_sr[k];
-    }
-    const long long nc = a.nc;
-    const double ravg = ts / (double)nc;
-    const double prev = st->r_avg;
-    int conv;
-    if (a.criterion == 0) {
-      conv = (10 * tn >= 9 * nc) && (tn == nc || tm < a.alpha * (prev * prev));
-    } else {
-      double dd = (ravg - prev) * (ravg - prev);
-      double ss = (ravg + prev) * (ravg + prev);
-      conv = dd < a.alpha * ss || dd == 0.0;
-    }
-    st->n_pass = tn;
-    st->max_d_fail = tm;
-    st->r_avg_prev = prev;
-    st->r_avg = ravg;
-    st->conv = conv;
-    st->iter = j;
-    bool finite = isfinite(ts);
-    if (!finite) {
-      st->done = 1;
-      st->status = CD_ENONFINITE;
-    } else if (a.fixed_iters > 0) {
-      if (j >= a.fixed_iters) {
-        st->done = 1;
-        st->status = CD_OK;
-      }
-    } else if (conv) {
+  if (tid != 0) return;
+  for (int k = 1; k < kDecideThreads / 64; ++k) {
+    tn += sh_np[k];
+    if (sh_md[k] > tm || sh_md[k] != sh_md[k]) tm = sh_md[k];
+    ts += sh_sr[k];
+  }
+  const long long nc = a.nc;
+  const int j = st->iter + 1;
+  const double ravg = ts / (double)nc;
+  const double prev = st->r_avg;
+  int conv;
+  if (a.criterion == 0) {
+    conv = (10 * tn >= 9 * nc) && (tn == nc || tm < a.alpha * (prev * prev));
+  } else {
+    double dd = (ravg - prev) * (ravg - prev);
+    double ss = (ravg + prev) * (ravg + prev);
+    conv = dd < a.alpha * ss || dd == 0.0;
+  }
+  st->n_pass = tn;
+  st->max_d_fail = tm;
+  st->r_avg_prev = prev;
+  st->r_avg = ravg;
+  st->conv = conv;
+  st->iter = j;
+  if (!isfinite(ts)) {
+    st->done = 1;
+    st->status = CD_ENONFINITE;
+  } else if (a.fixed_iters > 0) {
+    if (j >= a.fixed_iters) {
       st->done = 1;
       st->status = CD_OK;
-    } else if (j >= a.max_iter) {
-      st->done = 1;
-      st->status = CD_MAXITER;
     }
-    st->arrive = 0;
-    __threadfence();
+  } else if (conv) {
+    st->done = 1;
+    st->status = CD_OK;
+  } else if (j >= a.max_iter) {
+    st->done = 1;
+    st->status = CD_MAXITER;
   }
 }
 
 // R_avg of the starting forces and the solve state (one block, fixed order)
 template <int DIM>
-__global__ __launch_bounds__(kInitThreads) void k_solve_init(const double* rec0, int64_t nc,
-                                                            SolveState* st, int limit) {
+__global__ __launch_bounds__(kDecideThreads) void k_solve_init(const double* rec0, int64_t nc,
+                                                              SolveState* st, int limit) {
   constexpr int REC = DIM == 2 ? 4 : 12;
-  __shared__ double sh[kInitThreads / 64];
+  __shared__ double sh[kDecideThreads / 64];
   double s = 0.0;
-  for (int64_t q = threadIdx.x; q < nc; q += kInitThreads) {
+  for (int64_t q = threadIdx.x; q < nc; q += kDecideThreads) {
     const double* rc = rec0 + q * REC;
     double qq = 0.0;
     for (int k = 0; k < DIM; ++k) qq = qq + rc[k] * rc[k];
@@ -374,7 +395,7 @@ __global__ __launch_bounds__(kInitThreads) void k_solve_init(const double* rec0,
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int k = 0; k < kInitThreads / 64; ++k) t += sh[k];
+    for (int k = 0; k < kDecideThreads / 64; ++k) t += sh[k];
     st->iter = 0;
     st->arrive = 0;
     st->n_pass = 0;
@@ -412,17 +433,12 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.dom_start = c->dom_start;
   a.dcol = c->dcol;
   a.dncol = c->dncol;
-  a.dp = c->dp;
-  a.dp_count = c->dp_count;
-  a.v = c->v;
-  a.w = c->w;
-  a.f = c->f;
-  a.t = c->t;
-  a.r = c->r;
-  a.dtim = c->dtim;
-  a.dtii = c->dtii;
-  a.inc_ptr = c->inc_ptr;
-  a.inc = c->inc;
+  a.dp_start = c->dp_start;
+  a.gscr = c->gscr;
+  a.dpb = c->dpb;
+  a.dpe = 2 * c->cap;
+  a.dinc_ptr = c->dinc_ptr;
+  a.dinc = c->dinc;
   a.ab = c->slot_ab;
   a.geo = c->geo;
   a.walls_u = c->d_wall + (size_t)c->W * c->dim + c->W;
@@ -446,22 +462,37 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
 
 hipError_t cd_launch_solve_init(cd_ctx* c, int limit) {
   if (c->dim == 2)
-    hipLaunchKernelGGL(k_solve_init<2>, dim3(1), dim3(kInitThreads), 0, c->stream, c->rec[0], c->nc,
-                       c->d_state, limit);
+    hipLaunchKernelGGL(k_solve_init<2>, dim3(1), dim3(kDecideThreads), 0, c->stream, c->rec[0],
+                       c->nc, c->d_state, limit);
   else
-    hipLaunchKernelGGL(k_solve_init<3>, dim3(1), dim3(kInitThreads), 0, c->stream, c->rec[0], c->nc,
-                       c->d_state, limit);
+    hipLaunchKernelGGL(k_solve_init<3>, dim3(1), dim3(kDecideThreads), 0, c->stream, c->rec[0],
+                       c->nc, c->d_state, limit);
   return hipGetLastError();
 }
 
-hipError_t cd_launch_sweep(cd_ctx* c) {
+hipError_t cd_launch_sweep(cd_ctx* c, hipEvent_t before, hipEvent_t after) {
   SweepArgs a = cd_sweep_args(c);
-  if (c->dim == 2)
-    hipLaunchKernelGGL(k_sweep<2>, dim3(a.grid), dim3(c->sweep_threads), c->sweep_lds, c->stream,
-                       a);
-  else
-    hipLaunchKernelGGL(k_sweep<3>, dim3(a.grid), dim3(c->sweep_threads), c->sweep_lds, c->stream,
-                       a);
+  if (before) {
+    hipError_t e = hipEventRecord(before, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid(a.grid), block(c->sweep_threads);
+  if (c->dim == 2) {
+    if (c->sweep_global)
+      hipLaunchKernelGGL((k_sweep<2, true>), grid, block, 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((k_sweep<2, false>), grid, block, c->sweep_lds, c->stream, a);
+  } else {
+    if (c->sweep_global)
+      hipLaunchKernelGGL((k_sweep<3, true>), grid, block, 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((k_sweep<3, false>), grid, block, c->sweep_lds, c->stream, a);
+  }
+  if (after) {
+    hipError_t e = hipEventRecord(after, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideThreads), 0, c->stream, a);
   return hipGetLastError();
 }
 

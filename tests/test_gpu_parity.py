@@ -38,7 +38,7 @@ def both(pk, **kw):
 def close_rel(a, b, scale=None):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
-    s = np.abs(b).max() if scale is None else scale
+    s = np.abs(b).max(initial=0.0) if scale is None else scale
     s = max(s, 1e-300)
     return float(np.abs(a - b).max(initial=0.0)) / s
 
@@ -128,9 +128,25 @@ def test_fixed_sweeps_and_signed_gap():
 
 
 def test_more_domains_than_contacts():
+    """Empty domains and one-contact domains (a nearly fully parallel update),
+    over a fixed number of sweeps."""
+    pk = inputs.lattice_2d(6, 6, 15)
+    sim, ctx = both(pk, mu=0.3, n_domains=100, fixed_iters=12)
+    compare_step(sim, ctx, "P=100 tiny")
+
+
+def test_parallel_update_divergence_is_reported():
+    """With about one contact per domain the update is the fully parallel
+    (Jacobi) scheme, unstable in a dense packing (Sec. 2.3): both sides see
+    the forces diverge and report a non-finite force."""
+    from paper_1104_3516_amd import binding
     pk = inputs.lattice_2d(6, 6, 15)
     sim, ctx = both(pk, mu=0.3, n_domains=100)
-    compare_step(sim, ctx, "P=100 tiny")
+    with pytest.raises(RuntimeError, match="-4"):
+        sim.step()
+    with pytest.raises(binding.CDError) as err:
+        ctx.step()
+    assert err.value.code == binding.ENONFINITE
 
 
 def test_no_contacts():
@@ -149,6 +165,17 @@ def test_full_size_disks_262k_4096_domains_fixed_sweeps():
     pk = inputs.config("disks_262k")
     sim, ctx = both(pk, mu=0.3, n_domains=4096, repartition_every=10, fixed_iters=20)
     compare_step(sim, ctx, "262k fixed20")
+
+
+def test_full_size_disks_262k_300_sweeps_then_next_step():
+    """The bench configuration over 300 sweeps (host-synchronised chunks of
+    launches included), then a second step from the resulting state."""
+    pk = inputs.config("disks_262k")
+    sim, ctx = both(pk, mu=0.3, n_domains=4096, repartition_every=10, max_iter=300)
+    compare_step(sim, ctx, "262k 300 sweeps")
+    x, v, w = (t.cpu().numpy() for t in ctx.state())
+    print(f"[262k 300 sweeps] vmax after step = {np.sqrt((v ** 2).sum(0)).max():.4g}", flush=True)
+    compare_step(sim, ctx, "262k step 2")
 
 
 def test_full_size_tolerance_step_properties():
