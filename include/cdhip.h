@@ -91,8 +91,11 @@ typedef struct cd_timing {
   double order_ms;       /* per-domain colouring and slot layout */
   double solve_ms;       /* all sweeps, exchange and convergence tests */
   double update_ms;      /* Euler update */
-  double sweep_kernel_ms;  /* summed durations of the sweep launches that did work */
-  int sweep_launches;    /* sweep kernel launches in the last step (including idle ones) */
+  double sweep_kernel_ms;  /* duration of the solve kernel (one-launch mode), or the summed
+                            durations of the sweep launches that did work (per-sweep mode) */
+  int sweep_launches;    /* solve / sweep kernel launches in the last step */
+  int sweeps_executed;   /* sweeps computed, including the one the stop decision overlaps */
+  int block_threads;     /* threads of the workgroup that sweeps one domain */
 } cd_timing;
 
 typedef struct cd_ctx cd_ctx;
@@ -152,6 +155,16 @@ int cd_get_tree(cd_ctx* ctx, int32_t* axis, double* cut, int32_t* child, int32_t
 /* per_sweep_events != 0: bracket every sweep launch with HIP events so that
  * cd_timing.sweep_kernel_ms holds the summed kernel durations (default on). */
 int cd_set_timing(cd_ctx* ctx, int per_sweep_events);
+
+/* mode 1 (default): one launch per sweep plus a stop-decision launch.
+ * mode 0: all sweeps of a step in one launch, blocks synchronised by a grid
+ * barrier, the stop decision overlapping the next sweep.  Same results. */
+int cd_set_solve_mode(cd_ctx* ctx, int mode);
+
+/* Threads of the workgroup that sweeps one domain: 64, 128, 192 or 256;
+ * 0 (default) picks the smallest multiple of 64 covering the largest
+ * domain's contacts and particles. */
+int cd_set_launch(cd_ctx* ctx, int block_threads);
 
 /* Phase timings of the last step (host struct). */
 int cd_get_timing(cd_ctx* ctx, cd_timing* out);

@@ -126,9 +126,10 @@ int alloc_tree(cd_ctx* c) {
   CD_TRY(grow(&c->dncol, P));
   CD_TRY(grow(&c->dp_count, P + 1));
   CD_TRY(grow(&c->dp_start, P + 1));
+  CD_TRY(grow(&c->ddesc, 8 * (int64_t)P));
   int grid = 8 * ((P + 7) / 8);
-  CD_TRY(grow(&c->partial, grid));
-  c->partial_cap = grid;
+  CD_TRY(grow(&c->partial, 2 * grid));   // double-buffered by sweep parity
+  c->partial_cap = 2 * grid;
   return CD_OK;
 }
 
@@ -154,6 +155,7 @@ int ensure_capacity(cd_ctx* c, int64_t need) {
   CD_TRY(grow(&c->g_mask, 2 * cap));
   CD_TRY(grow(&c->dpb, (int64_t)(2 * c->dim + 2 * c->dr + 3) * 2 * cap));
   CD_TRY(grow(&c->dinc_ptr, 2 * cap + 1));
+  CD_TRY(grow(&c->drow, (int64_t)cd_row_width(c->dim) * 2 * cap));
   for (int k = 0; k < 3; ++k) {
     if (k < c->dim) CD_TRY(grow(&c->perm[k], cap));
   }
@@ -216,6 +218,9 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }
 
 }  // namespace
+
+static_assert(sizeof(GridBar) <= 512 && sizeof(DomainStats) <= 512 && 6 * sizeof(double) <= 512,
+              "pinned scratch holds every small readback");
 
 extern "C" {
 
@@ -292,11 +297,16 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
   alloci(&c->inc_cursor, n + 1);
   if (st == CD_OK && hipMalloc((void**)&c->d_state, sizeof(SolveState)) != hipSuccess) st = CD_ENOMEM;
   if (st == CD_OK && hipMalloc((void**)&c->d_stats, sizeof(DomainStats)) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK && hipMalloc((void**)&c->d_bar, sizeof(GridBar)) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK && (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount,
+                                            c->device) != hipSuccess ||
+                      c->num_cu < 1))
+    st = CD_EHIP;
   if (st == CD_OK && hipMalloc((void**)&c->d_vmax, sizeof(unsigned long long)) != hipSuccess)
     st = CD_ENOMEM;
   if (st == CD_OK && hipHostMalloc((void**)&c->h_state, sizeof(SolveState)) != hipSuccess)
     st = CD_ENOMEM;
-  if (st == CD_OK && hipHostMalloc((void**)&c->h_scratch, 64) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK && hipHostMalloc((void**)&c->h_scratch, 512) != hipSuccess) st = CD_ENOMEM;
   if (st == CD_OK) {
     build_tree_shape(c);
     st = alloc_tree(c);
@@ -341,8 +351,11 @@ int cd_destroy(cd_ctx* c) {
   release(&c->dpb);
   release(&c->dinc_ptr);
   release(&c->dinc);
+  release(&c->drow);
+  release(&c->ddesc);
   release(&c->d_state);
   release(&c->d_stats);
+  release(&c->d_bar);
   release(&c->partial);
   release(&c->d_vmax);
   if (c->h_state) (void)hipHostFree(c->h_state);
@@ -451,6 +464,18 @@ int cd_set_timing(cd_ctx* c, int per_sweep_events) {
   return CD_OK;
 }
 
+int cd_set_solve_mode(cd_ctx* c, int mode) {
+  if (!c || (mode != 0 && mode != 1)) return CD_EINVAL;
+  c->persistent = mode == 0;
+  return CD_OK;
+}
+
+int cd_set_launch(cd_ctx* c, int block_threads) {
+  if (!c || block_threads < 0 || block_threads > 256 || block_threads % 64 != 0) return CD_EINVAL;
+  c->block_override = block_threads;
+  return CD_OK;
+}
+
 int cd_step(cd_ctx* c, cd_result* out) {
   if (!c) return CD_EINVAL;
   if (!c->have_particles || !c->have_box) return fail(c, CD_ENOTREADY, "particles or box not set");
@@ -528,10 +553,19 @@ int cd_step(cd_ctx* c, cd_result* out) {
     c->dinc_cap = cap;
   }
   CD_TRY(cd_launch_order_entries(c));
-  const size_t lds = (size_t)std::max(ds.max_lds, 8);
-  // static LDS of the sweep kernel (reduction scratch) stays below 1 KiB
-  c->sweep_global = lds + 1024 > c->max_lds;
+  // LDS staging per domain, 32-byte aligned; the static LDS of the sweep
+  // kernels (colour offsets, reduction scratch) stays below 2 KiB
+  const size_t lds = ((size_t)std::max(ds.max_lds, 8) + 31) / 32 * 32;
+  c->sweep_global = lds + 2048 > c->max_lds;
   c->sweep_lds = c->sweep_global ? 0 : lds;
+  // one workgroup per domain, wide enough to stage its contacts and gather
+  // its particles in one pass (the work is latency-bound)
+  {
+    const int widest = std::max(ds.max_contacts, ds.max_particles);
+    int t = 64 * ((widest + 63) / 64);
+    c->sweep_block = std::min(256, std::max(64, t));
+    if (c->block_override > 0) c->sweep_block = c->block_override;
+  }
   if (c->sweep_global) {
     // domains too large for LDS stage their data in global memory
     const int sd = (dim == 2 ? 2 : 9) + 5 + dim;
@@ -541,40 +575,64 @@ int cd_step(cd_ctx* c, cd_result* out) {
       c->gscr_cap = need;
     }
   }
-  c->sweep_threads = ds.max_contacts > 512 ? 256 : (ds.max_contacts > 128 ? 128 : 64);
   CD_TRY(hipEventRecord(c->ev[3], c->stream));
   // ---- iterative solve
   const int limit = c->p.fixed_iters > 0 ? c->p.fixed_iters : c->p.max_iter;
   CD_TRY(cd_launch_solve_init(c, limit));
   int launched = 0;
-  int chunk = c->last.iterations > 8 ? c->last.iterations - 2 : 16;
-  if (c->p.fixed_iters > 0) chunk = limit;
-  if (c->time_sweeps && (int)c->sweep_ev.size() < 2 * limit) {
-    size_t old = c->sweep_ev.size();
-    c->sweep_ev.resize(2 * (size_t)limit, nullptr);
-    for (size_t k = old; k < c->sweep_ev.size(); ++k) CD_TRY(hipEventCreate(&c->sweep_ev[k]));
-  }
-  c->h_state->done = nc == 0 || limit <= 0;
-  while (!c->h_state->done && launched < limit) {
-    int k = std::min(chunk, limit - launched);
-    for (int q = 0; q < k; ++q) {
-      if (c->time_sweeps)
-        CD_TRY(cd_launch_sweep(c, c->sweep_ev[2 * (launched + q)],
-                               c->sweep_ev[2 * (launched + q) + 1]));
-      else
-        CD_TRY(cd_launch_sweep(c, nullptr, nullptr));
+  int executed = -1;
+  bool aborted = false;
+  const int G = c->persistent ? cd_solve_grid(c) : 0;
+  if (G >= 8 && nc > 0 && limit > 0) {
+    // all sweeps in one launch
+    if ((int)c->sweep_ev.size() < 2) {
+      size_t old = c->sweep_ev.size();
+      c->sweep_ev.resize(2, nullptr);
+      for (size_t k = old; k < 2; ++k) CD_TRY(hipEventCreate(&c->sweep_ev[k]));
     }
-    launched += k;
+    CD_TRY(hipEventRecord(c->sweep_ev[0], c->stream));
+    CD_TRY(cd_launch_solve(c, G, limit));
+    CD_TRY(hipEventRecord(c->sweep_ev[1], c->stream));
+    launched = 1;
     CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
                           c->stream));
+    GridBar* hb = (GridBar*)c->h_scratch;
+    CD_TRY(hipMemcpyAsync(hb, c->d_bar, sizeof(GridBar), hipMemcpyDeviceToHost, c->stream));
     CD_TRY(hipStreamSynchronize(c->stream));
-    chunk = 16;
+    aborted = hb->abort != 0;
+    // the sweep after the stopping one runs before the stop is seen
+    executed = c->h_state->done && c->h_state->iter < limit ? c->h_state->iter + 1 : c->h_state->iter;
+  } else {
+    int chunk = c->last.iterations > 8 ? c->last.iterations - 2 : 16;
+    if (c->p.fixed_iters > 0) chunk = limit;
+    if (c->time_sweeps && (int)c->sweep_ev.size() < 2 * limit) {
+      size_t old = c->sweep_ev.size();
+      c->sweep_ev.resize(2 * (size_t)limit, nullptr);
+      for (size_t k = old; k < c->sweep_ev.size(); ++k) CD_TRY(hipEventCreate(&c->sweep_ev[k]));
+    }
+    c->h_state->done = nc == 0 || limit <= 0;
+    while (!c->h_state->done && launched < limit) {
+      int k = std::min(chunk, limit - launched);
+      for (int q = 0; q < k; ++q) {
+        if (c->time_sweeps)
+          CD_TRY(cd_launch_sweep(c, c->sweep_ev[2 * (launched + q)],
+                                 c->sweep_ev[2 * (launched + q) + 1]));
+        else
+          CD_TRY(cd_launch_sweep(c, nullptr, nullptr));
+      }
+      launched += k;
+      CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
+                            c->stream));
+      CD_TRY(hipStreamSynchronize(c->stream));
+      chunk = 16;
+    }
+    if (nc == 0 || limit <= 0) {
+      CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
+                            c->stream));
+      CD_TRY(hipStreamSynchronize(c->stream));
+    }
   }
-  if (nc == 0 || limit <= 0) {
-    CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
-                          c->stream));
-    CD_TRY(hipStreamSynchronize(c->stream));
-  }
+  if (aborted) return fail(c, CD_EHIP, "solve grid barrier did not complete (poll limit)");
   SolveState s;
   memcpy(&s, c->h_state, sizeof(SolveState));
   CD_TRY(hipEventRecord(c->ev[4], c->stream));
@@ -620,10 +678,17 @@ int cd_step(cd_ctx* c, cd_result* out) {
   tm.solve_ms = elapsed(c->ev[3], c->ev[4]);
   tm.update_ms = elapsed(c->ev[4], c->ev[5]);
   tm.sweep_launches = launched;
+  tm.block_threads = c->sweep_block;
   double sk = 0.0;
-  if (c->time_sweeps)
-    for (int q = 0; q < std::min(launched, s.iter); ++q)
-      sk += elapsed(c->sweep_ev[2 * q], c->sweep_ev[2 * q + 1]);
+  if (executed >= 0) {
+    sk = elapsed(c->sweep_ev[0], c->sweep_ev[1]);
+    tm.sweeps_executed = executed;
+  } else {
+    if (c->time_sweeps)
+      for (int q = 0; q < std::min(launched, s.iter); ++q)
+        sk += elapsed(c->sweep_ev[2 * q], c->sweep_ev[2 * q + 1]);
+    tm.sweeps_executed = s.iter;
+  }
   tm.sweep_kernel_ms = sk;
   c->timing = tm;
   if (out) *out = res;

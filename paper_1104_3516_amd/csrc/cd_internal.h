@@ -39,7 +39,7 @@ struct SolveState {
   double r_avg;
   double r_avg_prev;
   int conv;
-  int pad;
+  int stop_at;        // the sweep whose decision stopped the solve (0: none yet)
 };
 
 struct DomainStats {
@@ -50,6 +50,16 @@ struct DomainStats {
   int max_lds;        // largest per-domain staging size of the sweep, bytes
   int dinc_total;     // incidences summed over all domain particle entries
   int dp_total;       // domain particle entries
+  int pad;
+};
+
+// grid barrier of the one-launch solve
+struct GridBar {
+  unsigned xcount[8][2];  // arrivals per XCD, alternating by sweep parity
+  unsigned count[2];      // XCDs whose blocks have all arrived, by parity
+  int gen;                // last sweep whose barrier has opened
+  int dec;                // last sweep whose stop decision is published
+  int abort;              // a wait exceeded its poll limit
   int pad;
 };
 
@@ -73,6 +83,8 @@ struct SweepArgs {
   int64_t dpe;
   const int* dinc_ptr;      // per entry: incident slots, ascending contact id
   const int* dinc;          // slot * 2 + (1 if body 2)
+  const int* drow;          // per entry: the same in fixed-width rows (see k_dinc_rows)
+  const int* ddesc;         // per domain: cs, nct, ps, np, ncol (8 ints)
   // slots
   const int2* ab;           // local body indices; b < 0: wall -1-b
   const double* geo;        // per-slot constants, SoA with stride cap
@@ -84,8 +96,9 @@ struct SweepArgs {
   int P;
   int n;                    // particles (SoA stride)
   int cap;                  // slot capacity (SoA stride of geo)
-  int grid;                 // blocks in the launch
+  int grid;                 // blocks of a one-sweep launch
   int per_xcd;              // domains per XCD in the block -> domain map
+  int wave_lds;             // LDS staging per wavefront (doubles)
   long long nc;
   double alpha;
   double mu;
@@ -185,6 +198,10 @@ struct cd_ctx {
   int* dinc_ptr = nullptr;       // 2 cap + 1
   int* dinc = nullptr;
   int64_t dinc_cap = 0;
+  int* drow = nullptr;           // 2 cap x row width
+  int* ddesc = nullptr;          // P x 8
+  int sweep_block = 64;          // threads per domain workgroup
+  int block_override = 0;        // 0: chosen from the domain sizes
   bool sweep_global = false;
   size_t max_lds = 65536;
   int *inc_count = nullptr, *inc_ptr = nullptr, *inc_cursor = nullptr, *inc = nullptr;
@@ -192,6 +209,9 @@ struct cd_ctx {
 
   // solve
   SolveState* d_state = nullptr;
+  GridBar* d_bar = nullptr;
+  int num_cu = 0;
+  bool persistent = false;  // one launch per solve (grid barrier) instead of per sweep
   SolveState* h_state = nullptr;   // pinned
   BlockPartial* partial = nullptr;
   int partial_cap = 0;
@@ -203,8 +223,7 @@ struct cd_ctx {
   int64_t scan_tmp_cap = 0;
 
   // sweep launch shape
-  int sweep_threads = 64;
-  size_t sweep_lds = 0;
+  size_t sweep_lds = 0;     // LDS staging per wavefront (domain), bytes
 
   // timing
   hipEvent_t ev[8] = {};
@@ -238,10 +257,16 @@ hipError_t cd_launch_order_entries(cd_ctx* c);   // after the stats readback
 hipError_t cd_launch_solve_init(cd_ctx* c, int limit);
 hipError_t cd_launch_sweep(cd_ctx* c, hipEvent_t before, hipEvent_t after);  // sweep + decision
 hipError_t cd_launch_unslot(cd_ctx* c, int final_iter);
+int cd_solve_grid(cd_ctx* c);                               // co-resident grid, 0 if none
+
+hipError_t cd_launch_solve(cd_ctx* c, int G, int limit);    // all sweeps in one launch
 // update.hip
 hipError_t cd_launch_update(cd_ctx* c, int final_iter);
 hipError_t cd_launch_derived(cd_ctx* c);
 SweepArgs cd_sweep_args(cd_ctx* c);
+
+// incidence row width of the sweep's particle gathers
+static inline int cd_row_width(int dim) { return dim == 2 ? 8 : 16; }
 
 // helpers
 static inline int cd_blocks(int64_t n, int threads) {

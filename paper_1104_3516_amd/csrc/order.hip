@@ -131,6 +131,7 @@ struct BuildArgs {
   double* rec0;
   int* dcol;
   int* dncol;
+  int* ddesc;             // per domain: cs, nct, ps, np, ncol, 0, 0, 0
   DomainStats* stats;
 };
 
@@ -197,6 +198,13 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   }
   const int ncol = s_ncol;
   if (threadIdx.x == 0) {
+    int* dd = a.ddesc + 8 * (int64_t)d;
+    dd[0] = cs;
+    dd[1] = nct;
+    dd[2] = ps;
+    dd[3] = np;
+    dd[4] = ncol;
+    dd[5] = dd[6] = dd[7] = 0;
     atomicMax(&a.stats->max_colors, ncol);
     atomicMax(&a.stats->max_contacts, nct);
     atomicMax(&a.stats->max_particles, np);
@@ -370,6 +378,25 @@ __global__ __launch_bounds__(kThreads) void k_dinc_fill(const int* dp, const int
   for (int k = s0; k < s1; ++k) dinc[o++] = inc[k];
 }
 
+// fixed-width incidence rows: the first KW incident slots of each domain
+// particle entry, padded with -1; a row starting with -2 marks an entry with
+// more than KW incidences, whose list is read through dinc_ptr / dinc
+__global__ __launch_bounds__(kThreads) void k_dinc_rows(const int* dp, const int* dp_start, int P,
+                                                       int64_t E, int KW, const int* inc_ptr,
+                                                       const int* inc, int* rows) {
+  int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= E || e >= dp_start[P]) return;
+  const int p = dp[e];
+  const int s0 = inc_ptr[p], deg = inc_ptr[p + 1] - s0;
+  int* row = rows + e * KW;
+  if (deg > KW) {
+    row[0] = -2;
+    for (int k = 1; k < KW; ++k) row[k] = -1;
+    return;
+  }
+  for (int k = 0; k < KW; ++k) row[k] = k < deg ? inc[s0 + k] : -1;
+}
+
 int bits_for(unsigned long long maxval) {
   int b = 0;
   while (b < 64 && (maxval >> b) != 0ull) ++b;
@@ -457,6 +484,7 @@ hipError_t cd_launch_order(cd_ctx* c) {
   a.rec0 = c->rec[0];
   a.dcol = c->dcol;
   a.dncol = c->dncol;
+  a.ddesc = c->ddesc;
   a.stats = c->d_stats;
   if (c->dim == 2)
     hipLaunchKernelGGL(k_dom_build<2>, dim3(P), dim3(kBuild), 0, c->stream, a);
@@ -499,5 +527,8 @@ hipError_t cd_launch_order_entries(cd_ctx* c) {
   const int64_t E = 2 * c->cap;
   hipLaunchKernelGGL(k_dinc_fill, dim3(cd_blocks(E, kThreads)), dim3(kThreads), 0, c->stream,
                      c->dp, c->dp_start, c->P, E, c->inc_ptr, c->inc, c->dinc_ptr, c->dinc);
+  hipLaunchKernelGGL(k_dinc_rows, dim3(cd_blocks(E, kThreads)), dim3(kThreads), 0, c->stream,
+                     c->dp, c->dp_start, c->P, E, cd_row_width(c->dim), c->inc_ptr, c->inc,
+                     c->drow);
   return hipGetLastError();
 }

@@ -13,7 +13,8 @@ def test_header_declares_the_boundary():
     for required in ("cd_create", "cd_destroy", "cd_set_particles", "cd_set_external",
                      "cd_set_walls", "cd_set_box", "cd_step", "cd_get_state",
                      "cd_get_contacts", "cd_get_tree", "cd_get_timing", "cd_status_string",
-                     "cd_last_error", "cd_num_contacts", "cd_get_walls", "cd_set_timing"):
+                     "cd_last_error", "cd_num_contacts", "cd_get_walls", "cd_set_timing",
+                     "cd_set_solve_mode", "cd_set_launch"):
         assert required in names
 
 
@@ -32,7 +33,7 @@ def test_struct_layouts_match_header():
     # the ctypes mirrors have the C sizes of the header structs
     assert ctypes.sizeof(binding.Params) == 4 * 2 + 8 * 3 + 4 * 8 + 8
     assert ctypes.sizeof(binding.Result) == 4 * 2 + 8 * 2 + 8 * 4 + 4 * 2
-    assert ctypes.sizeof(binding.Timing) == 8 * 6 + 8
+    assert ctypes.sizeof(binding.Timing) == 8 * 6 + 4 * 4
 
 
 def test_product_package_does_not_import_the_oracle():

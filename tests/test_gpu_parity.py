@@ -26,13 +26,13 @@ def _torch():
     return torch
 
 
-def both(pk, **kw):
+def both(pk, solve_mode=1, **kw):
     from oracle import cdref
     from paper_1104_3516_amd import binding
     _torch()
     po = cdref.make_params(pk.dim, pk.n_walls, **kw)
     pg = binding.make_params(pk.dim, pk.n_walls, **kw)
-    return cdref.Sim(po, pk), binding.Context(pg, pk)
+    return cdref.Sim(po, pk), binding.Context(pg, pk, solve_mode=solve_mode)
 
 
 def close_rel(a, b, scale=None):
@@ -104,6 +104,15 @@ def test_disks_4k_64_domains_multi_step():
     sim, ctx = both(pk, mu=0.3, n_domains=64, repartition_every=2)
     for s in range(4):
         compare_step(sim, ctx, f"disks_4k step{s}")
+
+
+def test_one_launch_solve_mode():
+    """The whole solve in one launch (grid barrier, overlapped stop decision)
+    gives the same results as one launch per sweep."""
+    pk = inputs.lattice_2d(48, 40, 17)
+    sim, ctx = both(pk, solve_mode=0, mu=0.3, n_domains=32, repartition_every=2)
+    for s in range(3):
+        compare_step(sim, ctx, f"one-launch mode step{s}")
 
 
 def test_ragged_lattice_odd_domain_count():
