@@ -49,7 +49,7 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_ctx(pk, binding, timing=True, solve_mode=1, block=0):
+def make_ctx(pk, binding, timing=1, solve_mode=1, block=0):
     params = binding.make_params(2, pk.n_walls, mu=0.3, dt=1e-3, alpha=1e-6, criterion=0,
                                  max_iter=2000, n_domains=N_DOMAINS, repartition_every=10,
                                  warm_start=1)
@@ -84,6 +84,8 @@ def main() -> int:
                     help="sweep cap of the CPU-oracle sample (0 skips it)")
     ap.add_argument("--solve-mode", type=int, default=1,
                     help="1: one launch per sweep; 0: all sweeps of a step in one launch")
+    ap.add_argument("--time-every", type=int, default=1,
+                    help="bracket every k-th sweep launch with HIP events (0: none)")
     ap.add_argument("--block", type=int, default=0,
                     help="threads per domain workgroup (0: chosen from the domain sizes)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles",
@@ -112,7 +114,8 @@ def main() -> int:
         ctx.close()
         del ctx
 
-    ctx = make_ctx(pk, binding, solve_mode=args.solve_mode, block=args.block)
+    ctx = make_ctx(pk, binding, timing=args.time_every, solve_mode=args.solve_mode,
+                   block=args.block)
     torch.cuda.synchronize()
     sweeps = 0
     updates = 0
@@ -121,6 +124,7 @@ def main() -> int:
     bytes_sweeps = 0.0
     maxiter_steps = 0
     executed = 0
+    timed = 0
     t0 = time.perf_counter()
     for s in range(args.steps):
         r = ctx.step()
@@ -130,6 +134,7 @@ def main() -> int:
         sweep_kernel_ms += tm.sweep_kernel_ms
         solve_ms += tm.solve_ms
         executed += tm.sweeps_executed
+        timed += tm.sweeps_timed
         bytes_sweeps += tm.sweeps_executed * (BYTES_PER_CONTACT_2D * r.n_contacts +
                                               BYTES_PER_PARTICLE_2D * pk.n)
         maxiter_steps += int(r.status == binding.MAXITER)
@@ -172,6 +177,7 @@ def main() -> int:
         "solve_contact_updates_per_s": updates / (solve_ms / 1e3) if solve_ms > 0 else None,
         "sweep_kernel_us": 1e6 * avg_sweep_s,
         "sweeps_executed": executed,
+        "sweeps_timed": timed,
         "solve_mode": args.solve_mode,
         "block_threads": tm.block_threads,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

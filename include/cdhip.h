@@ -91,11 +91,13 @@ typedef struct cd_timing {
   double order_ms;       /* per-domain colouring and slot layout */
   double solve_ms;       /* all sweeps, exchange and convergence tests */
   double update_ms;      /* Euler update */
-  double sweep_kernel_ms;  /* duration of the solve kernel (one-launch mode), or the summed
-                            durations of the sweep launches that did work (per-sweep mode) */
+  double sweep_kernel_ms;  /* duration of the solve kernel (one-launch mode), or the
+                            mean duration of the timed sweep launches times the sweeps
+                            executed (per-sweep mode) */
   int sweep_launches;    /* solve / sweep kernel launches in the last step */
   int sweeps_executed;   /* sweeps computed, including the one the stop decision overlaps */
   int block_threads;     /* threads of the workgroup that sweeps one domain */
+  int sweeps_timed;      /* sweep launches bracketed by events (per-sweep mode) */
 } cd_timing;
 
 typedef struct cd_ctx cd_ctx;
@@ -152,11 +154,14 @@ int cd_get_contacts(cd_ctx* ctx, int64_t cap, int32_t* ci, int32_t* cj, double* 
  * id (-1 for inner nodes). */
 int cd_get_tree(cd_ctx* ctx, int32_t* axis, double* cut, int32_t* child, int32_t* leaf);
 
-/* per_sweep_events != 0: bracket every sweep launch with HIP events so that
- * cd_timing.sweep_kernel_ms holds the summed kernel durations (default on). */
-int cd_set_timing(cd_ctx* ctx, int per_sweep_events);
+/* every > 0: bracket sweep launches 2, 2+every, 2+2 every, ... with HIP
+ * events; cd_timing.sweep_kernel_ms is their mean duration times the sweeps
+ * executed.  0 records no per-sweep events.  Default 1 (every launch). */
+int cd_set_timing(cd_ctx* ctx, int every);
 
-/* mode 1 (default): one launch per sweep plus a stop-decision launch.
+/* mode 1 (default): one launch per sweep; an extra workgroup of each launch
+ * takes the stop decision of the previous sweep, so the launch after the
+ * stopping sweep computes a sweep whose result is discarded.
  * mode 0: all sweeps of a step in one launch, blocks synchronised by a grid
  * barrier, the stop decision overlapping the next sweep.  Same results. */
 int cd_set_solve_mode(cd_ctx* ctx, int mode);

@@ -39,7 +39,8 @@ class Timing(C.Structure):
     _fields_ = [("detect_ms", C.c_double), ("partition_ms", C.c_double),
                 ("order_ms", C.c_double), ("solve_ms", C.c_double), ("update_ms", C.c_double),
                 ("sweep_kernel_ms", C.c_double), ("sweep_launches", C.c_int),
-                ("sweeps_executed", C.c_int), ("block_threads", C.c_int)]
+                ("sweeps_executed", C.c_int), ("block_threads", C.c_int),
+                ("sweeps_timed", C.c_int)]
 
 
 def make_params(dim: int, n_walls: int, *, dt=1e-3, alpha=1e-6, mu=0.3, criterion=0,
@@ -107,7 +108,7 @@ class CDError(RuntimeError):
 class Context:
     """One simulation on one GPU.  `packing` is a paper_1104_3516_amd.inputs.Packing."""
 
-    def __init__(self, params: Params, packing, device: str = "cuda:0", timing: bool = True,
+    def __init__(self, params: Params, packing, device: str = "cuda:0", timing: int = 1,
                  solve_mode: int = 1, block_threads: int = 0):
         import torch
         if not torch.cuda.is_available():
@@ -146,7 +147,7 @@ class Context:
             hi = np.ascontiguousarray(packing.box_hi, dtype=np.float64)
             self._check(self.L.cd_set_box(self.h, lo.ctypes.data_as(C.c_void_p),
                                           hi.ctypes.data_as(C.c_void_p)))
-            self._check(self.L.cd_set_timing(self.h, 1 if timing else 0))
+            self._check(self.L.cd_set_timing(self.h, int(timing)))
             self._check(self.L.cd_set_solve_mode(self.h, solve_mode))
             self._check(self.L.cd_set_launch(self.h, block_threads))
             torch.cuda.synchronize(self.device)

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 
 #include "cd_internal.h"
@@ -298,6 +299,8 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
   if (st == CD_OK && hipMalloc((void**)&c->d_state, sizeof(SolveState)) != hipSuccess) st = CD_ENOMEM;
   if (st == CD_OK && hipMalloc((void**)&c->d_stats, sizeof(DomainStats)) != hipSuccess) st = CD_ENOMEM;
   if (st == CD_OK && hipMalloc((void**)&c->d_bar, sizeof(GridBar)) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK && hipMalloc((void**)&c->init_part, sizeof(double) * 256) != hipSuccess)
+    st = CD_ENOMEM;
   if (st == CD_OK && (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount,
                                             c->device) != hipSuccess ||
                       c->num_cu < 1))
@@ -307,6 +310,10 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
   if (st == CD_OK && hipHostMalloc((void**)&c->h_state, sizeof(SolveState)) != hipSuccess)
     st = CD_ENOMEM;
   if (st == CD_OK && hipHostMalloc((void**)&c->h_scratch, 512) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK && hipHostMalloc((void**)&c->h_prog, sizeof(HostProg), hipHostMallocMapped) != hipSuccess)
+    st = CD_ENOMEM;
+  if (st == CD_OK && hipHostGetDevicePointer((void**)&c->d_prog, c->h_prog, 0) != hipSuccess)
+    st = CD_EHIP;
   if (st == CD_OK) {
     build_tree_shape(c);
     st = alloc_tree(c);
@@ -357,9 +364,11 @@ int cd_destroy(cd_ctx* c) {
   release(&c->d_stats);
   release(&c->d_bar);
   release(&c->partial);
+  release(&c->init_part);
   release(&c->d_vmax);
   if (c->h_state) (void)hipHostFree(c->h_state);
   if (c->h_scratch) (void)hipHostFree(c->h_scratch);
+  if (c->h_prog) (void)hipHostFree(c->h_prog);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c->sweep_ev)
@@ -458,9 +467,9 @@ int cd_set_box(cd_ctx* c, const double* lo, const double* hi) {
   return CD_OK;
 }
 
-int cd_set_timing(cd_ctx* c, int per_sweep_events) {
-  if (!c) return CD_EINVAL;
-  c->time_sweeps = per_sweep_events != 0;
+int cd_set_timing(cd_ctx* c, int every) {
+  if (!c || every < 0) return CD_EINVAL;
+  c->time_every = every;
   return CD_OK;
 }
 
@@ -546,7 +555,6 @@ int cd_step(cd_ctx* c, cd_result* out) {
     return fail(c, CD_ECAPACITY,
                 ds.overflow == 1 ? "a domain has more than 1024 contacts"
                                  : "a domain needs more than 64 colours");
-  const int dr = c->dr;
   if (ds.dinc_total > c->dinc_cap || !c->dinc) {
     int64_t cap = (int64_t)ds.dinc_total + ds.dinc_total / 4 + 1024;
     CD_TRY(grow(&c->dinc, cap));
@@ -568,8 +576,7 @@ int cd_step(cd_ctx* c, cd_result* out) {
   }
   if (c->sweep_global) {
     // domains too large for LDS stage their data in global memory
-    const int sd = (dim == 2 ? 2 : 9) + 5 + dim;
-    int64_t need = (int64_t)(dim + dr + 3) * 2 * c->cap + (int64_t)(sd + 1) * c->cap;
+    int64_t need = (int64_t)cd_stage_particle(dim) * 2 * c->cap;
     if (need > c->gscr_cap) {
       CD_TRY(grow(&c->gscr, need));
       c->gscr_cap = need;
@@ -582,6 +589,7 @@ int cd_step(cd_ctx* c, cd_result* out) {
   int launched = 0;
   int executed = -1;
   bool aborted = false;
+  bool one_launch = false;
   const int G = c->persistent ? cd_solve_grid(c) : 0;
   if (G >= 8 && nc > 0 && limit > 0) {
     // all sweeps in one launch
@@ -594,6 +602,7 @@ int cd_step(cd_ctx* c, cd_result* out) {
     CD_TRY(cd_launch_solve(c, G, limit));
     CD_TRY(hipEventRecord(c->sweep_ev[1], c->stream));
     launched = 1;
+    one_launch = true;
     CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
                           c->stream));
     GridBar* hb = (GridBar*)c->h_scratch;
@@ -602,35 +611,53 @@ int cd_step(cd_ctx* c, cd_result* out) {
     aborted = hb->abort != 0;
     // the sweep after the stopping one runs before the stop is seen
     executed = c->h_state->done && c->h_state->iter < limit ? c->h_state->iter + 1 : c->h_state->iter;
-  } else {
-    int chunk = c->last.iterations > 8 ? c->last.iterations - 2 : 16;
-    if (c->p.fixed_iters > 0) chunk = limit;
-    if (c->time_sweeps && (int)c->sweep_ev.size() < 2 * limit) {
+  } else if (nc > 0 && limit > 0) {
+    // one launch per sweep, queued ahead of the device by at most
+    // kLookahead sweeps past the last published decision; launches after
+    // the stop return at once.  Progress comes from the mapped record.
+    const int kLookahead = 8;
+    const int every = c->time_every;
+    const int timed_cap = every > 0 ? (limit + every - 1) / every : 0;
+    if ((int)c->sweep_ev.size() < 2 * timed_cap) {
       size_t old = c->sweep_ev.size();
-      c->sweep_ev.resize(2 * (size_t)limit, nullptr);
+      c->sweep_ev.resize(2 * (size_t)timed_cap, nullptr);
       for (size_t k = old; k < c->sweep_ev.size(); ++k) CD_TRY(hipEventCreate(&c->sweep_ev[k]));
     }
-    c->h_state->done = nc == 0 || limit <= 0;
-    while (!c->h_state->done && launched < limit) {
-      int k = std::min(chunk, limit - launched);
-      for (int q = 0; q < k; ++q) {
-        if (c->time_sweeps)
-          CD_TRY(cd_launch_sweep(c, c->sweep_ev[2 * (launched + q)],
-                                 c->sweep_ev[2 * (launched + q) + 1]));
-        else
-          CD_TRY(cd_launch_sweep(c, nullptr, nullptr));
+    volatile HostProg* hp = c->h_prog;
+    hp->decided = 0;
+    hp->done = 0;
+    __sync_synchronize();
+    while (launched < limit && !hp->done) {
+      if (launched - hp->decided >= kLookahead) {
+        // wait for the device; give up (CD_EHIP) if it stops making progress
+        const int seen = hp->decided;
+        auto t0 = std::chrono::steady_clock::now();
+        while (hp->decided == seen && !hp->done) {
+          if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
+            return fail(c, CD_EHIP, "solve made no progress for 60 s");
+        }
+        continue;
       }
-      launched += k;
-      CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
-                            c->stream));
-      CD_TRY(hipStreamSynchronize(c->stream));
-      chunk = 16;
+      const int j = launched + 1;
+      // sweeps 2, 2 + every, ... are timed (the first carries start-up costs)
+      const bool timed = every > 0 && j >= 2 && (j - 2) % every == 0;
+      const int slot = timed ? (j - 2) / every : -1;
+      CD_TRY(cd_launch_sweep(c, j, timed ? c->sweep_ev[2 * slot] : nullptr,
+                             timed ? c->sweep_ev[2 * slot + 1] : nullptr));
+      launched = j;
     }
-    if (nc == 0 || limit <= 0) {
-      CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
-                            c->stream));
-      CD_TRY(hipStreamSynchronize(c->stream));
-    }
+    // the decision of the last launched sweep, if the solve is still open
+    CD_TRY(cd_launch_decide(c, launched));
+    CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
+                          c->stream));
+    CD_TRY(hipStreamSynchronize(c->stream));
+    // sweeps that did work: every launch up to the one after the stopping sweep
+    executed = std::min(launched, c->h_state->iter + 1);
+  } else {
+    CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
+                          c->stream));
+    CD_TRY(hipStreamSynchronize(c->stream));
+    executed = 0;
   }
   if (aborted) return fail(c, CD_EHIP, "solve grid barrier did not complete (poll limit)");
   SolveState s;
@@ -680,14 +707,20 @@ int cd_step(cd_ctx* c, cd_result* out) {
   tm.sweep_launches = launched;
   tm.block_threads = c->sweep_block;
   double sk = 0.0;
-  if (executed >= 0) {
+  tm.sweeps_executed = std::max(executed, 0);
+  if (one_launch) {
     sk = elapsed(c->sweep_ev[0], c->sweep_ev[1]);
-    tm.sweeps_executed = executed;
-  } else {
-    if (c->time_sweeps)
-      for (int q = 0; q < std::min(launched, s.iter); ++q)
-        sk += elapsed(c->sweep_ev[2 * q], c->sweep_ev[2 * q + 1]);
-    tm.sweeps_executed = s.iter;
+  } else if (c->time_every > 0 && executed >= 2) {
+    // mean over the timed launches that did work, times the working sweeps
+    double sum = 0.0;
+    int cnt = 0;
+    for (int j = 2; j <= executed; j += c->time_every) {
+      const int slot = (j - 2) / c->time_every;
+      sum += elapsed(c->sweep_ev[2 * slot], c->sweep_ev[2 * slot + 1]);
+      ++cnt;
+    }
+    sk = cnt > 0 ? sum / cnt * executed : 0.0;
+    tm.sweeps_timed = cnt;
   }
   tm.sweep_kernel_ms = sk;
   c->timing = tm;

@@ -63,6 +63,14 @@ struct GridBar {
   int pad;
 };
 
+// progress of the solve, in mapped pinned host memory: written by the
+// device (system scope) so the host can follow without synchronising
+struct HostProg {
+  int decided;        // last sweep whose stop decision is taken
+  int done;
+  int pad[14];
+};
+
 struct BlockPartial {
   long long n_pass;
   double max_d_fail;
@@ -89,10 +97,12 @@ struct SweepArgs {
   const int2* ab;           // local body indices; b < 0: wall -1-b
   const double* geo;        // per-slot constants, SoA with stride cap
   const double* walls_u;    // W x dim wall velocities
+  int n_walls;
   double* rec[2];
   // convergence
   SolveState* state;
   BlockPartial* partial;
+  HostProg* prog;           // device address of the mapped progress record
   int P;
   int n;                    // particles (SoA stride)
   int cap;                  // slot capacity (SoA stride of geo)
@@ -213,7 +223,11 @@ struct cd_ctx {
   int num_cu = 0;
   bool persistent = false;  // one launch per solve (grid barrier) instead of per sweep
   SolveState* h_state = nullptr;   // pinned
+  HostProg* h_prog = nullptr;      // mapped pinned (host address)
+  HostProg* d_prog = nullptr;      // its device address
+  int time_every = 1;              // sweep launches timed with events: every k-th (0: none)
   BlockPartial* partial = nullptr;
+  double* init_part = nullptr;     // chunk sums of |R| at the start of a solve (256)
   int partial_cap = 0;
   unsigned long long* d_vmax = nullptr;
   long long* h_scratch = nullptr;  // pinned small readbacks
@@ -228,7 +242,6 @@ struct cd_ctx {
   // timing
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> sweep_ev;
-  bool time_sweeps = true;
   cd_timing timing{};
   cd_result last{};
 };
@@ -255,7 +268,9 @@ hipError_t cd_launch_order(cd_ctx* c);
 hipError_t cd_launch_order_entries(cd_ctx* c);   // after the stats readback
 // sweep.hip
 hipError_t cd_launch_solve_init(cd_ctx* c, int limit);
-hipError_t cd_launch_sweep(cd_ctx* c, hipEvent_t before, hipEvent_t after);  // sweep + decision
+// sweep j; its extra workgroup takes the stop decision of sweep j-1
+hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after);
+hipError_t cd_launch_decide(cd_ctx* c, int jd);            // stop decision of sweep jd alone
 hipError_t cd_launch_unslot(cd_ctx* c, int final_iter);
 int cd_solve_grid(cd_ctx* c);                               // co-resident grid, 0 if none
 
@@ -267,6 +282,9 @@ SweepArgs cd_sweep_args(cd_ctx* c);
 
 // incidence row width of the sweep's particle gathers
 static inline int cd_row_width(int dim) { return dim == 2 ? 8 : 16; }
+// doubles the sweep stages per domain particle: V, W, dt/m, dt/I, r, padded
+// to an even count (2D: 6, 3D: 10)
+__host__ __device__ constexpr int cd_stage_particle(int dim) { return dim == 2 ? 6 : 10; }
 
 // helpers
 static inline int cd_blocks(int64_t n, int threads) {

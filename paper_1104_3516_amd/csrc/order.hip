@@ -143,6 +143,7 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   __shared__ short s_col[kSmall];
   __shared__ int s_pos[kSmall];
   __shared__ int s_coloff[CD_MAX_COLORS + 1];
+  __shared__ int s_run[CD_MAX_COLORS];
   __shared__ int s_ncol, s_bad;
 
   const int d = blockIdx.x;
@@ -184,9 +185,8 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
       // stable counting sort by colour
       for (int k = 0; k < nct; ++k) s_coloff[(small ? s_col[k] : a.qcol[cs + k]) + 1] += 1;
       for (int q = 0; q < ncol; ++q) s_coloff[q + 1] += s_coloff[q];
-      int run[CD_MAX_COLORS];
-      for (int q = 0; q < ncol; ++q) run[q] = s_coloff[q];
-      for (int k = 0; k < nct; ++k) pos[k] = run[small ? s_col[k] : a.qcol[cs + k]]++;
+      for (int q = 0; q < ncol; ++q) s_run[q] = s_coloff[q];
+      for (int k = 0; k < nct; ++k) pos[k] = s_run[small ? s_col[k] : a.qcol[cs + k]]++;
     }
     s_ncol = ncol;
     s_bad = bad;
@@ -208,11 +208,9 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     atomicMax(&a.stats->max_colors, ncol);
     atomicMax(&a.stats->max_contacts, nct);
     atomicMax(&a.stats->max_particles, np);
-    // sweep staging: per particle V, W, dt/m, dt/I, r; per slot frame,
-    // five constants, the old force and the body pair
-    constexpr int PD = DIM + (DIM == 2 ? 1 : 3) + 3;
-    constexpr int SD = (DIM == 2 ? 2 : 9) + 5 + DIM;
-    long long bytes = 8ll * PD * np + (8ll * SD + 8ll) * nct;
+    // sweep staging in LDS: per particle V, W, dt/m, dt/I, r
+    constexpr int PD = cd_stage_particle(DIM);
+    long long bytes = 8ll * PD * np;
     atomicMax(&a.stats->max_lds, (int)(bytes < 0x7fffffffll ? bytes : 0x7fffffffll));
     a.dncol[d] = ncol;
   }
@@ -384,17 +382,20 @@ __global__ __launch_bounds__(kThreads) void k_dinc_fill(const int* dp, const int
 __global__ __launch_bounds__(kThreads) void k_dinc_rows(const int* dp, const int* dp_start, int P,
                                                        int64_t E, int KW, const int* inc_ptr,
                                                        const int* inc, int* rows) {
+  // rows are stored as KW/4 planes of int4, plane q holding entries 4q..4q+3
+  // of every particle entry: rows[(q E + e) 4 + k]
   int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (e >= E || e >= dp_start[P]) return;
   const int p = dp[e];
   const int s0 = inc_ptr[p], deg = inc_ptr[p + 1] - s0;
-  int* row = rows + e * KW;
-  if (deg > KW) {
-    row[0] = -2;
-    for (int k = 1; k < KW; ++k) row[k] = -1;
-    return;
+  for (int q = 0; q < KW / 4; ++q) {
+    int v[4];
+    for (int k = 0; k < 4; ++k) {
+      const int x = 4 * q + k;
+      v[k] = deg > KW ? (x == 0 ? -2 : -1) : (x < deg ? inc[s0 + x] : -1);
+    }
+    *(int4*)(rows + (q * E + e) * 4) = make_int4(v[0], v[1], v[2], v[3]);
   }
-  for (int k = 0; k < KW; ++k) row[k] = k < deg ? inc[s0 + k] : -1;
 }
 
 int bits_for(unsigned long long maxval) {

@@ -1,13 +1,9 @@
 // sweep.hip - the domain-wise iterative force solve (Sec. 2.1 and 3.1).
 //
-// One wavefront sweeps one domain; a 256-thread workgroup carries four
-// domains.  The whole solve of a time step runs in one launch of k_solve
-// (a grid barrier after every sweep); k_sweep + k_decide do one sweep per
-// launch pair and give the same results.
-//  per domain and sweep
-//   0. Stage the domain's slot data in LDS with coalesced loads: contact
-//      frame, force-law constants, the previous sweep's force and the body
-//      pair of every native contact.
+// One workgroup sweeps one domain.  k_sweep does one sweep per launch (its
+// extra workgroup takes the previous sweep's stop decision); k_solve runs all
+// sweeps of a step in one launch with a grid barrier after each.  Both give
+// the same results.  Per domain and sweep:
 //   1. Exchange: recompute the velocities of the domain's particles from
 //      their base velocities and external forces plus every incident contact
 //      force of the previous sweep (native and foreign), into LDS.  This is
@@ -16,7 +12,9 @@
 //   2. Sequential update: colours in order; in a colour, lanes update
 //      contacts that share no particle, each solving its own force law with
 //      all other forces fixed (Eqs. 3-9, Fig. 2) and applying the change to
-//      both bodies' LDS velocities.  New forces go to the other record array,
+//      both bodies' LDS velocities.  A contact's static data (frame,
+//      constants, previous force, body pair) is read from memory into
+//      registers one colour ahead.  New forces go to the other record array,
 //      so no domain sees a force of the current sweep from another domain
 //      (foreign contacts stay frozen for the sweep).
 //   3. The convergence test values (count passing the relative test,
@@ -37,16 +35,22 @@ struct Layout {
   static constexpr int DR = DIM == 2 ? 1 : 3;
   static constexpr int REC = DIM == 2 ? 4 : 12;
   static constexpr int NG = DIM == 2 ? 2 : 9;      // frame doubles per slot
-  static constexpr int PD = DIM + DR + 3;          // staged doubles per particle
-  static constexpr int SD = NG + 5 + DIM;          // staged doubles per slot
+  // staged particle record (doubles): V [0, DIM), W [DIM, DIM+DR), dt/m, dt/I,
+  // r, padded to an even count so that pairs load as 16-byte words
+  static constexpr int PS = cd_stage_particle(DIM);
+  static constexpr int P_W = DIM, P_DM = DIM + DR, P_DI = DIM + DR + 1, P_R = DIM + DR + 2;
+  static_assert(P_R < PS && PS % 2 == 0, "particle staging layout");
 };
 
+// The single-contact law (Eqs. 3-9, Fig. 2) for the contact's frame n, t1,
+// t2 and the body velocities; dwR = (dt w_n R_n, dt w_t R_t1, dt w_t R_t2) of
+// the contact's current force removes that force's own share of the relative
+// velocity.  Writes the new frame force.
 template <int DIM>
 __device__ inline void local_force(const double* n, const double* t1, const double* t2, double gdt,
-                                   double dwn, double dwt, double kn, double kt, double mu,
-                                   double ra, double rb, const double* Va, const double* Wa,
-                                   const double* Vb, const double* Wb, const double* Rold,
-                                   double* Rnew) {
+                                   const double* dwR, double kn, double kt, double mu, double ra,
+                                   double rb, const double* Va, const double* Wa, const double* Vb,
+                                   const double* Wb, double* Rnew) {
   double dV[3];
   for (int q = 0; q < DIM; ++q) dV[q] = Vb[q] - Va[q];
   double vn = 0.0;
@@ -70,9 +74,9 @@ __device__ inline void local_force(const double* n, const double* t1, const doub
     vt2 = dvt2 + s1;
   }
   // relative velocity the pair would have without this contact's force
-  double un = vn - dwn * Rold[0];
-  double ut1 = vt1 - dwt * Rold[1];
-  double ut2 = DIM == 3 ? vt2 - dwt * Rold[2] : 0.0;
+  double un = vn - dwR[0];
+  double ut1 = vt1 - dwR[1];
+  double ut2 = DIM == 3 ? vt2 - dwR[DIM - 1] : 0.0;
   double s = gdt + un;      // predicted gap / dt (Eq. 3)
   Rnew[0] = 0.0;
   Rnew[1] = 0.0;
@@ -101,6 +105,17 @@ __device__ inline void local_force(const double* n, const double* t1, const doub
 
 constexpr int kMaxBlock = 256;
 
+// Workgroup barrier ordering LDS only: unlike __syncthreads it does not wait
+// for the wave's outstanding global loads and stores.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// four doubles stored with one streaming (non-temporal) 32-byte store
+typedef double nt4 __attribute__((ext_vector_type(4)));
+
 // The domain of block b in pass k.  Block b runs on XCD x = b % 8
 // (round-robin dispatch); XCD x owns the contiguous domain range
 // [x per, (x+1) per) of the bisection order, so neighbouring domains share
@@ -116,37 +131,41 @@ __device__ inline int domain_of(const SweepArgs& a, int b, int k, int G8) {
 // Accumulate the previous sweep's contact forces on one particle entry, in
 // ascending contact id: acc -= F (body 1) or += F (body 2), tacc -= r q.
 template <int DIM>
+__device__ inline void add_record(const double* rin, int ent, double rp, double* acc,
+                                  double* tacc) {
+  constexpr int REC = DIM == 2 ? 4 : 12;
+  const double* rc = rin + (int64_t)(ent >> 1) * REC;
+  if (DIM == 2) {
+    const double4 r4 = *(const double4*)rc;
+    acc[0] = (ent & 1) ? acc[0] + r4.z : acc[0] - r4.z;
+    acc[1] = (ent & 1) ? acc[1] + r4.w : acc[1] - r4.w;
+    tacc[0] = tacc[0] - rp * r4.y;
+  } else {
+    const double4 f4 = *(const double4*)(rc + 4), q4 = *(const double4*)(rc + 8);
+    const double F[3] = {f4.x, f4.y, f4.z}, Q[3] = {q4.x, q4.y, q4.z};
+    for (int k = 0; k < 3; ++k) acc[k] = (ent & 1) ? acc[k] + F[k] : acc[k] - F[k];
+    for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * Q[k];
+  }
+}
+
+template <int DIM>
 __device__ inline void gather_forces(const SweepArgs& a, const double* rin, int64_t e, double rp,
                                      double* acc, double* tacc) {
   constexpr int REC = DIM == 2 ? 4 : 12;
   constexpr int KW = DIM == 2 ? 8 : 16;
-  const int* row = a.drow + e * KW;
-  if (row[0] == -2) {
+  // incidence rows: KW/4 planes of int4 (plane q: entries 4q..4q+3)
+  const int4* rows = (const int4*)a.drow;
+  const int64_t E = a.dpe;
+  int4 r4i = rows[e];
+  if (r4i.x == -2) {
     // more incidences than a row holds: the pointer list
     const int e1 = a.dinc_ptr[e + 1];
-    for (int x = a.dinc_ptr[e]; x < e1; ++x) {
-      const int ent = a.dinc[x];
-      const double* rc = rin + (int64_t)(ent >> 1) * REC;
-      if (DIM == 2) {
-        const double4 r4 = *(const double4*)rc;
-        acc[0] = (ent & 1) ? acc[0] + r4.z : acc[0] - r4.z;
-        acc[1] = (ent & 1) ? acc[1] + r4.w : acc[1] - r4.w;
-        tacc[0] = tacc[0] - rp * r4.y;
-      } else {
-        for (int k = 0; k < 3; ++k) {
-          double F = rc[4 + k];
-          acc[k] = (ent & 1) ? acc[k] + F : acc[k] - F;
-        }
-        for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * rc[8 + k];
-      }
-    }
+    for (int x = a.dinc_ptr[e]; x < e1; ++x) add_record<DIM>(rin, a.dinc[x], rp, acc, tacc);
     return;
   }
-  // rows hold the valid entries first: gathers in groups of four in flight
-  for (int g = 0; g < KW; g += 4) {
-    const int4 r4i = *(const int4*)(row + g);
+  // valid entries come first; the next plane is read only after a full one
+  for (int q = 0; q < KW / 4; ++q) {
     const int ent[4] = {r4i.x, r4i.y, r4i.z, r4i.w};
-    if (ent[0] < 0) break;
     if (DIM == 2) {
       double4 rec[4];
       for (int u = 0; u < 4; ++u)
@@ -173,44 +192,209 @@ __device__ inline void gather_forces(const SweepArgs& a, const double* rin, int6
         for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * Q[k];
       }
     }
+    if (ent[3] < 0 || q + 1 == KW / 4) break;
+    r4i = rows[(q + 1) * E + e];
   }
 }
 
-// One sweep of domain d by the calling workgroup: stage, exchange, colour-
-// major update; accumulates the convergence test values of its contacts.
-template <int DIM, bool GLOB>
-__device__ inline void sweep_domain(const SweepArgs& a, int d, const double* rin, double* rout,
-                                    double* lds, int* s_co, long long& npass, double& maxd,
-                                    double& sumr) {
-  using L = Layout<DIM>;
-  constexpr int DR = L::DR, REC = L::REC, NG = L::NG, PD = L::PD, SD = L::SD;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int* dd = a.ddesc + 8 * (int64_t)d;
-  const int cs = dd[0], nct = dd[1], ps = dd[2], np = dd[3], ncol = dd[4];
-  // staging: particles [PD][np], slots [SD][nct], body pairs [nct]
-  double* sp = GLOB ? a.gscr + (int64_t)PD * ps : lds;
-  double* ss = GLOB ? a.gscr + (int64_t)PD * 2 * a.cap + (int64_t)SD * cs : sp + PD * np;
-  int2* sab = GLOB ? (int2*)(a.gscr + (int64_t)PD * 2 * a.cap + (int64_t)SD * a.cap) + cs
-                   : (int2*)(ss + SD * nct);
-  double* sV = sp;
-  double* sW = sV + DIM * np;
-  double* sdm = sW + DR * np;
-  double* sdi = sdm + np;
-  double* sr = sdi + np;
+// Static data of one contact, read from memory into registers: body pair,
+// frame, g_e/dt, dt w_n, dt w_t, their reciprocals and the previous force.
+template <int DIM>
+struct SlotPre {
+  int2 ab;
+  double f[Layout<DIM>::NG];
+  double gdt, dwn, dwt, kn, kt;
+  double Ro[DIM];
+};
+
+template <int DIM>
+__device__ inline void fetch_slot(const SweepArgs& a, const double* rin, int64_t s, SlotPre<DIM>& o) {
+  constexpr int NG = Layout<DIM>::NG, REC = Layout<DIM>::REC;
   const int64_t cap = a.cap;
   const double* g = a.geo;
-  // 0. colour offsets, and this thread's first native contact (issued
-  //    before the particle gathers so that the latencies overlap)
-  for (int q = tid; q <= ncol; q += nthr) s_co[q] = a.dcol[(int64_t)d * (CD_MAX_COLORS + 1) + q];
-  double sv[SD];
-  int2 abv = make_int2(0, 0);
-  if (tid < nct) {
-    const int s = cs + tid;
-    for (int q = 0; q < NG; ++q) sv[q] = g[q * cap + s];
-    for (int q = 0; q < 5; ++q) sv[NG + q] = g[(G_GDT + q) * cap + s];
-    const double* ri = rin + (int64_t)s * REC;
-    for (int q = 0; q < DIM; ++q) sv[NG + 5 + q] = ri[q];
-    abv = a.ab[s];
+  o.ab = a.ab[s];
+  for (int q = 0; q < NG; ++q) o.f[q] = g[q * cap + s];
+  o.gdt = g[G_GDT * cap + s];
+  o.dwn = g[G_DWN * cap + s];
+  o.dwt = g[G_DWT * cap + s];
+  o.kn = g[G_KN * cap + s];
+  o.kt = g[G_KT * cap + s];
+  const double* ri = rin + s * REC;
+  if (DIM == 2) {
+    const double2 r2 = *(const double2*)ri;
+    o.Ro[0] = r2.x;
+    o.Ro[1] = r2.y;
+  } else {
+    for (int q = 0; q < DIM; ++q) o.Ro[q] = ri[q];
+  }
+}
+
+// A body's staged record: velocities, dt/m, dt/I, r.
+template <int DIM>
+struct Body {
+  double V[3], W[3], dm, di, r;
+};
+
+template <int DIM>
+__device__ inline void read_body(const double* sp, int l, Body<DIM>& b) {
+  const double2* p = (const double2*)(sp + (int64_t)Layout<DIM>::PS * l);
+  if (DIM == 2) {
+    const double2 x0 = p[0], x1 = p[1], x2 = p[2];
+    b.V[0] = x0.x;
+    b.V[1] = x0.y;
+    b.W[0] = x1.x;
+    b.dm = x1.y;
+    b.di = x2.x;
+    b.r = x2.y;
+    b.V[2] = b.W[1] = b.W[2] = 0.0;
+  } else {
+    const double2 x0 = p[0], x1 = p[1], x2 = p[2], x3 = p[3], x4 = p[4];
+    b.V[0] = x0.x;
+    b.V[1] = x0.y;
+    b.V[2] = x1.x;
+    b.W[0] = x1.y;
+    b.W[1] = x2.x;
+    b.W[2] = x2.y;
+    b.dm = x3.x;
+    b.di = x3.y;
+    b.r = x4.x;
+  }
+}
+
+template <int DIM>
+__device__ inline void write_velocities(double* sp, int l, const double* V, const double* W) {
+  double2* p = (double2*)(sp + (int64_t)Layout<DIM>::PS * l);
+  if (DIM == 2) {
+    p[0] = make_double2(V[0], V[1]);
+    sp[(int64_t)Layout<DIM>::PS * l + 2] = W[0];
+  } else {
+    p[0] = make_double2(V[0], V[1]);
+    p[1] = make_double2(V[2], W[0]);
+    p[2] = make_double2(W[1], W[2]);
+  }
+}
+
+// Convergence test values of one contact (Sec. 2.1): |R_new - R_old|^2
+// against alpha |R_new + R_old|^2, and |R_new| for R_avg.
+template <int DIM>
+__device__ inline void account(const double* Rold, const double* Rn, double alpha,
+                               long long& npass, double& maxd, double& sumr) {
+  double d2 = 0.0, s2 = 0.0, qq = 0.0;
+  for (int q = 0; q < DIM; ++q) {
+    double a1 = Rn[q], a0 = Rold[q];
+    d2 = d2 + (a1 - a0) * (a1 - a0);
+    s2 = s2 + (a1 + a0) * (a1 + a0);
+    qq = qq + a1 * a1;
+  }
+  sumr += sqrt(qq);
+  if (d2 < alpha * s2 || d2 == 0.0) npass += 1;
+  else if (d2 > maxd || d2 != d2) maxd = d2;
+}
+
+// The force law for one contact with the current velocities of its bodies
+// (staged particle records at sp; body 2 < 0 is wall -1-b with velocity
+// wu), the change applied to both bodies, the new record written to `ro`,
+// and the contact's test values accounted.
+template <int DIM>
+__device__ inline void update_contact(double* sp, const double* wu, const SlotPre<DIM>& c,
+                                      double mu, double alpha, double* ro, long long& npass,
+                                      double& maxd, double& sumr) {
+  constexpr int DR = Layout<DIM>::DR;
+  const int la = c.ab.x, lb = c.ab.y;
+  Body<DIM> A, B;
+  read_body<DIM>(sp, la, A);
+  if (lb >= 0) {
+    read_body<DIM>(sp, lb, B);
+  } else {
+    for (int q = 0; q < 3; ++q) B.V[q] = B.W[q] = 0.0;
+    for (int q = 0; q < DIM; ++q) B.V[q] = wu[(-1 - lb) * DIM + q];
+    B.dm = B.di = B.r = 0.0;
+  }
+  double nv[3] = {0.0, 0.0, 0.0}, t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < DIM; ++q) nv[q] = c.f[q];
+  if (DIM == 2) {
+    t1[0] = -nv[1];
+    t1[1] = nv[0];
+  } else {
+    for (int q = 0; q < 3; ++q) {
+      t1[q] = c.f[3 + q];
+      t2[q] = c.f[6 + q];
+    }
+  }
+  double Rold[3] = {0.0, 0.0, 0.0}, dwR[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < DIM; ++q) Rold[q] = c.Ro[q];
+  dwR[0] = c.dwn * Rold[0];
+  for (int q = 1; q < DIM; ++q) dwR[q] = c.dwt * Rold[q];
+  double Rn[3] = {0.0, 0.0, 0.0};
+  local_force<DIM>(nv, t1, t2, c.gdt, dwR, c.kn, c.kt, mu, A.r, B.r, A.V, A.W, B.V, B.W, Rn);
+  const double dRn = Rn[0] - Rold[0], dR1 = Rn[1] - Rold[1];
+  const double dR2 = DIM == 3 ? Rn[2] - Rold[2] : 0.0;
+  double dF[3], dq[3];
+  for (int q = 0; q < DIM; ++q) {
+    dF[q] = dRn * nv[q] + dR1 * t1[q];
+    if (DIM == 3) dF[q] = dF[q] + dR2 * t2[q];
+  }
+  if (DIM == 2) {
+    dq[0] = dR1;
+  } else {
+    for (int q = 0; q < 3; ++q) dq[q] = dR1 * t2[q] - dR2 * t1[q];
+  }
+  double Va[3], Wa[3];
+  for (int q = 0; q < DIM; ++q) Va[q] = A.V[q] - A.dm * dF[q];
+  for (int q = 0; q < DR; ++q) Wa[q] = A.W[q] - A.di * (A.r * dq[q]);
+  write_velocities<DIM>(sp, la, Va, Wa);
+  if (lb >= 0) {
+    double Vb[3], Wb[3];
+    for (int q = 0; q < DIM; ++q) Vb[q] = B.V[q] + B.dm * dF[q];
+    for (int q = 0; q < DR; ++q) Wb[q] = B.W[q] - B.di * (B.r * dq[q]);
+    write_velocities<DIM>(sp, lb, Vb, Wb);
+  }
+  // new record: frame force, world force, torque per unit lever (streamed
+  // out: nothing in this launch reads it back)
+  if (DIM == 2) {
+    const nt4 v4 = {Rn[0], Rn[1], Rn[0] * nv[0] + Rn[1] * t1[0], Rn[0] * nv[1] + Rn[1] * t1[1]};
+    __builtin_nontemporal_store(v4, (nt4*)ro);
+  } else {
+    double F[3], Q[3];
+    for (int q = 0; q < 3; ++q) {
+      double fk = Rn[0] * nv[q] + Rn[1] * t1[q];
+      F[q] = fk + Rn[2] * t2[q];
+      Q[q] = Rn[1] * t2[q] - Rn[2] * t1[q];
+    }
+    const nt4 v0 = {Rn[0], Rn[1], Rn[2], 0.0}, v1 = {F[0], F[1], F[2], 0.0},
+              v2 = {Q[0], Q[1], Q[2], 0.0};
+    __builtin_nontemporal_store(v0, (nt4*)ro);
+    __builtin_nontemporal_store(v1, (nt4*)(ro + 4));
+    __builtin_nontemporal_store(v2, (nt4*)(ro + 8));
+  }
+  account<DIM>(Rold, Rn, alpha, npass, maxd, sumr);
+}
+
+// One sweep of domain d by the calling workgroup: exchange, then the
+// colour-major update; accumulates the convergence test values of its
+// contacts.  GLOB: the particle records live in global scratch (domains
+// too large for LDS).
+template <int DIM, bool GLOB>
+__device__ inline void sweep_domain(const SweepArgs& a, int d, const double* rin, double* rout,
+                                    double* lds, int* s_co, double* s_wu, long long& npass,
+                                    double& maxd, double& sumr) {
+  using L = Layout<DIM>;
+  constexpr int DR = L::DR, REC = L::REC, PS = L::PS;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int* dd = a.ddesc + 8 * (int64_t)d;
+  // descriptor: first slot, slots, first particle entry, entries, colours
+  const int cs = dd[0], ps = dd[2], np = dd[3], ncol = dd[4];
+  double* sp = GLOB ? a.gscr + (int64_t)PS * ps : lds;
+  const int* dcol = a.dcol + (int64_t)d * (CD_MAX_COLORS + 1);
+  // 0. colour offsets and wall velocities to LDS; this thread's contact of
+  //    the first colour read ahead (its latency overlaps the exchange)
+  for (int q = tid; q <= ncol; q += nthr) s_co[q] = dcol[q];
+  for (int q = tid; q < a.n_walls * DIM; q += nthr) s_wu[q] = a.walls_u[q];
+  SlotPre<DIM> cur;
+  int kc = -1;
+  if (ncol > 0 && tid < dcol[1]) {
+    kc = tid;
+    fetch_slot<DIM>(a, rin, cs + kc, cur);
   }
   // 1. exchange: velocities from the previous sweep's forces
   const int64_t E = a.dpe;
@@ -225,115 +409,40 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const double* rin
     const double dm = a.dpb[q * E + e], di = a.dpb[(q + 1) * E + e];
     const double rp = a.dpb[(q + 2) * E + e];
     gather_forces<DIM>(a, rin, e, rp, acc, tacc);
-    for (int k = 0; k < DIM; ++k) sV[k * np + l] = a.dpb[k * E + e] + dm * acc[k];
-    for (int k = 0; k < DR; ++k) sW[k * np + l] = a.dpb[(DIM + k) * E + e] + di * tacc[k];
-    sdm[l] = dm;
-    sdi[l] = di;
-    sr[l] = rp;
-  }
-  if (tid < nct) {
-    for (int q = 0; q < SD; ++q) ss[q * nct + tid] = sv[q];
-    sab[tid] = abv;
-  }
-  for (int k = tid + nthr; k < nct; k += nthr) {
-    const int s = cs + k;
-    for (int q = 0; q < NG; ++q) ss[q * nct + k] = g[q * cap + s];
-    for (int q = 0; q < 5; ++q) ss[(NG + q) * nct + k] = g[(G_GDT + q) * cap + s];
-    const double* ri = rin + (int64_t)s * REC;
-    for (int q = 0; q < DIM; ++q) ss[(NG + 5 + q) * nct + k] = ri[q];
-    sab[k] = a.ab[s];
+    double* pr = sp + (int64_t)PS * l;
+    for (int k = 0; k < DIM; ++k) pr[k] = a.dpb[k * E + e] + dm * acc[k];
+    for (int k = 0; k < DR; ++k) pr[L::P_W + k] = a.dpb[(DIM + k) * E + e] + di * tacc[k];
+    pr[L::P_DM] = dm;
+    pr[L::P_DI] = di;
+    pr[L::P_R] = rp;
   }
   __syncthreads();
-  // 2. colour-major sequential update, from the staged data
+  // 2. colour-major sequential update
   for (int col = 0; col < ncol; ++col) {
     const int k0 = s_co[col], k1 = s_co[col + 1];
-    for (int k = k0 + tid; k < k1; k += nthr) {
-      const int2 ab = sab[k];
-      double nv[3] = {0.0, 0.0, 0.0}, t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
-      for (int q = 0; q < DIM; ++q) nv[q] = ss[q * nct + k];
-      if (DIM == 2) {
-        t1[0] = -nv[1];
-        t1[1] = nv[0];
-      } else {
-        for (int q = 0; q < 3; ++q) {
-          t1[q] = ss[(3 + q) * nct + k];
-          t2[q] = ss[(6 + q) * nct + k];
-        }
-      }
-      const double gdt = ss[NG * nct + k], dwn = ss[(NG + 1) * nct + k];
-      const double dwt = ss[(NG + 2) * nct + k], kn = ss[(NG + 3) * nct + k];
-      const double kt = ss[(NG + 4) * nct + k];
-      double Rold[3] = {0.0, 0.0, 0.0};
-      for (int q = 0; q < DIM; ++q) Rold[q] = ss[(NG + 5 + q) * nct + k];
-      const int la = ab.x, lb = ab.y;
-      double Va[3] = {0, 0, 0}, Wa[3] = {0, 0, 0}, Vb[3] = {0, 0, 0}, Wb[3] = {0, 0, 0};
-      for (int q = 0; q < DIM; ++q) Va[q] = sV[q * np + la];
-      for (int q = 0; q < DR; ++q) Wa[q] = sW[q * np + la];
-      const double ra = sr[la];
-      double rb = 0.0;
-      if (lb >= 0) {
-        for (int q = 0; q < DIM; ++q) Vb[q] = sV[q * np + lb];
-        for (int q = 0; q < DR; ++q) Wb[q] = sW[q * np + lb];
-        rb = sr[lb];
-      } else {
-        const double* u = a.walls_u + (-1 - lb) * DIM;
-        for (int q = 0; q < DIM; ++q) Vb[q] = u[q];
-      }
-      double Rn[3] = {0.0, 0.0, 0.0};
-      local_force<DIM>(nv, t1, t2, gdt, dwn, dwt, kn, kt, a.mu, ra, rb, Va, Wa, Vb, Wb, Rold, Rn);
-      const double dRn = Rn[0] - Rold[0], dR1 = Rn[1] - Rold[1];
-      const double dR2 = DIM == 3 ? Rn[2] - Rold[2] : 0.0;
-      double dF[3], dq[3];
-      for (int q = 0; q < DIM; ++q) {
-        dF[q] = dRn * nv[q] + dR1 * t1[q];
-        if (DIM == 3) dF[q] = dF[q] + dR2 * t2[q];
-      }
-      if (DIM == 2) {
-        dq[0] = dR1;
-      } else {
-        for (int q = 0; q < 3; ++q) dq[q] = dR1 * t2[q] - dR2 * t1[q];
-      }
-      const double dma = sdm[la], dia = sdi[la];
-      for (int q = 0; q < DIM; ++q) sV[q * np + la] = Va[q] - dma * dF[q];
-      for (int q = 0; q < DR; ++q) sW[q * np + la] = Wa[q] - dia * (ra * dq[q]);
-      if (lb >= 0) {
-        const double dmb = sdm[lb], dib = sdi[lb];
-        for (int q = 0; q < DIM; ++q) sV[q * np + lb] = Vb[q] + dmb * dF[q];
-        for (int q = 0; q < DR; ++q) sW[q * np + lb] = Wb[q] - dib * (rb * dq[q]);
-      }
-      // new record: frame force, world force, torque per unit lever
-      double* ro = rout + (int64_t)(cs + k) * REC;
-      if (DIM == 2) {
-        double4 rec4;
-        rec4.x = Rn[0];
-        rec4.y = Rn[1];
-        rec4.z = Rn[0] * nv[0] + Rn[1] * t1[0];
-        rec4.w = Rn[0] * nv[1] + Rn[1] * t1[1];
-        *(double4*)ro = rec4;
-      } else {
-        double F[3], Q[3];
-        for (int q = 0; q < 3; ++q) {
-          double fk = Rn[0] * nv[q] + Rn[1] * t1[q];
-          F[q] = fk + Rn[2] * t2[q];
-          Q[q] = Rn[1] * t2[q] - Rn[2] * t1[q];
-        }
-        *(double4*)ro = make_double4(Rn[0], Rn[1], Rn[2], 0.0);
-        *(double4*)(ro + 4) = make_double4(F[0], F[1], F[2], 0.0);
-        *(double4*)(ro + 8) = make_double4(Q[0], Q[1], Q[2], 0.0);
-      }
-      // convergence test values (Sec. 2.1)
-      double d2 = 0.0, s2 = 0.0, qq = 0.0;
-      for (int q = 0; q < DIM; ++q) {
-        double a1 = Rn[q], a0 = Rold[q];
-        d2 = d2 + (a1 - a0) * (a1 - a0);
-        s2 = s2 + (a1 + a0) * (a1 + a0);
-        qq = qq + a1 * a1;
-      }
-      sumr += sqrt(qq);
-      if (d2 < a.alpha * s2 || d2 == 0.0) npass += 1;
-      else if (d2 > maxd || d2 != d2) maxd = d2;
+    // the next colour's contact of this thread, read ahead
+    SlotPre<DIM> nxt;
+    int kn = -1;
+    if (col + 1 < ncol && s_co[col + 1] + tid < s_co[col + 2]) {
+      kn = s_co[col + 1] + tid;
+      fetch_slot<DIM>(a, rin, cs + kn, nxt);
     }
-    __syncthreads();
+    if (kc >= 0)
+      update_contact<DIM>(sp, s_wu, cur, a.mu, a.alpha, rout + (int64_t)(cs + kc) * REC, npass,
+                          maxd, sumr);
+    // colours wider than the workgroup
+    for (int k = k0 + tid + nthr; k < k1; k += nthr) {
+      SlotPre<DIM> sd;
+      fetch_slot<DIM>(a, rin, cs + k, sd);
+      update_contact<DIM>(sp, s_wu, sd, a.mu, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
+                          maxd, sumr);
+    }
+    // the colour's velocity updates must be seen by the next colour; the
+    // record stores and the read-ahead loads stay in flight
+    if (GLOB) __syncthreads();
+    else lds_barrier();
+    if (kn >= 0) cur = nxt;
+    kc = kn;
   }
 }
 
@@ -432,62 +541,57 @@ __device__ inline BlockPartial reduce_partials(const BlockPartial* part, int cou
   return block_partial(tn, tm, ts, sh);
 }
 
-// One sweep per launch: block b sweeps domain_of(b, 0).
+// Stop decision of sweep jd by the calling workgroup: fixed-order reduction
+// of that sweep's workgroup partials, test (I) or (II), and the progress
+// record for the host.  No-op once the solve is done.
+__device__ inline void decide_block(const SweepArgs& a, int jd, BlockRed& red, int& s_flag) {
+  SolveState* st = a.state;
+  if (threadIdx.x == 0) s_flag = *(volatile const int*)&st->done;
+  __syncthreads();
+  if (s_flag) return;
+  BlockPartial t = reduce_partials(a.partial + (int64_t)(jd & 1) * a.grid, a.grid, red);
+  if (threadIdx.x == 0) {
+    decide_sweep(a, st, jd, t.n_pass, t.max_d_fail, t.sum_r);
+    __hip_atomic_store(&a.prog->done, st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&a.prog->decided, jd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// Sweep j, one workgroup per domain (block b sweeps domain_of(b, 0)); the
+// extra last workgroup takes the stop decision of sweep j-1 meanwhile.  A
+// stop at j-1 leaves the forces of sweep j-1 final (sweep j writes the other
+// record array); a workgroup that already sees the stop skips its domain.
 template <int DIM, bool GLOB>
-__global__ __launch_bounds__(kMaxBlock) void k_sweep(SweepArgs a) {
+__global__ __launch_bounds__(kMaxBlock) void k_sweep(SweepArgs a, int j) {
   extern __shared__ double lds[];
   __shared__ BlockRed red;
   __shared__ int s_co[CD_MAX_COLORS + 1];
-  const SolveState* st = a.state;
-  if (*(volatile const int*)&st->done) return;
-  const int j = *(volatile const int*)&st->iter + 1;
+  __shared__ double s_wu[CD_MAX_WALLS * 3];
+  __shared__ int s_flag;
+  const int b = blockIdx.x;
+  if (b == a.grid) {
+    if (j >= 2) decide_block(a, j - 1, red, s_flag);
+    return;
+  }
+  // the decision workgroup may set `done` during this launch: read it once
+  if (threadIdx.x == 0) s_flag = *(volatile const int*)&a.state->done;
+  __syncthreads();
+  if (s_flag) return;
   const double* rin = a.rec[(j - 1) & 1];
   double* rout = a.rec[j & 1];
-  const int b = blockIdx.x;
   long long npass = 0;
   double maxd = 0.0, sumr = 0.0;
-  const int d = domain_of(a, b, 0, gridDim.x / 8);
-  if (d >= 0) sweep_domain<DIM, GLOB>(a, d, rin, rout, lds, s_co, npass, maxd, sumr);
+  const int d = domain_of(a, b, 0, a.grid / 8);
+  if (d >= 0) sweep_domain<DIM, GLOB>(a, d, rin, rout, lds, s_co, s_wu, npass, maxd, sumr);
   BlockPartial p = block_partial(npass, maxd, sumr, red);
-  if (threadIdx.x == 0) a.partial[b] = p;
+  if (threadIdx.x == 0) a.partial[(int64_t)(j & 1) * a.grid + b] = p;
 }
 
-// stop decision of the sweep just done: one workgroup
-__global__ __launch_bounds__(1024) void k_decide(SweepArgs a) {
-  __shared__ struct {
-    long long np[16];
-    double md[16], sr[16];
-  } red16;
-  SolveState* st = a.state;
-  if (st->done) return;
-  long long tn = 0;
-  double tm = 0.0, ts = 0.0;
-  for (int q = threadIdx.x; q < a.grid; q += blockDim.x) {
-    const BlockPartial p = a.partial[q];
-    tn += p.n_pass;
-    if (p.max_d_fail > tm || p.max_d_fail != p.max_d_fail) tm = p.max_d_fail;
-    ts += p.sum_r;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    tn += __shfl_xor(tn, off, 64);
-    double o = __shfl_xor(tm, off, 64);
-    if (o > tm || o != o) tm = o;
-    ts += __shfl_xor(ts, off, 64);
-  }
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    red16.np[wave] = tn;
-    red16.md[wave] = tm;
-    red16.sr[wave] = ts;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
-    tn += red16.np[k];
-    if (red16.md[k] > tm || red16.md[k] != red16.md[k]) tm = red16.md[k];
-    ts += red16.sr[k];
-  }
-  decide_sweep(a, st, st->iter + 1, tn, tm, ts);
+// stop decision of sweep jd alone (after the last launched sweep)
+__global__ __launch_bounds__(kMaxBlock) void k_decide(SweepArgs a, int jd) {
+  __shared__ BlockRed red;
+  __shared__ int s_flag;
+  decide_block(a, jd, red, s_flag);
 }
 
 __device__ inline int ld_relaxed(const int* p) {
@@ -529,6 +633,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(SweepArgs a, GridBar* bar, 
   extern __shared__ double lds[];
   __shared__ BlockRed red;
   __shared__ int s_co[CD_MAX_COLORS + 1];
+  __shared__ double s_wu[CD_MAX_WALLS * 3];
   __shared__ int s_last, s_stop;
   SolveState* st = a.state;
   if (*(volatile const int*)&st->done) return;   // nothing to solve: every block returns
@@ -550,7 +655,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(SweepArgs a, GridBar* bar, 
     for (int k = 0;; ++k) {
       const int d = domain_of(a, b, k, G8);
       if (d < 0) break;
-      sweep_domain<DIM, GLOB>(a, d, rin, rout, lds, s_co, npass, maxd, sumr);
+      sweep_domain<DIM, GLOB>(a, d, rin, rout, lds, s_co, s_wu, npass, maxd, sumr);
     }
     BlockPartial p = block_partial(npass, maxd, sumr, red);
     if (threadIdx.x == 0) {
@@ -599,25 +704,44 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(SweepArgs a, GridBar* bar, 
   if (owe) decide(owe);
 }
 
-// R_avg of the starting forces and the solve state (one block, fixed order)
+// R_avg of the starting forces: kInitBlocks workgroups sum |R| over
+// contiguous chunks of the slots, then one workgroup adds the chunk sums in
+// order (a fixed reduction order) and resets the solve state.
+constexpr int kInitBlocks = 256;
+
+__device__ inline double block_sum_256(double s, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+  return t;
+}
+
 template <int DIM>
-__global__ __launch_bounds__(1024) void k_solve_init(const double* rec0, int64_t nc,
-                                                    SolveState* st, int limit, GridBar* bar) {
+__global__ __launch_bounds__(256) void k_rsum(const double* rec0, int64_t nc, double* part) {
   constexpr int REC = DIM == 2 ? 4 : 12;
-  __shared__ double sh[16];
+  __shared__ double sh[4];
+  const int64_t chunk = (nc + kInitBlocks - 1) / kInitBlocks;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < nc ? lo + chunk : nc;
   double s = 0.0;
-  for (int64_t q = threadIdx.x; q < nc; q += blockDim.x) {
+  for (int64_t q = lo + threadIdx.x; q < hi; q += blockDim.x) {
     const double* rc = rec0 + q * REC;
     double qq = 0.0;
     for (int k = 0; k < DIM; ++k) qq = qq + rc[k] * rc[k];
     s += sqrt(qq);
   }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-  __syncthreads();
+  const double t = block_sum_256(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_solve_init(const double* part, int64_t nc, SolveState* st,
+                                                   int limit, GridBar* bar) {
+  __shared__ double sh[4];
+  const double t = block_sum_256(threadIdx.x < kInitBlocks ? part[threadIdx.x] : 0.0, sh);
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
     for (int x = 0; x < 8; ++x) bar->xcount[x][0] = bar->xcount[x][1] = 0;
     bar->count[0] = bar->count[1] = 0;
     bar->gen = 0;
@@ -670,10 +794,12 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.ab = c->slot_ab;
   a.geo = c->geo;
   a.walls_u = c->d_wall + (size_t)c->W * c->dim + c->W;
+  a.n_walls = c->W;
   a.rec[0] = c->rec[0];
   a.rec[1] = c->rec[1];
   a.state = c->d_state;
   a.partial = c->partial;
+  a.prog = c->d_prog;
   a.P = c->P;
   a.n = (int)c->n;
   a.cap = (int)c->cap;
@@ -692,39 +818,46 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
 
 hipError_t cd_launch_solve_init(cd_ctx* c, int limit) {
   if (c->dim == 2)
-    hipLaunchKernelGGL(k_solve_init<2>, dim3(1), dim3(1024), 0, c->stream, c->rec[0], c->nc,
-                       c->d_state, limit, c->d_bar);
+    hipLaunchKernelGGL(k_rsum<2>, dim3(kInitBlocks), dim3(256), 0, c->stream, c->rec[0], c->nc,
+                       c->init_part);
   else
-    hipLaunchKernelGGL(k_solve_init<3>, dim3(1), dim3(1024), 0, c->stream, c->rec[0], c->nc,
-                       c->d_state, limit, c->d_bar);
+    hipLaunchKernelGGL(k_rsum<3>, dim3(kInitBlocks), dim3(256), 0, c->stream, c->rec[0], c->nc,
+                       c->init_part);
+  hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(256), 0, c->stream, c->init_part, c->nc,
+                     c->d_state, limit, c->d_bar);
   return hipGetLastError();
 }
 
 static size_t block_lds(cd_ctx* c) { return c->sweep_global ? 0 : c->sweep_lds; }
 
-hipError_t cd_launch_sweep(cd_ctx* c, hipEvent_t before, hipEvent_t after) {
+hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after) {
   SweepArgs a = cd_sweep_args(c);
   if (before) {
     hipError_t e = hipEventRecord(before, c->stream);
     if (e != hipSuccess) return e;
   }
-  dim3 grid(a.grid), block(c->sweep_block);
+  // the domain workgroups plus the decision workgroup
+  dim3 grid(a.grid + 1), block(c->sweep_block);
   if (c->dim == 2) {
     if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<2, true>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((k_sweep<2, true>), grid, block, 0, c->stream, a, j);
     else
-      hipLaunchKernelGGL((k_sweep<2, false>), grid, block, block_lds(c), c->stream, a);
+      hipLaunchKernelGGL((k_sweep<2, false>), grid, block, block_lds(c), c->stream, a, j);
   } else {
     if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<3, true>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((k_sweep<3, true>), grid, block, 0, c->stream, a, j);
     else
-      hipLaunchKernelGGL((k_sweep<3, false>), grid, block, block_lds(c), c->stream, a);
+      hipLaunchKernelGGL((k_sweep<3, false>), grid, block, block_lds(c), c->stream, a, j);
   }
-  if (after) {
-    hipError_t e = hipEventRecord(after, c->stream);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, c->stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !after) return e;
+  return hipEventRecord(after, c->stream);
+}
+
+hipError_t cd_launch_decide(cd_ctx* c, int jd) {
+  if (jd < 1) return hipSuccess;
+  SweepArgs a = cd_sweep_args(c);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(kMaxBlock), 0, c->stream, a, jd);
   return hipGetLastError();
 }
 
