@@ -49,6 +49,19 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(path):
+    """HBM bytes per sweep launch from the committed counter measurement, or
+    None when the sweep kernel's sources changed since it was taken."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "cd_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1104_3516_amd", "csrc", f), "rb").read())
+    return rec.get("bytes_per_launch") if rec.get("kernel_sources_sha256") == h.hexdigest() else None
+
+
 def make_ctx(pk, binding, timing=1, solve_mode=1, block=0):
     params = binding.make_params(2, pk.n_walls, mu=0.3, dt=1e-3, alpha=1e-6, criterion=0,
                                  max_iter=2000, n_domains=N_DOMAINS, repartition_every=10,
@@ -80,14 +93,17 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sweeps", type=int, default=200,
+    ap.add_argument("--cpu-sweeps", type=int, default=600,
                     help="sweep cap of the CPU-oracle sample (0 skips it)")
     ap.add_argument("--solve-mode", type=int, default=1,
                     help="1: one launch per sweep; 0: all sweeps of a step in one launch")
-    ap.add_argument("--time-every", type=int, default=1,
-                    help="bracket every k-th sweep launch with HIP events (0: none)")
+    ap.add_argument("--time-every", type=int, default=8,
+                    help="time sweep launches in event-bracketed groups of this size (0: none)")
     ap.add_argument("--block", type=int, default=0,
                     help="threads per domain workgroup (0: chosen from the domain sizes)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times), the reference "
+                         "for scaling hardware byte counters, and exit")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles",
                                                           "sweep_disks_262k_traffic.json"))
     args = ap.parse_args()
@@ -103,6 +119,16 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         return 1
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 5}))
+        return 0
     pk = inputs.config("disks_262k")
 
     # warm-up on a throwaway context (kernels loaded, allocations made)
@@ -148,13 +174,9 @@ def main() -> int:
     # per executed sweep (the one-launch solve computes one sweep past the stop)
     avg_sweep_s = (sweep_kernel_ms / 1e3) / max(executed, 1)
     bytes_per_sweep = bytes_sweeps / max(executed, 1)
-    achieved = bytes_per_sweep / avg_sweep_s / 1e9 if sweeps else 0.0
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            traffic = json.load(open(args.traffic_json)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    # no per-sweep events (--time-every 0): no kernel duration, no roofline
+    achieved = bytes_per_sweep / avg_sweep_s / 1e9 if sweeps and avg_sweep_s > 0 else None
+    traffic = measured_traffic(args.traffic_json)
     out = {
         "metric": METRIC,
         "value": updates / elapsed,
@@ -175,13 +197,14 @@ def main() -> int:
         "steps_at_sweep_cap": maxiter_steps,
         "solve_ms_per_step": solve_ms / args.steps,
         "solve_contact_updates_per_s": updates / (solve_ms / 1e3) if solve_ms > 0 else None,
-        "sweep_kernel_us": 1e6 * avg_sweep_s,
+        "sweep_kernel_us": 1e6 * avg_sweep_s if avg_sweep_s > 0 else None,
         "sweeps_executed": executed,
         "sweeps_timed": timed,
         "solve_mode": args.solve_mode,
         "block_threads": tm.block_threads,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
+                     "traffic": traffic,
                      "kernel": "k_solve<2>" if args.solve_mode == 0 else "k_sweep<2>",
                      "bytes_per_sweep": bytes_per_sweep},
     }

@@ -97,7 +97,7 @@ typedef struct cd_timing {
   int sweep_launches;    /* solve / sweep kernel launches in the last step */
   int sweeps_executed;   /* sweeps computed, including the one the stop decision overlaps */
   int block_threads;     /* threads of the workgroup that sweeps one domain */
-  int sweeps_timed;      /* sweep launches bracketed by events (per-sweep mode) */
+  int sweeps_timed;      /* sweep launches inside the timed groups (per-sweep mode) */
 } cd_timing;
 
 typedef struct cd_ctx cd_ctx;
@@ -154,9 +154,11 @@ int cd_get_contacts(cd_ctx* ctx, int64_t cap, int32_t* ci, int32_t* cj, double* 
  * id (-1 for inner nodes). */
 int cd_get_tree(cd_ctx* ctx, int32_t* axis, double* cut, int32_t* child, int32_t* leaf);
 
-/* every > 0: bracket sweep launches 2, 2+every, 2+2 every, ... with HIP
- * events; cd_timing.sweep_kernel_ms is their mean duration times the sweeps
- * executed.  0 records no per-sweep events.  Default 1 (every launch). */
+/* every > 0: split sweep launches 2, 3, ... into consecutive groups of
+ * `every` and bracket each group with one pair of HIP events;
+ * cd_timing.sweep_kernel_ms is the mean launch duration over the complete
+ * groups of working launches times the sweeps executed.  0 records no
+ * per-sweep events.  Default 1 (every launch on its own). */
 int cd_set_timing(cd_ctx* ctx, int every);
 
 /* mode 1 (default): one launch per sweep; an extra workgroup of each launch
@@ -167,8 +169,8 @@ int cd_set_timing(cd_ctx* ctx, int every);
 int cd_set_solve_mode(cd_ctx* ctx, int mode);
 
 /* Threads of the workgroup that sweeps one domain: 64, 128, 192 or 256;
- * 0 (default) picks the smallest multiple of 64 covering the largest
- * domain's contacts and particles. */
+ * 0 (default) picks 128, or 64 when no domain has more than 64 contacts
+ * and 64 particles. */
 int cd_set_launch(cd_ctx* ctx, int block_threads);
 
 /* Phase timings of the last step (host struct). */

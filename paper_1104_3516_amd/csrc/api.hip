@@ -569,9 +569,11 @@ int cd_step(cd_ctx* c, cd_result* out) {
   // one workgroup per domain, wide enough to stage its contacts and gather
   // its particles in one pass (the work is latency-bound)
   {
+    // two wavefronts cover the particle gathers of typical domains while
+    // keeping every domain's workgroup resident at once; one is enough for
+    // small domains
     const int widest = std::max(ds.max_contacts, ds.max_particles);
-    int t = 64 * ((widest + 63) / 64);
-    c->sweep_block = std::min(256, std::max(64, t));
+    c->sweep_block = widest > 64 ? 128 : 64;
     if (c->block_override > 0) c->sweep_block = c->block_override;
   }
   if (c->sweep_global) {
@@ -590,6 +592,7 @@ int cd_step(cd_ctx* c, cd_result* out) {
   int executed = -1;
   bool aborted = false;
   bool one_launch = false;
+  int groups_closed = 0;
   const int G = c->persistent ? cd_solve_grid(c) : 0;
   if (G >= 8 && nc > 0 && limit > 0) {
     // all sweeps in one launch
@@ -616,13 +619,16 @@ int cd_step(cd_ctx* c, cd_result* out) {
     // kLookahead sweeps past the last published decision; launches after
     // the stop return at once.  Progress comes from the mapped record.
     const int kLookahead = 8;
+    // timing: launches 2, 3, ... in consecutive groups of `every`, each group
+    // bracketed by one pair of events (the first launch carries start-up costs)
     const int every = c->time_every;
-    const int timed_cap = every > 0 ? (limit + every - 1) / every : 0;
-    if ((int)c->sweep_ev.size() < 2 * timed_cap) {
+    const int groups_cap = every > 0 ? (limit + every - 1) / every : 0;
+    if ((int)c->sweep_ev.size() < 2 * groups_cap) {
       size_t old = c->sweep_ev.size();
-      c->sweep_ev.resize(2 * (size_t)timed_cap, nullptr);
+      c->sweep_ev.resize(2 * (size_t)groups_cap, nullptr);
       for (size_t k = old; k < c->sweep_ev.size(); ++k) CD_TRY(hipEventCreate(&c->sweep_ev[k]));
     }
+    groups_closed = 0;
     volatile HostProg* hp = c->h_prog;
     hp->decided = 0;
     hp->done = 0;
@@ -639,11 +645,12 @@ int cd_step(cd_ctx* c, cd_result* out) {
         continue;
       }
       const int j = launched + 1;
-      // sweeps 2, 2 + every, ... are timed (the first carries start-up costs)
-      const bool timed = every > 0 && j >= 2 && (j - 2) % every == 0;
-      const int slot = timed ? (j - 2) / every : -1;
-      CD_TRY(cd_launch_sweep(c, j, timed ? c->sweep_ev[2 * slot] : nullptr,
-                             timed ? c->sweep_ev[2 * slot + 1] : nullptr));
+      const int m = every > 0 && j >= 2 ? (j - 2) / every : -1;
+      const bool opens = m >= 0 && (j - 2) % every == 0;
+      const bool closes = m >= 0 && (j - 2) % every == every - 1;
+      CD_TRY(cd_launch_sweep(c, j, opens ? c->sweep_ev[2 * m] : nullptr,
+                             closes ? c->sweep_ev[2 * m + 1] : nullptr));
+      if (closes) groups_closed = m + 1;
       launched = j;
     }
     // the decision of the last launched sweep, if the solve is still open
@@ -711,13 +718,14 @@ int cd_step(cd_ctx* c, cd_result* out) {
   if (one_launch) {
     sk = elapsed(c->sweep_ev[0], c->sweep_ev[1]);
   } else if (c->time_every > 0 && executed >= 2) {
-    // mean over the timed launches that did work, times the working sweeps
+    // mean launch duration over the closed groups of launches that all did
+    // work, times the working sweeps
+    const int every = c->time_every;
     double sum = 0.0;
     int cnt = 0;
-    for (int j = 2; j <= executed; j += c->time_every) {
-      const int slot = (j - 2) / c->time_every;
-      sum += elapsed(c->sweep_ev[2 * slot], c->sweep_ev[2 * slot + 1]);
-      ++cnt;
+    for (int m = 0; m < groups_closed && 2 + (m + 1) * every - 1 <= executed; ++m) {
+      sum += elapsed(c->sweep_ev[2 * m], c->sweep_ev[2 * m + 1]);
+      cnt += every;
     }
     sk = cnt > 0 ? sum / cnt * executed : 0.0;
     tm.sweeps_timed = cnt;

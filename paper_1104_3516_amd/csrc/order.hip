@@ -26,7 +26,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kBuild = 64;
-constexpr int kSmall = 2048;   // LDS staging limit (contacts and particles of a domain)
+constexpr int kSmall = 512;    // colouring in LDS up to this many contacts and particles
 
 __global__ __launch_bounds__(kThreads) void k_dom_count(const int* dom, int64_t nc, int* count) {
   int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -135,67 +135,76 @@ struct BuildArgs {
   DomainStats* stats;
 };
 
+// Greedy first-fit colouring of a domain's contacts in canonical order
+// (serial by definition; thread 0): col[k], and rank[k] = number of earlier
+// contacts of the same colour, so that the stable order by colour is
+// pos[k] = offset[col[k]] + rank[k].  Returns the colour count, or -1 when a
+// contact finds all CD_MAX_COLORS colours taken.  MASK/LA/LB/COL/RANK are
+// LDS arrays in the small path and global scratch in the large one.
+template <typename M, typename I, typename C>
+__device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb_s, C* col_s,
+                                    C* rank_s, int* cnt) {
+  int ncol = 0;
+  for (int k = 0; k < nct; ++k) {
+    const int la = la_s[k], lb = lb_s[k];
+    const unsigned long long used = mask[la] | (lb >= 0 ? mask[lb] : 0ull);
+    if (used == ~0ull) return -1;
+    const int col = __ffsll((long long)~used) - 1;
+    col_s[k] = (C)col;
+    rank_s[k] = (C)cnt[col];
+    cnt[col] += 1;
+    mask[la] |= 1ull << col;
+    if (lb >= 0) mask[lb] |= 1ull << col;
+    if (col + 1 > ncol) ncol = col + 1;
+  }
+  return ncol;
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   constexpr int REC = DIM == 2 ? 4 : 12;
   __shared__ unsigned long long s_mask[kSmall];
   __shared__ int s_la[kSmall], s_lb[kSmall];
-  __shared__ short s_col[kSmall];
-  __shared__ int s_pos[kSmall];
+  __shared__ short s_col[kSmall], s_rank[kSmall];
+  __shared__ int s_cnt[CD_MAX_COLORS];
   __shared__ int s_coloff[CD_MAX_COLORS + 1];
-  __shared__ int s_run[CD_MAX_COLORS];
-  __shared__ int s_ncol, s_bad;
+  __shared__ int s_ncol;
 
   const int d = blockIdx.x;
   const int cs = a.dom_start[d], nct = a.dom_start[d + 1] - cs;
   const int ps = a.dp_start[d], np = a.dp_start[d + 1] - ps;
   const bool small = nct <= kSmall && np <= kSmall;
-  // generic pointers: LDS when the domain fits, global scratch otherwise
-  unsigned long long* mask = small ? s_mask : a.gmask + ps;
-  int* la_s = small ? s_la : (int*)a.qla + cs;
-  int* lb_s = small ? s_lb : (int*)a.qlb + cs;
-  int* pos = small ? s_pos : a.qpos + cs;
-  for (int k = threadIdx.x; k < np; k += blockDim.x) mask[k] = 0ull;
+  for (int q = threadIdx.x; q < CD_MAX_COLORS; q += blockDim.x) s_cnt[q] = 0;
   if (small) {
+    for (int k = threadIdx.x; k < np; k += blockDim.x) s_mask[k] = 0ull;
     for (int k = threadIdx.x; k < nct; k += blockDim.x) {
       s_la[k] = a.qla[cs + k];
       s_lb[k] = a.qlb[cs + k];
     }
+  } else {
+    for (int k = threadIdx.x; k < np; k += blockDim.x) a.gmask[ps + k] = 0ull;
   }
   __syncthreads();
-  // greedy first-fit colouring in canonical order (serial by definition)
   if (threadIdx.x == 0) {
-    int ncol = 0, bad = 0;
-    for (int k = 0; k < nct; ++k) {
-      int la = la_s[k], lb = lb_s[k];
-      unsigned long long used = mask[la] | (lb >= 0 ? mask[lb] : 0ull);
-      if (used == ~0ull) {
-        bad = 1;
-        break;
-      }
-      int col = __ffsll((long long)~used) - 1;
-      if (small) s_col[k] = (short)col;
-      else a.qcol[cs + k] = col;
-      mask[la] |= 1ull << col;
-      if (lb >= 0) mask[lb] |= 1ull << col;
-      if (col + 1 > ncol) ncol = col + 1;
-    }
-    for (int q = 0; q <= CD_MAX_COLORS; ++q) s_coloff[q] = 0;
-    if (!bad) {
-      // stable counting sort by colour
-      for (int k = 0; k < nct; ++k) s_coloff[(small ? s_col[k] : a.qcol[cs + k]) + 1] += 1;
-      for (int q = 0; q < ncol; ++q) s_coloff[q + 1] += s_coloff[q];
-      for (int q = 0; q < ncol; ++q) s_run[q] = s_coloff[q];
-      for (int k = 0; k < nct; ++k) pos[k] = s_run[small ? s_col[k] : a.qcol[cs + k]]++;
-    }
+    const int ncol = small ? colour_serial(nct, s_mask, s_la, s_lb, s_col, s_rank, s_cnt)
+                           : colour_serial(nct, a.gmask + ps, a.qla + cs, a.qlb + cs,
+                                           a.qcol + cs, a.qpos + cs, s_cnt);
+    s_coloff[0] = 0;
+    for (int q = 0; q < ncol; ++q) s_coloff[q + 1] = s_coloff[q] + s_cnt[q];
     s_ncol = ncol;
-    s_bad = bad;
   }
   __syncthreads();
-  if (s_bad) {
+  if (s_ncol < 0) {
     if (threadIdx.x == 0) atomicMax(&a.stats->overflow, 2);
     return;
   }
+  // stable order by colour
+  int* pos = a.qpos + cs;
+  if (small)
+    for (int k = threadIdx.x; k < nct; k += blockDim.x) pos[k] = s_coloff[s_col[k]] + s_rank[k];
+  else
+    for (int k = threadIdx.x; k < nct; k += blockDim.x) pos[k] = s_coloff[a.qcol[cs + k]] + pos[k];
+  __syncthreads();
   const int ncol = s_ncol;
   if (threadIdx.x == 0) {
     int* dd = a.ddesc + 8 * (int64_t)d;
@@ -225,7 +234,7 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     a.slot_contact[s] = c;
     a.contact_slot[c] = (int)s;
     a.color[c] = small ? s_col[k] : a.qcol[cs + k];
-    a.ab[s] = make_int2(la_s[k], lb_s[k]);
+    a.ab[s] = make_int2(a.qla[cs + k], a.qlb[cs + k]);
     double n3[3] = {0.0, 0.0, 0.0};
     for (int q = 0; q < DIM; ++q) n3[q] = a.nrm[q * nc + c];
     double t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
