@@ -1,6 +1,11 @@
 """Benchmark of the contact-force solve on one MI355X.
 
-Workload (the headline configuration): 2D disks, N = 262,144 on a 512x512
+`--workload disks_262k` (default) is the headline configuration below;
+`--workload spheres_1m` runs the 3D one (1,048,576 spheres on a 128x128x64
+jittered simple-cubic lattice, mu = 0.5, top wall driven down at 1e-3,
+16,384 domains, 50 steps).
+
+Headline workload: 2D disks, N = 262,144 on a 512x512
 jittered triangular lattice (spacing 2.05, radii U[0.8, 1.2], jitter +-0.05),
 rigid box walls, gravity 1, mass ~ r^2, mu = 0.3, dt = 1e-3, initial
 velocities N(0, 0.01^2), hierarchical bisection balanced by contact count
@@ -32,17 +37,29 @@ sys.path.insert(0, ROOT)
 
 METRIC = "contact updates/sec and ms per converged time step at tol 1e-6 (FP64), % HBM peak"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes a streaming sweep must move (2D): per contact the pair
+# algorithmic bytes a streaming sweep must move: per contact the pair
 # indices, normal, gap, force read and force write; per particle the base
-# velocities and the mass, inertia and radius terms
-BYTES_PER_CONTACT_2D = 64
-BYTES_PER_PARTICLE_2D = 48
+# velocities and the mass, inertia and radius terms (2D: 64 and 48 B; 3D:
+# 88 and 72 B)
+BYTES = {2: (64, 48), 3: (88, 72)}
 
-N_DOMAINS = 2048
-WORKLOAD = ("disks_262k: 2D disks N=262144 (512x512 jittered triangular lattice), mu=0.3, "
-            "dt=1e-3, gravity 1, 2048 contact-count-balanced bisection domains (4096 diverges), "
-            "repartition every 10 steps, alpha=1e-6 local test, max 2000 sweeps, gravity "
-            "settling")
+# name -> (generator config, dim, mu, domains, default steps, traffic record, description)
+WORKLOADS = {
+    "disks_262k": dict(
+        config="disks_262k", dim=2, mu=0.3, domains=2048, steps=100, cpu_sweeps=600,
+        traffic="sweep_disks_262k_traffic.json",
+        text=("disks_262k: 2D disks N=262144 (512x512 jittered triangular lattice), mu=0.3, "
+              "dt=1e-3, gravity 1, 2048 contact-count-balanced bisection domains (4096 "
+              "diverges), repartition every 10 steps, alpha=1e-6 local test, max 2000 sweeps, "
+              "gravity settling")),
+    "spheres_1m": dict(
+        config="spheres_1m", dim=3, mu=0.5, domains=16384, steps=50, cpu_sweeps=60,
+        traffic="sweep_spheres_1m_traffic.json",
+        text=("spheres_1m: 3D spheres N=1048576 (128x128x64 jittered simple-cubic lattice), "
+              "mu=0.5, dt=1e-3, no gravity, top wall driven down at 1e-3, 16384 "
+              "contact-count-balanced bisection domains, repartition every 10 steps, "
+              "alpha=1e-6 local test, max 2000 sweeps")),
+}
 
 
 def log(msg: str) -> None:
@@ -62,27 +79,27 @@ def measured_traffic(path):
     return rec.get("bytes_per_launch") if rec.get("kernel_sources_sha256") == h.hexdigest() else None
 
 
-def make_ctx(pk, binding, timing=1, solve_mode=1, block=0):
-    params = binding.make_params(2, pk.n_walls, mu=0.3, dt=1e-3, alpha=1e-6, criterion=0,
-                                 max_iter=2000, n_domains=N_DOMAINS, repartition_every=10,
-                                 warm_start=1)
+def make_ctx(wl, pk, binding, timing=1, solve_mode=1, block=0):
+    params = binding.make_params(wl["dim"], pk.n_walls, mu=wl["mu"], dt=1e-3, alpha=1e-6,
+                                 criterion=0, max_iter=2000, n_domains=wl["domains"],
+                                 repartition_every=10, warm_start=1)
     return binding.Context(params, pk, timing=timing, solve_mode=solve_mode, block_threads=block)
 
 
-def cpu_baseline(pk, sweeps: int) -> dict:
+def cpu_baseline(wl, pk, sweeps: int) -> dict:
     """The oracle as it is, single-threaded, on the first time step of the
     same workload with the sweep count capped."""
     from oracle import cdref
     cdref.build(force=False)
-    p = cdref.make_params(2, pk.n_walls, mu=0.3, dt=1e-3, alpha=1e-6, criterion=0,
-                          max_iter=sweeps, n_domains=N_DOMAINS, repartition_every=10)
+    p = cdref.make_params(wl["dim"], pk.n_walls, mu=wl["mu"], dt=1e-3, alpha=1e-6, criterion=0,
+                          max_iter=sweeps, n_domains=wl["domains"], repartition_every=10)
     sim = cdref.Sim(p, pk)
     t0 = time.perf_counter()
     info = sim.step()
     dt = time.perf_counter() - t0
     updates = info.iterations * info.n_contacts
     return {"value": updates / dt, "unit": "contact updates/s", "cores": 1, "kind": "oracle",
-            "sample": (f"first time step of the same workload (N=262144, {N_DOMAINS} domains), "
+            "sample": (f"first time step of the same workload (N={pk.n}, {wl['domains']} domains), "
                        f"sweeps capped at {sweeps} ({info.iterations} run, "
                        f"{info.n_contacts} contacts), whole step incl. detection and "
                        f"partition, {dt:.1f} s single-threaded")}
@@ -91,10 +108,13 @@ def cpu_baseline(pk, sweeps: int) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--workload", default="disks_262k", choices=sorted(WORKLOADS),
+                    help="disks_262k (the headline configuration) or spheres_1m (3D)")
+    ap.add_argument("--steps", type=int, default=0, help="time steps (0: the workload's own)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sweeps", type=int, default=600,
-                    help="sweep cap of the CPU-oracle sample (0 skips it)")
+    ap.add_argument("--cpu-sweeps", type=int, default=-1,
+                    help="sweep cap of the CPU-oracle sample (0 skips it; default: about "
+                         "20 s of oracle work for the workload)")
     ap.add_argument("--solve-mode", type=int, default=1,
                     help="1: one launch per sweep; 0: all sweeps of a step in one launch")
     ap.add_argument("--time-every", type=int, default=8,
@@ -104,9 +124,16 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), the reference "
                          "for scaling hardware byte counters, and exit")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles",
-                                                          "sweep_disks_262k_traffic.json"))
+    ap.add_argument("--traffic-json", default=None,
+                    help="counter record of the sweep kernel (default: the workload's)")
     args = ap.parse_args()
+    wl = WORKLOADS[args.workload]
+    if args.steps <= 0:
+        args.steps = wl["steps"]
+    if args.cpu_sweeps < 0:
+        args.cpu_sweeps = wl["cpu_sweeps"]
+    if args.traffic_json is None:
+        args.traffic_json = os.path.join(ROOT, "profiles", wl["traffic"])
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
               f"(the path shards by subtrees of the bisection tree, see the design notes)",
@@ -129,18 +156,19 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 5}))
         return 0
-    pk = inputs.config("disks_262k")
+    pk = inputs.config(wl["config"])
+    dim = wl["dim"]
 
     # warm-up on a throwaway context (kernels loaded, allocations made)
     if args.warmup > 0:
-        ctx = make_ctx(pk, binding, solve_mode=args.solve_mode, block=args.block)
+        ctx = make_ctx(wl, pk, binding, solve_mode=args.solve_mode, block=args.block)
         for s in range(args.warmup):
             r = ctx.step()
             log(f"warmup step {s}: {r.iterations} sweeps, {r.n_contacts} contacts")
         ctx.close()
         del ctx
 
-    ctx = make_ctx(pk, binding, timing=args.time_every, solve_mode=args.solve_mode,
+    ctx = make_ctx(wl, pk, binding, timing=args.time_every, solve_mode=args.solve_mode,
                    block=args.block)
     torch.cuda.synchronize()
     sweeps = 0
@@ -161,8 +189,8 @@ def main() -> int:
         solve_ms += tm.solve_ms
         executed += tm.sweeps_executed
         timed += tm.sweeps_timed
-        bytes_sweeps += tm.sweeps_executed * (BYTES_PER_CONTACT_2D * r.n_contacts +
-                                              BYTES_PER_PARTICLE_2D * pk.n)
+        bytes_sweeps += tm.sweeps_executed * (BYTES[dim][0] * r.n_contacts +
+                                              BYTES[dim][1] * pk.n)
         maxiter_steps += int(r.status == binding.MAXITER)
         if s % 10 == 0 or s == args.steps - 1:
             log(f"step {s}: {r.iterations} sweeps, {r.n_contacts} contacts, status {r.status}, "
@@ -190,7 +218,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n_particles": pk.n, "n_domains": N_DOMAINS,
+        "config": {"workload": wl["text"], "n_particles": pk.n, "n_domains": wl["domains"],
                    "time_steps": args.steps},
         "sweeps_total": sweeps,
         "sweeps_per_step": sweeps / args.steps,
@@ -205,12 +233,12 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
                      "traffic": traffic,
-                     "kernel": "k_solve<2>" if args.solve_mode == 0 else "k_sweep<2>",
+                     "kernel": f"k_solve<{dim}>" if args.solve_mode == 0 else f"k_sweep<{dim}>",
                      "bytes_per_sweep": bytes_per_sweep},
     }
     if args.cpu_sweeps > 0:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(pk, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(wl, pk, args.cpu_sweeps)
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0

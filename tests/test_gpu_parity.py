@@ -208,3 +208,37 @@ def test_full_size_tolerance_step_properties():
     x, v, w = (t.cpu().numpy() for t in ctx.state())
     assert close_rel(v, V) <= RTOL
     assert close_rel(w, W, max(np.abs(W).max(), 1e-12)) <= RTOL
+
+
+def test_full_size_spheres_1m_16384_domains_fixed_sweeps():
+    """128x128x64 spheres, 16384 domains, 3D cone mu = 0.5, the top wall
+    driven down: the 3D bench configuration for a fixed 10 sweeps, then a
+    second step."""
+    pk = inputs.config("spheres_1m")
+    sim, ctx = both(pk, mu=0.5, n_domains=16384, repartition_every=10, fixed_iters=10)
+    compare_step(sim, ctx, "1m spheres fixed10")
+    compare_step(sim, ctx, "1m spheres step 2")
+
+
+def test_full_size_spheres_tolerance_step_properties():
+    """The 3D tolerance-mode step at bench size: cone and unilateral normal
+    force on the GPU's converged forces, and the velocities equal to the
+    oracle's sum over those forces."""
+    from oracle import cdref
+    from paper_1104_3516_amd import binding
+    _torch()
+    pk = inputs.config("spheres_1m")
+    ctx = binding.Context(binding.make_params(3, pk.n_walls, mu=0.5, n_domains=16384,
+                                              repartition_every=10), pk)
+    res = ctx.step()
+    print(f"[1m tol] it={res.iterations} status={res.status} nc={res.n_contacts}", flush=True)
+    assert res.status in (0, 1)
+    c = {k: v.cpu().numpy() for k, v in ctx.contacts().items()}
+    R = c["R"]
+    assert np.all(R[0] >= 0)
+    rt = np.sqrt(R[1] ** 2 + R[2] ** 2)
+    assert np.all(rt <= 0.5 * R[0] * (1 + 1e-14))
+    V, W = cdref.velocities(pk, 1e-3, c["ci"], c["cj"], c["normal"], R)
+    x, v, w = (t.cpu().numpy() for t in ctx.state())
+    assert close_rel(v, V) <= RTOL
+    assert close_rel(w, W, max(np.abs(W).max(), 1e-12)) <= RTOL
