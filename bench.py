@@ -59,6 +59,13 @@ WORKLOADS = {
               "mu=0.5, dt=1e-3, no gravity, top wall driven down at 1e-3, 16384 "
               "contact-count-balanced bisection domains, repartition every 10 steps, "
               "alpha=1e-6 local test, max 2000 sweeps")),
+    "batch512": dict(
+        config="batch512", dim=2, mu=None, domains=None, steps=20, cpu_sweeps=600,
+        traffic="sweep_batch512_traffic.json",
+        text=("batch512: 512 independent 2D disk packings (generator of the 1k case), N "
+              "log-uniform in [256, 65536] (sum 5,580,310), mu uniform in [0.1, 0.6] per "
+              "packing, autotuned contacts per domain, repartition every 10 steps, alpha=1e-6 "
+              "local test, max 2000 sweeps, one sweep launch over all packings per sweep")),
 }
 
 
@@ -86,6 +93,107 @@ def make_ctx(wl, pk, binding, timing=1, solve_mode=1, block=0):
     return binding.Context(params, pk, timing=timing, solve_mode=solve_mode, block_threads=block)
 
 
+def batch_domains(pk, target):
+    """Domains of a packing for about `target` contacts per domain."""
+    from paper_1104_3516_amd.tune import domains_for
+    return domains_for(pk.n, target)
+
+
+def batch_params_p(binding, pk, mu, n_domains):
+    return binding.make_params(2, pk.n_walls, mu=float(mu), dt=1e-3, alpha=1e-6, criterion=0,
+                               max_iter=2000, n_domains=n_domains, repartition_every=10,
+                               warm_start=1)
+
+
+def batch_params(binding, pk, mu, target):
+    return batch_params_p(binding, pk, mu, batch_domains(pk, target))
+
+
+def run_batch(args, wl, torch, binding, inputs) -> dict:
+    """The batched workload: value over the timed steps of the batch, and the
+    same packings stepped one at a time (cd_step) on the same GPU for two
+    steps as the plain comparison."""
+    packs, mus = inputs.uneven_batch(512)
+    tuning = None
+    if args.target > 0:
+        target = args.target
+    else:
+        from paper_1104_3516_amd import tune
+        tuning = tune.tune_batch_target(
+            packs, mus, lambda pk, mu, p: batch_params_p(binding, pk, mu, p), binding, log=log)
+        target = tuning["target"]
+        log(f"tuned contacts per domain: {target} (cached: {tuning['cached']})")
+    if args.warmup > 0:
+        ctxs = [binding.Context(batch_params(binding, pk, mu, target), pk, timing=0)
+                for pk, mu in zip(packs, mus)]
+        bt = binding.Batch(ctxs)
+        for s in range(args.warmup):
+            bt.step()
+            log(f"warmup step {s}")
+        bt.close()
+        del bt, ctxs
+    ctxs = [binding.Context(batch_params(binding, pk, mu, target), pk, timing=0)
+            for pk, mu in zip(packs, mus)]
+    bt = binding.Batch(ctxs, timing=args.time_every)
+    torch.cuda.synchronize()
+    updates = sweeps_max = 0
+    kernel_ms = solve_ms = prepare_ms = finish_ms = 0.0
+    bytes_all = 0.0
+    executed = timed = 0
+    n_maxiter = 0
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        res = bt.step()
+        tm = bt.timing()
+        for pk, r in zip(packs, res):
+            updates += r.iterations * r.n_contacts
+            n_maxiter += int(r.status == binding.MAXITER)
+            bytes_all += r.iterations * (BYTES[2][0] * r.n_contacts + BYTES[2][1] * pk.n)
+        sweeps_max += max(r.iterations for r in res)
+        kernel_ms += tm.sweep_kernel_ms
+        solve_ms += tm.solve_ms
+        prepare_ms += tm.prepare_ms
+        finish_ms += tm.finish_ms
+        executed += tm.sweeps_executed
+        timed += tm.sweeps_timed
+        log(f"step {s}: sweep launches {tm.sweep_launches}, slowest packing "
+            f"{max(r.iterations for r in res)} sweeps, prepare {tm.prepare_ms:.1f} ms, solve "
+            f"{tm.solve_ms:.1f} ms, finish {tm.finish_ms:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    bt.close()
+    # the plain comparison: every packing on its own, two steps
+    plain_steps = 2
+    ctxs_p = [binding.Context(batch_params(binding, pk, mu, target), pk, timing=0)
+              for pk, mu in zip(packs, mus)]
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    plain_updates = 0
+    for s in range(plain_steps):
+        for c in ctxs_p:
+            r = c.step()
+            plain_updates += r.iterations * r.n_contacts
+    torch.cuda.synchronize()
+    plain_elapsed = time.perf_counter() - tp
+    achieved = bytes_all / (kernel_ms / 1e3) / 1e9 if kernel_ms > 0 else None
+    return {
+        "value": updates / elapsed, "elapsed": elapsed, "updates": updates,
+        "sweeps_per_step": sweeps_max / args.steps, "steps_at_sweep_cap": n_maxiter,
+        "solve_ms_per_step": solve_ms / args.steps, "prepare_ms_per_step": prepare_ms / args.steps,
+        "finish_ms_per_step": finish_ms / args.steps,
+        "sweep_kernel_us": 1e3 * kernel_ms / max(executed, 1),
+        "sweeps_executed": executed, "sweeps_timed": timed,
+        "contacts_per_domain_target": target,
+        "tuning": tuning,
+        "packings_failed": int(sum(1 for r in res if r.status < 0)),
+        "plain": {"steps": plain_steps, "ms_per_step": 1e3 * plain_elapsed / plain_steps,
+                  "contact_updates_per_s": plain_updates / plain_elapsed,
+                  "note": "the same 512 packings stepped one at a time with cd_step"},
+        "achieved": achieved, "bytes_per_sweep": bytes_all / max(executed, 1),
+        "n_particles": int(sum(pk.n for pk in packs)),
+    }
+
+
 def cpu_baseline(wl, pk, sweeps: int) -> dict:
     """The oracle as it is, single-threaded, on the first time step of the
     same workload with the sweep count capped."""
@@ -103,6 +211,29 @@ def cpu_baseline(wl, pk, sweeps: int) -> dict:
                        f"sweeps capped at {sweeps} ({info.iterations} run, "
                        f"{info.n_contacts} contacts), whole step incl. detection and "
                        f"partition, {dt:.1f} s single-threaded")}
+
+
+def cpu_baseline_batch(packs, mus, target, sweeps: int) -> dict:
+    """The oracle, single-threaded, on the first step of the first packings of
+    the batch (about 20 s of work), sweeps capped."""
+    from oracle import cdref
+    cdref.build(force=False)
+    updates, spent, used = 0, 0.0, 0
+    for pk, mu in zip(packs, mus):
+        p = cdref.make_params(2, pk.n_walls, mu=float(mu), dt=1e-3, alpha=1e-6, criterion=0,
+                              max_iter=sweeps, n_domains=batch_domains(pk, target),
+                              repartition_every=10)
+        sim = cdref.Sim(p, pk)
+        t0 = time.perf_counter()
+        info = sim.step()
+        spent += time.perf_counter() - t0
+        updates += info.iterations * info.n_contacts
+        used += 1
+        if spent > 20.0:
+            break
+    return {"value": updates / spent, "unit": "contact updates/s", "cores": 1, "kind": "oracle",
+            "sample": (f"first time step of the first {used} of the 512 packings, sweeps capped "
+                       f"at {sweeps}, {spent:.1f} s single-threaded")}
 
 
 def main() -> int:
@@ -124,6 +255,8 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), the reference "
                          "for scaling hardware byte counters, and exit")
+    ap.add_argument("--target", type=int, default=0,
+                    help="batch512: contacts per domain (0: the workload's default)")
     ap.add_argument("--traffic-json", default=None,
                     help="counter record of the sweep kernel (default: the workload's)")
     args = ap.parse_args()
@@ -155,6 +288,40 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 5}))
+        return 0
+    if args.workload == "batch512":
+        rb = run_batch(args, wl, torch, binding, inputs)
+        traffic = measured_traffic(args.traffic_json)
+        out = {
+            "metric": METRIC, "value": rb["value"], "unit": "contact updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1e3 * rb["elapsed"] / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": wl["text"], "n_particles": rb["n_particles"],
+                       "n_packings": 512, "time_steps": args.steps},
+            "sweeps_per_step": rb["sweeps_per_step"],
+            "steps_at_sweep_cap": rb["steps_at_sweep_cap"],
+            "solve_ms_per_step": rb["solve_ms_per_step"],
+            "prepare_ms_per_step": rb["prepare_ms_per_step"],
+            "finish_ms_per_step": rb["finish_ms_per_step"],
+            "sweep_kernel_us": rb["sweep_kernel_us"], "sweeps_executed": rb["sweeps_executed"],
+            "sweeps_timed": rb["sweeps_timed"],
+            "contacts_per_domain_target": rb["contacts_per_domain_target"],
+            "domain_size_tuning": rb["tuning"],
+            "packings_failed": rb["packings_failed"],
+            "plain_comparison": rb["plain"],
+            "roofline": {"bound": "hbm", "achieved": rb["achieved"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s",
+                         "frac": rb["achieved"] / HBM_PEAK_GBS if rb["achieved"] else None,
+                         "traffic": traffic, "kernel": "k_sweep_batch<2>",
+                         "bytes_per_sweep": rb["bytes_per_sweep"]},
+        }
+        if args.cpu_sweeps > 0:
+            log("cpu baseline (oracle) ...")
+            packs, mus = inputs.uneven_batch(512)
+            out["cpu_baseline"] = cpu_baseline_batch(packs, mus, rb["contacts_per_domain_target"],
+                                                     args.cpu_sweeps)
+        print(json.dumps(out), flush=True)
         return 0
     pk = inputs.config(wl["config"])
     dim = wl["dim"]

@@ -170,7 +170,12 @@ int cd_set_solve_mode(cd_ctx* ctx, int mode);
 
 /* Threads of the workgroup that sweeps one domain: 64, 128, 192 or 256;
  * 0 (default) picks 128, or 64 when no domain has more than 64 contacts
- * and 64 particles. */
+ * and 64 particles; -1 tunes it: the next four steps run with 64, 128, 192
+ * and 256 threads (results do not depend on the width), the width with the
+ * fastest mean sweep launch is kept, and the choice is cached for the
+ * process per (dimension, log2 N, log2 P, device) so that later contexts of
+ * the same kind start with it.  Tuning needs sweep timing (cd_set_timing
+ * with every > 0). */
 int cd_set_launch(cd_ctx* ctx, int block_threads);
 
 /* Phase timings of the last step (host struct). */
@@ -179,6 +184,56 @@ int cd_get_timing(cd_ctx* ctx, cd_timing* out);
 /* Static description of a status code, and the last error of a context. */
 const char* cd_status_string(int status);
 const char* cd_last_error(const cd_ctx* ctx);
+
+/* ---- Batches of independent packings ------------------------------------
+ * Many packings stepped together: each packing is a context created and
+ * filled as above (its own parameters, friction, domain count, walls); the
+ * batch runs, per time step, every packing's detection, partition and order,
+ * then ONE kernel launch per sweep over the domains of all packings whose
+ * solve is still open (per-packing stop decisions; stopped packings idle),
+ * then every packing's update.  A packing's results equal those of cd_step
+ * on that context alone: same list, partition, order and arithmetic.
+ * Motivation: the paper's one-process-per-domain scheme (Sec. 3) applied to
+ * many small systems at once keeps a GPU full where one small packing
+ * cannot. */
+typedef struct cd_batch cd_batch;
+
+typedef struct cd_batch_timing {
+  double prepare_ms;       /* detection, partition and order of all packings */
+  double solve_ms;         /* the batched sweeps and decisions */
+  double finish_ms;        /* canonical forces and updates of all packings */
+  double sweep_kernel_ms;  /* mean timed sweep launch x sweeps executed */
+  int sweep_launches;      /* batched sweep launches */
+  int sweeps_executed;     /* launches that did work for some packing */
+  int sweeps_timed;        /* launches inside the timed groups */
+  int block_threads;       /* threads per domain workgroup */
+  int workgroups;          /* workgroups of one batched launch */
+  int pad;
+} cd_batch_timing;
+
+/* ctxs: `count` contexts (host array of handles), all of one dimension, on
+ * one device and one stream; the batch keeps the handles (the caller keeps
+ * ownership and must not destroy a context while the batch lives) and uses
+ * their stream.  CD_EINVAL for mismatched contexts. */
+int cd_batch_create(cd_batch** out, cd_ctx* const* ctxs, int count);
+int cd_batch_destroy(cd_batch* batch);
+
+/* Per-sweep event timing of the batched launches, as cd_set_timing. */
+int cd_batch_set_timing(cd_batch* batch, int every);
+
+/* One time step of every packing.  results: host array of `count`
+ * cd_result, filled for every packing.  A packing whose solve diverges
+ * (non-finite force, or velocities beyond the displacement bound at the next
+ * step: the instability of the mixed parallel/sequential update, Sec. 2.3)
+ * leaves the batch: its result status is CD_ENONFINITE or CD_EINVAL from then
+ * on and the others go on.  Returns CD_OK, CD_MAXITER (some packing hit its
+ * sweep cap), CD_ENONFINITE (some packing has left the batch), or the error
+ * of the first packing whose preparation failed otherwise (named by
+ * cd_batch_last_error); CD_ECAPACITY when a packing's domain does not fit in
+ * LDS (use more domains for it). */
+int cd_batch_step(cd_batch* batch, cd_result* results);
+int cd_batch_get_timing(cd_batch* batch, cd_batch_timing* out);
+const char* cd_batch_last_error(const cd_batch* batch);
 
 #ifdef __cplusplus
 }

@@ -43,6 +43,13 @@ class Timing(C.Structure):
                 ("sweeps_timed", C.c_int)]
 
 
+class BatchTiming(C.Structure):
+    _fields_ = [("prepare_ms", C.c_double), ("solve_ms", C.c_double), ("finish_ms", C.c_double),
+                ("sweep_kernel_ms", C.c_double), ("sweep_launches", C.c_int),
+                ("sweeps_executed", C.c_int), ("sweeps_timed", C.c_int),
+                ("block_threads", C.c_int), ("workgroups", C.c_int), ("pad", C.c_int)]
+
+
 def make_params(dim: int, n_walls: int, *, dt=1e-3, alpha=1e-6, mu=0.3, criterion=0,
                 max_iter=2000, fixed_iters=0, overlap_mode=0, n_domains=1,
                 repartition_every=1, warm_start=1, skin=-1.0) -> Params:
@@ -91,6 +98,13 @@ def lib():
         L.cd_status_string.restype = C.c_char_p
         L.cd_last_error.argtypes = [P]
         L.cd_last_error.restype = C.c_char_p
+        L.cd_batch_create.argtypes = [C.POINTER(P), C.POINTER(P), C.c_int]
+        L.cd_batch_destroy.argtypes = [P]
+        L.cd_batch_set_timing.argtypes = [P, C.c_int]
+        L.cd_batch_step.argtypes = [P, C.POINTER(Result)]
+        L.cd_batch_get_timing.argtypes = [P, C.POINTER(BatchTiming)]
+        L.cd_batch_last_error.argtypes = [P]
+        L.cd_batch_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -230,3 +244,50 @@ class Context:
         t = Timing()
         self._check(self.L.cd_get_timing(self.h, C.byref(t)))
         return t
+
+
+class Batch:
+    """Independent packings stepped together (cd_batch_*): one sweep launch
+    per sweep over the domains of every packing still solving.  `contexts`
+    are Context objects on one device and stream; they stay owned by the
+    caller and must outlive the batch."""
+
+    def __init__(self, contexts, timing: int = 8):
+        self.L = lib()
+        self.contexts = list(contexts)
+        handles = (C.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        h = C.c_void_p()
+        code = self.L.cd_batch_create(C.byref(h), handles, len(self.contexts))
+        if code < 0:
+            raise CDError(code, "cd_batch_create: contexts differ in dimension, device or stream")
+        self.h = h
+        self._check(self.L.cd_batch_set_timing(self.h, int(timing)))
+
+    def _check(self, code: int):
+        if code < 0:
+            raise CDError(code, (self.L.cd_batch_last_error(self.h) or b"").decode())
+        return code
+
+    def step(self):
+        res = (Result * len(self.contexts))()
+        code = self.L.cd_batch_step(self.h, res)
+        if code < 0 and code != ENONFINITE:
+            self._check(code)
+        # packings that diverged carry ENONFINITE or EINVAL in their status
+        return list(res)
+
+    def timing(self) -> BatchTiming:
+        t = BatchTiming()
+        self._check(self.L.cd_batch_get_timing(self.h, C.byref(t)))
+        return t
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.cd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <chrono>
 #include <cstdio>
 
@@ -42,6 +43,66 @@ void release(T** p) {
   *p = nullptr;
 }
 
+int fail(cd_ctx* c, int code, const std::string& msg);
+
+// ---- workgroup-width tuning (cd_set_launch(ctx, -1)) ----------------------
+// The first steps of a context run with the candidate widths in turn; each
+// step's mean sweep launch time (HIP events) is recorded and the fastest
+// width is kept from then on.  Widths do not change the arithmetic.  The
+// choice is cached for the process by (dimension, log2 N, log2 P, device)
+// so that later contexts of the same kind start with it.
+constexpr int kTuneWidths[4] = {64, 128, 192, 256};
+
+struct TuneKey {
+  int dim, nbits, pbits, device;
+  bool operator==(const TuneKey& o) const {
+    return dim == o.dim && nbits == o.nbits && pbits == o.pbits && device == o.device;
+  }
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, int>> g_tune_cache;
+
+int ilog2(int64_t v) {
+  int b = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+TuneKey tune_key(const cd_ctx* c) { return TuneKey{c->dim, ilog2(c->n), ilog2(c->P), c->device}; }
+
+// the width for the coming solve: a cached choice, the next candidate, or the best seen
+int tune_block_pick(cd_ctx* c) {
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (auto& e : g_tune_cache)
+      if (e.first == tune_key(c)) {
+        c->tune_next = 4;
+        c->tune_best = e.second;
+        return e.second;
+      }
+  }
+  if (c->tune_next < 4) return kTuneWidths[c->tune_next];
+  return c->tune_best > 0 ? c->tune_best : 128;
+}
+
+// record the width just used with its mean sweep time
+void tune_block_record(cd_ctx* c, double us_per_sweep) {
+  if (c->block_override >= 0 || c->tune_next >= 4 || us_per_sweep <= 0.0) return;
+  if (c->tune_best == 0 || us_per_sweep < c->tune_best_us) {
+    c->tune_best = c->sweep_block;
+    c->tune_best_us = us_per_sweep;
+  }
+  if (++c->tune_next == 4) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache.emplace_back(tune_key(c), c->tune_best);
+  }
+}
+}  // namespace
+int cd_fail(cd_ctx* c, int code, const char* msg) { return fail(c, code, msg); }
+namespace {
 int fail(cd_ctx* c, int code, const std::string& msg) {
   c->err = msg;
   return code;
@@ -297,6 +358,13 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
   alloci(&c->inc_ptr, n + 1);
   alloci(&c->inc_cursor, n + 1);
   if (st == CD_OK && hipMalloc((void**)&c->d_state, sizeof(SolveState)) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK) {
+    // no solve open until a step sets one up (a batched launch may read it)
+    SolveState s0{};
+    s0.done = 1;
+    if (hipMemcpy(c->d_state, &s0, sizeof(SolveState), hipMemcpyHostToDevice) != hipSuccess)
+      st = CD_EHIP;
+  }
   if (st == CD_OK && hipMalloc((void**)&c->d_stats, sizeof(DomainStats)) != hipSuccess) st = CD_ENOMEM;
   if (st == CD_OK && hipMalloc((void**)&c->d_bar, sizeof(GridBar)) != hipSuccess) st = CD_ENOMEM;
   if (st == CD_OK && hipMalloc((void**)&c->init_part, sizeof(double) * 256) != hipSuccess)
@@ -480,12 +548,22 @@ int cd_set_solve_mode(cd_ctx* c, int mode) {
 }
 
 int cd_set_launch(cd_ctx* c, int block_threads) {
-  if (!c || block_threads < 0 || block_threads > 256 || block_threads % 64 != 0) return CD_EINVAL;
+  if (!c || block_threads < -1 || block_threads > 256 ||
+      (block_threads > 0 && block_threads % 64 != 0))
+    return CD_EINVAL;
   c->block_override = block_threads;
+  c->tune_next = 0;
+  c->tune_best_us = 0.0;
   return CD_OK;
 }
 
-int cd_step(cd_ctx* c, cd_result* out) {
+}  // extern "C"
+
+// A time step runs in three phases: step_prepare (boundary width,
+// detection, warm start, partition, order, solve set-up), the solve (one
+// context: solve_single; several: the batched solve) and step_finish
+// (canonical forces, Euler update, walls, results).
+int step_prepare(cd_ctx* c) {
   if (!c) return CD_EINVAL;
   if (!c->have_particles || !c->have_box) return fail(c, CD_ENOTREADY, "particles or box not set");
   const int dim = c->dim;
@@ -575,6 +653,7 @@ int cd_step(cd_ctx* c, cd_result* out) {
     const int widest = std::max(ds.max_contacts, ds.max_particles);
     c->sweep_block = widest > 64 ? 128 : 64;
     if (c->block_override > 0) c->sweep_block = c->block_override;
+    if (c->block_override < 0) c->sweep_block = tune_block_pick(c);
   }
   if (c->sweep_global) {
     // domains too large for LDS stage their data in global memory
@@ -585,9 +664,19 @@ int cd_step(cd_ctx* c, cd_result* out) {
     }
   }
   CD_TRY(hipEventRecord(c->ev[3], c->stream));
-  // ---- iterative solve
-  const int limit = c->p.fixed_iters > 0 ? c->p.fixed_iters : c->p.max_iter;
-  CD_TRY(cd_launch_solve_init(c, limit));
+  // ---- iterative solve: set-up
+  c->st_skin = skin;
+  c->st_ds = ds;
+  c->st_limit = c->p.fixed_iters > 0 ? c->p.fixed_iters : c->p.max_iter;
+  CD_TRY(cd_launch_solve_init(c, c->st_limit));
+  c->run = SolveRun{};
+  return CD_OK;
+}
+
+// The solve of one context alone.
+int solve_single(cd_ctx* c) {
+  const int64_t nc = c->nc;
+  const int limit = c->st_limit;
   int launched = 0;
   int executed = -1;
   bool aborted = false;
@@ -666,7 +755,23 @@ int cd_step(cd_ctx* c, cd_result* out) {
     CD_TRY(hipStreamSynchronize(c->stream));
     executed = 0;
   }
+  c->run.launched = launched;
+  c->run.executed = executed;
+  c->run.groups_closed = groups_closed;
+  c->run.one_launch = one_launch;
   if (aborted) return fail(c, CD_EHIP, "solve grid barrier did not complete (poll limit)");
+  return CD_OK;
+}
+
+int step_finish(cd_ctx* c, cd_result* out) {
+  const int dim = c->dim;
+  const double dt = c->p.dt;
+  const int64_t nc = c->nc;
+  const double skin = c->st_skin;
+  const DomainStats& ds = c->st_ds;
+  const int launched = c->run.launched, executed = c->run.executed;
+  const int groups_closed = c->run.groups_closed;
+  const bool one_launch = c->run.one_launch;
   SolveState s;
   memcpy(&s, c->h_state, sizeof(SolveState));
   CD_TRY(hipEventRecord(c->ev[4], c->stream));
@@ -689,7 +794,7 @@ int cd_step(cd_ctx* c, cd_result* out) {
       if (c->wn[wi * dim + k] == -1.0) c->hi[k] = -c->wo[wi];
     }
   }
-  st = upload_walls(c);
+  int st = upload_walls(c);
   if (st != CD_OK) return st;
   c->step += 1;
   // ---- result and timings
@@ -732,9 +837,21 @@ int cd_step(cd_ctx* c, cd_result* out) {
   }
   tm.sweep_kernel_ms = sk;
   c->timing = tm;
+  if (c->block_override < 0 && tm.sweeps_timed > 0)
+    tune_block_record(c, 1e3 * sk / std::max(executed, 1));
   if (out) *out = res;
   if (res.status == CD_ENONFINITE) return fail(c, CD_ENONFINITE, "non-finite contact force");
   return res.status;
+}
+
+extern "C" {
+
+int cd_step(cd_ctx* c, cd_result* out) {
+  int st = step_prepare(c);
+  if (st != CD_OK) return st;
+  st = solve_single(c);
+  if (st != CD_OK) return st;
+  return step_finish(c, out);
 }
 
 int cd_get_state(cd_ctx* c, double* x, double* v, double* w) {

@@ -1,0 +1,269 @@
+// batch.hip - many independent packings stepped together.
+//
+// Each packing is an ordinary context (its own parameters, domains, walls,
+// contact list, tree and order), so a packing's results are those of its
+// own cd_step.  Per time step the batch runs every packing's preparation
+// (detection, partition, order), then ONE launch per sweep over the domains
+// of all packings (each packing's workgroups plus its decision workgroup);
+// a packing whose solve has stopped leaves its workgroups idle, and the
+// launches end once every packing has stopped.  Then every packing's update.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "cd_internal.h"
+
+struct cd_batch {
+  std::vector<cd_ctx*> ctx;
+  hipStream_t stream = nullptr;
+  int dim = 2;
+  int grid_total = 0;           // workgroups of one batched sweep launch
+  SweepArgs* h_tab = nullptr;   // pinned
+  SweepArgs* d_tab = nullptr;
+  int* d_blk = nullptr;         // per workgroup: packing, workgroup within the packing
+  SolveState* h_states = nullptr;  // pinned
+  SolveState* d_states = nullptr;
+  BatchProg* h_prog = nullptr;  // mapped pinned
+  BatchProg* d_prog = nullptr;
+  int time_every = 8;
+  std::vector<int> failed;      // per packing: 0, or the error that took it out
+  std::vector<hipEvent_t> sweep_ev;
+  hipEvent_t ev[4] = {};
+  cd_batch_timing timing{};
+  std::string err;
+};
+
+namespace {
+
+int bfail(cd_batch* b, int code, const std::string& msg) {
+  b->err = msg;
+  return code;
+}
+
+#define BTRY(expr)                                                               \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) return bfail(b, CD_EHIP, hipGetErrorString(e_));       \
+  } while (0)
+
+float ms_between(hipEvent_t a, hipEvent_t c) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, c) != hipSuccess) return 0.f;
+  return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cd_batch_create(cd_batch** out, cd_ctx* const* ctxs, int count) {
+  if (!out || !ctxs || count < 1) return CD_EINVAL;
+  *out = nullptr;
+  cd_batch* b = new cd_batch();
+  b->ctx.assign(ctxs, ctxs + count);
+  b->stream = ctxs[0]->stream;
+  b->dim = ctxs[0]->dim;
+  std::vector<int> blk;
+  for (int p = 0; p < count; ++p) {
+    cd_ctx* c = ctxs[p];
+    if (!c || c->stream != b->stream || c->dim != b->dim || c->device != ctxs[0]->device) {
+      delete b;
+      return CD_EINVAL;
+    }
+    // the packing's domain workgroups and its decision workgroup
+    const int grid = cd_sweep_args(c).grid;
+    for (int q = 0; q <= grid; ++q) {
+      blk.push_back(p);
+      blk.push_back(q);
+    }
+  }
+  b->grid_total = (int)blk.size() / 2;
+  b->failed.assign(count, 0);
+  int st = CD_OK;
+  if (hipHostMalloc((void**)&b->h_tab, sizeof(SweepArgs) * count) != hipSuccess ||
+      hipMalloc((void**)&b->d_tab, sizeof(SweepArgs) * count) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_states, sizeof(SolveState) * count) != hipSuccess ||
+      hipMalloc((void**)&b->d_states, sizeof(SolveState) * count) != hipSuccess ||
+      hipMalloc((void**)&b->d_blk, sizeof(int) * blk.size()) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_prog, sizeof(BatchProg), hipHostMallocMapped) != hipSuccess)
+    st = CD_ENOMEM;
+  if (st == CD_OK && hipHostGetDevicePointer((void**)&b->d_prog, b->h_prog, 0) != hipSuccess)
+    st = CD_EHIP;
+  if (st == CD_OK &&
+      hipMemcpy(b->d_blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice) != hipSuccess)
+    st = CD_EHIP;
+  for (int k = 0; k < 4 && st == CD_OK; ++k)
+    if (hipEventCreate(&b->ev[k]) != hipSuccess) st = CD_EHIP;
+  if (st != CD_OK) {
+    cd_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return CD_OK;
+}
+
+int cd_batch_destroy(cd_batch* b) {
+  if (!b) return CD_OK;
+  if (b->h_tab) (void)hipHostFree(b->h_tab);
+  if (b->d_tab) (void)hipFree(b->d_tab);
+  if (b->h_states) (void)hipHostFree(b->h_states);
+  if (b->d_states) (void)hipFree(b->d_states);
+  if (b->d_blk) (void)hipFree(b->d_blk);
+  if (b->h_prog) (void)hipHostFree(b->h_prog);
+  for (auto& e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : b->sweep_ev)
+    if (e) (void)hipEventDestroy(e);
+  delete b;
+  return CD_OK;
+}
+
+int cd_batch_set_timing(cd_batch* b, int every) {
+  if (!b || every < 0) return CD_EINVAL;
+  b->time_every = every;
+  return CD_OK;
+}
+
+int cd_batch_step(cd_batch* b, cd_result* results) {
+  if (!b || !results) return CD_EINVAL;
+  const int B = (int)b->ctx.size();
+  BTRY(hipEventRecord(b->ev[0], b->stream));
+  // ---- every packing's preparation.  A packing whose velocities broke the
+  // displacement bound or turned non-finite (its solve diverged, Sec. 2.3)
+  // leaves the batch: its result carries the error in every later step.
+  for (int p = 0; p < B; ++p) {
+    if (b->failed[p]) continue;
+    int st = step_prepare(b->ctx[p]);
+    if (st == CD_EINVAL || st == CD_ENONFINITE) {
+      b->failed[p] = st;
+      continue;
+    }
+    if (st != CD_OK)
+      return bfail(b, st, "packing " + std::to_string(p) + ": " + cd_last_error(b->ctx[p]));
+  }
+  BTRY(hipEventRecord(b->ev[1], b->stream));
+  // ---- the batched solve
+  int limit = 0, open = 0, block = 64;
+  size_t lds = 8;
+  for (int p = 0; p < B; ++p) {
+    cd_ctx* c = b->ctx[p];
+    if (!b->failed[p] && c->sweep_global)
+      return bfail(b, CD_ECAPACITY,
+                   "packing " + std::to_string(p) + ": a domain does not fit in LDS");
+    b->h_tab[p] = cd_sweep_args(c);
+    block = std::max(block, c->sweep_block);
+    lds = std::max(lds, c->sweep_lds);
+    if (!b->failed[p] && c->nc > 0 && c->st_limit > 0) {
+      ++open;
+      limit = std::max(limit, c->st_limit);
+    }
+  }
+  BTRY(hipMemcpyAsync(b->d_tab, b->h_tab, sizeof(SweepArgs) * B, hipMemcpyHostToDevice,
+                      b->stream));
+  const int every = b->time_every;
+  const int groups_cap = every > 0 ? (limit + every - 1) / every : 0;
+  if ((int)b->sweep_ev.size() < 2 * groups_cap) {
+    size_t old = b->sweep_ev.size();
+    b->sweep_ev.resize(2 * (size_t)groups_cap, nullptr);
+    for (size_t k = old; k < b->sweep_ev.size(); ++k) BTRY(hipEventCreate(&b->sweep_ev[k]));
+  }
+  volatile BatchProg* hp = b->h_prog;
+  hp->decided = 0;
+  hp->ndone = 0;
+  __sync_synchronize();
+  const int kLookahead = 8;
+  int launched = 0, groups_closed = 0;
+  while (launched < limit && hp->ndone < open) {
+    if (launched - hp->decided >= kLookahead) {
+      const int seen = hp->decided;
+      auto t0 = std::chrono::steady_clock::now();
+      while (hp->decided == seen && hp->ndone < open) {
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
+          return bfail(b, CD_EHIP, "batched solve made no progress for 60 s");
+      }
+      continue;
+    }
+    const int j = launched + 1;
+    const int m = every > 0 && j >= 2 ? (j - 2) / every : -1;
+    const bool opens = m >= 0 && (j - 2) % every == 0;
+    const bool closes = m >= 0 && (j - 2) % every == every - 1;
+    if (opens) BTRY(hipEventRecord(b->sweep_ev[2 * m], b->stream));
+    BTRY(cd_launch_sweep_batch(b->stream, b->dim, b->d_tab, b->d_blk, b->grid_total, block, lds, j,
+                               b->d_prog));
+    if (closes) {
+      BTRY(hipEventRecord(b->sweep_ev[2 * m + 1], b->stream));
+      groups_closed = m + 1;
+    }
+    launched = j;
+  }
+  // the decisions of the last launched sweep for the packings still open
+  BTRY(cd_launch_decide_batch(b->stream, b->d_tab, B, launched, b->d_prog));
+  BTRY(cd_launch_gather_states(b->stream, b->d_tab, B, b->d_states));
+  BTRY(hipMemcpyAsync(b->h_states, b->d_states, sizeof(SolveState) * B, hipMemcpyDeviceToHost,
+                      b->stream));
+  BTRY(hipEventRecord(b->ev[2], b->stream));
+  BTRY(hipStreamSynchronize(b->stream));
+  int max_exec = 0;
+  for (int p = 0; p < B; ++p) {
+    cd_ctx* c = b->ctx[p];
+    if (b->failed[p]) continue;
+    memcpy(c->h_state, &b->h_states[p], sizeof(SolveState));
+    c->run = SolveRun{};
+    c->run.launched = launched;
+    c->run.executed = c->nc > 0 ? std::min(launched, c->h_state->iter + 1) : 0;
+    max_exec = std::max(max_exec, c->run.executed);
+  }
+  // ---- every packing's update
+  int status = CD_OK;
+  for (int p = 0; p < B; ++p) {
+    if (b->failed[p]) {
+      results[p] = cd_result{};
+      results[p].status = b->failed[p];
+      status = CD_ENONFINITE;
+      continue;
+    }
+    int st = step_finish(b->ctx[p], &results[p]);
+    if (st < 0 && st != CD_ENONFINITE)
+      return bfail(b, st, "packing " + std::to_string(p) + ": " + cd_last_error(b->ctx[p]));
+    if (st == CD_ENONFINITE) {
+      b->failed[p] = CD_ENONFINITE;
+      status = CD_ENONFINITE;
+    } else if (st == CD_MAXITER && status == CD_OK) {
+      status = CD_MAXITER;
+    }
+  }
+  BTRY(hipEventRecord(b->ev[3], b->stream));
+  BTRY(hipEventSynchronize(b->ev[3]));
+  cd_batch_timing tm{};
+  tm.prepare_ms = ms_between(b->ev[0], b->ev[1]);
+  tm.solve_ms = ms_between(b->ev[1], b->ev[2]);
+  tm.finish_ms = ms_between(b->ev[2], b->ev[3]);
+  tm.sweep_launches = launched;
+  tm.sweeps_executed = max_exec;
+  tm.block_threads = block;
+  tm.workgroups = b->grid_total;
+  double sum = 0.0;
+  int cnt = 0;
+  for (int m = 0; m < groups_closed && 2 + (m + 1) * every - 1 <= max_exec; ++m) {
+    sum += ms_between(b->sweep_ev[2 * m], b->sweep_ev[2 * m + 1]);
+    cnt += every;
+  }
+  tm.sweep_kernel_ms = cnt > 0 ? sum / cnt * max_exec : 0.0;
+  tm.sweeps_timed = cnt;
+  b->timing = tm;
+  if (status == CD_ENONFINITE) b->err = "some packings diverged and left the batch";
+  return status;
+}
+
+int cd_batch_get_timing(cd_batch* b, cd_batch_timing* out) {
+  if (!b || !out) return CD_EINVAL;
+  *out = b->timing;
+  return CD_OK;
+}
+
+const char* cd_batch_last_error(const cd_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+}  // extern "C"

@@ -71,6 +71,13 @@ struct HostProg {
   int pad[14];
 };
 
+// progress of a batched solve (mapped pinned host memory)
+struct BatchProg {
+  int decided;        // last sweep whose stop decisions are taken
+  int ndone;          // packings whose solve stopped in a decision
+  int pad[14];
+};
+
 struct BlockPartial {
   long long n_pass;
   double max_d_fail;
@@ -128,6 +135,14 @@ enum {
   G_KN = 12,    // 1 / (dt w_n)
   G_KT = 13,    // 1 / (dt w_t)
   G_COUNT = 14
+};
+
+// how the last solve ran (per-sweep launches, timing groups)
+struct SolveRun {
+  int launched = 0;       // sweep launches (1 for the one-launch solve)
+  int executed = 0;       // launches that did work
+  int groups_closed = 0;  // complete timing groups of launches
+  bool one_launch = false;
 };
 
 struct cd_ctx {
@@ -211,7 +226,10 @@ struct cd_ctx {
   int* drow = nullptr;           // 2 cap x row width
   int* ddesc = nullptr;          // P x 8
   int sweep_block = 64;          // threads per domain workgroup
-  int block_override = 0;        // 0: chosen from the domain sizes
+  int block_override = 0;        // 0: chosen from the domain sizes; -1: tuned
+  int tune_next = 0;             // next candidate width to try (4: tuning over)
+  int tune_best = 0;             // fastest width seen
+  double tune_best_us = 0.0;     // its mean sweep launch time
   bool sweep_global = false;
   size_t max_lds = 65536;
   int *inc_count = nullptr, *inc_ptr = nullptr, *inc_cursor = nullptr, *inc = nullptr;
@@ -244,7 +262,18 @@ struct cd_ctx {
   std::vector<hipEvent_t> sweep_ev;
   cd_timing timing{};
   cd_result last{};
+  // the current step, between its phases
+  double st_skin = 0.0;
+  DomainStats st_ds{};
+  int st_limit = 0;
+  SolveRun run;
 };
+
+// phases of a time step (api.hip); the batch runs them for several contexts
+int step_prepare(cd_ctx* c);
+int solve_single(cd_ctx* c);
+int step_finish(cd_ctx* c, cd_result* out);
+int cd_fail(cd_ctx* c, int code, const char* msg);
 
 // ---- launch wrappers (each enqueues on ctx->stream) -----------------------
 // scan.hip
@@ -271,6 +300,12 @@ hipError_t cd_launch_solve_init(cd_ctx* c, int limit);
 // sweep j; its extra workgroup takes the stop decision of sweep j-1
 hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after);
 hipError_t cd_launch_decide(cd_ctx* c, int jd);            // stop decision of sweep jd alone
+// batched solve over the packings of tab (device array of their arguments)
+hipError_t cd_launch_sweep_batch(hipStream_t stream, int dim, const SweepArgs* tab, const int* blk,
+                                 int grid, int block, size_t lds, int j, BatchProg* bp);
+hipError_t cd_launch_decide_batch(hipStream_t stream, const SweepArgs* tab, int B, int jd,
+                                  BatchProg* bp);
+hipError_t cd_launch_gather_states(hipStream_t stream, const SweepArgs* tab, int B, SolveState* out);
 hipError_t cd_launch_unslot(cd_ctx* c, int final_iter);
 int cd_solve_grid(cd_ctx* c);                               // co-resident grid, 0 if none
 

@@ -544,7 +544,8 @@ __device__ inline BlockPartial reduce_partials(const BlockPartial* part, int cou
 // Stop decision of sweep jd by the calling workgroup: fixed-order reduction
 // of that sweep's workgroup partials, test (I) or (II), and the progress
 // record for the host.  No-op once the solve is done.
-__device__ inline void decide_block(const SweepArgs& a, int jd, BlockRed& red, int& s_flag) {
+__device__ inline void decide_block(const SweepArgs& a, int jd, BlockRed& red, int& s_flag,
+                                    BatchProg* bp) {
   SolveState* st = a.state;
   if (threadIdx.x == 0) s_flag = *(volatile const int*)&st->done;
   __syncthreads();
@@ -554,23 +555,27 @@ __device__ inline void decide_block(const SweepArgs& a, int jd, BlockRed& red, i
     decide_sweep(a, st, jd, t.n_pass, t.max_d_fail, t.sum_r);
     __hip_atomic_store(&a.prog->done, st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(&a.prog->decided, jd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (bp) {
+      // batched solve: one more packing has stopped
+      if (st->done) __hip_atomic_fetch_add(&bp->ndone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&bp->decided, jd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
-// Sweep j, one workgroup per domain (block b sweeps domain_of(b, 0)); the
-// extra last workgroup takes the stop decision of sweep j-1 meanwhile.  A
-// stop at j-1 leaves the forces of sweep j-1 final (sweep j writes the other
-// record array); a workgroup that already sees the stop skips its domain.
+// Sweep j of one domain by workgroup b of a packing's launch, or (b ==
+// a.grid) the stop decision of sweep j-1.  A stop at j-1 leaves the forces
+// of sweep j-1 final (sweep j writes the other record array); a workgroup
+// that already sees the stop skips its domain.
 template <int DIM, bool GLOB>
-__global__ __launch_bounds__(kMaxBlock) void k_sweep(SweepArgs a, int j) {
+__device__ inline void sweep_block(const SweepArgs& a, int b, int j, BatchProg* bp) {
   extern __shared__ double lds[];
   __shared__ BlockRed red;
   __shared__ int s_co[CD_MAX_COLORS + 1];
   __shared__ double s_wu[CD_MAX_WALLS * 3];
   __shared__ int s_flag;
-  const int b = blockIdx.x;
   if (b == a.grid) {
-    if (j >= 2) decide_block(a, j - 1, red, s_flag);
+    if (j >= 2) decide_block(a, j - 1, red, s_flag, bp);
     return;
   }
   // the decision workgroup may set `done` during this launch: read it once
@@ -587,11 +592,42 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(SweepArgs a, int j) {
   if (threadIdx.x == 0) a.partial[(int64_t)(j & 1) * a.grid + b] = p;
 }
 
+// Sweep j of one context: a.grid domain workgroups plus its decision workgroup.
+template <int DIM, bool GLOB>
+__global__ __launch_bounds__(kMaxBlock) void k_sweep(SweepArgs a, int j) {
+  sweep_block<DIM, GLOB>(a, blockIdx.x, j, nullptr);
+}
+
+// Sweep j of a batch of packings: workgroup b serves packing blk[2b] as its
+// workgroup blk[2b+1] (tab holds each packing's arguments).
+template <int DIM>
+__global__ __launch_bounds__(kMaxBlock) void k_sweep_batch(const SweepArgs* tab, const int* blk,
+                                                          int j, BatchProg* bp) {
+  const int2 pb = ((const int2*)blk)[blockIdx.x];
+  const SweepArgs a = tab[pb.x];
+  sweep_block<DIM, false>(a, pb.y, j, bp);
+}
+
 // stop decision of sweep jd alone (after the last launched sweep)
 __global__ __launch_bounds__(kMaxBlock) void k_decide(SweepArgs a, int jd) {
   __shared__ BlockRed red;
   __shared__ int s_flag;
-  decide_block(a, jd, red, s_flag);
+  decide_block(a, jd, red, s_flag, nullptr);
+}
+
+// the same for every packing of a batch: workgroup p decides packing p
+__global__ __launch_bounds__(kMaxBlock) void k_decide_batch(const SweepArgs* tab, int jd,
+                                                           BatchProg* bp) {
+  __shared__ BlockRed red;
+  __shared__ int s_flag;
+  const SweepArgs a = tab[blockIdx.x];
+  decide_block(a, jd, red, s_flag, bp);
+}
+
+// solve states of a batch gathered into one array (one copy to the host)
+__global__ __launch_bounds__(64) void k_gather_states(const SweepArgs* tab, int B, SolveState* out) {
+  const int p = blockIdx.x * 64 + threadIdx.x;
+  if (p < B) out[p] = *tab[p].state;
 }
 
 __device__ inline int ld_relaxed(const int* p) {
@@ -852,6 +888,28 @@ hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !after) return e;
   return hipEventRecord(after, c->stream);
+}
+
+hipError_t cd_launch_sweep_batch(hipStream_t stream, int dim, const SweepArgs* tab, const int* blk,
+                                 int grid, int block, size_t lds, int j, BatchProg* bp) {
+  if (dim == 2)
+    hipLaunchKernelGGL(k_sweep_batch<2>, dim3(grid), dim3(block), lds, stream, tab, blk, j, bp);
+  else
+    hipLaunchKernelGGL(k_sweep_batch<3>, dim3(grid), dim3(block), lds, stream, tab, blk, j, bp);
+  return hipGetLastError();
+}
+
+hipError_t cd_launch_decide_batch(hipStream_t stream, const SweepArgs* tab, int B, int jd,
+                                  BatchProg* bp) {
+  if (jd < 1 || B < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_decide_batch, dim3(B), dim3(kMaxBlock), 0, stream, tab, jd, bp);
+  return hipGetLastError();
+}
+
+hipError_t cd_launch_gather_states(hipStream_t stream, const SweepArgs* tab, int B, SolveState* out) {
+  if (B < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_states, dim3((B + 63) / 64), dim3(64), 0, stream, tab, B, out);
+  return hipGetLastError();
 }
 
 hipError_t cd_launch_decide(cd_ctx* c, int jd) {

@@ -54,6 +54,11 @@ def margin_tiny(info, alpha):
 def compare_step(sim, ctx, label, alpha=1e-6, check_tree=True):
     io = sim.step()
     ig = ctx.step()
+    return compare_results(sim, ctx, io, ig, label, alpha, check_tree)
+
+
+def compare_results(sim, ctx, io, ig, label, alpha=1e-6, check_tree=True):
+    """One step's results of the oracle (sim, io) and the HIP path (ctx, ig)."""
     print(f"[{label}] oracle it={io.iterations} st={io.status} nc={io.n_contacts}  "
           f"gpu it={ig.iterations} st={ig.status} nc={ig.n_contacts}", flush=True)
     assert ig.n_contacts == io.n_contacts
