@@ -378,6 +378,9 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
   if (st == CD_OK && hipHostMalloc((void**)&c->h_state, sizeof(SolveState)) != hipSuccess)
     st = CD_ENOMEM;
   if (st == CD_OK && hipHostMalloc((void**)&c->h_scratch, 512) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK &&
+      hipHostMalloc((void**)&c->h_walls, sizeof(double) * CD_MAX_WALLS * 7) != hipSuccess)
+    st = CD_ENOMEM;
   if (st == CD_OK && hipHostMalloc((void**)&c->h_prog, sizeof(HostProg), hipHostMallocMapped) != hipSuccess)
     st = CD_ENOMEM;
   if (st == CD_OK && hipHostGetDevicePointer((void**)&c->d_prog, c->h_prog, 0) != hipSuccess)
@@ -436,6 +439,7 @@ int cd_destroy(cd_ctx* c) {
   release(&c->d_vmax);
   if (c->h_state) (void)hipHostFree(c->h_state);
   if (c->h_scratch) (void)hipHostFree(c->h_scratch);
+  if (c->h_walls) (void)hipHostFree(c->h_walls);
   if (c->h_prog) (void)hipHostFree(c->h_prog);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
@@ -498,8 +502,12 @@ int cd_set_external(cd_ctx* c, const double* force, const double* torque) {
   return CD_OK;
 }
 
-static int upload_walls(cd_ctx* c) {
-  double buf[CD_MAX_WALLS * 7];
+// Wall normals, offsets and velocities to the device through the pinned
+// staging buffer.  sync = false leaves the copy in flight: the caller must
+// not change the walls again before the stream has passed it (a time step
+// synchronises before its next wall update).
+static int upload_walls(cd_ctx* c, bool sync = true) {
+  double* buf = c->h_walls;
   const int W = c->W, dim = c->dim;
   for (int k = 0; k < W * dim; ++k) buf[k] = c->wn[k];
   for (int k = 0; k < W; ++k) buf[W * dim + k] = c->wo[k];
@@ -507,8 +515,7 @@ static int upload_walls(cd_ctx* c) {
   if (W > 0)
     CD_TRY(hipMemcpyAsync(c->d_wall, buf, sizeof(double) * (size_t)(W * (2 * dim + 1)),
                           hipMemcpyHostToDevice, c->stream));
-  // the host buffer must outlive the copy
-  CD_TRY(hipStreamSynchronize(c->stream));
+  if (sync) CD_TRY(hipStreamSynchronize(c->stream));
   return CD_OK;
 }
 
@@ -563,17 +570,20 @@ int cd_set_launch(cd_ctx* c, int block_threads) {
 // detection, warm start, partition, order, solve set-up), the solve (one
 // context: solve_single; several: the batched solve) and step_finish
 // (canonical forces, Euler update, walls, results).
-int step_prepare(cd_ctx* c) {
+int prep_phase0(cd_ctx* c) {
   if (!c) return CD_EINVAL;
   if (!c->have_particles || !c->have_box) return fail(c, CD_ENOTREADY, "particles or box not set");
-  const int dim = c->dim;
-  const double dt = c->p.dt;
   CD_TRY(hipEventRecord(c->ev[0], c->stream));
   // ---- boundary width: 2 vmax dt (Sec. 3.1)
   CD_TRY(cd_launch_vmax(c));
   CD_TRY(hipMemcpyAsync(c->h_scratch, c->d_vmax, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                         c->stream));
-  CD_TRY(hipStreamSynchronize(c->stream));
+  return CD_OK;
+}
+
+int prep_phase1(cd_ctx* c) {
+  const int dim = c->dim;
+  const double dt = c->p.dt;
   double vmax;
   {
     unsigned long long bits = (unsigned long long)c->h_scratch[0];
@@ -587,6 +597,7 @@ int step_prepare(cd_ctx* c) {
   }
   if (!isfinite(vmax)) return fail(c, CD_ENONFINITE, "non-finite velocity");
   const double skin = c->p.skin >= 0.0 ? c->p.skin : 2.0 * vmax * dt;
+  c->st_skin = skin;
   if (!(skin <= 0.2 * c->rmax))
     return fail(c, CD_EINVAL, "boundary width exceeds 0.2 r_max (displacement bound)");
   // ---- the previous step's list becomes the warm-start source
@@ -602,10 +613,14 @@ int step_prepare(cd_ctx* c) {
   CD_TRY(cd_launch_pair_count(c, skin));
   CD_TRY(hipMemcpyAsync(c->h_scratch, c->pair_off + c->n, sizeof(int), hipMemcpyDeviceToHost,
                         c->stream));
-  CD_TRY(hipStreamSynchronize(c->stream));
+  return CD_OK;
+}
+
+int prep_phase2(cd_ctx* c) {
+  const double skin = c->st_skin;
   const int64_t nc = (int64_t)((int*)c->h_scratch)[0];
   if (nc < 0 || nc > ((int64_t)1 << 30)) return fail(c, CD_ECAPACITY, "too many contacts");
-  st = ensure_capacity(c, nc);
+  int st = ensure_capacity(c, nc);
   if (st != CD_OK) return st;
   st = ensure_list(c, nc, &c->cap_list, &c->ci, &c->cj, &c->R);
   if (st != CD_OK) return st;
@@ -626,7 +641,11 @@ int step_prepare(cd_ctx* c) {
   CD_TRY(cd_launch_order(c));
   CD_TRY(hipMemcpyAsync(c->h_scratch, c->d_stats, sizeof(DomainStats), hipMemcpyDeviceToHost,
                         c->stream));
-  CD_TRY(hipStreamSynchronize(c->stream));
+  return CD_OK;
+}
+
+int prep_phase3(cd_ctx* c) {
+  const int dim = c->dim;
   DomainStats ds;
   memcpy(&ds, c->h_scratch, sizeof(DomainStats));
   if (ds.overflow)
@@ -665,12 +684,32 @@ int step_prepare(cd_ctx* c) {
   }
   CD_TRY(hipEventRecord(c->ev[3], c->stream));
   // ---- iterative solve: set-up
-  c->st_skin = skin;
   c->st_ds = ds;
   c->st_limit = c->p.fixed_iters > 0 ? c->p.fixed_iters : c->p.max_iter;
   CD_TRY(cd_launch_solve_init(c, c->st_limit));
   c->run = SolveRun{};
   return CD_OK;
+}
+
+int step_prepare(cd_ctx* c) {
+  int st = prep_phase0(c);
+  if (st != CD_OK) return st;
+  for (int k = 1; k < kPrepPhases; ++k) {
+    CD_TRY(hipStreamSynchronize(c->stream));
+    st = prep_phase(c, k);
+    if (st != CD_OK) return st;
+  }
+  return CD_OK;
+}
+
+int prep_phase(cd_ctx* c, int k) {
+  switch (k) {
+    case 0: return prep_phase0(c);
+    case 1: return prep_phase1(c);
+    case 2: return prep_phase2(c);
+    case 3: return prep_phase3(c);
+  }
+  return CD_EINVAL;
 }
 
 // The solve of one context alone.
@@ -763,7 +802,25 @@ int solve_single(cd_ctx* c) {
   return CD_OK;
 }
 
+int finish_enqueue(cd_ctx* c) {
+  SolveState s;
+  memcpy(&s, c->h_state, sizeof(SolveState));
+  CD_TRY(hipEventRecord(c->ev[4], c->stream));
+  // ---- Euler update and canonical forces
+  CD_TRY(cd_launch_unslot(c, s.iter));
+  CD_TRY(cd_launch_update(c, s.iter));
+  CD_TRY(hipEventRecord(c->ev[5], c->stream));
+  return CD_OK;
+}
+
 int step_finish(cd_ctx* c, cd_result* out) {
+  int st = finish_enqueue(c);
+  if (st != CD_OK) return st;
+  CD_TRY(hipStreamSynchronize(c->stream));
+  return finish_complete(c, out);
+}
+
+int finish_complete(cd_ctx* c, cd_result* out) {
   const int dim = c->dim;
   const double dt = c->p.dt;
   const int64_t nc = c->nc;
@@ -774,12 +831,6 @@ int step_finish(cd_ctx* c, cd_result* out) {
   const bool one_launch = c->run.one_launch;
   SolveState s;
   memcpy(&s, c->h_state, sizeof(SolveState));
-  CD_TRY(hipEventRecord(c->ev[4], c->stream));
-  // ---- Euler update and canonical forces
-  CD_TRY(cd_launch_unslot(c, s.iter));
-  CD_TRY(cd_launch_update(c, s.iter));
-  CD_TRY(hipEventRecord(c->ev[5], c->stream));
-  CD_TRY(hipStreamSynchronize(c->stream));
   // walls move; a box face follows the axis-aligned wall lying on it
   for (int wi = 0; wi < c->W; ++wi) {
     double un = 0.0;
@@ -794,7 +845,7 @@ int step_finish(cd_ctx* c, cd_result* out) {
       if (c->wn[wi * dim + k] == -1.0) c->hi[k] = -c->wo[wi];
     }
   }
-  int st = upload_walls(c);
+  int st = upload_walls(c, false);
   if (st != CD_OK) return st;
   c->step += 1;
   // ---- result and timings

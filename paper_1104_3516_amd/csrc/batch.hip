@@ -24,6 +24,8 @@ struct cd_batch {
   SweepArgs* h_tab = nullptr;   // pinned
   SweepArgs* d_tab = nullptr;
   int* d_blk = nullptr;         // per workgroup: packing, workgroup within the packing
+  std::vector<int> blk_all;     // the same for every packing (host)
+  int* h_blk[2] = {nullptr, nullptr};  // pinned staging of compacted tables
   SolveState* h_states = nullptr;  // pinned
   SolveState* d_states = nullptr;
   BatchProg* h_prog = nullptr;  // mapped pinned
@@ -81,6 +83,7 @@ int cd_batch_create(cd_batch** out, cd_ctx* const* ctxs, int count) {
     }
   }
   b->grid_total = (int)blk.size() / 2;
+  b->blk_all = blk;
   b->failed.assign(count, 0);
   int st = CD_OK;
   if (hipHostMalloc((void**)&b->h_tab, sizeof(SweepArgs) * count) != hipSuccess ||
@@ -88,6 +91,8 @@ int cd_batch_create(cd_batch** out, cd_ctx* const* ctxs, int count) {
       hipHostMalloc((void**)&b->h_states, sizeof(SolveState) * count) != hipSuccess ||
       hipMalloc((void**)&b->d_states, sizeof(SolveState) * count) != hipSuccess ||
       hipMalloc((void**)&b->d_blk, sizeof(int) * blk.size()) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_blk[0], sizeof(int) * blk.size()) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_blk[1], sizeof(int) * blk.size()) != hipSuccess ||
       hipHostMalloc((void**)&b->h_prog, sizeof(BatchProg), hipHostMallocMapped) != hipSuccess)
     st = CD_ENOMEM;
   if (st == CD_OK && hipHostGetDevicePointer((void**)&b->d_prog, b->h_prog, 0) != hipSuccess)
@@ -112,6 +117,8 @@ int cd_batch_destroy(cd_batch* b) {
   if (b->h_states) (void)hipHostFree(b->h_states);
   if (b->d_states) (void)hipFree(b->d_states);
   if (b->d_blk) (void)hipFree(b->d_blk);
+  for (int k = 0; k < 2; ++k)
+    if (b->h_blk[k]) (void)hipHostFree(b->h_blk[k]);
   if (b->h_prog) (void)hipHostFree(b->h_prog);
   for (auto& e : b->ev)
     if (e) (void)hipEventDestroy(e);
@@ -131,18 +138,23 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
   if (!b || !results) return CD_EINVAL;
   const int B = (int)b->ctx.size();
   BTRY(hipEventRecord(b->ev[0], b->stream));
-  // ---- every packing's preparation.  A packing whose velocities broke the
-  // displacement bound or turned non-finite (its solve diverged, Sec. 2.3)
-  // leaves the batch: its result carries the error in every later step.
-  for (int p = 0; p < B; ++p) {
-    if (b->failed[p]) continue;
-    int st = step_prepare(b->ctx[p]);
-    if (st == CD_EINVAL || st == CD_ENONFINITE) {
-      b->failed[p] = st;
-      continue;
+  // ---- every packing's preparation, phase by phase with one stream
+  // synchronisation between phases for the whole batch.  A packing whose
+  // velocities broke the displacement bound or turned non-finite (its solve
+  // diverged, Sec. 2.3) leaves the batch: its result carries the error in
+  // every later step.
+  for (int k = 0; k < kPrepPhases; ++k) {
+    if (k > 0) BTRY(hipStreamSynchronize(b->stream));
+    for (int p = 0; p < B; ++p) {
+      if (b->failed[p]) continue;
+      int st = prep_phase(b->ctx[p], k);
+      if (st == CD_EINVAL || st == CD_ENONFINITE) {
+        b->failed[p] = st;
+        continue;
+      }
+      if (st != CD_OK)
+        return bfail(b, st, "packing " + std::to_string(p) + ": " + cd_last_error(b->ctx[p]));
     }
-    if (st != CD_OK)
-      return bfail(b, st, "packing " + std::to_string(p) + ": " + cd_last_error(b->ctx[p]));
   }
   BTRY(hipEventRecord(b->ev[1], b->stream));
   // ---- the batched solve
@@ -170,13 +182,53 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
     b->sweep_ev.resize(2 * (size_t)groups_cap, nullptr);
     for (size_t k = old; k < b->sweep_ev.size(); ++k) BTRY(hipEventCreate(&b->sweep_ev[k]));
   }
+  // the launch table: every packing's workgroups; as packings stop, the
+  // table is rebuilt without them (their workgroups would only return)
+  int grid_now = b->grid_total, stage = 0, live = open;
+  BTRY(hipMemcpyAsync(b->d_blk, b->blk_all.data(), sizeof(int) * b->blk_all.size(),
+                      hipMemcpyHostToDevice, b->stream));
+  BTRY(hipStreamSynchronize(b->stream));
+  // each packing's own progress record says when its solve has stopped
+  for (int p = 0; p < B; ++p) {
+    volatile HostProg* cp = b->ctx[p]->h_prog;
+    cp->decided = 0;
+    cp->done = 0;
+  }
   volatile BatchProg* hp = b->h_prog;
   hp->decided = 0;
   hp->ndone = 0;
   __sync_synchronize();
   const int kLookahead = 8;
-  int launched = 0, groups_closed = 0;
+  int launched = 0, groups_closed = 0, last_build = 0;
   while (launched < limit && hp->ndone < open) {
+    if (launched - last_build >= 16 && open - hp->ndone <= (3 * live) / 4) {
+      // compact: keep the packings whose stop has not been published; the
+      // copy is ordered after the launches already queued, and a staging
+      // buffer is rewritten only 16 or more launches after its last copy,
+      // when the lookahead bound guarantees that copy has run
+      int* tab = b->h_blk[stage];
+      int n2 = 0, still = 0;
+      for (int p = 0; p < B; ++p) {
+        const cd_ctx* c = b->ctx[p];
+        if (b->failed[p] || c->nc == 0 || c->st_limit <= 0 || ((volatile HostProg*)c->h_prog)->done)
+          continue;
+        ++still;
+        const int grid = b->h_tab[p].grid;
+        for (int q = 0; q <= grid; ++q) {
+          tab[2 * n2] = p;
+          tab[2 * n2 + 1] = q;
+          ++n2;
+        }
+      }
+      if (n2 > 0) {
+        BTRY(hipMemcpyAsync(b->d_blk, tab, sizeof(int) * 2 * (size_t)n2, hipMemcpyHostToDevice,
+                            b->stream));
+        grid_now = n2;
+        stage ^= 1;
+      }
+      live = still;
+      last_build = launched;
+    }
     if (launched - hp->decided >= kLookahead) {
       const int seen = hp->decided;
       auto t0 = std::chrono::steady_clock::now();
@@ -191,7 +243,7 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
     const bool opens = m >= 0 && (j - 2) % every == 0;
     const bool closes = m >= 0 && (j - 2) % every == every - 1;
     if (opens) BTRY(hipEventRecord(b->sweep_ev[2 * m], b->stream));
-    BTRY(cd_launch_sweep_batch(b->stream, b->dim, b->d_tab, b->d_blk, b->grid_total, block, lds, j,
+    BTRY(cd_launch_sweep_batch(b->stream, b->dim, b->d_tab, b->d_blk, grid_now, block, lds, j,
                                b->d_prog));
     if (closes) {
       BTRY(hipEventRecord(b->sweep_ev[2 * m + 1], b->stream));
@@ -216,8 +268,16 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
     c->run.executed = c->nc > 0 ? std::min(launched, c->h_state->iter + 1) : 0;
     max_exec = std::max(max_exec, c->run.executed);
   }
-  // ---- every packing's update
+  // ---- every packing's update: launches for all, one synchronisation,
+  // then walls, results and timings
   int status = CD_OK;
+  for (int p = 0; p < B; ++p) {
+    if (b->failed[p]) continue;
+    int st = finish_enqueue(b->ctx[p]);
+    if (st != CD_OK)
+      return bfail(b, st, "packing " + std::to_string(p) + ": " + cd_last_error(b->ctx[p]));
+  }
+  BTRY(hipStreamSynchronize(b->stream));
   for (int p = 0; p < B; ++p) {
     if (b->failed[p]) {
       results[p] = cd_result{};
@@ -225,7 +285,7 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
       status = CD_ENONFINITE;
       continue;
     }
-    int st = step_finish(b->ctx[p], &results[p]);
+    int st = finish_complete(b->ctx[p], &results[p]);
     if (st < 0 && st != CD_ENONFINITE)
       return bfail(b, st, "packing " + std::to_string(p) + ": " + cd_last_error(b->ctx[p]));
     if (st == CD_ENONFINITE) {

@@ -249,6 +249,7 @@ struct cd_ctx {
   int partial_cap = 0;
   unsigned long long* d_vmax = nullptr;
   long long* h_scratch = nullptr;  // pinned small readbacks
+  double* h_walls = nullptr;       // pinned staging of the wall upload
 
   // scan workspace
   int* scan_tmp = nullptr;
@@ -271,8 +272,17 @@ struct cd_ctx {
 
 // phases of a time step (api.hip); the batch runs them for several contexts
 int step_prepare(cd_ctx* c);
+// step_prepare in kPrepPhases parts; each part but the last ends with a small
+// device-to-host copy that the next part reads, so the caller synchronises
+// the stream between parts (once for a whole batch)
+constexpr int kPrepPhases = 4;
+int prep_phase(cd_ctx* c, int k);
 int solve_single(cd_ctx* c);
 int step_finish(cd_ctx* c, cd_result* out);
+// step_finish in two parts: the update launches, then (after the stream has
+// passed them) the walls, results and timings
+int finish_enqueue(cd_ctx* c);
+int finish_complete(cd_ctx* c, cd_result* out);
 int cd_fail(cd_ctx* c, int code, const char* msg);
 
 // ---- launch wrappers (each enqueues on ctx->stream) -----------------------
