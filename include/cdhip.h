@@ -185,6 +185,43 @@ int cd_get_timing(cd_ctx* ctx, cd_timing* out);
 const char* cd_status_string(int status);
 const char* cd_last_error(const cd_ctx* ctx);
 
+/* ---- A step in phases, per-contact friction, adjoint ---------------------
+ * cd_step = cd_prepare + cd_solve.  Between the two the contact list of the
+ * coming solve is known (cd_num_contacts, cd_get_contacts), so per-contact
+ * inputs can be given in its canonical order. */
+
+/* Boundary width, detection, warm start, partition and order of the coming
+ * step (the first part of cd_step). */
+int cd_prepare(cd_ctx* ctx);
+
+/* Friction coefficient of every contact of the prepared list (DEVICE array
+ * of cd_num_contacts doubles, canonical order), for the coming cd_solve only
+ * (Sec. 2.1 allows a coefficient per contact).  CD_ENOTREADY without
+ * cd_prepare. */
+int cd_set_contact_mu(cd_ctx* ctx, const double* mu);
+
+/* The solve and the Euler update of the prepared step (the rest of cd_step). */
+int cd_solve(cd_ctx* ctx, cd_result* out);
+
+/* checkpoint_every > 0: solves with a fixed sweep count (params.fixed_iters)
+ * record the forces before the first sweep and after every checkpoint_every
+ * sweeps, for cd_adjoint (2D).  0 (default): no recording. */
+int cd_set_adjoint(cd_ctx* ctx, int checkpoint_every);
+
+/* Reverse mode of the last recorded solve: given dL_dR (DEVICE, dim x n_c,
+ * canonical order, frame components (R_n, R_t) of the forces after the last
+ * sweep), writes dL_dmu (DEVICE, n_c: per contact friction), dL_dv (DEVICE,
+ * dim x N) and dL_dw (DEVICE, N) of the velocities the step started from;
+ * any output may be NULL.  The sweeps are differentiated exactly in the
+ * branch each contact took (open, stick, slide; Eqs. 3-9), segment by
+ * segment from the checkpoints.  The slot data of the solve must still be in
+ * place: call it before the next cd_prepare / cd_step.  CD_ENOTREADY without
+ * a recorded solve, CD_EINVAL in 3D, CD_ECAPACITY when a domain is too large
+ * for the reverse sweep's LDS.  Motivation: gradients of contact forces with
+ * respect to friction and initial velocities for inverse problems and
+ * calibration, on top of the paper's fixed-iteration option (Sec. 2.1). */
+int cd_adjoint(cd_ctx* ctx, const double* dL_dR, double* dL_dmu, double* dL_dv, double* dL_dw);
+
 /* ---- Batches of independent packings ------------------------------------
  * Many packings stepped together: each packing is a context created and
  * filled as above (its own parameters, friction, domain count, walls); the

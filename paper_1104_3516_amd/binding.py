@@ -98,6 +98,11 @@ def lib():
         L.cd_status_string.restype = C.c_char_p
         L.cd_last_error.argtypes = [P]
         L.cd_last_error.restype = C.c_char_p
+        L.cd_prepare.argtypes = [P]
+        L.cd_set_contact_mu.argtypes = [P, P]
+        L.cd_solve.argtypes = [P, C.POINTER(Result)]
+        L.cd_set_adjoint.argtypes = [P, C.c_int]
+        L.cd_adjoint.argtypes = [P, P, P, P, P]
         L.cd_batch_create.argtypes = [C.POINTER(P), C.POINTER(P), C.c_int]
         L.cd_batch_destroy.argtypes = [P]
         L.cd_batch_set_timing.argtypes = [P, C.c_int]
@@ -150,6 +155,10 @@ class Context:
             f, t = dev(packing.f), dev(packing.t)
             self._check(self.L.cd_set_particles(self.h, _ptr(x), _ptr(v), _ptr(w), _ptr(r),
                                                 _ptr(m), _ptr(inertia)))
+            self._x0, self._r, self._m, self._inertia = x, r, m, inertia
+            self._v0, self._w0 = v, w
+            self._walls = (packing.wall_normal, packing.wall_offset, packing.wall_velocity,
+                           packing.box_lo, packing.box_hi)
             self._check(self.L.cd_set_external(self.h, _ptr(f), _ptr(t)))
             wn = np.ascontiguousarray(packing.wall_normal, dtype=np.float64)
             wo = np.ascontiguousarray(packing.wall_offset, dtype=np.float64)
@@ -244,6 +253,82 @@ class Context:
         t = Timing()
         self._check(self.L.cd_get_timing(self.h, C.byref(t)))
         return t
+
+    # ---- a step in phases, per-contact friction, adjoint (cd_prepare ...) ----
+    def reset(self, v=None, w=None):
+        """Back to the initial positions and walls (cold start), with the
+        given velocities (default: the packing's)."""
+        torch = self.torch
+        v = self._v0 if v is None else v.detach().to(self.device, torch.float64).contiguous()
+        w = self._w0 if w is None else w.detach().to(self.device, torch.float64).contiguous()
+        self._check(self.L.cd_set_particles(self.h, _ptr(self._x0), _ptr(v), _ptr(w),
+                                            _ptr(self._r), _ptr(self._m), _ptr(self._inertia)))
+        wn, wo, wv, lo, hi = (np.ascontiguousarray(a, dtype=np.float64) for a in self._walls)
+        self._check(self.L.cd_set_walls(self.h, wn.ctypes.data_as(C.c_void_p),
+                                        wo.ctypes.data_as(C.c_void_p),
+                                        wv.ctypes.data_as(C.c_void_p)))
+        self._check(self.L.cd_set_box(self.h, lo.ctypes.data_as(C.c_void_p),
+                                      hi.ctypes.data_as(C.c_void_p)))
+
+    def prepare(self) -> int:
+        self._check(self.L.cd_prepare(self.h))
+        return self.num_contacts()
+
+    def set_contact_mu(self, mu):
+        mu = mu.detach().to(self.device, self.torch.float64).contiguous()
+        self._mu_keep = mu
+        self._check(self.L.cd_set_contact_mu(self.h, _ptr(mu)))
+
+    def solve(self) -> Result:
+        res = Result()
+        self._check(self.L.cd_solve(self.h, C.byref(res)))
+        return res
+
+    def set_adjoint(self, checkpoint_every: int):
+        self._check(self.L.cd_set_adjoint(self.h, int(checkpoint_every)))
+
+    def adjoint(self, dL_dR):
+        """dL/dmu (n_c), dL/dv (dim x N), dL/dw (dr x N) of the last recorded solve."""
+        torch = self.torch
+        nc = self.num_contacts()
+        g = dL_dR.detach().to(self.device, torch.float64).contiguous()
+        dmu = torch.zeros(max(nc, 1), dtype=torch.float64, device=self.device)
+        dv = torch.zeros((self.dim, self.n), dtype=torch.float64, device=self.device)
+        dw = torch.zeros((self.dr, self.n), dtype=torch.float64, device=self.device)
+        self._check(self.L.cd_adjoint(self.h, _ptr(g), _ptr(dmu), _ptr(dv), _ptr(dw)))
+        return dmu[:nc], dv, dw
+
+
+def _forces_function():
+    import torch
+
+    class ContactForces(torch.autograd.Function):
+        """R = forces after a fixed-count solve of one step from the initial
+        positions, as a function of per-contact friction mu (n_c) and initial
+        velocities v (dim x N), w (dr x N).  Backward: cd_adjoint.  The
+        context must be set to a fixed sweep count, a fixed boundary width
+        (so that the contact list does not depend on v) and cd_set_adjoint."""
+
+        @staticmethod
+        def forward(fctx, mu, v, w, context):
+            context.reset(v, w)
+            context.prepare()
+            context.set_contact_mu(mu)
+            context.solve()
+            fctx.context = context
+            return context.contacts()["R"].clone()
+
+        @staticmethod
+        def backward(fctx, gR):
+            dmu, dv, dw = fctx.context.adjoint(gR)
+            return dmu, dv, dw, None
+
+    return ContactForces
+
+
+def contact_forces(mu, v, w, context):
+    """Autograd-aware forces of one fixed-count solve (see ContactForces)."""
+    return _forces_function().apply(mu, v, w, context)
 
 
 class Batch:

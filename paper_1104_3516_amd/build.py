@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcdhip.so")
 SOURCES = ["api.hip", "scan.hip", "sort.hip", "detect.hip", "partition.hip", "order.hip",
-           "sweep.hip", "update.hip", "batch.hip"]
+           "sweep.hip", "update.hip", "batch.hip", "adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Wall", "-Wno-unused-function",

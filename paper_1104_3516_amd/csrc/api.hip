@@ -436,6 +436,9 @@ int cd_destroy(cd_ctx* c) {
   release(&c->d_bar);
   release(&c->partial);
   release(&c->init_part);
+  release(&c->mu_slot);
+  release(&c->ck);
+  cd_adjoint_release(c);
   release(&c->d_vmax);
   if (c->h_state) (void)hipHostFree(c->h_state);
   if (c->h_scratch) (void)hipHostFree(c->h_scratch);
@@ -573,6 +576,9 @@ int cd_set_launch(cd_ctx* c, int block_threads) {
 int prep_phase0(cd_ctx* c) {
   if (!c) return CD_EINVAL;
   if (!c->have_particles || !c->have_box) return fail(c, CD_ENOTREADY, "particles or box not set");
+  c->adj_valid = false;
+  c->use_mu_slot = false;
+  c->prepared = false;
   CD_TRY(hipEventRecord(c->ev[0], c->stream));
   // ---- boundary width: 2 vmax dt (Sec. 3.1)
   CD_TRY(cd_launch_vmax(c));
@@ -688,6 +694,7 @@ int prep_phase3(cd_ctx* c) {
   c->st_limit = c->p.fixed_iters > 0 ? c->p.fixed_iters : c->p.max_iter;
   CD_TRY(cd_launch_solve_init(c, c->st_limit));
   c->run = SolveRun{};
+  c->prepared = true;
   return CD_OK;
 }
 
@@ -761,6 +768,19 @@ int solve_single(cd_ctx* c) {
     hp->decided = 0;
     hp->done = 0;
     __sync_synchronize();
+    // adjoint recording: the forces before the first sweep and after every
+    // adj_every-th sweep (fixed sweep count, 2D)
+    const bool record = c->adj_every > 0 && c->p.fixed_iters > 0 && c->dim == 2;
+    const int64_t rec_bytes = (int64_t)sizeof(double) * 4 * c->cap;
+    if (record) {
+      const int64_t slots = limit / c->adj_every + 1;
+      if (slots * 4 * c->cap > c->ck_cap) {
+        CD_TRY(grow(&c->ck, slots * 4 * c->cap));
+        c->ck_cap = slots * 4 * c->cap;
+      }
+      c->ck_stride = 4 * c->cap;
+      CD_TRY(hipMemcpyAsync(c->ck, c->rec[0], rec_bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
     while (launched < limit && !hp->done) {
       if (launched - hp->decided >= kLookahead) {
         // wait for the device; give up (CD_EHIP) if it stops making progress
@@ -780,6 +800,13 @@ int solve_single(cd_ctx* c) {
                              closes ? c->sweep_ev[2 * m + 1] : nullptr));
       if (closes) groups_closed = m + 1;
       launched = j;
+      if (record && j % c->adj_every == 0)
+        CD_TRY(hipMemcpyAsync(c->ck + (j / c->adj_every) * c->ck_stride, c->rec[j & 1], rec_bytes,
+                              hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (record) {
+      c->adj_K = launched;
+      c->adj_valid = true;
     }
     // the decision of the last launched sweep, if the solve is still open
     CD_TRY(cd_launch_decide(c, launched));
@@ -897,9 +924,39 @@ int finish_complete(cd_ctx* c, cd_result* out) {
 
 extern "C" {
 
+int cd_prepare(cd_ctx* c) { return step_prepare(c); }
+
+int cd_set_contact_mu(cd_ctx* c, const double* mu) {
+  if (!c || (!mu && c->nc > 0)) return CD_EINVAL;
+  if (!c->prepared) return fail(c, CD_ENOTREADY, "cd_set_contact_mu needs cd_prepare first");
+  if (c->cap > c->mu_slot_cap) {
+    CD_TRY(grow(&c->mu_slot, c->cap));
+    c->mu_slot_cap = c->cap;
+  }
+  CD_TRY(cd_launch_mu_scatter(c, mu));
+  c->use_mu_slot = true;
+  return CD_OK;
+}
+
+int cd_solve(cd_ctx* c, cd_result* out) {
+  if (!c) return CD_EINVAL;
+  if (!c->prepared) return fail(c, CD_ENOTREADY, "cd_solve needs cd_prepare first");
+  c->prepared = false;
+  int st = solve_single(c);
+  if (st != CD_OK) return st;
+  return step_finish(c, out);
+}
+
+int cd_set_adjoint(cd_ctx* c, int checkpoint_every) {
+  if (!c || checkpoint_every < 0) return CD_EINVAL;
+  c->adj_every = checkpoint_every;
+  return CD_OK;
+}
+
 int cd_step(cd_ctx* c, cd_result* out) {
   int st = step_prepare(c);
   if (st != CD_OK) return st;
+  c->prepared = false;
   st = solve_single(c);
   if (st != CD_OK) return st;
   return step_finish(c, out);

@@ -106,6 +106,7 @@ struct SweepArgs {
   const double* walls_u;    // W x dim wall velocities
   int n_walls;
   double* rec[2];
+  const double* mu_slot;    // per-slot friction coefficients, or null: mu for all
   // convergence
   SolveState* state;
   BlockPartial* partial;
@@ -181,6 +182,17 @@ struct cd_ctx {
   int64_t cap_list = 0, cap_prev = 0, nc_prev = 0;
   int *ci_prev = nullptr, *cj_prev = nullptr;
   double* R_prev = nullptr;
+  double* mu_slot = nullptr;     // per-slot friction of the prepared list (cap)
+  int64_t mu_slot_cap = 0;
+  bool use_mu_slot = false;      // set by cd_set_contact_mu for the coming solve
+  bool prepared = false;         // a step has been prepared and not yet solved
+  // adjoint: force checkpoints of the last recorded solve
+  int adj_every = 0;             // checkpoint interval in sweeps (0: no recording)
+  int adj_K = 0;                 // sweeps of the recorded solve
+  bool adj_valid = false;        // the slot data of that solve are still in place
+  double* ck = nullptr;          // checkpoints, ck_stride doubles each
+  int64_t ck_cap = 0, ck_stride = 0;
+  struct AdjointWork* adj = nullptr;  // reverse-pass workspace (adjoint.hip)
 
   // tree (host shape + device arrays)
   int P = 1;
@@ -310,12 +322,18 @@ hipError_t cd_launch_solve_init(cd_ctx* c, int limit);
 // sweep j; its extra workgroup takes the stop decision of sweep j-1
 hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after);
 hipError_t cd_launch_decide(cd_ctx* c, int jd);            // stop decision of sweep jd alone
+// sweep j with explicit arguments and only the domain workgroups (no decision)
+hipError_t cd_launch_sweep_grid(cd_ctx* c, const SweepArgs& a, int j, int grid);
 // batched solve over the packings of tab (device array of their arguments)
 hipError_t cd_launch_sweep_batch(hipStream_t stream, int dim, const SweepArgs* tab, const int* blk,
                                  int grid, int block, size_t lds, int j, BatchProg* bp);
 hipError_t cd_launch_decide_batch(hipStream_t stream, const SweepArgs* tab, int B, int jd,
                                   BatchProg* bp);
 hipError_t cd_launch_gather_states(hipStream_t stream, const SweepArgs* tab, int B, SolveState* out);
+// canonical per-contact friction into slot order (c->mu_slot)
+hipError_t cd_launch_mu_scatter(cd_ctx* c, const double* mu);
+// adjoint.hip
+void cd_adjoint_release(cd_ctx* c);
 hipError_t cd_launch_unslot(cd_ctx* c, int final_iter);
 int cd_solve_grid(cd_ctx* c);                               // co-resident grid, 0 if none
 

@@ -26,425 +26,9 @@
 // dispatched round-robin over them) works on a contiguous run of domains,
 // which are spatial neighbours in the bisection tree and share halo data in
 // that XCD's L2.
-#include "cd_internal.h"
+#include "sweep_core.h"
 
 namespace {
-
-template <int DIM>
-struct Layout {
-  static constexpr int DR = DIM == 2 ? 1 : 3;
-  static constexpr int REC = DIM == 2 ? 4 : 12;
-  static constexpr int NG = DIM == 2 ? 2 : 9;      // frame doubles per slot
-  // staged particle record (doubles): V [0, DIM), W [DIM, DIM+DR), dt/m, dt/I,
-  // r, padded to an even count so that pairs load as 16-byte words
-  static constexpr int PS = cd_stage_particle(DIM);
-  static constexpr int P_W = DIM, P_DM = DIM + DR, P_DI = DIM + DR + 1, P_R = DIM + DR + 2;
-  static_assert(P_R < PS && PS % 2 == 0, "particle staging layout");
-};
-
-// The single-contact law (Eqs. 3-9, Fig. 2) for the contact's frame n, t1,
-// t2 and the body velocities; dwR = (dt w_n R_n, dt w_t R_t1, dt w_t R_t2) of
-// the contact's current force removes that force's own share of the relative
-// velocity.  Writes the new frame force.
-template <int DIM>
-__device__ inline void local_force(const double* n, const double* t1, const double* t2, double gdt,
-                                   const double* dwR, double kn, double kt, double mu, double ra,
-                                   double rb, const double* Va, const double* Wa, const double* Vb,
-                                   const double* Wb, double* Rnew) {
-  double dV[3];
-  for (int q = 0; q < DIM; ++q) dV[q] = Vb[q] - Va[q];
-  double vn = 0.0;
-  for (int q = 0; q < DIM; ++q) vn = vn + dV[q] * n[q];
-  double vt1, vt2 = 0.0;
-  if (DIM == 2) {
-    double dvt = dV[0] * t1[0] + dV[1] * t1[1];
-    double spin = ra * Wa[0] + rb * Wb[0];
-    vt1 = dvt - spin;
-  } else {
-    double spin[3];
-    for (int q = 0; q < 3; ++q) spin[q] = ra * Wa[q] + rb * Wb[q];
-    double dvt1 = 0.0, dvt2 = 0.0, s2 = 0.0, s1 = 0.0;
-    for (int q = 0; q < 3; ++q) {
-      dvt1 = dvt1 + dV[q] * t1[q];
-      dvt2 = dvt2 + dV[q] * t2[q];
-      s2 = s2 + spin[q] * t2[q];
-      s1 = s1 + spin[q] * t1[q];
-    }
-    vt1 = dvt1 - s2;
-    vt2 = dvt2 + s1;
-  }
-  // relative velocity the pair would have without this contact's force
-  double un = vn - dwR[0];
-  double ut1 = vt1 - dwR[1];
-  double ut2 = DIM == 3 ? vt2 - dwR[DIM - 1] : 0.0;
-  double s = gdt + un;      // predicted gap / dt (Eq. 3)
-  Rnew[0] = 0.0;
-  Rnew[1] = 0.0;
-  if (DIM == 3) Rnew[2] = 0.0;
-  if (s >= 0.0) return;     // stays open
-  double rn = -s * kn;      // sticking force, normal part (Eqs. 4-5)
-  double T1 = -ut1 * kt;
-  double T2 = DIM == 3 ? -ut2 * kt : 0.0;
-  double lim = mu * rn;     // Coulomb bound (Eq. 7)
-  Rnew[0] = rn;
-  if (DIM == 2) {
-    if (fabs(T1) <= lim) Rnew[1] = T1;
-    else Rnew[1] = T1 > 0.0 ? lim : -lim;   // sliding (Eqs. 8-9)
-  } else {
-    double tn = sqrt(T1 * T1 + T2 * T2);
-    if (tn <= lim) {
-      Rnew[1] = T1;
-      Rnew[2] = T2;
-    } else {
-      double fac = lim / tn;
-      Rnew[1] = T1 * fac;
-      Rnew[2] = T2 * fac;
-    }
-  }
-}
-
-constexpr int kMaxBlock = 256;
-
-// Workgroup barrier ordering LDS only: unlike __syncthreads it does not wait
-// for the wave's outstanding global loads and stores.
-__device__ inline void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// four doubles stored with one streaming (non-temporal) 32-byte store
-typedef double nt4 __attribute__((ext_vector_type(4)));
-
-// The domain of block b in pass k.  Block b runs on XCD x = b % 8
-// (round-robin dispatch); XCD x owns the contiguous domain range
-// [x per, (x+1) per) of the bisection order, so neighbouring domains share
-// that XCD's L2.  G8 blocks per XCD.  Returns -1 past the range.
-__device__ inline int domain_of(const SweepArgs& a, int b, int k, int G8) {
-  const int x = b % 8, i = b / 8;
-  const int local = i + k * G8;
-  if (local >= a.per_xcd) return -1;
-  const int d = x * a.per_xcd + local;
-  return d < a.P ? d : -1;
-}
-
-// Accumulate the previous sweep's contact forces on one particle entry, in
-// ascending contact id: acc -= F (body 1) or += F (body 2), tacc -= r q.
-template <int DIM>
-__device__ inline void add_record(const double* rin, int ent, double rp, double* acc,
-                                  double* tacc) {
-  constexpr int REC = DIM == 2 ? 4 : 12;
-  const double* rc = rin + (int64_t)(ent >> 1) * REC;
-  if (DIM == 2) {
-    const double4 r4 = *(const double4*)rc;
-    acc[0] = (ent & 1) ? acc[0] + r4.z : acc[0] - r4.z;
-    acc[1] = (ent & 1) ? acc[1] + r4.w : acc[1] - r4.w;
-    tacc[0] = tacc[0] - rp * r4.y;
-  } else {
-    const double4 f4 = *(const double4*)(rc + 4), q4 = *(const double4*)(rc + 8);
-    const double F[3] = {f4.x, f4.y, f4.z}, Q[3] = {q4.x, q4.y, q4.z};
-    for (int k = 0; k < 3; ++k) acc[k] = (ent & 1) ? acc[k] + F[k] : acc[k] - F[k];
-    for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * Q[k];
-  }
-}
-
-template <int DIM>
-__device__ inline void gather_forces(const SweepArgs& a, const double* rin, int64_t e, double rp,
-                                     double* acc, double* tacc) {
-  constexpr int REC = DIM == 2 ? 4 : 12;
-  constexpr int KW = DIM == 2 ? 8 : 16;
-  // incidence rows: KW/4 planes of int4 (plane q: entries 4q..4q+3)
-  const int4* rows = (const int4*)a.drow;
-  const int64_t E = a.dpe;
-  int4 r4i = rows[e];
-  if (r4i.x == -2) {
-    // more incidences than a row holds: the pointer list
-    const int e1 = a.dinc_ptr[e + 1];
-    for (int x = a.dinc_ptr[e]; x < e1; ++x) add_record<DIM>(rin, a.dinc[x], rp, acc, tacc);
-    return;
-  }
-  // valid entries come first; the next plane is read only after a full one
-  for (int q = 0; q < KW / 4; ++q) {
-    const int ent[4] = {r4i.x, r4i.y, r4i.z, r4i.w};
-    if (DIM == 2) {
-      double4 rec[4];
-      for (int u = 0; u < 4; ++u)
-        if (ent[u] >= 0) rec[u] = *(const double4*)(rin + (int64_t)(ent[u] >> 1) * REC);
-      for (int u = 0; u < 4; ++u) {
-        if (ent[u] < 0) break;
-        acc[0] = (ent[u] & 1) ? acc[0] + rec[u].z : acc[0] - rec[u].z;
-        acc[1] = (ent[u] & 1) ? acc[1] + rec[u].w : acc[1] - rec[u].w;
-        tacc[0] = tacc[0] - rp * rec[u].y;
-      }
-    } else {
-      double4 fq[4][2];
-      for (int u = 0; u < 4; ++u)
-        if (ent[u] >= 0) {
-          const double* rc = rin + (int64_t)(ent[u] >> 1) * REC;
-          fq[u][0] = *(const double4*)(rc + 4);
-          fq[u][1] = *(const double4*)(rc + 8);
-        }
-      for (int u = 0; u < 4; ++u) {
-        if (ent[u] < 0) break;
-        const double F[3] = {fq[u][0].x, fq[u][0].y, fq[u][0].z};
-        const double Q[3] = {fq[u][1].x, fq[u][1].y, fq[u][1].z};
-        for (int k = 0; k < 3; ++k) acc[k] = (ent[u] & 1) ? acc[k] + F[k] : acc[k] - F[k];
-        for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * Q[k];
-      }
-    }
-    if (ent[3] < 0 || q + 1 == KW / 4) break;
-    r4i = rows[(q + 1) * E + e];
-  }
-}
-
-// Static data of one contact, read from memory into registers: body pair,
-// frame, g_e/dt, dt w_n, dt w_t, their reciprocals and the previous force.
-template <int DIM>
-struct SlotPre {
-  int2 ab;
-  double f[Layout<DIM>::NG];
-  double gdt, dwn, dwt, kn, kt;
-  double Ro[DIM];
-};
-
-template <int DIM>
-__device__ inline void fetch_slot(const SweepArgs& a, const double* rin, int64_t s, SlotPre<DIM>& o) {
-  constexpr int NG = Layout<DIM>::NG, REC = Layout<DIM>::REC;
-  const int64_t cap = a.cap;
-  const double* g = a.geo;
-  o.ab = a.ab[s];
-  for (int q = 0; q < NG; ++q) o.f[q] = g[q * cap + s];
-  o.gdt = g[G_GDT * cap + s];
-  o.dwn = g[G_DWN * cap + s];
-  o.dwt = g[G_DWT * cap + s];
-  o.kn = g[G_KN * cap + s];
-  o.kt = g[G_KT * cap + s];
-  const double* ri = rin + s * REC;
-  if (DIM == 2) {
-    const double2 r2 = *(const double2*)ri;
-    o.Ro[0] = r2.x;
-    o.Ro[1] = r2.y;
-  } else {
-    for (int q = 0; q < DIM; ++q) o.Ro[q] = ri[q];
-  }
-}
-
-// A body's staged record: velocities, dt/m, dt/I, r.
-template <int DIM>
-struct Body {
-  double V[3], W[3], dm, di, r;
-};
-
-template <int DIM>
-__device__ inline void read_body(const double* sp, int l, Body<DIM>& b) {
-  const double2* p = (const double2*)(sp + (int64_t)Layout<DIM>::PS * l);
-  if (DIM == 2) {
-    const double2 x0 = p[0], x1 = p[1], x2 = p[2];
-    b.V[0] = x0.x;
-    b.V[1] = x0.y;
-    b.W[0] = x1.x;
-    b.dm = x1.y;
-    b.di = x2.x;
-    b.r = x2.y;
-    b.V[2] = b.W[1] = b.W[2] = 0.0;
-  } else {
-    const double2 x0 = p[0], x1 = p[1], x2 = p[2], x3 = p[3], x4 = p[4];
-    b.V[0] = x0.x;
-    b.V[1] = x0.y;
-    b.V[2] = x1.x;
-    b.W[0] = x1.y;
-    b.W[1] = x2.x;
-    b.W[2] = x2.y;
-    b.dm = x3.x;
-    b.di = x3.y;
-    b.r = x4.x;
-  }
-}
-
-template <int DIM>
-__device__ inline void write_velocities(double* sp, int l, const double* V, const double* W) {
-  double2* p = (double2*)(sp + (int64_t)Layout<DIM>::PS * l);
-  if (DIM == 2) {
-    p[0] = make_double2(V[0], V[1]);
-    sp[(int64_t)Layout<DIM>::PS * l + 2] = W[0];
-  } else {
-    p[0] = make_double2(V[0], V[1]);
-    p[1] = make_double2(V[2], W[0]);
-    p[2] = make_double2(W[1], W[2]);
-  }
-}
-
-// Convergence test values of one contact (Sec. 2.1): |R_new - R_old|^2
-// against alpha |R_new + R_old|^2, and |R_new| for R_avg.
-template <int DIM>
-__device__ inline void account(const double* Rold, const double* Rn, double alpha,
-                               long long& npass, double& maxd, double& sumr) {
-  double d2 = 0.0, s2 = 0.0, qq = 0.0;
-  for (int q = 0; q < DIM; ++q) {
-    double a1 = Rn[q], a0 = Rold[q];
-    d2 = d2 + (a1 - a0) * (a1 - a0);
-    s2 = s2 + (a1 + a0) * (a1 + a0);
-    qq = qq + a1 * a1;
-  }
-  sumr += sqrt(qq);
-  if (d2 < alpha * s2 || d2 == 0.0) npass += 1;
-  else if (d2 > maxd || d2 != d2) maxd = d2;
-}
-
-// The force law for one contact with the current velocities of its bodies
-// (staged particle records at sp; body 2 < 0 is wall -1-b with velocity
-// wu), the change applied to both bodies, the new record written to `ro`,
-// and the contact's test values accounted.
-template <int DIM>
-__device__ inline void update_contact(double* sp, const double* wu, const SlotPre<DIM>& c,
-                                      double mu, double alpha, double* ro, long long& npass,
-                                      double& maxd, double& sumr) {
-  constexpr int DR = Layout<DIM>::DR;
-  const int la = c.ab.x, lb = c.ab.y;
-  Body<DIM> A, B;
-  read_body<DIM>(sp, la, A);
-  if (lb >= 0) {
-    read_body<DIM>(sp, lb, B);
-  } else {
-    for (int q = 0; q < 3; ++q) B.V[q] = B.W[q] = 0.0;
-    for (int q = 0; q < DIM; ++q) B.V[q] = wu[(-1 - lb) * DIM + q];
-    B.dm = B.di = B.r = 0.0;
-  }
-  double nv[3] = {0.0, 0.0, 0.0}, t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
-  for (int q = 0; q < DIM; ++q) nv[q] = c.f[q];
-  if (DIM == 2) {
-    t1[0] = -nv[1];
-    t1[1] = nv[0];
-  } else {
-    for (int q = 0; q < 3; ++q) {
-      t1[q] = c.f[3 + q];
-      t2[q] = c.f[6 + q];
-    }
-  }
-  double Rold[3] = {0.0, 0.0, 0.0}, dwR[3] = {0.0, 0.0, 0.0};
-  for (int q = 0; q < DIM; ++q) Rold[q] = c.Ro[q];
-  dwR[0] = c.dwn * Rold[0];
-  for (int q = 1; q < DIM; ++q) dwR[q] = c.dwt * Rold[q];
-  double Rn[3] = {0.0, 0.0, 0.0};
-  local_force<DIM>(nv, t1, t2, c.gdt, dwR, c.kn, c.kt, mu, A.r, B.r, A.V, A.W, B.V, B.W, Rn);
-  const double dRn = Rn[0] - Rold[0], dR1 = Rn[1] - Rold[1];
-  const double dR2 = DIM == 3 ? Rn[2] - Rold[2] : 0.0;
-  double dF[3], dq[3];
-  for (int q = 0; q < DIM; ++q) {
-    dF[q] = dRn * nv[q] + dR1 * t1[q];
-    if (DIM == 3) dF[q] = dF[q] + dR2 * t2[q];
-  }
-  if (DIM == 2) {
-    dq[0] = dR1;
-  } else {
-    for (int q = 0; q < 3; ++q) dq[q] = dR1 * t2[q] - dR2 * t1[q];
-  }
-  double Va[3], Wa[3];
-  for (int q = 0; q < DIM; ++q) Va[q] = A.V[q] - A.dm * dF[q];
-  for (int q = 0; q < DR; ++q) Wa[q] = A.W[q] - A.di * (A.r * dq[q]);
-  write_velocities<DIM>(sp, la, Va, Wa);
-  if (lb >= 0) {
-    double Vb[3], Wb[3];
-    for (int q = 0; q < DIM; ++q) Vb[q] = B.V[q] + B.dm * dF[q];
-    for (int q = 0; q < DR; ++q) Wb[q] = B.W[q] - B.di * (B.r * dq[q]);
-    write_velocities<DIM>(sp, lb, Vb, Wb);
-  }
-  // new record: frame force, world force, torque per unit lever (streamed
-  // out: nothing in this launch reads it back)
-  if (DIM == 2) {
-    const nt4 v4 = {Rn[0], Rn[1], Rn[0] * nv[0] + Rn[1] * t1[0], Rn[0] * nv[1] + Rn[1] * t1[1]};
-    __builtin_nontemporal_store(v4, (nt4*)ro);
-  } else {
-    double F[3], Q[3];
-    for (int q = 0; q < 3; ++q) {
-      double fk = Rn[0] * nv[q] + Rn[1] * t1[q];
-      F[q] = fk + Rn[2] * t2[q];
-      Q[q] = Rn[1] * t2[q] - Rn[2] * t1[q];
-    }
-    const nt4 v0 = {Rn[0], Rn[1], Rn[2], 0.0}, v1 = {F[0], F[1], F[2], 0.0},
-              v2 = {Q[0], Q[1], Q[2], 0.0};
-    __builtin_nontemporal_store(v0, (nt4*)ro);
-    __builtin_nontemporal_store(v1, (nt4*)(ro + 4));
-    __builtin_nontemporal_store(v2, (nt4*)(ro + 8));
-  }
-  account<DIM>(Rold, Rn, alpha, npass, maxd, sumr);
-}
-
-// One sweep of domain d by the calling workgroup: exchange, then the
-// colour-major update; accumulates the convergence test values of its
-// contacts.  GLOB: the particle records live in global scratch (domains
-// too large for LDS).
-template <int DIM, bool GLOB>
-__device__ inline void sweep_domain(const SweepArgs& a, int d, const double* rin, double* rout,
-                                    double* lds, int* s_co, double* s_wu, long long& npass,
-                                    double& maxd, double& sumr) {
-  using L = Layout<DIM>;
-  constexpr int DR = L::DR, REC = L::REC, PS = L::PS;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int* dd = a.ddesc + 8 * (int64_t)d;
-  // descriptor: first slot, slots, first particle entry, entries, colours
-  const int cs = dd[0], ps = dd[2], np = dd[3], ncol = dd[4];
-  double* sp = GLOB ? a.gscr + (int64_t)PS * ps : lds;
-  const int* dcol = a.dcol + (int64_t)d * (CD_MAX_COLORS + 1);
-  // 0. colour offsets and wall velocities to LDS; this thread's contact of
-  //    the first colour read ahead (its latency overlaps the exchange)
-  for (int q = tid; q <= ncol; q += nthr) s_co[q] = dcol[q];
-  for (int q = tid; q < a.n_walls * DIM; q += nthr) s_wu[q] = a.walls_u[q];
-  SlotPre<DIM> cur;
-  int kc = -1;
-  if (ncol > 0 && tid < dcol[1]) {
-    kc = tid;
-    fetch_slot<DIM>(a, rin, cs + kc, cur);
-  }
-  // 1. exchange: velocities from the previous sweep's forces
-  const int64_t E = a.dpe;
-  for (int l = tid; l < np; l += nthr) {
-    const int64_t e = ps + l;
-    double acc[DIM], tacc[DR];
-    int q = DIM + DR;
-    for (int k = 0; k < DIM; ++k) acc[k] = a.dpb[(q + k) * E + e];
-    q += DIM;
-    for (int k = 0; k < DR; ++k) tacc[k] = a.dpb[(q + k) * E + e];
-    q += DR;
-    const double dm = a.dpb[q * E + e], di = a.dpb[(q + 1) * E + e];
-    const double rp = a.dpb[(q + 2) * E + e];
-    gather_forces<DIM>(a, rin, e, rp, acc, tacc);
-    double* pr = sp + (int64_t)PS * l;
-    for (int k = 0; k < DIM; ++k) pr[k] = a.dpb[k * E + e] + dm * acc[k];
-    for (int k = 0; k < DR; ++k) pr[L::P_W + k] = a.dpb[(DIM + k) * E + e] + di * tacc[k];
-    pr[L::P_DM] = dm;
-    pr[L::P_DI] = di;
-    pr[L::P_R] = rp;
-  }
-  __syncthreads();
-  // 2. colour-major sequential update
-  for (int col = 0; col < ncol; ++col) {
-    const int k0 = s_co[col], k1 = s_co[col + 1];
-    // the next colour's contact of this thread, read ahead
-    SlotPre<DIM> nxt;
-    int kn = -1;
-    if (col + 1 < ncol && s_co[col + 1] + tid < s_co[col + 2]) {
-      kn = s_co[col + 1] + tid;
-      fetch_slot<DIM>(a, rin, cs + kn, nxt);
-    }
-    if (kc >= 0)
-      update_contact<DIM>(sp, s_wu, cur, a.mu, a.alpha, rout + (int64_t)(cs + kc) * REC, npass,
-                          maxd, sumr);
-    // colours wider than the workgroup
-    for (int k = k0 + tid + nthr; k < k1; k += nthr) {
-      SlotPre<DIM> sd;
-      fetch_slot<DIM>(a, rin, cs + k, sd);
-      update_contact<DIM>(sp, s_wu, sd, a.mu, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
-                          maxd, sumr);
-    }
-    // the colour's velocity updates must be seen by the next colour; the
-    // record stores and the read-ahead loads stay in flight
-    if (GLOB) __syncthreads();
-    else lds_barrier();
-    if (kn >= 0) cur = nxt;
-    kc = kn;
-  }
-}
 
 struct BlockRed {
   long long np[kMaxBlock / 64];
@@ -833,6 +417,7 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.n_walls = c->W;
   a.rec[0] = c->rec[0];
   a.rec[1] = c->rec[1];
+  a.mu_slot = c->use_mu_slot ? c->mu_slot : nullptr;
   a.state = c->d_state;
   a.partial = c->partial;
   a.prog = c->d_prog;
@@ -909,6 +494,22 @@ hipError_t cd_launch_decide_batch(hipStream_t stream, const SweepArgs* tab, int 
 hipError_t cd_launch_gather_states(hipStream_t stream, const SweepArgs* tab, int B, SolveState* out) {
   if (B < 1) return hipSuccess;
   hipLaunchKernelGGL(k_gather_states, dim3((B + 63) / 64), dim3(64), 0, stream, tab, B, out);
+  return hipGetLastError();
+}
+
+hipError_t cd_launch_sweep_grid(cd_ctx* c, const SweepArgs& a, int j, int grid) {
+  dim3 g(grid), block(c->sweep_block);
+  if (c->dim == 2) {
+    if (c->sweep_global)
+      hipLaunchKernelGGL((k_sweep<2, true>), g, block, 0, c->stream, a, j);
+    else
+      hipLaunchKernelGGL((k_sweep<2, false>), g, block, block_lds(c), c->stream, a, j);
+  } else {
+    if (c->sweep_global)
+      hipLaunchKernelGGL((k_sweep<3, true>), g, block, 0, c->stream, a, j);
+    else
+      hipLaunchKernelGGL((k_sweep<3, false>), g, block, block_lds(c), c->stream, a, j);
+  }
   return hipGetLastError();
 }
 

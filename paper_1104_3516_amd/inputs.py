@@ -164,6 +164,26 @@ def uneven_batch(count: int, seed: int = 3, n_lo: int = 256, n_hi: int = 65536,
     return packs, mus
 
 
+def _splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 (Steele, Lea, Flood 2014) on uint64 arrays."""
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def pair_mu(seed: int, ci: np.ndarray, cj: np.ndarray, lo: float = 0.2, hi: float = 0.4):
+    """Friction coefficient of each contact pair (i, j), uniform in [lo, hi),
+    from a stateless hash of (seed, i, j): the same pair gets the same value
+    whatever list it appears in."""
+    ci = np.asarray(ci, dtype=np.uint64)
+    cj = np.asarray(cj, dtype=np.uint64)
+    h = _splitmix64(_splitmix64(_splitmix64(np.full(ci.shape, seed, dtype=np.uint64)) ^ ci) ^ cj)
+    u = (h >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return lo + (hi - lo) * u
+
+
 def chain_2d(n: int, force: float, radius: float = 1.0) -> Packing:
     """n touching equal disks on the x axis between two walls; the first disk
     is pushed with `force` towards the fixed wall at the far end (Fig. 13a

@@ -1,0 +1,146 @@
+"""Adjoint of the fixed-count solve (cd_adjoint): against the autograd
+reference (oracle/torch_ref.py) on small packings, and against central
+differences of the HIP forward at the 65k-disk size."""
+import numpy as np
+import pytest
+
+from paper_1104_3516_amd import inputs
+from tests.test_gpu_parity import _torch
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_case(pk, P, K, every, mu_seed=7, block=0):
+    from paper_1104_3516_amd import binding
+    torch = _torch()
+    skin = 0.2 * pk.r.max()
+    ctx = binding.Context(binding.make_params(2, pk.n_walls, fixed_iters=K, n_domains=P,
+                                              skin=skin), pk, timing=0, block_threads=block)
+    ctx.set_adjoint(every)
+    ctx.prepare()
+    c = {k: v.cpu().numpy() for k, v in ctx.contacts().items()}
+    mu = torch.as_tensor(inputs.pair_mu(mu_seed, c["ci"], c["cj"]), device="cuda")
+    return ctx, c, mu
+
+
+def bottom_seed(torch, c, n, nc):
+    g = torch.zeros((2, nc), dtype=torch.float64, device="cuda")
+    g[0, torch.as_tensor(c["cj"] == n + 2, device="cuda")] = 1.0
+    return g
+
+
+@pytest.mark.parametrize("P,K,every", [(4, 20, 6), (1, 9, 4), (7, 13, 13)])
+def test_adjoint_matches_autograd_reference(P, K, every):
+    import torch
+    from oracle import torch_ref
+    pk = inputs.lattice_2d(12, 10, 41)
+    ctx, c, mu = gpu_case(pk, P, K, every)
+    ctx.set_contact_mu(mu)
+    res = ctx.solve()
+    assert res.iterations == K
+    R_gpu = ctx.contacts()["R"].cpu().numpy()
+    nc = R_gpu.shape[1]
+    seed = bottom_seed(torch, c, pk.n, nc)
+    dmu, dv, dw = (t.cpu().numpy() for t in ctx.adjoint(seed))
+    pb = torch_ref.setup(pk, P, 0.2 * pk.r.max())
+    np.testing.assert_array_equal(pb.ci, c["ci"])
+    np.testing.assert_array_equal(pb.cj, c["cj"])
+    mu_t = torch.as_tensor(mu.cpu().numpy()).requires_grad_(True)
+    v_t = torch.as_tensor(pk.v).requires_grad_(True)
+    w_t = torch.as_tensor(pk.w).requires_grad_(True)
+    R_ref = torch_ref.forces(pb, pk, mu_t, v_t, w_t, K)
+    assert np.abs(R_ref.detach().numpy() - R_gpu).max() <= 1e-12 * np.abs(R_gpu).max()
+    L = R_ref[0][torch.as_tensor(pb.cj == pk.n + 2)].sum()
+    gm, gv, gw = (t.numpy() for t in torch.autograd.grad(L, [mu_t, v_t, w_t]))
+    for name, a, b in (("mu", dmu, gm), ("v", dv, gv), ("w", dw, gw)):
+        err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+        print(f"[adjoint P={P} K={K} every={every}] d/d{name}: max rel {err:.2e}, "
+              f"|grad| {np.abs(b).max():.3e}", flush=True)
+        assert err <= 1e-10
+    assert np.abs(gm).max() > 0 and np.abs(gv).max() > 0
+
+
+def test_autograd_function_end_to_end():
+    """binding.contact_forces inside a torch graph: loss.backward() gives the
+    adjoint's gradients, and the forward can be evaluated again."""
+    from paper_1104_3516_amd import binding
+    torch = _torch()
+    pk = inputs.lattice_2d(16, 12, 43)
+    ctx, c, mu = gpu_case(pk, 5, 15, 5)
+    v = torch.as_tensor(pk.v, device="cuda").requires_grad_(True)
+    w = torch.as_tensor(pk.w, device="cuda").requires_grad_(True)
+    mu = mu.clone().requires_grad_(True)
+    bottom = torch.as_tensor(c["cj"] == pk.n + 2, device="cuda")
+    R = binding.contact_forces(mu, v, w, ctx)
+    loss = (R[0] * bottom).sum()
+    loss.backward()
+    seed = bottom_seed(torch, c, pk.n, R.shape[1])
+    R2 = binding.contact_forces(mu.detach(), v.detach(), w.detach(), ctx)
+    assert torch.equal(R, R2)
+    dmu, dv, dw = ctx.adjoint(seed)
+    assert torch.equal(mu.grad, dmu) and torch.equal(v.grad, dv) and torch.equal(w.grad, dw)
+
+
+def test_adjoint_central_differences_65k():
+    """256x256 disks, 256 domains, 200 sweeps, checkpoints every 10 sweeps,
+    friction per pair in [0.2, 0.4]: dL/d(mu, v, w) along 64 random
+    directions against central differences (h = 1e-6) of the HIP forward.
+    Directions whose contact states (open / stick / slide after the last
+    sweep) change at +-h cross a kink and are counted apart."""
+    import time
+    torch = _torch()
+    pk = inputs.config("disks_65k")
+    ctx, c, mu = gpu_case(pk, 256, 200, 10)
+    nc = len(c["ci"])
+    bottom = torch.as_tensor(c["cj"] == pk.n + 2, device="cuda")
+    v0 = torch.as_tensor(pk.v, device="cuda")
+    w0 = torch.as_tensor(pk.w, device="cuda")
+
+    def run(m, v, w):
+        ctx.reset(v, w)
+        ctx.prepare()
+        ctx.set_contact_mu(m)
+        ctx.solve()
+        R = ctx.contacts()["R"]
+        lim = (m * R[0]).abs()
+        state = torch.where(R[0] == 0, 0, torch.where(torch.isclose(R[1].abs(), lim, rtol=1e-13,
+                                                                    atol=0.0), 2, 1))
+        return float((R[0] * bottom).sum()), state
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L0, s0 = run(mu, v0, w0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    seed = torch.zeros((2, nc), dtype=torch.float64, device="cuda")
+    seed[0] = bottom.double()
+    dmu, dv, dw = ctx.adjoint(seed)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(f"[adjoint 65k] nc={nc} loss={L0:.6e} primal {1e3 * (t1 - t0):.1f} ms, "
+          f"adjoint {1e3 * (t2 - t1):.1f} ms", flush=True)
+    gen = torch.Generator(device="cuda").manual_seed(4004)
+    h = 1e-6
+    ok = kinks = bad = 0
+    worst = 0.0
+    for _ in range(64):
+        dm = torch.randn(nc, generator=gen, device="cuda", dtype=torch.float64) * 0.1
+        ddv = torch.randn(v0.shape, generator=gen, device="cuda", dtype=torch.float64) * 0.01
+        ddw = torch.randn(w0.shape, generator=gen, device="cuda", dtype=torch.float64) * 0.01
+        lp, sp = run(mu + h * dm, v0 + h * ddv, w0 + h * ddw)
+        lm, sm = run(mu - h * dm, v0 - h * ddv, w0 - h * ddw)
+        fd = (lp - lm) / (2 * h)
+        an = float((dmu * dm).sum() + (dv * ddv).sum() + (dw * ddw).sum())
+        if not (torch.equal(sp, s0) and torch.equal(sm, s0)):
+            kinks += 1
+            continue
+        err = abs(fd - an) / max(abs(an), 1e-300)
+        worst = max(worst, err)
+        if err <= 1e-5:
+            ok += 1
+        else:
+            bad += 1
+            print(f"  direction off: fd={fd:.9e} adjoint={an:.9e} rel={err:.2e}", flush=True)
+    print(f"[adjoint 65k FD] agree {ok}, kink-crossing {kinks}, disagree {bad}, "
+          f"worst rel err {worst:.2e}", flush=True)
+    assert bad == 0 and ok >= 16
