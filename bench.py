@@ -66,6 +66,14 @@ WORKLOADS = {
               "log-uniform in [256, 65536] (sum 5,580,310), mu uniform in [0.1, 0.6] per "
               "packing, autotuned contacts per domain, repartition every 10 steps, alpha=1e-6 "
               "local test, max 2000 sweeps, one sweep launch over all packings per sweep")),
+    "adjoint65k": dict(
+        config="disks_65k", dim=2, mu=None, domains=256, steps=20, cpu_sweeps=0,
+        traffic="sweep_adjoint65k_traffic.json", sweeps=200, every=10,
+        text=("adjoint65k: 2D disks N=65536 (256x256 jittered triangular lattice), friction per "
+              "pair uniform in [0.2, 0.4] (hash of the pair), 256 domains, contact list of gap <= "
+              "0.2 r_max, exactly 200 sweeps, checkpoints every 10 sweeps; each timed step is one "
+              "time step from the initial state followed by its adjoint (dL/dmu, dL/dv, dL/dw of "
+              "the bottom-wall normal forces)")),
 }
 
 
@@ -81,7 +89,7 @@ def measured_traffic(path):
         return None
     rec = json.load(open(path))
     h = hashlib.sha256()
-    for f in ("sweep.hip", "cd_internal.h"):
+    for f in ("sweep.hip", "sweep_core.h", "cd_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1104_3516_amd", "csrc", f), "rb").read())
     return rec.get("bytes_per_launch") if rec.get("kernel_sources_sha256") == h.hexdigest() else None
 
@@ -213,6 +221,57 @@ def cpu_baseline(wl, pk, sweeps: int) -> dict:
                        f"partition, {dt:.1f} s single-threaded")}
 
 
+def run_adjoint(args, wl, torch, binding, inputs) -> dict:
+    """Primal step (200 sweeps) and its adjoint, timed separately."""
+    pk = inputs.config(wl["config"])
+    skin = 0.2 * pk.r.max()
+    ctx = binding.Context(binding.make_params(2, pk.n_walls, fixed_iters=wl["sweeps"],
+                                              n_domains=wl["domains"], skin=skin), pk,
+                          timing=args.time_every)
+    ctx.set_adjoint(wl["every"])
+    ctx.prepare()
+    c = {k: v.cpu().numpy() for k, v in ctx.contacts().items()}
+    mu = torch.as_tensor(inputs.pair_mu(1004, c["ci"], c["cj"]), device="cuda")
+    nc = len(c["ci"])
+    seed = torch.zeros((2, nc), dtype=torch.float64, device="cuda")
+    seed[0] = torch.as_tensor(c["cj"] == pk.n + 2, device="cuda").double()
+
+    def primal():
+        ctx.reset()
+        ctx.prepare()
+        ctx.set_contact_mu(mu)
+        return ctx.solve()
+
+    for _ in range(max(args.warmup, 1)):
+        primal()
+        ctx.adjoint(seed)
+    torch.cuda.synchronize()
+    t_primal = t_adj = 0.0
+    kernel_ms = 0.0
+    executed = 0
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        r = primal()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.adjoint(seed)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_primal += t1 - t0
+        t_adj += t2 - t1
+        tm = ctx.timing()
+        kernel_ms += tm.sweep_kernel_ms
+        executed += tm.sweeps_executed
+    updates = args.steps * wl["sweeps"] * nc
+    avg = (kernel_ms / 1e3) / max(executed, 1)
+    bps = BYTES[2][0] * nc + BYTES[2][1] * pk.n
+    achieved = bps / avg / 1e9 if avg > 0 else None
+    return {"value": updates / t_primal, "primal_ms": 1e3 * t_primal / args.steps,
+            "adjoint_ms": 1e3 * t_adj / args.steps, "adjoint_over_primal": t_adj / t_primal,
+            "n_contacts": nc, "n_particles": pk.n, "sweep_kernel_us": 1e6 * avg if avg > 0 else None,
+            "achieved": achieved, "bytes_per_sweep": bps, "sweeps": wl["sweeps"]}
+
+
 def cpu_baseline_batch(packs, mus, target, sweeps: int) -> dict:
     """The oracle, single-threaded, on the first step of the first packings of
     the batch (about 20 s of work), sweeps capped."""
@@ -288,6 +347,28 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 5}))
+        return 0
+    if args.workload == "adjoint65k":
+        ra = run_adjoint(args, wl, torch, binding, inputs)
+        traffic = measured_traffic(args.traffic_json)
+        out = {
+            "metric": METRIC, "value": ra["value"], "unit": "contact updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ra["primal_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": wl["text"], "n_particles": ra["n_particles"],
+                       "n_domains": wl["domains"], "time_steps": args.steps},
+            "adjoint_ms_per_step": ra["adjoint_ms"],
+            "adjoint_over_primal": ra["adjoint_over_primal"],
+            "n_contacts": ra["n_contacts"], "sweeps_per_step": ra["sweeps"],
+            "sweep_kernel_us": ra["sweep_kernel_us"],
+            "roofline": {"bound": "hbm", "achieved": ra["achieved"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s",
+                         "frac": ra["achieved"] / HBM_PEAK_GBS if ra["achieved"] else None,
+                         "traffic": traffic, "kernel": "k_sweep<2>",
+                         "bytes_per_sweep": ra["bytes_per_sweep"]},
+        }
+        print(json.dumps(out), flush=True)
         return 0
     if args.workload == "batch512":
         rb = run_batch(args, wl, torch, binding, inputs)
