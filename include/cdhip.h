@@ -208,11 +208,27 @@ int cd_solve(cd_ctx* ctx, cd_result* out);
  * sweeps, for cd_adjoint (2D).  0 (default): no recording. */
 int cd_set_adjoint(cd_ctx* ctx, int checkpoint_every);
 
-/* Reverse mode of the last recorded solve: given dL_dR (DEVICE, dim x n_c,
- * canonical order, frame components (R_n, R_t) of the forces after the last
- * sweep), writes dL_dmu (DEVICE, n_c: per contact friction), dL_dv (DEVICE,
- * dim x N) and dL_dw (DEVICE, N) of the velocities the step started from;
- * any output may be NULL.  The sweeps are differentiated exactly in the
+/* on != 0 (2D): the next step detects, partitions and orders as usual and
+ * every later step keeps that contact list, tree and colouring: it only
+ * recomputes normals and gaps at the new positions (Sec. 2.1, Fig. 1),
+ * starts from the previous step's forces and solves.  Contacts that would
+ * form meanwhile are not seen, so keep the window short against the skin.
+ * Per-contact friction set with cd_set_contact_mu stays in force over the
+ * kept steps.  With cd_set_adjoint active, all steps since the list was
+ * built form the window that cd_adjoint reverses (without a kept list the
+ * window is the last step).  on = 0 returns to per-step detection; a new
+ * cd_set_particles also rebuilds the list.  CD_EINVAL in 3D. */
+int cd_set_frozen_list(cd_ctx* ctx, int on);
+
+/* Reverse mode of the recorded window (the last step, or every step since
+ * the kept list was built, see cd_set_frozen_list): given dL_dR (DEVICE,
+ * dim x n_c, canonical order, frame components (R_n, R_t) of the forces
+ * after the last sweep of the last step), writes dL_dmu (DEVICE, n_c: per
+ * contact friction, summed over the window's steps), dL_dv (DEVICE, dim x N)
+ * and dL_dw (DEVICE, N) of the velocities the window's first step started
+ * from; any output may be NULL.  Over several steps the chain runs through
+ * each step's velocity and position update (Eqs. 1-2) and its normals and
+ * gaps; the forces the first step started from count as constants.  The sweeps are differentiated exactly in the
  * branch each contact took (open, stick, slide; Eqs. 3-9), segment by
  * segment from the checkpoints.  The slot data of the solve must still be in
  * place: call it before the next cd_prepare / cd_step.  CD_ENOTREADY without

@@ -102,6 +102,7 @@ def lib():
         L.cd_set_contact_mu.argtypes = [P, P]
         L.cd_solve.argtypes = [P, C.POINTER(Result)]
         L.cd_set_adjoint.argtypes = [P, C.c_int]
+        L.cd_set_frozen_list.argtypes = [P, C.c_int]
         L.cd_adjoint.argtypes = [P, P, P, P, P]
         L.cd_batch_create.argtypes = [C.POINTER(P), C.POINTER(P), C.c_int]
         L.cd_batch_destroy.argtypes = [P]
@@ -286,6 +287,11 @@ class Context:
 
     def set_adjoint(self, checkpoint_every: int):
         self._check(self.L.cd_set_adjoint(self.h, int(checkpoint_every)))
+
+    def set_frozen_list(self, on: bool = True):
+        """Keep the next step's contact list, tree and colouring for the
+        steps after it (geometry recomputed each step)."""
+        self._check(self.L.cd_set_frozen_list(self.h, int(bool(on))))
 
     def adjoint(self, dL_dR):
         """dL/dmu (n_c), dL/dv (dim x N), dL/dw (dr x N) of the last recorded solve."""

@@ -43,6 +43,12 @@ struct AdjointWork {
   int* p2e_cnt = nullptr;    // entries of each particle (CSR)
   int* p2e_ptr = nullptr;
   int* p2e = nullptr;
+  double* gn = nullptr;      // per slot: adjoint of the normal (2 x cap), this step
+  double* ggdt = nullptr;    // per slot: adjoint of g_e/dt, this step
+  double* gx = nullptr;      // per particle: adjoint of x^t (2 x N)
+  double* gv_next = nullptr; // adjoints of v, w of the following step (3 x N)
+  double* gx_next = nullptr; // adjoint of x of the following step (2 x N)
+  double* gvt = nullptr;     // adjoint of v^(t+1) in full (2 x N)
   SolveState* state = nullptr;  // "open" state for the recomputing sweeps
   int64_t cap = 0, n = 0, seg_cap = 0;
 };
@@ -139,11 +145,12 @@ __device__ inline void law_forward(double* sp, const double* wu, const SlotPre<2
 // Reverse of one contact update.  tape: the body velocities it saw (V_a,
 // W_a, V_b, W_b); gR: adjoint of its new force (R_n, R_t); ga, gb: adjoints
 // of the bodies' velocities after the update (V_x, V_y, W), replaced by
-// those before it; returns the adjoint of its old force and dL/dmu.
+// those before it; returns the adjoint of its old force, dL/dmu, and the
+// adjoints of its normal (gn) and of g_e/dt (ggdt).
 __device__ inline void law_reverse(const SlotPre<2>& c, const double* tape, double rA,
                                    double dmA, double diA, double rB, double dmB, double diB,
                                    bool wall, const double* gR, double* ga, double* gb,
-                                   double* gRold, double& gmu) {
+                                   double* gRold, double& gmu, double* gn, double& ggdt) {
   const double n0 = c.f[0], n1 = c.f[1], t0 = -c.f[1], t1 = c.f[0];
   const double Va0 = tape[0], Va1 = tape[1], Wa = tape[2];
   const double Vb0 = tape[3], Vb1 = tape[4], Wb = tape[5];
@@ -158,6 +165,22 @@ __device__ inline void law_reverse(const SlotPre<2>& c, const double* tape, doub
   const double un = vn - c.dwn * c.Ro[0];
   const double ut = vt - c.dwt * c.Ro[1];
   const double s = c.gdt + un;
+  double Rn = 0.0, Rt = 0.0, sg = 0.0;
+  bool stick = false;
+  if (s < 0.0) {
+    const double rn = -s * c.kn;
+    const double T = -ut * c.kt;
+    const double lim = c.mu * rn;
+    Rn = rn;
+    if (fabs(T) <= lim) {
+      stick = true;
+      Rt = T;
+    } else {
+      sg = T > 0.0 ? 1.0 : -1.0;
+      Rt = T > 0.0 ? lim : -lim;
+    }
+  }
+  const double dRn = Rn - c.Ro[0], dRt = Rt - c.Ro[1];
   // adjoint of the velocity updates (identity part kept in ga, gb)
   double gdF0 = -dmA * ga[0], gdF1 = -dmA * ga[1];
   double gdq = -diA * rA * ga[2];
@@ -168,28 +191,31 @@ __device__ inline void law_reverse(const SlotPre<2>& c, const double* tape, doub
   }
   const double gdRn = gdF0 * n0 + gdF1 * n1;
   const double gdRt = gdF0 * t0 + gdF1 * t1 + gdq;
-  double gRn = gR[0] + gdRn, gRt = gR[1] + gdRt;   // total adjoint of the new force
+  // dF = dR_n n + dR_t t with t = (-n_y, n_x)
+  gn[0] = dRn * gdF0 + dRt * gdF1;
+  gn[1] = -dRt * gdF0 + dRn * gdF1;
+  const double gRn = gR[0] + gdRn, gRt = gR[1] + gdRt;   // total adjoint of the new force
   gRold[0] = -gdRn;
   gRold[1] = -gdRt;
   gmu = 0.0;
   double gs = 0.0, gut = 0.0;
   if (s < 0.0) {
-    const double rn = -s * c.kn;
-    const double T = -ut * c.kt;
-    const double lim = c.mu * rn;
-    if (fabs(T) <= lim) {
-      gs = -c.kn * gRn;        // stick
+    if (stick) {
+      gs = -c.kn * gRn;        // R_n = -(g_e/dt + u_n)/(dt w_n), R_t = -u_t/(dt w_t)
       gut = -c.kt * gRt;
     } else {
-      const double sg = T > 0.0 ? 1.0 : -1.0;   // slide: R_t = sign(T) mu R_n
-      gmu = sg * rn * gRt;
+      gmu = sg * Rn * gRt;     // slide: R_t = sign(T) mu R_n
       gs = -c.kn * (gRn + sg * c.mu * gRt);
     }
   }
+  ggdt = gs;
   // u_n = v_n - dt w_n R_n,old ; u_t = v_t - dt w_t R_t,old
   gRold[0] = gRold[0] - c.dwn * gs;
   gRold[1] = gRold[1] - c.dwt * gut;
   const double gvn = gs, gvt = gut;
+  // v_n = dV.n, v_t = dV.t - spin
+  gn[0] = gn[0] + gvn * dV0 + gvt * dV1;
+  gn[1] = gn[1] + gvn * dV1 - gvt * dV0;
   const double gspin = -gvt;
   const double gdV0 = gvn * n0 + gvt * t0, gdV1 = gvn * n1 + gvt * t1;
   ga[0] = ga[0] - gdV0;
@@ -206,7 +232,9 @@ __device__ inline void law_reverse(const SlotPre<2>& c, const double* tape, doub
 __global__ __launch_bounds__(kMaxBlock) void k_sweep_adjoint(SweepArgs a, const double* rin,
                                                               const double* lam_in,
                                                               double* own_out, double* gE,
-                                                              double* gmu_slot, int np_max) {
+                                                              double* gmu_slot, double* gn_slot,
+                                                              double* ggdt_slot, int64_t cap,
+                                                              int np_max) {
   using L = Layout<2>;
   constexpr int PS = L::PS;
   extern __shared__ double lds[];
@@ -280,9 +308,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep_adjoint(SweepArgs a, const 
       if (!wall)
         for (int q = 0; q < 3; ++q) gb[q] = gp[3 * lb + q];
       const double gR[2] = {lam_in[2 * s], lam_in[2 * s + 1]};
-      double gRold[2], gm;
+      double gRold[2], gm, gn[2], gg;
       law_reverse(c, tape + 6 * (int64_t)k, rA, dmA, diA, rB, dmB, diB, wall, gR, ga, gb, gRold,
-                  gm);
+                  gm, gn, gg);
+      gn_slot[s] = gn_slot[s] + gn[0];
+      gn_slot[cap + s] = gn_slot[cap + s] + gn[1];
+      ggdt_slot[s] = ggdt_slot[s] + gg;
       for (int q = 0; q < 3; ++q) gp[3 * la + q] = ga[q];
       if (!wall)
         for (int q = 0; q < 3; ++q) gp[3 * lb + q] = gb[q];
@@ -318,14 +349,16 @@ __global__ __launch_bounds__(kT) void k_adjoint_particles(int64_t n, const int* 
 }
 
 // per slot: adjoint of R^(k-1) = own-law part + exchange part of both bodies
-// (V = v + dt/m (f + sum of +-F), W = w + dt/I (t - sum r R_t))
+// (V = v + dt/m (f + sum of +-F), W = w + dt/I (t - sum r R_t)), and the
+// exchange's share of the normal's adjoint (F = R_n n + R_t t)
 __global__ __launch_bounds__(kT) void k_adjoint_contacts(int64_t nc, int64_t n,
                                                          const int* slot_contact, const int* ci,
                                                          const int* cj, const double* geo,
                                                          int64_t cap, const double* dtim,
                                                          const double* dtii, const double* r,
                                                          const double* own, const double* GV,
-                                                         double* lam_out) {
+                                                         const double* rin, double* lam_out,
+                                                         double* gn_slot) {
   const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (s >= nc) return;
   const int c = slot_contact[s];
@@ -341,6 +374,142 @@ __global__ __launch_bounds__(kT) void k_adjoint_contacts(int64_t nc, int64_t n,
   }
   lam_out[2 * s] = own[2 * s] + (gF0 * n0 + gF1 * n1);
   lam_out[2 * s + 1] = own[2 * s + 1] + ((gF0 * t0 + gF1 * t1) + gRt);
+  const double Rn = rin[4 * s], Rt = rin[4 * s + 1];
+  gn_slot[s] = gn_slot[s] + (Rn * gF0 + Rt * gF1);
+  gn_slot[cap + s] = gn_slot[cap + s] + (-Rt * gF0 + Rn * gF1);
+}
+
+// ---- between time steps (frozen contact list) -----------------------------
+
+// the kept list at new positions: slot normals and g_e/dt, the previous
+// step's canonical forces as the starting records (the world force with the
+// new normal, as the order stage writes them)
+__global__ __launch_bounds__(kT) void k_frozen_refresh(int64_t nc, const int* slot_contact,
+                                                       const double* nrm, const double* gap,
+                                                       const double* R, double dt, int clamp,
+                                                       double* geo, int64_t cap, double* rec0) {
+  const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (s >= nc) return;
+  const int c = slot_contact[s];
+  const double n0 = nrm[c], n1 = nrm[nc + c];
+  double ge = gap[c];
+  if (clamp && ge < 0.0) ge = 0.0;
+  geo[G_N0 * cap + s] = n0;
+  geo[(G_N0 + 1) * cap + s] = n1;
+  geo[G_GDT * cap + s] = ge / dt;
+  const double rn = R[c], r1 = R[nc + c];
+  const double t0 = -n1, t1 = n0;
+  double* rc = rec0 + 4 * s;
+  rc[0] = rn;
+  rc[1] = r1;
+  rc[2] = rn * n0 + r1 * t0;
+  rc[3] = rn * n1 + r1 * t1;
+}
+
+// base velocities of the domain particle entries (rows v_x, v_y, w)
+__global__ __launch_bounds__(kT) void k_dpb_base(const int* dp, const int* dp_start, int P,
+                                                 int64_t E, const double* v, const double* w,
+                                                 int64_t n, double* dpb) {
+  const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (e >= E || e >= dp_start[P]) return;
+  const int p = dp[e];
+  dpb[e] = v[p];
+  dpb[E + e] = v[n + p];
+  dpb[2 * E + e] = w[p];
+}
+
+// slot geometry of a recorded step back into the slot constants
+__global__ __launch_bounds__(kT) void k_restore_geo(int64_t nc, const double* gn, const double* gdt,
+                                                    double* geo, int64_t cap) {
+  const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (s >= nc) return;
+  geo[G_N0 * cap + s] = gn[s];
+  geo[(G_N0 + 1) * cap + s] = gn[cap + s];
+  geo[G_GDT * cap + s] = gdt[s];
+}
+
+// adjoint of v^(t+1) in full: from the next step's base velocity and, through
+// x^(t+1) = x^t + dt v^(t+1), from the next step's positions
+__global__ __launch_bounds__(kT) void k_euler_prep(int64_t n, double dt, const double* gv_next,
+                                                   const double* gx_next, double* gvt) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (p >= n) return;
+  gvt[p] = gv_next[p] + dt * gx_next[p];
+  gvt[n + p] = gv_next[n + p] + dt * gx_next[n + p];
+}
+
+// reverse of the velocity update v^(t+1) = v^t + dt/m (f + sum +-F(R^K)),
+// w^(t+1) = w^t + dt/I (t - sum r R_t): adds to the adjoint of the final
+// forces and of the normals of step t
+__global__ __launch_bounds__(kT) void k_euler_reverse(int64_t nc, int64_t n,
+                                                      const int* slot_contact, const int* ci,
+                                                      const int* cj, const double* geo,
+                                                      int64_t cap, const double* dtim,
+                                                      const double* dtii, const double* r,
+                                                      const double* gvt, const double* gw_next,
+                                                      const double* fin, double* lam,
+                                                      double* gn_slot) {
+  const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (s >= nc) return;
+  const int c = slot_contact[s];
+  const int i = ci[c], j = cj[c];
+  const double n0 = geo[G_N0 * cap + s], n1 = geo[(G_N0 + 1) * cap + s];
+  double gF0 = -dtim[i] * gvt[i], gF1 = -dtim[i] * gvt[n + i];
+  double gRt = -dtii[i] * r[i] * gw_next[i];
+  if (j < n) {
+    gF0 = gF0 + dtim[j] * gvt[j];
+    gF1 = gF1 + dtim[j] * gvt[n + j];
+    gRt = gRt - dtii[j] * r[j] * gw_next[j];
+  }
+  lam[2 * s] = lam[2 * s] + (gF0 * n0 + gF1 * n1);
+  lam[2 * s + 1] = lam[2 * s + 1] + ((gF0 * -n1 + gF1 * n0) + gRt);
+  const double Rn = fin[4 * s], Rt = fin[4 * s + 1];
+  gn_slot[s] = gn_slot[s] + (Rn * gF0 + Rt * gF1);
+  gn_slot[cap + s] = gn_slot[cap + s] + (-Rt * gF0 + Rn * gF1);
+}
+
+// reverse of the geometry of step t per particle, over its contacts in
+// ascending id: n = d/|d|, g = |d| - r_i - r_j with d = x_j - x_i, or for a
+// wall n = -nu, g = nu.x_i - o - r_i; g_e = max(g, 0) (clamped) or g
+__global__ __launch_bounds__(kT) void k_geom_reverse(int64_t n, const int* inc_ptr, const int* inc,
+                                                     const int* slot_contact, const int* ci,
+                                                     const int* cj, const double* x,
+                                                     const double* wall, const double* gap,
+                                                     int64_t cap, double dt, int clamp,
+                                                     const double* gn_slot,
+                                                     const double* ggdt_slot, double* gx) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (p >= n) return;
+  double g0 = 0.0, g1 = 0.0;
+  for (int e = inc_ptr[p]; e < inc_ptr[p + 1]; ++e) {
+    const int ent = inc[e];
+    const int64_t s = ent >> 1;
+    const int c = slot_contact[s];
+    const int i = ci[c], j = cj[c];
+    const double gg = (clamp && !(gap[c] > 0.0)) ? 0.0 : ggdt_slot[s] / dt;
+    if (j < n) {
+      const double d0 = x[j] - x[i], d1 = x[n + j] - x[n + i];
+      const double dist = sqrt(d0 * d0 + d1 * d1);
+      const double m0 = d0 / dist, m1 = d1 / dist;
+      const double ln0 = gn_slot[s], ln1 = gn_slot[cap + s];
+      const double proj = m0 * ln0 + m1 * ln1;
+      const double gd0 = (ln0 - m0 * proj) / dist + m0 * gg;
+      const double gd1 = (ln1 - m1 * proj) / dist + m1 * gg;
+      if (ent & 1) {
+        g0 = g0 + gd0;
+        g1 = g1 + gd1;
+      } else {
+        g0 = g0 - gd0;
+        g1 = g1 - gd1;
+      }
+    } else {
+      const double* nu = wall + 2 * (j - n);
+      g0 = g0 + nu[0] * gg;
+      g1 = g1 + nu[1] * gg;
+    }
+  }
+  gx[p] = gx[p] + g0;
+  gx[n + p] = gx[n + p] + g1;
 }
 
 __global__ __launch_bounds__(kT) void k_adjoint_out(int64_t nc, int64_t n, const int* contact_slot,
@@ -368,10 +537,68 @@ hipError_t cd_launch_mu_scatter(cd_ctx* c, const double* mu) {
   return hipGetLastError();
 }
 
+hipError_t cd_launch_frozen_refresh(cd_ctx* c) {
+  if (c->nc > 0)
+    hipLaunchKernelGGL(k_frozen_refresh, dim3(blocks_for(c->nc)), dim3(kT), 0, c->stream, c->nc,
+                       c->slot_contact, c->nrm, c->gap, c->R, c->p.dt, c->p.overlap_mode == 0,
+                       c->geo, c->cap, c->rec[0]);
+  const int64_t E = 2 * c->cap;
+  if (c->dim == 2) {
+    hipLaunchKernelGGL(k_dpb_base, dim3(blocks_for(E)), dim3(kT), 0, c->stream, c->dp,
+                       c->dp_start, c->P, E, c->v, c->w, c->n, c->dpb);
+  } else {
+    return hipErrorInvalidValue;   // kept lists are 2D (the adjoint's case)
+  }
+  return hipGetLastError();
+}
+
+void cd_window_clear(cd_ctx* c) {
+  for (auto& r : c->win) {
+    double* ptrs[] = {r.x, r.v, r.w, r.geo_n, r.geo_gdt, r.gap, r.ck, r.fin};
+    for (double* q : ptrs)
+      if (q) (void)hipFree(q);
+  }
+  c->win.clear();
+}
+
+int cd_window_begin(cd_ctx* c) {
+  c->win.emplace_back();
+  cd_ctx::StepRec& r = c->win.back();
+  const int64_t n = c->n;
+  if (alloc_n(&r.x, c->dim * n) != hipSuccess || alloc_n(&r.v, c->dim * n) != hipSuccess ||
+      alloc_n(&r.w, c->dr * n) != hipSuccess)
+    return cd_fail(c, CD_ENOMEM, "adjoint window: out of device memory");
+  const size_t b = sizeof(double) * (size_t)n;
+  if (hipMemcpyAsync(r.x, c->x, b * c->dim, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(r.v, c->v, b * c->dim, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(r.w, c->w, b * c->dr, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return cd_fail(c, CD_EHIP, "adjoint window: copy failed");
+  return CD_OK;
+}
+
+int cd_window_geometry(cd_ctx* c) {
+  if (c->win.empty()) return CD_OK;
+  cd_ctx::StepRec& r = c->win.back();
+  const int64_t cap = c->cap, nc = c->nc;
+  if (alloc_n(&r.geo_n, 2 * cap) != hipSuccess || alloc_n(&r.geo_gdt, cap) != hipSuccess ||
+      alloc_n(&r.gap, nc) != hipSuccess)
+    return cd_fail(c, CD_ENOMEM, "adjoint window: out of device memory");
+  const size_t b = sizeof(double);
+  if (hipMemcpyAsync(r.geo_n, c->geo + G_N0 * cap, b * 2 * cap, hipMemcpyDeviceToDevice,
+                     c->stream) != hipSuccess ||
+      hipMemcpyAsync(r.geo_gdt, c->geo + G_GDT * cap, b * cap, hipMemcpyDeviceToDevice,
+                     c->stream) != hipSuccess ||
+      (nc > 0 && hipMemcpyAsync(r.gap, c->gap, b * nc, hipMemcpyDeviceToDevice, c->stream) !=
+                     hipSuccess))
+    return cd_fail(c, CD_EHIP, "adjoint window: copy failed");
+  return CD_OK;
+}
+
 void cd_adjoint_release(cd_ctx* c) {
   AdjointWork* w = c->adj;
   if (!w) return;
-  double** dptrs[] = {&w->lam[0], &w->lam[1], &w->own, &w->gE, &w->GV, &w->gv, &w->gmu, &w->seg};
+  double** dptrs[] = {&w->lam[0], &w->lam[1], &w->own, &w->gE, &w->GV, &w->gv, &w->gmu, &w->seg,
+                      &w->gn, &w->ggdt, &w->gx, &w->gv_next, &w->gx_next, &w->gvt};
   for (double** q : dptrs)
     if (*q) (void)hipFree(*q);
   int** iptrs[] = {&w->p2e_cnt, &w->p2e_ptr, &w->p2e};
@@ -384,29 +611,40 @@ void cd_adjoint_release(cd_ctx* c) {
 
 extern "C" {
 
+// Reverse of every step of the recorded window, last to first.  For step t:
+// the Euler update's reverse (from the adjoints of x, v, w at step t+1), the
+// solve's reverse (seeded with the adjoint of its final forces), the
+// geometry's reverse; the adjoint of the step's starting forces (its warm
+// start) seeds the previous step's final forces.
 int cd_adjoint(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv, double* dL_dw) {
   if (!c || !dL_dR) return CD_EINVAL;
   if (c->dim != 2) return cd_fail(c, CD_EINVAL, "the adjoint is implemented for 2D");
-  if (!c->adj_valid || c->adj_K < 1)
+  if (!c->adj_valid || c->win.empty() || c->win.back().K < 1)
     return cd_fail(c, CD_ENOTREADY,
                    "cd_adjoint needs a solve recorded with cd_set_adjoint and fixed_iters");
   if (c->sweep_global)
     return cd_fail(c, CD_ECAPACITY, "the adjoint needs every domain in LDS");
   const int64_t nc = c->nc, n = c->n, cap = c->cap, E = 2 * cap;
-  const int C = c->adj_every, K = c->adj_K;
+  const int C = c->adj_every;
+  const int T = (int)c->win.size();
+  const double dt = c->p.dt;
+  const int clamp = c->p.overlap_mode == 0;
   hipStream_t st = c->stream;
   // LDS of the reverse sweep: particle records, tape, particle adjoints
   const int np_max = std::max(c->st_ds.max_particles, 1);
-  const size_t lds = sizeof(double) * ((size_t)Layout<2>::PS * np_max + 6 * (size_t)c->st_ds.max_contacts +
-                                       3 * (size_t)np_max);
-  if (lds + 2048 > c->max_lds) return cd_fail(c, CD_ECAPACITY, "a domain is too large for the adjoint");
+  const size_t lds = sizeof(double) * ((size_t)Layout<2>::PS * np_max +
+                                       6 * (size_t)c->st_ds.max_contacts + 3 * (size_t)np_max);
+  if (lds + 2048 > c->max_lds)
+    return cd_fail(c, CD_ECAPACITY, "a domain is too large for the adjoint");
   if (!c->adj) c->adj = new AdjointWork();
   AdjointWork* w = c->adj;
-  auto TRYH = [&](hipError_t e) { return e == hipSuccess ? CD_OK : cd_fail(c, CD_EHIP, hipGetErrorString(e)); };
-#define ATRY(expr)                 \
-  do {                             \
-    int r_ = TRYH(expr);           \
-    if (r_ != CD_OK) return r_;    \
+  auto TRYH = [&](hipError_t e) {
+    return e == hipSuccess ? CD_OK : cd_fail(c, CD_EHIP, hipGetErrorString(e));
+  };
+#define ATRY(expr)              \
+  do {                          \
+    int r_ = TRYH(expr);        \
+    if (r_ != CD_OK) return r_; \
   } while (0)
   if (w->cap < cap || w->n < n) {
     ATRY(alloc_n(&w->lam[0], 2 * cap));
@@ -414,8 +652,14 @@ int cd_adjoint(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv, do
     ATRY(alloc_n(&w->own, 2 * cap));
     ATRY(alloc_n(&w->gE, 3 * E));
     ATRY(alloc_n(&w->gmu, cap));
+    ATRY(alloc_n(&w->gn, 2 * cap));
+    ATRY(alloc_n(&w->ggdt, cap));
     ATRY(alloc_n(&w->GV, 3 * n));
     ATRY(alloc_n(&w->gv, 3 * n));
+    ATRY(alloc_n(&w->gx, 2 * n));
+    ATRY(alloc_n(&w->gv_next, 3 * n));
+    ATRY(alloc_n(&w->gx_next, 2 * n));
+    ATRY(alloc_n(&w->gvt, 2 * n));
     ATRY(alloc_n(&w->p2e_cnt, n + 1));
     ATRY(alloc_n(&w->p2e_ptr, n + 1));
     ATRY(alloc_n(&w->p2e, E));
@@ -433,14 +677,16 @@ int cd_adjoint(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv, do
     ATRY(hipMemcpy(w->state, &s0, sizeof(SolveState), hipMemcpyHostToDevice));
   }
   ATRY(hipMemsetAsync(w->gmu, 0, sizeof(double) * cap, st));
-  ATRY(hipMemsetAsync(w->gv, 0, sizeof(double) * 3 * n, st));
   ATRY(hipMemsetAsync(w->gE, 0, sizeof(double) * 3 * E, st));
+  ATRY(hipMemsetAsync(w->gv_next, 0, sizeof(double) * 3 * n, st));
+  ATRY(hipMemsetAsync(w->gx_next, 0, sizeof(double) * 2 * n, st));
+  ATRY(hipMemsetAsync(w->lam[0], 0, sizeof(double) * 2 * cap, st));
   if (nc > 0) {
-    hipLaunchKernelGGL(k_lambda_init, dim3(blocks_for(nc)), dim3(kT), 0, st, dL_dR, c->contact_slot,
-                       nc, w->lam[0]);
+    hipLaunchKernelGGL(k_lambda_init, dim3(blocks_for(nc)), dim3(kT), 0, st, dL_dR,
+                       c->contact_slot, nc, w->lam[0]);
     ATRY(hipGetLastError());
   }
-  // entries of each particle
+  // entries of each particle (the same for every step of the window)
   int dp_total = 0;
   ATRY(hipMemcpy(&dp_total, c->dp_start + c->P, sizeof(int), hipMemcpyDeviceToHost));
   ATRY(hipMemsetAsync(w->p2e_cnt, 0, sizeof(int) * (n + 1), st));
@@ -452,36 +698,77 @@ int cd_adjoint(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv, do
                      (int64_t)dp_total, w->p2e_ptr, w->p2e_cnt, w->p2e);
   hipLaunchKernelGGL(k_p2e_sort, dim3(blocks_for(n)), dim3(kT), 0, st, n, w->p2e_ptr, w->p2e);
   ATRY(hipGetLastError());
-  SweepArgs a = cd_sweep_args(c);
   const int block = c->sweep_block;
-  const int S = (K + C - 1) / C;
-  int cur = 0;   // lam[cur] holds the adjoint of R^k
-  for (int sgi = S - 1; sgi >= 0; --sgi) {
-    const int k0 = sgi * C, k1 = std::min(K, (sgi + 1) * C);
-    const double* ck = c->ck + sgi * c->ck_stride;
-    // forces R^(k0+1) .. R^(k1-1) of this segment, recomputed from R^k0
-    auto R_of = [&](int k) -> const double* {
-      return k == k0 ? ck : w->seg + (int64_t)(k - k0 - 1) * 4 * cap;
-    };
-    for (int k = k0 + 1; k < k1; ++k) {
-      SweepArgs f = a;
-      f.rec[(k - 1) & 1] = const_cast<double*>(R_of(k - 1));
-      f.rec[k & 1] = w->seg + (int64_t)(k - k0 - 1) * 4 * cap;
-      f.state = w->state;
-      ATRY(cd_launch_sweep_grid(c, f, k, f.grid));
-    }
-    for (int k = k1; k > k0; --k) {
-      hipLaunchKernelGGL(k_sweep_adjoint, dim3(a.grid), dim3(block), lds, st, a, R_of(k - 1),
-                         w->lam[cur], w->own, w->gE, w->gmu, np_max);
-      hipLaunchKernelGGL(k_adjoint_particles, dim3(blocks_for(n)), dim3(kT), 0, st, n, w->p2e_ptr,
-                         w->p2e, w->gE, w->GV, w->gv);
+  int cur = 0;   // lam[cur] holds the adjoint of the forces being reversed
+  for (int t = T - 1; t >= 0; --t) {
+    const cd_ctx::StepRec& r = c->win[t];
+    const int K = r.K;
+    // the step's geometry and base velocities back in place
+    if (nc > 0)
+      hipLaunchKernelGGL(k_restore_geo, dim3(blocks_for(nc)), dim3(kT), 0, st, nc, r.geo_n,
+                         r.geo_gdt, c->geo, cap);
+    hipLaunchKernelGGL(k_dpb_base, dim3(blocks_for(E)), dim3(kT), 0, st, c->dp, c->dp_start, c->P,
+                       E, r.v, r.w, n, c->dpb);
+    ATRY(hipGetLastError());
+    ATRY(hipMemsetAsync(w->gv, 0, sizeof(double) * 3 * n, st));
+    ATRY(hipMemsetAsync(w->gn, 0, sizeof(double) * 2 * cap, st));
+    ATRY(hipMemsetAsync(w->ggdt, 0, sizeof(double) * cap, st));
+    // the Euler update of step t (x, v, w of step t+1 depend on its forces)
+    if (t < T - 1) {
+      hipLaunchKernelGGL(k_euler_prep, dim3(blocks_for(n)), dim3(kT), 0, st, n, dt, w->gv_next,
+                         w->gx_next, w->gvt);
       if (nc > 0)
-        hipLaunchKernelGGL(k_adjoint_contacts, dim3(blocks_for(nc)), dim3(kT), 0, st, nc, n,
+        hipLaunchKernelGGL(k_euler_reverse, dim3(blocks_for(nc)), dim3(kT), 0, st, nc, n,
                            c->slot_contact, c->ci, c->cj, c->geo, cap, c->dtim, c->dtii, c->r,
-                           w->own, w->GV, w->lam[cur ^ 1]);
+                           w->gvt, w->gv_next + 2 * n, r.fin, w->lam[cur], w->gn);
       ATRY(hipGetLastError());
-      cur ^= 1;
+      // v^t and w^t pass into v^(t+1), w^(t+1) unchanged; x^t into x^(t+1)
+      ATRY(hipMemcpyAsync(w->gv, w->gvt, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, st));
+      ATRY(hipMemcpyAsync(w->gv + 2 * n, w->gv_next + 2 * n, sizeof(double) * n,
+                          hipMemcpyDeviceToDevice, st));
+      ATRY(hipMemcpyAsync(w->gx, w->gx_next, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice,
+                          st));
+    } else {
+      ATRY(hipMemsetAsync(w->gx, 0, sizeof(double) * 2 * n, st));
     }
+    // the solve of step t, sweep by sweep from the last
+    SweepArgs a = cd_sweep_args(c);
+    const int S = (K + C - 1) / C;
+    for (int sgi = S - 1; sgi >= 0; --sgi) {
+      const int k0 = sgi * C, k1 = std::min(K, (sgi + 1) * C);
+      const double* ck = r.ck + sgi * c->ck_stride;
+      auto R_of = [&](int k) -> const double* {
+        return k == k0 ? ck : w->seg + (int64_t)(k - k0 - 1) * 4 * cap;
+      };
+      for (int k = k0 + 1; k < k1; ++k) {
+        SweepArgs f = a;
+        f.rec[(k - 1) & 1] = const_cast<double*>(R_of(k - 1));
+        f.rec[k & 1] = w->seg + (int64_t)(k - k0 - 1) * 4 * cap;
+        f.state = w->state;
+        ATRY(cd_launch_sweep_grid(c, f, k, f.grid));
+      }
+      for (int k = k1; k > k0; --k) {
+        hipLaunchKernelGGL(k_sweep_adjoint, dim3(a.grid), dim3(block), lds, st, a, R_of(k - 1),
+                           w->lam[cur], w->own, w->gE, w->gmu, w->gn, w->ggdt, cap, np_max);
+        hipLaunchKernelGGL(k_adjoint_particles, dim3(blocks_for(n)), dim3(kT), 0, st, n,
+                           w->p2e_ptr, w->p2e, w->gE, w->GV, w->gv);
+        if (nc > 0)
+          hipLaunchKernelGGL(k_adjoint_contacts, dim3(blocks_for(nc)), dim3(kT), 0, st, nc, n,
+                             c->slot_contact, c->ci, c->cj, c->geo, cap, c->dtim, c->dtii, c->r,
+                             w->own, w->GV, R_of(k - 1), w->lam[cur ^ 1], w->gn);
+        ATRY(hipGetLastError());
+        cur ^= 1;
+      }
+    }
+    // the geometry of step t
+    hipLaunchKernelGGL(k_geom_reverse, dim3(blocks_for(n)), dim3(kT), 0, st, n, c->inc_ptr,
+                       c->inc, c->slot_contact, c->ci, c->cj, r.x, c->d_wall, r.gap, cap, dt,
+                       clamp, w->gn, w->ggdt, w->gx);
+    ATRY(hipGetLastError());
+    // adjoints of x^t, v^t, w^t for the step before
+    ATRY(hipMemcpyAsync(w->gv_next, w->gv, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+    ATRY(hipMemcpyAsync(w->gx_next, w->gx, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, st));
+    // lam[cur] now holds the adjoint of step t's starting forces = step t-1's final forces
   }
   hipLaunchKernelGGL(k_adjoint_out, dim3(blocks_for(std::max(nc, n))), dim3(kT), 0, st, nc, n,
                      c->contact_slot, w->gmu, w->gv, dL_dmu, dL_dv, dL_dw);

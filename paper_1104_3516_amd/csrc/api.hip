@@ -439,6 +439,7 @@ int cd_destroy(cd_ctx* c) {
   release(&c->mu_slot);
   release(&c->ck);
   cd_adjoint_release(c);
+  cd_window_clear(c);
   release(&c->d_vmax);
   if (c->h_state) (void)hipHostFree(c->h_state);
   if (c->h_scratch) (void)hipHostFree(c->h_scratch);
@@ -484,6 +485,7 @@ int cd_set_particles(cd_ctx* c, const double* x, const double* v, const double* 
   CD_TRY(cd_launch_derived(c));
   c->have_particles = true;
   c->have_tree = false;
+  c->frozen_ready = false;
   c->step = 0;
   c->nc_prev = 0;
   return CD_OK;
@@ -577,9 +579,32 @@ int prep_phase0(cd_ctx* c) {
   if (!c) return CD_EINVAL;
   if (!c->have_particles || !c->have_box) return fail(c, CD_ENOTREADY, "particles or box not set");
   c->adj_valid = false;
-  c->use_mu_slot = false;
   c->prepared = false;
+  c->frozen_now = c->frozen && c->frozen_ready;
+  // per-contact friction belongs to a list: it lapses when the list is rebuilt
+  if (!c->frozen_now) c->use_mu_slot = false;
+  if (c->adj_every > 0) {
+    // a new step of the adjoint window (the window restarts unless the list is kept)
+    if (!c->frozen_now) cd_window_clear(c);
+    int st = cd_window_begin(c);
+    if (st != CD_OK) return st;
+  }
   CD_TRY(hipEventRecord(c->ev[0], c->stream));
+  if (c->frozen_now) {
+    // the kept list: its geometry at the new positions, slot constants, the
+    // previous step's forces as warm start, the new base velocities
+    CD_TRY(cd_launch_geometry(c));
+    CD_TRY(hipEventRecord(c->ev[1], c->stream));
+    CD_TRY(hipEventRecord(c->ev[2], c->stream));
+    CD_TRY(cd_launch_frozen_refresh(c));
+    CD_TRY(hipEventRecord(c->ev[3], c->stream));
+    c->st_limit = c->p.fixed_iters > 0 ? c->p.fixed_iters : c->p.max_iter;
+    CD_TRY(cd_launch_solve_init(c, c->st_limit));
+    c->run = SolveRun{};
+    c->prepared = true;
+    if (c->adj_every > 0) return cd_window_geometry(c);
+    return CD_OK;
+  }
   // ---- boundary width: 2 vmax dt (Sec. 3.1)
   CD_TRY(cd_launch_vmax(c));
   CD_TRY(hipMemcpyAsync(c->h_scratch, c->d_vmax, sizeof(unsigned long long), hipMemcpyDeviceToHost,
@@ -588,6 +613,7 @@ int prep_phase0(cd_ctx* c) {
 }
 
 int prep_phase1(cd_ctx* c) {
+  if (c->frozen_now) return CD_OK;
   const int dim = c->dim;
   const double dt = c->p.dt;
   double vmax;
@@ -623,6 +649,7 @@ int prep_phase1(cd_ctx* c) {
 }
 
 int prep_phase2(cd_ctx* c) {
+  if (c->frozen_now) return CD_OK;
   const double skin = c->st_skin;
   const int64_t nc = (int64_t)((int*)c->h_scratch)[0];
   if (nc < 0 || nc > ((int64_t)1 << 30)) return fail(c, CD_ECAPACITY, "too many contacts");
@@ -651,6 +678,7 @@ int prep_phase2(cd_ctx* c) {
 }
 
 int prep_phase3(cd_ctx* c) {
+  if (c->frozen_now) return CD_OK;
   const int dim = c->dim;
   DomainStats ds;
   memcpy(&ds, c->h_scratch, sizeof(DomainStats));
@@ -695,6 +723,8 @@ int prep_phase3(cd_ctx* c) {
   CD_TRY(cd_launch_solve_init(c, c->st_limit));
   c->run = SolveRun{};
   c->prepared = true;
+  if (c->frozen) c->frozen_ready = true;
+  if (c->adj_every > 0) return cd_window_geometry(c);
   return CD_OK;
 }
 
@@ -770,16 +800,17 @@ int solve_single(cd_ctx* c) {
     __sync_synchronize();
     // adjoint recording: the forces before the first sweep and after every
     // adj_every-th sweep (fixed sweep count, 2D)
-    const bool record = c->adj_every > 0 && c->p.fixed_iters > 0 && c->dim == 2;
+    const bool record = c->adj_every > 0 && c->p.fixed_iters > 0 && c->dim == 2 && !c->win.empty();
     const int64_t rec_bytes = (int64_t)sizeof(double) * 4 * c->cap;
+    double* ck = nullptr;
     if (record) {
+      cd_ctx::StepRec& r = c->win.back();
       const int64_t slots = limit / c->adj_every + 1;
-      if (slots * 4 * c->cap > c->ck_cap) {
-        CD_TRY(grow(&c->ck, slots * 4 * c->cap));
-        c->ck_cap = slots * 4 * c->cap;
-      }
+      CD_TRY(grow(&r.ck, slots * 4 * c->cap));
+      CD_TRY(grow(&r.fin, 4 * c->cap));
+      ck = r.ck;
       c->ck_stride = 4 * c->cap;
-      CD_TRY(hipMemcpyAsync(c->ck, c->rec[0], rec_bytes, hipMemcpyDeviceToDevice, c->stream));
+      CD_TRY(hipMemcpyAsync(ck, c->rec[0], rec_bytes, hipMemcpyDeviceToDevice, c->stream));
     }
     while (launched < limit && !hp->done) {
       if (launched - hp->decided >= kLookahead) {
@@ -801,10 +832,14 @@ int solve_single(cd_ctx* c) {
       if (closes) groups_closed = m + 1;
       launched = j;
       if (record && j % c->adj_every == 0)
-        CD_TRY(hipMemcpyAsync(c->ck + (j / c->adj_every) * c->ck_stride, c->rec[j & 1], rec_bytes,
+        CD_TRY(hipMemcpyAsync(ck + (j / c->adj_every) * c->ck_stride, c->rec[j & 1], rec_bytes,
                               hipMemcpyDeviceToDevice, c->stream));
     }
     if (record) {
+      cd_ctx::StepRec& r = c->win.back();
+      CD_TRY(hipMemcpyAsync(r.fin, c->rec[launched & 1], rec_bytes, hipMemcpyDeviceToDevice,
+                            c->stream));
+      r.K = launched;
       c->adj_K = launched;
       c->adj_valid = true;
     }
@@ -950,6 +985,16 @@ int cd_solve(cd_ctx* c, cd_result* out) {
 int cd_set_adjoint(cd_ctx* c, int checkpoint_every) {
   if (!c || checkpoint_every < 0) return CD_EINVAL;
   c->adj_every = checkpoint_every;
+  cd_window_clear(c);
+  c->adj_valid = false;
+  return CD_OK;
+}
+
+int cd_set_frozen_list(cd_ctx* c, int on) {
+  if (!c) return CD_EINVAL;
+  if (on && c->dim != 2) return fail(c, CD_EINVAL, "kept contact lists are implemented for 2D");
+  c->frozen = on != 0;
+  c->frozen_ready = false;
   return CD_OK;
 }
 

@@ -186,6 +186,11 @@ struct cd_ctx {
   int64_t mu_slot_cap = 0;
   bool use_mu_slot = false;      // set by cd_set_contact_mu for the coming solve
   bool prepared = false;         // a step has been prepared and not yet solved
+  // frozen contact list: the list, tree and order of the first prepared step
+  // are kept for the following steps (geometry recomputed each step)
+  bool frozen = false;           // requested by cd_set_frozen_list
+  bool frozen_ready = false;     // a list to keep exists
+  bool frozen_now = false;       // the step being prepared reuses it
   // adjoint: force checkpoints of the last recorded solve
   int adj_every = 0;             // checkpoint interval in sweeps (0: no recording)
   int adj_K = 0;                 // sweeps of the recorded solve
@@ -193,6 +198,20 @@ struct cd_ctx {
   double* ck = nullptr;          // checkpoints, ck_stride doubles each
   int64_t ck_cap = 0, ck_stride = 0;
   struct AdjointWork* adj = nullptr;  // reverse-pass workspace (adjoint.hip)
+  // recorded steps of the adjoint window (one per solve; several only with a
+  // frozen list): starting state, geometry, checkpoints, final records
+  struct StepRec {
+    double* x = nullptr;         // dim x N positions at the step's start
+    double* v = nullptr;         // dim x N velocities at the step's start
+    double* w = nullptr;         // dr x N
+    double* geo_n = nullptr;     // 2 x cap slot normals
+    double* geo_gdt = nullptr;   // cap slot g_e/dt
+    double* gap = nullptr;       // nc canonical gaps
+    double* ck = nullptr;        // checkpoints (S+1) x 4 cap
+    double* fin = nullptr;       // final records 4 cap
+    int K = 0;                   // sweeps
+  };
+  std::vector<StepRec> win;
 
   // tree (host shape + device arrays)
   int P = 1;
@@ -334,6 +353,11 @@ hipError_t cd_launch_gather_states(hipStream_t stream, const SweepArgs* tab, int
 hipError_t cd_launch_mu_scatter(cd_ctx* c, const double* mu);
 // adjoint.hip
 void cd_adjoint_release(cd_ctx* c);
+void cd_window_clear(cd_ctx* c);
+int cd_window_begin(cd_ctx* c);      // a new recorded step: starting state
+int cd_window_geometry(cd_ctx* c);   // its slot geometry (after preparation)
+// frozen-list preparation: geometry, slot constants, warm start, base velocities
+hipError_t cd_launch_frozen_refresh(cd_ctx* c);
 hipError_t cd_launch_unslot(cd_ctx* c, int final_iter);
 int cd_solve_grid(cd_ctx* c);                               // co-resident grid, 0 if none
 
