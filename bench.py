@@ -486,7 +486,7 @@ def main() -> int:
         "sweeps_executed": executed,
         "sweeps_timed": timed,
         "solve_mode": args.solve_mode,
-        "block_threads": tm.block_threads,
+        "block_threads": tm.block_threads, "contact_data_in_lds": bool(tm.staged),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
                      "traffic": traffic,

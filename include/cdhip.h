@@ -98,6 +98,8 @@ typedef struct cd_timing {
   int sweeps_executed;   /* sweeps computed, including the one the stop decision overlaps */
   int block_threads;     /* threads of the workgroup that sweeps one domain */
   int sweeps_timed;      /* sweep launches inside the timed groups (per-sweep mode) */
+  int staged;            /* 1: the sweeps read each domain's contact data from LDS */
+  int pad;
 } cd_timing;
 
 typedef struct cd_ctx cd_ctx;
@@ -163,9 +165,14 @@ int cd_set_timing(cd_ctx* ctx, int every);
 
 /* mode 1 (default): one launch per sweep; an extra workgroup of each launch
  * takes the stop decision of the previous sweep, so the launch after the
- * stopping sweep computes a sweep whose result is discarded.
+ * stopping sweep computes a sweep whose result is discarded.  Each domain's
+ * contact data is copied to LDS alongside the exchange when that keeps every
+ * workgroup of a launch resident at once; otherwise each thread reads its
+ * contact of the next colour into registers one colour ahead.
+ * mode 2: as mode 1, always in the register form.
  * mode 0: all sweeps of a step in one launch, blocks synchronised by a grid
- * barrier, the stop decision overlapping the next sweep.  Same results. */
+ * barrier, the stop decision overlapping the next sweep.  Same results in
+ * every mode. */
 int cd_set_solve_mode(cd_ctx* ctx, int mode);
 
 /* Threads of the workgroup that sweeps one domain: 64, 128, 192 or 256;
@@ -261,7 +268,7 @@ typedef struct cd_batch_timing {
   int sweeps_timed;        /* launches inside the timed groups */
   int block_threads;       /* threads per domain workgroup */
   int workgroups;          /* workgroups of one batched launch */
-  int pad;
+  int staged;              /* 1: the sweeps read each domain's contact data from LDS */
 } cd_batch_timing;
 
 /* ctxs: `count` contexts (host array of handles), all of one dimension, on

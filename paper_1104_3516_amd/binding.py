@@ -40,14 +40,14 @@ class Timing(C.Structure):
                 ("order_ms", C.c_double), ("solve_ms", C.c_double), ("update_ms", C.c_double),
                 ("sweep_kernel_ms", C.c_double), ("sweep_launches", C.c_int),
                 ("sweeps_executed", C.c_int), ("block_threads", C.c_int),
-                ("sweeps_timed", C.c_int)]
+                ("sweeps_timed", C.c_int), ("staged", C.c_int), ("pad", C.c_int)]
 
 
 class BatchTiming(C.Structure):
     _fields_ = [("prepare_ms", C.c_double), ("solve_ms", C.c_double), ("finish_ms", C.c_double),
                 ("sweep_kernel_ms", C.c_double), ("sweep_launches", C.c_int),
                 ("sweeps_executed", C.c_int), ("sweeps_timed", C.c_int),
-                ("block_threads", C.c_int), ("workgroups", C.c_int), ("pad", C.c_int)]
+                ("block_threads", C.c_int), ("workgroups", C.c_int), ("staged", C.c_int)]
 
 
 def make_params(dim: int, n_walls: int, *, dt=1e-3, alpha=1e-6, mu=0.3, criterion=0,

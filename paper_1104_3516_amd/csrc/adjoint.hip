@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep_adjoint(SweepArgs a, const 
   for (int col = 0; col < ncol; ++col) {
     for (int k = s_co[col] + tid; k < s_co[col + 1]; k += nthr) {
       SlotPre<2> c;
-      fetch_slot<2>(a, rin, cs + k, c);
+      fetch_slot<2, true>(a, rin, cs + k, c);
       Body<2> A, B;
       law_forward(sp, s_wu, c, A, B);
       double* t = tape + 6 * (int64_t)k;
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep_adjoint(SweepArgs a, const 
     for (int k = s_co[col] + tid; k < s_co[col + 1]; k += nthr) {
       const int64_t s = cs + k;
       SlotPre<2> c;
-      fetch_slot<2>(a, rin, s, c);
+      fetch_slot<2, true>(a, rin, s, c);
       const int la = c.ab.x, lb = c.ab.y;
       const bool wall = lb < 0;
       const double* pa = sp + (int64_t)PS * la;

@@ -349,7 +349,7 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
   alloc(&c->inv_I, n);
   alloc(&c->dtim, n);
   alloc(&c->dtii, n);
-  alloc(&c->d_wall, (int64_t)CD_MAX_WALLS * 7);
+  alloc(&c->d_wall, (int64_t)CD_WALL_MU + 1);
   alloci(&c->cell_of, n);
   alloci(&c->cell_members, n);
   alloci(&c->pair_count, n + 1);
@@ -357,6 +357,9 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
   alloci(&c->inc_count, n + 1);
   alloci(&c->inc_ptr, n + 1);
   alloci(&c->inc_cursor, n + 1);
+  if (st == CD_OK && hipMemcpy(c->d_wall + CD_WALL_MU, &c->p.mu, sizeof(double),
+                               hipMemcpyHostToDevice) != hipSuccess)
+    st = CD_EHIP;
   if (st == CD_OK && hipMalloc((void**)&c->d_state, sizeof(SolveState)) != hipSuccess) st = CD_ENOMEM;
   if (st == CD_OK) {
     // no solve open until a step sets one up (a batched launch may read it)
@@ -554,8 +557,9 @@ int cd_set_timing(cd_ctx* c, int every) {
 }
 
 int cd_set_solve_mode(cd_ctx* c, int mode) {
-  if (!c || (mode != 0 && mode != 1)) return CD_EINVAL;
+  if (!c || mode < 0 || mode > 2) return CD_EINVAL;
   c->persistent = mode == 0;
+  c->stage_off = mode == 2;
   return CD_OK;
 }
 
@@ -758,7 +762,9 @@ int solve_single(cd_ctx* c) {
   bool aborted = false;
   bool one_launch = false;
   int groups_closed = 0;
+  c->sweep_stage = false;   // the one-launch solve never stages
   const int G = c->persistent ? cd_solve_grid(c) : 0;
+  if (G < 8) cd_sweep_mode(c);
   if (G >= 8 && nc > 0 && limit > 0) {
     // all sweeps in one launch
     if ((int)c->sweep_ev.size() < 2) {
@@ -949,6 +955,7 @@ int finish_complete(cd_ctx* c, cd_result* out) {
     tm.sweeps_timed = cnt;
   }
   tm.sweep_kernel_ms = sk;
+  tm.staged = c->sweep_stage ? 1 : 0;
   c->timing = tm;
   if (c->block_override < 0 && tm.sweeps_timed > 0)
     tune_block_record(c, 1e3 * sk / std::max(executed, 1));

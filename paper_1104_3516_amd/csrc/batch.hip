@@ -21,6 +21,7 @@ struct cd_batch {
   hipStream_t stream = nullptr;
   int dim = 2;
   int grid_total = 0;           // workgroups of one batched sweep launch
+  bool staged = false;          // the last batched solve staged contact data in LDS
   SweepArgs* h_tab = nullptr;   // pinned
   SweepArgs* d_tab = nullptr;
   int* d_blk = nullptr;         // per workgroup: packing, workgroup within the packing
@@ -159,7 +160,7 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
   BTRY(hipEventRecord(b->ev[1], b->stream));
   // ---- the batched solve
   int limit = 0, open = 0, block = 64;
-  size_t lds = 8;
+  size_t lds = 8, lds_stage = 8;
   for (int p = 0; p < B; ++p) {
     cd_ctx* c = b->ctx[p];
     if (!b->failed[p] && c->sweep_global)
@@ -168,6 +169,7 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
     b->h_tab[p] = cd_sweep_args(c);
     block = std::max(block, c->sweep_block);
     lds = std::max(lds, c->sweep_lds);
+    lds_stage = std::max(lds_stage, cd_stage_lds(c, c->st_ds.max_particles, c->st_ds.max_contacts));
     if (!b->failed[p] && c->nc > 0 && c->st_limit > 0) {
       ++open;
       limit = std::max(limit, c->st_limit);
@@ -175,6 +177,12 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
   }
   BTRY(hipMemcpyAsync(b->d_tab, b->h_tab, sizeof(SweepArgs) * B, hipMemcpyHostToDevice,
                       b->stream));
+  // contact data staged in LDS when that costs no extra round of workgroups
+  const bool stg = !b->ctx[0]->stage_off &&
+                   cd_stage_pick(b->dim, block, lds, lds_stage, b->grid_total, b->ctx[0]->num_cu,
+                                 b->ctx[0]->max_lds, true);
+  const size_t lds_launch = stg ? lds_stage : lds;
+  b->staged = stg;
   const int every = b->time_every;
   const int groups_cap = every > 0 ? (limit + every - 1) / every : 0;
   if ((int)b->sweep_ev.size() < 2 * groups_cap) {
@@ -243,8 +251,8 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
     const bool opens = m >= 0 && (j - 2) % every == 0;
     const bool closes = m >= 0 && (j - 2) % every == every - 1;
     if (opens) BTRY(hipEventRecord(b->sweep_ev[2 * m], b->stream));
-    BTRY(cd_launch_sweep_batch(b->stream, b->dim, b->d_tab, b->d_blk, grid_now, block, lds, j,
-                               b->d_prog));
+    BTRY(cd_launch_sweep_batch(b->stream, b->dim, b->d_tab, b->d_blk, grid_now, block,
+                               lds_launch, stg, j, b->d_prog));
     if (closes) {
       BTRY(hipEventRecord(b->sweep_ev[2 * m + 1], b->stream));
       groups_closed = m + 1;
@@ -313,6 +321,7 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
   }
   tm.sweep_kernel_ms = cnt > 0 ? sum / cnt * max_exec : 0.0;
   tm.sweeps_timed = cnt;
+  tm.staged = b->staged ? 1 : 0;
   b->timing = tm;
   if (status == CD_ENONFINITE) b->err = "some packings diverged and left the batch";
   return status;

@@ -28,6 +28,8 @@
 #define CD_MAX_DC 1024       // contacts per domain
 #define CD_MAX_DP 2048       // particles per domain
 #define CD_MAX_WALLS 8
+// index, in the device wall buffer, of the friction coefficient shared by all contacts
+#define CD_WALL_MU (CD_MAX_WALLS * 7)
 
 struct SolveState {
   int iter;           // sweeps completed
@@ -106,7 +108,8 @@ struct SweepArgs {
   const double* walls_u;    // W x dim wall velocities
   int n_walls;
   double* rec[2];
-  const double* mu_slot;    // per-slot friction coefficients, or null: mu for all
+  const double* mu_slot;    // friction of slot s at mu_slot[s * mu_step]
+  int mu_step;              // 1: per slot; 0: one coefficient for all
   // convergence
   SolveState* state;
   BlockPartial* partial;
@@ -288,6 +291,9 @@ struct cd_ctx {
 
   // sweep launch shape
   size_t sweep_lds = 0;     // LDS staging per wavefront (domain), bytes
+  size_t sweep_lds_stage = 0;  // the same with the domain's contact data staged too
+  bool sweep_stage = false;    // this solve stages contact data in LDS
+  bool stage_off = false;      // never stage (the register read-ahead form only)
 
   // timing
   hipEvent_t ev[8] = {};
@@ -345,7 +351,17 @@ hipError_t cd_launch_decide(cd_ctx* c, int jd);            // stop decision of s
 hipError_t cd_launch_sweep_grid(cd_ctx* c, const SweepArgs& a, int j, int grid);
 // batched solve over the packings of tab (device array of their arguments)
 hipError_t cd_launch_sweep_batch(hipStream_t stream, int dim, const SweepArgs* tab, const int* blk,
-                                 int grid, int block, size_t lds, int j, BatchProg* bp);
+                                 int grid, int block, size_t lds, bool stage, int j,
+                                 BatchProg* bp);
+// LDS of the staged sweep for domains of these sizes (particle entries,
+// contacts), with the context's friction mode
+size_t cd_stage_lds(cd_ctx* c, int max_particles, int max_contacts);
+// whether a launch of `workgroups` should stage contact data: it must fit and
+// must not need more rounds of resident workgroups than the register form
+bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64_t workgroups,
+                   int num_cu, size_t max_lds, bool batch);
+// sets sweep_stage / sweep_lds_stage for the coming per-sweep solve
+void cd_sweep_mode(cd_ctx* c);
 hipError_t cd_launch_decide_batch(hipStream_t stream, const SweepArgs* tab, int B, int jd,
                                   BatchProg* bp);
 hipError_t cd_launch_gather_states(hipStream_t stream, const SweepArgs* tab, int B, SolveState* out);

@@ -28,6 +28,10 @@
 // that XCD's L2.
 #include "sweep_core.h"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace {
 
 struct BlockRed {
@@ -151,7 +155,7 @@ __device__ inline void decide_block(const SweepArgs& a, int jd, BlockRed& red, i
 // a.grid) the stop decision of sweep j-1.  A stop at j-1 leaves the forces
 // of sweep j-1 final (sweep j writes the other record array); a workgroup
 // that already sees the stop skips its domain.
-template <int DIM, bool GLOB>
+template <int DIM, bool GLOB, bool STAGE>
 __device__ inline void sweep_block(const SweepArgs& a, int b, int j, BatchProg* bp) {
   extern __shared__ double lds[];
   __shared__ BlockRed red;
@@ -162,6 +166,10 @@ __device__ inline void sweep_block(const SweepArgs& a, int b, int j, BatchProg* 
     if (j >= 2) decide_block(a, j - 1, red, s_flag, bp);
     return;
   }
+  // the domain's head is read together with the stop flag (one latency)
+  const int d = domain_of(a, b, 0, a.grid / 8);
+  DomainHead h{};
+  if (d >= 0) h = load_head<DIM>(a, d);
   // the decision workgroup may set `done` during this launch: read it once
   if (threadIdx.x == 0) s_flag = *(volatile const int*)&a.state->done;
   __syncthreads();
@@ -170,26 +178,29 @@ __device__ inline void sweep_block(const SweepArgs& a, int b, int j, BatchProg* 
   double* rout = a.rec[j & 1];
   long long npass = 0;
   double maxd = 0.0, sumr = 0.0;
-  const int d = domain_of(a, b, 0, a.grid / 8);
-  if (d >= 0) sweep_domain<DIM, GLOB>(a, d, rin, rout, lds, s_co, s_wu, npass, maxd, sumr);
+  if (d >= 0)
+    sweep_domain<DIM, GLOB, STAGE>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr);
   BlockPartial p = block_partial(npass, maxd, sumr, red);
   if (threadIdx.x == 0) a.partial[(int64_t)(j & 1) * a.grid + b] = p;
 }
 
 // Sweep j of one context: a.grid domain workgroups plus its decision workgroup.
-template <int DIM, bool GLOB>
-__global__ __launch_bounds__(kMaxBlock) void k_sweep(SweepArgs a, int j) {
-  sweep_block<DIM, GLOB>(a, blockIdx.x, j, nullptr);
+// The staged 2D form keeps to 96 VGPRs (five wavefronts per SIMD) so that a
+// launch of 2,048 two-wavefront domain workgroups plus the decision
+// workgroup is resident at once on 256 CUs.
+template <int DIM, bool GLOB, bool STAGE>
+__global__ __launch_bounds__(kMaxBlock, STAGE && DIM == 2 ? 5 : 1) void k_sweep(SweepArgs a, int j) {
+  sweep_block<DIM, GLOB, STAGE>(a, blockIdx.x, j, nullptr);
 }
 
 // Sweep j of a batch of packings: workgroup b serves packing blk[2b] as its
 // workgroup blk[2b+1] (tab holds each packing's arguments).
-template <int DIM>
+template <int DIM, bool STAGE>
 __global__ __launch_bounds__(kMaxBlock) void k_sweep_batch(const SweepArgs* tab, const int* blk,
                                                           int j, BatchProg* bp) {
   const int2 pb = ((const int2*)blk)[blockIdx.x];
   const SweepArgs a = tab[pb.x];
-  sweep_block<DIM, false>(a, pb.y, j, bp);
+  sweep_block<DIM, false, STAGE>(a, pb.y, j, bp);
 }
 
 // stop decision of sweep jd alone (after the last launched sweep)
@@ -275,7 +286,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(SweepArgs a, GridBar* bar, 
     for (int k = 0;; ++k) {
       const int d = domain_of(a, b, k, G8);
       if (d < 0) break;
-      sweep_domain<DIM, GLOB>(a, d, rin, rout, lds, s_co, s_wu, npass, maxd, sumr);
+      const DomainHead h = load_head<DIM>(a, d);
+      sweep_domain<DIM, GLOB, false>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr);
     }
     BlockPartial p = block_partial(npass, maxd, sumr, red);
     if (threadIdx.x == 0) {
@@ -417,7 +429,8 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.n_walls = c->W;
   a.rec[0] = c->rec[0];
   a.rec[1] = c->rec[1];
-  a.mu_slot = c->use_mu_slot ? c->mu_slot : nullptr;
+  a.mu_slot = c->use_mu_slot ? c->mu_slot : c->d_wall + CD_WALL_MU;
+  a.mu_step = c->use_mu_slot ? 1 : 0;
   a.state = c->d_state;
   a.partial = c->partial;
   a.prog = c->d_prog;
@@ -449,7 +462,62 @@ hipError_t cd_launch_solve_init(cd_ctx* c, int limit) {
   return hipGetLastError();
 }
 
-static size_t block_lds(cd_ctx* c) { return c->sweep_global ? 0 : c->sweep_lds; }
+static size_t block_lds(cd_ctx* c) {
+  return c->sweep_global ? 0 : (c->sweep_stage ? c->sweep_lds_stage : c->sweep_lds);
+}
+
+// Workgroups of kernel k resident per CU at this width and dynamic LDS
+// (cached: the query is not free and the answer depends only on these).
+static int resident_per_cu(const void* k, int block, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, int, size_t>, int> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto key = std::make_tuple(k, block, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block, lds) != hipSuccess) n = 0;
+  cache[key] = n;
+  return n;
+}
+
+size_t cd_stage_lds(cd_ctx* c, int max_particles, int max_contacts) {
+  const int ps = cd_stage_particle(c->dim);
+  const int sw = c->dim == 2 ? slot_stage_doubles<2>(c->use_mu_slot)
+                             : slot_stage_doubles<3>(c->use_mu_slot);
+  const size_t b = 8 * ((size_t)ps * std::max(max_particles, 1) +
+                        (size_t)sw * std::max(max_contacts, 1));
+  return (b + 31) / 32 * 32;
+}
+
+bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64_t workgroups,
+                   int num_cu, size_t max_lds, bool batch) {
+  if (lds_stage + 2048 > max_lds) return false;
+  const void* ks;
+  const void* kp;
+  if (batch) {
+    ks = dim == 2 ? (const void*)k_sweep_batch<2, true> : (const void*)k_sweep_batch<3, true>;
+    kp = dim == 2 ? (const void*)k_sweep_batch<2, false> : (const void*)k_sweep_batch<3, false>;
+  } else {
+    ks = dim == 2 ? (const void*)k_sweep<2, false, true> : (const void*)k_sweep<3, false, true>;
+    kp = dim == 2 ? (const void*)k_sweep<2, false, false> : (const void*)k_sweep<3, false, false>;
+  }
+  const int64_t rs = resident_per_cu(ks, block, lds_stage);
+  const int64_t rp = resident_per_cu(kp, block, lds_plain);
+  if (rs < 1) return false;
+  if (rp < 1) return true;
+  // staging must not add a round of workgroups
+  const int64_t slots_s = rs * num_cu, slots_p = rp * num_cu;
+  return (workgroups + slots_s - 1) / slots_s <= (workgroups + slots_p - 1) / slots_p;
+}
+
+void cd_sweep_mode(cd_ctx* c) {
+  c->sweep_stage = false;
+  if (c->sweep_global || c->stage_off) return;
+  c->sweep_lds_stage = cd_stage_lds(c, c->st_ds.max_particles, c->st_ds.max_contacts);
+  c->sweep_stage = cd_stage_pick(c->dim, c->sweep_block, c->sweep_lds, c->sweep_lds_stage,
+                                 (int64_t)8 * ((c->P + 7) / 8) + 1, c->num_cu, c->max_lds, false);
+}
 
 hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after) {
   SweepArgs a = cd_sweep_args(c);
@@ -461,14 +529,18 @@ hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after
   dim3 grid(a.grid + 1), block(c->sweep_block);
   if (c->dim == 2) {
     if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<2, true>), grid, block, 0, c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<2, true, false>), grid, block, 0, c->stream, a, j);
+    else if (c->sweep_stage)
+      hipLaunchKernelGGL((k_sweep<2, false, true>), grid, block, block_lds(c), c->stream, a, j);
     else
-      hipLaunchKernelGGL((k_sweep<2, false>), grid, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<2, false, false>), grid, block, block_lds(c), c->stream, a, j);
   } else {
     if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<3, true>), grid, block, 0, c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<3, true, false>), grid, block, 0, c->stream, a, j);
+    else if (c->sweep_stage)
+      hipLaunchKernelGGL((k_sweep<3, false, true>), grid, block, block_lds(c), c->stream, a, j);
     else
-      hipLaunchKernelGGL((k_sweep<3, false>), grid, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<3, false, false>), grid, block, block_lds(c), c->stream, a, j);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !after) return e;
@@ -476,11 +548,19 @@ hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after
 }
 
 hipError_t cd_launch_sweep_batch(hipStream_t stream, int dim, const SweepArgs* tab, const int* blk,
-                                 int grid, int block, size_t lds, int j, BatchProg* bp) {
-  if (dim == 2)
-    hipLaunchKernelGGL(k_sweep_batch<2>, dim3(grid), dim3(block), lds, stream, tab, blk, j, bp);
-  else
-    hipLaunchKernelGGL(k_sweep_batch<3>, dim3(grid), dim3(block), lds, stream, tab, blk, j, bp);
+                                 int grid, int block, size_t lds, bool stage, int j,
+                                 BatchProg* bp) {
+  if (dim == 2) {
+    if (stage)
+      hipLaunchKernelGGL((k_sweep_batch<2, true>), dim3(grid), dim3(block), lds, stream, tab, blk, j, bp);
+    else
+      hipLaunchKernelGGL((k_sweep_batch<2, false>), dim3(grid), dim3(block), lds, stream, tab, blk, j, bp);
+  } else {
+    if (stage)
+      hipLaunchKernelGGL((k_sweep_batch<3, true>), dim3(grid), dim3(block), lds, stream, tab, blk, j, bp);
+    else
+      hipLaunchKernelGGL((k_sweep_batch<3, false>), dim3(grid), dim3(block), lds, stream, tab, blk, j, bp);
+  }
   return hipGetLastError();
 }
 
@@ -501,14 +581,18 @@ hipError_t cd_launch_sweep_grid(cd_ctx* c, const SweepArgs& a, int j, int grid) 
   dim3 g(grid), block(c->sweep_block);
   if (c->dim == 2) {
     if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<2, true>), g, block, 0, c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<2, true, false>), g, block, 0, c->stream, a, j);
+    else if (c->sweep_stage)
+      hipLaunchKernelGGL((k_sweep<2, false, true>), g, block, block_lds(c), c->stream, a, j);
     else
-      hipLaunchKernelGGL((k_sweep<2, false>), g, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<2, false, false>), g, block, block_lds(c), c->stream, a, j);
   } else {
     if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<3, true>), g, block, 0, c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<3, true, false>), g, block, 0, c->stream, a, j);
+    else if (c->sweep_stage)
+      hipLaunchKernelGGL((k_sweep<3, false, true>), g, block, block_lds(c), c->stream, a, j);
     else
-      hipLaunchKernelGGL((k_sweep<3, false>), g, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<3, false, false>), g, block, block_lds(c), c->stream, a, j);
   }
   return hipGetLastError();
 }

@@ -81,6 +81,8 @@ __device__ inline void local_force(const double* n, const double* t1, const doub
 }
 
 constexpr int kMaxBlock = 256;
+// s_waitcnt immediate (gfx9 encoding) waiting for vmcnt = 0 only
+constexpr int kWaitVm0 = 0x0F70;
 
 // Workgroup barrier ordering LDS only: unlike __syncthreads it does not wait
 // for the wave's outstanding global loads and stores.
@@ -175,7 +177,8 @@ __device__ inline void gather_forces(const SweepArgs& a, const double* rin, int6
 }
 
 // Static data of one contact, read from memory into registers: body pair,
-// frame, g_e/dt, dt w_n, dt w_t, their reciprocals and the previous force.
+// frame, g_e/dt, dt w_n, dt w_t, their reciprocals (RECIP) and the previous
+// force.
 template <int DIM>
 struct SlotPre {
   int2 ab;
@@ -185,7 +188,7 @@ struct SlotPre {
   double Ro[DIM];
 };
 
-template <int DIM>
+template <int DIM, bool RECIP>
 __device__ inline void fetch_slot(const SweepArgs& a, const double* rin, int64_t s, SlotPre<DIM>& o) {
   constexpr int NG = Layout<DIM>::NG, REC = Layout<DIM>::REC;
   const int64_t cap = a.cap;
@@ -195,9 +198,14 @@ __device__ inline void fetch_slot(const SweepArgs& a, const double* rin, int64_t
   o.gdt = g[G_GDT * cap + s];
   o.dwn = g[G_DWN * cap + s];
   o.dwt = g[G_DWT * cap + s];
-  o.kn = g[G_KN * cap + s];
-  o.kt = g[G_KT * cap + s];
-  o.mu = a.mu_slot ? a.mu_slot[s] : a.mu;
+  if (RECIP) {
+    o.kn = g[G_KN * cap + s];
+    o.kt = g[G_KT * cap + s];
+  }
+  // always a global load (the shared coefficient sits in device memory too):
+  // choosing between device memory and the kernel arguments would compile to
+  // a flat load, which waits for every outstanding load and store of the wave
+  o.mu = a.mu_slot[s * a.mu_step];
   const double* ri = rin + s * REC;
   if (DIM == 2) {
     const double2 r2 = *(const double2*)ri;
@@ -206,6 +214,18 @@ __device__ inline void fetch_slot(const SweepArgs& a, const double* rin, int64_t
   } else {
     for (int q = 0; q < DIM; ++q) o.Ro[q] = ri[q];
   }
+}
+
+// Marks a read-ahead register set as arrived on every path (also in waves
+// with no contact to update): the empty statement reads every register, so
+// the wait for exactly this set's loads is taken here and its registers can
+// be reused later without draining all outstanding memory accesses.
+template <int DIM>
+__device__ inline void settle(const SlotPre<DIM>& c) {
+  asm volatile("" ::"v"(c.ab.x), "v"(c.ab.y), "v"(c.f[0]), "v"(c.f[1]), "v"(c.gdt), "v"(c.dwn),
+               "v"(c.dwt), "v"(c.kn), "v"(c.kt), "v"(c.mu), "v"(c.Ro[0]), "v"(c.Ro[1]));
+  if (DIM == 3)
+    asm volatile("" ::"v"(c.f[Layout<DIM>::NG - 1]), "v"(c.Ro[DIM - 1]));
 }
 
 // A body's staged record: velocities, dt/m, dt/I, r.
@@ -349,31 +369,114 @@ __device__ inline void update_contact(double* sp, const double* wu, const SlotPr
   account<DIM>(Rold, Rn, alpha, npass, maxd, sumr);
 }
 
-// One sweep of domain d by the calling workgroup: exchange, then the
-// colour-major update; accumulates the convergence test values of its
-// contacts.  GLOB: the particle records live in global scratch (domains
-// too large for LDS).
-template <int DIM, bool GLOB>
-__device__ inline void sweep_domain(const SweepArgs& a, int d, const double* rin, double* rout,
-                                    double* lds, int* s_co, double* s_wu, long long& npass,
-                                    double& maxd, double& sumr) {
+// Per-domain values a workgroup needs before its sweep: the descriptor
+// (first slot, slots, first particle entry, entries, colours), one colour
+// offset and one wall velocity component per thread.  Read before the stop
+// check so that their latency overlaps it.
+struct DomainHead {
+  int cs, nct, ps, np, ncol;
+  int co;       // colour offset number threadIdx.x (threads 0..CD_MAX_COLORS)
+  double wu;    // wall velocity component number threadIdx.x
+};
+
+template <int DIM>
+__device__ inline DomainHead load_head(const SweepArgs& a, int d) {
+  DomainHead h;
+  const int* dd = a.ddesc + 8 * (int64_t)d;
+  h.cs = dd[0];
+  h.nct = dd[1];
+  h.ps = dd[2];
+  h.np = dd[3];
+  h.ncol = dd[4];
+  const int tid = threadIdx.x;
+  // every colour offset of a domain is written (unused ones hold the count)
+  h.co = tid <= CD_MAX_COLORS ? a.dcol[(int64_t)d * (CD_MAX_COLORS + 1) + tid] : 0;
+  h.wu = tid < a.n_walls * DIM ? a.walls_u[tid] : 0.0;
+  return h;
+}
+
+// Doubles per staged slot in LDS: body pair, frame, g_e/dt, dt w_n, dt w_t,
+// previous force, and the friction coefficient when it is per slot.
+template <int DIM>
+__host__ __device__ constexpr int slot_stage_doubles(bool mu_per_slot) {
+  return 1 + Layout<DIM>::NG + 3 + DIM + (mu_per_slot ? 1 : 0);
+}
+
+// The domain's contact data, slot k at column k of an LDS block of `nct`
+// columns: pair (as one 8-byte word), frame, g_e/dt, dt w_n, dt w_t, the
+// previous sweep's force, friction if per slot.
+template <int DIM>
+__device__ inline void put_slot(double* sl, int nct, int k, const SlotPre<DIM>& c, bool mu_slot) {
+  constexpr int NG = Layout<DIM>::NG;
+  ((int2*)sl)[k] = c.ab;
+  for (int q = 0; q < NG; ++q) sl[(1 + q) * nct + k] = c.f[q];
+  sl[(1 + NG) * nct + k] = c.gdt;
+  sl[(2 + NG) * nct + k] = c.dwn;
+  sl[(3 + NG) * nct + k] = c.dwt;
+  for (int q = 0; q < DIM; ++q) sl[(4 + NG + q) * nct + k] = c.Ro[q];
+  if (mu_slot) sl[(4 + NG + DIM) * nct + k] = c.mu;
+}
+
+// Reads a staged slot back; the reciprocals 1/(dt w) are recomputed (the
+// same IEEE division as when the slot constants were built).
+template <int DIM>
+__device__ inline void get_slot(const double* sl, int nct, int k, double mu0, bool mu_slot,
+                                SlotPre<DIM>& c) {
+  constexpr int NG = Layout<DIM>::NG;
+  c.ab = ((const int2*)sl)[k];
+  for (int q = 0; q < NG; ++q) c.f[q] = sl[(1 + q) * nct + k];
+  c.gdt = sl[(1 + NG) * nct + k];
+  c.dwn = sl[(2 + NG) * nct + k];
+  c.dwt = sl[(3 + NG) * nct + k];
+  for (int q = 0; q < DIM; ++q) c.Ro[q] = sl[(4 + NG + q) * nct + k];
+  c.mu = mu_slot ? sl[(4 + NG + DIM) * nct + k] : mu0;
+  c.kn = 1.0 / c.dwn;
+  c.kt = 1.0 / c.dwt;
+}
+
+// One sweep of domain d (head h) by the calling workgroup: exchange, then
+// the colour-major update; accumulates the convergence test values of its
+// contacts.  GLOB: the particle records live in global scratch (domains too
+// large for LDS).  STAGE: the domain's contact data is copied to LDS
+// alongside the exchange (all its loads in flight at once) and the colours
+// read it from there; otherwise each thread reads its contact of the next
+// colour into registers one colour ahead.
+template <int DIM, bool GLOB, bool STAGE>
+__device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead& h,
+                                    const double* rin, double* rout, double* lds, int* s_co,
+                                    double* s_wu, long long& npass, double& maxd, double& sumr) {
+  static_assert(!(GLOB && STAGE), "staged contact data needs the particles in LDS");
   using L = Layout<DIM>;
   constexpr int DR = L::DR, REC = L::REC, PS = L::PS;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int* dd = a.ddesc + 8 * (int64_t)d;
-  // descriptor: first slot, slots, first particle entry, entries, colours
-  const int cs = dd[0], ps = dd[2], np = dd[3], ncol = dd[4];
+  const int cs = h.cs, nct = h.nct, ps = h.ps, np = h.np, ncol = h.ncol;
   double* sp = GLOB ? a.gscr + (int64_t)PS * ps : lds;
   const int* dcol = a.dcol + (int64_t)d * (CD_MAX_COLORS + 1);
-  // 0. colour offsets and wall velocities to LDS; this thread's contact of
-  //    the first colour read ahead (its latency overlaps the exchange)
-  for (int q = tid; q <= ncol; q += nthr) s_co[q] = dcol[q];
-  for (int q = tid; q < a.n_walls * DIM; q += nthr) s_wu[q] = a.walls_u[q];
+  // 0. colour offsets and wall velocities to LDS
+  if (tid <= CD_MAX_COLORS) s_co[tid] = h.co;
+  for (int q = tid + nthr; q <= CD_MAX_COLORS; q += nthr) s_co[q] = dcol[q];
+  if (tid < a.n_walls * DIM) s_wu[tid] = h.wu;
   SlotPre<DIM> cur;
   int kc = -1;
-  if (ncol > 0 && tid < dcol[1]) {
-    kc = tid;
-    fetch_slot<DIM>(a, rin, cs + kc, cur);
+  double* sl = lds + (int64_t)PS * np;
+  const bool mu_slot = a.mu_step != 0;
+  if (STAGE) {
+    // 1a. the domain's contact data to LDS, two slots per thread and pass
+    //     so that both reads are in flight together
+    for (int k = tid; k < nct; k += 2 * nthr) {
+      const int k2 = k + nthr;
+      const bool two = k2 < nct;
+      SlotPre<DIM> x, y;
+      fetch_slot<DIM, false>(a, rin, cs + k, x);
+      fetch_slot<DIM, false>(a, rin, cs + (two ? k2 : k), y);
+      put_slot<DIM>(sl, nct, k, x, mu_slot);
+      if (two) put_slot<DIM>(sl, nct, k2, y, mu_slot);
+    }
+  } else if (ncol > 0) {
+    // this thread's contact of the first colour read ahead (its latency
+    // overlaps the exchange); lanes without one read the first slot
+    kc = tid < dcol[1] ? tid : -1;
+    fetch_slot<DIM, true>(a, rin, cs + (kc >= 0 ? kc : 0), cur);
   }
   // 1. exchange: velocities from the previous sweep's forces
   const int64_t E = a.dpe;
@@ -396,33 +499,63 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const double* rin
     pr[L::P_R] = rp;
   }
   __syncthreads();
-  // 2. colour-major sequential update
-  for (int col = 0; col < ncol; ++col) {
-    const int k0 = s_co[col], k1 = s_co[col + 1];
-    // the next colour's contact of this thread, read ahead
-    SlotPre<DIM> nxt;
-    int kn = -1;
-    if (col + 1 < ncol && s_co[col + 1] + tid < s_co[col + 2]) {
-      kn = s_co[col + 1] + tid;
-      fetch_slot<DIM>(a, rin, cs + kn, nxt);
+  if (STAGE) {
+    // 2. colour-major sequential update from the staged contact data
+    const double mu0 = mu_slot ? 0.0 : a.mu_slot[0];
+    for (int col = 0; col < ncol; ++col) {
+      const int k0 = s_co[col], k1 = s_co[col + 1];
+      for (int k = k0 + tid; k < k1; k += nthr) {
+        SlotPre<DIM> c;
+        get_slot<DIM>(sl, nct, k, mu0, mu_slot, c);
+        update_contact<DIM>(sp, s_wu, c, a.alpha, rout + (int64_t)(cs + k) * REC, npass, maxd,
+                            sumr);
+      }
+      // the colour's velocity updates must be seen by the next colour; the
+      // record stores stay in flight
+      lds_barrier();
     }
-    if (kc >= 0)
-      update_contact<DIM>(sp, s_wu, cur, a.alpha, rout + (int64_t)(cs + kc) * REC, npass,
+    return;
+  }
+  // 2. colour-major sequential update.  Each thread's contact of the next
+  // colour is read into the other of two register sets while this colour is
+  // updated (no copy between the sets, so nothing waits for the read-ahead
+  // or the record stores before the next colour needs them).
+  auto colour = [&](int col, const SlotPre<DIM>& use, int ku, SlotPre<DIM>& pre, int& kp) {
+    const int k0 = s_co[col], k1 = s_co[col + 1];
+    // lanes without a next contact (all lanes in the last colour) read the
+    // domain's first slot: the loads are issued on every path, so the wait
+    // for them counts exactly instead of draining every outstanding access
+    kp = (col + 1 < ncol && k1 + tid < s_co[col + 2]) ? k1 + tid : -1;
+    fetch_slot<DIM, true>(a, rin, cs + (kp >= 0 ? kp : 0), pre);
+    settle<DIM>(use);
+    if (ku >= 0)
+      update_contact<DIM>(sp, s_wu, use, a.alpha, rout + (int64_t)(cs + ku) * REC, npass,
                           maxd, sumr);
-    // colours wider than the workgroup
-    for (int k = k0 + tid + nthr; k < k1; k += nthr) {
-      SlotPre<DIM> sd;
-      fetch_slot<DIM>(a, rin, cs + k, sd);
-      update_contact<DIM>(sp, s_wu, sd, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
-                          maxd, sumr);
+    // colours wider than the workgroup (rare); the path ends with all its
+    // memory accesses complete, so that it leaves no pending store whose
+    // registers the common path would have to wait for
+    if (k1 - k0 > nthr) {
+      for (int k = k0 + tid + nthr; k < k1; k += nthr) {
+        SlotPre<DIM> sd;
+        fetch_slot<DIM, true>(a, rin, cs + k, sd);
+        update_contact<DIM>(sp, s_wu, sd, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
+                            maxd, sumr);
+      }
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
     }
     // the colour's velocity updates must be seen by the next colour; the
     // record stores and the read-ahead loads stay in flight
     if (GLOB) __syncthreads();
     else lds_barrier();
-    if (kn >= 0) cur = nxt;
-    kc = kn;
+  };
+  SlotPre<DIM> other;
+  int ko = -1;
+  int col = 0;
+  for (; col + 1 < ncol; col += 2) {
+    colour(col, cur, kc, other, ko);
+    colour(col + 1, other, ko, cur, kc);
   }
+  if (col < ncol) colour(col, cur, kc, other, ko);
 }
 
 }  // namespace

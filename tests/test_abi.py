@@ -33,7 +33,7 @@ def test_struct_layouts_match_header():
     # the ctypes mirrors have the C sizes of the header structs
     assert ctypes.sizeof(binding.Params) == 4 * 2 + 8 * 3 + 4 * 8 + 8
     assert ctypes.sizeof(binding.Result) == 4 * 2 + 8 * 2 + 8 * 4 + 4 * 2
-    assert ctypes.sizeof(binding.Timing) == 8 * 6 + 4 * 4
+    assert ctypes.sizeof(binding.Timing) == 8 * 6 + 4 * 6
     assert ctypes.sizeof(binding.BatchTiming) == 8 * 4 + 4 * 6
 
 

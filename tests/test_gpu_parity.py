@@ -104,11 +104,15 @@ def test_disks_1k_single_domain(criterion):
     compare_step(sim, ctx, f"disks_1k crit{criterion}")
 
 
-def test_disks_4k_64_domains_multi_step():
+@pytest.mark.parametrize("solve_mode", [1, 2])
+def test_disks_4k_64_domains_multi_step(solve_mode):
+    """Mode 1 stages each domain's contact data in LDS here; mode 2 reads it
+    into registers one colour ahead."""
     pk = inputs.lattice_2d(64, 64, 11)
-    sim, ctx = both(pk, mu=0.3, n_domains=64, repartition_every=2)
+    sim, ctx = both(pk, solve_mode=solve_mode, mu=0.3, n_domains=64, repartition_every=2)
     for s in range(4):
-        compare_step(sim, ctx, f"disks_4k step{s}")
+        compare_step(sim, ctx, f"disks_4k mode{solve_mode} step{s}")
+    assert ctx.timing().staged == (1 if solve_mode == 1 else 0)
 
 
 def test_one_launch_solve_mode():
@@ -120,18 +124,20 @@ def test_one_launch_solve_mode():
         compare_step(sim, ctx, f"one-launch mode step{s}")
 
 
-def test_ragged_lattice_odd_domain_count():
+@pytest.mark.parametrize("solve_mode", [1, 2])
+def test_ragged_lattice_odd_domain_count(solve_mode):
     pk = inputs.lattice_2d(45, 37, 12, n=1600)
-    sim, ctx = both(pk, mu=0.25, n_domains=14, repartition_every=3)
+    sim, ctx = both(pk, solve_mode=solve_mode, mu=0.25, n_domains=14, repartition_every=3)
     for s in range(3):
-        compare_step(sim, ctx, f"ragged step{s}")
+        compare_step(sim, ctx, f"ragged mode{solve_mode} step{s}")
 
 
-def test_spheres_3d_moving_wall():
+@pytest.mark.parametrize("solve_mode", [1, 2])
+def test_spheres_3d_moving_wall(solve_mode):
     pk = inputs.lattice_3d(12, 12, 10, 13, gravity=1.0, top_velocity=1e-3)
-    sim, ctx = both(pk, mu=0.5, n_domains=16, repartition_every=2)
+    sim, ctx = both(pk, solve_mode=solve_mode, mu=0.5, n_domains=16, repartition_every=2)
     for s in range(3):
-        compare_step(sim, ctx, f"spheres step{s}")
+        compare_step(sim, ctx, f"spheres mode{solve_mode} step{s}")
 
 
 def test_fixed_sweeps_and_signed_gap():
@@ -179,6 +185,17 @@ def test_full_size_disks_262k_4096_domains_fixed_sweeps():
     pk = inputs.config("disks_262k")
     sim, ctx = both(pk, mu=0.3, n_domains=4096, repartition_every=10, fixed_iters=20)
     compare_step(sim, ctx, "262k fixed20")
+
+
+@pytest.mark.parametrize("solve_mode", [1, 2])
+def test_full_size_disks_262k_2048_domains_both_forms(solve_mode):
+    """512x512 disks, 2048 domains (the bench's default), 20 sweeps: the
+    staged form (mode 1 picks it at this size) and the register form."""
+    pk = inputs.config("disks_262k")
+    sim, ctx = both(pk, solve_mode=solve_mode, mu=0.3, n_domains=2048, repartition_every=10,
+                    fixed_iters=20)
+    compare_step(sim, ctx, f"262k 2048 domains mode{solve_mode}")
+    assert ctx.timing().staged == (1 if solve_mode == 1 else 0)
 
 
 def test_full_size_disks_262k_300_sweeps_then_next_step():
