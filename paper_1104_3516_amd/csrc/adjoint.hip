@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep_adjoint(SweepArgs a, const 
     for (int k = 0; k < 2; ++k) acc[k] = a.dpb[(3 + k) * E + e];
     tacc[0] = a.dpb[5 * E + e];
     const double dm = a.dpb[6 * E + e], di = a.dpb[7 * E + e], rp = a.dpb[8 * E + e];
-    gather_forces<2>(a, rin, e, rp, acc, tacc);
+    gather_forces<2>(a, rin, e, ((const int4*)a.drow)[e], rp, acc, tacc);
     double* pr = sp + (int64_t)PS * l;
     for (int k = 0; k < 2; ++k) pr[k] = a.dpb[k * E + e] + dm * acc[k];
     pr[L::P_W] = a.dpb[2 * E + e] + di * tacc[0];

@@ -175,6 +175,7 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
       limit = std::max(limit, c->st_limit);
     }
   }
+  for (int p = 0; p < B; ++p) b->h_tab[p].block = block;   // one width for the whole batch
   BTRY(hipMemcpyAsync(b->d_tab, b->h_tab, sizeof(SweepArgs) * B, hipMemcpyHostToDevice,
                       b->stream));
   // contact data staged in LDS when that costs no extra round of workgroups

@@ -118,6 +118,7 @@ struct SweepArgs {
   int n;                    // particles (SoA stride)
   int cap;                  // slot capacity (SoA stride of geo)
   int grid;                 // blocks of a one-sweep launch
+  int block;                // threads per block of a sweep launch
   int per_xcd;              // domains per XCD in the block -> domain map
   int wave_lds;             // LDS staging per wavefront (doubles)
   long long nc;

@@ -42,8 +42,8 @@ struct BlockRed {
 // Fixed-order reduction of per-thread test values over the workgroup;
 // thread 0 gets the totals.
 __device__ inline BlockPartial block_partial(long long npass, double maxd, double sumr,
-                                             BlockRed& sh) {
-  const int tid = threadIdx.x, nthr = blockDim.x;
+                                             BlockRed& sh, int nthr) {
+  const int tid = threadIdx.x;
   for (int off = 32; off > 0; off >>= 1) {
     npass += __shfl_xor(npass, off, 64);
     double o = __shfl_xor(maxd, off, 64);
@@ -117,28 +117,29 @@ __device__ inline void decide_sweep(const SweepArgs& a, SolveState* st, int j, l
 
 // Fixed-order reduction of `count` workgroup partials by the calling
 // workgroup; thread 0 receives the totals.
-__device__ inline BlockPartial reduce_partials(const BlockPartial* part, int count, BlockRed& sh) {
+__device__ inline BlockPartial reduce_partials(const BlockPartial* part, int count, BlockRed& sh,
+                                               int nthr) {
   long long tn = 0;
   double tm = 0.0, ts = 0.0;
-  for (int q = threadIdx.x; q < count; q += blockDim.x) {
+  for (int q = threadIdx.x; q < count; q += nthr) {
     const BlockPartial p = part[q];
     tn += p.n_pass;
     if (p.max_d_fail > tm || p.max_d_fail != p.max_d_fail) tm = p.max_d_fail;
     ts += p.sum_r;
   }
-  return block_partial(tn, tm, ts, sh);
+  return block_partial(tn, tm, ts, sh, nthr);
 }
 
 // Stop decision of sweep jd by the calling workgroup: fixed-order reduction
 // of that sweep's workgroup partials, test (I) or (II), and the progress
 // record for the host.  No-op once the solve is done.
 __device__ inline void decide_block(const SweepArgs& a, int jd, BlockRed& red, int& s_flag,
-                                    BatchProg* bp) {
+                                    BatchProg* bp, int nthr) {
   SolveState* st = a.state;
   if (threadIdx.x == 0) s_flag = *(volatile const int*)&st->done;
   __syncthreads();
   if (s_flag) return;
-  BlockPartial t = reduce_partials(a.partial + (int64_t)(jd & 1) * a.grid, a.grid, red);
+  BlockPartial t = reduce_partials(a.partial + (int64_t)(jd & 1) * a.grid, a.grid, red, nthr);
   if (threadIdx.x == 0) {
     decide_sweep(a, st, jd, t.n_pass, t.max_d_fail, t.sum_r);
     __hip_atomic_store(&a.prog->done, st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -163,7 +164,7 @@ __device__ inline void sweep_block(const SweepArgs& a, int b, int j, BatchProg* 
   __shared__ double s_wu[CD_MAX_WALLS * 3];
   __shared__ int s_flag;
   if (b == a.grid) {
-    if (j >= 2) decide_block(a, j - 1, red, s_flag, bp);
+    if (j >= 2) decide_block(a, j - 1, red, s_flag, bp, a.block);
     return;
   }
   // the domain's head is read together with the stop flag (one latency)
@@ -180,7 +181,7 @@ __device__ inline void sweep_block(const SweepArgs& a, int b, int j, BatchProg* 
   double maxd = 0.0, sumr = 0.0;
   if (d >= 0)
     sweep_domain<DIM, GLOB, STAGE>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr);
-  BlockPartial p = block_partial(npass, maxd, sumr, red);
+  BlockPartial p = block_partial(npass, maxd, sumr, red, a.block);
   if (threadIdx.x == 0) a.partial[(int64_t)(j & 1) * a.grid + b] = p;
 }
 
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep_batch(const SweepArgs* tab,
 __global__ __launch_bounds__(kMaxBlock) void k_decide(SweepArgs a, int jd) {
   __shared__ BlockRed red;
   __shared__ int s_flag;
-  decide_block(a, jd, red, s_flag, nullptr);
+  decide_block(a, jd, red, s_flag, nullptr, kMaxBlock);
 }
 
 // the same for every packing of a batch: workgroup p decides packing p
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_decide_batch(const SweepArgs* tab
   __shared__ BlockRed red;
   __shared__ int s_flag;
   const SweepArgs a = tab[blockIdx.x];
-  decide_block(a, jd, red, s_flag, bp);
+  decide_block(a, jd, red, s_flag, bp, kMaxBlock);
 }
 
 // solve states of a batch gathered into one array (one copy to the host)
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(SweepArgs a, GridBar* bar, 
   const int b = blockIdx.x, x = b % 8, G8 = G / 8;
   int owe = 0;   // sweep whose decision this block owes (0: none)
   auto decide = [&](int jd) {
-    BlockPartial t = reduce_partials(a.partial + (int64_t)(jd & 1) * G, G, red);
+    BlockPartial t = reduce_partials(a.partial + (int64_t)(jd & 1) * G, G, red, blockDim.x);
     if (threadIdx.x == 0) {
       if (!__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         decide_sweep(a, st, jd, t.n_pass, t.max_d_fail, t.sum_r);
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(SweepArgs a, GridBar* bar, 
       const DomainHead h = load_head<DIM>(a, d);
       sweep_domain<DIM, GLOB, false>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr);
     }
-    BlockPartial p = block_partial(npass, maxd, sumr, red);
+    BlockPartial p = block_partial(npass, maxd, sumr, red, blockDim.x);
     if (threadIdx.x == 0) {
       a.partial[(int64_t)(j & 1) * G + b] = p;
       // this block's forces and partial, device-wide, before the arrival
@@ -439,6 +440,7 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.cap = (int)c->cap;
   a.per_xcd = (c->P + 7) / 8;
   a.grid = 8 * a.per_xcd;
+  a.block = c->sweep_block;
   a.drow = c->drow;
   a.ddesc = c->ddesc;
   a.nc = c->nc;

@@ -128,14 +128,14 @@ __device__ inline void add_record(const double* rin, int ent, double rp, double*
 }
 
 template <int DIM>
-__device__ inline void gather_forces(const SweepArgs& a, const double* rin, int64_t e, double rp,
-                                     double* acc, double* tacc) {
+__device__ inline void gather_forces(const SweepArgs& a, const double* rin, int64_t e, int4 r4i,
+                                     double rp, double* acc, double* tacc) {
   constexpr int REC = DIM == 2 ? 4 : 12;
   constexpr int KW = DIM == 2 ? 8 : 16;
-  // incidence rows: KW/4 planes of int4 (plane q: entries 4q..4q+3)
+  // incidence rows: KW/4 planes of int4 (plane q: entries 4q..4q+3); the
+  // first plane (r4i) is read by the caller
   const int4* rows = (const int4*)a.drow;
   const int64_t E = a.dpe;
-  int4 r4i = rows[e];
   if (r4i.x == -2) {
     // more incidences than a row holds: the pointer list
     const int e1 = a.dinc_ptr[e + 1];
@@ -369,6 +369,51 @@ __device__ inline void update_contact(double* sp, const double* wu, const SlotPr
   account<DIM>(Rold, Rn, alpha, npass, maxd, sumr);
 }
 
+// Base data of one domain particle entry read into registers: base
+// velocities, external force and torque, dt/m, dt/I, r, and the first plane
+// of its incidence row.
+template <int DIM>
+struct EntryPre {
+  double v[DIM], w[Layout<DIM>::DR], f[DIM], t[Layout<DIM>::DR], dm, di, r;
+  int4 row;
+};
+
+template <int DIM>
+__device__ inline void entry_load(const SweepArgs& a, int64_t e, EntryPre<DIM>& o) {
+  constexpr int DR = Layout<DIM>::DR;
+  const int64_t E = a.dpe;
+  for (int k = 0; k < DIM; ++k) o.v[k] = a.dpb[k * E + e];
+  for (int k = 0; k < DR; ++k) o.w[k] = a.dpb[(DIM + k) * E + e];
+  int q = DIM + DR;
+  for (int k = 0; k < DIM; ++k) o.f[k] = a.dpb[(q + k) * E + e];
+  q += DIM;
+  for (int k = 0; k < DR; ++k) o.t[k] = a.dpb[(q + k) * E + e];
+  q += DR;
+  o.dm = a.dpb[q * E + e];
+  o.di = a.dpb[(q + 1) * E + e];
+  o.r = a.dpb[(q + 2) * E + e];
+  o.row = ((const int4*)a.drow)[e];
+}
+
+// The entry's velocities from its base data and the previous sweep's forces
+// on it (ascending contact id), written as staged particle record l.
+template <int DIM>
+__device__ inline void entry_finish(const SweepArgs& a, const double* rin, int64_t e,
+                                    const EntryPre<DIM>& o, double* sp, int l) {
+  using L = Layout<DIM>;
+  constexpr int DR = L::DR, PS = L::PS;
+  double acc[DIM], tacc[DR];
+  for (int k = 0; k < DIM; ++k) acc[k] = o.f[k];
+  for (int k = 0; k < DR; ++k) tacc[k] = o.t[k];
+  gather_forces<DIM>(a, rin, e, o.row, o.r, acc, tacc);
+  double* pr = sp + (int64_t)PS * l;
+  for (int k = 0; k < DIM; ++k) pr[k] = o.v[k] + o.dm * acc[k];
+  for (int k = 0; k < DR; ++k) pr[L::P_W + k] = o.w[k] + o.di * tacc[k];
+  pr[L::P_DM] = o.dm;
+  pr[L::P_DI] = o.di;
+  pr[L::P_R] = o.r;
+}
+
 // Per-domain values a workgroup needs before its sweep: the descriptor
 // (first slot, slots, first particle entry, entries, colours), one colour
 // offset and one wall velocity component per thread.  Read before the stop
@@ -447,8 +492,8 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
                                     double* s_wu, long long& npass, double& maxd, double& sumr) {
   static_assert(!(GLOB && STAGE), "staged contact data needs the particles in LDS");
   using L = Layout<DIM>;
-  constexpr int DR = L::DR, REC = L::REC, PS = L::PS;
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  constexpr int REC = L::REC, PS = L::PS;
+  const int tid = threadIdx.x, nthr = a.block;
   const int cs = h.cs, nct = h.nct, ps = h.ps, np = h.np, ncol = h.ncol;
   double* sp = GLOB ? a.gscr + (int64_t)PS * ps : lds;
   const int* dcol = a.dcol + (int64_t)d * (CD_MAX_COLORS + 1);
@@ -461,42 +506,47 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
   double* sl = lds + (int64_t)PS * np;
   const bool mu_slot = a.mu_step != 0;
   if (STAGE) {
-    // 1a. the domain's contact data to LDS, two slots per thread and pass
-    //     so that both reads are in flight together
-    for (int k = tid; k < nct; k += 2 * nthr) {
-      const int k2 = k + nthr;
-      const bool two = k2 < nct;
+    // 1. this thread's first two contacts and first particle entry: every
+    //    read is issued before any is used (indices clamped to valid ones
+    //    so that the loads are unconditional), then the contact data goes
+    //    to LDS while the entry's force gathers are in flight
+    {
+      const int k1 = tid, k2 = tid + nthr;
       SlotPre<DIM> x, y;
-      fetch_slot<DIM, false>(a, rin, cs + k, x);
-      fetch_slot<DIM, false>(a, rin, cs + (two ? k2 : k), y);
-      put_slot<DIM>(sl, nct, k, x, mu_slot);
-      if (two) put_slot<DIM>(sl, nct, k2, y, mu_slot);
+      EntryPre<DIM> ep;
+      const int64_t s0 = nct > 0 ? cs : 0;
+      fetch_slot<DIM, false>(a, rin, s0 + (k1 < nct ? k1 : 0), x);
+      fetch_slot<DIM, false>(a, rin, s0 + (k2 < nct ? k2 : 0), y);
+      const int64_t e1 = np > 0 ? ps + (tid < np ? tid : 0) : 0;
+      entry_load<DIM>(a, e1, ep);
+      if (k1 < nct) put_slot<DIM>(sl, nct, k1, x, mu_slot);
+      if (k2 < nct) put_slot<DIM>(sl, nct, k2, y, mu_slot);
+      if (tid < np) entry_finish<DIM>(a, rin, e1, ep, sp, tid);
     }
-  } else if (ncol > 0) {
-    // this thread's contact of the first colour read ahead (its latency
-    // overlaps the exchange); lanes without one read the first slot
-    kc = tid < dcol[1] ? tid : -1;
-    fetch_slot<DIM, true>(a, rin, cs + (kc >= 0 ? kc : 0), cur);
-  }
-  // 1. exchange: velocities from the previous sweep's forces
-  const int64_t E = a.dpe;
-  for (int l = tid; l < np; l += nthr) {
-    const int64_t e = ps + l;
-    double acc[DIM], tacc[DR];
-    int q = DIM + DR;
-    for (int k = 0; k < DIM; ++k) acc[k] = a.dpb[(q + k) * E + e];
-    q += DIM;
-    for (int k = 0; k < DR; ++k) tacc[k] = a.dpb[(q + k) * E + e];
-    q += DR;
-    const double dm = a.dpb[q * E + e], di = a.dpb[(q + 1) * E + e];
-    const double rp = a.dpb[(q + 2) * E + e];
-    gather_forces<DIM>(a, rin, e, rp, acc, tacc);
-    double* pr = sp + (int64_t)PS * l;
-    for (int k = 0; k < DIM; ++k) pr[k] = a.dpb[k * E + e] + dm * acc[k];
-    for (int k = 0; k < DR; ++k) pr[L::P_W + k] = a.dpb[(DIM + k) * E + e] + di * tacc[k];
-    pr[L::P_DM] = dm;
-    pr[L::P_DI] = di;
-    pr[L::P_R] = rp;
+    // the rest (domains larger than two contacts or one entry per thread)
+    for (int k = tid + 2 * nthr; k < nct; k += nthr) {
+      SlotPre<DIM> x;
+      fetch_slot<DIM, false>(a, rin, cs + k, x);
+      put_slot<DIM>(sl, nct, k, x, mu_slot);
+    }
+    for (int l = tid + nthr; l < np; l += nthr) {
+      EntryPre<DIM> ep;
+      entry_load<DIM>(a, ps + l, ep);
+      entry_finish<DIM>(a, rin, ps + l, ep, sp, l);
+    }
+  } else {
+    if (ncol > 0) {
+      // this thread's contact of the first colour read ahead (its latency
+      // overlaps the exchange); lanes without one read the first slot
+      kc = tid < dcol[1] ? tid : -1;
+      fetch_slot<DIM, true>(a, rin, cs + (kc >= 0 ? kc : 0), cur);
+    }
+    // 1. exchange: velocities from the previous sweep's forces
+    for (int l = tid; l < np; l += nthr) {
+      EntryPre<DIM> ep;
+      entry_load<DIM>(a, ps + l, ep);
+      entry_finish<DIM>(a, rin, ps + l, ep, sp, l);
+    }
   }
   __syncthreads();
   if (STAGE) {
