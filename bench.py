@@ -490,7 +490,8 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
                      "traffic": traffic,
-                     "kernel": f"k_solve<{dim}>" if args.solve_mode == 0 else f"k_sweep<{dim}>",
+                     "kernel": (f"k_solve<{dim}>" if args.solve_mode == 0 else
+                                f"k_sweep<{dim}, {'staged' if tm.staged else 'register'}>"),
                      "bytes_per_sweep": bytes_per_sweep},
     }
     if args.cpu_sweeps > 0:
