@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "cd_internal.h"
@@ -35,6 +36,11 @@ struct cd_batch {
   std::vector<int> failed;      // per packing: 0, or the error that took it out
   std::vector<hipEvent_t> sweep_ev;
   hipEvent_t ev[4] = {};
+  // lanes: the per-packing preparation and update are spread over a few
+  // streams, each fed by its own host thread, so that the many small
+  // kernels of different packings run side by side
+  std::vector<hipStream_t> lane;
+  std::vector<hipEvent_t> lane_ev;
   cd_batch_timing timing{};
   std::string err;
 };
@@ -44,6 +50,74 @@ namespace {
 int bfail(cd_batch* b, int code, const std::string& msg) {
   b->err = msg;
   return code;
+}
+
+constexpr int kLanes = 4;
+
+// The packings' work on the lanes: packing p on lane p % lanes.
+void lanes_attach(cd_batch* b) {
+  for (size_t p = 0; p < b->ctx.size(); ++p) b->ctx[p]->stream = b->lane[p % b->lane.size()];
+}
+void lanes_detach(cd_batch* b) {
+  for (cd_ctx* c : b->ctx) c->stream = b->stream;
+}
+
+// Every lane waits for what the batch stream has queued so far.
+hipError_t lanes_after_batch_stream(cd_batch* b) {
+  hipError_t e = hipEventRecord(b->lane_ev[0], b->stream);
+  for (size_t t = 0; e == hipSuccess && t < b->lane.size(); ++t)
+    e = hipStreamWaitEvent(b->lane[t], b->lane_ev[0], 0);
+  return e;
+}
+
+// The batch stream waits for everything queued on the lanes.
+hipError_t batch_stream_after_lanes(cd_batch* b) {
+  hipError_t e = hipSuccess;
+  for (size_t t = 0; e == hipSuccess && t < b->lane.size(); ++t) {
+    e = hipEventRecord(b->lane_ev[1 + t], b->lane[t]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->lane_ev[1 + t], 0);
+  }
+  return e;
+}
+
+hipError_t lanes_sync(cd_batch* b) {
+  hipError_t e = hipSuccess;
+  for (hipStream_t s : b->lane)
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
+// fn(p) for every packing still in the batch, lane t's packings on host
+// thread t.  With `soft`, a packing whose step fails with a per-packing
+// error (bad input, non-finite state) leaves the batch; any other error is
+// returned for the first packing that raised it.
+template <class F>
+int over_lanes(cd_batch* b, bool soft, F fn) {
+  const int B = (int)b->ctx.size(), S = (int)b->lane.size();
+  std::vector<int> st(S, CD_OK), at(S, -1);
+  auto work = [&](int t) {
+    for (int p = t; p < B; p += S) {
+      if (b->failed[p]) continue;
+      const int r = fn(p);
+      if (soft && (r == CD_EINVAL || r == CD_ENONFINITE)) {
+        b->failed[p] = r;
+        continue;
+      }
+      if (r != CD_OK) {
+        st[t] = r;
+        at[t] = p;
+        return;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < S; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& x : th) x.join();
+  for (int t = 0; t < S; ++t)
+    if (st[t] != CD_OK)
+      return bfail(b, st[t], "packing " + std::to_string(at[t]) + ": " + cd_last_error(b->ctx[at[t]]));
+  return CD_OK;
 }
 
 #define BTRY(expr)                                                               \
@@ -103,6 +177,17 @@ int cd_batch_create(cd_batch** out, cd_ctx* const* ctxs, int count) {
     st = CD_EHIP;
   for (int k = 0; k < 4 && st == CD_OK; ++k)
     if (hipEventCreate(&b->ev[k]) != hipSuccess) st = CD_EHIP;
+  const int lanes = std::min(kLanes, (int)count);
+  for (int t = 0; t < lanes && st == CD_OK; ++t) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) st = CD_EHIP;
+    else b->lane.push_back(s);
+  }
+  for (int t = 0; t <= lanes && st == CD_OK; ++t) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) st = CD_EHIP;
+    else b->lane_ev.push_back(e);
+  }
   if (st != CD_OK) {
     cd_batch_destroy(b);
     return st;
@@ -125,6 +210,10 @@ int cd_batch_destroy(cd_batch* b) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : b->sweep_ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : b->lane_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& s : b->lane)
+    if (s) (void)hipStreamDestroy(s);
   delete b;
   return CD_OK;
 }
@@ -144,18 +233,27 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
   // velocities broke the displacement bound or turned non-finite (its solve
   // diverged, Sec. 2.3) leaves the batch: its result carries the error in
   // every later step.
+  BTRY(lanes_after_batch_stream(b));
+  lanes_attach(b);
   for (int k = 0; k < kPrepPhases; ++k) {
-    if (k > 0) BTRY(hipStreamSynchronize(b->stream));
-    for (int p = 0; p < B; ++p) {
-      if (b->failed[p]) continue;
-      int st = prep_phase(b->ctx[p], k);
-      if (st == CD_EINVAL || st == CD_ENONFINITE) {
-        b->failed[p] = st;
-        continue;
+    if (k > 0) {
+      hipError_t e = lanes_sync(b);
+      if (e != hipSuccess) {
+        lanes_detach(b);
+        return bfail(b, CD_EHIP, hipGetErrorString(e));
       }
-      if (st != CD_OK)
-        return bfail(b, st, "packing " + std::to_string(p) + ": " + cd_last_error(b->ctx[p]));
     }
+    int st = over_lanes(b, true, [&](int p) { return prep_phase(b->ctx[p], k); });
+    if (st != CD_OK) {
+      (void)lanes_sync(b);
+      lanes_detach(b);
+      return st;
+    }
+  }
+  {
+    hipError_t e = batch_stream_after_lanes(b);
+    lanes_detach(b);
+    if (e != hipSuccess) return bfail(b, CD_EHIP, hipGetErrorString(e));
   }
   BTRY(hipEventRecord(b->ev[1], b->stream));
   // ---- the batched solve
@@ -280,11 +378,14 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
   // ---- every packing's update: launches for all, one synchronisation,
   // then walls, results and timings
   int status = CD_OK;
-  for (int p = 0; p < B; ++p) {
-    if (b->failed[p]) continue;
-    int st = finish_enqueue(b->ctx[p]);
-    if (st != CD_OK)
-      return bfail(b, st, "packing " + std::to_string(p) + ": " + cd_last_error(b->ctx[p]));
+  BTRY(lanes_after_batch_stream(b));
+  lanes_attach(b);
+  {
+    int st = over_lanes(b, false, [&](int p) { return finish_enqueue(b->ctx[p]); });
+    hipError_t e = lanes_sync(b);
+    lanes_detach(b);
+    if (st != CD_OK) return st;
+    if (e != hipSuccess) return bfail(b, CD_EHIP, hipGetErrorString(e));
   }
   BTRY(hipStreamSynchronize(b->stream));
   for (int p = 0; p < B; ++p) {
