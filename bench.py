@@ -487,6 +487,7 @@ def main() -> int:
         "sweeps_timed": timed,
         "solve_mode": args.solve_mode,
         "block_threads": tm.block_threads, "contact_data_in_lds": bool(tm.staged),
+        "decision_in_workgroup0": tm.staged == 2,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
                      "traffic": traffic,

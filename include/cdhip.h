@@ -98,7 +98,8 @@ typedef struct cd_timing {
   int sweeps_executed;   /* sweeps computed, including the one the stop decision overlaps */
   int block_threads;     /* threads of the workgroup that sweeps one domain */
   int sweeps_timed;      /* sweep launches inside the timed groups (per-sweep mode) */
-  int staged;            /* 1: the sweeps read each domain's contact data from LDS */
+  int staged;            /* 1: the sweeps read each domain's contact data from LDS;
+                            2: and workgroup 0 also took each stop decision */
   int pad;
 } cd_timing;
 

@@ -763,6 +763,7 @@ int solve_single(cd_ctx* c) {
   bool one_launch = false;
   int groups_closed = 0;
   c->sweep_stage = false;   // the one-launch solve never stages
+  c->sweep_fold = false;
   const int G = c->persistent ? cd_solve_grid(c) : 0;
   if (G < 8) cd_sweep_mode(c);
   if (G >= 8 && nc > 0 && limit > 0) {
@@ -955,7 +956,7 @@ int finish_complete(cd_ctx* c, cd_result* out) {
     tm.sweeps_timed = cnt;
   }
   tm.sweep_kernel_ms = sk;
-  tm.staged = c->sweep_stage ? 1 : 0;
+  tm.staged = c->sweep_stage ? (c->sweep_fold ? 2 : 1) : 0;
   c->timing = tm;
   if (c->block_override < 0 && tm.sweeps_timed > 0)
     tune_block_record(c, 1e3 * sk / std::max(executed, 1));

@@ -278,8 +278,8 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
                       b->stream));
   // contact data staged in LDS when that costs no extra round of workgroups
   const bool stg = !b->ctx[0]->stage_off &&
-                   cd_stage_pick(b->dim, block, lds, lds_stage, b->grid_total, b->ctx[0]->num_cu,
-                                 b->ctx[0]->max_lds, true);
+                   cd_stage_pick(b->dim, block, lds, lds_stage, b->grid_total, b->grid_total,
+                                 b->ctx[0]->num_cu, b->ctx[0]->max_lds, true);
   const size_t lds_launch = stg ? lds_stage : lds;
   b->staged = stg;
   const int every = b->time_every;

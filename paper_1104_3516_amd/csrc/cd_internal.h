@@ -294,6 +294,7 @@ struct cd_ctx {
   size_t sweep_lds = 0;     // LDS staging per wavefront (domain), bytes
   size_t sweep_lds_stage = 0;  // the same with the domain's contact data staged too
   bool sweep_stage = false;    // this solve stages contact data in LDS
+  bool sweep_fold = false;     // ... and takes the stop decision in workgroup 0
   bool stage_off = false;      // never stage (the register read-ahead form only)
 
   // timing
@@ -359,8 +360,8 @@ hipError_t cd_launch_sweep_batch(hipStream_t stream, int dim, const SweepArgs* t
 size_t cd_stage_lds(cd_ctx* c, int max_particles, int max_contacts);
 // whether a launch of `workgroups` should stage contact data: it must fit and
 // must not need more rounds of resident workgroups than the register form
-bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64_t workgroups,
-                   int num_cu, size_t max_lds, bool batch);
+bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64_t wg_stage,
+                   int64_t wg_plain, int num_cu, size_t max_lds, bool batch);
 // sets sweep_stage / sweep_lds_stage for the coming per-sweep solve
 void cd_sweep_mode(cd_ctx* c);
 hipError_t cd_launch_decide_batch(hipStream_t stream, const SweepArgs* tab, int B, int jd,

@@ -213,7 +213,10 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     dd[2] = ps;
     dd[3] = np;
     dd[4] = ncol;
-    dd[5] = dd[6] = dd[7] = 0;
+    int widest = 0;   // the largest colour
+    for (int q = 0; q < ncol; ++q) widest = max(widest, s_coloff[q + 1] - s_coloff[q]);
+    dd[5] = widest;
+    dd[6] = dd[7] = 0;
     atomicMax(&a.stats->max_colors, ncol);
     atomicMax(&a.stats->max_contacts, nct);
     atomicMax(&a.stats->max_particles, np);

@@ -152,18 +152,67 @@ __device__ inline void decide_block(const SweepArgs& a, int jd, BlockRed& red, i
   }
 }
 
+// The same decision taken by one wavefront alone (the calling wave's 64
+// lanes): strided fixed-order sums of the partials, then a butterfly.
+__device__ inline void decide_wave(const SweepArgs& a, int jd) {
+  SolveState* st = a.state;
+  const int lane = threadIdx.x & 63;
+  int done = 0;
+  if (lane == 0) done = *(volatile const int*)&st->done;
+  done = __shfl(done, 0, 64);
+  if (done) return;
+  const BlockPartial* part = a.partial + (int64_t)(jd & 1) * a.grid;
+  long long tn = 0;
+  double tm = 0.0, ts = 0.0;
+  // eight partials per lane in flight at once (indices clamped so that the
+  // loads are unconditional), then summed in index order
+  constexpr int U = 8;
+  for (int q0 = lane; q0 < a.grid; q0 += 64 * U) {
+    long long np[U];
+    double md[U], sr[U];
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + 64 * u;
+      const BlockPartial* pp = part + (q < a.grid ? q : 0);
+      np[u] = pp->n_pass;
+      md[u] = pp->max_d_fail;
+      sr[u] = pp->sum_r;
+    }
+    for (int u = 0; u < U; ++u) {
+      if (q0 + 64 * u >= a.grid) break;
+      tn += np[u];
+      if (md[u] > tm || md[u] != md[u]) tm = md[u];
+      ts += sr[u];
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    tn += __shfl_xor(tn, off, 64);
+    const double o = __shfl_xor(tm, off, 64);
+    if (o > tm || o != o) tm = o;
+    ts += __shfl_xor(ts, off, 64);
+  }
+  if (lane == 0) {
+    decide_sweep(a, st, jd, tn, tm, ts);
+    __hip_atomic_store(&a.prog->done, st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&a.prog->decided, jd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // Sweep j of one domain by workgroup b of a packing's launch, or (b ==
 // a.grid) the stop decision of sweep j-1.  A stop at j-1 leaves the forces
 // of sweep j-1 final (sweep j writes the other record array); a workgroup
 // that already sees the stop skips its domain.
-template <int DIM, bool GLOB, bool STAGE>
+// FOLD (single context, workgroups of two or more wavefronts): there is no
+// decision workgroup; the second wavefront of workgroup 0 takes the decision
+// while the first updates the colours (or after them when a colour is wider
+// than a wavefront), so that a launch has one workgroup per domain.
+template <int DIM, bool GLOB, bool STAGE, bool FOLD>
 __device__ inline void sweep_block(const SweepArgs& a, int b, int j, BatchProg* bp) {
   extern __shared__ double lds[];
   __shared__ BlockRed red;
   __shared__ int s_co[CD_MAX_COLORS + 1];
   __shared__ double s_wu[CD_MAX_WALLS * 3];
   __shared__ int s_flag;
-  if (b == a.grid) {
+  if (!FOLD && b == a.grid) {
     if (j >= 2) decide_block(a, j - 1, red, s_flag, bp, a.block);
     return;
   }
@@ -179,8 +228,13 @@ __device__ inline void sweep_block(const SweepArgs& a, int b, int j, BatchProg* 
   double* rout = a.rec[j & 1];
   long long npass = 0;
   double maxd = 0.0, sumr = 0.0;
+  auto idle = [&]() {
+    if (FOLD && b == 0 && j >= 2 && (threadIdx.x >> 6) == 1) decide_wave(a, j - 1);
+  };
   if (d >= 0)
-    sweep_domain<DIM, GLOB, STAGE>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr);
+    sweep_domain<DIM, GLOB, STAGE>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr, idle);
+  else
+    idle();
   BlockPartial p = block_partial(npass, maxd, sumr, red, a.block);
   if (threadIdx.x == 0) a.partial[(int64_t)(j & 1) * a.grid + b] = p;
 }
@@ -189,9 +243,9 @@ __device__ inline void sweep_block(const SweepArgs& a, int b, int j, BatchProg* 
 // The staged 2D form keeps to 96 VGPRs (five wavefronts per SIMD) so that a
 // launch of 2,048 two-wavefront domain workgroups plus the decision
 // workgroup is resident at once on 256 CUs.
-template <int DIM, bool GLOB, bool STAGE>
+template <int DIM, bool GLOB, bool STAGE, bool FOLD>
 __global__ __launch_bounds__(kMaxBlock, STAGE && DIM == 2 ? 5 : 1) void k_sweep(SweepArgs a, int j) {
-  sweep_block<DIM, GLOB, STAGE>(a, blockIdx.x, j, nullptr);
+  sweep_block<DIM, GLOB, STAGE, FOLD>(a, blockIdx.x, j, nullptr);
 }
 
 // Sweep j of a batch of packings: workgroup b serves packing blk[2b] as its
@@ -201,7 +255,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep_batch(const SweepArgs* tab,
                                                           int j, BatchProg* bp) {
   const int2 pb = ((const int2*)blk)[blockIdx.x];
   const SweepArgs a = tab[pb.x];
-  sweep_block<DIM, false, STAGE>(a, pb.y, j, bp);
+  sweep_block<DIM, false, STAGE, false>(a, pb.y, j, bp);
 }
 
 // stop decision of sweep jd alone (after the last launched sweep)
@@ -288,7 +342,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(SweepArgs a, GridBar* bar, 
       const int d = domain_of(a, b, k, G8);
       if (d < 0) break;
       const DomainHead h = load_head<DIM>(a, d);
-      sweep_domain<DIM, GLOB, false>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr);
+      sweep_domain<DIM, GLOB, false>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr,
+                                     [] {});
     }
     BlockPartial p = block_partial(npass, maxd, sumr, red, blockDim.x);
     if (threadIdx.x == 0) {
@@ -492,8 +547,8 @@ size_t cd_stage_lds(cd_ctx* c, int max_particles, int max_contacts) {
   return (b + 31) / 32 * 32;
 }
 
-bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64_t workgroups,
-                   int num_cu, size_t max_lds, bool batch) {
+bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64_t wg_stage,
+                   int64_t wg_plain, int num_cu, size_t max_lds, bool batch) {
   if (lds_stage + 2048 > max_lds) return false;
   const void* ks;
   const void* kp;
@@ -501,8 +556,8 @@ bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64
     ks = dim == 2 ? (const void*)k_sweep_batch<2, true> : (const void*)k_sweep_batch<3, true>;
     kp = dim == 2 ? (const void*)k_sweep_batch<2, false> : (const void*)k_sweep_batch<3, false>;
   } else {
-    ks = dim == 2 ? (const void*)k_sweep<2, false, true> : (const void*)k_sweep<3, false, true>;
-    kp = dim == 2 ? (const void*)k_sweep<2, false, false> : (const void*)k_sweep<3, false, false>;
+    ks = dim == 2 ? (const void*)k_sweep<2, false, true, true> : (const void*)k_sweep<3, false, true, true>;
+    kp = dim == 2 ? (const void*)k_sweep<2, false, false, false> : (const void*)k_sweep<3, false, false, false>;
   }
   const int64_t rs = resident_per_cu(ks, block, lds_stage);
   const int64_t rp = resident_per_cu(kp, block, lds_plain);
@@ -510,15 +565,29 @@ bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64
   if (rp < 1) return true;
   // staging must not add a round of workgroups
   const int64_t slots_s = rs * num_cu, slots_p = rp * num_cu;
-  return (workgroups + slots_s - 1) / slots_s <= (workgroups + slots_p - 1) / slots_p;
+  return (wg_stage + slots_s - 1) / slots_s <= (wg_plain + slots_p - 1) / slots_p;
 }
 
 void cd_sweep_mode(cd_ctx* c) {
   c->sweep_stage = false;
+  c->sweep_fold = false;
   if (c->sweep_global || c->stage_off) return;
   c->sweep_lds_stage = cd_stage_lds(c, c->st_ds.max_particles, c->st_ds.max_contacts);
+  // With two or more wavefronts per workgroup the decision can fold into
+  // workgroup 0.  That pays when a launch runs in several rounds of
+  // resident workgroups (a separate decision workgroup would be dispatched
+  // last and finish last); when every workgroup is resident at once, the
+  // separate decision workgroup runs alongside the domains and workgroup 0
+  // would only become the slowest one.
+  const int64_t domains = (int64_t)8 * ((c->P + 7) / 8);
   c->sweep_stage = cd_stage_pick(c->dim, c->sweep_block, c->sweep_lds, c->sweep_lds_stage,
-                                 (int64_t)8 * ((c->P + 7) / 8) + 1, c->num_cu, c->max_lds, false);
+                                 domains + 1, domains + 1, c->num_cu, c->max_lds, false);
+  if (c->sweep_stage && c->sweep_block >= 128) {
+    const void* kf = c->dim == 2 ? (const void*)k_sweep<2, false, true, true>
+                                 : (const void*)k_sweep<3, false, true, true>;
+    const int64_t slots = (int64_t)resident_per_cu(kf, c->sweep_block, c->sweep_lds_stage) * c->num_cu;
+    c->sweep_fold = domains + 1 > slots;
+  }
 }
 
 hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after) {
@@ -527,22 +596,29 @@ hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after
     hipError_t e = hipEventRecord(before, c->stream);
     if (e != hipSuccess) return e;
   }
-  // the domain workgroups plus the decision workgroup
-  dim3 grid(a.grid + 1), block(c->sweep_block);
+  // the domain workgroups, plus the decision workgroup unless the decision
+  // is folded into workgroup 0
+  const bool fold = c->sweep_fold;
+  dim3 grid(a.grid + (fold ? 0 : 1)), block(c->sweep_block);
+  const size_t lds = block_lds(c);
   if (c->dim == 2) {
     if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<2, true, false>), grid, block, 0, c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<2, true, false, false>), grid, block, 0, c->stream, a, j);
+    else if (fold)
+      hipLaunchKernelGGL((k_sweep<2, false, true, true>), grid, block, lds, c->stream, a, j);
     else if (c->sweep_stage)
-      hipLaunchKernelGGL((k_sweep<2, false, true>), grid, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<2, false, true, false>), grid, block, lds, c->stream, a, j);
     else
-      hipLaunchKernelGGL((k_sweep<2, false, false>), grid, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<2, false, false, false>), grid, block, lds, c->stream, a, j);
   } else {
     if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<3, true, false>), grid, block, 0, c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<3, true, false, false>), grid, block, 0, c->stream, a, j);
+    else if (fold)
+      hipLaunchKernelGGL((k_sweep<3, false, true, true>), grid, block, lds, c->stream, a, j);
     else if (c->sweep_stage)
-      hipLaunchKernelGGL((k_sweep<3, false, true>), grid, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<3, false, true, false>), grid, block, lds, c->stream, a, j);
     else
-      hipLaunchKernelGGL((k_sweep<3, false, false>), grid, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<3, false, false, false>), grid, block, lds, c->stream, a, j);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !after) return e;
@@ -583,18 +659,18 @@ hipError_t cd_launch_sweep_grid(cd_ctx* c, const SweepArgs& a, int j, int grid) 
   dim3 g(grid), block(c->sweep_block);
   if (c->dim == 2) {
     if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<2, true, false>), g, block, 0, c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<2, true, false, false>), g, block, 0, c->stream, a, j);
     else if (c->sweep_stage)
-      hipLaunchKernelGGL((k_sweep<2, false, true>), g, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<2, false, true, false>), g, block, block_lds(c), c->stream, a, j);
     else
-      hipLaunchKernelGGL((k_sweep<2, false, false>), g, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<2, false, false, false>), g, block, block_lds(c), c->stream, a, j);
   } else {
     if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<3, true, false>), g, block, 0, c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<3, true, false, false>), g, block, 0, c->stream, a, j);
     else if (c->sweep_stage)
-      hipLaunchKernelGGL((k_sweep<3, false, true>), g, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<3, false, true, false>), g, block, block_lds(c), c->stream, a, j);
     else
-      hipLaunchKernelGGL((k_sweep<3, false, false>), g, block, block_lds(c), c->stream, a, j);
+      hipLaunchKernelGGL((k_sweep<3, false, false, false>), g, block, block_lds(c), c->stream, a, j);
   }
   return hipGetLastError();
 }

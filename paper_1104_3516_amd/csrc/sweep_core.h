@@ -92,6 +92,15 @@ __device__ inline void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Orders the calling wavefront's LDS writes before its later LDS reads (for
+// the compiler only: the hardware completes a wavefront's LDS operations in
+// issue order, so no wait is needed).
+__device__ inline void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // four doubles stored with one streaming (non-temporal) 32-byte store
 typedef double nt4 __attribute__((ext_vector_type(4)));
 
@@ -415,11 +424,13 @@ __device__ inline void entry_finish(const SweepArgs& a, const double* rin, int64
 }
 
 // Per-domain values a workgroup needs before its sweep: the descriptor
-// (first slot, slots, first particle entry, entries, colours), one colour
+// (first slot, slots, first particle entry, entries, colours, largest
+// colour), one colour
 // offset and one wall velocity component per thread.  Read before the stop
 // check so that their latency overlaps it.
 struct DomainHead {
   int cs, nct, ps, np, ncol;
+  int widest;   // contacts of the domain's largest colour
   int co;       // colour offset number threadIdx.x (threads 0..CD_MAX_COLORS)
   double wu;    // wall velocity component number threadIdx.x
 };
@@ -433,6 +444,7 @@ __device__ inline DomainHead load_head(const SweepArgs& a, int d) {
   h.ps = dd[2];
   h.np = dd[3];
   h.ncol = dd[4];
+  h.widest = dd[5];
   const int tid = threadIdx.x;
   // every colour offset of a domain is written (unused ones hold the count)
   h.co = tid <= CD_MAX_COLORS ? a.dcol[(int64_t)d * (CD_MAX_COLORS + 1) + tid] : 0;
@@ -486,10 +498,11 @@ __device__ inline void get_slot(const double* sl, int nct, int k, double mu0, bo
 // alongside the exchange (all its loads in flight at once) and the colours
 // read it from there; otherwise each thread reads its contact of the next
 // colour into registers one colour ahead.
-template <int DIM, bool GLOB, bool STAGE>
+template <int DIM, bool GLOB, bool STAGE, class Idle>
 __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead& h,
                                     const double* rin, double* rout, double* lds, int* s_co,
-                                    double* s_wu, long long& npass, double& maxd, double& sumr) {
+                                    double* s_wu, long long& npass, double& maxd, double& sumr,
+                                    Idle&& idle) {
   static_assert(!(GLOB && STAGE), "staged contact data needs the particles in LDS");
   using L = Layout<DIM>;
   constexpr int REC = L::REC, PS = L::PS;
@@ -552,6 +565,27 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
   if (STAGE) {
     // 2. colour-major sequential update from the staged contact data
     const double mu0 = mu_slot ? 0.0 : a.mu_slot[0];
+    if (h.widest <= 64) {
+      // every colour fits one wavefront: the first wavefront updates them
+      // all, ordered by its own LDS accesses (a wavefront's LDS operations
+      // complete in issue order), with no workgroup barrier per colour; the
+      // other wavefronts are free for `idle`
+      if (tid < 64) {
+        for (int col = 0; col < ncol; ++col) {
+          const int k = s_co[col] + tid;
+          if (k < s_co[col + 1]) {
+            SlotPre<DIM> c;
+            get_slot<DIM>(sl, nct, k, mu0, mu_slot, c);
+            update_contact<DIM>(sp, s_wu, c, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
+                                maxd, sumr);
+          }
+          wave_lds_order();
+        }
+      } else {
+        idle();
+      }
+      return;
+    }
     for (int col = 0; col < ncol; ++col) {
       const int k0 = s_co[col], k1 = s_co[col + 1];
       for (int k = k0 + tid; k < k1; k += nthr) {
@@ -564,6 +598,7 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
       // record stores stay in flight
       lds_barrier();
     }
+    idle();
     return;
   }
   // 2. colour-major sequential update.  Each thread's contact of the next
@@ -606,6 +641,7 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
     colour(col + 1, other, ko, cur, kc);
   }
   if (col < ncol) colour(col, cur, kc, other, ko);
+  idle();
 }
 
 }  // namespace

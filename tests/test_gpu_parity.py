@@ -185,6 +185,8 @@ def test_full_size_disks_262k_4096_domains_fixed_sweeps():
     pk = inputs.config("disks_262k")
     sim, ctx = both(pk, mu=0.3, n_domains=4096, repartition_every=10, fixed_iters=20)
     compare_step(sim, ctx, "262k fixed20")
+    # 4,097 workgroups need two rounds: the decision is folded into workgroup 0
+    assert ctx.timing().staged == 2
 
 
 @pytest.mark.parametrize("solve_mode", [1, 2])
@@ -240,6 +242,7 @@ def test_full_size_spheres_1m_16384_domains_fixed_sweeps():
     sim, ctx = both(pk, mu=0.5, n_domains=16384, repartition_every=10, fixed_iters=10)
     compare_step(sim, ctx, "1m spheres fixed10")
     compare_step(sim, ctx, "1m spheres step 2")
+    assert ctx.timing().staged == 2
 
 
 def test_full_size_spheres_tolerance_step_properties():
