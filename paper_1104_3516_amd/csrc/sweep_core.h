@@ -423,6 +423,106 @@ __device__ inline void entry_finish(const SweepArgs& a, const double* rin, int64
   pr[L::P_R] = o.r;
 }
 
+// World force F and torque factor Q (2D: R_t; 3D: t2 R_1 - t1 R_2) of
+// the previous sweep's force of slot s: from the staged copy when the slot
+// is one of the domain's own (the same products as the record's, so the
+// same values), else from the record.
+template <int DIM>
+__device__ inline void incidence_force(const double* rin, const double* sl, int cs, int nct,
+                                       int64_t s, double* F, double* Q) {
+  constexpr int NG = Layout<DIM>::NG, REC = Layout<DIM>::REC;
+  const int64_t k = s - cs;
+  if (k >= 0 && k < nct) {
+    double f[NG], R[DIM];
+    for (int q = 0; q < NG; ++q) f[q] = sl[(1 + q) * nct + k];
+    for (int q = 0; q < DIM; ++q) R[q] = sl[(4 + NG + q) * nct + k];
+    if (DIM == 2) {
+      const double t0 = -f[1], t1 = f[0];
+      F[0] = R[0] * f[0] + R[1] * t0;
+      F[1] = R[0] * f[1] + R[1] * t1;
+      Q[0] = R[1];
+    } else {
+      for (int q = 0; q < 3; ++q) {
+        const double fk = R[0] * f[q] + R[1] * f[3 + q];
+        F[q] = fk + R[2] * f[6 + q];
+        Q[q] = R[1] * f[6 + q] - R[2] * f[3 + q];
+      }
+    }
+  } else {
+    const double* rc = rin + s * REC;
+    if (DIM == 2) {
+      const double4 r4 = *(const double4*)rc;
+      F[0] = r4.z;
+      F[1] = r4.w;
+      Q[0] = r4.y;
+    } else {
+      const double4 f4 = *(const double4*)(rc + 4), q4 = *(const double4*)(rc + 8);
+      F[0] = f4.x;
+      F[1] = f4.y;
+      F[2] = f4.z;
+      Q[0] = q4.x;
+      Q[1] = q4.y;
+      Q[2] = q4.z;
+    }
+  }
+}
+
+// gather_forces with the domain's own contacts read from its staged copy
+template <int DIM>
+__device__ inline void gather_forces_staged(const SweepArgs& a, const double* rin, int64_t e,
+                                            int4 r4i, double rp, const double* sl, int cs,
+                                            int nct, double* acc, double* tacc) {
+  constexpr int DR = Layout<DIM>::DR;
+  constexpr int KW = DIM == 2 ? 8 : 16;
+  const int4* rows = (const int4*)a.drow;
+  const int64_t E = a.dpe;
+  auto add = [&](int ent, const double* F, const double* Q) {
+    for (int k = 0; k < DIM; ++k) acc[k] = (ent & 1) ? acc[k] + F[k] : acc[k] - F[k];
+    for (int k = 0; k < DR; ++k) tacc[k] = tacc[k] - rp * Q[k];
+  };
+  if (r4i.x == -2) {
+    const int e1 = a.dinc_ptr[e + 1];
+    for (int x = a.dinc_ptr[e]; x < e1; ++x) {
+      const int ent = a.dinc[x];
+      double F[DIM], Q[DR];
+      incidence_force<DIM>(rin, sl, cs, nct, ent >> 1, F, Q);
+      add(ent, F, Q);
+    }
+    return;
+  }
+  for (int q = 0; q < KW / 4; ++q) {
+    const int ent[4] = {r4i.x, r4i.y, r4i.z, r4i.w};
+    double F[4][DIM], Q[4][DR];
+    for (int u = 0; u < 4; ++u)
+      if (ent[u] >= 0) incidence_force<DIM>(rin, sl, cs, nct, ent[u] >> 1, F[u], Q[u]);
+    for (int u = 0; u < 4; ++u) {
+      if (ent[u] < 0) break;
+      add(ent[u], F[u], Q[u]);
+    }
+    if (ent[3] < 0 || q + 1 == KW / 4) break;
+    r4i = rows[(q + 1) * E + e];
+  }
+}
+
+// entry_finish with the domain's own contacts read from its staged copy
+template <int DIM>
+__device__ inline void entry_finish_staged(const SweepArgs& a, const double* rin, int64_t e,
+                                           const EntryPre<DIM>& o, double* sp, int l,
+                                           const double* sl, int cs, int nct) {
+  using L = Layout<DIM>;
+  constexpr int DR = L::DR, PS = L::PS;
+  double acc[DIM], tacc[DR];
+  for (int k = 0; k < DIM; ++k) acc[k] = o.f[k];
+  for (int k = 0; k < DR; ++k) tacc[k] = o.t[k];
+  gather_forces_staged<DIM>(a, rin, e, o.row, o.r, sl, cs, nct, acc, tacc);
+  double* pr = sp + (int64_t)PS * l;
+  for (int k = 0; k < DIM; ++k) pr[k] = o.v[k] + o.dm * acc[k];
+  for (int k = 0; k < DR; ++k) pr[L::P_W + k] = o.w[k] + o.di * tacc[k];
+  pr[L::P_DM] = o.dm;
+  pr[L::P_DI] = o.di;
+  pr[L::P_R] = o.r;
+}
+
 // Per-domain values a workgroup needs before its sweep: the descriptor
 // (first slot, slots, first particle entry, entries, colours, largest
 // colour), one colour
@@ -534,18 +634,30 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
       entry_load<DIM>(a, e1, ep);
       if (k1 < nct) put_slot<DIM>(sl, nct, k1, x, mu_slot);
       if (k2 < nct) put_slot<DIM>(sl, nct, k2, y, mu_slot);
-      if (tid < np) entry_finish<DIM>(a, rin, e1, ep, sp, tid);
-    }
-    // the rest (domains larger than two contacts or one entry per thread)
-    for (int k = tid + 2 * nthr; k < nct; k += nthr) {
-      SlotPre<DIM> x;
-      fetch_slot<DIM, false>(a, rin, cs + k, x);
-      put_slot<DIM>(sl, nct, k, x, mu_slot);
+      if (DIM == 2) {
+        // 2D: the gathers read whole 32-byte records, the domain's own mostly
+        // from cache right after this workgroup read them
+        if (tid < np) entry_finish<DIM>(a, rin, e1, ep, sp, tid);
+      }
+      // the rest of the contacts (domains of more than two per thread)
+      for (int k = tid + 2 * nthr; k < nct; k += nthr) {
+        SlotPre<DIM> z;
+        fetch_slot<DIM, false>(a, rin, cs + k, z);
+        put_slot<DIM>(sl, nct, k, z, mu_slot);
+      }
+      if (DIM == 3) {
+        // 3D: the gathers read the domain's own contacts (most of a
+        // particle's incidences) from the staged copy instead of 64 bytes
+        // of record each, and only foreign ones from memory
+        __syncthreads();
+        if (tid < np) entry_finish_staged<DIM>(a, rin, e1, ep, sp, tid, sl, cs, nct);
+      }
     }
     for (int l = tid + nthr; l < np; l += nthr) {
       EntryPre<DIM> ep;
       entry_load<DIM>(a, ps + l, ep);
-      entry_finish<DIM>(a, rin, ps + l, ep, sp, l);
+      if (DIM == 2) entry_finish<DIM>(a, rin, ps + l, ep, sp, l);
+      else entry_finish_staged<DIM>(a, rin, ps + l, ep, sp, l, sl, cs, nct);
     }
   } else {
     if (ncol > 0) {
