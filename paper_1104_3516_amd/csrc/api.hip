@@ -688,7 +688,7 @@ int prep_phase3(cd_ctx* c) {
   memcpy(&ds, c->h_scratch, sizeof(DomainStats));
   if (ds.overflow)
     return fail(c, CD_ECAPACITY,
-                ds.overflow == 1 ? "a domain has more than 1024 contacts"
+                ds.overflow == 3 ? "a particle touches contacts of more than 32 domains"
                                  : "a domain needs more than 64 colours");
   if (ds.dinc_total > c->dinc_cap || !c->dinc) {
     int64_t cap = (int64_t)ds.dinc_total + ds.dinc_total / 4 + 1024;

@@ -48,7 +48,8 @@ struct DomainStats {
   int max_colors;
   int max_contacts;
   int max_particles;
-  int overflow;       // 2: a domain needs more than CD_MAX_COLORS colours
+  int overflow;       // 2: a domain needs more than CD_MAX_COLORS colours; 3: a particle
+                      // touches more than 32 domains
   int max_lds;        // largest per-domain staging size of the sweep, bytes
   int dinc_total;     // incidences summed over all domain particle entries
   int dp_total;       // domain particle entries

@@ -28,11 +28,6 @@ constexpr int kThreads = 256;
 constexpr int kBuild = 64;
 constexpr int kSmall = 512;    // colouring in LDS up to this many contacts and particles
 
-__global__ __launch_bounds__(kThreads) void k_dom_count(const int* dom, int64_t nc, int* count) {
-  int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (c < nc) atomicAdd(&count[dom[c]], 1);
-}
-
 __global__ __launch_bounds__(kThreads) void k_dom_keys(const int* dom, int64_t nc,
                                                       unsigned long long* keys, int* vals) {
   int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -41,39 +36,79 @@ __global__ __launch_bounds__(kThreads) void k_dom_keys(const int* dom, int64_t n
   vals[c] = (int)c;
 }
 
-__global__ __launch_bounds__(kThreads) void k_end_keys(const int* bucket, const int* dom,
-                                                      const int* ci, const int* cj, int64_t nc,
-                                                      int64_t n, unsigned long long* keys,
-                                                      int* vals) {
-  int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (q >= nc) return;
-  int c = bucket[q];
-  unsigned long long d = (unsigned long long)dom[c];
-  keys[2 * q] = d * (unsigned long long)n + (unsigned long long)ci[c];
-  int b = cj[c];
-  keys[2 * q + 1] = b < n ? d * (unsigned long long)n + (unsigned long long)b : ~0ull;
-  vals[2 * q] = 0;
-  vals[2 * q + 1] = 0;
+// First index of each domain d in 0..P in the contacts sorted by domain
+// (binary search over the sorted keys): the domain's contact range.
+__global__ __launch_bounds__(kThreads) void k_dom_bounds(const unsigned long long* keys,
+                                                        int64_t m, int P, int* start) {
+  const int d = blockIdx.x * kThreads + threadIdx.x;
+  if (d > P) return;
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < (unsigned long long)d) lo = mid + 1;
+    else hi = mid;
+  }
+  start[d] = (int)lo;
 }
 
-__global__ __launch_bounds__(kThreads) void k_unique_flags(const unsigned long long* keys,
-                                                          int64_t m, int* flag) {
-  int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (k >= m) return;
-  unsigned long long v = keys[k];
-  flag[k] = (v != ~0ull) && (k == 0 || keys[k - 1] != v);
+// Distinct domains of particle p's incident contacts (its domain entries),
+// in increasing domain order; returns their count.
+__device__ inline int particle_domains(const int* inc_ptr, const int* inc, const int* dom, int p,
+                                       int* out, int cap_out) {
+  int k = 0;
+  for (int e = inc_ptr[p]; e < inc_ptr[p + 1]; ++e) {
+    const int d = dom[inc[e] >> 1];
+    int q = 0;
+    while (q < k && out[q] < d) ++q;
+    if (q < k && out[q] == d) continue;
+    if (k == cap_out) return -1;
+    for (int r = k; r > q; --r) out[r] = out[r - 1];
+    out[q] = d;
+    ++k;
+  }
+  return k;
 }
 
-__global__ __launch_bounds__(kThreads) void k_unique_compact(const unsigned long long* keys,
-                                                            int64_t m, const int* flag,
-                                                            const int* pos, int64_t n, int* dp,
-                                                            int* dp_count) {
-  int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (k >= m || !flag[k]) return;
-  unsigned long long v = keys[k];
-  unsigned long long d = v / (unsigned long long)n;
-  dp[pos[k]] = (int)(v - d * (unsigned long long)n);
-  atomicAdd(&dp_count[d], 1);
+// slots k >= count of the pair arrays: a key past every domain
+__global__ __launch_bounds__(kThreads) void k_pad_keys(const int* count, int64_t m,
+                                                      unsigned long long* keys, int* vals) {
+  const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= m || k < *count) return;
+  keys[k] = ~0ull;
+  vals[k] = 0;
+}
+
+constexpr int kMaxPartDomains = 32;   // distinct domains of one particle's contacts
+
+__global__ __launch_bounds__(kThreads) void k_pdom_count(const int* inc_ptr, const int* inc,
+                                                        const int* dom, int64_t n, int* count,
+                                                        DomainStats* stats) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  int ds[kMaxPartDomains];
+  int k = particle_domains(inc_ptr, inc, dom, (int)p, ds, kMaxPartDomains);
+  if (k < 0) {
+    atomicMax(&stats->overflow, 3);
+    k = 0;
+  }
+  count[p] = k;
+}
+
+// (domain, particle) pairs in particle-major order; a stable sort by domain
+// then gives every domain's particles in increasing id
+__global__ __launch_bounds__(kThreads) void k_pdom_write(const int* inc_ptr, const int* inc,
+                                                        const int* dom, int64_t n, const int* off,
+                                                        unsigned long long* keys, int* vals) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  int ds[kMaxPartDomains];
+  const int k = particle_domains(inc_ptr, inc, dom, (int)p, ds, kMaxPartDomains);
+  if (k < 0) return;
+  const int o = off[p];
+  for (int q = 0; q < k; ++q) {
+    keys[o + q] = (unsigned long long)ds[q];
+    vals[o + q] = (int)p;
+  }
 }
 
 __device__ inline int lower_bound_i(const int* a, int n, int v) {
@@ -96,9 +131,14 @@ __global__ __launch_bounds__(kThreads) void k_local_index(const int* bucket, con
   int c = bucket[q];
   int d = dom[c];
   int ps = dp_start[d], np = dp_start[d + 1] - ps;
-  qla[q] = lower_bound_i(dp + ps, np, ci[c]);
+  // (clamped: only a particle dropped by a reported overflow is missing)
+  auto find = [&](int v) {
+    const int k = lower_bound_i(dp + ps, np, v);
+    return k < np ? k : (np > 0 ? np - 1 : 0);
+  };
+  qla[q] = find(ci[c]);
   int b = cj[c];
-  qlb[q] = b < n ? lower_bound_i(dp + ps, np, b) : -1 - (int)(b - n);
+  qlb[q] = b < n ? find(b) : -1 - (int)(b - n);
 }
 
 struct BuildArgs {
@@ -173,6 +213,11 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   const int d = blockIdx.x;
   const int cs = a.dom_start[d], nct = a.dom_start[d + 1] - cs;
   const int ps = a.dp_start[d], np = a.dp_start[d + 1] - ps;
+  if (nct > 0 && np == 0) {
+    // only after a reported overflow (particles dropped from the entries)
+    if (threadIdx.x == 0) atomicMax(&a.stats->overflow, 3);
+    return;
+  }
   const bool small = nct <= kSmall && np <= kSmall;
   for (int q = threadIdx.x; q < CD_MAX_COLORS; q += blockDim.x) s_cnt[q] = 0;
   if (small) {
@@ -319,9 +364,8 @@ __global__ __launch_bounds__(kThreads) void k_inc_fill(const int* ci, const int*
   if (b < n) inc[ptr[b] + atomicAdd(&cursor[b], 1)] = (int)(2 * c + 1);
 }
 
-// sort each particle's incidences by contact id, then refer to slots
-__global__ __launch_bounds__(kThreads) void k_inc_finish(int64_t n, const int* ptr,
-                                                        const int* contact_slot, int* inc) {
+// sort each particle's incidences by contact id
+__global__ __launch_bounds__(kThreads) void k_inc_sort(int64_t n, const int* ptr, int* inc) {
   int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
   int s0 = ptr[p], s1 = ptr[p + 1];
@@ -334,10 +378,15 @@ __global__ __launch_bounds__(kThreads) void k_inc_finish(int64_t n, const int* p
     }
     inc[q] = v;
   }
-  for (int k = s0; k < s1; ++k) {
-    int v = inc[k];
-    inc[k] = 2 * contact_slot[v >> 1] + (v & 1);
-  }
+}
+
+// the incidences refer to slots instead of contacts (order kept)
+__global__ __launch_bounds__(kThreads) void k_inc_slots(const int* total, int64_t m,
+                                                       const int* contact_slot, int* inc) {
+  int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= m || k >= *total) return;
+  const int v = inc[k];
+  inc[k] = 2 * contact_slot[v >> 1] + (v & 1);
 }
 
 // domain particle entries in domain order: base data (SoA, stride E) and
@@ -423,44 +472,66 @@ hipError_t cd_launch_order(cd_ctx* c) {
   const int64_t n = c->n;
   const int P = c->P;
   hipError_t e;
-  e = hipMemsetAsync(c->dom_count, 0, sizeof(int) * (size_t)(P + 1), c->stream);
-  if (e != hipSuccess) return e;
   e = hipMemsetAsync(c->d_stats, 0, sizeof(DomainStats), c->stream);
   if (e != hipSuccess) return e;
-  e = hipMemsetAsync(c->dp_count, 0, sizeof(int) * (size_t)(P + 1), c->stream);
-  if (e != hipSuccess) return e;
-  if (nc > 0)
-    hipLaunchKernelGGL(k_dom_count, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
-                       c->dom, nc, c->dom_count);
-  e = cd_scan_exclusive(c, c->dom_count, c->dom_start, P);
-  if (e != hipSuccess) return e;
+  // 1. contacts by domain, canonical order kept (stable sort); each
+  //    domain's contact range from the sorted keys
+  unsigned long long* ko = c->sort_keys[0];
+  int* vo = c->sort_vals[0];
   if (nc > 0) {
-    // 1. contacts by domain, canonical order kept (stable sort)
     hipLaunchKernelGGL(k_dom_keys, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
                        c->dom, nc, c->sort_keys[0], c->sort_vals[0]);
-    unsigned long long* ko;
-    int* vo;
     e = cd_radix_sort(c, c->sort_keys[0], c->sort_vals[0], c->sort_keys[1], c->sort_vals[1], nc,
                       bits_for((unsigned long long)(P - 1)), &ko, &vo);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(c->bucket, vo, sizeof(int) * (size_t)nc, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return e;
-    // 2. each domain's particles: sorted unique (domain, particle) keys
-    const int64_t m = 2 * nc;
-    hipLaunchKernelGGL(k_end_keys, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
-                       c->bucket, c->dom, c->ci, c->cj, nc, n, c->sort_keys[0], c->sort_vals[0]);
-    e = cd_radix_sort(c, c->sort_keys[0], c->sort_vals[0], c->sort_keys[1], c->sort_vals[1], m,
-                      bits_for((unsigned long long)P * (unsigned long long)n), &ko, &vo);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_unique_flags, dim3(cd_blocks(m, kThreads)), dim3(kThreads), 0, c->stream,
-                       ko, m, c->flag);
-    e = cd_scan_exclusive(c, c->flag, c->flag_scan, m);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_unique_compact, dim3(cd_blocks(m, kThreads)), dim3(kThreads), 0,
-                       c->stream, ko, m, c->flag, c->flag_scan, n, c->dp, c->dp_count);
   }
-  e = cd_scan_exclusive(c, c->dp_count, c->dp_start, P);
+  hipLaunchKernelGGL(k_dom_bounds, dim3(cd_blocks(P + 1, kThreads)), dim3(kThreads), 0, c->stream,
+                     ko, nc, P, c->dom_start);
+  // 2. incidence lists: each particle's contacts in increasing id
+  e = hipMemsetAsync(c->inc_count, 0, sizeof(int) * (size_t)(n + 1), c->stream);
   if (e != hipSuccess) return e;
+  if (nc > 0)
+    hipLaunchKernelGGL(k_inc_count, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
+                       c->ci, c->cj, nc, n, c->inc_count);
+  e = cd_scan_exclusive(c, c->inc_count, c->inc_ptr, n);
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(c->inc_cursor, 0, sizeof(int) * (size_t)(n + 1), c->stream);
+  if (e != hipSuccess) return e;
+  if (nc > 0)
+    hipLaunchKernelGGL(k_inc_fill, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
+                       c->ci, c->cj, nc, n, c->inc_ptr, c->inc_cursor, c->inc);
+  hipLaunchKernelGGL(k_inc_sort, dim3(cd_blocks(n, kThreads)), dim3(kThreads), 0, c->stream, n,
+                     c->inc_ptr, c->inc);
+  // 3. each domain's particles: per particle the distinct domains of its
+  //    contacts as (domain, particle) pairs in particle order, sorted stably
+  //    by domain (the per-particle counts and offsets reuse the incidence
+  //    cursor and count arrays, free by now)
+  int* pcount = c->inc_cursor;
+  int* poff = c->inc_count;
+  hipLaunchKernelGGL(k_pdom_count, dim3(cd_blocks(n, kThreads)), dim3(kThreads), 0, c->stream,
+                     c->inc_ptr, c->inc, c->dom, n, pcount, c->d_stats);
+  e = cd_scan_exclusive(c, pcount, poff, n);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pdom_write, dim3(cd_blocks(n, kThreads)), dim3(kThreads), 0, c->stream,
+                     c->inc_ptr, c->inc, c->dom, n, poff, c->sort_keys[0], c->sort_vals[0]);
+  // the number of pairs is poff[n] (at most 2 n_c), known on the device only:
+  // the sort covers the 2 n_c slots, the unused tail keyed past every domain
+  {
+    const int64_t m = 2 * nc;
+    if (m > 0) {
+      hipLaunchKernelGGL(k_pad_keys, dim3(cd_blocks(m, kThreads)), dim3(kThreads), 0, c->stream,
+                         poff + n, m, c->sort_keys[0], c->sort_vals[0]);
+      e = cd_radix_sort(c, c->sort_keys[0], c->sort_vals[0], c->sort_keys[1], c->sort_vals[1], m,
+                        bits_for((unsigned long long)P), &ko, &vo);
+      if (e != hipSuccess) return e;
+      e = hipMemcpyAsync(c->dp, vo, sizeof(int) * (size_t)m, hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_dom_bounds, dim3(cd_blocks(P + 1, kThreads)), dim3(kThreads), 0,
+                       c->stream, ko, m, P, c->dp_start);
+  }
   // 3. local body indices
   if (nc > 0)
     hipLaunchKernelGGL(k_local_index, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
@@ -505,21 +576,10 @@ hipError_t cd_launch_order(cd_ctx* c) {
     hipLaunchKernelGGL(k_dom_build<3>, dim3(P), dim3(kBuild), 0, c->stream, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // 5. incidence lists
-  e = hipMemsetAsync(c->inc_count, 0, sizeof(int) * (size_t)(n + 1), c->stream);
-  if (e != hipSuccess) return e;
+  // 5. the incidence lists refer to slots from here on
   if (nc > 0)
-    hipLaunchKernelGGL(k_inc_count, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
-                       c->ci, c->cj, nc, n, c->inc_count);
-  e = cd_scan_exclusive(c, c->inc_count, c->inc_ptr, n);
-  if (e != hipSuccess) return e;
-  e = hipMemsetAsync(c->inc_cursor, 0, sizeof(int) * (size_t)(n + 1), c->stream);
-  if (e != hipSuccess) return e;
-  if (nc > 0)
-    hipLaunchKernelGGL(k_inc_fill, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
-                       c->ci, c->cj, nc, n, c->inc_ptr, c->inc_cursor, c->inc);
-  hipLaunchKernelGGL(k_inc_finish, dim3(cd_blocks(n, kThreads)), dim3(kThreads), 0, c->stream, n,
-                     c->inc_ptr, c->contact_slot, c->inc);
+    hipLaunchKernelGGL(k_inc_slots, dim3(cd_blocks(2 * nc, kThreads)), dim3(kThreads), 0,
+                       c->stream, c->inc_ptr + n, 2 * nc, c->contact_slot, c->inc);
   // 6. domain particle entries and their incidence counts
   const int64_t E = 2 * c->cap;
   if (c->dim == 2)
