@@ -25,7 +25,7 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kBuild = 64;
+constexpr int kBuild = 64;   // one wavefront: the small-domain colouring runs in lockstep
 constexpr int kSmall = 512;    // colouring in LDS up to this many contacts and particles
 
 __global__ __launch_bounds__(kThreads) void k_dom_keys(const int* dom, int64_t nc,
@@ -200,6 +200,81 @@ __device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb
   return ncol;
 }
 
+// The same colouring by one whole wavefront in lockstep (small domains,
+// LDS arrays): every lane follows the same contact, lane q keeps the count
+// of colour q in a register, and each step costs one round trip to LDS
+// (the next contact's bodies are read one step ahead).
+__device__ inline int colour_wave(int nct, unsigned long long* mask, const int* la_s,
+                                  const int* lb_s, short* col_s, short* rank_s, int* cnt_out) {
+  static_assert(CD_MAX_COLORS == 64, "one lane per colour");
+  const int lane = threadIdx.x & 63;
+  int cnt = 0;   // contacts of colour `lane` so far
+  int ncol = 0;
+  int la = nct > 0 ? la_s[0] : 0, lb = nct > 0 ? lb_s[0] : -1;
+  for (int k = 0; k < nct; ++k) {
+    const int la_n = k + 1 < nct ? la_s[k + 1] : 0;
+    const int lb_n = k + 1 < nct ? lb_s[k + 1] : -1;
+    const unsigned long long ma = mask[la], mb = lb >= 0 ? mask[lb] : 0ull;
+    const unsigned long long used = ma | mb;
+    if (used == ~0ull) return -1;
+    const int col = __builtin_amdgcn_readfirstlane(__ffsll((long long)~used) - 1);
+    const int rank = __builtin_amdgcn_readlane(cnt, col);
+    if (lane == col) ++cnt;
+    if (lane == 0) {
+      col_s[k] = (short)col;
+      rank_s[k] = (short)rank;
+      mask[la] = ma | (1ull << col);
+      if (lb >= 0) mask[lb] = mb | (1ull << col);
+    }
+    if (col + 1 > ncol) ncol = col + 1;
+    la = la_n;
+    lb = lb_n;
+  }
+  cnt_out[lane] = cnt;
+  return ncol;
+}
+
+// Largest colour count, contacts, particle entries and LDS staging over
+// all domain descriptors, by one workgroup (a same-address atomic from
+// every domain workgroup would serialise).
+constexpr int kStats = 1024;
+__global__ __launch_bounds__(kStats) void k_dom_stats(const int* ddesc, int P, int stage_doubles,
+                                                     DomainStats* stats) {
+  __shared__ int sh[4][kStats / 64];
+  int mc = 0, mn = 0, mp = 0;
+  for (int d = threadIdx.x; d < P; d += kStats) {
+    const int* dd = ddesc + 8 * (int64_t)d;
+    mn = max(mn, dd[1]);
+    mp = max(mp, dd[3]);
+    mc = max(mc, dd[4]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mc = max(mc, __shfl_xor(mc, off, 64));
+    mn = max(mn, __shfl_xor(mn, off, 64));
+    mp = max(mp, __shfl_xor(mp, off, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = mc;
+    sh[1][w] = mn;
+    sh[2][w] = mp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kStats / 64; ++k) {
+      mc = max(mc, sh[0][k]);
+      mn = max(mn, sh[1][k]);
+      mp = max(mp, sh[2][k]);
+    }
+    stats->max_colors = mc;
+    stats->max_contacts = mn;
+    stats->max_particles = mp;
+    // sweep staging in LDS: per particle V, W, dt/m, dt/I, r
+    const long long bytes = 8ll * stage_doubles * mp;
+    stats->max_lds = (int)(bytes < 0x7fffffffll ? bytes : 0x7fffffffll);
+  }
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   constexpr int REC = DIM == 2 ? 4 : 12;
@@ -230,8 +305,11 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     for (int k = threadIdx.x; k < np; k += blockDim.x) a.gmask[ps + k] = 0ull;
   }
   __syncthreads();
+  int ncol_w = 0;
+  if (small) ncol_w = colour_wave(nct, s_mask, s_la, s_lb, s_col, s_rank, s_cnt);
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const int ncol = small ? colour_serial(nct, s_mask, s_la, s_lb, s_col, s_rank, s_cnt)
+    const int ncol = small ? ncol_w
                            : colour_serial(nct, a.gmask + ps, a.qla + cs, a.qlb + cs,
                                            a.qcol + cs, a.qpos + cs, s_cnt);
     s_coloff[0] = 0;
@@ -262,13 +340,6 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     for (int q = 0; q < ncol; ++q) widest = max(widest, s_coloff[q + 1] - s_coloff[q]);
     dd[5] = widest;
     dd[6] = dd[7] = 0;
-    atomicMax(&a.stats->max_colors, ncol);
-    atomicMax(&a.stats->max_contacts, nct);
-    atomicMax(&a.stats->max_particles, np);
-    // sweep staging in LDS: per particle V, W, dt/m, dt/I, r
-    constexpr int PD = cd_stage_particle(DIM);
-    long long bytes = 8ll * PD * np;
-    atomicMax(&a.stats->max_lds, (int)(bytes < 0x7fffffffll ? bytes : 0x7fffffffll));
     a.dncol[d] = ncol;
   }
   for (int q = threadIdx.x; q <= CD_MAX_COLORS; q += blockDim.x)
@@ -574,6 +645,8 @@ hipError_t cd_launch_order(cd_ctx* c) {
     hipLaunchKernelGGL(k_dom_build<2>, dim3(P), dim3(kBuild), 0, c->stream, a);
   else
     hipLaunchKernelGGL(k_dom_build<3>, dim3(P), dim3(kBuild), 0, c->stream, a);
+  hipLaunchKernelGGL(k_dom_stats, dim3(1), dim3(kStats), 0, c->stream, c->ddesc, P,
+                     cd_stage_particle(c->dim), c->d_stats);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // 5. the incidence lists refer to slots from here on
