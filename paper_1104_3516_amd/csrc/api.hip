@@ -369,6 +369,7 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
       st = CD_EHIP;
   }
   if (st == CD_OK && hipMalloc((void**)&c->d_stats, sizeof(DomainStats)) != hipSuccess) st = CD_ENOMEM;
+  if (st == CD_OK && hipMemset(c->d_stats, 0, sizeof(DomainStats)) != hipSuccess) st = CD_EHIP;
   if (st == CD_OK && hipMalloc((void**)&c->d_bar, sizeof(GridBar)) != hipSuccess) st = CD_ENOMEM;
   if (st == CD_OK && hipMalloc((void**)&c->init_part, sizeof(double) * 256) != hipSuccess)
     st = CD_ENOMEM;
@@ -420,12 +421,13 @@ int cd_destroy(cd_ctx* c) {
                   &c->perm_tmp, &c->cnode, &c->side, &c->flag, &c->flag_scan, &c->dom_count,
                   &c->dom_start, &c->dom_cursor, &c->bucket, &c->slot_contact,
                   &c->contact_slot, &c->dcol, &c->dncol, &c->dp, &c->dp_count, &c->inc_count,
-                  &c->inc_ptr, &c->inc_cursor, &c->inc, &c->scan_tmp,
+                  &c->inc_ptr, &c->inc_cursor, &c->inc,
                   &c->dp_start, &c->q_la, &c->q_lb, &c->q_col, &c->q_pos};
   for (auto p : ints) release(p);
   release(&c->sort_keys[0]);
   release(&c->sort_keys[1]);
   release(&c->sort_hist);
+  release(&c->scan_tmp);
   release(&c->slot_ab);
   release(&c->g_mask);
   release(&c->gscr);
@@ -686,6 +688,8 @@ int prep_phase3(cd_ctx* c) {
   const int dim = c->dim;
   DomainStats ds;
   memcpy(&ds, c->h_scratch, sizeof(DomainStats));
+  if (ds.scan_fault)
+    return fail(c, CD_EHIP, "a prefix scan gave up waiting on a predecessor tile");
   if (ds.overflow)
     return fail(c, CD_ECAPACITY,
                 ds.overflow == 3 ? "a particle touches contacts of more than 32 domains"

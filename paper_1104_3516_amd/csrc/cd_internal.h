@@ -53,7 +53,8 @@ struct DomainStats {
   int max_lds;        // largest per-domain staging size of the sweep, bytes
   int dinc_total;     // incidences summed over all domain particle entries
   int dp_total;       // domain particle entries
-  int pad;
+  int scan_fault;     // sticky: a prefix scan gave up waiting on a predecessor tile
+                      // (never cleared by the per-step reset of the fields above)
 };
 
 // grid barrier of the one-launch solve
@@ -288,8 +289,9 @@ struct cd_ctx {
   double* h_walls = nullptr;       // pinned staging of the wall upload
 
   // scan workspace
-  int* scan_tmp = nullptr;
-  int64_t scan_tmp_cap = 0;
+  unsigned long long* scan_tmp = nullptr;  // ticket counter, then per-tile status words
+  int64_t scan_tmp_cap = 0;                // status words
+  uint64_t scan_epoch = 0;                 // scans issued on this context
 
   // sweep launch shape
   size_t sweep_lds = 0;     // LDS staging per wavefront (domain), bytes

@@ -543,7 +543,7 @@ hipError_t cd_launch_order(cd_ctx* c) {
   const int64_t n = c->n;
   const int P = c->P;
   hipError_t e;
-  e = hipMemsetAsync(c->d_stats, 0, sizeof(DomainStats), c->stream);
+  e = hipMemsetAsync(c->d_stats, 0, offsetof(DomainStats, scan_fault), c->stream);
   if (e != hipSuccess) return e;
   // 1. contacts by domain, canonical order kept (stable sort); each
   //    domain's contact range from the sorted keys

@@ -1,13 +1,29 @@
-// scan.hip - exclusive prefix sum of int32 counts (out has n+1 entries,
-// out[n] = total).  Three passes: per-block totals, a single-block scan of
-// the totals, and the per-block scan with its offset added.
+// scan.hip - exclusive prefix sum of nonnegative int32 counts (out has n+1
+// entries, out[n] = total), in one launch.
+//
+// Tiles of kTile counts are scanned in the order of a ticket taken from a
+// device counter (not blockIdx), so every tile that a tile waits on has
+// already started.  Each tile publishes its total at once ("aggregate"),
+// then its inclusive prefix once known; a tile finds its exclusive prefix
+// by walking back over its predecessors 64 at a time with one wavefront,
+// summing aggregates until it meets a published prefix (decoupled
+// look-back).  A status word is {epoch:32, prefix flag:1, value:31}; the
+// host advances the epoch with every scan, so words left by earlier scans
+// read as not yet published and the status array is never cleared between
+// scans.  The workgroup holding the launch's last ticket resets the counter
+// for the next scan on the stream.
 #include "cd_internal.h"
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 4;
+constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;
+constexpr unsigned long long kPrefixBit = 1ull << 31;
+constexpr unsigned long long kValueMask = kPrefixBit - 1;
+// polls of one look-back window before giving up (the wait always ends in
+// practice: a predecessor only waits on its own predecessors)
+constexpr long long kPollLimit = 1ll << 20;
 
 // inclusive scan of one value per thread across the block; returns the
 // inclusive prefix and writes the block total to *total
@@ -36,52 +52,97 @@ __device__ int block_inclusive_scan(int v, int* sh, int* total) {
   return v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_block_sums(const int* in, int64_t n, int* sums) {
-  __shared__ int sh[kThreads / 64 + 1];
-  int64_t base = (int64_t)blockIdx.x * kTile;
-  int s = 0;
-  for (int k = 0; k < kItems; ++k) {
-    int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
-    if (i < n) s += in[i];
-  }
-  int total;
-  block_inclusive_scan(s, sh, &total);
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+__device__ inline unsigned long long status_load(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void status_store(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_sums(int* sums, int nb, int* grand) {
-  __shared__ int sh[kThreads / 64 + 1];
-  int carry = 0;
-  for (int base = 0; base < nb; base += kThreads) {
-    int i = base + threadIdx.x;
-    int v = i < nb ? sums[i] : 0;
-    int total;
-    int inc = block_inclusive_scan(v, sh, &total);
-    if (i < nb) sums[i] = carry + inc - v;
-    carry += total;
+// Exclusive prefix of tile t (t >= 1) over tiles 0..t-1, by wavefront 0.
+__device__ int look_back(const unsigned long long* status, int t, unsigned epoch, int* fault) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long tag = (unsigned long long)epoch << 32;
+  int excl = 0;
+  long long polls = 0;
+  for (int base = t - 1;;) {
+    // lane L looks at tile base - L; tiles before tile 0 read as a zero
+    // prefix (tile 0 always publishes its prefix, so they are never summed)
+    const int q = base - lane;
+    const unsigned long long w = q >= 0 ? status_load(status + q) : (tag | kPrefixBit);
+    const bool valid = (unsigned)(w >> 32) == epoch;
+    const unsigned long long pref = __ballot(valid && (w & kPrefixBit));
+    const unsigned long long bad = __ballot(!valid);
+    // the nearest published prefix ends the walk; every tile up to it
+    // must have published at least its aggregate
+    const int last = pref ? __builtin_ctzll(pref) : 63;
+    const unsigned long long need = last == 63 ? ~0ull : ((2ull << last) - 1);
+    if (bad & need) {
+      if (++polls <= kPollLimit) {
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      // give up: flag the fault and finish with what is known, so that
+      // every tile still reaches the end of the kernel
+      if (lane == 0) __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    polls = 0;
+    int v = lane <= last ? (int)(w & kValueMask) : 0;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    excl += v;
+    if (pref) break;
+    base -= 64;
   }
-  if (threadIdx.x == 0) *grand = carry;
+  return excl;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_tiles(const int* in, int* out, int64_t n,
-                                                        const int* sums) {
+__global__ __launch_bounds__(kThreads) void k_scan(const int* in, int* out, int64_t n, int nb,
+                                                  unsigned long long* ticket,
+                                                  unsigned long long* status, unsigned epoch,
+                                                  int* fault) {
   __shared__ int sh[kThreads / 64 + 1];
-  int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+  __shared__ int s_tile, s_excl;
+  if (threadIdx.x == 0) {
+    const int t = (int)__hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    // every other tile of this launch already holds its ticket
+    if (t == nb - 1) __hip_atomic_store(ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_tile = t;
+  }
+  __syncthreads();
+  const int t = s_tile;
+  const int64_t base = (int64_t)t * kTile + (int64_t)threadIdx.x * kItems;
   int vals[kItems];
   int s = 0;
   for (int k = 0; k < kItems; ++k) {
-    int64_t i = base + k;
+    const int64_t i = base + k;
     vals[k] = i < n ? in[i] : 0;
     s += vals[k];
   }
   int total;
-  int inc = block_inclusive_scan(s, sh, &total);
-  int run = sums[blockIdx.x] + inc - s;
+  const int inc = block_inclusive_scan(s, sh, &total);
+  if (threadIdx.x < 64) {
+    const unsigned long long tag = (unsigned long long)epoch << 32;
+    int excl = 0;
+    if (t == 0) {
+      if (threadIdx.x == 0) status_store(status, tag | kPrefixBit | (unsigned)total);
+    } else {
+      if (threadIdx.x == 0) status_store(status + t, tag | (unsigned)total);
+      excl = look_back(status, t, epoch, fault);
+      if (threadIdx.x == 0) status_store(status + t, tag | kPrefixBit | (unsigned)(excl + total));
+    }
+    if (threadIdx.x == 0) s_excl = excl;
+  }
+  __syncthreads();
+  const int excl = s_excl;
+  int run = excl + inc - s;
   for (int k = 0; k < kItems; ++k) {
-    int64_t i = base + k;
+    const int64_t i = base + k;
     if (i < n) out[i] = run;
     run += vals[k];
   }
+  if (t == nb - 1 && threadIdx.x == 0) out[n] = excl + total;
 }
 
 }  // namespace
@@ -89,16 +150,28 @@ __global__ __launch_bounds__(kThreads) void k_scan_tiles(const int* in, int* out
 hipError_t cd_scan_exclusive(cd_ctx* c, const int* in, int* out, int64_t n) {
   int nb = (int)((n + kTile - 1) / kTile);
   if (nb < 1) nb = 1;
+  hipError_t e;
   if (c->scan_tmp_cap < nb) {
     if (c->scan_tmp) (void)hipFree(c->scan_tmp);
     c->scan_tmp = nullptr;
-    hipError_t e = hipMalloc(&c->scan_tmp, sizeof(int) * (size_t)(nb + 64));
+    c->scan_tmp_cap = 0;
+    const int64_t cap = nb + nb / 4 + 64;
+    // word 0: ticket counter; status words from word 32 on
+    e = hipMalloc(&c->scan_tmp, sizeof(unsigned long long) * (size_t)(cap + 32));
     if (e != hipSuccess) return e;
-    c->scan_tmp_cap = nb;
+    e = hipMemsetAsync(c->scan_tmp, 0, sizeof(unsigned long long) * (size_t)(cap + 32), c->stream);
+    if (e != hipSuccess) return e;
+    c->scan_tmp_cap = cap;
   }
-  hipLaunchKernelGGL(k_block_sums, dim3(nb), dim3(kThreads), 0, c->stream, in, n, c->scan_tmp);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kThreads), 0, c->stream, c->scan_tmp, nb, out + n);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(kThreads), 0, c->stream, in, out, n,
-                     c->scan_tmp);
+  unsigned epoch = (unsigned)++c->scan_epoch;
+  if (epoch == 0) {
+    // after 2^32 scans: clear the words so no stale one carries the epoch
+    e = hipMemsetAsync(c->scan_tmp + 32, 0, sizeof(unsigned long long) * (size_t)c->scan_tmp_cap,
+                       c->stream);
+    if (e != hipSuccess) return e;
+    epoch = (unsigned)++c->scan_epoch;
+  }
+  hipLaunchKernelGGL(k_scan, dim3(nb), dim3(kThreads), 0, c->stream, in, out, n, nb, c->scan_tmp,
+                     c->scan_tmp + 32, epoch, &c->d_stats->scan_fault);
   return hipGetLastError();
 }
