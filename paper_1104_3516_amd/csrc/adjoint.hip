@@ -116,13 +116,19 @@ __device__ inline void law_forward(double* sp, const double* wu, const SlotPre<2
                                    Body<2>& B) {
   const int la = c.ab.x, lb = c.ab.y;
   read_body<2>(sp, la, A);
-  if (lb >= 0) {
-    read_body<2>(sp, lb, B);
-  } else {
-    for (int q = 0; q < 3; ++q) B.V[q] = B.W[q] = 0.0;
-    for (int q = 0; q < 2; ++q) B.V[q] = wu[(-1 - lb) * 2 + q];
-    B.dm = B.di = B.r = 0.0;
-  }
+  // body 2 chosen over scalars (a choice between two fillings of B's arrays
+  // would be kept in scratch memory)
+  const int lw = lb >= 0 ? lb : la;
+  const double* pb = sp + (int64_t)Layout<2>::PS * lw;
+  const double* pw = wu + 2 * (lb >= 0 ? 0 : -1 - lb);
+  const bool part = lb >= 0;
+  B.V[0] = part ? pb[0] : pw[0];
+  B.V[1] = part ? pb[1] : pw[1];
+  B.W[0] = part ? pb[Layout<2>::P_W] : 0.0;
+  B.dm = part ? pb[Layout<2>::P_DM] : 0.0;
+  B.di = part ? pb[Layout<2>::P_DI] : 0.0;
+  B.r = part ? pb[Layout<2>::P_R] : 0.0;
+  B.V[2] = B.W[1] = B.W[2] = 0.0;
   double nv[3] = {c.f[0], c.f[1], 0.0}, t1[3] = {-c.f[1], c.f[0], 0.0}, t2[3] = {0.0, 0.0, 0.0};
   double Rold[3] = {c.Ro[0], c.Ro[1], 0.0}, dwR[3] = {c.dwn * c.Ro[0], c.dwt * c.Ro[1], 0.0};
   double Rn[3] = {0.0, 0.0, 0.0};

@@ -206,7 +206,8 @@ __device__ inline void decide_wave(const SweepArgs& a, int jd) {
 // while the first updates the colours (or after them when a colour is wider
 // than a wavefront), so that a launch has one workgroup per domain.
 template <int DIM, bool GLOB, bool STAGE, bool FOLD>
-__device__ inline void sweep_block(const SweepArgs& a, int b, int j, BatchProg* bp) {
+__device__ __attribute__((always_inline)) inline void sweep_block(const SweepArgs& a, int b, int j,
+                                                                  BatchProg* bp) {
   extern __shared__ double lds[];
   __shared__ BlockRed red;
   __shared__ int s_co[CD_MAX_COLORS + 1];
@@ -254,7 +255,8 @@ template <int DIM, bool STAGE>
 __global__ __launch_bounds__(kMaxBlock) void k_sweep_batch(const SweepArgs* tab, const int* blk,
                                                           int j, BatchProg* bp) {
   const int2 pb = ((const int2*)blk)[blockIdx.x];
-  const SweepArgs a = tab[pb.x];
+  // read in place: a local copy of the arguments would live in scratch
+  const SweepArgs& a = tab[pb.x];
   sweep_block<DIM, false, STAGE, false>(a, pb.y, j, bp);
 }
 
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_decide_batch(const SweepArgs* tab
                                                            BatchProg* bp) {
   __shared__ BlockRed red;
   __shared__ int s_flag;
-  const SweepArgs a = tab[blockIdx.x];
+  const SweepArgs& a = tab[blockIdx.x];
   decide_block(a, jd, red, s_flag, bp, kMaxBlock);
 }
 
