@@ -95,11 +95,69 @@ def measured_traffic(path):
     return rec.get("bytes_per_launch") if rec.get("kernel_sources_sha256") == h.hexdigest() else None
 
 
-def make_ctx(wl, pk, binding, timing=1, solve_mode=1, block=0):
+def make_ctx(wl, pk, binding, timing=1, solve_mode=1, block=0, n_domains=None, max_iter=2000):
     params = binding.make_params(wl["dim"], pk.n_walls, mu=wl["mu"], dt=1e-3, alpha=1e-6,
-                                 criterion=0, max_iter=2000, n_domains=wl["domains"],
+                                 criterion=0, max_iter=max_iter,
+                                 n_domains=wl["domains"] if n_domains is None else n_domains,
                                  repartition_every=10, warm_start=1)
     return binding.Context(params, pk, timing=timing, solve_mode=solve_mode, block_threads=block)
+
+
+def boundary_fraction(n, c):
+    """Fraction of contacts with a body that also has contacts in another
+    domain (walls excluded): the share of the update that sees frozen
+    foreign forces, the parallel fraction p of Sec. 2.3."""
+    import numpy as np
+    ci, cj, dom = c["ci"].astype(np.int64), c["cj"].astype(np.int64), c["dom"].astype(np.int64)
+    if ci.size == 0:
+        return 0.0
+    body = np.concatenate([ci, cj[cj < n]])
+    d = np.concatenate([dom, dom[cj < n]])
+    lo = np.full(n, np.iinfo(np.int64).max)
+    hi = np.full(n, -1)
+    np.minimum.at(lo, body, d)
+    np.maximum.at(hi, body, d)
+    shared = lo != hi
+    shared_c = shared[ci] | np.where(cj < n, shared[np.minimum(cj, n - 1)], False)
+    return float(shared_c.mean())
+
+
+def sequential_comparison(wl, pk, ctx, torch, binding, max_iter):
+    """One time step solved from scratch (cold start) on the state the timed
+    steps ended in, with the workload's domains and with a single domain
+    (the plain sequential solve): the extra sweeps of the domain-wise solve,
+    N_I(P) / N_I(1) (Sec. 4.4), and the macroscopic observables of Sec. 4.5."""
+    from paper_1104_3516_amd import analysis
+    q = pk.copy()
+    x, v, w = (t.cpu().numpy() for t in ctx.state())
+    q.x, q.v, q.w = x, v, w
+    q.wall_offset = ctx.wall_offsets()
+    runs = {}
+    for P in (wl["domains"], 1):
+        log(f"sequential comparison: one cold-started step with {P} domain(s) ...")
+        c = make_ctx(wl, q, binding, timing=0, n_domains=P, max_iter=max_iter)
+        t0 = time.perf_counter()
+        r = c.step()
+        torch.cuda.synchronize()
+        hc = analysis.host_contacts(c.contacts())
+        runs[P] = dict(x=q.x, c=hc, it=r.iterations, status=r.status,
+                       seconds=time.perf_counter() - t0, glob=c.timing().global_records)
+        log(f"  {r.iterations} sweeps, status {r.status}, {runs[P]['seconds']:.1f} s")
+        c.close()
+    P = wl["domains"]
+    d = analysis.compare(q, runs[1], runs[P])
+    return {
+        "state": "the positions and velocities after the timed steps, forces from zero",
+        "n_domains": P, "sweeps": runs[P]["it"], "sweeps_one_domain": runs[1]["it"],
+        "status": runs[P]["status"], "status_one_domain": runs[1]["status"],
+        "extra_sweep_factor": runs[P]["it"] / max(runs[1]["it"], 1),
+        "boundary_contact_fraction": boundary_fraction(q.n, runs[P]["c"]),
+        "mean_stress_rel_diff": d["mean_stress"], "sigma_yy_strips_rel_diff": d["strips"],
+        "orientation_tv_distance": d["orientation_tv"],
+        "max_force_rel_diff": d.get("forces"),
+        "one_domain_seconds": runs[1]["seconds"],
+        "one_domain_global_records": bool(runs[1]["glob"]),
+    }
 
 
 def batch_domains(pk, target):
@@ -322,6 +380,10 @@ def main() -> int:
                          "for scaling hardware byte counters, and exit")
     ap.add_argument("--target", type=int, default=0,
                     help="batch512: contacts per domain (0: the workload's default)")
+    ap.add_argument("--sequential", type=int, default=1,
+                    help="after the timed steps, solve one step from scratch with the "
+                         "workload's domains and with one domain (2D workloads)")
+    ap.add_argument("--sequential-max-iter", type=int, default=20000)
     ap.add_argument("--traffic-json", default=None,
                     help="counter record of the sweep kernel (default: the workload's)")
     args = ap.parse_args()
@@ -495,6 +557,9 @@ def main() -> int:
                                 f"k_sweep<{dim}, {'staged' if tm.staged else 'register'}>"),
                      "bytes_per_sweep": bytes_per_sweep},
     }
+    if args.sequential and dim == 2:
+        out["sequential_comparison"] = sequential_comparison(wl, pk, ctx, torch, binding,
+                                                             args.sequential_max_iter)
     if args.cpu_sweeps > 0:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, pk, args.cpu_sweeps)

@@ -100,7 +100,8 @@ typedef struct cd_timing {
   int sweeps_timed;      /* sweep launches inside the timed groups (per-sweep mode) */
   int staged;            /* 1: the sweeps read each domain's contact data from LDS;
                             2: and workgroup 0 also took each stop decision */
-  int pad;
+  int global_records;    /* 1: a domain's particle records did not fit in LDS and the
+                            sweeps kept them in global memory */
 } cd_timing;
 
 typedef struct cd_ctx cd_ctx;

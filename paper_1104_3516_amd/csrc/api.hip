@@ -961,6 +961,7 @@ int finish_complete(cd_ctx* c, cd_result* out) {
   }
   tm.sweep_kernel_ms = sk;
   tm.staged = c->sweep_stage ? (c->sweep_fold ? 2 : 1) : 0;
+  tm.global_records = c->sweep_global ? 1 : 0;
   c->timing = tm;
   if (c->block_override < 0 && tm.sweeps_timed > 0)
     tune_block_record(c, 1e3 * sk / std::max(executed, 1));

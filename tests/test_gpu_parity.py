@@ -104,6 +104,17 @@ def test_disks_1k_single_domain(criterion):
     compare_step(sim, ctx, f"disks_1k crit{criterion}")
 
 
+def test_disks_9k_single_domain_global_records():
+    """96x96 disks in one domain: the records of its particles in contact
+    (about 7,000 x 48 B) do not fit in a workgroup's 160 KiB of LDS, so the
+    sweeps keep them in global memory; two steps, the second warm-started."""
+    pk = inputs.lattice_2d(96, 96, 1000)
+    sim, ctx = both(pk, mu=0.3, n_domains=1)
+    for s in range(2):
+        compare_step(sim, ctx, f"9k one domain s{s}")
+        assert ctx.timing().global_records == 1
+
+
 @pytest.mark.parametrize("solve_mode", [1, 2])
 def test_disks_4k_64_domains_multi_step(solve_mode):
     """Mode 1 stages each domain's contact data in LDS here; mode 2 reads it
