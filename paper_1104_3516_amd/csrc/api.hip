@@ -611,28 +611,42 @@ int prep_phase0(cd_ctx* c) {
     if (c->adj_every > 0) return cd_window_geometry(c);
     return CD_OK;
   }
-  // ---- boundary width: 2 vmax dt (Sec. 3.1)
+  // ---- boundary width 2 vmax dt (Sec. 3.1): the particles' maximum speed
+  // stays on the device, where the pair search reads it; the host checks
+  // the width with the pair count
   CD_TRY(cd_launch_vmax(c));
+  {
+    const int dim = c->dim;
+    double ws = 0.0;
+    for (int wi = 0; wi < c->W; ++wi) {
+      double q = 0.0;
+      for (int k = 0; k < dim; ++k) q = q + c->wu[wi * dim + k] * c->wu[wi * dim + k];
+      const double sp = sqrt(q);
+      if (sp > ws) ws = sp;
+    }
+    c->st_wall_speed = ws;
+  }
+  // ---- cells and pair count
+  int st = setup_grid(c);
+  if (st != CD_OK) return st;
+  CD_TRY(cd_launch_cells(c));
+  CD_TRY(cd_launch_pair_count(c));
   CD_TRY(hipMemcpyAsync(c->h_scratch, c->d_vmax, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                        c->stream));
+  CD_TRY(hipMemcpyAsync(c->h_scratch + 1, c->pair_off + c->n, sizeof(int), hipMemcpyDeviceToHost,
                         c->stream));
   return CD_OK;
 }
 
 int prep_phase1(cd_ctx* c) {
   if (c->frozen_now) return CD_OK;
-  const int dim = c->dim;
   const double dt = c->p.dt;
   double vmax;
   {
     unsigned long long bits = (unsigned long long)c->h_scratch[0];
     memcpy(&vmax, &bits, sizeof(double));
   }
-  for (int wi = 0; wi < c->W; ++wi) {
-    double q = 0.0;
-    for (int k = 0; k < dim; ++k) q = q + c->wu[wi * dim + k] * c->wu[wi * dim + k];
-    double sp = sqrt(q);
-    if (sp > vmax) vmax = sp;
-  }
+  if (c->st_wall_speed > vmax) vmax = c->st_wall_speed;
   if (!isfinite(vmax)) return fail(c, CD_ENONFINITE, "non-finite velocity");
   const double skin = c->p.skin >= 0.0 ? c->p.skin : 2.0 * vmax * dt;
   c->st_skin = skin;
@@ -644,27 +658,14 @@ int prep_phase1(cd_ctx* c) {
   std::swap(c->R, c->R_prev);
   std::swap(c->cap_prev, c->cap_list);
   c->nc_prev = c->step > 0 ? c->nc : 0;
-  // ---- cells and pair search
-  int st = setup_grid(c);
-  if (st != CD_OK) return st;
-  CD_TRY(cd_launch_cells(c));
-  CD_TRY(cd_launch_pair_count(c, skin));
-  CD_TRY(hipMemcpyAsync(c->h_scratch, c->pair_off + c->n, sizeof(int), hipMemcpyDeviceToHost,
-                        c->stream));
-  return CD_OK;
-}
-
-int prep_phase2(cd_ctx* c) {
-  if (c->frozen_now) return CD_OK;
-  const double skin = c->st_skin;
-  const int64_t nc = (int64_t)((int*)c->h_scratch)[0];
+  const int64_t nc = (int64_t)((int*)(c->h_scratch + 1))[0];
   if (nc < 0 || nc > ((int64_t)1 << 30)) return fail(c, CD_ECAPACITY, "too many contacts");
   int st = ensure_capacity(c, nc);
   if (st != CD_OK) return st;
   st = ensure_list(c, nc, &c->cap_list, &c->ci, &c->cj, &c->R);
   if (st != CD_OK) return st;
   c->nc = nc;
-  CD_TRY(cd_launch_pair_fill(c, skin));
+  CD_TRY(cd_launch_pair_fill(c));
   CD_TRY(cd_launch_geometry(c));
   CD_TRY(cd_launch_warm_start(c));
   CD_TRY(hipEventRecord(c->ev[1], c->stream));
@@ -683,7 +684,7 @@ int prep_phase2(cd_ctx* c) {
   return CD_OK;
 }
 
-int prep_phase3(cd_ctx* c) {
+int prep_phase2(cd_ctx* c) {
   if (c->frozen_now) return CD_OK;
   const int dim = c->dim;
   DomainStats ds;
@@ -752,7 +753,6 @@ int prep_phase(cd_ctx* c, int k) {
     case 0: return prep_phase0(c);
     case 1: return prep_phase1(c);
     case 2: return prep_phase2(c);
-    case 3: return prep_phase3(c);
   }
   return CD_EINVAL;
 }

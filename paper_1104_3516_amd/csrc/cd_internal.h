@@ -307,6 +307,7 @@ struct cd_ctx {
   cd_result last{};
   // the current step, between its phases
   double st_skin = 0.0;
+  double st_wall_speed = 0.0;   // largest wall speed of the step (host)
   DomainStats st_ds{};
   int st_limit = 0;
   SolveRun run;
@@ -317,7 +318,7 @@ int step_prepare(cd_ctx* c);
 // step_prepare in kPrepPhases parts; each part but the last ends with a small
 // device-to-host copy that the next part reads, so the caller synchronises
 // the stream between parts (once for a whole batch)
-constexpr int kPrepPhases = 4;
+constexpr int kPrepPhases = 3;
 int prep_phase(cd_ctx* c, int k);
 int solve_single(cd_ctx* c);
 int step_finish(cd_ctx* c, cd_result* out);
@@ -337,8 +338,8 @@ hipError_t cd_radix_sort(cd_ctx* c, unsigned long long* keys, int* vals, unsigne
 // detect.hip
 hipError_t cd_launch_vmax(cd_ctx* c);
 hipError_t cd_launch_cells(cd_ctx* c);
-hipError_t cd_launch_pair_count(cd_ctx* c, double skin);
-hipError_t cd_launch_pair_fill(cd_ctx* c, double skin);
+hipError_t cd_launch_pair_count(cd_ctx* c);   // boundary width from d_vmax and st_wall_speed
+hipError_t cd_launch_pair_fill(cd_ctx* c);
 hipError_t cd_launch_geometry(cd_ctx* c);
 hipError_t cd_launch_warm_start(cd_ctx* c);
 // partition.hip

@@ -108,14 +108,30 @@ __device__ inline double wall_gap(const double* x, const double* r, int64_t n, i
   return (proj - wall[W * DIM + w]) - r[i];
 }
 
+// The boundary width of the step: `fixed` when given (>= 0), else 2 vmax dt
+// with vmax the larger of the particles' maximum speed (device, from k_vmax)
+// and the walls' (host): the same operations as the host's check of it.
+struct SkinArgs {
+  const unsigned long long* vmax_bits;
+  double wall_speed, fixed, dt;
+};
+
+__device__ inline double skin_of(const SkinArgs& k) {
+  if (k.fixed >= 0.0) return k.fixed;
+  double vm = __longlong_as_double((long long)*k.vmax_bits);
+  if (k.wall_speed > vm) vm = k.wall_speed;
+  return 2.0 * vm * k.dt;
+}
+
 template <int DIM, bool FILL>
 __global__ __launch_bounds__(kThreads) void k_pairs(const double* x, const double* r, int64_t n,
                                                    CellGrid g, const int* cell_of,
                                                    const int* cell_start, const int* members,
-                                                   const double* wall, int W, double skin,
+                                                   const double* wall, int W, SkinArgs sk,
                                                    int* count, const int* off, int* ci, int* cj) {
   int64_t ii = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (ii >= n) return;
+  const double skin = skin_of(sk);
   int i = (int)ii;
   int cell = cell_of[i];
   int cx = cell % g.ncell[0];
@@ -266,8 +282,9 @@ hipError_t cd_launch_cells(cd_ctx* c) {
   return hipGetLastError();
 }
 
-hipError_t cd_launch_pair_count(cd_ctx* c, double skin) {
+hipError_t cd_launch_pair_count(cd_ctx* c) {
   CellGrid g = make_grid(c);
+  const SkinArgs skin{c->d_vmax, c->st_wall_speed, c->p.skin, c->p.dt};
   int nb = cd_blocks(c->n, kThreads);
   if (c->dim == 2)
     hipLaunchKernelGGL((k_pairs<2, false>), dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->r,
@@ -282,8 +299,9 @@ hipError_t cd_launch_pair_count(cd_ctx* c, double skin) {
   return cd_scan_exclusive(c, c->pair_count, c->pair_off, c->n);
 }
 
-hipError_t cd_launch_pair_fill(cd_ctx* c, double skin) {
+hipError_t cd_launch_pair_fill(cd_ctx* c) {
   CellGrid g = make_grid(c);
+  const SkinArgs skin{c->d_vmax, c->st_wall_speed, c->p.skin, c->p.dt};
   int nb = cd_blocks(c->n, kThreads);
   if (c->dim == 2)
     hipLaunchKernelGGL((k_pairs<2, true>), dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->r,
