@@ -294,11 +294,77 @@ static int cmp_f64(const void* a, const void* b) {
   return (x > y) - (x < y);
 }
 
-/* split `node` owning contacts ids[0..cnt) in region [lo, hi] */
-static void orb_split(int dim, const tree_shape* t, int node, const double* lo,
-                      const double* hi, int64_t nc, const double* xmid, int32_t* ids,
-                      int64_t cnt, int32_t* node_axis, double* node_cut, int32_t* dom,
-                      double* scratch, int32_t* tmp_ids) {
+/* ------------------------------------------------------------------ */
+/* adaptive load balancing (Sec. 3.3)                                   */
+/* ------------------------------------------------------------------ */
+
+/* Load imbalance of a step (Sec. 3.3): sigma_T = sqrt(<T^2> - <T>^2) / <T>,
+ * the averages taken over the P domains' times. */
+double cdref_sigma_t(int P, const double* T) {
+  if (P < 1) return 0.0;
+  double s = 0.0, s2 = 0.0;
+  for (int i = 0; i < P; ++i) {
+    s = s + T[i];
+    s2 = s2 + T[i] * T[i];
+  }
+  double mean = s / (double)P, mean2 = s2 / (double)P;
+  double var = mean2 - mean * mean;
+  if (var < 0.0) var = 0.0;
+  return mean > 0.0 ? sqrt(var) / mean : 0.0;
+}
+
+/* Share of its node's contacts that the left branch of every inner node
+ * receives (Sec. 3.3): nu_L / (nu_L + nu_R), where nu of a branch sums the
+ * capacities of the leaves below it (the paper's nu_j = sum V_i / T_i; here
+ * a capacity is the contacts a domain handled per unit time).  A capacity
+ * that is not positive and finite carries no measurement and counts as the
+ * mean of the valid ones (1 when there are none).  node_frac has 2P-1
+ * entries in creation order (0 for leaves). */
+static int balance_fractions(const tree_shape* t, const double* capacity, double* node_frac) {
+  double* nu = (double*)malloc(sizeof(double) * (size_t)t->count);
+  if (!nu) return CDREF_ENOMEM;
+  double sum = 0.0;
+  int valid = 0;
+  int P = (t->count + 1) / 2;
+  for (int i = 0; i < P; ++i) {
+    if (capacity[i] > 0.0 && isfinite(capacity[i])) {
+      sum = sum + capacity[i];
+      ++valid;
+    }
+  }
+  double fill = valid > 0 ? sum / (double)valid : 1.0;
+  /* children are created after their parents: reverse creation order is
+     bottom-up */
+  for (int node = t->count - 1; node >= 0; --node) {
+    int left = t->child[2 * node], right = t->child[2 * node + 1];
+    if (left < 0) {
+      double c = capacity[t->leaf[node]];
+      nu[node] = (c > 0.0 && isfinite(c)) ? c : fill;
+      node_frac[node] = 0.0;
+    } else {
+      nu[node] = nu[left] + nu[right];
+      node_frac[node] = nu[left] / nu[node];
+    }
+  }
+  free(nu);
+  return CDREF_OK;
+}
+
+int cdref_balance_fractions(int P, const double* capacity, double* node_frac) {
+  if (P < 1) return CDREF_EINVAL;
+  tree_shape t;
+  int st = tree_shape_build(P, &t);
+  if (st == CDREF_OK) st = balance_fractions(&t, capacity, node_frac);
+  tree_shape_free(&t);
+  return st;
+}
+
+/* split `node` owning contacts ids[0..cnt) in region [lo, hi]; frac (or
+   NULL: leaf counts) gives the left branch's share of the contacts */
+static void orb_split(int dim, const tree_shape* t, const double* frac, int node,
+                      const double* lo, const double* hi, int64_t nc, const double* xmid,
+                      int32_t* ids, int64_t cnt, int32_t* node_axis, double* node_cut,
+                      int32_t* dom, double* scratch, int32_t* tmp_ids) {
   if (t->child[2 * node] < 0) {
     node_axis[node] = -1;
     node_cut[node] = 0.0;
@@ -317,7 +383,15 @@ static void orb_split(int dim, const tree_shape* t, int node, const double* lo,
   if (cnt > 0) {
     for (int64_t s = 0; s < cnt; ++s) scratch[s] = xmid[(int64_t)axis * nc + ids[s]];
     qsort(scratch, (size_t)cnt, sizeof(double), cmp_f64);
-    int64_t k = (cnt * ll) / (ll + lr);   /* share of contacts ~ share of leaves */
+    int64_t k;
+    if (frac) {
+      /* share of contacts = share of capacity (Sec. 3.3) */
+      k = (int64_t)floor((double)cnt * frac[node]);
+      if (k > cnt - 1) k = cnt - 1;
+      if (k < 0) k = 0;
+    } else {
+      k = (cnt * ll) / (ll + lr);   /* share of contacts ~ share of leaves */
+    }
     cut = scratch[k];
   } else {
     cut = 0.5 * (lo[axis] + hi[axis]);
@@ -335,34 +409,50 @@ static void orb_split(int dim, const tree_shape* t, int node, const double* lo,
   for (int k = 0; k < dim; ++k) { llo[k] = rlo[k] = lo[k]; lhi[k] = rhi[k] = hi[k]; }
   lhi[axis] = cut;
   rlo[axis] = cut;
-  orb_split(dim, t, left, llo, lhi, nc, xmid, ids, nl, node_axis, node_cut, dom, scratch, tmp_ids);
-  orb_split(dim, t, right, rlo, rhi, nc, xmid, ids + nl, nr, node_axis, node_cut, dom, scratch,
+  orb_split(dim, t, frac, left, llo, lhi, nc, xmid, ids, nl, node_axis, node_cut, dom, scratch,
             tmp_ids);
+  orb_split(dim, t, frac, right, rlo, rhi, nc, xmid, ids + nl, nr, node_axis, node_cut, dom,
+            scratch, tmp_ids);
 }
 
 int cdref_orb(int dim, int P, const double* box_lo, const double* box_hi,
               int64_t nc, const double* xmid,
               int32_t* node_axis, double* node_cut, int32_t* node_child,
               int32_t* node_leaf, int32_t* node_leaves, int32_t* dom) {
+  return cdref_orb_capacity(dim, P, box_lo, box_hi, nc, xmid, NULL, node_axis, node_cut,
+                            node_child, node_leaf, node_leaves, dom);
+}
+
+int cdref_orb_capacity(int dim, int P, const double* box_lo, const double* box_hi,
+                       int64_t nc, const double* xmid, const double* capacity,
+                       int32_t* node_axis, double* node_cut, int32_t* node_child,
+                       int32_t* node_leaf, int32_t* node_leaves, int32_t* dom) {
   if (P < 1 || (dim != 2 && dim != 3)) return CDREF_EINVAL;
   tree_shape t;
   int st = tree_shape_build(P, &t);
   if (st != CDREF_OK) { tree_shape_free(&t); return st; }
+  double* frac = NULL;
+  if (capacity) {
+    frac = (double*)malloc(sizeof(double) * (size_t)t.count);
+    if (!frac) { tree_shape_free(&t); return CDREF_ENOMEM; }
+    st = balance_fractions(&t, capacity, frac);
+    if (st != CDREF_OK) { free(frac); tree_shape_free(&t); return st; }
+  }
   int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
   int32_t* tmp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
   double* scratch = (double*)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
   if (!ids || !tmp || !scratch) {
-    free(ids); free(tmp); free(scratch); tree_shape_free(&t);
+    free(ids); free(tmp); free(scratch); free(frac); tree_shape_free(&t);
     return CDREF_ENOMEM;
   }
   for (int64_t c = 0; c < nc; ++c) ids[c] = (int32_t)c;
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   for (int k = 0; k < dim; ++k) { lo[k] = box_lo[k]; hi[k] = box_hi[k]; }
-  orb_split(dim, &t, 0, lo, hi, nc, xmid, ids, nc, node_axis, node_cut, dom, scratch, tmp);
+  orb_split(dim, &t, frac, 0, lo, hi, nc, xmid, ids, nc, node_axis, node_cut, dom, scratch, tmp);
   memcpy(node_child, t.child, sizeof(int32_t) * 2 * (size_t)t.count);
   memcpy(node_leaf, t.leaf, sizeof(int32_t) * (size_t)t.count);
   if (node_leaves) memcpy(node_leaves, t.leaves, sizeof(int32_t) * (size_t)t.count);
-  free(ids); free(tmp); free(scratch); tree_shape_free(&t);
+  free(ids); free(tmp); free(scratch); free(frac); tree_shape_free(&t);
   return CDREF_OK;
 }
 
@@ -782,6 +872,7 @@ struct cdref_sim {
   int32_t *axis, *child, *leaf;
   double* cut;
   int have_tree;
+  double* capacity;   /* per-domain capacities for the tree rebuilds, or NULL */
   /* contacts of the last step */
   int64_t nc, cap;
   int32_t *ci, *cj, *dom, *color, *slot;
@@ -836,7 +927,21 @@ void cdref_sim_destroy(cdref_sim* s) {
   free(s->axis); free(s->child); free(s->leaf); free(s->cut);
   free(s->ci); free(s->cj); free(s->dom); free(s->color); free(s->slot);
   free(s->normal); free(s->gap); free(s->xmid); free(s->R);
+  free(s->capacity);
   free(s);
+}
+
+int cdref_sim_set_capacity(cdref_sim* s, const double* capacity) {
+  int P = s->p.n_domains;
+  if (!capacity) {
+    free(s->capacity);
+    s->capacity = NULL;
+    return CDREF_OK;
+  }
+  if (!s->capacity) s->capacity = (double*)malloc(sizeof(double) * (size_t)P);
+  if (!s->capacity) return CDREF_ENOMEM;
+  memcpy(s->capacity, capacity, sizeof(double) * (size_t)P);
+  return CDREF_OK;
 }
 
 static int ensure_capacity(cdref_sim* s, int64_t need) {
@@ -947,8 +1052,8 @@ int cdref_sim_step(cdref_sim* s, cdref_info* info) {
      descend the existing one (Sec. 3.2) */
   int P = p->n_domains;
   if (!s->have_tree || s->step % p->repartition_every == 0) {
-    st = cdref_orb(dim, P, s->lo, s->hi, nc, s->xmid, s->axis, s->cut, s->child, s->leaf, NULL,
-                   s->dom);
+    st = cdref_orb_capacity(dim, P, s->lo, s->hi, nc, s->xmid, s->capacity, s->axis, s->cut,
+                            s->child, s->leaf, NULL, s->dom);
     if (st != CDREF_OK) return st;
     s->have_tree = 1;
   } else {

@@ -101,6 +101,24 @@ int cdref_orb(int dim, int P, const double* box_lo, const double* box_hi,
               int32_t* node_axis, double* node_cut, int32_t* node_child,
               int32_t* node_leaf, int32_t* node_leaves, int32_t* dom);
 
+/* The same with the cuts placed by capacity (Sec. 3.3): the left branch of
+ * every inner node receives the share nu_L / (nu_L + nu_R) of the node's
+ * contacts (k = floor(n share), at most n - 1), nu of a branch summing the
+ * capacities (P doubles, domain order) of its leaves; NULL capacity: leaf
+ * counts, as cdref_orb. */
+int cdref_orb_capacity(int dim, int P, const double* box_lo, const double* box_hi,
+                       int64_t nc, const double* xmid, const double* capacity,
+                       int32_t* node_axis, double* node_cut, int32_t* node_child,
+                       int32_t* node_leaf, int32_t* node_leaves, int32_t* dom);
+
+/* The left-branch shares of the inner nodes for P capacities (2P-1 entries,
+ * 0 for leaves); capacities that are not positive and finite count as the
+ * mean of the valid ones (1 if none). */
+int cdref_balance_fractions(int P, const double* capacity, double* node_frac);
+
+/* Load imbalance sigma_T = sqrt(<T^2> - <T>^2) / <T> over P times (Sec. 3.3). */
+double cdref_sigma_t(int P, const double* T);
+
 /* Assign contacts to domains by descending an existing tree (Sec. 3.2). */
 void cdref_descend(int dim, int P, const int32_t* node_axis, const double* node_cut,
                    const int32_t* node_child, const int32_t* node_leaf,
@@ -163,6 +181,9 @@ void cdref_sim_state(const cdref_sim* s, double* x, double* v, double* w, double
 int64_t cdref_sim_contacts(const cdref_sim* s, int64_t cap, int32_t* ci, int32_t* cj,
                            double* normal, double* gap, double* R, int32_t* dom,
                            int32_t* color, int32_t* slot_contact);
+/* capacities (P doubles, domain order) used by every later tree rebuild;
+ * NULL: back to leaf counts */
+int cdref_sim_set_capacity(cdref_sim* s, const double* capacity);
 /* the current tree (2P-1 nodes) */
 void cdref_sim_tree(const cdref_sim* s, int32_t* node_axis, double* node_cut,
                     int32_t* node_child, int32_t* node_leaf);

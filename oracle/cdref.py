@@ -60,6 +60,11 @@ def lib():
         L.cdref_geometry.argtypes = [C.c_int, i64, P, P, C.c_int, P, P, i64, P, P, P, P, P]
         L.cdref_geometry.restype = None
         L.cdref_orb.argtypes = [C.c_int, C.c_int, P, P, i64, P, P, P, P, P, P, P]
+        L.cdref_orb_capacity.argtypes = [C.c_int, C.c_int, P, P, i64, P, P, P, P, P, P, P, P]
+        L.cdref_balance_fractions.argtypes = [C.c_int, P, P]
+        L.cdref_sigma_t.argtypes = [C.c_int, P]
+        L.cdref_sigma_t.restype = C.c_double
+        L.cdref_sim_set_capacity.argtypes = [P, P]
         L.cdref_descend.argtypes = [C.c_int, C.c_int, P, P, P, P, i64, P, P]
         L.cdref_descend.restype = None
         L.cdref_tree_leaves.argtypes = [C.c_int, P]
@@ -147,7 +152,9 @@ class Tree:
     leaves: np.ndarray
 
 
-def orb(dim: int, P: int, box_lo, box_hi, xmid):
+def orb(dim: int, P: int, box_lo, box_hi, xmid, capacity=None):
+    """Bisection tree and domains; `capacity` (P values) places the cuts by
+    capacity share (Sec. 3.3) instead of leaf counts."""
     L = lib()
     xmid = _f64(xmid)
     nc = xmid.shape[1] if xmid.ndim == 2 else 0
@@ -155,11 +162,29 @@ def orb(dim: int, P: int, box_lo, box_hi, xmid):
     t = Tree(np.zeros(nodes, np.int32), np.zeros(nodes), np.zeros(2 * nodes, np.int32),
              np.zeros(nodes, np.int32), np.zeros(nodes, np.int32))
     dom = np.zeros(max(nc, 1), np.int32)
-    st = L.cdref_orb(dim, P, _p(_f64(box_lo)), _p(_f64(box_hi)), nc, _p(xmid), _p(t.axis),
-                     _p(t.cut), _p(t.child), _p(t.leaf), _p(t.leaves), _p(dom))
+    cap = None if capacity is None else _f64(capacity)
+    st = L.cdref_orb_capacity(dim, P, _p(_f64(box_lo)), _p(_f64(box_hi)), nc, _p(xmid), _p(cap),
+                              _p(t.axis), _p(t.cut), _p(t.child), _p(t.leaf), _p(t.leaves),
+                              _p(dom))
     if st != OK:
         raise RuntimeError(f"cdref_orb failed: {st}")
     return t, dom[:nc]
+
+
+def balance_fractions(P: int, capacity) -> np.ndarray:
+    """Left-branch share of every inner node for per-domain capacities
+    (Sec. 3.3); 2P-1 entries in creation order, 0 for leaves."""
+    out = np.zeros(2 * P - 1)
+    st = lib().cdref_balance_fractions(P, _p(_f64(capacity)), _p(out))
+    if st != OK:
+        raise RuntimeError(st)
+    return out
+
+
+def sigma_t(T) -> float:
+    """Load imbalance of per-domain times (Sec. 3.3)."""
+    T = _f64(T)
+    return float(lib().cdref_sigma_t(len(T), _p(T)))
 
 
 def descend(dim: int, P: int, tree: Tree, xmid):
@@ -302,6 +327,13 @@ class Sim:
                                   _p(dom), _p(color), _p(slot))
         return dict(ci=ci[:nc], cj=cj[:nc], normal=normal[:, :nc], gap=gap[:nc], R=R[:, :nc],
                     dom=dom[:nc], color=color[:nc], slot=slot[:nc])
+
+    def set_capacity(self, capacity=None):
+        """Per-domain capacities for every later tree rebuild (None: leaf counts)."""
+        self._cap = None if capacity is None else _f64(capacity)
+        st = self.L.cdref_sim_set_capacity(self.h, _p(self._cap))
+        if st != OK:
+            raise RuntimeError(st)
 
     def tree(self) -> Tree:
         P = self.params.n_domains
