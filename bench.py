@@ -380,6 +380,9 @@ def main() -> int:
                          "for scaling hardware byte counters, and exit")
     ap.add_argument("--target", type=int, default=0,
                     help="batch512: contacts per domain (0: the workload's default)")
+    ap.add_argument("--balance", type=float, default=-1.0, metavar="SIGMA",
+                    help="adaptive load balancing (Sec. 3.3) with this threshold on sigma_T "
+                         "(negative: off, the headline configuration)")
     ap.add_argument("--sequential", type=int, default=1,
                     help="after the timed steps, solve one step from scratch with the "
                          "workload's domains and with one domain (2D workloads)")
@@ -489,6 +492,9 @@ def main() -> int:
 
     ctx = make_ctx(wl, pk, binding, timing=args.time_every, solve_mode=args.solve_mode,
                    block=args.block)
+    if args.balance >= 0.0:
+        ctx.set_load_balance(args.balance)
+    sigmas = []
     torch.cuda.synchronize()
     sweeps = 0
     updates = 0
@@ -511,6 +517,8 @@ def main() -> int:
         bytes_sweeps += tm.sweeps_executed * (BYTES[dim][0] * r.n_contacts +
                                               BYTES[dim][1] * pk.n)
         maxiter_steps += int(r.status == binding.MAXITER)
+        if args.balance >= 0.0:
+            sigmas.append(ctx.domain_times()[1])
         if s % 10 == 0 or s == args.steps - 1:
             log(f"step {s}: {r.iterations} sweeps, {r.n_contacts} contacts, status {r.status}, "
                 f"solve {tm.solve_ms:.2f} ms, sweep kernels {tm.sweep_kernel_ms:.2f} ms "
@@ -557,6 +565,14 @@ def main() -> int:
                                 f"k_sweep<{dim}, {'staged' if tm.staged else 'register'}>"),
                      "bytes_per_sweep": bytes_per_sweep},
     }
+    if args.balance >= 0.0:
+        out["load_balance"] = {
+            "threshold": args.balance,
+            "sigma_t_first_step": sigmas[0] if sigmas else None,
+            "sigma_t_last_step": sigmas[-1] if sigmas else None,
+            "sigma_t_mean": sum(sigmas) / len(sigmas) if sigmas else None,
+            "note": "per-domain sweep times measured in the timed steps; capacities n_i / T_i "
+                    "place the cuts of every later rebuild (Sec. 3.3)"}
     if args.sequential and dim == 2:
         out["sequential_comparison"] = sequential_comparison(wl, pk, ctx, torch, binding,
                                                              args.sequential_max_iter)

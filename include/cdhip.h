@@ -187,6 +187,36 @@ int cd_set_solve_mode(cd_ctx* ctx, int mode);
  * with every > 0). */
 int cd_set_launch(cd_ctx* ctx, int block_threads);
 
+/* Adaptive load balancing (Sec. 3.3).  sigma_star >= 0 switches load
+ * measurement on: every sweep launch records, per domain, the real time its
+ * workgroup spends on it (per-sweep launches only: solve modes 1-3, not the
+ * one-launch mode 0, not batched sweeps), summed over the step.  After each
+ * step the imbalance sigma_T = sqrt(<T^2> - <T>^2) / <T> over the P domain
+ * times T_i is computed; when sigma_T >= sigma_star the per-domain
+ * capacities become n_i / T_i (n_i the domain's contacts in that step), and
+ * every later tree rebuild (cd_params.repartition_every) cuts each inner
+ * node so that its left branch receives the share nu_L / (nu_L + nu_R) of
+ * the node's contacts, nu of a branch summing the capacities of its leaves
+ * (a domain without contacts or time counts as the mean capacity).  Below
+ * the threshold the last capacities stay in force, as the paper keeps the
+ * domain configuration.  sigma_star < 0 (default) switches measurement off
+ * and returns to leaf-count cuts.  CD_EINVAL for a non-finite threshold,
+ * CD_ENOMEM / CD_EHIP when the measurement buffers or the clock rate are
+ * unavailable. */
+int cd_set_load_balance(cd_ctx* ctx, double sigma_star);
+
+/* Capacities for the tree rebuilds from now on (host array of P doubles in
+ * domain order, copied), in place of measured ones: for tests and for
+ * callers with a cost model of their own.  NULL returns to leaf-count
+ * cuts.  Measured capacities (cd_set_load_balance) replace them when the
+ * threshold is reached. */
+int cd_set_domain_capacity(cd_ctx* ctx, const double* capacity);
+
+/* The last measured step's per-domain times in microseconds (host array of
+ * P doubles, or NULL) and their sigma_T (or NULL).  CD_ENOTREADY before a
+ * measured step. */
+int cd_get_domain_times(cd_ctx* ctx, double* times_us, double* sigma_t);
+
 /* Phase timings of the last step (host struct). */
 int cd_get_timing(cd_ctx* ctx, cd_timing* out);
 

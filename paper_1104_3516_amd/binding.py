@@ -103,6 +103,9 @@ def lib():
         L.cd_solve.argtypes = [P, C.POINTER(Result)]
         L.cd_set_adjoint.argtypes = [P, C.c_int]
         L.cd_set_frozen_list.argtypes = [P, C.c_int]
+        L.cd_set_load_balance.argtypes = [P, C.c_double]
+        L.cd_set_domain_capacity.argtypes = [P, P]
+        L.cd_get_domain_times.argtypes = [P, P, P]
         L.cd_adjoint.argtypes = [P, P, P, P, P]
         L.cd_batch_create.argtypes = [C.POINTER(P), C.POINTER(P), C.c_int]
         L.cd_batch_destroy.argtypes = [P]
@@ -292,6 +295,29 @@ class Context:
         """Keep the next step's contact list, tree and colouring for the
         steps after it (geometry recomputed each step)."""
         self._check(self.L.cd_set_frozen_list(self.h, int(bool(on))))
+
+    def set_load_balance(self, sigma_star: float):
+        """Adaptive load balancing (Sec. 3.3) with threshold sigma_star on
+        sigma_T; negative switches it off."""
+        self._check(self.L.cd_set_load_balance(self.h, float(sigma_star)))
+
+    def set_domain_capacity(self, capacity=None):
+        """Per-domain capacities for the tree rebuilds (None: leaf counts)."""
+        if capacity is None:
+            self._check(self.L.cd_set_domain_capacity(self.h, None))
+            return
+        cap = np.ascontiguousarray(capacity, dtype=np.float64)
+        if cap.shape != (self.params.n_domains,):
+            raise ValueError("one capacity per domain")
+        self._check(self.L.cd_set_domain_capacity(self.h, cap.ctypes.data_as(C.c_void_p)))
+
+    def domain_times(self):
+        """(per-domain times of the last measured step in microseconds, sigma_T)."""
+        t = np.zeros(self.params.n_domains)
+        sig = C.c_double(0.0)
+        self._check(self.L.cd_get_domain_times(self.h, t.ctypes.data_as(C.c_void_p),
+                                               C.byref(sig)))
+        return t, sig.value
 
     def adjoint(self, dL_dR):
         """dL/dmu (n_c), dL/dv (dim x N), dL/dw (dr x N) of the last recorded solve."""

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <chrono>
 #include <cstdio>
@@ -446,6 +447,11 @@ int cd_destroy(cd_ctx* c) {
   cd_adjoint_release(c);
   cd_window_clear(c);
   release(&c->d_vmax);
+  release(&c->d_dtick);
+  release(&c->d_frac);
+  if (c->h_dtick) (void)hipHostFree(c->h_dtick);
+  if (c->h_domstart) (void)hipHostFree(c->h_domstart);
+  if (c->h_frac) (void)hipHostFree(c->h_frac);
   if (c->h_state) (void)hipHostFree(c->h_state);
   if (c->h_scratch) (void)hipHostFree(c->h_scratch);
   if (c->h_walls) (void)hipHostFree(c->h_walls);
@@ -562,6 +568,49 @@ int cd_set_solve_mode(cd_ctx* c, int mode) {
   if (!c || mode < 0 || mode > 2) return CD_EINVAL;
   c->persistent = mode == 0;
   c->stage_off = mode == 2;
+  return CD_OK;
+}
+
+int cd_set_load_balance(cd_ctx* c, double sigma_star) {
+  if (!c || !std::isfinite(sigma_star)) return CD_EINVAL;
+  if (sigma_star < 0.0) {
+    c->lb_sigma_star = -1.0;
+    c->lb_capacity.clear();
+    c->lb_have_times = false;
+    return CD_OK;
+  }
+  if (!c->d_dtick) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess ||
+        khz <= 0)
+      return fail(c, CD_EHIP, "no real-time clock rate");
+    c->wall_khz = khz;
+    if (hipMalloc((void**)&c->d_dtick, sizeof(unsigned long long) * (size_t)c->P) != hipSuccess)
+      return fail(c, CD_ENOMEM, "load measurement buffers");
+    if (hipHostMalloc((void**)&c->h_dtick, sizeof(unsigned long long) * (size_t)c->P) !=
+            hipSuccess ||
+        hipHostMalloc((void**)&c->h_domstart, sizeof(int) * ((size_t)c->P + 1)) != hipSuccess)
+      return fail(c, CD_ENOMEM, "load measurement buffers");
+  }
+  c->lb_sigma_star = sigma_star;
+  return CD_OK;
+}
+
+int cd_set_domain_capacity(cd_ctx* c, const double* capacity) {
+  if (!c) return CD_EINVAL;
+  if (!capacity) {
+    c->lb_capacity.clear();
+    return CD_OK;
+  }
+  c->lb_capacity.assign(capacity, capacity + c->P);
+  return CD_OK;
+}
+
+int cd_get_domain_times(cd_ctx* c, double* times_us, double* sigma_t) {
+  if (!c) return CD_EINVAL;
+  if (!c->lb_have_times) return fail(c, CD_ENOTREADY, "no measured step (cd_set_load_balance)");
+  if (times_us) std::copy(c->lb_times.begin(), c->lb_times.end(), times_us);
+  if (sigma_t) *sigma_t = c->lb_sigma;
   return CD_OK;
 }
 
@@ -757,6 +806,37 @@ int prep_phase(cd_ctx* c, int k) {
   return CD_EINVAL;
 }
 
+// Adaptive load balancing (Sec. 3.3) after a measured solve: per-domain
+// times in microseconds, their imbalance sigma_T, and, when sigma_T reaches
+// the threshold, new capacities (contacts per microsecond; a domain without
+// contacts or time gets 0, which the rebuild treats as no measurement)
+// that every later tree rebuild uses.
+static void lb_after_solve(cd_ctx* c) {
+  const int P = c->P;
+  const double us_per_tick = 1000.0 / (double)c->wall_khz;
+  c->lb_times.assign(P, 0.0);
+  double s = 0.0, s2 = 0.0;
+  for (int i = 0; i < P; ++i) {
+    const double T = (double)c->h_dtick[i] * us_per_tick;
+    c->lb_times[i] = T;
+    s = s + T;
+    s2 = s2 + T * T;
+  }
+  const double mean = s / (double)P, mean2 = s2 / (double)P;
+  double var = mean2 - mean * mean;
+  if (var < 0.0) var = 0.0;
+  c->lb_sigma = mean > 0.0 ? sqrt(var) / mean : 0.0;
+  c->lb_have_times = true;
+  if (c->lb_sigma >= c->lb_sigma_star) {
+    c->lb_capacity.assign(P, 0.0);
+    for (int i = 0; i < P; ++i) {
+      const int n = c->h_domstart[i + 1] - c->h_domstart[i];
+      const double T = c->lb_times[i];
+      c->lb_capacity[i] = (n > 0 && T > 0.0) ? (double)n / T : 0.0;
+    }
+  }
+}
+
 // The solve of one context alone.
 int solve_single(cd_ctx* c) {
   const int64_t nc = c->nc;
@@ -858,9 +938,17 @@ int solve_single(cd_ctx* c) {
     CD_TRY(cd_launch_decide(c, launched));
     CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
                           c->stream));
+    const bool measure = c->lb_sigma_star >= 0.0 && c->d_dtick && c->P > 0;
+    if (measure) {
+      CD_TRY(hipMemcpyAsync(c->h_dtick, c->d_dtick, sizeof(unsigned long long) * (size_t)c->P,
+                            hipMemcpyDeviceToHost, c->stream));
+      CD_TRY(hipMemcpyAsync(c->h_domstart, c->dom_start, sizeof(int) * ((size_t)c->P + 1),
+                            hipMemcpyDeviceToHost, c->stream));
+    }
     CD_TRY(hipStreamSynchronize(c->stream));
     // sweeps that did work: every launch up to the one after the stopping sweep
     executed = std::min(launched, c->h_state->iter + 1);
+    if (measure) lb_after_solve(c);
   } else {
     CD_TRY(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
                           c->stream));

@@ -265,6 +265,7 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
       return bfail(b, CD_ECAPACITY,
                    "packing " + std::to_string(p) + ": a domain does not fit in LDS");
     b->h_tab[p] = cd_sweep_args(c);
+    b->h_tab[p].dtick = nullptr;   // batched sweeps do not measure the load
     block = std::max(block, c->sweep_block);
     lds = std::max(lds, c->sweep_lds);
     lds_stage = std::max(lds_stage, cd_stage_lds(c, c->st_ds.max_particles, c->st_ds.max_contacts));

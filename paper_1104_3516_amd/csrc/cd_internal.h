@@ -121,6 +121,7 @@ struct SweepArgs {
   int cap;                  // slot capacity (SoA stride of geo)
   int grid;                 // blocks of a one-sweep launch
   int block;                // threads per block of a sweep launch
+  unsigned long long* dtick;  // per-domain elapsed real-time ticks of the step, or null
   int per_xcd;              // domains per XCD in the block -> domain map
   int wave_lds;             // LDS staging per wavefront (doubles)
   long long nc;
@@ -308,6 +309,19 @@ struct cd_ctx {
   // the current step, between its phases
   double st_skin = 0.0;
   double st_wall_speed = 0.0;   // largest wall speed of the step (host)
+
+  // adaptive load balancing (Sec. 3.3)
+  double lb_sigma_star = -1.0;          // threshold on sigma_T; < 0: no measurement
+  std::vector<double> lb_capacity;      // capacities of the tree rebuilds (empty: leaf counts)
+  std::vector<double> lb_times;         // last step's per-domain sweep times, microseconds
+  double lb_sigma = 0.0;                // their sigma_T
+  bool lb_have_times = false;
+  int wall_khz = 0;                     // real-time counter frequency
+  unsigned long long* d_dtick = nullptr;   // per-domain ticks (P)
+  unsigned long long* h_dtick = nullptr;   // pinned copies of them and of the domain
+  int* h_domstart = nullptr;               // contact offsets (P + 1)
+  double* d_frac = nullptr;             // left-branch shares of the nodes (2P-1)
+  double* h_frac = nullptr;             // pinned staging of them
   DomainStats st_ds{};
   int st_limit = 0;
   SolveRun run;

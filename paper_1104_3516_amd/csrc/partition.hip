@@ -12,6 +12,9 @@
 // k = floor(n L / (L + R)), and contacts strictly below the cut go left.  A
 // node without contacts is cut in the middle of its region.  This balances
 // by contact number, the balancing the paper calls the most exact (Sec. 5).
+// With per-domain capacities (adaptive load balancing, Sec. 3.3) the left
+// branch's share is nu_L / (nu_L + nu_R) instead, nu summing the capacities
+// of the leaves below: k = floor(n share), at most n - 1.
 //
 // GPU form: the contact positions are sorted once per axis (stable radix
 // sort of order-preserving keys); every node owns one contiguous segment of
@@ -19,6 +22,8 @@
 // element and one binary search, and per list one stable split of every
 // segment (flag, prefix sum, scatter).
 #include "cd_internal.h"
+
+#include <cmath>
 
 namespace {
 
@@ -55,6 +60,7 @@ struct LevelArgs {
   int first, count;
   const int* child;
   const int* leaves;
+  const double* frac;   // left-branch shares (capacities), or null: leaf counts
   const int* perm0;
   const int* perm1;
   const int* perm2;
@@ -90,7 +96,14 @@ __global__ __launch_bounds__(kThreads) void k_level_nodes(LevelArgs a) {
   double cut;
   int nl = 0;
   if (cnt > 0) {
-    long long k = (cnt * ll) / (ll + lr);
+    long long k;
+    if (a.frac) {
+      k = (long long)floor((double)cnt * a.frac[node]);
+      if (k > cnt - 1) k = cnt - 1;
+      if (k < 0) k = 0;
+    } else {
+      k = (cnt * ll) / (ll + lr);
+    }
     cut = coord[perm[s0 + k]];
     // contacts strictly below the cut: first sorted position with coord >= cut
     int lo_i = s0, hi_i = s0 + (int)k;
@@ -184,6 +197,36 @@ __global__ __launch_bounds__(kThreads) void k_descend(const double* xmid, int64_
 
 }  // namespace
 
+// Left-branch shares of the inner nodes from the capacities (Sec. 3.3):
+// nu of a node is its leaf's capacity or the sum of its two branches' nu
+// (nodes are created after their parents, so reverse creation order is
+// bottom-up); capacities that are not positive and finite count as the
+// mean of the valid ones, or 1.
+static void node_shares(const cd_ctx* c, double* share) {
+  const int P = c->P, nodes = 2 * P - 1;
+  const std::vector<double>& cap = c->lb_capacity;
+  double sum = 0.0;
+  int valid = 0;
+  for (int i = 0; i < P; ++i)
+    if (cap[i] > 0.0 && std::isfinite(cap[i])) {
+      sum = sum + cap[i];
+      ++valid;
+    }
+  const double fill = valid > 0 ? sum / (double)valid : 1.0;
+  std::vector<double> nu(nodes);
+  for (int node = nodes - 1; node >= 0; --node) {
+    const int l = c->t_child[2 * node], r = c->t_child[2 * node + 1];
+    if (l < 0) {
+      const double v = cap[c->t_leaf[node]];
+      nu[node] = (v > 0.0 && std::isfinite(v)) ? v : fill;
+      share[node] = 0.0;
+    } else {
+      nu[node] = nu[l] + nu[r];
+      share[node] = nu[l] / nu[node];
+    }
+  }
+}
+
 hipError_t cd_launch_orb(cd_ctx* c) {
   const int64_t nc = c->nc;
   const int nodes = 2 * c->P - 1;
@@ -226,9 +269,29 @@ hipError_t cd_launch_orb(cd_ctx* c) {
   if (nc > 0)
     hipLaunchKernelGGL(k_fill_int, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
                        c->cnode, nc, 0);
+  // capacity shares (adaptive load balancing), staged through pinned memory
+  const double* frac = nullptr;
+  if ((int)c->lb_capacity.size() == c->P) {
+    if (!c->h_frac) {
+      e = hipHostMalloc((void**)&c->h_frac, sizeof(double) * (size_t)nodes);
+      if (e != hipSuccess) return e;
+    }
+    if (!c->d_frac) {
+      e = hipMalloc((void**)&c->d_frac, sizeof(double) * (size_t)nodes);
+      if (e != hipSuccess) return e;
+    }
+    // the previous rebuild's upload has finished (the host synchronises the
+    // stream between the phases of every step)
+    node_shares(c, c->h_frac);
+    e = hipMemcpyAsync(c->d_frac, c->h_frac, sizeof(double) * (size_t)nodes,
+                       hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    frac = c->d_frac;
+  }
   for (size_t lev = 0; lev < c->t_level_first.size(); ++lev) {
     int first = c->t_level_first[lev], count = c->t_level_count[lev];
     LevelArgs a;
+    a.frac = frac;
     a.xmid = c->xmid;
     a.nc = nc;
     a.dim = c->dim;

@@ -232,10 +232,16 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
   auto idle = [&]() {
     if (FOLD && b == 0 && j >= 2 && (threadIdx.x >> 6) == 1) decide_wave(a, j - 1);
   };
-  if (d >= 0)
+  if (d >= 0) {
+    // load measurement (Sec. 3.3): the real-time ticks thread 0 spends on
+    // its domain (its wavefront runs the colours; a folded decision is
+    // taken by another wavefront and not counted), summed over the step
+    const unsigned long long t0 = a.dtick ? __builtin_amdgcn_s_memrealtime() : 0ull;
     sweep_domain<DIM, GLOB, STAGE>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr, idle);
-  else
+    if (a.dtick && threadIdx.x == 0) a.dtick[d] += __builtin_amdgcn_s_memrealtime() - t0;
+  } else {
     idle();
+  }
   BlockPartial p = block_partial(npass, maxd, sumr, red, a.block);
   if (threadIdx.x == 0) a.partial[(int64_t)(j & 1) * a.grid + b] = p;
 }
@@ -498,6 +504,7 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.per_xcd = (c->P + 7) / 8;
   a.grid = 8 * a.per_xcd;
   a.block = c->sweep_block;
+  a.dtick = c->lb_sigma_star >= 0.0 ? c->d_dtick : nullptr;
   a.drow = c->drow;
   a.ddesc = c->ddesc;
   a.nc = c->nc;
@@ -518,6 +525,11 @@ hipError_t cd_launch_solve_init(cd_ctx* c, int limit) {
                        c->init_part);
   hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(256), 0, c->stream, c->init_part, c->nc,
                      c->d_state, limit, c->d_bar);
+  if (c->lb_sigma_star >= 0.0 && c->d_dtick) {
+    hipError_t e = hipMemsetAsync(c->d_dtick, 0, sizeof(unsigned long long) * (size_t)c->P,
+                                  c->stream);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 
