@@ -295,6 +295,33 @@ static int cmp_f64(const void* a, const void* b) {
 }
 
 /* ------------------------------------------------------------------ */
+/* mixed sequential/parallel update (Sec. 2.3)                          */
+/* ------------------------------------------------------------------ */
+
+/* SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014): the finaliser applied to x + golden gamma. */
+static uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* A uniform number in [0, 1) for the pair (i, j): the top 53 bits of
+ * SplitMix64(SplitMix64(SplitMix64(seed) ^ i) ^ j). */
+double cdref_pair_uniform(uint64_t seed, int64_t i, int64_t j) {
+  uint64_t h = splitmix64(splitmix64(splitmix64(seed) ^ (uint64_t)i) ^ (uint64_t)j);
+  return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* The contacts updated in parallel: those whose pair number falls below p. */
+void cdref_parallel_flags(int64_t nc, const int32_t* ci, const int32_t* cj, double p,
+                          uint64_t seed, uint8_t* flags) {
+  for (int64_t c = 0; c < nc; ++c)
+    flags[c] = cdref_pair_uniform(seed, ci[c], cj[c]) < p ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* adaptive load balancing (Sec. 3.3)                                   */
 /* ------------------------------------------------------------------ */
 
@@ -480,7 +507,17 @@ void cdref_descend(int dim, int P, const int32_t* node_axis, const double* node_
 int cdref_order(int64_t n, int64_t nc, const int32_t* ci, const int32_t* cj,
                 int P, const int32_t* dom, int32_t* color, int32_t* slot_contact,
                 int64_t* dom_start) {
+  return cdref_order_mixed(n, nc, ci, cj, P, dom, NULL, color, slot_contact, dom_start);
+}
+
+/* The same with the contacts flagged in `parallel` (NULL: none) updated in
+ * parallel (Sec. 2.3): they take colour 0 and come first in their domain,
+ * and the other contacts are coloured first-fit from colour 1. */
+int cdref_order_mixed(int64_t n, int64_t nc, const int32_t* ci, const int32_t* cj,
+                      int P, const int32_t* dom, const uint8_t* parallel, int32_t* color,
+                      int32_t* slot_contact, int64_t* dom_start) {
   const int words = CDREF_MAX_COLORS / 64;
+  const int first = parallel ? 1 : 0;   /* the first colour of a sequential contact */
   uint64_t* used = (uint64_t*)calloc((size_t)(n > 0 ? n : 1) * words, sizeof(uint64_t));
   int64_t* count = (int64_t*)calloc((size_t)P + 1, sizeof(int64_t));
   int64_t* members_start = (int64_t*)calloc((size_t)P + 1, sizeof(int64_t));
@@ -504,7 +541,12 @@ int cdref_order(int64_t n, int64_t nc, const int32_t* ci, const int32_t* cj,
     for (int64_t s = members_start[d]; s < members_start[d + 1]; ++s) {
       int32_t c = members[s];
       int64_t a = ci[c], b = cj[c];
-      int k = 0;
+      if (parallel && parallel[c]) {
+        color[c] = 0;
+        if (maxcol < 0) maxcol = 0;
+        continue;
+      }
+      int k = first;
       for (; k < CDREF_MAX_COLORS; ++k) {
         uint64_t bit = 1ull << (k % 64);
         int in_a = (used[a * words + k / 64] & bit) != 0;
@@ -717,6 +759,18 @@ int cdref_solve(const cdref_params* p, int64_t n, const double* v, const double*
                 const double* normal, const double* gap, const double* mu_c,
                 int P, const int64_t* dom_start, const int32_t* slot_contact,
                 double* R, cdref_info* info, double* history) {
+  return cdref_solve_mixed(p, n, v, w, r, m, inertia, f, t, wall_velocity, nc, ci, cj, normal,
+                           gap, mu_c, NULL, P, dom_start, slot_contact, R, info, history);
+}
+
+int cdref_solve_mixed(const cdref_params* p, int64_t n, const double* v, const double* w,
+                      const double* r, const double* m, const double* inertia,
+                      const double* f, const double* t, const double* wall_velocity,
+                      int64_t nc, const int32_t* ci, const int32_t* cj,
+                      const double* normal, const double* gap, const double* mu_c,
+                      const uint8_t* parallel, int P, const int64_t* dom_start,
+                      const int32_t* slot_contact, double* R, cdref_info* info,
+                      double* history) {
   int dim = p->dim, dr = dim == 2 ? 1 : 3;
   int64_t nn = n > 0 ? n : 1, ncc = nc > 0 ? nc : 1;
   memset(info, 0, sizeof(*info));
@@ -777,8 +831,14 @@ int cdref_solve(const cdref_params* p, int64_t n, const double* v, const double*
     /* each domain sweeps its native contacts sequentially on a private copy
        of the velocities; other domains' contacts keep their sweep j-1 value */
     for (int d = 0; d < P; ++d) {
+      /* pass 0: the domain's parallel contacts (Sec. 2.3) from the velocities
+         of the exchange, their changes not applied in this sweep (the other
+         contacts see their old forces); pass 1: the sequential update */
+      for (int pass = parallel ? 0 : 1; pass < 2; ++pass)
       for (int64_t s = dom_start[d]; s < dom_start[d + 1]; ++s) {
         int64_t c = slot_contact[s];
+        const int par = parallel ? parallel[c] != 0 : 0;
+        if (par != (pass == 0)) continue;
         int64_t a = ci[c], b = cj[c];
         double nv[3], t1[3], t2[3];
         contact_frame(dim, normal, nc, c, nv, t1, t2);
@@ -799,6 +859,7 @@ int cdref_solve(const cdref_params* p, int64_t n, const double* v, const double*
         double dRn = Rnew[0] - Rold[0], dR1 = Rnew[1] - Rold[1];
         double dR2 = dim == 3 ? Rnew[2] - Rold[2] : 0.0;
         for (int k = 0; k < dim; ++k) R[k * nc + c] = Rnew[k];
+        if (par) continue;
         /* apply the change to both bodies' private velocities */
         double dF[3], dq[3];
         for (int k = 0; k < dim; ++k) {
@@ -873,6 +934,8 @@ struct cdref_sim {
   double* cut;
   int have_tree;
   double* capacity;   /* per-domain capacities for the tree rebuilds, or NULL */
+  double mixed_p;     /* share of contacts updated in parallel (< 0: none) */
+  uint64_t mixed_seed;
   /* contacts of the last step */
   int64_t nc, cap;
   int32_t *ci, *cj, *dom, *color, *slot;
@@ -894,6 +957,7 @@ cdref_sim* cdref_sim_create(const cdref_params* p, int64_t n, const double* x,
   if (p->dim != 2 && p->dim != 3) return NULL;
   if (p->n_domains < 1 || n < 1) return NULL;
   cdref_sim* s = (cdref_sim*)calloc(1, sizeof(cdref_sim));
+  if (s) s->mixed_p = -1.0;
   if (!s) return NULL;
   s->p = *p;
   if (s->p.repartition_every < 1) s->p.repartition_every = 1;
@@ -929,6 +993,11 @@ void cdref_sim_destroy(cdref_sim* s) {
   free(s->normal); free(s->gap); free(s->xmid); free(s->R);
   free(s->capacity);
   free(s);
+}
+
+void cdref_sim_set_mixed(cdref_sim* s, double p, uint64_t seed) {
+  s->mixed_p = p;
+  s->mixed_seed = seed;
 }
 
 int cdref_sim_set_capacity(cdref_sim* s, const double* capacity) {
@@ -1060,10 +1129,19 @@ int cdref_sim_step(cdref_sim* s, cdref_info* info) {
     cdref_descend(dim, P, s->axis, s->cut, s->child, s->leaf, nc, s->xmid, s->dom);
   }
   int64_t* dom_start = (int64_t*)malloc(sizeof(int64_t) * ((size_t)P + 1));
-  st = cdref_order(n, nc, s->ci, s->cj, P, s->dom, s->color, s->slot, dom_start);
-  if (st != CDREF_OK) { free(dom_start); return st; }
-  st = cdref_solve(p, n, s->v, s->w, s->r, s->m, s->I, s->f, s->t, s->wu, nc, s->ci, s->cj,
-                   s->normal, s->gap, NULL, P, dom_start, s->slot, s->R, info, NULL);
+  /* mixed update (Sec. 2.3): the contacts whose pair draw falls below p */
+  uint8_t* par = NULL;
+  if (s->mixed_p >= 0.0) {
+    par = (uint8_t*)malloc((size_t)(nc > 0 ? nc : 1));
+    if (!par) { free(dom_start); return CDREF_ENOMEM; }
+    cdref_parallel_flags(nc, s->ci, s->cj, s->mixed_p, s->mixed_seed, par);
+  }
+  st = cdref_order_mixed(n, nc, s->ci, s->cj, P, s->dom, par, s->color, s->slot, dom_start);
+  if (st != CDREF_OK) { free(dom_start); free(par); return st; }
+  st = cdref_solve_mixed(p, n, s->v, s->w, s->r, s->m, s->I, s->f, s->t, s->wu, nc, s->ci,
+                         s->cj, s->normal, s->gap, NULL, par, P, dom_start, s->slot, s->R, info,
+                         NULL);
+  free(par);
   info->skin = skin;
   info->n_contacts = nc;
   free(dom_start);

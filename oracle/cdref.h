@@ -116,6 +116,29 @@ int cdref_orb_capacity(int dim, int P, const double* box_lo, const double* box_h
  * mean of the valid ones (1 if none). */
 int cdref_balance_fractions(int P, const double* capacity, double* node_frac);
 
+/* Mixed sequential/parallel update (Sec. 2.3).  The pair number
+ * u(seed, i, j) in [0, 1): top 53 bits of SplitMix64(SplitMix64(SplitMix64(seed)
+ * ^ i) ^ j); a contact is updated in parallel when u < p. */
+double cdref_pair_uniform(uint64_t seed, int64_t i, int64_t j);
+void cdref_parallel_flags(int64_t nc, const int32_t* ci, const int32_t* cj, double p,
+                          uint64_t seed, uint8_t* flags);
+/* order with parallel contacts (flags, or NULL): they take colour 0 and come
+ * first in their domain; the others are coloured first-fit from colour 1 */
+int cdref_order_mixed(int64_t n, int64_t nc, const int32_t* ci, const int32_t* cj,
+                      int P, const int32_t* dom, const uint8_t* parallel, int32_t* color,
+                      int32_t* slot_contact, int64_t* dom_start);
+/* solve in which each domain first computes its parallel contacts from the
+ * velocities of the exchange without applying their changes, then updates
+ * the others sequentially */
+int cdref_solve_mixed(const cdref_params* p, int64_t n, const double* v, const double* w,
+                      const double* r, const double* m, const double* inertia,
+                      const double* f, const double* t, const double* wall_velocity,
+                      int64_t nc, const int32_t* ci, const int32_t* cj,
+                      const double* normal, const double* gap, const double* mu_c,
+                      const uint8_t* parallel, int P, const int64_t* dom_start,
+                      const int32_t* slot_contact, double* R, cdref_info* info,
+                      double* history);
+
 /* Load imbalance sigma_T = sqrt(<T^2> - <T>^2) / <T> over P times (Sec. 3.3). */
 double cdref_sigma_t(int P, const double* T);
 
@@ -181,6 +204,8 @@ void cdref_sim_state(const cdref_sim* s, double* x, double* v, double* w, double
 int64_t cdref_sim_contacts(const cdref_sim* s, int64_t cap, int32_t* ci, int32_t* cj,
                            double* normal, double* gap, double* R, int32_t* dom,
                            int32_t* color, int32_t* slot_contact);
+/* mixed update from now on: contacts with pair number below p (p < 0: none) */
+void cdref_sim_set_mixed(cdref_sim* s, double p, uint64_t seed);
 /* capacities (P doubles, domain order) used by every later tree rebuild;
  * NULL: back to leaf counts */
 int cdref_sim_set_capacity(cdref_sim* s, const double* capacity);

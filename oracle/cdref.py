@@ -65,6 +65,15 @@ def lib():
         L.cdref_sigma_t.argtypes = [C.c_int, P]
         L.cdref_sigma_t.restype = C.c_double
         L.cdref_sim_set_capacity.argtypes = [P, P]
+        L.cdref_pair_uniform.argtypes = [C.c_uint64, i64, i64]
+        L.cdref_pair_uniform.restype = C.c_double
+        L.cdref_parallel_flags.argtypes = [i64, P, P, C.c_double, C.c_uint64, P]
+        L.cdref_parallel_flags.restype = None
+        L.cdref_order_mixed.argtypes = [i64, i64, P, P, C.c_int, P, P, P, P, P]
+        L.cdref_solve_mixed.argtypes = [C.POINTER(Params), i64, P, P, P, P, P, P, P, P, i64, P,
+                                        P, P, P, P, P, C.c_int, P, P, P, C.POINTER(Info), P]
+        L.cdref_sim_set_mixed.argtypes = [P, C.c_double, C.c_uint64]
+        L.cdref_sim_set_mixed.restype = None
         L.cdref_descend.argtypes = [C.c_int, C.c_int, P, P, P, P, i64, P, P]
         L.cdref_descend.restype = None
         L.cdref_tree_leaves.argtypes = [C.c_int, P]
@@ -205,21 +214,38 @@ def tree_leaves(P: int) -> np.ndarray:
     return out
 
 
-def order(n: int, ci, cj, P: int, dom):
+def _u8(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def pair_uniform(seed: int, i: int, j: int) -> float:
+    return float(lib().cdref_pair_uniform(seed, i, j))
+
+
+def parallel_flags(ci, cj, p: float, seed: int) -> np.ndarray:
+    """Contacts updated in parallel in the mixed scheme (Sec. 2.3)."""
+    nc = len(ci)
+    out = np.zeros(max(nc, 1), np.uint8)
+    lib().cdref_parallel_flags(nc, _p(_i32(ci)), _p(_i32(cj)), p, seed, _p(out))
+    return out[:nc]
+
+
+def order(n: int, ci, cj, P: int, dom, parallel=None):
     L = lib()
     nc = len(ci)
     color = np.zeros(max(nc, 1), np.int32)
     slot = np.zeros(max(nc, 1), np.int32)
     dom_start = np.zeros(P + 1, np.int64)
-    st = L.cdref_order(n, nc, _p(_i32(ci)), _p(_i32(cj)), P, _p(_i32(dom)), _p(color), _p(slot),
-                       _p(dom_start))
+    par = None if parallel is None else _u8(parallel)
+    st = L.cdref_order_mixed(n, nc, _p(_i32(ci)), _p(_i32(cj)), P, _p(_i32(dom)), _p(par),
+                             _p(color), _p(slot), _p(dom_start))
     if st != OK:
         raise RuntimeError(f"cdref_order failed: {st}")
     return color[:nc], slot[:nc], dom_start
 
 
 def solve(params: Params, pk, ci, cj, normal, gap, P: int, dom_start, slot, R0=None,
-          mu_c=None, history: bool = False):
+          mu_c=None, history: bool = False, parallel=None):
     """One force solve.  Returns (R, info, history-or-None)."""
     L = lib()
     nc = len(ci)
@@ -228,13 +254,14 @@ def solve(params: Params, pk, ci, cj, normal, gap, P: int, dom_start, slot, R0=N
     info = Info()
     limit = params.fixed_iters if params.fixed_iters > 0 else params.max_iter
     hist = np.zeros((4, limit)) if history else None
-    st = L.cdref_solve(C.byref(params), pk.n, _p(_f64(pk.v)), _p(_f64(pk.w)), _p(_f64(pk.r)),
-                       _p(_f64(pk.m)), _p(_f64(pk.inertia)), _p(_f64(pk.f)), _p(_f64(pk.t)),
-                       _p(_f64(pk.wall_velocity)), nc, _p(_i32(ci)), _p(_i32(cj)),
-                       _p(_f64(normal)), _p(_f64(gap)),
-                       None if mu_c is None else _p(_f64(mu_c)), P,
-                       _p(np.ascontiguousarray(dom_start, np.int64)), _p(_i32(slot)), _p(R),
-                       C.byref(info), _p(hist))
+    par = None if parallel is None else _u8(parallel)
+    st = L.cdref_solve_mixed(C.byref(params), pk.n, _p(_f64(pk.v)), _p(_f64(pk.w)),
+                             _p(_f64(pk.r)), _p(_f64(pk.m)), _p(_f64(pk.inertia)),
+                             _p(_f64(pk.f)), _p(_f64(pk.t)), _p(_f64(pk.wall_velocity)), nc,
+                             _p(_i32(ci)), _p(_i32(cj)), _p(_f64(normal)), _p(_f64(gap)),
+                             None if mu_c is None else _p(_f64(mu_c)), _p(par), P,
+                             _p(np.ascontiguousarray(dom_start, np.int64)), _p(_i32(slot)),
+                             _p(R), C.byref(info), _p(hist))
     if st < 0:
         raise RuntimeError(f"cdref_solve failed: {st}")
     if hist is not None:
@@ -327,6 +354,11 @@ class Sim:
                                   _p(dom), _p(color), _p(slot))
         return dict(ci=ci[:nc], cj=cj[:nc], normal=normal[:, :nc], gap=gap[:nc], R=R[:, :nc],
                     dom=dom[:nc], color=color[:nc], slot=slot[:nc])
+
+    def set_mixed(self, p: float, seed: int = 0):
+        """Mixed update from now on (Sec. 2.3): contacts with pair number
+        below p are updated in parallel; p < 0 switches it off."""
+        self.L.cdref_sim_set_mixed(self.h, float(p), int(seed))
 
     def set_capacity(self, capacity=None):
         """Per-domain capacities for every later tree rebuild (None: leaf counts)."""
