@@ -122,6 +122,45 @@ def boundary_fraction(n, c):
     return float(shared_c.mean())
 
 
+def mixed_experiment(torch, binding, inputs, cap=3000, settle=50, seed=2023):
+    """The mixed-update experiment of Sec. 2.3: a packing of 128 x 128 disks
+    settled for `settle` steps, then one step solved from zero forces on that
+    geometry with a single domain and a share p of the contacts (by pair
+    number) updated in parallel; the sweeps to convergence N_I(p), and p_c,
+    the smallest p that does not converge within `cap` sweeps."""
+    wl = dict(WORKLOADS["disks_262k"], domains=64)
+    pk = inputs.lattice_2d(128, 128, 1005)
+    ctx = make_ctx(wl, pk, binding, timing=0)
+    for s in range(settle):
+        ctx.step()
+    q = pk.copy()
+    x, v, w = (t.cpu().numpy() for t in ctx.state())
+    q.x, q.v, q.w = x, v, w
+    q.wall_offset = ctx.wall_offsets()
+    nc = ctx.num_contacts()
+    ctx.close()
+    rows = []
+    for p in (0.0, 0.01, 0.02, 0.03, 0.04, 0.05, 0.07, 0.1, 0.2, 0.5, 1.0):
+        c = make_ctx(wl, q, binding, timing=0, n_domains=1, max_iter=cap)
+        c.set_mixed_update(p, seed)
+        t0 = time.perf_counter()
+        try:
+            r = c.step()
+            status, sweeps = int(r.status), int(r.iterations)
+        except binding.CDError as err:
+            status, sweeps = int(err.code), None
+        torch.cuda.synchronize()
+        rows.append({"p": p, "sweeps": sweeps, "status": status,
+                     "converged": status == 0, "seconds": time.perf_counter() - t0})
+        log(f"mixed update p={p:.2f}: {sweeps} sweeps, status {status}")
+        c.close()
+    failing = [row["p"] for row in rows if not row["converged"]]
+    return {"packing": f"128x128 disks settled for {settle} steps, {nc} contacts, mu=0.3",
+            "procedure": "one step from zero forces, one domain, alpha=1e-6, at most "
+                         f"{cap} sweeps; parallel contacts by pair number (seed {seed})",
+            "rows": rows, "p_c": min(failing) if failing else None}
+
+
 def sequential_comparison(wl, pk, ctx, torch, binding, max_iter):
     """One time step solved from scratch (cold start) on the state the timed
     steps ended in, with the workload's domains and with a single domain
@@ -383,6 +422,8 @@ def main() -> int:
     ap.add_argument("--balance", type=float, default=-1.0, metavar="SIGMA",
                     help="adaptive load balancing (Sec. 3.3) with this threshold on sigma_T "
                          "(negative: off, the headline configuration)")
+    ap.add_argument("--mixed-experiment", action="store_true",
+                    help="also run the mixed-update experiment of Sec. 2.3 (N_I(p), p_c)")
     ap.add_argument("--sequential", type=int, default=1,
                     help="after the timed steps, solve one step from scratch with the "
                          "workload's domains and with one domain (2D workloads)")
@@ -573,6 +614,8 @@ def main() -> int:
             "sigma_t_mean": sum(sigmas) / len(sigmas) if sigmas else None,
             "note": "per-domain sweep times measured in the timed steps; capacities n_i / T_i "
                     "place the cuts of every later rebuild (Sec. 3.3)"}
+    if args.mixed_experiment:
+        out["mixed_parallelness"] = mixed_experiment(torch, binding, inputs)
     if args.sequential and dim == 2:
         out["sequential_comparison"] = sequential_comparison(wl, pk, ctx, torch, binding,
                                                              args.sequential_max_iter)

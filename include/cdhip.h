@@ -187,6 +187,18 @@ int cd_set_solve_mode(cd_ctx* ctx, int mode);
  * with every > 0). */
 int cd_set_launch(cd_ctx* ctx, int block_threads);
 
+/* Mixed sequential/parallel update (Sec. 2.3) from the next step on: the
+ * contacts whose pair number u(seed, i, j) in [0, 1) - the top 53 bits of
+ * SplitMix64(SplitMix64(SplitMix64(seed) ^ i) ^ j) - falls below p are
+ * updated in parallel: each takes its new force from the velocities at the
+ * start of the sweep (all other forces at their previous values) and its
+ * change reaches the other contacts only through the next exchange; the
+ * rest are updated sequentially as before.  Such contacts form colour 0 of
+ * their domain (cd_get_contacts), the sequential ones colour from 1.  p >= 1
+ * updates every contact in parallel (the Jacobi scheme); p < 0 (default)
+ * none.  CD_EINVAL for p = NaN or together with the adjoint. */
+int cd_set_mixed_update(cd_ctx* ctx, double p, unsigned long long seed);
+
 /* Adaptive load balancing (Sec. 3.3).  sigma_star >= 0 switches load
  * measurement on: every sweep launch records, per domain, the real time its
  * workgroup spends on it (per-sweep launches only: solve modes 1-3, not the

@@ -103,6 +103,7 @@ def lib():
         L.cd_solve.argtypes = [P, C.POINTER(Result)]
         L.cd_set_adjoint.argtypes = [P, C.c_int]
         L.cd_set_frozen_list.argtypes = [P, C.c_int]
+        L.cd_set_mixed_update.argtypes = [P, C.c_double, C.c_ulonglong]
         L.cd_set_load_balance.argtypes = [P, C.c_double]
         L.cd_set_domain_capacity.argtypes = [P, P]
         L.cd_get_domain_times.argtypes = [P, P, P]
@@ -295,6 +296,11 @@ class Context:
         """Keep the next step's contact list, tree and colouring for the
         steps after it (geometry recomputed each step)."""
         self._check(self.L.cd_set_frozen_list(self.h, int(bool(on))))
+
+    def set_mixed_update(self, p: float, seed: int = 0):
+        """Mixed sequential/parallel update (Sec. 2.3): contacts with pair
+        number below p are updated in parallel; p < 0 switches it off."""
+        self._check(self.L.cd_set_mixed_update(self.h, float(p), int(seed)))
 
     def set_load_balance(self, sigma_star: float):
         """Adaptive load balancing (Sec. 3.3) with threshold sigma_star on

@@ -448,6 +448,7 @@ int cd_destroy(cd_ctx* c) {
   cd_window_clear(c);
   release(&c->d_vmax);
   release(&c->d_dtick);
+  release(&c->par);
   release(&c->d_frac);
   if (c->h_dtick) (void)hipHostFree(c->h_dtick);
   if (c->h_domstart) (void)hipHostFree(c->h_domstart);
@@ -848,6 +849,8 @@ int solve_single(cd_ctx* c) {
   int groups_closed = 0;
   c->sweep_stage = false;   // the one-launch solve never stages
   c->sweep_fold = false;
+  if (c->persistent && c->order_mixed)
+    return fail(c, CD_EINVAL, "the one-launch solve has no mixed update (solve modes 1-3 do)");
   const int G = c->persistent ? cd_solve_grid(c) : 0;
   if (G < 8) cd_sweep_mode(c);
   if (G >= 8 && nc > 0 && limit > 0) {
@@ -1083,8 +1086,19 @@ int cd_solve(cd_ctx* c, cd_result* out) {
   return step_finish(c, out);
 }
 
+int cd_set_mixed_update(cd_ctx* c, double p, unsigned long long seed) {
+  if (!c || std::isnan(p)) return CD_EINVAL;
+  if (p >= 0.0 && c->adj_every > 0)
+    return fail(c, CD_EINVAL, "the adjoint differentiates the sequential update only");
+  c->mixed_p = p >= 0.0 ? p : -1.0;
+  c->mixed_seed = seed;
+  return CD_OK;
+}
+
 int cd_set_adjoint(cd_ctx* c, int checkpoint_every) {
   if (!c || checkpoint_every < 0) return CD_EINVAL;
+  if (checkpoint_every > 0 && c->mixed_p >= 0.0)
+    return fail(c, CD_EINVAL, "the adjoint differentiates the sequential update only");
   c->adj_every = checkpoint_every;
   cd_window_clear(c);
   c->adj_valid = false;

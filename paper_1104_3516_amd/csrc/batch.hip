@@ -264,6 +264,9 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
     if (!b->failed[p] && c->sweep_global)
       return bfail(b, CD_ECAPACITY,
                    "packing " + std::to_string(p) + ": a domain does not fit in LDS");
+    if (!b->failed[p] && c->order_mixed)
+      return bfail(b, CD_EINVAL,
+                   "packing " + std::to_string(p) + ": batched sweeps have no mixed update");
     b->h_tab[p] = cd_sweep_args(c);
     b->h_tab[p].dtick = nullptr;   // batched sweeps do not measure the load
     block = std::max(block, c->sweep_block);

@@ -310,6 +310,13 @@ struct cd_ctx {
   double st_skin = 0.0;
   double st_wall_speed = 0.0;   // largest wall speed of the step (host)
 
+  // mixed sequential/parallel update (Sec. 2.3)
+  double mixed_p = -1.0;                // share of contacts updated in parallel; < 0: none
+  unsigned long long mixed_seed = 0;
+  unsigned char* par = nullptr;         // per contact: updated in parallel
+  int64_t par_cap = 0;
+  bool order_mixed = false;             // the current order has a parallel colour 0
+
   // adaptive load balancing (Sec. 3.3)
   double lb_sigma_star = -1.0;          // threshold on sigma_T; < 0: no measurement
   std::vector<double> lb_capacity;      // capacities of the tree rebuilds (empty: leaf counts)

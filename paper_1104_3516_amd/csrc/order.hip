@@ -173,6 +173,7 @@ struct BuildArgs {
   int* dncol;
   int* ddesc;             // per domain: cs, nct, ps, np, ncol, 0, 0, 0
   DomainStats* stats;
+  const unsigned char* par;   // contacts updated in parallel (canonical order), or null
 };
 
 // Greedy first-fit colouring of a domain's contacts in canonical order
@@ -180,12 +181,21 @@ struct BuildArgs {
 // contacts of the same colour, so that the stable order by colour is
 // pos[k] = offset[col[k]] + rank[k].  Returns the colour count, or -1 when a
 // contact finds all CD_MAX_COLORS colours taken.  MASK/LA/LB/COL/RANK are
-// LDS arrays in the small path and global scratch in the large one.
-template <typename M, typename I, typename C>
+// LDS arrays in the small path and global scratch in the large one.  In
+// the mixed update (Sec. 2.3) a contact with par(k) takes colour 0 and the
+// masks start with colour 0 taken, so that the others colour from 1.
+template <typename M, typename I, typename C, typename Par>
 __device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb_s, C* col_s,
-                                    C* rank_s, int* cnt) {
+                                    C* rank_s, int* cnt, Par&& par) {
   int ncol = 0;
   for (int k = 0; k < nct; ++k) {
+    if (par(k)) {
+      col_s[k] = (C)0;
+      rank_s[k] = (C)cnt[0];
+      cnt[0] += 1;
+      if (ncol < 1) ncol = 1;
+      continue;
+    }
     const int la = la_s[k], lb = lb_s[k];
     const unsigned long long used = mask[la] | (lb >= 0 ? mask[lb] : 0ull);
     if (used == ~0ull) return -1;
@@ -205,7 +215,8 @@ __device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb
 // of colour q in a register, and each step costs one round trip to LDS
 // (the next contact's bodies are read one step ahead).
 __device__ inline int colour_wave(int nct, unsigned long long* mask, const int* la_s,
-                                  const int* lb_s, short* col_s, short* rank_s, int* cnt_out) {
+                                  const int* lb_s, short* col_s, short* rank_s, int* cnt_out,
+                                  const unsigned char* par) {
   static_assert(CD_MAX_COLORS == 64, "one lane per colour");
   const int lane = threadIdx.x & 63;
   int cnt = 0;   // contacts of colour `lane` so far
@@ -214,6 +225,19 @@ __device__ inline int colour_wave(int nct, unsigned long long* mask, const int* 
   for (int k = 0; k < nct; ++k) {
     const int la_n = k + 1 < nct ? la_s[k + 1] : 0;
     const int lb_n = k + 1 < nct ? lb_s[k + 1] : -1;
+    if (par && par[k]) {
+      // updated in parallel: colour 0, no mask (the same for every lane)
+      const int rank = __builtin_amdgcn_readlane(cnt, 0);
+      if (lane == 0) {
+        ++cnt;
+        col_s[k] = 0;
+        rank_s[k] = (short)rank;
+      }
+      if (ncol < 1) ncol = 1;
+      la = la_n;
+      lb = lb_n;
+      continue;
+    }
     const unsigned long long ma = mask[la], mb = lb >= 0 ? mask[lb] : 0ull;
     const unsigned long long used = ma | mb;
     if (used == ~0ull) return -1;
@@ -232,6 +256,28 @@ __device__ inline int colour_wave(int nct, unsigned long long* mask, const int* 
   }
   cnt_out[lane] = cnt;
   return ncol;
+}
+
+// Contacts updated in parallel in the mixed update (Sec. 2.3): those whose
+// pair number u = top 53 bits of SplitMix64(SplitMix64(SplitMix64(seed) ^ i)
+// ^ j) (Steele, Lea and Flood 2014) falls below p.
+__device__ inline unsigned long long splitmix64(unsigned long long x) {
+  unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kThreads) void k_par_flags(const int* ci, const int* cj, int64_t nc,
+                                                       double p, unsigned long long seed,
+                                                       unsigned char* par) {
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= nc) return;
+  const unsigned long long h =
+      splitmix64(splitmix64(splitmix64(seed) ^ (unsigned long long)(long long)ci[c]) ^
+                 (unsigned long long)(long long)cj[c]);
+  const double u = (double)(h >> 11) * (1.0 / 9007199254740992.0);
+  par[c] = u < p ? 1 : 0;
 }
 
 // Largest colour count, contacts, particle entries and LDS staging over
@@ -281,6 +327,7 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   __shared__ unsigned long long s_mask[kSmall];
   __shared__ int s_la[kSmall], s_lb[kSmall];
   __shared__ short s_col[kSmall], s_rank[kSmall];
+  __shared__ unsigned char s_par[kSmall];
   __shared__ int s_cnt[CD_MAX_COLORS];
   __shared__ int s_coloff[CD_MAX_COLORS + 1];
   __shared__ int s_ncol;
@@ -295,23 +342,30 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   }
   const bool small = nct <= kSmall && np <= kSmall;
   for (int q = threadIdx.x; q < CD_MAX_COLORS; q += blockDim.x) s_cnt[q] = 0;
+  // mixed update: colour 0 is reserved for the contacts updated in parallel
+  const unsigned long long mask0 = a.par ? 1ull : 0ull;
   if (small) {
-    for (int k = threadIdx.x; k < np; k += blockDim.x) s_mask[k] = 0ull;
+    for (int k = threadIdx.x; k < np; k += blockDim.x) s_mask[k] = mask0;
     for (int k = threadIdx.x; k < nct; k += blockDim.x) {
       s_la[k] = a.qla[cs + k];
       s_lb[k] = a.qlb[cs + k];
+      s_par[k] = a.par ? a.par[a.bucket[cs + k]] : 0;
     }
   } else {
-    for (int k = threadIdx.x; k < np; k += blockDim.x) a.gmask[ps + k] = 0ull;
+    for (int k = threadIdx.x; k < np; k += blockDim.x) a.gmask[ps + k] = mask0;
   }
   __syncthreads();
   int ncol_w = 0;
-  if (small) ncol_w = colour_wave(nct, s_mask, s_la, s_lb, s_col, s_rank, s_cnt);
+  if (small) ncol_w = colour_wave(nct, s_mask, s_la, s_lb, s_col, s_rank, s_cnt,
+                                  a.par ? s_par : nullptr);
   __syncthreads();
   if (threadIdx.x == 0) {
+    const unsigned char* par = a.par;
+    const int* bk = a.bucket + cs;
+    auto is_par = [&](int k) { return par != nullptr && par[bk[k]] != 0; };
     const int ncol = small ? ncol_w
                            : colour_serial(nct, a.gmask + ps, a.qla + cs, a.qlb + cs,
-                                           a.qcol + cs, a.qpos + cs, s_cnt);
+                                           a.qcol + cs, a.qpos + cs, s_cnt, is_par);
     s_coloff[0] = 0;
     for (int q = 0; q < ncol; ++q) s_coloff[q + 1] = s_coloff[q] + s_cnt[q];
     s_ncol = ncol;
@@ -336,8 +390,8 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     dd[2] = ps;
     dd[3] = np;
     dd[4] = ncol;
-    int widest = 0;   // the largest colour
-    for (int q = 0; q < ncol; ++q) widest = max(widest, s_coloff[q + 1] - s_coloff[q]);
+    int widest = 0;   // the largest colour (of the sequential ones in the mixed update)
+    for (int q = a.par ? 1 : 0; q < ncol; ++q) widest = max(widest, s_coloff[q + 1] - s_coloff[q]);
     dd[5] = widest;
     dd[6] = dd[7] = 0;
     a.dncol[d] = ncol;
@@ -609,7 +663,25 @@ hipError_t cd_launch_order(cd_ctx* c) {
                        c->bucket, c->dom, c->ci, c->cj, nc, n, c->dp, c->dp_start, c->q_la,
                        c->q_lb);
   // 4. colouring and slots
+  // mixed update (Sec. 2.3): the contacts updated in parallel
+  const unsigned char* par = nullptr;
+  if (c->mixed_p >= 0.0) {
+    if (c->par_cap < nc || !c->par) {
+      if (c->par) (void)hipFree(c->par);
+      c->par = nullptr;
+      c->par_cap = 0;
+      e = hipMalloc((void**)&c->par, (size_t)(c->cap > nc ? c->cap : nc) + 1);
+      if (e != hipSuccess) return e;
+      c->par_cap = c->cap > nc ? c->cap : nc;
+    }
+    if (nc > 0)
+      hipLaunchKernelGGL(k_par_flags, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0,
+                         c->stream, c->ci, c->cj, nc, c->mixed_p, c->mixed_seed, c->par);
+    par = c->par;
+  }
+  c->order_mixed = par != nullptr;
   BuildArgs a;
+  a.par = par;
   a.dom_start = c->dom_start;
   a.bucket = c->bucket;
   a.dp_start = c->dp_start;

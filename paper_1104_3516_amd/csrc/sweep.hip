@@ -205,7 +205,9 @@ __device__ inline void decide_wave(const SweepArgs& a, int jd) {
 // decision workgroup; the second wavefront of workgroup 0 takes the decision
 // while the first updates the colours (or after them when a colour is wider
 // than a wavefront), so that a launch has one workgroup per domain.
-template <int DIM, bool GLOB, bool STAGE, bool FOLD>
+// TIMED: per-domain load measurement when a.dtick is set (single contexts;
+// batched sweeps never measure).
+template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = true>
 __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArgs& a, int b, int j,
                                                                   BatchProg* bp) {
   extern __shared__ double lds[];
@@ -236,9 +238,11 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
     // load measurement (Sec. 3.3): the real-time ticks thread 0 spends on
     // its domain (its wavefront runs the colours; a folded decision is
     // taken by another wavefront and not counted), summed over the step
-    const unsigned long long t0 = a.dtick ? __builtin_amdgcn_s_memrealtime() : 0ull;
-    sweep_domain<DIM, GLOB, STAGE>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr, idle);
-    if (a.dtick && threadIdx.x == 0) a.dtick[d] += __builtin_amdgcn_s_memrealtime() - t0;
+    const bool timed = TIMED && a.dtick != nullptr;
+    const unsigned long long t0 = timed ? __builtin_amdgcn_s_memrealtime() : 0ull;
+    sweep_domain<DIM, GLOB, STAGE, MIXED>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr,
+                                          idle);
+    if (timed && threadIdx.x == 0) a.dtick[d] += __builtin_amdgcn_s_memrealtime() - t0;
   } else {
     idle();
   }
@@ -250,9 +254,11 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
 // The staged 2D form keeps to 96 VGPRs (five wavefronts per SIMD) so that a
 // launch of 2,048 two-wavefront domain workgroups plus the decision
 // workgroup is resident at once on 256 CUs.
-template <int DIM, bool GLOB, bool STAGE, bool FOLD>
+// MIXED: colour 0 of every domain holds its contacts updated in parallel
+// (Sec. 2.3), a separate instantiation so that the plain sweep is unchanged.
+template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false>
 __global__ __launch_bounds__(kMaxBlock, STAGE && DIM == 2 ? 5 : 1) void k_sweep(SweepArgs a, int j) {
-  sweep_block<DIM, GLOB, STAGE, FOLD>(a, blockIdx.x, j, nullptr);
+  sweep_block<DIM, GLOB, STAGE, FOLD, MIXED>(a, blockIdx.x, j, nullptr);
 }
 
 // Sweep j of a batch of packings: workgroup b serves packing blk[2b] as its
@@ -263,7 +269,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep_batch(const SweepArgs* tab,
   const int2 pb = ((const int2*)blk)[blockIdx.x];
   // read in place: a local copy of the arguments would live in scratch
   const SweepArgs& a = tab[pb.x];
-  sweep_block<DIM, false, STAGE, false>(a, pb.y, j, bp);
+  sweep_block<DIM, false, STAGE, false, false, false>(a, pb.y, j, bp);
 }
 
 // stop decision of sweep jd alone (after the last launched sweep)
@@ -604,6 +610,23 @@ void cd_sweep_mode(cd_ctx* c) {
   }
 }
 
+// One sweep launch in the context's form (global records, staged with the
+// decision folded into workgroup 0, staged, register read-ahead).
+template <int DIM, bool MIXED>
+static void launch_sweep_form(cd_ctx* c, const SweepArgs& a, dim3 grid, dim3 block, size_t lds,
+                              bool fold, int j) {
+  if (c->sweep_global)
+    hipLaunchKernelGGL((k_sweep<DIM, true, false, false, MIXED>), grid, block, 0, c->stream, a, j);
+  else if (fold)
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED>), grid, block, lds, c->stream, a, j);
+  else if (c->sweep_stage)
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED>), grid, block, lds, c->stream, a,
+                       j);
+  else
+    hipLaunchKernelGGL((k_sweep<DIM, false, false, false, MIXED>), grid, block, lds, c->stream, a,
+                       j);
+}
+
 hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after) {
   SweepArgs a = cd_sweep_args(c);
   if (before) {
@@ -616,23 +639,11 @@ hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after
   dim3 grid(a.grid + (fold ? 0 : 1)), block(c->sweep_block);
   const size_t lds = block_lds(c);
   if (c->dim == 2) {
-    if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<2, true, false, false>), grid, block, 0, c->stream, a, j);
-    else if (fold)
-      hipLaunchKernelGGL((k_sweep<2, false, true, true>), grid, block, lds, c->stream, a, j);
-    else if (c->sweep_stage)
-      hipLaunchKernelGGL((k_sweep<2, false, true, false>), grid, block, lds, c->stream, a, j);
-    else
-      hipLaunchKernelGGL((k_sweep<2, false, false, false>), grid, block, lds, c->stream, a, j);
+    if (c->order_mixed) launch_sweep_form<2, true>(c, a, grid, block, lds, fold, j);
+    else launch_sweep_form<2, false>(c, a, grid, block, lds, fold, j);
   } else {
-    if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<3, true, false, false>), grid, block, 0, c->stream, a, j);
-    else if (fold)
-      hipLaunchKernelGGL((k_sweep<3, false, true, true>), grid, block, lds, c->stream, a, j);
-    else if (c->sweep_stage)
-      hipLaunchKernelGGL((k_sweep<3, false, true, false>), grid, block, lds, c->stream, a, j);
-    else
-      hipLaunchKernelGGL((k_sweep<3, false, false, false>), grid, block, lds, c->stream, a, j);
+    if (c->order_mixed) launch_sweep_form<3, true>(c, a, grid, block, lds, fold, j);
+    else launch_sweep_form<3, false>(c, a, grid, block, lds, fold, j);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !after) return e;

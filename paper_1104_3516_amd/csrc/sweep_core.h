@@ -302,8 +302,10 @@ __device__ inline void account(const double* Rold, const double* Rn, double alph
 // The force law for one contact with the current velocities of its bodies
 // (staged particle records at sp; body 2 < 0 is wall -1-b with velocity
 // wu), the change applied to both bodies, the new record written to `ro`,
-// and the contact's test values accounted.
-template <int DIM>
+// and the contact's test values accounted.  APPLY = false (a contact
+// updated in parallel, Sec. 2.3): the change is not applied to the bodies,
+// which see it only through the next exchange.
+template <int DIM, bool APPLY = true>
 __device__ inline void update_contact(double* sp, const double* wu, const SlotPre<DIM>& c,
                                       double alpha, double* ro, long long& npass,
                                       double& maxd, double& sumr) {
@@ -350,8 +352,8 @@ __device__ inline void update_contact(double* sp, const double* wu, const SlotPr
   double Va[3], Wa[3];
   for (int q = 0; q < DIM; ++q) Va[q] = A.V[q] - A.dm * dF[q];
   for (int q = 0; q < DR; ++q) Wa[q] = A.W[q] - A.di * (A.r * dq[q]);
-  write_velocities<DIM>(sp, la, Va, Wa);
-  if (lb >= 0) {
+  if (APPLY) write_velocities<DIM>(sp, la, Va, Wa);
+  if (APPLY && lb >= 0) {
     double Vb[3], Wb[3];
     for (int q = 0; q < DIM; ++q) Vb[q] = B.V[q] + B.dm * dF[q];
     for (int q = 0; q < DR; ++q) Wb[q] = B.W[q] - B.di * (B.r * dq[q]);
@@ -598,7 +600,7 @@ __device__ inline void get_slot(const double* sl, int nct, int k, double mu0, bo
 // alongside the exchange (all its loads in flight at once) and the colours
 // read it from there; otherwise each thread reads its contact of the next
 // colour into registers one colour ahead.
-template <int DIM, bool GLOB, bool STAGE, class Idle>
+template <int DIM, bool GLOB, bool STAGE, bool MIXED = false, class Idle>
 __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead& h,
                                     const double* rin, double* rout, double* lds, int* s_co,
                                     double* s_wu, long long& npass, double& maxd, double& sumr,
@@ -608,6 +610,9 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
   constexpr int REC = L::REC, PS = L::PS;
   const int tid = threadIdx.x, nthr = a.block;
   const int cs = h.cs, nct = h.nct, ps = h.ps, np = h.np, ncol = h.ncol;
+  // mixed update (Sec. 2.3): colour 0 holds the contacts updated in parallel
+  // and the sequential colours start at c0
+  const int c0 = MIXED ? 1 : 0;
   double* sp = GLOB ? a.gscr + (int64_t)PS * ps : lds;
   const int* dcol = a.dcol + (int64_t)d * (CD_MAX_COLORS + 1);
   // 0. colour offsets and wall velocities to LDS
@@ -660,10 +665,12 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
       else entry_finish_staged<DIM>(a, rin, ps + l, ep, sp, l, sl, cs, nct);
     }
   } else {
-    if (ncol > 0) {
-      // this thread's contact of the first colour read ahead (its latency
-      // overlaps the exchange); lanes without one read the first slot
-      kc = tid < dcol[1] ? tid : -1;
+    if (ncol > c0) {
+      // this thread's contact of the first sequential colour read ahead
+      // (its latency overlaps the exchange); lanes without one read the
+      // first slot
+      const int b0 = dcol[c0];
+      kc = b0 + tid < dcol[c0 + 1] ? b0 + tid : -1;
       fetch_slot<DIM, true>(a, rin, cs + (kc >= 0 ? kc : 0), cur);
     }
     // 1. exchange: velocities from the previous sweep's forces
@@ -675,15 +682,26 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
   }
   __syncthreads();
   if (STAGE) {
-    // 2. colour-major sequential update from the staged contact data
     const double mu0 = mu_slot ? 0.0 : a.mu_slot[0];
+    if (MIXED) {
+      // the parallel contacts, every thread, from the velocities of the
+      // exchange; their reads precede the colours' writes
+      for (int k = s_co[0] + tid; k < s_co[1]; k += nthr) {
+        SlotPre<DIM> c;
+        get_slot<DIM>(sl, nct, k, mu0, mu_slot, c);
+        update_contact<DIM, false>(sp, s_wu, c, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
+                                   maxd, sumr);
+      }
+      lds_barrier();
+    }
+    // 2. colour-major sequential update from the staged contact data
     if (h.widest <= 64) {
       // every colour fits one wavefront: the first wavefront updates them
       // all, ordered by its own LDS accesses (a wavefront's LDS operations
       // complete in issue order), with no workgroup barrier per colour; the
       // other wavefronts are free for `idle`
       if (tid < 64) {
-        for (int col = 0; col < ncol; ++col) {
+        for (int col = c0; col < ncol; ++col) {
           const int k = s_co[col] + tid;
           if (k < s_co[col + 1]) {
             SlotPre<DIM> c;
@@ -698,7 +716,7 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
       }
       return;
     }
-    for (int col = 0; col < ncol; ++col) {
+    for (int col = c0; col < ncol; ++col) {
       const int k0 = s_co[col], k1 = s_co[col + 1];
       for (int k = k0 + tid; k < k1; k += nthr) {
         SlotPre<DIM> c;
@@ -745,9 +763,21 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
     if (GLOB) __syncthreads();
     else lds_barrier();
   };
+  if (MIXED) {
+    // the parallel contacts (Sec. 2.3), every thread, from the velocities of
+    // the exchange; their reads precede the colours' writes
+    for (int k = s_co[0] + tid; k < s_co[1]; k += nthr) {
+      SlotPre<DIM> pc;
+      fetch_slot<DIM, true>(a, rin, cs + k, pc);
+      update_contact<DIM, false>(sp, s_wu, pc, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
+                                 maxd, sumr);
+    }
+    if (GLOB) __syncthreads();
+    else lds_barrier();
+  }
   SlotPre<DIM> other;
   int ko = -1;
-  int col = 0;
+  int col = c0;
   for (; col + 1 < ncol; col += 2) {
     colour(col, cur, kc, other, ko);
     colour(col + 1, other, ko, cur, kc);
