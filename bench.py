@@ -22,7 +22,15 @@ The JSON line reports whole-step contact updates/s (sum over steps of sweeps
 x contacts, divided by the timed wall-clock), the milliseconds per step, the
 roofline of the sweep kernel (algorithmic bytes per sweep over the summed
 durations of the sweep launches that did work, from HIP events on the
-library's stream) and the CPU oracle on a bounded sample.
+library's stream) and the CPU oracle on a bounded sample.  For the 2D
+workloads it also solves the final state once more from zero forces with the
+workload's domains and with one domain (`sequential_comparison`: the extra
+sweeps of Sec. 4.4 and the observables of Sec. 4.5; `--sequential 0` skips
+it, outside the timed region either way).  Optional legs:
+`--mixed-experiment` (the mixed sequential/parallel update of Sec. 2.3:
+sweeps N_I(p) and the critical share p_c on a settled pile) and
+`--balance SIGMA` (adaptive load balancing of Sec. 3.3 in the timed steps,
+which then no longer measure the headline configuration).
 """
 from __future__ import annotations
 
@@ -185,12 +193,18 @@ def sequential_comparison(wl, pk, ctx, torch, binding, max_iter):
         c.close()
     P = wl["domains"]
     d = analysis.compare(q, runs[1], runs[P])
+    frac = boundary_fraction(q.n, runs[P]["c"])
+    # Sec. 4.4: N_I ~ 1 / D with D = D_p p + D_s (1 - p), D_s / D_p = 1.53
+    model = 1.0 / (1.0 - frac * (1.0 - 1.0 / 1.53))
     return {
         "state": "the positions and velocities after the timed steps, forces from zero",
         "n_domains": P, "sweeps": runs[P]["it"], "sweeps_one_domain": runs[1]["it"],
         "status": runs[P]["status"], "status_one_domain": runs[1]["status"],
         "extra_sweep_factor": runs[P]["it"] / max(runs[1]["it"], 1),
-        "boundary_contact_fraction": boundary_fraction(q.n, runs[P]["c"]),
+        "boundary_contact_fraction": frac,
+        "model_extra_sweep_factor": model,
+        "model": "1 / (1 - p (1 - D_p / D_s)), D_s / D_p = 1.53 fitted in Sec. 4.4, p the "
+                 "boundary contact fraction",
         "mean_stress_rel_diff": d["mean_stress"], "sigma_yy_strips_rel_diff": d["strips"],
         "orientation_tv_distance": d["orientation_tv"],
         "max_force_rel_diff": d.get("forces"),

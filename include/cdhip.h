@@ -201,7 +201,7 @@ int cd_set_mixed_update(cd_ctx* ctx, double p, unsigned long long seed);
 
 /* Adaptive load balancing (Sec. 3.3).  sigma_star >= 0 switches load
  * measurement on: every sweep launch records, per domain, the real time its
- * workgroup spends on it (per-sweep launches only: solve modes 1-3, not the
+ * workgroup spends on it (per-sweep launches only: solve modes 1 and 2, not the
  * one-launch mode 0, not batched sweeps), summed over the step.  After each
  * step the imbalance sigma_T = sqrt(<T^2> - <T>^2) / <T> over the P domain
  * times T_i is computed; when sigma_T >= sigma_star the per-domain

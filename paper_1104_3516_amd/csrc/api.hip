@@ -850,7 +850,7 @@ int solve_single(cd_ctx* c) {
   c->sweep_stage = false;   // the one-launch solve never stages
   c->sweep_fold = false;
   if (c->persistent && c->order_mixed)
-    return fail(c, CD_EINVAL, "the one-launch solve has no mixed update (solve modes 1-3 do)");
+    return fail(c, CD_EINVAL, "the one-launch solve has no mixed update (solve modes 1 and 2 do)");
   const int G = c->persistent ? cd_solve_grid(c) : 0;
   if (G < 8) cd_sweep_mode(c);
   if (G >= 8 && nc > 0 && limit > 0) {

@@ -604,13 +604,18 @@ hipError_t cd_launch_order(cd_ctx* c) {
   unsigned long long* ko = c->sort_keys[0];
   int* vo = c->sort_vals[0];
   if (nc > 0) {
+    // the contact ids are sorted in place in `bucket` (an even number of
+    // passes ends there; otherwise the result is copied back)
     hipLaunchKernelGGL(k_dom_keys, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
-                       c->dom, nc, c->sort_keys[0], c->sort_vals[0]);
-    e = cd_radix_sort(c, c->sort_keys[0], c->sort_vals[0], c->sort_keys[1], c->sort_vals[1], nc,
+                       c->dom, nc, c->sort_keys[0], c->bucket);
+    e = cd_radix_sort(c, c->sort_keys[0], c->bucket, c->sort_keys[1], c->sort_vals[1], nc,
                       bits_for((unsigned long long)(P - 1)), &ko, &vo);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(c->bucket, vo, sizeof(int) * (size_t)nc, hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return e;
+    if (vo != c->bucket) {
+      e = hipMemcpyAsync(c->bucket, vo, sizeof(int) * (size_t)nc, hipMemcpyDeviceToDevice,
+                         c->stream);
+      if (e != hipSuccess) return e;
+    }
   }
   hipLaunchKernelGGL(k_dom_bounds, dim3(cd_blocks(P + 1, kThreads)), dim3(kThreads), 0, c->stream,
                      ko, nc, P, c->dom_start);
@@ -640,19 +645,23 @@ hipError_t cd_launch_order(cd_ctx* c) {
   e = cd_scan_exclusive(c, pcount, poff, n);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pdom_write, dim3(cd_blocks(n, kThreads)), dim3(kThreads), 0, c->stream,
-                     c->inc_ptr, c->inc, c->dom, n, poff, c->sort_keys[0], c->sort_vals[0]);
+                     c->inc_ptr, c->inc, c->dom, n, poff, c->sort_keys[0], c->dp);
   // the number of pairs is poff[n] (at most 2 n_c), known on the device only:
   // the sort covers the 2 n_c slots, the unused tail keyed past every domain
   {
     const int64_t m = 2 * nc;
     if (m > 0) {
+      // sorted in place in `dp` when the pass count is even
       hipLaunchKernelGGL(k_pad_keys, dim3(cd_blocks(m, kThreads)), dim3(kThreads), 0, c->stream,
-                         poff + n, m, c->sort_keys[0], c->sort_vals[0]);
-      e = cd_radix_sort(c, c->sort_keys[0], c->sort_vals[0], c->sort_keys[1], c->sort_vals[1], m,
+                         poff + n, m, c->sort_keys[0], c->dp);
+      e = cd_radix_sort(c, c->sort_keys[0], c->dp, c->sort_keys[1], c->sort_vals[1], m,
                         bits_for((unsigned long long)P), &ko, &vo);
       if (e != hipSuccess) return e;
-      e = hipMemcpyAsync(c->dp, vo, sizeof(int) * (size_t)m, hipMemcpyDeviceToDevice, c->stream);
-      if (e != hipSuccess) return e;
+      if (vo != c->dp) {
+        e = hipMemcpyAsync(c->dp, vo, sizeof(int) * (size_t)m, hipMemcpyDeviceToDevice,
+                           c->stream);
+        if (e != hipSuccess) return e;
+      }
     }
     hipLaunchKernelGGL(k_dom_bounds, dim3(cd_blocks(P + 1, kThreads)), dim3(kThreads), 0,
                        c->stream, ko, m, P, c->dp_start);

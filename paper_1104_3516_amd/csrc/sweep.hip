@@ -205,9 +205,9 @@ __device__ inline void decide_wave(const SweepArgs& a, int jd) {
 // decision workgroup; the second wavefront of workgroup 0 takes the decision
 // while the first updates the colours (or after them when a colour is wider
 // than a wavefront), so that a launch has one workgroup per domain.
-// TIMED: per-domain load measurement when a.dtick is set (single contexts;
-// batched sweeps never measure).
-template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = true>
+// TIMED: per-domain load measurement into a.dtick (single contexts with load
+// balancing on; a separate instantiation so that the plain sweep is unchanged).
+template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false>
 __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArgs& a, int b, int j,
                                                                   BatchProg* bp) {
   extern __shared__ double lds[];
@@ -238,11 +238,10 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
     // load measurement (Sec. 3.3): the real-time ticks thread 0 spends on
     // its domain (its wavefront runs the colours; a folded decision is
     // taken by another wavefront and not counted), summed over the step
-    const bool timed = TIMED && a.dtick != nullptr;
-    const unsigned long long t0 = timed ? __builtin_amdgcn_s_memrealtime() : 0ull;
+    const unsigned long long t0 = TIMED ? __builtin_amdgcn_s_memrealtime() : 0ull;
     sweep_domain<DIM, GLOB, STAGE, MIXED>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr,
                                           idle);
-    if (timed && threadIdx.x == 0) a.dtick[d] += __builtin_amdgcn_s_memrealtime() - t0;
+    if (TIMED && threadIdx.x == 0) a.dtick[d] += __builtin_amdgcn_s_memrealtime() - t0;
   } else {
     idle();
   }
@@ -256,9 +255,9 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
 // workgroup is resident at once on 256 CUs.
 // MIXED: colour 0 of every domain holds its contacts updated in parallel
 // (Sec. 2.3), a separate instantiation so that the plain sweep is unchanged.
-template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false>
+template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false>
 __global__ __launch_bounds__(kMaxBlock, STAGE && DIM == 2 ? 5 : 1) void k_sweep(SweepArgs a, int j) {
-  sweep_block<DIM, GLOB, STAGE, FOLD, MIXED>(a, blockIdx.x, j, nullptr);
+  sweep_block<DIM, GLOB, STAGE, FOLD, MIXED, TIMED>(a, blockIdx.x, j, nullptr);
 }
 
 // Sweep j of a batch of packings: workgroup b serves packing blk[2b] as its
@@ -269,7 +268,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep_batch(const SweepArgs* tab,
   const int2 pb = ((const int2*)blk)[blockIdx.x];
   // read in place: a local copy of the arguments would live in scratch
   const SweepArgs& a = tab[pb.x];
-  sweep_block<DIM, false, STAGE, false, false, false>(a, pb.y, j, bp);
+  sweep_block<DIM, false, STAGE, false>(a, pb.y, j, bp);
 }
 
 // stop decision of sweep jd alone (after the last launched sweep)
@@ -612,19 +611,34 @@ void cd_sweep_mode(cd_ctx* c) {
 
 // One sweep launch in the context's form (global records, staged with the
 // decision folded into workgroup 0, staged, register read-ahead).
-template <int DIM, bool MIXED>
+template <int DIM, bool MIXED, bool TIMED>
 static void launch_sweep_form(cd_ctx* c, const SweepArgs& a, dim3 grid, dim3 block, size_t lds,
                               bool fold, int j) {
   if (c->sweep_global)
-    hipLaunchKernelGGL((k_sweep<DIM, true, false, false, MIXED>), grid, block, 0, c->stream, a, j);
+    hipLaunchKernelGGL((k_sweep<DIM, true, false, false, MIXED, TIMED>), grid, block, 0,
+                       c->stream, a, j);
   else if (fold)
-    hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED>), grid, block, lds, c->stream, a, j);
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED, TIMED>), grid, block, lds,
+                       c->stream, a, j);
   else if (c->sweep_stage)
-    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED>), grid, block, lds, c->stream, a,
-                       j);
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED, TIMED>), grid, block, lds,
+                       c->stream, a, j);
   else
-    hipLaunchKernelGGL((k_sweep<DIM, false, false, false, MIXED>), grid, block, lds, c->stream, a,
-                       j);
+    hipLaunchKernelGGL((k_sweep<DIM, false, false, false, MIXED, TIMED>), grid, block, lds,
+                       c->stream, a, j);
+}
+
+template <int DIM>
+static void launch_sweep_dim(cd_ctx* c, const SweepArgs& a, dim3 grid, dim3 block, size_t lds,
+                             bool fold, int j) {
+  const bool timed = a.dtick != nullptr;
+  if (c->order_mixed) {
+    if (timed) launch_sweep_form<DIM, true, true>(c, a, grid, block, lds, fold, j);
+    else launch_sweep_form<DIM, true, false>(c, a, grid, block, lds, fold, j);
+  } else {
+    if (timed) launch_sweep_form<DIM, false, true>(c, a, grid, block, lds, fold, j);
+    else launch_sweep_form<DIM, false, false>(c, a, grid, block, lds, fold, j);
+  }
 }
 
 hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after) {
@@ -638,13 +652,8 @@ hipError_t cd_launch_sweep(cd_ctx* c, int j, hipEvent_t before, hipEvent_t after
   const bool fold = c->sweep_fold;
   dim3 grid(a.grid + (fold ? 0 : 1)), block(c->sweep_block);
   const size_t lds = block_lds(c);
-  if (c->dim == 2) {
-    if (c->order_mixed) launch_sweep_form<2, true>(c, a, grid, block, lds, fold, j);
-    else launch_sweep_form<2, false>(c, a, grid, block, lds, fold, j);
-  } else {
-    if (c->order_mixed) launch_sweep_form<3, true>(c, a, grid, block, lds, fold, j);
-    else launch_sweep_form<3, false>(c, a, grid, block, lds, fold, j);
-  }
+  if (c->dim == 2) launch_sweep_dim<2>(c, a, grid, block, lds, fold, j);
+  else launch_sweep_dim<3>(c, a, grid, block, lds, fold, j);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !after) return e;
   return hipEventRecord(after, c->stream);

@@ -86,3 +86,19 @@ def test_benchmark_tolerance_observables():
     assert d["strips"] <= 1e-2
     assert d["orientation_tv"] <= 0.02
     assert other["it"] <= 1.5 * ref["it"]
+
+
+def test_chain_sweeps_follow_the_diffusion_model():
+    """Sec. 4.4, Fig. 13(a, b): 64 touching disks compressed by a force, cut
+    into P domains: N_I(P) / N_I(1) within 2 % of 1 / (1 - p (1 - D_p/D_s)),
+    p = P / 64, D_s / D_p = 1.53."""
+    pk = inputs.chain_2d(64, 1.0)
+    base = None
+    for P in (1, 2, 4, 8, 16):
+        run = _solve(pk, P, mu=0.3, max_iter=100000)
+        assert run["status"] == 0
+        base = base or run["it"]
+        model = 1.0 / (1.0 - (P / 64) * (1.0 - 1.0 / 1.53))
+        print(f"[chain P={P}] sweeps {run['it']} ratio {run['it'] / base:.3f} model {model:.3f}",
+              flush=True)
+        assert run["it"] / base == pytest.approx(model, rel=0.02)

@@ -84,3 +84,21 @@ def test_no_parallel_contacts_is_the_plain_solve(oracle):
     np.testing.assert_array_equal(Rm, R0)
     assert im.iterations == i0.iterations
     np.testing.assert_array_equal(color, c0 + 1)   # colours shifted past the parallel block
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_chain_sweeps_follow_the_diffusion_model(oracle, n):
+    """Sec. 4.4, Fig. 13(a, b): a chain of n touching disks compressed by a
+    force, cut into P domains, needs N_I(P) / N_I(1) = D_s / D_eff sweeps
+    with D_eff = D_p p + D_s (1 - p), p = P / n and the fitted
+    D_s / D_p = 1.53; within 2 %."""
+    pk = inputs.chain_2d(n, 1.0)
+    base = None
+    for P in (1, 2, 4, 8, 16):
+        sim = oracle.Sim(oracle.make_params(2, pk.n_walls, mu=0.3, n_domains=P, max_iter=100000),
+                         pk)
+        info = sim.step()
+        assert info.status == 0
+        base = base or info.iterations
+        model = 1.0 / (1.0 - (P / n) * (1.0 - 1.0 / 1.53))
+        assert info.iterations / base == pytest.approx(model, rel=0.02)
