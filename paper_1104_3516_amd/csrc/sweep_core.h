@@ -203,7 +203,27 @@ __device__ inline void fetch_slot(const SweepArgs& a, const double* rin, int64_t
   const int64_t cap = a.cap;
   const double* g = a.geo;
   o.ab = a.ab[s];
-  for (int q = 0; q < NG; ++q) o.f[q] = g[q * cap + s];
+  if (DIM == 3 && !RECIP) {
+    // staged 3D slots: the tangents follow from the normal (the basis of Duff
+    // et al., JCGT 6(1), 2017, with the operations of the domain build that
+    // stored them), 48 bytes per slot not read from memory
+    double n3[3];
+    for (int q = 0; q < 3; ++q) n3[q] = g[q * cap + s];
+    const double sign = copysign(1.0, n3[2]);
+    const double aa = -1.0 / (sign + n3[2]);
+    const double bb = n3[0] * n3[1] * aa;
+    o.f[0] = n3[0];
+    o.f[1] = n3[1];
+    o.f[2] = n3[2];
+    o.f[NG > 3 ? 3 : 0] = 1.0 + sign * n3[0] * n3[0] * aa;
+    o.f[NG > 4 ? 4 : 0] = sign * bb;
+    o.f[NG > 5 ? 5 : 0] = -sign * n3[0];
+    o.f[NG > 6 ? 6 : 0] = bb;
+    o.f[NG > 7 ? 7 : 0] = sign + n3[1] * n3[1] * aa;
+    o.f[NG > 8 ? 8 : 0] = -n3[1];
+  } else {
+    for (int q = 0; q < NG; ++q) o.f[q] = g[q * cap + s];
+  }
   o.gdt = g[G_GDT * cap + s];
   o.dwn = g[G_DWN * cap + s];
   o.dwt = g[G_DWT * cap + s];
