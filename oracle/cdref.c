@@ -322,6 +322,34 @@ void cdref_parallel_flags(int64_t nc, const int32_t* ci, const int32_t* cj, doub
 }
 
 /* ------------------------------------------------------------------ */
+/* random sequential order (Sec. 2.1)                                   */
+/* ------------------------------------------------------------------ */
+
+/* The key of time step `step`: SplitMix64(SplitMix64(seed) ^ step). */
+uint64_t cdref_random_step_key(uint64_t seed, int64_t step) {
+  return splitmix64(splitmix64(seed) ^ (uint64_t)step);
+}
+
+/* The draw of slot s in sweep j (1-based) of the step with key k:
+ * SplitMix64(SplitMix64(k ^ j) ^ s).  A domain updates its contacts in the
+ * order of increasing draw, equal draws by slot. */
+uint64_t cdref_random_slot_key(uint64_t step_key, int j, int64_t s) {
+  return splitmix64(splitmix64(step_key ^ (uint64_t)j) ^ (uint64_t)s);
+}
+
+typedef struct {
+  uint64_t key;
+  int64_t slot;
+} rand_slot;
+
+static int rand_slot_cmp(const void* a, const void* b) {
+  const rand_slot* x = (const rand_slot*)a;
+  const rand_slot* y = (const rand_slot*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->slot < y->slot ? -1 : (x->slot > y->slot ? 1 : 0);
+}
+
+/* ------------------------------------------------------------------ */
 /* adaptive load balancing (Sec. 3.3)                                   */
 /* ------------------------------------------------------------------ */
 
@@ -763,14 +791,18 @@ int cdref_solve(const cdref_params* p, int64_t n, const double* v, const double*
                            gap, mu_c, NULL, P, dom_start, slot_contact, R, info, history);
 }
 
-int cdref_solve_mixed(const cdref_params* p, int64_t n, const double* v, const double* w,
+/* The solve; `parallel` (or NULL) flags contacts updated in parallel
+ * (Sec. 2.3); with `step_key` non-NULL each domain instead updates its
+ * contacts in the random order of cdref_random_slot_key, drawn afresh in
+ * every sweep (Sec. 2.1). */
+static int solve_impl(const cdref_params* p, int64_t n, const double* v, const double* w,
                       const double* r, const double* m, const double* inertia,
                       const double* f, const double* t, const double* wall_velocity,
                       int64_t nc, const int32_t* ci, const int32_t* cj,
                       const double* normal, const double* gap, const double* mu_c,
-                      const uint8_t* parallel, int P, const int64_t* dom_start,
-                      const int32_t* slot_contact, double* R, cdref_info* info,
-                      double* history) {
+                      const uint8_t* parallel, const uint64_t* step_key, int P,
+                      const int64_t* dom_start, const int32_t* slot_contact, double* R,
+                      cdref_info* info, double* history) {
   int dim = p->dim, dr = dim == 2 ? 1 : 3;
   int64_t nn = n > 0 ? n : 1, ncc = nc > 0 ? nc : 1;
   memset(info, 0, sizeof(*info));
@@ -785,8 +817,10 @@ int cdref_solve_mixed(const cdref_params* p, int64_t n, const double* v, const d
   double* Wd = (double*)malloc(sizeof(double) * (size_t)(dr * nn));
   double* dtim = (double*)malloc(sizeof(double) * (size_t)nn);
   double* dtii = (double*)malloc(sizeof(double) * (size_t)nn);
-  if (!cc || !Rprev || !Vg || !Wg || !Vd || !Wd || !dtim || !dtii) {
+  rand_slot* ord = step_key ? (rand_slot*)malloc(sizeof(rand_slot) * (size_t)ncc) : NULL;
+  if (!cc || !Rprev || !Vg || !Wg || !Vd || !Wd || !dtim || !dtii || (step_key && !ord)) {
     free(cc); free(Rprev); free(Vg); free(Wg); free(Vd); free(Wd); free(dtim); free(dtii);
+    free(ord);
     return CDREF_ENOMEM;
   }
   for (int64_t i = 0; i < n; ++i) {
@@ -831,11 +865,22 @@ int cdref_solve_mixed(const cdref_params* p, int64_t n, const double* v, const d
     /* each domain sweeps its native contacts sequentially on a private copy
        of the velocities; other domains' contacts keep their sweep j-1 value */
     for (int d = 0; d < P; ++d) {
+      const int64_t len = dom_start[d + 1] - dom_start[d];
+      if (step_key) {
+        /* this sweep's random order of the domain's contacts */
+        for (int64_t q = 0; q < len; ++q) {
+          ord[q].slot = dom_start[d] + q;
+          ord[q].key = cdref_random_slot_key(*step_key, j, ord[q].slot);
+        }
+        qsort(ord, (size_t)len, sizeof(rand_slot), rand_slot_cmp);
+      }
       /* pass 0: the domain's parallel contacts (Sec. 2.3) from the velocities
          of the exchange, their changes not applied in this sweep (the other
-         contacts see their old forces); pass 1: the sequential update */
+         contacts see their old forces); pass 1: the sequential update, in
+         slot order or in the sweep's random order */
       for (int pass = parallel ? 0 : 1; pass < 2; ++pass)
-      for (int64_t s = dom_start[d]; s < dom_start[d + 1]; ++s) {
+      for (int64_t q = 0; q < len; ++q) {
+        int64_t s = step_key ? ord[q].slot : dom_start[d] + q;
         int64_t c = slot_contact[s];
         const int par = parallel ? parallel[c] != 0 : 0;
         if (par != (pass == 0)) continue;
@@ -914,7 +959,32 @@ int cdref_solve_mixed(const cdref_params* p, int64_t n, const double* v, const d
   }
   info->status = status;
   free(cc); free(Rprev); free(Vg); free(Wg); free(Vd); free(Wd); free(dtim); free(dtii);
+  free(ord);
   return status;
+}
+
+int cdref_solve_mixed(const cdref_params* p, int64_t n, const double* v, const double* w,
+                      const double* r, const double* m, const double* inertia,
+                      const double* f, const double* t, const double* wall_velocity,
+                      int64_t nc, const int32_t* ci, const int32_t* cj,
+                      const double* normal, const double* gap, const double* mu_c,
+                      const uint8_t* parallel, int P, const int64_t* dom_start,
+                      const int32_t* slot_contact, double* R, cdref_info* info,
+                      double* history) {
+  return solve_impl(p, n, v, w, r, m, inertia, f, t, wall_velocity, nc, ci, cj, normal, gap,
+                    mu_c, parallel, NULL, P, dom_start, slot_contact, R, info, history);
+}
+
+int cdref_solve_random(const cdref_params* p, int64_t n, const double* v, const double* w,
+                       const double* r, const double* m, const double* inertia,
+                       const double* f, const double* t, const double* wall_velocity,
+                       int64_t nc, const int32_t* ci, const int32_t* cj,
+                       const double* normal, const double* gap, const double* mu_c, int P,
+                       const int64_t* dom_start, const int32_t* slot_contact, uint64_t seed,
+                       int64_t step, double* R, cdref_info* info, double* history) {
+  const uint64_t key = cdref_random_step_key(seed, step);
+  return solve_impl(p, n, v, w, r, m, inertia, f, t, wall_velocity, nc, ci, cj, normal, gap,
+                    mu_c, NULL, &key, P, dom_start, slot_contact, R, info, history);
 }
 
 /* ------------------------------------------------------------------ */
@@ -936,6 +1006,8 @@ struct cdref_sim {
   double* capacity;   /* per-domain capacities for the tree rebuilds, or NULL */
   double mixed_p;     /* share of contacts updated in parallel (< 0: none) */
   uint64_t mixed_seed;
+  int rand_on;        /* random sequential order (Sec. 2.1) */
+  uint64_t rand_seed;
   /* contacts of the last step */
   int64_t nc, cap;
   int32_t *ci, *cj, *dom, *color, *slot;
@@ -998,6 +1070,12 @@ void cdref_sim_destroy(cdref_sim* s) {
 void cdref_sim_set_mixed(cdref_sim* s, double p, uint64_t seed) {
   s->mixed_p = p;
   s->mixed_seed = seed;
+}
+
+int cdref_sim_set_random(cdref_sim* s, int on, uint64_t seed) {
+  s->rand_on = on != 0;
+  s->rand_seed = seed;
+  return CDREF_OK;
 }
 
 int cdref_sim_set_capacity(cdref_sim* s, const double* capacity) {
@@ -1138,9 +1216,17 @@ int cdref_sim_step(cdref_sim* s, cdref_info* info) {
   }
   st = cdref_order_mixed(n, nc, s->ci, s->cj, P, s->dom, par, s->color, s->slot, dom_start);
   if (st != CDREF_OK) { free(dom_start); free(par); return st; }
-  st = cdref_solve_mixed(p, n, s->v, s->w, s->r, s->m, s->I, s->f, s->t, s->wu, nc, s->ci,
-                         s->cj, s->normal, s->gap, NULL, par, P, dom_start, s->slot, s->R, info,
-                         NULL);
+  if (s->rand_on && par) {
+    st = CDREF_EINVAL;   /* the random order has no parallel contacts */
+  } else if (s->rand_on) {
+    st = cdref_solve_random(p, n, s->v, s->w, s->r, s->m, s->I, s->f, s->t, s->wu, nc, s->ci,
+                            s->cj, s->normal, s->gap, NULL, P, dom_start, s->slot,
+                            s->rand_seed, s->step, s->R, info, NULL);
+  } else {
+    st = cdref_solve_mixed(p, n, s->v, s->w, s->r, s->m, s->I, s->f, s->t, s->wu, nc, s->ci,
+                           s->cj, s->normal, s->gap, NULL, par, P, dom_start, s->slot, s->R,
+                           info, NULL);
+  }
   free(par);
   info->skin = skin;
   info->n_contacts = nc;

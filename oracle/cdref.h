@@ -139,6 +139,20 @@ int cdref_solve_mixed(const cdref_params* p, int64_t n, const double* v, const d
                       const int32_t* slot_contact, double* R, cdref_info* info,
                       double* history);
 
+/* Random sequential order (Sec. 2.1): in sweep j (1-based) of time step
+ * `step` each domain updates its contacts one at a time in the order of
+ * increasing draw SplitMix64(SplitMix64(K ^ j) ^ s), s the slot, equal draws
+ * by slot, K = SplitMix64(SplitMix64(seed) ^ step). */
+uint64_t cdref_random_step_key(uint64_t seed, int64_t step);
+uint64_t cdref_random_slot_key(uint64_t step_key, int j, int64_t s);
+int cdref_solve_random(const cdref_params* p, int64_t n, const double* v, const double* w,
+                       const double* r, const double* m, const double* inertia,
+                       const double* f, const double* t, const double* wall_velocity,
+                       int64_t nc, const int32_t* ci, const int32_t* cj,
+                       const double* normal, const double* gap, const double* mu_c, int P,
+                       const int64_t* dom_start, const int32_t* slot_contact, uint64_t seed,
+                       int64_t step, double* R, cdref_info* info, double* history);
+
 /* Load imbalance sigma_T = sqrt(<T^2> - <T>^2) / <T> over P times (Sec. 3.3). */
 double cdref_sigma_t(int P, const double* T);
 
@@ -206,6 +220,9 @@ int64_t cdref_sim_contacts(const cdref_sim* s, int64_t cap, int32_t* ci, int32_t
                            int32_t* color, int32_t* slot_contact);
 /* mixed update from now on: contacts with pair number below p (p < 0: none) */
 void cdref_sim_set_mixed(cdref_sim* s, double p, uint64_t seed);
+/* random sequential order from now on (on = 0: colour-major); the step
+ * index of the draws is the number of steps taken before */
+int cdref_sim_set_random(cdref_sim* s, int on, uint64_t seed);
 /* capacities (P doubles, domain order) used by every later tree rebuild;
  * NULL: back to leaf counts */
 int cdref_sim_set_capacity(cdref_sim* s, const double* capacity);

@@ -74,6 +74,14 @@ def lib():
                                         P, P, P, P, P, C.c_int, P, P, P, C.POINTER(Info), P]
         L.cdref_sim_set_mixed.argtypes = [P, C.c_double, C.c_uint64]
         L.cdref_sim_set_mixed.restype = None
+        L.cdref_random_step_key.argtypes = [C.c_uint64, i64]
+        L.cdref_random_step_key.restype = C.c_uint64
+        L.cdref_random_slot_key.argtypes = [C.c_uint64, C.c_int, i64]
+        L.cdref_random_slot_key.restype = C.c_uint64
+        L.cdref_solve_random.argtypes = [C.POINTER(Params), i64, P, P, P, P, P, P, P, P, i64, P,
+                                         P, P, P, P, C.c_int, P, P, C.c_uint64, i64, P,
+                                         C.POINTER(Info), P]
+        L.cdref_sim_set_random.argtypes = [P, C.c_int, C.c_uint64]
         L.cdref_descend.argtypes = [C.c_int, C.c_int, P, P, P, P, i64, P, P]
         L.cdref_descend.restype = None
         L.cdref_tree_leaves.argtypes = [C.c_int, P]
@@ -245,8 +253,10 @@ def order(n: int, ci, cj, P: int, dom, parallel=None):
 
 
 def solve(params: Params, pk, ci, cj, normal, gap, P: int, dom_start, slot, R0=None,
-          mu_c=None, history: bool = False, parallel=None):
-    """One force solve.  Returns (R, info, history-or-None)."""
+          mu_c=None, history: bool = False, parallel=None, random_order=None):
+    """One force solve.  Returns (R, info, history-or-None).  `random_order`
+    = (seed, step): each domain updates its contacts in the random order of
+    `random_slot_key`, drawn afresh in every sweep (Sec. 2.1)."""
     L = lib()
     nc = len(ci)
     dim = pk.dim
@@ -255,6 +265,20 @@ def solve(params: Params, pk, ci, cj, normal, gap, P: int, dom_start, slot, R0=N
     limit = params.fixed_iters if params.fixed_iters > 0 else params.max_iter
     hist = np.zeros((4, limit)) if history else None
     par = None if parallel is None else _u8(parallel)
+    if random_order is not None:
+        if parallel is not None:
+            raise ValueError("the random order has no parallel contacts")
+        seed, step = random_order
+        st = L.cdref_solve_random(C.byref(params), pk.n, _p(_f64(pk.v)), _p(_f64(pk.w)),
+                                  _p(_f64(pk.r)), _p(_f64(pk.m)), _p(_f64(pk.inertia)),
+                                  _p(_f64(pk.f)), _p(_f64(pk.t)), _p(_f64(pk.wall_velocity)), nc,
+                                  _p(_i32(ci)), _p(_i32(cj)), _p(_f64(normal)), _p(_f64(gap)),
+                                  None if mu_c is None else _p(_f64(mu_c)), P,
+                                  _p(np.ascontiguousarray(dom_start, np.int64)), _p(_i32(slot)),
+                                  int(seed), int(step), _p(R), C.byref(info), _p(hist))
+        if st < 0:
+            raise RuntimeError(f"cdref_solve_random failed: {st}")
+        return R, info, (hist[:, :info.iterations] if hist is not None else None)
     st = L.cdref_solve_mixed(C.byref(params), pk.n, _p(_f64(pk.v)), _p(_f64(pk.w)),
                              _p(_f64(pk.r)), _p(_f64(pk.m)), _p(_f64(pk.inertia)),
                              _p(_f64(pk.f)), _p(_f64(pk.t)), _p(_f64(pk.wall_velocity)), nc,
@@ -267,6 +291,16 @@ def solve(params: Params, pk, ci, cj, normal, gap, P: int, dom_start, slot, R0=N
     if hist is not None:
         hist = hist[:, :info.iterations]
     return R, info, hist
+
+
+def random_step_key(seed: int, step: int) -> int:
+    """K = SplitMix64(SplitMix64(seed) ^ step) of a time step's random order."""
+    return int(lib().cdref_random_step_key(seed, step))
+
+
+def random_slot_key(step_key: int, j: int, s: int) -> int:
+    """Draw of slot s in sweep j: SplitMix64(SplitMix64(K ^ j) ^ s)."""
+    return int(lib().cdref_random_slot_key(step_key, j, s))
 
 
 def criterion(Rprev, R, ravg_prev: float, alpha: float, which: int = 0):
@@ -359,6 +393,11 @@ class Sim:
         """Mixed update from now on (Sec. 2.3): contacts with pair number
         below p are updated in parallel; p < 0 switches it off."""
         self.L.cdref_sim_set_mixed(self.h, float(p), int(seed))
+
+    def set_random(self, on: bool = True, seed: int = 0):
+        """Random sequential order from now on (Sec. 2.1); the draws of a
+        step use the number of steps taken before it."""
+        self.L.cdref_sim_set_random(self.h, 1 if on else 0, int(seed))
 
     def set_capacity(self, capacity=None):
         """Per-domain capacities for every later tree rebuild (None: leaf counts)."""
