@@ -199,6 +199,24 @@ int cd_set_launch(cd_ctx* ctx, int block_threads);
  * none.  CD_EINVAL for p = NaN or together with the adjoint. */
 int cd_set_mixed_update(cd_ctx* ctx, double p, unsigned long long seed);
 
+/* Random sequential order (Sec. 2.1) from the next solve on (on != 0): in
+ * every sweep each domain updates its own contacts one at a time in a
+ * random order drawn afresh for that sweep, instead of colour by colour.
+ * Slot s (the contact's position in the domain-major, colour-major slot
+ * order of cd_get_contacts) draws SplitMix64(SplitMix64(K ^ j) ^ s) in
+ * sweep j (1-based) of time step t, K = SplitMix64(SplitMix64(seed) ^ t), t
+ * the number of steps the context has taken; a domain takes its slots by
+ * increasing draw, equal draws by slot.  The domain semantics (frozen
+ * foreign contacts, exchange between sweeps) are unchanged.  One thread per
+ * domain runs the updates, so a sweep is much slower than the colour-major
+ * one: the mode is for comparing orders (Sec. 4.4), not for throughput.
+ * Needs 12 bytes of LDS per contact of the largest domain beyond the
+ * sweep's own staging (CD_ECAPACITY from the step otherwise).  CD_EINVAL
+ * together with the mixed update, the adjoint or load measurement; the
+ * one-launch solve (mode 0) and the batch refuse it.  on = 0: colour-major
+ * (default). */
+int cd_set_random_order(cd_ctx* ctx, int on, unsigned long long seed);
+
 /* Adaptive load balancing (Sec. 3.3).  sigma_star >= 0 switches load
  * measurement on: every sweep launch records, per domain, the real time its
  * workgroup spends on it (per-sweep launches only: solve modes 1 and 2, not the

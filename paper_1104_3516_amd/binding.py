@@ -104,6 +104,7 @@ def lib():
         L.cd_set_adjoint.argtypes = [P, C.c_int]
         L.cd_set_frozen_list.argtypes = [P, C.c_int]
         L.cd_set_mixed_update.argtypes = [P, C.c_double, C.c_ulonglong]
+        L.cd_set_random_order.argtypes = [P, C.c_int, C.c_ulonglong]
         L.cd_set_load_balance.argtypes = [P, C.c_double]
         L.cd_set_domain_capacity.argtypes = [P, P]
         L.cd_get_domain_times.argtypes = [P, P, P]
@@ -301,6 +302,12 @@ class Context:
         """Mixed sequential/parallel update (Sec. 2.3): contacts with pair
         number below p are updated in parallel; p < 0 switches it off."""
         self._check(self.L.cd_set_mixed_update(self.h, float(p), int(seed)))
+
+    def set_random_order(self, on: bool = True, seed: int = 0):
+        """Random sequential order (Sec. 2.1): every sweep, each domain's
+        contacts one at a time in a fresh SplitMix64 draw of (seed, step,
+        sweep, slot); False returns to the colour-major order."""
+        self._check(self.L.cd_set_random_order(self.h, int(bool(on)), int(seed)))
 
     def set_load_balance(self, sigma_star: float):
         """Adaptive load balancing (Sec. 3.3) with threshold sigma_star on

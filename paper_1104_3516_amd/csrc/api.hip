@@ -574,6 +574,8 @@ int cd_set_solve_mode(cd_ctx* c, int mode) {
 
 int cd_set_load_balance(cd_ctx* c, double sigma_star) {
   if (!c || !std::isfinite(sigma_star)) return CD_EINVAL;
+  if (sigma_star >= 0.0 && c->order_random)
+    return fail(c, CD_EINVAL, "the load is measured on the colour-major sweep only");
   if (sigma_star < 0.0) {
     c->lb_sigma_star = -1.0;
     c->lb_capacity.clear();
@@ -851,8 +853,16 @@ int solve_single(cd_ctx* c) {
   c->sweep_fold = false;
   if (c->persistent && c->order_mixed)
     return fail(c, CD_EINVAL, "the one-launch solve has no mixed update (solve modes 1 and 2 do)");
+  if (c->persistent && c->order_random)
+    return fail(c, CD_EINVAL, "the one-launch solve has no random order (solve modes 1 and 2 do)");
   const int G = c->persistent ? cd_solve_grid(c) : 0;
   if (G < 8) cd_sweep_mode(c);
+  if (c->order_random && nc > 0) {
+    const size_t form = c->sweep_global ? 0 : (c->sweep_stage ? c->sweep_lds_stage : c->sweep_lds);
+    if (form + cd_random_lds(c) + 2048 > c->max_lds)
+      return fail(c, CD_ECAPACITY,
+                  "the random order needs 12 bytes of LDS per contact of the largest domain");
+  }
   if (G >= 8 && nc > 0 && limit > 0) {
     // all sweeps in one launch
     if ((int)c->sweep_ev.size() < 2) {
@@ -1090,8 +1100,23 @@ int cd_set_mixed_update(cd_ctx* c, double p, unsigned long long seed) {
   if (!c || std::isnan(p)) return CD_EINVAL;
   if (p >= 0.0 && c->adj_every > 0)
     return fail(c, CD_EINVAL, "the adjoint differentiates the sequential update only");
+  if (p >= 0.0 && c->order_random)
+    return fail(c, CD_EINVAL, "the random order has no parallel contacts");
   c->mixed_p = p >= 0.0 ? p : -1.0;
   c->mixed_seed = seed;
+  return CD_OK;
+}
+
+int cd_set_random_order(cd_ctx* c, int on, unsigned long long seed) {
+  if (!c) return CD_EINVAL;
+  if (on && c->adj_every > 0)
+    return fail(c, CD_EINVAL, "the adjoint differentiates the colour-major order only");
+  if (on && c->mixed_p >= 0.0)
+    return fail(c, CD_EINVAL, "the random order has no parallel contacts");
+  if (on && c->lb_sigma_star >= 0.0)
+    return fail(c, CD_EINVAL, "the load is measured on the colour-major sweep only");
+  c->order_random = on != 0;
+  c->rand_seed = seed;
   return CD_OK;
 }
 
@@ -1099,6 +1124,8 @@ int cd_set_adjoint(cd_ctx* c, int checkpoint_every) {
   if (!c || checkpoint_every < 0) return CD_EINVAL;
   if (checkpoint_every > 0 && c->mixed_p >= 0.0)
     return fail(c, CD_EINVAL, "the adjoint differentiates the sequential update only");
+  if (checkpoint_every > 0 && c->order_random)
+    return fail(c, CD_EINVAL, "the adjoint differentiates the colour-major order only");
   c->adj_every = checkpoint_every;
   cd_window_clear(c);
   c->adj_valid = false;

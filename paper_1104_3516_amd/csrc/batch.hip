@@ -267,6 +267,9 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
     if (!b->failed[p] && c->order_mixed)
       return bfail(b, CD_EINVAL,
                    "packing " + std::to_string(p) + ": batched sweeps have no mixed update");
+    if (!b->failed[p] && c->order_random)
+      return bfail(b, CD_EINVAL,
+                   "packing " + std::to_string(p) + ": batched sweeps have no random order");
     b->h_tab[p] = cd_sweep_args(c);
     b->h_tab[p].dtick = nullptr;   // batched sweeps do not measure the load
     block = std::max(block, c->sweep_block);

@@ -122,6 +122,7 @@ struct SweepArgs {
   int grid;                 // blocks of a one-sweep launch
   int block;                // threads per block of a sweep launch
   unsigned long long* dtick;  // per-domain elapsed real-time ticks of the step, or null
+  unsigned long long rkey;  // random sequential order: the step's key K (Sec. 2.1)
   int per_xcd;              // domains per XCD in the block -> domain map
   int wave_lds;             // LDS staging per wavefront (doubles)
   long long nc;
@@ -316,6 +317,8 @@ struct cd_ctx {
   unsigned char* par = nullptr;         // per contact: updated in parallel
   int64_t par_cap = 0;
   bool order_mixed = false;             // the current order has a parallel colour 0
+  bool order_random = false;            // random sequential order in every sweep (Sec. 2.1)
+  unsigned long long rand_seed = 0;
 
   // adaptive load balancing (Sec. 3.3)
   double lb_sigma_star = -1.0;          // threshold on sigma_T; < 0: no measurement
@@ -383,6 +386,8 @@ hipError_t cd_launch_sweep_batch(hipStream_t stream, int dim, const SweepArgs* t
 // LDS of the staged sweep for domains of these sizes (particle entries,
 // contacts), with the context's friction mode
 size_t cd_stage_lds(cd_ctx* c, int max_particles, int max_contacts);
+// LDS of the random order's draws and ranked slots per workgroup (0 without it)
+size_t cd_random_lds(cd_ctx* c);
 // whether a launch of `workgroups` should stage contact data: it must fit and
 // must not need more rounds of resident workgroups than the register form
 bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64_t wg_stage,

@@ -207,7 +207,8 @@ __device__ inline void decide_wave(const SweepArgs& a, int jd) {
 // than a wavefront), so that a launch has one workgroup per domain.
 // TIMED: per-domain load measurement into a.dtick (single contexts with load
 // balancing on; a separate instantiation so that the plain sweep is unchanged).
-template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false>
+template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false,
+          bool RAND = false>
 __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArgs& a, int b, int j,
                                                                   BatchProg* bp) {
   extern __shared__ double lds[];
@@ -239,8 +240,9 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
     // its domain (its wavefront runs the colours; a folded decision is
     // taken by another wavefront and not counted), summed over the step
     const unsigned long long t0 = TIMED ? __builtin_amdgcn_s_memrealtime() : 0ull;
-    sweep_domain<DIM, GLOB, STAGE, MIXED>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr,
-                                          idle);
+    sweep_domain<DIM, GLOB, STAGE, MIXED, RAND>(
+        a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr,
+        RAND ? rand_mix(a.rkey ^ (unsigned long long)j) : 0ull, idle);
     if (TIMED && threadIdx.x == 0) a.dtick[d] += __builtin_amdgcn_s_memrealtime() - t0;
   } else {
     idle();
@@ -255,9 +257,12 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
 // workgroup is resident at once on 256 CUs.
 // MIXED: colour 0 of every domain holds its contacts updated in parallel
 // (Sec. 2.3), a separate instantiation so that the plain sweep is unchanged.
-template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false>
+// RAND: the random sequential order of Sec. 2.1 (thread 0 of each domain's
+// workgroup updates its contacts one at a time), a separate instantiation.
+template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false,
+          bool RAND = false>
 __global__ __launch_bounds__(kMaxBlock, STAGE && DIM == 2 ? 5 : 1) void k_sweep(SweepArgs a, int j) {
-  sweep_block<DIM, GLOB, STAGE, FOLD, MIXED, TIMED>(a, blockIdx.x, j, nullptr);
+  sweep_block<DIM, GLOB, STAGE, FOLD, MIXED, TIMED, RAND>(a, blockIdx.x, j, nullptr);
 }
 
 // Sweep j of a batch of packings: workgroup b serves packing blk[2b] as its
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(SweepArgs a, GridBar* bar, 
       if (d < 0) break;
       const DomainHead h = load_head<DIM>(a, d);
       sweep_domain<DIM, GLOB, false>(a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr,
-                                     [] {});
+                                     0ull, [] {});
     }
     BlockPartial p = block_partial(npass, maxd, sumr, red, blockDim.x);
     if (threadIdx.x == 0) {
@@ -510,6 +515,8 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.grid = 8 * a.per_xcd;
   a.block = c->sweep_block;
   a.dtick = c->lb_sigma_star >= 0.0 ? c->d_dtick : nullptr;
+  // random sequential order: K = SplitMix64(SplitMix64(seed) ^ step)
+  a.rkey = c->order_random ? rand_mix(rand_mix(c->rand_seed) ^ (unsigned long long)c->step) : 0ull;
   a.drow = c->drow;
   a.ddesc = c->ddesc;
   a.nc = c->nc;
@@ -538,8 +545,15 @@ hipError_t cd_launch_solve_init(cd_ctx* c, int limit) {
   return hipGetLastError();
 }
 
+// LDS of the random order's draws and ranked slots (12 bytes per contact of
+// the largest domain, rounded up)
+size_t cd_random_lds(cd_ctx* c) {
+  return c->order_random ? ((size_t)16 * std::max(c->st_ds.max_contacts, 1) + 31) / 32 * 32 : 0;
+}
+
 static size_t block_lds(cd_ctx* c) {
-  return c->sweep_global ? 0 : (c->sweep_stage ? c->sweep_lds_stage : c->sweep_lds);
+  return (c->sweep_global ? 0 : (c->sweep_stage ? c->sweep_lds_stage : c->sweep_lds)) +
+         cd_random_lds(c);
 }
 
 // Workgroups of kernel k resident per CU at this width and dynamic LDS
@@ -599,8 +613,10 @@ void cd_sweep_mode(cd_ctx* c) {
   // separate decision workgroup runs alongside the domains and workgroup 0
   // would only become the slowest one.
   const int64_t domains = (int64_t)8 * ((c->P + 7) / 8);
-  c->sweep_stage = cd_stage_pick(c->dim, c->sweep_block, c->sweep_lds, c->sweep_lds_stage,
-                                 domains + 1, domains + 1, c->num_cu, c->max_lds, false);
+  const size_t extra = cd_random_lds(c);
+  c->sweep_stage = cd_stage_pick(c->dim, c->sweep_block, c->sweep_lds + extra,
+                                 c->sweep_lds_stage + extra, domains + 1, domains + 1, c->num_cu,
+                                 c->max_lds, false);
   if (c->sweep_stage && c->sweep_block >= 128) {
     const void* kf = c->dim == 2 ? (const void*)k_sweep<2, false, true, true>
                                  : (const void*)k_sweep<3, false, true, true>;
@@ -611,20 +627,20 @@ void cd_sweep_mode(cd_ctx* c) {
 
 // One sweep launch in the context's form (global records, staged with the
 // decision folded into workgroup 0, staged, register read-ahead).
-template <int DIM, bool MIXED, bool TIMED>
+template <int DIM, bool MIXED, bool TIMED, bool RAND = false>
 static void launch_sweep_form(cd_ctx* c, const SweepArgs& a, dim3 grid, dim3 block, size_t lds,
                               bool fold, int j) {
   if (c->sweep_global)
-    hipLaunchKernelGGL((k_sweep<DIM, true, false, false, MIXED, TIMED>), grid, block, 0,
-                       c->stream, a, j);
+    hipLaunchKernelGGL((k_sweep<DIM, true, false, false, MIXED, TIMED, RAND>), grid, block,
+                       RAND ? lds : 0, c->stream, a, j);
   else if (fold)
-    hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED, TIMED>), grid, block, lds,
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED, TIMED, RAND>), grid, block, lds,
                        c->stream, a, j);
   else if (c->sweep_stage)
-    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED, TIMED>), grid, block, lds,
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED, TIMED, RAND>), grid, block, lds,
                        c->stream, a, j);
   else
-    hipLaunchKernelGGL((k_sweep<DIM, false, false, false, MIXED, TIMED>), grid, block, lds,
+    hipLaunchKernelGGL((k_sweep<DIM, false, false, false, MIXED, TIMED, RAND>), grid, block, lds,
                        c->stream, a, j);
 }
 
@@ -632,7 +648,9 @@ template <int DIM>
 static void launch_sweep_dim(cd_ctx* c, const SweepArgs& a, dim3 grid, dim3 block, size_t lds,
                              bool fold, int j) {
   const bool timed = a.dtick != nullptr;
-  if (c->order_mixed) {
+  if (c->order_random) {
+    launch_sweep_form<DIM, false, false, true>(c, a, grid, block, lds, fold, j);
+  } else if (c->order_mixed) {
     if (timed) launch_sweep_form<DIM, true, true>(c, a, grid, block, lds, fold, j);
     else launch_sweep_form<DIM, true, false>(c, a, grid, block, lds, fold, j);
   } else {

@@ -613,18 +613,31 @@ __device__ inline void get_slot(const double* sl, int nct, int k, double mu0, bo
   c.kt = 1.0 / c.dwt;
 }
 
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the finaliser applied to
+// x plus the golden gamma.
+__host__ __device__ inline unsigned long long rand_mix(unsigned long long x) {
+  unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // One sweep of domain d (head h) by the calling workgroup: exchange, then
 // the colour-major update; accumulates the convergence test values of its
-// contacts.  GLOB: the particle records live in global scratch (domains too
+// contacts.  RAND: the random sequential order (Sec. 2.1) instead of the
+// colours: slot s draws rand_mix(jkey ^ s), jkey = rand_mix(K ^ j) of sweep
+// j, and thread 0 updates the domain's contacts one at a time by increasing
+// draw (equal draws by slot); the draws and the ranked slots take 12 bytes
+// of LDS per contact after the form's own staging.  GLOB: the particle records live in global scratch (domains too
 // large for LDS).  STAGE: the domain's contact data is copied to LDS
 // alongside the exchange (all its loads in flight at once) and the colours
 // read it from there; otherwise each thread reads its contact of the next
 // colour into registers one colour ahead.
-template <int DIM, bool GLOB, bool STAGE, bool MIXED = false, class Idle>
+template <int DIM, bool GLOB, bool STAGE, bool MIXED = false, bool RAND = false, class Idle>
 __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead& h,
                                     const double* rin, double* rout, double* lds, int* s_co,
                                     double* s_wu, long long& npass, double& maxd, double& sumr,
-                                    Idle&& idle) {
+                                    unsigned long long jkey, Idle&& idle) {
   static_assert(!(GLOB && STAGE), "staged contact data needs the particles in LDS");
   using L = Layout<DIM>;
   constexpr int REC = L::REC, PS = L::PS;
@@ -685,7 +698,7 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
       else entry_finish_staged<DIM>(a, rin, ps + l, ep, sp, l, sl, cs, nct);
     }
   } else {
-    if (ncol > c0) {
+    if (!RAND && ncol > c0) {
       // this thread's contact of the first sequential colour read ahead
       // (its latency overlaps the exchange); lanes without one read the
       // first slot
@@ -701,6 +714,37 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
     }
   }
   __syncthreads();
+  if (RAND) {
+    unsigned long long* key =
+        (unsigned long long*)(STAGE ? sl + (int64_t)slot_stage_doubles<DIM>(mu_slot) * nct
+                                    : (GLOB ? lds : lds + (int64_t)PS * np));
+    int* perm = (int*)(key + nct);
+    for (int k = tid; k < nct; k += nthr) key[k] = rand_mix(jkey ^ (unsigned long long)(cs + k));
+    __syncthreads();
+    for (int k = tid; k < nct; k += nthr) {
+      const unsigned long long kk = key[k];
+      int rank = 0;
+      for (int m = 0; m < nct; ++m) {
+        const unsigned long long km = key[m];
+        rank += (km < kk || (km == kk && m < k)) ? 1 : 0;
+      }
+      perm[rank] = k;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double mu0 = mu_slot ? 0.0 : a.mu_slot[0];
+      for (int q = 0; q < nct; ++q) {
+        const int k = perm[q];
+        SlotPre<DIM> c;
+        if (STAGE) get_slot<DIM>(sl, nct, k, mu0, mu_slot, c);
+        else fetch_slot<DIM, true>(a, rin, cs + k, c);
+        update_contact<DIM>(sp, s_wu, c, a.alpha, rout + (int64_t)(cs + k) * REC, npass, maxd,
+                            sumr);
+      }
+    }
+    idle();
+    return;
+  }
   if (STAGE) {
     const double mu0 = mu_slot ? 0.0 : a.mu_slot[0];
     if (MIXED) {
