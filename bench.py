@@ -28,7 +28,9 @@ workload's domains and with one domain (`sequential_comparison`: the extra
 sweeps of Sec. 4.4 and the observables of Sec. 4.5; `--sequential 0` skips
 it, outside the timed region either way).  Optional legs:
 `--mixed-experiment` (the mixed sequential/parallel update of Sec. 2.3:
-sweeps N_I(p) and the critical share p_c on a settled pile) and
+sweeps N_I(p) and the critical share p_c on a settled pile),
+`--order-experiment` (sweeps in colour-major, random sequential and Jacobi
+order on the chain of Fig. 13(a) and a pile, Sec. 4.4) and
 `--balance SIGMA` (adaptive load balancing of Sec. 3.3 in the timed steps,
 which then no longer measure the headline configuration).
 """
@@ -167,6 +169,65 @@ def mixed_experiment(torch, binding, inputs, cap=3000, settle=50, seed=2023):
             "procedure": "one step from zero forces, one domain, alpha=1e-6, at most "
                          f"{cap} sweeps; parallel contacts by pair number (seed {seed})",
             "rows": rows, "p_c": min(failing) if failing else None}
+
+
+def order_experiment(torch, binding, inputs, seeds=8):
+    """Sweeps of one cold-started time step in three update orders (Sec. 2.1,
+    Sec. 4.4): colour-major, random sequential (mean over `seeds` draws) and
+    parallel (Jacobi, the mixed update with p = 1).  On the compressed chain
+    of Fig. 13(a) (128 disks) at 1 to 16 domains: N_I(Jacobi) / N_I(random)
+    estimates D_s / D_p, and N_I(P) / N_I(1) of each order is set beside the
+    diffusion model 1 / (1 - (P/n)(1 - D_p/D_s)) with the paper's 1.53.  On a
+    64 x 64 disk pile (mu = 0.3): one domain and 16."""
+    import numpy as np
+
+    def sweeps(pk, P, order, seed=0, max_iter=200000):
+        prm = binding.make_params(2, pk.n_walls, mu=0.3, n_domains=P, max_iter=max_iter)
+        c = binding.Context(prm, pk, timing=0)
+        if order == "random":
+            c.set_random_order(True, seed)
+        elif order == "jacobi":
+            c.set_mixed_update(1.0, 0)
+        r = c.step()
+        c.close()
+        return int(r.iterations), int(r.status)
+
+    def mean_random(pk, P):
+        runs = [sweeps(pk, P, "random", s) for s in range(seeds)]
+        return float(np.mean([r[0] for r in runs])), max(r[1] for r in runs)
+
+    n = 128
+    chain = inputs.chain_2d(n, 1.0)
+    rows = []
+    for P in (1, 2, 4, 8, 16):
+        cm, st_cm = sweeps(chain, P, "colour")
+        rd, st_rd = mean_random(chain, P)
+        rows.append({"domains": P, "colour_major": cm, "random_mean": rd,
+                     "status": max(st_cm, st_rd),
+                     "model_ratio": 1.0 / (1.0 - (P / n) * (1.0 - 1.0 / 1.53))})
+        log(f"order experiment, chain P={P}: colour-major {cm}, random {rd:.1f}")
+    for r in rows:
+        r["colour_major_ratio"] = r["colour_major"] / rows[0]["colour_major"]
+        r["random_ratio"] = r["random_mean"] / rows[0]["random_mean"]
+    jac, st_j = sweeps(chain, 1, "jacobi")
+    pile = inputs.lattice_2d(64, 64, 1000)
+    pile_rows = []
+    for P in (1, 16):
+        cm, st_cm = sweeps(pile, P, "colour", max_iter=20000)
+        # one domain: a single thread per sweep walks all 4,800 contacts
+        runs = [sweeps(pile, P, "random", s, max_iter=20000) for s in range(2 if P == 1 else seeds)]
+        rd, st_rd = float(np.mean([r[0] for r in runs])), max(r[1] for r in runs)
+        pile_rows.append({"domains": P, "colour_major": cm, "random_mean": rd,
+                          "status": max(st_cm, st_rd)})
+        log(f"order experiment, 64x64 pile P={P}: colour-major {cm}, random {rd:.1f}")
+    return {
+        "chain": {"disks": n, "rows": rows, "jacobi_one_domain": jac, "jacobi_status": st_j,
+                  "ds_over_dp_estimate": jac / rows[0]["random_mean"],
+                  "ds_over_dp_paper": 1.53, "q_s_over_q_p_theory": 0.797 / 0.5},
+        "pile_64x64": pile_rows,
+        "procedure": "one step from zero forces, mu=0.3, alpha=1e-6; random order mean over "
+                     f"{seeds} seeds (2 on the one-domain pile)",
+    }
 
 
 def sequential_comparison(wl, pk, ctx, torch, binding, max_iter):
@@ -436,6 +497,8 @@ def main() -> int:
     ap.add_argument("--balance", type=float, default=-1.0, metavar="SIGMA",
                     help="adaptive load balancing (Sec. 3.3) with this threshold on sigma_T "
                          "(negative: off, the headline configuration)")
+    ap.add_argument("--order-experiment", action="store_true",
+                    help="sweeps in colour-major, random sequential and Jacobi order (Sec. 4.4)")
     ap.add_argument("--mixed-experiment", action="store_true",
                     help="also run the mixed-update experiment of Sec. 2.3 (N_I(p), p_c)")
     ap.add_argument("--sequential", type=int, default=1,
@@ -630,6 +693,8 @@ def main() -> int:
                     "place the cuts of every later rebuild (Sec. 3.3)"}
     if args.mixed_experiment:
         out["mixed_parallelness"] = mixed_experiment(torch, binding, inputs)
+    if args.order_experiment:
+        out["update_orders"] = order_experiment(torch, binding, inputs)
     if args.sequential and dim == 2:
         out["sequential_comparison"] = sequential_comparison(wl, pk, ctx, torch, binding,
                                                              args.sequential_max_iter)

@@ -756,7 +756,12 @@ int prep_phase2(cd_ctx* c) {
   // LDS staging per domain, 32-byte aligned; the static LDS of the sweep
   // kernels (colour offsets, reduction scratch) stays below 2 KiB
   const size_t lds = ((size_t)std::max(ds.max_lds, 8) + 31) / 32 * 32;
-  c->sweep_global = lds + 2048 > c->max_lds;
+  // the random order also keeps its draws and ranks in LDS (16 bytes per
+  // contact reserved): domains whose records do not fit beside them keep
+  // the records in global memory
+  const size_t rand_lds =
+      c->order_random ? ((size_t)16 * std::max(ds.max_contacts, 1) + 31) / 32 * 32 : 0;
+  c->sweep_global = lds + rand_lds + 2048 > c->max_lds;
   c->sweep_lds = c->sweep_global ? 0 : lds;
   // one workgroup per domain, wide enough to stage its contacts and gather
   // its particles in one pass (the work is latency-bound)

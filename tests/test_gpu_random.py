@@ -38,6 +38,16 @@ def test_random_single_domain_global_records():
     assert ctx.timing().global_records == 1
 
 
+def test_random_single_domain_records_move_to_global_memory():
+    """64x64 disks in one domain: the particle records (about 150 KB) fit in
+    LDS alone but not beside the draws and ranks, so the random order keeps
+    them in global memory; 10 sweeps."""
+    pk = inputs.lattice_2d(64, 64, 1000)
+    sim, ctx = _random_pair(pk, 15, mu=0.3, n_domains=1, fixed_iters=10)
+    compare_step(sim, ctx, "random one domain 64x64")
+    assert ctx.timing().global_records == 1
+
+
 def test_random_3d():
     pk = inputs.lattice_3d(12, 12, 10, 13, gravity=1.0, top_velocity=1e-3)
     sim, ctx = _random_pair(pk, 13, mu=0.5, n_domains=16, repartition_every=2, fixed_iters=40)
