@@ -23,6 +23,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------ */
 /* small vector helpers (component order fixed: 0, 1, 2)               */
@@ -341,6 +344,11 @@ typedef struct {
   uint64_t key;
   int64_t slot;
 } rand_slot;
+
+/* threads over which the domains of a sweep are spread (1: serial) */
+static int g_threads = 1;
+
+void cdref_set_threads(int threads) { g_threads = threads > 1 ? threads : 1; }
 
 static int rand_slot_cmp(const void* a, const void* b) {
   const rand_slot* x = (const rand_slot*)a;
@@ -813,11 +821,14 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
   double* Rprev = (double*)malloc(sizeof(double) * (size_t)(dim * ncc));
   double* Vg = (double*)malloc(sizeof(double) * (size_t)(dim * nn));
   double* Wg = (double*)malloc(sizeof(double) * (size_t)(dr * nn));
-  double* Vd = (double*)malloc(sizeof(double) * (size_t)(dim * nn));
-  double* Wd = (double*)malloc(sizeof(double) * (size_t)(dr * nn));
+  /* one private velocity copy per thread (domains run on `threads` threads) */
+  const int threads = g_threads;
+  double* Vd = (double*)malloc(sizeof(double) * (size_t)(dim * nn) * (size_t)threads);
+  double* Wd = (double*)malloc(sizeof(double) * (size_t)(dr * nn) * (size_t)threads);
   double* dtim = (double*)malloc(sizeof(double) * (size_t)nn);
   double* dtii = (double*)malloc(sizeof(double) * (size_t)nn);
-  rand_slot* ord = step_key ? (rand_slot*)malloc(sizeof(rand_slot) * (size_t)ncc) : NULL;
+  rand_slot* ord =
+      step_key ? (rand_slot*)malloc(sizeof(rand_slot) * (size_t)ncc * (size_t)threads) : NULL;
   if (!cc || !Rprev || !Vg || !Wg || !Vd || !Wd || !dtim || !dtii || (step_key && !ord)) {
     free(cc); free(Rprev); free(Vg); free(Wg); free(Vd); free(Wd); free(dtim); free(dtii);
     free(ord);
@@ -860,19 +871,40 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
     memcpy(Rprev, R, sizeof(double) * (size_t)(dim * nc));
     /* exchange: every particle's velocity from the forces of sweep j-1 */
     cdref_velocities(dim, n, dt, v, w, m, inertia, r, f, t, nc, ci, cj, normal, Rprev, Vg, Wg);
-    memcpy(Vd, Vg, sizeof(double) * (size_t)(dim * n));
-    memcpy(Wd, Wg, sizeof(double) * (size_t)(dr * n));
     /* each domain sweeps its native contacts sequentially on a private copy
-       of the velocities; other domains' contacts keep their sweep j-1 value */
+       of the velocities; other domains' contacts keep their sweep j-1 value.
+       The domains of a sweep are independent: with threads > 1 they are
+       spread over OpenMP threads, each with its own copy */
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 8) if (threads > 1)
+#endif
     for (int d = 0; d < P; ++d) {
+      int tid = 0;
+#ifdef _OPENMP
+      tid = omp_get_thread_num();
+#endif
+      double* Vt = Vd + (int64_t)tid * dim * nn;
+      double* Wt = Wd + (int64_t)tid * dr * nn;
+      rand_slot* od = ord ? ord + (int64_t)tid * ncc : NULL;
       const int64_t len = dom_start[d + 1] - dom_start[d];
+      /* the domain starts from the exchanged velocities of its bodies */
+      for (int64_t s = dom_start[d]; s < dom_start[d + 1]; ++s) {
+        int64_t c = slot_contact[s];
+        int64_t ends[2] = {ci[c], cj[c]};
+        for (int e = 0; e < 2; ++e) {
+          int64_t q = ends[e];
+          if (q >= n) continue;
+          for (int k = 0; k < dim; ++k) Vt[k * n + q] = Vg[k * n + q];
+          for (int k = 0; k < dr; ++k) Wt[k * n + q] = Wg[k * n + q];
+        }
+      }
       if (step_key) {
         /* this sweep's random order of the domain's contacts */
         for (int64_t q = 0; q < len; ++q) {
-          ord[q].slot = dom_start[d] + q;
-          ord[q].key = cdref_random_slot_key(*step_key, j, ord[q].slot);
+          od[q].slot = dom_start[d] + q;
+          od[q].key = cdref_random_slot_key(*step_key, j, od[q].slot);
         }
-        qsort(ord, (size_t)len, sizeof(rand_slot), rand_slot_cmp);
+        qsort(od, (size_t)len, sizeof(rand_slot), rand_slot_cmp);
       }
       /* pass 0: the domain's parallel contacts (Sec. 2.3) from the velocities
          of the exchange, their changes not applied in this sweep (the other
@@ -880,7 +912,7 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
          slot order or in the sweep's random order */
       for (int pass = parallel ? 0 : 1; pass < 2; ++pass)
       for (int64_t q = 0; q < len; ++q) {
-        int64_t s = step_key ? ord[q].slot : dom_start[d] + q;
+        int64_t s = step_key ? od[q].slot : dom_start[d] + q;
         int64_t c = slot_contact[s];
         const int par = parallel ? parallel[c] != 0 : 0;
         if (par != (pass == 0)) continue;
@@ -888,12 +920,12 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
         double nv[3], t1[3], t2[3];
         contact_frame(dim, normal, nc, c, nv, t1, t2);
         double Va[3] = {0, 0, 0}, Wa[3] = {0, 0, 0}, Vb[3] = {0, 0, 0}, Wb[3] = {0, 0, 0};
-        for (int k = 0; k < dim; ++k) Va[k] = Vd[k * n + a];
-        for (int k = 0; k < dr; ++k) Wa[k] = Wd[k * n + a];
+        for (int k = 0; k < dim; ++k) Va[k] = Vt[k * n + a];
+        for (int k = 0; k < dr; ++k) Wa[k] = Wt[k * n + a];
         double rb = 0.0;
         if (b < n) {
-          for (int k = 0; k < dim; ++k) Vb[k] = Vd[k * n + b];
-          for (int k = 0; k < dr; ++k) Wb[k] = Wd[k * n + b];
+          for (int k = 0; k < dim; ++k) Vb[k] = Vt[k * n + b];
+          for (int k = 0; k < dr; ++k) Wb[k] = Wt[k * n + b];
           rb = r[b];
         } else {
           for (int k = 0; k < dim; ++k) Vb[k] = wall_velocity[(b - n) * dim + k];
@@ -913,22 +945,11 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
         }
         if (dim == 2) dq[0] = dR1;
         else for (int k = 0; k < 3; ++k) dq[k] = dR1 * t2[k] - dR2 * t1[k];
-        for (int k = 0; k < dim; ++k) Vd[k * n + a] = Vd[k * n + a] - dtim[a] * dF[k];
-        for (int k = 0; k < dr; ++k) Wd[k * n + a] = Wd[k * n + a] - dtii[a] * (r[a] * dq[k]);
+        for (int k = 0; k < dim; ++k) Vt[k * n + a] = Vt[k * n + a] - dtim[a] * dF[k];
+        for (int k = 0; k < dr; ++k) Wt[k * n + a] = Wt[k * n + a] - dtii[a] * (r[a] * dq[k]);
         if (b < n) {
-          for (int k = 0; k < dim; ++k) Vd[k * n + b] = Vd[k * n + b] + dtim[b] * dF[k];
-          for (int k = 0; k < dr; ++k) Wd[k * n + b] = Wd[k * n + b] - dtii[b] * (r[b] * dq[k]);
-        }
-      }
-      /* the domain's private copy ends with the sweep: restore from Vg */
-      for (int64_t s = dom_start[d]; s < dom_start[d + 1]; ++s) {
-        int64_t c = slot_contact[s];
-        int64_t ends[2] = {ci[c], cj[c]};
-        for (int e = 0; e < 2; ++e) {
-          int64_t q = ends[e];
-          if (q >= n) continue;
-          for (int k = 0; k < dim; ++k) Vd[k * n + q] = Vg[k * n + q];
-          for (int k = 0; k < dr; ++k) Wd[k * n + q] = Wg[k * n + q];
+          for (int k = 0; k < dim; ++k) Vt[k * n + b] = Vt[k * n + b] + dtim[b] * dF[k];
+          for (int k = 0; k < dr; ++k) Wt[k * n + b] = Wt[k * n + b] - dtii[b] * (r[b] * dq[k]);
         }
       }
     }

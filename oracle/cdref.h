@@ -143,6 +143,10 @@ int cdref_solve_mixed(const cdref_params* p, int64_t n, const double* v, const d
  * `step` each domain updates its contacts one at a time in the order of
  * increasing draw SplitMix64(SplitMix64(K ^ j) ^ s), s the slot, equal draws
  * by slot, K = SplitMix64(SplitMix64(seed) ^ step). */
+/* Threads over which the domains of each sweep are spread (OpenMP; 1, the
+ * default, runs them one after another).  The domains of a sweep are
+ * independent, so the results do not depend on it. */
+void cdref_set_threads(int threads);
 uint64_t cdref_random_step_key(uint64_t seed, int64_t step);
 uint64_t cdref_random_slot_key(uint64_t step_key, int j, int64_t s);
 int cdref_solve_random(const cdref_params* p, int64_t n, const double* v, const double* w,

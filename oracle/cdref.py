@@ -25,7 +25,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-                               "-Wall", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+                               "-Wall", "-fPIC", "-fopenmp", "-shared", "-o", tmp, src, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -74,6 +74,8 @@ def lib():
                                         P, P, P, P, P, C.c_int, P, P, P, C.POINTER(Info), P]
         L.cdref_sim_set_mixed.argtypes = [P, C.c_double, C.c_uint64]
         L.cdref_sim_set_mixed.restype = None
+        L.cdref_set_threads.argtypes = [C.c_int]
+        L.cdref_set_threads.restype = None
         L.cdref_random_step_key.argtypes = [C.c_uint64, i64]
         L.cdref_random_step_key.restype = C.c_uint64
         L.cdref_random_slot_key.argtypes = [C.c_uint64, C.c_int, i64]
@@ -291,6 +293,11 @@ def solve(params: Params, pk, ci, cj, normal, gap, P: int, dom_start, slot, R0=N
     if hist is not None:
         hist = hist[:, :info.iterations]
     return R, info, hist
+
+
+def set_threads(threads: int) -> None:
+    """Spread the domains of each sweep over `threads` OpenMP threads."""
+    lib().cdref_set_threads(int(threads))
 
 
 def random_step_key(seed: int, step: int) -> int:
