@@ -30,7 +30,9 @@ it, outside the timed region either way).  Optional legs:
 `--mixed-experiment` (the mixed sequential/parallel update of Sec. 2.3:
 sweeps N_I(p) and the critical share p_c on a settled pile),
 `--order-experiment` (sweeps in colour-major, random sequential and Jacobi
-order on the chain of Fig. 13(a) and a pile, Sec. 4.4) and
+order on the chain of Fig. 13(a) and a pile, Sec. 4.4), `--random-order
+SEED` (the timed steps in the random sequential order of Sec. 2.1, which
+then no longer measure the headline configuration) and
 `--balance SIGMA` (adaptive load balancing of Sec. 3.3 in the timed steps,
 which then no longer measure the headline configuration).
 """
@@ -522,6 +524,9 @@ def main() -> int:
     ap.add_argument("--balance", type=float, default=-1.0, metavar="SIGMA",
                     help="adaptive load balancing (Sec. 3.3) with this threshold on sigma_T "
                          "(negative: off, the headline configuration)")
+    ap.add_argument("--random-order", type=int, default=-1, metavar="SEED",
+                    help="timed steps in the random sequential order (Sec. 2.1) instead of "
+                         "colour-major; the headline configuration is colour-major")
     ap.add_argument("--order-experiment", action="store_true",
                     help="sweeps in colour-major, random sequential and Jacobi order (Sec. 4.4)")
     ap.add_argument("--mixed-experiment", action="store_true",
@@ -637,6 +642,8 @@ def main() -> int:
                    block=args.block)
     if args.balance >= 0.0:
         ctx.set_load_balance(args.balance)
+    if args.random_order >= 0:
+        ctx.set_random_order(True, args.random_order)
     sigmas = []
     torch.cuda.synchronize()
     sweeps = 0
@@ -674,7 +681,8 @@ def main() -> int:
     bytes_per_sweep = bytes_sweeps / max(executed, 1)
     # no per-sweep events (--time-every 0): no kernel duration, no roofline
     achieved = bytes_per_sweep / avg_sweep_s / 1e9 if sweeps and avg_sweep_s > 0 else None
-    traffic = measured_traffic(args.traffic_json)
+    # the counters were taken on the colour-major sweep
+    traffic = measured_traffic(args.traffic_json) if args.random_order < 0 else None
     out = {
         "metric": METRIC,
         "value": updates / elapsed,
@@ -705,9 +713,13 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
                      "traffic": traffic,
                      "kernel": (f"k_solve<{dim}>" if args.solve_mode == 0 else
-                                f"k_sweep<{dim}, {'staged' if tm.staged else 'register'}>"),
+                                f"k_sweep<{dim}, {'staged' if tm.staged else 'register'}"
+                                f"{', random order' if args.random_order >= 0 else ''}>"),
                      "bytes_per_sweep": bytes_per_sweep},
     }
+    if args.random_order >= 0:
+        out["update_order"] = (f"random sequential (Sec. 2.1), seed {args.random_order}: one "
+                               "thread per domain walks its contacts in a fresh draw each sweep")
     if args.balance >= 0.0:
         out["load_balance"] = {
             "threshold": args.balance,
