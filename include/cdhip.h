@@ -199,7 +199,7 @@ int cd_set_launch(cd_ctx* ctx, int block_threads);
  * none.  CD_EINVAL for p = NaN or together with the adjoint. */
 int cd_set_mixed_update(cd_ctx* ctx, double p, unsigned long long seed);
 
-/* Random sequential order (Sec. 2.1) from the next solve on (on != 0): in
+/* Random sequential order (Sec. 2.1) from the next step on (on != 0): in
  * every sweep each domain updates its own contacts one at a time in a
  * random order drawn afresh for that sweep, instead of colour by colour.
  * Slot s (the contact's position in the domain-major, colour-major slot
@@ -210,8 +210,11 @@ int cd_set_mixed_update(cd_ctx* ctx, double p, unsigned long long seed);
  * foreign contacts, exchange between sweeps) are unchanged.  One thread per
  * domain runs the updates, so a sweep is much slower than the colour-major
  * one: the mode is for comparing orders (Sec. 4.4), not for throughput.
- * Needs 12 bytes of LDS per contact of the largest domain beyond the
- * sweep's own staging (CD_ECAPACITY from the step otherwise).  CD_EINVAL
+ * Needs 12 bytes of LDS per contact of the largest domain: the step's
+ * preparation keeps the particle records in global memory when they do not
+ * fit beside them, and the solve returns CD_ECAPACITY when the draws alone
+ * do not fit (or when the mode was switched on after cd_prepare, whose
+ * sizing did not include them).  CD_EINVAL
  * together with the mixed update, the adjoint or load measurement; the
  * one-launch solve (mode 0) and the batch refuse it.  on = 0: colour-major
  * (default). */
