@@ -152,3 +152,18 @@ def test_sim_uses_the_step_index(oracle):
     args = (prm, q, c["ci"], c["cj"], c["normal"], c["gap"], 2, ds, c["slot"])
     np.testing.assert_array_equal(oracle.solve(*args, random_order=(3, 1))[0], c["R"])
     assert np.abs(oracle.solve(*args, random_order=(3, 0))[0] - c["R"]).max() > 1e-9
+
+
+def test_frictionless_converged_forces_do_not_depend_on_the_order(oracle):
+    """Without friction these piles (about 1.15 contacts per disk) have one
+    solution: a converged solve (4,000 sweeps) gives the same forces in the
+    colour-major order and in random orders of two seeds."""
+    pk = inputs.lattice_2d(24, 24, 46)
+    ci, cj, normal, gap, slot, ds = _setup(oracle, pk, 4)
+    prm = oracle.make_params(2, pk.n_walls, n_domains=4, fixed_iters=4000, mu=0.0)
+    ref, _, _ = oracle.solve(prm, pk, ci, cj, normal, gap, 4, ds, slot)
+    scale = np.abs(ref).max()
+    for seed in (1, 2):
+        R, _, _ = oracle.solve(prm, pk, ci, cj, normal, gap, 4, ds, slot, random_order=(seed, 0))
+        assert np.abs(R - ref).max() <= 1e-12 * scale
+
