@@ -55,6 +55,17 @@ def test_random_3d():
         compare_step(sim, ctx, f"random 3D step{s}")
 
 
+def test_random_full_size_spheres_folded_decision():
+    """128x128x64 spheres, 16,384 domains: more workgroups than fit at once,
+    so the stop decision is folded into workgroup 0 beside the random
+    order's serial walk; 3 sweeps."""
+    pk = inputs.config("spheres_1m")
+    sim, ctx = _random_pair(pk, 16, mu=0.5, n_domains=16384, repartition_every=10,
+                            fixed_iters=3)
+    compare_step(sim, ctx, "random 1m spheres fixed3")
+    assert ctx.timing().staged == 2
+
+
 @pytest.mark.parametrize("P", [1, 4])
 def test_random_chain_to_the_tolerance(P):
     """The compressed chain of Fig. 13(a), 128 disks: the same sweep count."""
