@@ -1310,6 +1310,13 @@ int64_t cdref_sim_contacts(const cdref_sim* s, int64_t cap, int32_t* ci, int32_t
   return nc;
 }
 
+void cdref_sim_box(const cdref_sim* s, double* lo, double* hi) {
+  for (int k = 0; k < s->p.dim; ++k) {
+    lo[k] = s->lo[k];
+    hi[k] = s->hi[k];
+  }
+}
+
 void cdref_sim_tree(const cdref_sim* s, int32_t* node_axis, double* node_cut,
                     int32_t* node_child, int32_t* node_leaf) {
   int nodes = 2 * s->p.n_domains - 1;

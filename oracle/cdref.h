@@ -231,6 +231,9 @@ int cdref_sim_set_random(cdref_sim* s, int on, uint64_t seed);
  * NULL: back to leaf counts */
 int cdref_sim_set_capacity(cdref_sim* s, const double* capacity);
 /* the current tree (2P-1 nodes) */
+/* The simulation box after the steps so far (dim entries each): a face
+ * lying on an axis-aligned wall moves with that wall. */
+void cdref_sim_box(const cdref_sim* s, double* lo, double* hi);
 void cdref_sim_tree(const cdref_sim* s, int32_t* node_axis, double* node_cut,
                     int32_t* node_child, int32_t* node_leaf);
 

@@ -105,6 +105,8 @@ def lib():
         L.cdref_sim_state.restype = None
         L.cdref_sim_contacts.argtypes = [P, i64, P, P, P, P, P, P, P, P]
         L.cdref_sim_contacts.restype = i64
+        L.cdref_sim_box.argtypes = [P, P, P]
+        L.cdref_sim_box.restype = None
         L.cdref_sim_tree.argtypes = [P, P, P, P, P]
         L.cdref_sim_tree.restype = None
         _lib = L
@@ -379,6 +381,12 @@ class Sim:
         wo = np.zeros(max(self.params.n_walls, 1))
         self.L.cdref_sim_state(self.h, _p(x), _p(v), _p(w), _p(wo))
         return x, v, w, wo[:self.params.n_walls]
+
+    def box(self):
+        lo = np.zeros(self.dim)
+        hi = np.zeros(self.dim)
+        self.L.cdref_sim_box(self.h, _p(lo), _p(hi))
+        return lo, hi
 
     def contacts(self):
         nc = self.L.cdref_sim_contacts(self.h, 0, None, None, None, None, None, None, None, None)

@@ -186,3 +186,52 @@ def frictionless_lcp_2d(pk, ci, cj, normal, gap, dt):
     b = -scipy.linalg.solve_triangular(L, q, lower=True)
     Rn, _ = scipy.optimize.nnls(L.T, b, maxiter=100 * len(q))
     return Rn
+
+
+def orthonormal_frames_3d(normal: np.ndarray):
+    """A right-handed orthonormal frame (n, t1, t2) per contact by
+    Gram-Schmidt from the coordinate axis least aligned with n (any
+    tangent basis serves: the force law is isotropic in the tangent plane)."""
+    n = normal.T
+    frames = []
+    for c in range(n.shape[0]):
+        e = np.zeros(3)
+        e[np.argmin(np.abs(n[c]))] = 1.0
+        t1 = e - (e @ n[c]) * n[c]
+        t1 /= np.linalg.norm(t1)
+        t2 = np.cross(n[c], t1)
+        frames.append((n[c].copy(), t1, t2))
+    return frames
+
+
+def delassus_3d(pk, ci, cj, frames, dt):
+    """3D analogue of delassus_2d: generalized velocities per body
+    (vx, vy, vz, wx, wy, wz); contact rows (u_n, u_t1, u_t2) of the relative
+    velocity of the contact points, body 2 minus body 1, with lever arms
+    r_a n on body 1 and -r_b n on body 2: (W x rho) . e = W . (rho x e)."""
+    N = pk.n
+    nc = len(ci)
+    J = np.zeros((3 * nc, 6 * N))
+    uw = np.zeros(3 * nc)
+    for c in range(nc):
+        a, b = int(ci[c]), int(cj[c])
+        n = frames[c][0]
+        for k, e in enumerate(frames[c]):
+            row = 3 * c + k
+            J[row, 6 * a:6 * a + 3] -= e
+            J[row, 6 * a + 3:6 * a + 6] -= np.cross(pk.r[a] * n, e)
+            if b < N:
+                J[row, 6 * b:6 * b + 3] += e
+                J[row, 6 * b + 3:6 * b + 6] += np.cross(-pk.r[b] * n, e)
+            else:
+                uw[row] = pk.wall_velocity[b - N] @ e
+    minv = np.zeros(6 * N)
+    for k in range(3):
+        minv[k::6] = 1.0 / pk.m
+        minv[3 + k::6] = 1.0 / pk.inertia
+    q0 = np.zeros(6 * N)
+    for k in range(3):
+        q0[k::6] = pk.v[k] + dt * pk.f[k] / pk.m
+        q0[3 + k::6] = pk.w[k] + dt * pk.t[k] / pk.inertia
+    A = dt * (J * minv) @ J.T
+    return A, J @ q0 + uw, J, minv, q0
