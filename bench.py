@@ -1,21 +1,20 @@
 """Benchmark of the contact-force solve on one MI355X.
 
-`--workload disks_262k` (default) is the headline configuration below;
-`--workload spheres_1m` runs the 3D one (1,048,576 spheres on a 128x128x64
-jittered simple-cubic lattice, mu = 0.5, top wall driven down at 1e-3,
-16,384 domains, 50 steps).
+Headline workload (`--workload spheres_1m`, the default): 3D spheres,
+N = 1,048,576 on a 128x128x64 jittered simple-cubic lattice (spacing 2.05,
+radii U[0.8, 1.2], jitter +-0.05), mass ~ r^3, Coulomb cone mu = 0.5,
+dt = 1e-3, no gravity, top wall driven down at 1e-3 (uniaxial compression),
+initial velocities N(0, 0.01^2), hierarchical bisection balanced by contact
+count into 16,384 domains, repartition every 10 steps, tolerance
+alpha = 1e-6 on the local test (I), at most 2,000 sweeps per step.
 
-Headline workload: 2D disks, N = 262,144 on a 512x512
-jittered triangular lattice (spacing 2.05, radii U[0.8, 1.2], jitter +-0.05),
-rigid box walls, gravity 1, mass ~ r^2, mu = 0.3, dt = 1e-3, initial
-velocities N(0, 0.01^2), hierarchical bisection balanced by contact count
-into 2,048 domains, repartition every 10 steps, tolerance alpha = 1e-6 on the
-local test (I), at most 2,000 sweeps per step, 100 time steps of settling
-under gravity.  With 4,096 domains (about 64 disks each) boundary contacts
-outnumber bulk ones and the mixed parallel/sequential update diverges on
-this packing in the second step (the instability of Sec. 2.3; the CPU oracle
-diverges identically), so the benchmark uses the largest stable power of
-two.  A "step" is one full time step: detection, warm start,
+With the headline the line also carries `other_workloads`: the 2D
+workload of 262,144 disks (512x512 jittered triangular lattice, gravity 1,
+mu = 0.3) timed at 2,048 domains, and the outcome of the same packing at
+the 4,096 domains of its stated configuration, where the domain-wise update
+diverges (the instability of Sec. 2.3; the CPU oracle diverges identically).
+`--workload disks_262k`, `batch512` and `adjoint65k` time those workloads
+on their own.  A "step" is one full time step: detection, warm start,
 partition, order, the sweeps to convergence and the Euler update.
 
 The JSON line reports whole-step contact updates/s (sum over steps of sweeps
@@ -25,12 +24,12 @@ durations of the sweep launches that did work, from HIP events on the
 library's stream) and the CPU oracle on a bounded sample.  For the 2D
 workloads it also solves the final state once more from zero forces with the
 workload's domains and with one domain (`sequential_comparison`: the extra
-sweeps of Sec. 4.4 and the observables of Sec. 4.5; `--sequential 0` skips
+sweeps of Sec. 4.3 and the observables of Sec. 4.4; `--sequential 0` skips
 it, outside the timed region either way).  Optional legs:
 `--mixed-experiment` (the mixed sequential/parallel update of Sec. 2.3:
 sweeps N_I(p) and the critical share p_c on a settled pile),
 `--order-experiment` (sweeps in colour-major, random sequential and Jacobi
-order on the chain of Fig. 13(a) and a pile, Sec. 4.4), `--random-order
+order on the chain of Fig. 13(a) and a pile, Sec. 4.3), `--random-order
 SEED` (the timed steps in the random sequential order of Sec. 2.1, which
 then no longer measure the headline configuration) and
 `--balance SIGMA` (adaptive load balancing of Sec. 3.3 in the timed steps,
@@ -175,7 +174,7 @@ def mixed_experiment(torch, binding, inputs, cap=3000, settle=50, seed=2023):
 
 def order_experiment(torch, binding, inputs, seeds=8):
     """Sweeps of one cold-started time step in three update orders (Sec. 2.1,
-    Sec. 4.4): colour-major, random sequential (mean over `seeds` draws) and
+    Sec. 4.3): colour-major, random sequential (mean over `seeds` draws) and
     parallel (Jacobi, the mixed update with p = 1).  On the compressed chain
     of Fig. 13(a) (128 disks) at 1 to 16 domains: N_I(Jacobi) / N_I(random)
     estimates D_s / D_p, and N_I(P) / N_I(1) of each order is set beside the
@@ -236,7 +235,7 @@ def sequential_comparison(wl, pk, ctx, torch, binding, max_iter):
     """One time step solved from scratch (cold start) on the state the timed
     steps ended in, with the workload's domains and with a single domain
     (the plain sequential solve): the extra sweeps of the domain-wise solve,
-    N_I(P) / N_I(1) (Sec. 4.4), and the macroscopic observables of Sec. 4.5."""
+    N_I(P) / N_I(1) (Sec. 4.3), and the macroscopic observables of Sec. 4.4."""
     from paper_1104_3516_amd import analysis
     q = pk.copy()
     x, v, w = (t.cpu().numpy() for t in ctx.state())
@@ -257,7 +256,7 @@ def sequential_comparison(wl, pk, ctx, torch, binding, max_iter):
     P = wl["domains"]
     d = analysis.compare(q, runs[1], runs[P])
     frac = boundary_fraction(q.n, runs[P]["c"])
-    # Sec. 4.4: N_I ~ 1 / D with D = D_p p + D_s (1 - p), D_s / D_p = 1.53
+    # Sec. 4.3: N_I ~ 1 / D with D = D_p p + D_s (1 - p), D_s / D_p = 1.53
     model = 1.0 / (1.0 - frac * (1.0 - 1.0 / 1.53))
     return {
         "state": "the positions and velocities after the timed steps, forces from zero",
@@ -266,7 +265,7 @@ def sequential_comparison(wl, pk, ctx, torch, binding, max_iter):
         "extra_sweep_factor": runs[P]["it"] / max(runs[1]["it"], 1),
         "boundary_contact_fraction": frac,
         "model_extra_sweep_factor": model,
-        "model": "1 / (1 - p (1 - D_p / D_s)), D_s / D_p = 1.53 fitted in Sec. 4.4, p the "
+        "model": "1 / (1 - p (1 - D_p / D_s)), D_s / D_p = 1.53 fitted in Sec. 4.3, p the "
                  "boundary contact fraction",
         "mean_stress_rel_diff": d["mean_stress"], "sigma_yy_strips_rel_diff": d["strips"],
         "orientation_tv_distance": d["orientation_tv"],
@@ -503,8 +502,13 @@ def cpu_baseline_batch(packs, mus, target, sweeps: int) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="disks_262k", choices=sorted(WORKLOADS),
-                    help="disks_262k (the headline configuration) or spheres_1m (3D)")
+    ap.add_argument("--workload", default="spheres_1m", choices=sorted(WORKLOADS),
+                    help="spheres_1m (the headline: 3D, 1,048,576 spheres, 16,384 domains), "
+                         "disks_262k, batch512 or adjoint65k")
+    ap.add_argument("--extra", type=int, default=1,
+                    help="with the headline workload also time disks_262k (2,048 domains) and "
+                         "report the 4,096-domain configuration's divergence (0: skip)")
+    ap.add_argument("--extra-steps", type=int, default=20)
     ap.add_argument("--steps", type=int, default=0, help="time steps (0: the workload's own)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sweeps", type=int, default=-1,
@@ -528,7 +532,7 @@ def main() -> int:
                     help="timed steps in the random sequential order (Sec. 2.1) instead of "
                          "colour-major; the headline configuration is colour-major")
     ap.add_argument("--order-experiment", action="store_true",
-                    help="sweeps in colour-major, random sequential and Jacobi order (Sec. 4.4)")
+                    help="sweeps in colour-major, random sequential and Jacobi order (Sec. 4.3)")
     ap.add_argument("--mixed-experiment", action="store_true",
                     help="also run the mixed-update experiment of Sec. 2.3 (N_I(p), p_c)")
     ap.add_argument("--sequential", type=int, default=1,
@@ -627,23 +631,52 @@ def main() -> int:
         print(json.dumps(out), flush=True)
         return 0
     pk = inputs.config(wl["config"])
-    dim = wl["dim"]
+    out = run_single(args, wl, pk, torch, binding, inputs, steps=args.steps,
+                     warmup=args.warmup, time_every=args.time_every,
+                     traffic_json=args.traffic_json, random_order=args.random_order,
+                     balance=args.balance)
+    if args.mixed_experiment:
+        out["mixed_parallelness"] = mixed_experiment(torch, binding, inputs)
+    if args.order_experiment:
+        out["update_orders"] = order_experiment(torch, binding, inputs)
+    ctx = out.pop("_ctx")
+    if args.sequential and wl["dim"] == 2:
+        out["sequential_comparison"] = sequential_comparison(wl, pk, ctx, torch, binding,
+                                                             args.sequential_max_iter)
+    ctx.close()
+    if args.workload == "spheres_1m" and args.extra:
+        out["other_workloads"] = extra_workloads(args, torch, binding, inputs)
+    if args.cpu_sweeps > 0:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(wl, pk, args.cpu_sweeps)
+        out["cpu_parallel"] = cpu_parallel(wl, pk, args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+    return 0
 
+
+def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, traffic_json,
+               random_order=-1, balance=-1.0, n_domains=None, quiet=False) -> dict:
+    """Time `steps` whole time steps of one context after `warmup` steps on a
+    throwaway context; returns the JSON fields of the line (the context of
+    the timed steps under "_ctx", still open)."""
+    dim = wl["dim"]
+    P = wl["domains"] if n_domains is None else n_domains
     # warm-up on a throwaway context (kernels loaded, allocations made)
-    if args.warmup > 0:
-        ctx = make_ctx(wl, pk, binding, solve_mode=args.solve_mode, block=args.block)
-        for s in range(args.warmup):
+    if warmup > 0:
+        ctx = make_ctx(wl, pk, binding, solve_mode=args.solve_mode, block=args.block,
+                       n_domains=P)
+        for s in range(warmup):
             r = ctx.step()
             log(f"warmup step {s}: {r.iterations} sweeps, {r.n_contacts} contacts")
         ctx.close()
         del ctx
 
-    ctx = make_ctx(wl, pk, binding, timing=args.time_every, solve_mode=args.solve_mode,
-                   block=args.block)
-    if args.balance >= 0.0:
-        ctx.set_load_balance(args.balance)
-    if args.random_order >= 0:
-        ctx.set_random_order(True, args.random_order)
+    ctx = make_ctx(wl, pk, binding, timing=time_every, solve_mode=args.solve_mode,
+                   block=args.block, n_domains=P)
+    if balance >= 0.0:
+        ctx.set_load_balance(balance)
+    if random_order >= 0:
+        ctx.set_random_order(True, random_order)
     sigmas = []
     torch.cuda.synchronize()
     sweeps = 0
@@ -655,7 +688,7 @@ def main() -> int:
     executed = 0
     timed = 0
     t0 = time.perf_counter()
-    for s in range(args.steps):
+    for s in range(steps):
         r = ctx.step()
         tm = ctx.timing()
         sweeps += r.iterations
@@ -667,9 +700,9 @@ def main() -> int:
         bytes_sweeps += tm.sweeps_executed * (BYTES[dim][0] * r.n_contacts +
                                               BYTES[dim][1] * pk.n)
         maxiter_steps += int(r.status == binding.MAXITER)
-        if args.balance >= 0.0:
+        if balance >= 0.0:
             sigmas.append(ctx.domain_times()[1])
-        if s % 10 == 0 or s == args.steps - 1:
+        if s % 10 == 0 or s == steps - 1:
             log(f"step {s}: {r.iterations} sweeps, {r.n_contacts} contacts, status {r.status}, "
                 f"solve {tm.solve_ms:.2f} ms, sweep kernels {tm.sweep_kernel_ms:.2f} ms "
                 f"({tm.sweep_launches} launches)")
@@ -682,26 +715,26 @@ def main() -> int:
     # no per-sweep events (--time-every 0): no kernel duration, no roofline
     achieved = bytes_per_sweep / avg_sweep_s / 1e9 if sweeps and avg_sweep_s > 0 else None
     # the counters were taken on the colour-major sweep
-    traffic = measured_traffic(args.traffic_json) if args.random_order < 0 else None
+    traffic = measured_traffic(traffic_json) if random_order < 0 else None
     out = {
         "metric": METRIC,
         "value": updates / elapsed,
         "unit": "contact updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl["text"], "n_particles": pk.n, "n_domains": wl["domains"],
-                   "time_steps": args.steps},
+        "config": {"workload": wl["text"], "n_particles": pk.n, "n_domains": P,
+                   "time_steps": steps},
         "sweeps_total": sweeps,
-        "sweeps_per_step": sweeps / args.steps,
+        "sweeps_per_step": sweeps / steps,
         "steps_at_sweep_cap": maxiter_steps,
-        "solve_ms_per_step": solve_ms / args.steps,
+        "solve_ms_per_step": solve_ms / steps,
         "solve_contact_updates_per_s": updates / (solve_ms / 1e3) if solve_ms > 0 else None,
         "sweep_kernel_us": 1e6 * avg_sweep_s if avg_sweep_s > 0 else None,
         "sweeps_executed": executed,
@@ -712,36 +745,61 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
                      "traffic": traffic,
-                     "kernel": (f"k_solve<{dim}>" if args.solve_mode == 0 else
-                                f"k_sweep<{dim}, {'staged' if tm.staged else 'register'}"
-                                f"{', random order' if args.random_order >= 0 else ''}>"),
+                     "kernel": (f"k_sweep<{dim}>, one launch per step" if args.solve_mode == 0
+                                else f"k_sweep<{dim}, {'staged' if tm.staged else 'register'}"
+                                f"{', random order' if random_order >= 0 else ''}>"),
                      "bytes_per_sweep": bytes_per_sweep},
+        "_ctx": ctx,
     }
-    if args.random_order >= 0:
-        out["update_order"] = (f"random sequential (Sec. 2.1), seed {args.random_order}: one "
+    if random_order >= 0:
+        out["update_order"] = (f"random sequential (Sec. 2.1), seed {random_order}: one "
                                "thread per domain walks its contacts in a fresh draw each sweep")
-    if args.balance >= 0.0:
+    if balance >= 0.0:
         out["load_balance"] = {
-            "threshold": args.balance,
+            "threshold": balance,
             "sigma_t_first_step": sigmas[0] if sigmas else None,
             "sigma_t_last_step": sigmas[-1] if sigmas else None,
             "sigma_t_mean": sum(sigmas) / len(sigmas) if sigmas else None,
             "note": "per-domain sweep times measured in the timed steps; capacities n_i / T_i "
                     "place the cuts of every later rebuild (Sec. 3.3)"}
-    if args.mixed_experiment:
-        out["mixed_parallelness"] = mixed_experiment(torch, binding, inputs)
-    if args.order_experiment:
-        out["update_orders"] = order_experiment(torch, binding, inputs)
-    if args.sequential and dim == 2:
-        out["sequential_comparison"] = sequential_comparison(wl, pk, ctx, torch, binding,
-                                                             args.sequential_max_iter)
-    if args.cpu_sweeps > 0:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, pk, args.cpu_sweeps)
-        out["cpu_parallel"] = cpu_parallel(wl, pk, args.cpu_sweeps)
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def extra_workloads(args, torch, binding, inputs) -> dict:
+    """Beside the 3D headline: the 2D 262,144-disk workload at 2,048 domains
+    (timed like the headline, fewer steps) and the same packing at the 4,096
+    domains of its stated configuration, which diverges (the step and the
+    status at which it fails are reported)."""
+    wl = WORKLOADS["disks_262k"]
+    pk = inputs.config(wl["config"])
+    res = {}
+    log("extra workload: disks_262k at 2,048 domains ...")
+    o = run_single(args, wl, pk, torch, binding, inputs, steps=args.extra_steps, warmup=2,
+                   time_every=args.time_every,
+                   traffic_json=os.path.join(ROOT, "profiles", wl["traffic"]))
+    o.pop("_ctx").close()
+    keep = ("value", "unit", "ms_per_step", "steps", "sweeps_per_step", "steps_at_sweep_cap",
+            "sweep_kernel_us", "roofline", "config")
+    res["disks_262k"] = {k: o[k] for k in keep}
+    log("extra workload: disks_262k at 4,096 domains (the stated configuration) ...")
+    ctx = make_ctx(wl, pk, binding, timing=0, n_domains=4096)
+    steps = []
+    failed = None
+    for s in range(10):
+        try:
+            r = ctx.step()
+            steps.append({"step": s, "sweeps": int(r.iterations), "status": int(r.status)})
+        except binding.CDError as err:
+            failed = {"step": s, "status": int(err.code), "error": str(err)}
+            break
+    torch.cuda.synchronize()
     ctx.close()
-    return 0
+    res["disks_262k_4096_domains"] = {
+        "result": "fails" if failed else "runs", "steps_completed": steps, "failure": failed,
+        "note": ("the domain-wise update of this packing at 4,096 domains (about 74 contacts "
+                 "per domain) diverges; the CPU oracle with the same partition diverges "
+                 "identically, so the 2D line above uses 2,048 domains")}
+    return res
 
 
 if __name__ == "__main__":

@@ -209,8 +209,8 @@ int cd_set_mixed_update(cd_ctx* ctx, double p, unsigned long long seed);
  * increasing draw, equal draws by slot.  The domain semantics (frozen
  * foreign contacts, exchange between sweeps) are unchanged.  One thread per
  * domain runs the updates, so a sweep is much slower than the colour-major
- * one: the mode is for comparing orders (Sec. 4.4), not for throughput.
- * Needs 12 bytes of LDS per contact of the largest domain: the step's
+ * one: the mode is for comparing orders (Sec. 4.3), not for throughput.
+ * Needs 16 bytes of LDS per contact of the largest domain: the step's
  * preparation keeps the particle records in global memory when they do not
  * fit beside them, and the solve returns CD_ECAPACITY when the draws alone
  * do not fit (or when the mode was switched on after cd_prepare, whose

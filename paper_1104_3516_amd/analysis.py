@@ -1,5 +1,5 @@
 """Macroscopic observables of a solved step, for comparing solves that differ
-only in their domain decomposition (Sec. 4.5): the mean stress tensor, the
+only in their domain decomposition (Sec. 4.4): the mean stress tensor, the
 sigma_yy profile in horizontal strips of width 2 r_max, and the histogram of
 contact force orientations over [0, pi) in 18 bins.
 

@@ -140,6 +140,7 @@ class Context:
             raise RuntimeError("libcdhip needs a ROCm GPU; none is visible")
         self.torch = torch
         self.L = lib()
+        self.solves = 0     # solves started on this context (stamps autograd records)
         self.device = torch.device(device)
         self.params = params
         self.dim = packing.dim
@@ -200,6 +201,7 @@ class Context:
 
     def step(self) -> Result:
         res = Result()
+        self.solves += 1
         self._check(self.L.cd_step(self.h, C.byref(res)))
         return res
 
@@ -282,11 +284,16 @@ class Context:
 
     def set_contact_mu(self, mu):
         mu = mu.detach().to(self.device, self.torch.float64).contiguous()
+        nc = self.num_contacts()
+        if mu.numel() != nc:
+            raise ValueError(f"one friction coefficient per contact of the prepared list: "
+                             f"{mu.numel()} given, {nc} contacts")
         self._mu_keep = mu
         self._check(self.L.cd_set_contact_mu(self.h, _ptr(mu)))
 
     def solve(self) -> Result:
         res = Result()
+        self.solves += 1
         self._check(self.L.cd_solve(self.h, C.byref(res)))
         return res
 
@@ -336,6 +343,9 @@ class Context:
         """dL/dmu (n_c), dL/dv (dim x N), dL/dw (dr x N) of the last recorded solve."""
         torch = self.torch
         nc = self.num_contacts()
+        if tuple(dL_dR.shape) != (self.dim, nc):
+            raise ValueError(f"dL_dR must be ({self.dim}, {nc}) for the recorded solve, "
+                             f"got {tuple(dL_dR.shape)}")
         g = dL_dR.detach().to(self.device, torch.float64).contiguous()
         dmu = torch.zeros(max(nc, 1), dtype=torch.float64, device=self.device)
         dv = torch.zeros((self.dim, self.n), dtype=torch.float64, device=self.device)
@@ -356,15 +366,24 @@ def _forces_function():
 
         @staticmethod
         def forward(fctx, mu, v, w, context):
+            if not context.params.skin >= 0.0:
+                # with the width 2 v_max dt the list would depend on v
+                raise ValueError("contact_forces needs a fixed boundary width (params.skin >= 0)")
+            if context.params.fixed_iters <= 0:
+                raise ValueError("contact_forces needs a fixed sweep count (params.fixed_iters)")
             context.reset(v, w)
             context.prepare()
             context.set_contact_mu(mu)
             context.solve()
             fctx.context = context
+            fctx.solve_stamp = context.solves
             return context.contacts()["R"].clone()
 
         @staticmethod
         def backward(fctx, gR):
+            if fctx.context.solves != fctx.solve_stamp:
+                raise RuntimeError("the context has solved again since this forward; its "
+                                   "adjoint would belong to the later solve")
             dmu, dv, dw = fctx.context.adjoint(gR)
             return dmu, dv, dw, None
 

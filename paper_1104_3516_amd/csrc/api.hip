@@ -866,7 +866,7 @@ int solve_single(cd_ctx* c) {
     const size_t form = c->sweep_global ? 0 : (c->sweep_stage ? c->sweep_lds_stage : c->sweep_lds);
     if (form + cd_random_lds(c) + 2048 > c->max_lds)
       return fail(c, CD_ECAPACITY,
-                  "the random order needs 12 bytes of LDS per contact of the largest domain");
+                  "the random order needs 16 bytes of LDS per contact of the largest domain");
   }
   if (G >= 8 && nc > 0 && limit > 0) {
     // all sweeps in one launch

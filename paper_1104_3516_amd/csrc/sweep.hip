@@ -545,8 +545,9 @@ hipError_t cd_launch_solve_init(cd_ctx* c, int limit) {
   return hipGetLastError();
 }
 
-// LDS of the random order's draws and ranked slots (12 bytes per contact of
-// the largest domain, rounded up)
+// LDS of the random order's draws and ranked slots: 16 bytes reserved per
+// contact of the largest domain (an 8-byte draw and a 4-byte rank, padded),
+// rounded up to 32 bytes
 size_t cd_random_lds(cd_ctx* c) {
   return c->order_random ? ((size_t)16 * std::max(c->st_ds.max_contacts, 1) + 31) / 32 * 32 : 0;
 }
@@ -620,7 +621,8 @@ void cd_sweep_mode(cd_ctx* c) {
   if (c->sweep_stage && c->sweep_block >= 128) {
     const void* kf = c->dim == 2 ? (const void*)k_sweep<2, false, true, true>
                                  : (const void*)k_sweep<3, false, true, true>;
-    const int64_t slots = (int64_t)resident_per_cu(kf, c->sweep_block, c->sweep_lds_stage) * c->num_cu;
+    const int64_t slots =
+        (int64_t)resident_per_cu(kf, c->sweep_block, c->sweep_lds_stage + extra) * c->num_cu;
     c->sweep_fold = domains + 1 > slots;
   }
 }

@@ -627,7 +627,7 @@ __host__ __device__ inline unsigned long long rand_mix(unsigned long long x) {
 // contacts.  RAND: the random sequential order (Sec. 2.1) instead of the
 // colours: slot s draws rand_mix(jkey ^ s), jkey = rand_mix(K ^ j) of sweep
 // j, and thread 0 updates the domain's contacts one at a time by increasing
-// draw (equal draws by slot); the draws and the ranked slots take 12 bytes
+// draw (equal draws by slot); the draws and the ranked slots take 16 bytes
 // of LDS per contact after the form's own staging.  GLOB: the particle records live in global scratch (domains too
 // large for LDS).  STAGE: the domain's contact data is copied to LDS
 // alongside the exchange (all its loads in flight at once) and the colours

@@ -81,6 +81,35 @@ def test_autograd_function_end_to_end():
     assert torch.equal(mu.grad, dmu) and torch.equal(v.grad, dv) and torch.equal(w.grad, dw)
 
 
+def test_binding_refuses_mismatched_or_stale_inputs():
+    """The binding checks what the kernels cannot: a friction array whose
+    length is not the prepared list's, a dL/dR of the wrong shape, a
+    backward after the context has solved again, and a forward whose list
+    would depend on the velocities (boundary width 2 v_max dt)."""
+    from paper_1104_3516_amd import binding
+    torch = _torch()
+    pk = inputs.lattice_2d(16, 12, 43)
+    ctx, c, mu = gpu_case(pk, 5, 15, 5)
+    with pytest.raises(ValueError):
+        ctx.set_contact_mu(mu[:-1])
+    ctx.set_contact_mu(mu)
+    ctx.solve()
+    nc = len(c["ci"])
+    with pytest.raises(ValueError):
+        ctx.adjoint(torch.zeros((2, nc + 1), dtype=torch.float64, device="cuda"))
+    v = torch.as_tensor(pk.v, device="cuda").requires_grad_(True)
+    w = torch.as_tensor(pk.w, device="cuda").requires_grad_(True)
+    R = binding.contact_forces(mu, v, w, ctx)
+    binding.contact_forces(mu, v.detach(), w.detach(), ctx)     # solves again
+    with pytest.raises(RuntimeError, match="solved again"):
+        R[0].sum().backward()
+    loose = binding.Context(binding.make_params(2, pk.n_walls, fixed_iters=5, n_domains=2), pk,
+                            timing=0)
+    loose.set_adjoint(5)
+    with pytest.raises(ValueError, match="boundary width"):
+        binding.contact_forces(mu, v, w, loose)
+
+
 def test_adjoint_central_differences_65k():
     """256x256 disks, 256 domains, 200 sweeps, checkpoints every 10 sweeps,
     friction per pair in [0.2, 0.4]: dL/d(mu, v, w) along 64 random

@@ -1,4 +1,4 @@
-"""Sequential (one domain) against domain-wise solves on the GPU (Sec. 4.5).
+"""Sequential (one domain) against domain-wise solves on the GPU (Sec. 4.4).
 
 The paper compares runs on different processor counts through macroscopic
 observables (force-orientation distribution, sigma_yy strips), because the
@@ -14,7 +14,7 @@ exact limit where the solution of the step is unique:
   and of 16 domains agree to 1e-6;
 * at the benchmark tolerance (alpha = 1e-6 on squared ratios) the
   observables differ only as much as the tolerance allows, the extra sweep
-  count N_I(P)/N_I(1) of Sec. 4.4 is reported, and individual forces may
+  count N_I(P)/N_I(1) of Sec. 4.3 is reported, and individual forces may
   differ by a few percent.
 
 The bounds were read off runs of the same cases; the domain-wise results
@@ -89,7 +89,7 @@ def test_benchmark_tolerance_observables():
 
 
 def test_chain_sweeps_follow_the_diffusion_model():
-    """Sec. 4.4, Fig. 13(a, b): 64 touching disks compressed by a force, cut
+    """Sec. 4.3, Fig. 13(a, b): 64 touching disks compressed by a force, cut
     into P domains: N_I(P) / N_I(1) within 2 % of 1 / (1 - p (1 - D_p/D_s)),
     p = P / 64, D_s / D_p = 1.53."""
     pk = inputs.chain_2d(64, 1.0)

@@ -88,7 +88,7 @@ def test_no_parallel_contacts_is_the_plain_solve(oracle):
 
 @pytest.mark.parametrize("n", [64, 128])
 def test_chain_sweeps_follow_the_diffusion_model(oracle, n):
-    """Sec. 4.4, Fig. 13(a, b): a chain of n touching disks compressed by a
+    """Sec. 4.3, Fig. 13(a, b): a chain of n touching disks compressed by a
     force, cut into P domains, needs N_I(P) / N_I(1) = D_s / D_eff sweeps
     with D_eff = D_p p + D_s (1 - p), p = P / n and the fitted
     D_s / D_p = 1.53; within 2 %."""

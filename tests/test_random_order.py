@@ -9,7 +9,7 @@ slots listed in that order, a semantics pinned elsewhere; so k sweeps in
 random order must equal, bit for bit, k single plain sweeps each fed the
 slots in that sweep's drawn order.  The physics pin is the paper's: on a
 compressed chain the parallel (Jacobi) update needs D_s/D_p = 1.53 times
-the sweeps of the random sequential one (Sec. 4.4, Fig. 13).
+the sweeps of the random sequential one (Sec. 4.3, Fig. 13).
 """
 import numpy as np
 import pytest
@@ -115,7 +115,7 @@ def test_contacts_without_shared_bodies_do_not_depend_on_the_order(oracle):
 
 @pytest.mark.parametrize("n", [128, 256])
 def test_chain_parallel_over_random_sequential_sweeps(oracle, n):
-    """Sec. 4.4: N_I ~ 1/D, so Jacobi needs D_s/D_p = 1.53 (the paper's fit;
+    """Sec. 4.3: N_I ~ 1/D, so Jacobi needs D_s/D_p = 1.53 (the paper's fit;
     q_s/q_p = 0.797/0.5 = 1.59 from theory) times the sweeps of the random
     sequential update on the chain of Fig. 13(a); mean over eight seeds,
     within 5 % of 1.53."""
