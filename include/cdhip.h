@@ -81,6 +81,12 @@ typedef struct cd_result {
   double skin;           /* boundary width used */
   int max_colors;        /* largest number of colours in a domain */
   int max_domain_contacts;  /* largest domain (contacts) */
+  int64_t n_active;      /* contacts carrying a force after the solve (R_n > 0) */
+  double crit_last;      /* share of contacts passing the relative test (I-a) in the last
+                            sweep: n_pass / n_contacts (1 without contacts) */
+  double rel_change_last;  /* relative change of the mean force in the last sweep, the
+                              quantity of test (II): (dR_avg)^2 / (R_avg + R_avg_prev)^2
+                              (0 when both are 0) */
 } cd_result;
 
 /* Time spent in each phase of the last step, milliseconds, from HIP events
@@ -106,27 +112,39 @@ typedef struct cd_timing {
 
 typedef struct cd_ctx cd_ctx;
 
-/* Create a context for n_particles bodies on the current HIP device.
- * stream: a hipStream_t (NULL = the null stream) on which all work runs.
- * The context owns its workspace and frees it in cd_destroy. */
-int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* stream);
+/* Create a context for n_particles bodies (Sec. 2.1: rigid disks or spheres,
+ * each with mass, moment of inertia and radius) on the current HIP device.
+ * contact_capacity > 0 sizes the contact arrays for that many contacts up
+ * front, so that steps with at most that many contacts do not reallocate
+ * them; 0 sizes them at the first step.  Either way they grow by a quarter when a
+ * step needs more.  stream: a hipStream_t (NULL = the null stream) on which
+ * all work runs.  The context owns its workspace and frees it in cd_destroy.
+ * CD_EINVAL for dim not 2 or 3, N < 1, P < 1, dt <= 0, more than 8 walls or
+ * a negative capacity; CD_ENOMEM when the workspace does not fit. */
+int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles,
+              int64_t contact_capacity, void* stream);
 int cd_destroy(cd_ctx* ctx);
 
-/* Particle state and properties (device pointers, copied in):
- * x, v (dim x N); w (dr x N); radius, mass, inertia (N), all > 0. */
+/* Particle state and properties (Sec. 2.1, Eqs. 1-2; device pointers,
+ * copied in): x, v (dim x N); w (dr x N, NULL = 0); radius, mass, inertia
+ * (N), all positive and finite, else CD_EINVAL.  Starts a new simulation:
+ * the step counter, the tree and the warm-start list are reset. */
 int cd_set_particles(cd_ctx* ctx, const double* x, const double* v, const double* w,
                      const double* radius, const double* mass, const double* inertia);
 
-/* External forces (dim x N) and torques (dr x N, NULL = zero); device pointers. */
+/* External forces (dim x N) and torques (dr x N), the F_i of Eq. (1) and
+ * its rotational analogue; device pointers, NULL = zero. */
 int cd_set_external(cd_ctx* ctx, const double* force, const double* torque);
 
-/* Walls (HOST pointers): normal (W x dim, unit, into the box), offset (W),
- * velocity (W x dim).  W must equal params.n_walls. */
+/* Walls, bodies of prescribed motion (Sec. 2.1), HOST pointers: normal
+ * (W x dim, unit, into the box), offset (W), velocity (W x dim, NULL = at
+ * rest).  W must equal params.n_walls. */
 int cd_set_walls(cd_ctx* ctx, const double* normal, const double* offset, const double* velocity);
 
 /* Simulation box (HOST pointers, dim each): the root region of the
- * bisection tree and the extent of the cell grid.  Box faces lying on an
- * axis-aligned wall move with that wall. */
+ * bisection tree (Sec. 3.2, Fig. 8) and the extent of the cell grid
+ * (Sec. 3.2).  Box faces lying on an axis-aligned wall move with that wall.
+ * CD_EINVAL unless hi > lo on every axis. */
 int cd_set_box(cd_ctx* ctx, const double* lo, const double* hi);
 
 /* One time step: detection, warm start, partition, order, force solve,
@@ -135,20 +153,55 @@ int cd_set_box(cd_ctx* ctx, const double* lo, const double* hi);
  * CD_OK, CD_MAXITER or an error. */
 int cd_step(cd_ctx* ctx, cd_result* out);
 
-/* Copy the state out (device pointers, NULL skips): x, v (dim x N), w (dr x N). */
+/* The iterative force solve alone (Sec. 2.1 sweeps and tests, Sec. 3.1
+ * domain-wise update and exchange) on a contact list the caller gives, at
+ * the context's current positions, velocities and walls; no detection and
+ * no time step.  All pointers are DEVICE pointers of n_c entries:
+ *   ci, cj   the list in canonical order: 0 <= ci < N, ci < cj < N + W, the
+ *            keys (ci, cj) strictly increasing (the order of cd_get_contacts);
+ *   dom      the domain of each contact, in [0, P); NULL: the contact-count
+ *            bisection of the mid-gap positions (Sec. 3.2, Fig. 8);
+ *   order    the sequential update order: the contacts of domain 0, then
+ *            of domain 1, ..., each domain's in the order they are to be
+ *            updated (a permutation of 0..n_c-1 with non-decreasing
+ *            dom[order[s]]; needs dom); NULL: first-fit colour-major order.
+ *            A given order is run colour by colour with colour = one above
+ *            the highest colour of the earlier contacts sharing a body, which
+ *            is the same sequential order; CD_ECAPACITY when it needs more
+ *            than 64 colours in a domain;
+ *   R_inout  (dim x n_c, contact frame) the starting forces, overwritten
+ *            with the forces after the last sweep.
+ * The normals, gaps and constants follow from the context's positions
+ * (Fig. 1, Eq. 5).  The list and its forces become the context's current
+ * list: cd_get_contacts returns them and the next cd_step warm-starts from
+ * them.  out (host, may be NULL) receives the outcome (skin = 0).  Returns
+ * CD_OK, CD_MAXITER or an error: CD_EINVAL when the list, dom or order
+ * fails its checks (nothing is solved), for an order without dom or
+ * together with the mixed update or the random order, and while the
+ * adjoint records (cd_set_adjoint); CD_ENOTREADY before cd_set_particles /
+ * cd_set_box. */
+int cd_solve_contacts(cd_ctx* ctx, int64_t n_c, const int32_t* ci, const int32_t* cj,
+                      const int32_t* dom, const int32_t* order, double* R_inout,
+                      cd_result* out);
+
+/* Copy the state after the steps so far out (Eqs. 1-2; device pointers,
+ * NULL skips): x, v (dim x N), w (dr x N). */
 int cd_get_state(cd_ctx* ctx, double* x, double* v, double* w);
 
-/* Wall offsets after the steps so far (HOST pointer, W entries). */
+/* Wall offsets after the steps so far (HOST pointer, W entries): each wall
+ * has moved by dt times its normal velocity per step (Sec. 2.1). */
 int cd_get_walls(cd_ctx* ctx, double* offset);
 
-/* Number of contacts of the last step (host value, no device work). */
+/* Number of contacts in the context's current list (Sec. 3.1: pairs within
+ * the boundary width; host value, no device work). */
 int64_t cd_num_contacts(const cd_ctx* ctx);
 
 /* The contacts of the last step in canonical (ci, cj) order (device
- * pointers, NULL skips): ci, cj (nc), normal (dim x nc), gap (nc),
- * R (dim x nc, contact frame), dom (nc), color (nc) and slot_contact (nc:
- * the contact at each position of the domain-major update order).
- * cap must be >= cd_num_contacts(). */
+ * pointers, NULL skips): ci, cj (nc), normal (dim x nc) and gap (nc) of
+ * Fig. 1, R (dim x nc, contact frame, Eqs. 3-9), dom (nc, the domain of the
+ * contact's mid-gap position, Sec. 3.1), color (nc) and slot_contact (nc:
+ * the contact at each position of the domain-major sequential update
+ * order).  cap must be >= cd_num_contacts(), else CD_EINVAL. */
 int cd_get_contacts(cd_ctx* ctx, int64_t cap, int32_t* ci, int32_t* cj, double* normal,
                     double* gap, double* R, int32_t* dom, int32_t* color,
                     int32_t* slot_contact);
@@ -250,10 +303,11 @@ int cd_set_domain_capacity(cd_ctx* ctx, const double* capacity);
  * measured step. */
 int cd_get_domain_times(cd_ctx* ctx, double* times_us, double* sigma_t);
 
-/* Phase timings of the last step (host struct). */
+/* Phase timings of the last step (host struct), the phases of Fig. 7. */
 int cd_get_timing(cd_ctx* ctx, cd_timing* out);
 
-/* Static description of a status code, and the last error of a context. */
+/* Static description of a status code, and the last error of a context
+ * (plumbing: no passage of the paper defines them). */
 const char* cd_status_string(int status);
 const char* cd_last_error(const cd_ctx* ctx);
 

@@ -32,7 +32,8 @@ class Result(C.Structure):
     _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("n_contacts", C.c_int64),
                 ("n_pass", C.c_int64), ("max_d_fail", C.c_double), ("r_avg", C.c_double),
                 ("r_avg_prev", C.c_double), ("skin", C.c_double), ("max_colors", C.c_int),
-                ("max_domain_contacts", C.c_int)]
+                ("max_domain_contacts", C.c_int), ("n_active", C.c_int64),
+                ("crit_last", C.c_double), ("rel_change_last", C.c_double)]
 
 
 class Timing(C.Structure):
@@ -77,7 +78,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         i64 = C.c_int64
-        L.cd_create.argtypes = [C.POINTER(P), C.POINTER(Params), i64, P]
+        L.cd_create.argtypes = [C.POINTER(P), C.POINTER(Params), i64, i64, P]
+        L.cd_solve_contacts.argtypes = [P, i64, P, P, P, P, P, C.POINTER(Result)]
         L.cd_destroy.argtypes = [P]
         L.cd_set_particles.argtypes = [P, P, P, P, P, P, P]
         L.cd_set_external.argtypes = [P, P, P]
@@ -134,7 +136,7 @@ class Context:
     """One simulation on one GPU.  `packing` is a paper_1104_3516_amd.inputs.Packing."""
 
     def __init__(self, params: Params, packing, device: str = "cuda:0", timing: int = 1,
-                 solve_mode: int = 1, block_threads: int = 0):
+                 solve_mode: int = 1, block_threads: int = 0, contact_capacity: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libcdhip needs a ROCm GPU; none is visible")
@@ -153,6 +155,7 @@ class Context:
             self.stream = torch.cuda.current_stream(self.device)
             h = C.c_void_p()
             self._check(self.L.cd_create(C.byref(h), C.byref(params), self.n,
+                                         int(contact_capacity),
                                          C.c_void_p(self.stream.cuda_stream)), None)
             self.h = h
             dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64),
@@ -203,6 +206,36 @@ class Context:
         res = Result()
         self.solves += 1
         self._check(self.L.cd_step(self.h, C.byref(res)))
+        return res
+
+    def solve_contacts(self, ci, cj, R=None, dom=None, order=None) -> Result:
+        """The force solve alone on a given canonical list (cd_solve_contacts):
+        ci, cj (n_c), optional starting forces R (dim x n_c, default 0),
+        domains dom (n_c) and update order (n_c, needs dom).  Returns the
+        result; the forces are in self.last_R (dim x n_c) and in contacts()."""
+        torch = self.torch
+        dev = dict(device=self.device)
+        i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.int32, **dev)
+        ci_t, cj_t = i32(ci), i32(cj)
+        nc = int(ci_t.numel())
+        if cj_t.numel() != nc:
+            raise ValueError("ci and cj differ in length")
+        if R is None:
+            R_t = torch.zeros((self.dim, nc), dtype=torch.float64, **dev)
+        else:
+            R_t = torch.as_tensor(R, dtype=torch.float64, **dev).clone().contiguous()
+            if tuple(R_t.shape) != (self.dim, nc):
+                raise ValueError(f"R must be ({self.dim}, {nc})")
+        dom_t = None if dom is None else i32(dom)
+        order_t = None if order is None else i32(order)
+        for t in (dom_t, order_t):
+            if t is not None and t.numel() != nc:
+                raise ValueError("dom and order need one entry per contact")
+        res = Result()
+        self.solves += 1
+        self._check(self.L.cd_solve_contacts(self.h, nc, _ptr(ci_t), _ptr(cj_t), _ptr(dom_t),
+                                             _ptr(order_t), _ptr(R_t), C.byref(res)))
+        self.last_R = R_t
         return res
 
     def state(self):

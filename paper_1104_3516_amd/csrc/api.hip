@@ -284,6 +284,8 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 static_assert(sizeof(GridBar) <= 512 && sizeof(DomainStats) <= 512 && 6 * sizeof(double) <= 512,
               "pinned scratch holds every small readback");
+static_assert(sizeof(GridBar) <= 8 * kActiveSlot && sizeof(DomainStats) <= 8 * kActiveSlot,
+              "the active-contact count has a slot of its own in the pinned scratch");
 
 extern "C" {
 
@@ -303,12 +305,14 @@ const char* cd_status_string(int s) {
 
 const char* cd_last_error(const cd_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* stream) {
+int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles,
+              int64_t contact_capacity, void* stream) {
   if (!out || !params) return CD_EINVAL;
   *out = nullptr;
   if ((params->dim != 2 && params->dim != 3) || n_particles < 1 || params->n_domains < 1 ||
       params->n_walls < 0 || params->n_walls > CD_MAX_WALLS || !(params->dt > 0.0) ||
-      n_particles > (int64_t)1 << 30)
+      n_particles > (int64_t)1 << 30 || contact_capacity < 0 ||
+      contact_capacity > (int64_t)1 << 30)
     return CD_EINVAL;
   cd_ctx* c = new cd_ctx();
   c->p = *params;
@@ -380,6 +384,8 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
     st = CD_EHIP;
   if (st == CD_OK && hipMalloc((void**)&c->d_vmax, sizeof(unsigned long long)) != hipSuccess)
     st = CD_ENOMEM;
+  if (st == CD_OK && hipMalloc((void**)&c->d_active, sizeof(unsigned long long)) != hipSuccess)
+    st = CD_ENOMEM;
   if (st == CD_OK && hipHostMalloc((void**)&c->h_state, sizeof(SolveState)) != hipSuccess)
     st = CD_ENOMEM;
   if (st == CD_OK && hipHostMalloc((void**)&c->h_scratch, 512) != hipSuccess) st = CD_ENOMEM;
@@ -398,6 +404,14 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles, void* 
     if (hipEventCreate(&c->ev[k]) != hipSuccess) st = CD_EHIP;
   if (st == CD_OK && hipMemset(c->t, 0, sizeof(double) * c->dr * n) != hipSuccess) st = CD_EHIP;
   if (st == CD_OK && hipMemset(c->f, 0, sizeof(double) * c->dim * n) != hipSuccess) st = CD_EHIP;
+  if (st == CD_OK && contact_capacity > 0) {
+    // contact arrays sized up front: both lists of the warm start and every
+    // contact-sized workspace
+    st = ensure_capacity(c, contact_capacity);
+    if (st == CD_OK) st = ensure_list(c, contact_capacity, &c->cap_list, &c->ci, &c->cj, &c->R);
+    if (st == CD_OK)
+      st = ensure_list(c, contact_capacity, &c->cap_prev, &c->ci_prev, &c->cj_prev, &c->R_prev);
+  }
   if (st != CD_OK) {
     cd_destroy(c);
     return st;
@@ -447,6 +461,7 @@ int cd_destroy(cd_ctx* c) {
   cd_adjoint_release(c);
   cd_window_clear(c);
   release(&c->d_vmax);
+  release(&c->d_active);
   release(&c->d_dtick);
   release(&c->par);
   release(&c->d_frac);
@@ -500,6 +515,7 @@ int cd_set_particles(cd_ctx* c, const double* x, const double* v, const double* 
   c->frozen_ready = false;
   c->step = 0;
   c->nc_prev = 0;
+  c->list_solved = false;
   return CD_OK;
 }
 
@@ -709,7 +725,7 @@ int prep_phase1(cd_ctx* c) {
   std::swap(c->cj, c->cj_prev);
   std::swap(c->R, c->R_prev);
   std::swap(c->cap_prev, c->cap_list);
-  c->nc_prev = c->step > 0 ? c->nc : 0;
+  c->nc_prev = (c->step > 0 || c->list_solved) ? c->nc : 0;
   const int64_t nc = (int64_t)((int*)(c->h_scratch + 1))[0];
   if (nc < 0 || nc > ((int64_t)1 << 30)) return fail(c, CD_ECAPACITY, "too many contacts");
   int st = ensure_capacity(c, nc);
@@ -989,6 +1005,9 @@ int finish_enqueue(cd_ctx* c) {
   CD_TRY(cd_launch_unslot(c, s.iter));
   CD_TRY(cd_launch_update(c, s.iter));
   CD_TRY(hipEventRecord(c->ev[5], c->stream));
+  CD_TRY(cd_launch_count_active(c, c->d_active));
+  CD_TRY(hipMemcpyAsync(c->h_scratch + kActiveSlot, c->d_active, sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, c->stream));
   return CD_OK;
 }
 
@@ -999,35 +1018,16 @@ int step_finish(cd_ctx* c, cd_result* out) {
   return finish_complete(c, out);
 }
 
-int finish_complete(cd_ctx* c, cd_result* out) {
-  const int dim = c->dim;
-  const double dt = c->p.dt;
+// The outcome of the last solve and its timings (after the stream has
+// passed the finish launches), in c->last, c->timing and *out.
+static int collect_result(cd_ctx* c, cd_result* out) {
   const int64_t nc = c->nc;
-  const double skin = c->st_skin;
   const DomainStats& ds = c->st_ds;
   const int launched = c->run.launched, executed = c->run.executed;
   const int groups_closed = c->run.groups_closed;
   const bool one_launch = c->run.one_launch;
   SolveState s;
   memcpy(&s, c->h_state, sizeof(SolveState));
-  // walls move; a box face follows the axis-aligned wall lying on it
-  for (int wi = 0; wi < c->W; ++wi) {
-    double un = 0.0;
-    for (int k = 0; k < dim; ++k) un = un + c->wn[wi * dim + k] * c->wu[wi * dim + k];
-    c->wo[wi] = c->wo[wi] + dt * un;
-    for (int k = 0; k < dim; ++k) {
-      bool unit = true;
-      for (int q = 0; q < dim; ++q)
-        if (q != k && c->wn[wi * dim + q] != 0.0) unit = false;
-      if (!unit) continue;
-      if (c->wn[wi * dim + k] == 1.0) c->lo[k] = c->wo[wi];
-      if (c->wn[wi * dim + k] == -1.0) c->hi[k] = -c->wo[wi];
-    }
-  }
-  int st = upload_walls(c, false);
-  if (st != CD_OK) return st;
-  c->step += 1;
-  // ---- result and timings
   cd_result res{};
   res.status = nc == 0 ? CD_OK : s.status;
   res.iterations = s.iter;
@@ -1036,9 +1036,16 @@ int finish_complete(cd_ctx* c, cd_result* out) {
   res.max_d_fail = s.max_d_fail;
   res.r_avg = s.r_avg;
   res.r_avg_prev = s.r_avg_prev;
-  res.skin = skin;
+  res.skin = c->st_skin;
   res.max_colors = ds.max_colors;
   res.max_domain_contacts = ds.max_contacts;
+  res.n_active = nc > 0 ? (int64_t)c->h_scratch[kActiveSlot] : 0;
+  res.crit_last = nc > 0 ? (double)s.n_pass / (double)nc : 1.0;
+  {
+    const double dd = (s.r_avg - s.r_avg_prev) * (s.r_avg - s.r_avg_prev);
+    const double ss = (s.r_avg + s.r_avg_prev) * (s.r_avg + s.r_avg_prev);
+    res.rel_change_last = ss > 0.0 ? dd / ss : 0.0;
+  }
   c->last = res;
   cd_timing tm{};
   tm.detect_ms = elapsed(c->ev[0], c->ev[1]);
@@ -1074,6 +1081,29 @@ int finish_complete(cd_ctx* c, cd_result* out) {
   if (out) *out = res;
   if (res.status == CD_ENONFINITE) return fail(c, CD_ENONFINITE, "non-finite contact force");
   return res.status;
+}
+
+int finish_complete(cd_ctx* c, cd_result* out) {
+  const int dim = c->dim;
+  const double dt = c->p.dt;
+  // walls move; a box face follows the axis-aligned wall lying on it
+  for (int wi = 0; wi < c->W; ++wi) {
+    double un = 0.0;
+    for (int k = 0; k < dim; ++k) un = un + c->wn[wi * dim + k] * c->wu[wi * dim + k];
+    c->wo[wi] = c->wo[wi] + dt * un;
+    for (int k = 0; k < dim; ++k) {
+      bool unit = true;
+      for (int q = 0; q < dim; ++q)
+        if (q != k && c->wn[wi * dim + q] != 0.0) unit = false;
+      if (!unit) continue;
+      if (c->wn[wi * dim + k] == 1.0) c->lo[k] = c->wo[wi];
+      if (c->wn[wi * dim + k] == -1.0) c->hi[k] = -c->wo[wi];
+    }
+  }
+  int st = upload_walls(c, false);
+  if (st != CD_OK) return st;
+  c->step += 1;
+  return collect_result(c, out);
 }
 
 extern "C" {
@@ -1152,6 +1182,93 @@ int cd_step(cd_ctx* c, cd_result* out) {
   st = solve_single(c);
   if (st != CD_OK) return st;
   return step_finish(c, out);
+}
+
+int cd_solve_contacts(cd_ctx* c, int64_t n_c, const int32_t* ci, const int32_t* cj,
+                      const int32_t* dom, const int32_t* order, double* R_inout,
+                      cd_result* out) {
+  if (!c) return CD_EINVAL;
+  if (!c->have_particles || !c->have_box) return fail(c, CD_ENOTREADY, "particles or box not set");
+  if (n_c < 0 || n_c > ((int64_t)1 << 30)) return fail(c, CD_EINVAL, "contact count out of range");
+  if (n_c > 0 && (!ci || !cj || !R_inout)) return fail(c, CD_EINVAL, "ci, cj and R are required");
+  if (order && !dom) return fail(c, CD_EINVAL, "an update order needs the domains it runs in");
+  if (order && (c->mixed_p >= 0.0 || c->order_random))
+    return fail(c, CD_EINVAL, "a given update order excludes the mixed update and the random order");
+  if (c->adj_every > 0)
+    return fail(c, CD_EINVAL, "the adjoint records time steps (cd_step), not cd_solve_contacts");
+  c->prepared = false;
+  c->adj_valid = false;
+  c->frozen_ready = false;
+  CD_TRY(hipEventRecord(c->ev[0], c->stream));
+  // ---- the caller's list becomes the context's current list
+  int st = ensure_capacity(c, n_c);
+  if (st != CD_OK) return st;
+  st = ensure_list(c, n_c, &c->cap_list, &c->ci, &c->cj, &c->R);
+  if (st != CD_OK) return st;
+  c->nc = n_c;
+  c->st_skin = 0.0;
+  if (n_c > 0) {
+    CD_TRY(hipMemcpyAsync(c->ci, ci, sizeof(int) * (size_t)n_c, hipMemcpyDeviceToDevice, c->stream));
+    CD_TRY(hipMemcpyAsync(c->cj, cj, sizeof(int) * (size_t)n_c, hipMemcpyDeviceToDevice, c->stream));
+    CD_TRY(hipMemcpyAsync(c->R, R_inout, sizeof(double) * c->dim * (size_t)n_c,
+                          hipMemcpyDeviceToDevice, c->stream));
+    if (dom)
+      CD_TRY(hipMemcpyAsync(c->dom, dom, sizeof(int) * (size_t)n_c, hipMemcpyDeviceToDevice,
+                            c->stream));
+    // every index is checked before a kernel uses it
+    int* fault = &c->d_stats->input_fault;
+    CD_TRY(cd_launch_check_inputs(c, dom ? c->dom : nullptr, order, fault));
+    CD_TRY(hipMemcpyAsync(c->h_scratch, fault, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    CD_TRY(hipStreamSynchronize(c->stream));
+    const int bad = ((int*)c->h_scratch)[0];
+    if (bad) {
+      c->nc = 0;
+      return fail(c, CD_EINVAL,
+                  (bad & 1) ? "contact list: need 0 <= ci < N, ci < cj < N + W, keys increasing"
+                  : (bad & 2) ? "domains must lie in [0, P)"
+                              : "order must be a permutation with non-decreasing domains");
+    }
+  }
+  CD_TRY(cd_launch_geometry(c));
+  CD_TRY(hipEventRecord(c->ev[1], c->stream));
+  // ---- partition (Sec. 3.2) unless given
+  if (!dom) {
+    CD_TRY(cd_launch_orb(c));
+    c->have_tree = true;
+  }
+  CD_TRY(hipEventRecord(c->ev[2], c->stream));
+  // ---- order: colour-major first fit, or the caller's order by levels
+  c->given_order = order;
+  hipError_t oe = cd_launch_order(c);
+  c->given_order = nullptr;
+  CD_TRY(oe);
+  CD_TRY(hipMemcpyAsync(c->h_scratch, c->d_stats, sizeof(DomainStats), hipMemcpyDeviceToHost,
+                        c->stream));
+  CD_TRY(hipStreamSynchronize(c->stream));
+  const bool frozen = c->frozen;
+  c->frozen_now = false;
+  c->frozen = false;          // the set-up below must not keep this list for later steps
+  st = prep_phase2(c);
+  c->frozen = frozen;
+  if (st != CD_OK) return st;
+  c->prepared = false;
+  st = solve_single(c);
+  if (st != CD_OK) return st;
+  // ---- forces back in canonical order
+  SolveState s;
+  memcpy(&s, c->h_state, sizeof(SolveState));
+  CD_TRY(hipEventRecord(c->ev[4], c->stream));
+  CD_TRY(cd_launch_unslot(c, s.iter));
+  CD_TRY(hipEventRecord(c->ev[5], c->stream));
+  CD_TRY(cd_launch_count_active(c, c->d_active));
+  CD_TRY(hipMemcpyAsync(c->h_scratch + kActiveSlot, c->d_active, sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, c->stream));
+  if (n_c > 0)
+    CD_TRY(hipMemcpyAsync(R_inout, c->R, sizeof(double) * c->dim * (size_t)n_c,
+                          hipMemcpyDeviceToDevice, c->stream));
+  CD_TRY(hipStreamSynchronize(c->stream));
+  c->list_solved = true;
+  return collect_result(c, out);
 }
 
 int cd_get_state(cd_ctx* c, double* x, double* v, double* w) {

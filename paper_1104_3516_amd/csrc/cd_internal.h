@@ -53,6 +53,7 @@ struct DomainStats {
   int max_lds;        // largest per-domain staging size of the sweep, bytes
   int dinc_total;     // incidences summed over all domain particle entries
   int dp_total;       // domain particle entries
+  int input_fault;    // a caller's list, domains or order failed the checks (bits 1, 2, 4)
   int scan_fault;     // sticky: a prefix scan gave up waiting on a predecessor tile
                       // (never cleared by the per-step reset of the fields above)
 };
@@ -307,6 +308,10 @@ struct cd_ctx {
   std::vector<hipEvent_t> sweep_ev;
   cd_timing timing{};
   cd_result last{};
+  // cd_solve_contacts: the caller's update order (device, during the call only)
+  const int* given_order = nullptr;
+  bool list_solved = false;    // the current list holds forces of cd_solve_contacts
+  unsigned long long* d_active = nullptr;   // closed contacts after the last solve
   // the current step, between its phases
   double st_skin = 0.0;
   double st_wall_speed = 0.0;   // largest wall speed of the step (host)
@@ -372,6 +377,8 @@ hipError_t cd_launch_descend(cd_ctx* c);
 // order.hip
 hipError_t cd_launch_order(cd_ctx* c);
 hipError_t cd_launch_order_entries(cd_ctx* c);   // after the stats readback
+// checks of a caller's list (c->ci, c->cj, c->nc), domains and order before use
+hipError_t cd_launch_check_inputs(cd_ctx* c, const int* dom, const int* order, int* fault);
 // sweep.hip
 hipError_t cd_launch_solve_init(cd_ctx* c, int limit);
 // sweep j; its extra workgroup takes the stop decision of sweep j-1
@@ -412,6 +419,8 @@ int cd_solve_grid(cd_ctx* c);                               // co-resident grid,
 hipError_t cd_launch_solve(cd_ctx* c, int G, int limit);    // all sweeps in one launch
 // update.hip
 hipError_t cd_launch_update(cd_ctx* c, int final_iter);
+// contacts with R_n > 0 in the canonical forces c->R, into *count (device)
+hipError_t cd_launch_count_active(cd_ctx* c, unsigned long long* count);
 hipError_t cd_launch_derived(cd_ctx* c);
 SweepArgs cd_sweep_args(cd_ctx* c);
 
@@ -420,6 +429,10 @@ static inline int cd_row_width(int dim) { return dim == 2 ? 8 : 16; }
 // doubles the sweep stages per domain particle: V, W, dt/m, dt/I, r, padded
 // to an even count (2D: 6, 3D: 10)
 __host__ __device__ constexpr int cd_stage_particle(int dim) { return dim == 2 ? 6 : 10; }
+
+// slot of the pinned 64-entry scratch (c->h_scratch) that receives the
+// active-contact count of a finished solve
+constexpr int kActiveSlot = 63;
 
 // helpers
 static inline int cd_blocks(int64_t n, int threads) {

@@ -174,7 +174,60 @@ struct BuildArgs {
   int* ddesc;             // per domain: cs, nct, ps, np, ncol, 0, 0, 0
   DomainStats* stats;
   const unsigned char* par;   // contacts updated in parallel (canonical order), or null
+  int levels;                 // colours by level: the bucket order is the caller's order
 };
+
+// Checks a caller's contact list (cd_solve_contacts) before any kernel
+// indexes with it: 0 <= ci < n, ci < cj < n + W, keys (ci, cj) strictly
+// increasing; domains in [0, P); the order a permutation of the contacts
+// with non-decreasing domains.  Bits of *fault: 1 list, 2 domains, 4 order.
+// `seen` (nc ints) must be zero.
+__global__ __launch_bounds__(kThreads) void k_check_inputs(const int* ci, const int* cj,
+                                                          int64_t nc, int64_t n, int W,
+                                                          const int* dom, int P,
+                                                          const int* order, int* seen,
+                                                          int* fault) {
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (q >= nc) return;
+  int bad = 0;
+  const int a = ci[q], b = cj[q];
+  if (a < 0 || (int64_t)a >= n || b <= a || (int64_t)b >= n + W) bad |= 1;
+  if (q > 0) {
+    const int a0 = ci[q - 1], b0 = cj[q - 1];
+    if (a0 > a || (a0 == a && b0 >= b)) bad |= 1;
+  }
+  if (dom) {
+    const int d = dom[q];
+    if (d < 0 || d >= P) bad |= 2;
+  }
+  if (order) {
+    const int o = order[q];
+    if (o < 0 || (int64_t)o >= nc) {
+      bad |= 4;
+    } else {
+      if (atomicAdd(&seen[o], 1) != 0) bad |= 4;
+      if (q > 0) {
+        const int o0 = order[q - 1];
+        if (o0 >= 0 && (int64_t)o0 < nc && dom) {
+          const int d0 = dom[o0], d1 = dom[o];
+          if (d0 >= 0 && d0 < P && d1 >= 0 && d1 < P && d0 > d1) bad |= 4;
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(fault, bad);
+}
+
+// The caller's order as the bucket, and its sorted domain keys
+__global__ __launch_bounds__(kThreads) void k_order_keys(const int* order, const int* dom,
+                                                        int64_t nc, unsigned long long* keys,
+                                                        int* bucket) {
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (q >= nc) return;
+  const int c = order[q];
+  bucket[q] = c;
+  keys[q] = (unsigned long long)dom[c];
+}
 
 // Greedy first-fit colouring of a domain's contacts in canonical order
 // (serial by definition; thread 0): col[k], and rank[k] = number of earlier
@@ -184,9 +237,20 @@ struct BuildArgs {
 // LDS arrays in the small path and global scratch in the large one.  In
 // the mixed update (Sec. 2.3) a contact with par(k) takes colour 0 and the
 // masks start with colour 0 taken, so that the others colour from 1.
+// The colour a contact takes given the colours `used` by earlier contacts on
+// its bodies: first fit, or (LEVELS, for an update order the caller gives)
+// one above the highest, so that every contact follows all earlier contacts
+// it shares a body with and each colour holds contacts of disjoint bodies:
+// colour by colour, ties by position, is then the same sequential order.
+// Returns CD_MAX_COLORS when none is left.
+__device__ inline int colour_of(unsigned long long used, bool levels) {
+  if (levels) return used == 0ull ? 0 : 64 - __clzll((long long)used);
+  return used == ~0ull ? CD_MAX_COLORS : __ffsll((long long)~used) - 1;
+}
+
 template <typename M, typename I, typename C, typename Par>
 __device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb_s, C* col_s,
-                                    C* rank_s, int* cnt, Par&& par) {
+                                    C* rank_s, int* cnt, Par&& par, bool levels) {
   int ncol = 0;
   for (int k = 0; k < nct; ++k) {
     if (par(k)) {
@@ -198,8 +262,8 @@ __device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb
     }
     const int la = la_s[k], lb = lb_s[k];
     const unsigned long long used = mask[la] | (lb >= 0 ? mask[lb] : 0ull);
-    if (used == ~0ull) return -1;
-    const int col = __ffsll((long long)~used) - 1;
+    const int col = colour_of(used, levels);
+    if (col >= CD_MAX_COLORS) return -1;
     col_s[k] = (C)col;
     rank_s[k] = (C)cnt[col];
     cnt[col] += 1;
@@ -216,7 +280,7 @@ __device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb
 // (the next contact's bodies are read one step ahead).
 __device__ inline int colour_wave(int nct, unsigned long long* mask, const int* la_s,
                                   const int* lb_s, short* col_s, short* rank_s, int* cnt_out,
-                                  const unsigned char* par) {
+                                  const unsigned char* par, bool levels) {
   static_assert(CD_MAX_COLORS == 64, "one lane per colour");
   const int lane = threadIdx.x & 63;
   int cnt = 0;   // contacts of colour `lane` so far
@@ -240,8 +304,8 @@ __device__ inline int colour_wave(int nct, unsigned long long* mask, const int* 
     }
     const unsigned long long ma = mask[la], mb = lb >= 0 ? mask[lb] : 0ull;
     const unsigned long long used = ma | mb;
-    if (used == ~0ull) return -1;
-    const int col = __builtin_amdgcn_readfirstlane(__ffsll((long long)~used) - 1);
+    const int col = __builtin_amdgcn_readfirstlane(colour_of(used, levels));
+    if (col >= CD_MAX_COLORS) return -1;
     const int rank = __builtin_amdgcn_readlane(cnt, col);
     if (lane == col) ++cnt;
     if (lane == 0) {
@@ -357,7 +421,7 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   __syncthreads();
   int ncol_w = 0;
   if (small) ncol_w = colour_wave(nct, s_mask, s_la, s_lb, s_col, s_rank, s_cnt,
-                                  a.par ? s_par : nullptr);
+                                  a.par ? s_par : nullptr, a.levels != 0);
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned char* par = a.par;
@@ -365,7 +429,8 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     auto is_par = [&](int k) { return par != nullptr && par[bk[k]] != 0; };
     const int ncol = small ? ncol_w
                            : colour_serial(nct, a.gmask + ps, a.qla + cs, a.qlb + cs,
-                                           a.qcol + cs, a.qpos + cs, s_cnt, is_par);
+                                           a.qcol + cs, a.qpos + cs, s_cnt, is_par,
+                                           a.levels != 0);
     s_coloff[0] = 0;
     for (int q = 0; q < ncol; ++q) s_coloff[q + 1] = s_coloff[q] + s_cnt[q];
     s_ncol = ncol;
@@ -603,7 +668,11 @@ hipError_t cd_launch_order(cd_ctx* c) {
   //    domain's contact range from the sorted keys
   unsigned long long* ko = c->sort_keys[0];
   int* vo = c->sort_vals[0];
-  if (nc > 0) {
+  if (nc > 0 && c->given_order) {
+    // a caller's order (checked): its domain segments are already sorted
+    hipLaunchKernelGGL(k_order_keys, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0,
+                       c->stream, c->given_order, c->dom, nc, c->sort_keys[0], c->bucket);
+  } else if (nc > 0) {
     // the contact ids are sorted in place in `bucket` (an even number of
     // passes ends there; otherwise the result is copied back)
     hipLaunchKernelGGL(k_dom_keys, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
@@ -691,6 +760,7 @@ hipError_t cd_launch_order(cd_ctx* c) {
   c->order_mixed = par != nullptr;
   BuildArgs a;
   a.par = par;
+  a.levels = c->given_order != nullptr;
   a.dom_start = c->dom_start;
   a.bucket = c->bucket;
   a.dp_start = c->dp_start;
@@ -747,6 +817,20 @@ hipError_t cd_launch_order(cd_ctx* c) {
   e = cd_scan_exclusive(c, c->flag, c->dinc_ptr, E);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dinc_total, dim3(1), dim3(1), 0, c->stream, c->dinc_ptr, E, c->d_stats);
+  return hipGetLastError();
+}
+
+hipError_t cd_launch_check_inputs(cd_ctx* c, const int* dom, const int* order, int* fault) {
+  const int64_t nc = c->nc;
+  if (nc <= 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(fault, 0, sizeof(int), c->stream);
+  if (e != hipSuccess) return e;
+  if (order) {
+    e = hipMemsetAsync(c->flag, 0, sizeof(int) * (size_t)nc, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_check_inputs, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
+                     c->ci, c->cj, nc, c->n, c->W, dom, c->P, order, c->flag, fault);
   return hipGetLastError();
 }
 

@@ -66,7 +66,32 @@ __global__ __launch_bounds__(kThreads) void k_update(double* x, double* v, doubl
   for (int k = 0; k < DR; ++k) w[k * n + p] = w[k * n + p] + di * tacc[k];
 }
 
+// Contacts that carry a force after the solve (R_n > 0: closed contacts),
+// summed per block and added to *count.
+__global__ __launch_bounds__(kThreads) void k_count_active(const double* R, int64_t nc,
+                                                          unsigned long long* count) {
+  __shared__ int part[kThreads / 64];
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  int on = c < nc && R[c] > 0.0 ? 1 : 0;
+  for (int off = 32; off > 0; off >>= 1) on += __shfl_xor(on, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = on;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int k = 0; k < kThreads / 64; ++k) s += part[k];
+    if (s) atomicAdd(count, (unsigned long long)s);
+  }
+}
+
 }  // namespace
+
+hipError_t cd_launch_count_active(cd_ctx* c, unsigned long long* count) {
+  hipError_t e = hipMemsetAsync(count, 0, sizeof(unsigned long long), c->stream);
+  if (e != hipSuccess || c->nc == 0) return e;
+  hipLaunchKernelGGL(k_count_active, dim3(cd_blocks(c->nc, kThreads)), dim3(kThreads), 0,
+                     c->stream, c->R, c->nc, count);
+  return hipGetLastError();
+}
 
 hipError_t cd_launch_derived(cd_ctx* c) {
   hipLaunchKernelGGL(k_derived, dim3(cd_blocks(c->n, kThreads)), dim3(kThreads), 0, c->stream,

@@ -14,7 +14,7 @@ def test_header_declares_the_boundary():
                      "cd_set_walls", "cd_set_box", "cd_step", "cd_get_state",
                      "cd_get_contacts", "cd_get_tree", "cd_get_timing", "cd_status_string",
                      "cd_last_error", "cd_num_contacts", "cd_get_walls", "cd_set_timing",
-                     "cd_set_solve_mode", "cd_set_launch"):
+                     "cd_set_solve_mode", "cd_set_launch", "cd_solve_contacts"):
         assert required in names
 
 
@@ -29,12 +29,28 @@ def test_library_exports_every_declared_symbol():
     assert L.cd_status_string(1).startswith(b"sweep cap")
 
 
-def test_struct_layouts_match_header():
-    # the ctypes mirrors have the C sizes of the header structs
-    assert ctypes.sizeof(binding.Params) == 4 * 2 + 8 * 3 + 4 * 8 + 8
-    assert ctypes.sizeof(binding.Result) == 4 * 2 + 8 * 2 + 8 * 4 + 4 * 2
-    assert ctypes.sizeof(binding.Timing) == 8 * 6 + 4 * 6
-    assert ctypes.sizeof(binding.BatchTiming) == 8 * 4 + 4 * 6
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes mirrors have the sizes and field offsets the C compiler gives
+    # the header structs
+    import subprocess
+    structs = {"cd_params": binding.Params, "cd_result": binding.Result,
+               "cd_timing": binding.Timing, "cd_batch_timing": binding.BatchTiming}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cdhip.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
 
 
 def test_product_package_does_not_import_the_oracle():
