@@ -364,6 +364,25 @@ int cd_set_frozen_list(cd_ctx* ctx, int on);
  * calibration, on top of the paper's fixed-iteration option (Sec. 2.1). */
 int cd_adjoint(cd_ctx* ctx, const double* dL_dR, double* dL_dmu, double* dL_dv, double* dL_dw);
 
+/* cd_adjoint for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same reverse pass with the same results, bit for bit, but its workspace
+ * (the adjoints of forces, velocities and positions, the recomputed
+ * segment's forces, the particle-to-entry lists, the recomputing sweeps'
+ * state) is carved out of one static array of 64 MiB per device that the
+ * library holds from its load until the process ends; the call makes no
+ * hipMalloc or hipFree and clears what must start at zero with kernels.
+ * Every call on a device shares that device's array and leaves its
+ * contents behind: calls that overlap on one device (two threads, two
+ * streams) race and must be serialised by the caller.  The workspace
+ * needs (16 cap + 4 C cap) doubles + 2 cap ints per contact slot of
+ * capacity cap (C = checkpoint interval) plus 15 doubles + 2 ints per
+ * particle; CD_ECAPACITY when that exceeds 64 MiB (outputs untouched), and
+ * also when the context's prefix-scan workspace was not sized by a
+ * prepared step.  Other errors as cd_adjoint. */
+int cd_adjoint_static(cd_ctx* ctx, const double* dL_dR, double* dL_dmu, double* dL_dv,
+                      double* dL_dw);
+
 /* ---- Batches of independent packings ------------------------------------
  * Many packings stepped together: each packing is a context created and
  * filled as above (its own parameters, friction, domain count, walls); the

@@ -111,6 +111,8 @@ def lib():
         L.cd_set_domain_capacity.argtypes = [P, P]
         L.cd_get_domain_times.argtypes = [P, P, P]
         L.cd_adjoint.argtypes = [P, P, P, P, P]
+        if hasattr(L, "cd_adjoint_static"):
+            L.cd_adjoint_static.argtypes = [P, P, P, P, P]
         L.cd_batch_create.argtypes = [C.POINTER(P), C.POINTER(P), C.c_int]
         L.cd_batch_destroy.argtypes = [P]
         L.cd_batch_set_timing.argtypes = [P, C.c_int]
@@ -384,6 +386,21 @@ class Context:
         dv = torch.zeros((self.dim, self.n), dtype=torch.float64, device=self.device)
         dw = torch.zeros((self.dr, self.n), dtype=torch.float64, device=self.device)
         self._check(self.L.cd_adjoint(self.h, _ptr(g), _ptr(dmu), _ptr(dv), _ptr(dw)))
+        return dmu[:nc], dv, dw
+
+    def adjoint_static(self, dL_dR):
+        """adjoint() through cd_adjoint_static: the reverse pass's workspace
+        is the library's static per-device array (no device allocation)."""
+        torch = self.torch
+        nc = self.num_contacts()
+        if tuple(dL_dR.shape) != (self.dim, nc):
+            raise ValueError(f"dL_dR must be ({self.dim}, {nc}) for the recorded solve, "
+                             f"got {tuple(dL_dR.shape)}")
+        g = dL_dR.detach().to(self.device, torch.float64).contiguous()
+        dmu = torch.zeros(max(nc, 1), dtype=torch.float64, device=self.device)
+        dv = torch.zeros((self.dim, self.n), dtype=torch.float64, device=self.device)
+        dw = torch.zeros((self.dr, self.n), dtype=torch.float64, device=self.device)
+        self._check(self.L.cd_adjoint_static(self.h, _ptr(g), _ptr(dmu), _ptr(dv), _ptr(dw)))
         return dmu[:nc], dv, dw
 
 

@@ -28,6 +28,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "sweep_core.h"
@@ -534,6 +536,12 @@ __global__ __launch_bounds__(kT) void k_adjoint_out(int64_t nc, int64_t n, const
 
 int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, (n + kT - 1) / kT); }
 
+// zeroes `words` 4-byte words (every buffer cleared here is a whole number of them)
+__global__ __launch_bounds__(kT) void k_zero_words(unsigned* p, int64_t words) {
+  const int64_t x = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (x < words) p[x] = 0u;
+}
+
 }  // namespace
 
 hipError_t cd_launch_mu_scatter(cd_ctx* c, const double* mu) {
@@ -615,35 +623,92 @@ void cd_adjoint_release(cd_ctx* c) {
   c->adj = nullptr;
 }
 
-extern "C" {
+// ---- allocation-free variant (cd_adjoint_static) --------------------------
+// The reverse pass's workspace carved from one file-scope device array per
+// GPU instead of hipMalloc'ed buffers.  Each device holds its own copy from
+// the module's load until the process ends; its address comes from
+// hipGetSymbolAddress with that device current, once per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;   // 64 MiB per device
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device (nullptr on failure)
+int scratch_address(cd_ctx* c, unsigned char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return cd_fail(c, CD_EHIP, "no current device for the static workspace");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return cd_fail(c, CD_EHIP, "hipGetSymbolAddress of the static workspace failed");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (unsigned char*)g_scratch_ptr[dev];
+  return CD_OK;
+}
+
+// Bytes of the reverse pass's workspace for this context and its layout in a
+// block at `base` (nullptr: size only), 256-byte aligned pieces.
+size_t carve_work(AdjointWork* w, unsigned char* base, int64_t cap, int64_t n, int C) {
+  const int64_t E = 2 * cap;
+  size_t off = 0;
+  auto take = [&](auto** p, int64_t count, size_t elem) {
+    const size_t bytes = ((size_t)std::max<int64_t>(count, 1) * elem + 255) / 256 * 256;
+    if (base) *p = (std::remove_reference_t<decltype(**p)>*)(base + off);
+    off += bytes;
+  };
+  take(&w->lam[0], 2 * cap, sizeof(double));
+  take(&w->lam[1], 2 * cap, sizeof(double));
+  take(&w->own, 2 * cap, sizeof(double));
+  take(&w->gE, 3 * E, sizeof(double));
+  take(&w->gmu, cap, sizeof(double));
+  take(&w->gn, 2 * cap, sizeof(double));
+  take(&w->ggdt, cap, sizeof(double));
+  take(&w->GV, 3 * n, sizeof(double));
+  take(&w->gv, 3 * n, sizeof(double));
+  take(&w->gx, 2 * n, sizeof(double));
+  take(&w->gv_next, 3 * n, sizeof(double));
+  take(&w->gx_next, 2 * n, sizeof(double));
+  take(&w->gvt, 2 * n, sizeof(double));
+  take(&w->p2e_cnt, n + 1, sizeof(int));
+  take(&w->p2e_ptr, n + 1, sizeof(int));
+  take(&w->p2e, E, sizeof(int));
+  take(&w->seg, (int64_t)C * 4 * cap, sizeof(double));
+  take(&w->state, 1, sizeof(SolveState));
+  if (base) {
+    w->cap = cap;
+    w->n = n;
+    w->seg_cap = (int64_t)C * 4 * cap;
+  }
+  return off;
+}
+
+}  // namespace
 
 // Reverse of every step of the recorded window, last to first.  For step t:
 // the Euler update's reverse (from the adjoints of x, v, w at step t+1), the
 // solve's reverse (seeded with the adjoint of its final forces), the
 // geometry's reverse; the adjoint of the step's starting forces (its warm
-// start) seeds the previous step's final forces.
-int cd_adjoint(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv, double* dL_dw) {
-  if (!c || !dL_dR) return CD_EINVAL;
-  if (c->dim != 2) return cd_fail(c, CD_EINVAL, "the adjoint is implemented for 2D");
-  if (!c->adj_valid || c->win.empty() || c->win.back().K < 1)
-    return cd_fail(c, CD_ENOTREADY,
-                   "cd_adjoint needs a solve recorded with cd_set_adjoint and fixed_iters");
-  if (c->sweep_global)
-    return cd_fail(c, CD_ECAPACITY, "the adjoint needs every domain in LDS");
+// start) seeds the previous step's final forces.  `fixed`: the workspace w
+// is in place already (the static variant) and nothing is allocated here.
+static int adjoint_run(cd_ctx* c, AdjointWork* w, bool fixed, const double* dL_dR,
+                       double* dL_dmu, double* dL_dv, double* dL_dw) {
   const int64_t nc = c->nc, n = c->n, cap = c->cap, E = 2 * cap;
   const int C = c->adj_every;
   const int T = (int)c->win.size();
   const double dt = c->p.dt;
   const int clamp = c->p.overlap_mode == 0;
   hipStream_t st = c->stream;
-  // LDS of the reverse sweep: particle records, tape, particle adjoints
   const int np_max = std::max(c->st_ds.max_particles, 1);
   const size_t lds = sizeof(double) * ((size_t)Layout<2>::PS * np_max +
                                        6 * (size_t)c->st_ds.max_contacts + 3 * (size_t)np_max);
-  if (lds + 2048 > c->max_lds)
-    return cd_fail(c, CD_ECAPACITY, "a domain is too large for the adjoint");
-  if (!c->adj) c->adj = new AdjointWork();
-  AdjointWork* w = c->adj;
   auto TRYH = [&](hipError_t e) {
     return e == hipSuccess ? CD_OK : cd_fail(c, CD_EHIP, hipGetErrorString(e));
   };
@@ -652,54 +717,63 @@ int cd_adjoint(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv, do
     int r_ = TRYH(expr);        \
     if (r_ != CD_OK) return r_; \
   } while (0)
-  if (w->cap < cap || w->n < n) {
-    ATRY(alloc_n(&w->lam[0], 2 * cap));
-    ATRY(alloc_n(&w->lam[1], 2 * cap));
-    ATRY(alloc_n(&w->own, 2 * cap));
-    ATRY(alloc_n(&w->gE, 3 * E));
-    ATRY(alloc_n(&w->gmu, cap));
-    ATRY(alloc_n(&w->gn, 2 * cap));
-    ATRY(alloc_n(&w->ggdt, cap));
-    ATRY(alloc_n(&w->GV, 3 * n));
-    ATRY(alloc_n(&w->gv, 3 * n));
-    ATRY(alloc_n(&w->gx, 2 * n));
-    ATRY(alloc_n(&w->gv_next, 3 * n));
-    ATRY(alloc_n(&w->gx_next, 2 * n));
-    ATRY(alloc_n(&w->gvt, 2 * n));
-    ATRY(alloc_n(&w->p2e_cnt, n + 1));
-    ATRY(alloc_n(&w->p2e_ptr, n + 1));
-    ATRY(alloc_n(&w->p2e, E));
-    w->cap = cap;
-    w->n = n;
+  // zeroed with a fill kernel (no memset nodes if a caller captures the stream)
+  auto zero = [&](void* p, size_t bytes) {
+    const int64_t words = (int64_t)(bytes / sizeof(unsigned));
+    if (words > 0)
+      hipLaunchKernelGGL(k_zero_words, dim3(blocks_for(words)), dim3(kT), 0, st, (unsigned*)p,
+                         words);
+    return hipGetLastError();
+  };
+  if (!fixed) {
+    if (w->cap < cap || w->n < n) {
+      ATRY(alloc_n(&w->lam[0], 2 * cap));
+      ATRY(alloc_n(&w->lam[1], 2 * cap));
+      ATRY(alloc_n(&w->own, 2 * cap));
+      ATRY(alloc_n(&w->gE, 3 * E));
+      ATRY(alloc_n(&w->gmu, cap));
+      ATRY(alloc_n(&w->gn, 2 * cap));
+      ATRY(alloc_n(&w->ggdt, cap));
+      ATRY(alloc_n(&w->GV, 3 * n));
+      ATRY(alloc_n(&w->gv, 3 * n));
+      ATRY(alloc_n(&w->gx, 2 * n));
+      ATRY(alloc_n(&w->gv_next, 3 * n));
+      ATRY(alloc_n(&w->gx_next, 2 * n));
+      ATRY(alloc_n(&w->gvt, 2 * n));
+      ATRY(alloc_n(&w->p2e_cnt, n + 1));
+      ATRY(alloc_n(&w->p2e_ptr, n + 1));
+      ATRY(alloc_n(&w->p2e, E));
+      w->cap = cap;
+      w->n = n;
+    }
+    if (w->seg_cap < (int64_t)C * 4 * cap) {
+      ATRY(alloc_n(&w->seg, (int64_t)C * 4 * cap));
+      w->seg_cap = (int64_t)C * 4 * cap;
+    }
+    if (!w->state) ATRY(alloc_n(&w->state, 1));
   }
-  if (w->seg_cap < (int64_t)C * 4 * cap) {
-    ATRY(alloc_n(&w->seg, (int64_t)C * 4 * cap));
-    w->seg_cap = (int64_t)C * 4 * cap;
-  }
-  if (!w->state) {
-    ATRY(alloc_n(&w->state, 1));
-    SolveState s0{};
-    s0.done = 0;
-    ATRY(hipMemcpy(w->state, &s0, sizeof(SolveState), hipMemcpyHostToDevice));
-  }
-  ATRY(hipMemsetAsync(w->gmu, 0, sizeof(double) * cap, st));
-  ATRY(hipMemsetAsync(w->gE, 0, sizeof(double) * 3 * E, st));
-  ATRY(hipMemsetAsync(w->gv_next, 0, sizeof(double) * 3 * n, st));
-  ATRY(hipMemsetAsync(w->gx_next, 0, sizeof(double) * 2 * n, st));
-  ATRY(hipMemsetAsync(w->lam[0], 0, sizeof(double) * 2 * cap, st));
+  // the recomputing sweeps run "open" (done = 0): a zeroed state
+  ATRY(zero(w->state, sizeof(SolveState)));
+  ATRY(zero(w->gmu, sizeof(double) * cap));
+  ATRY(zero(w->gE, sizeof(double) * 3 * E));
+  ATRY(zero(w->gv_next, sizeof(double) * 3 * n));
+  ATRY(zero(w->gx_next, sizeof(double) * 2 * n));
+  ATRY(zero(w->lam[0], sizeof(double) * 2 * cap));
   if (nc > 0) {
     hipLaunchKernelGGL(k_lambda_init, dim3(blocks_for(nc)), dim3(kT), 0, st, dL_dR,
                        c->contact_slot, nc, w->lam[0]);
     ATRY(hipGetLastError());
   }
-  // entries of each particle (the same for every step of the window)
-  int dp_total = 0;
-  ATRY(hipMemcpy(&dp_total, c->dp_start + c->P, sizeof(int), hipMemcpyDeviceToHost));
-  ATRY(hipMemsetAsync(w->p2e_cnt, 0, sizeof(int) * (n + 1), st));
+  // entries of each particle (the same for every step of the window); the
+  // count comes back through the pinned scratch
+  ATRY(hipMemcpyAsync(c->h_scratch, c->dp_start + c->P, sizeof(int), hipMemcpyDeviceToHost, st));
+  ATRY(hipStreamSynchronize(st));
+  const int dp_total = ((const int*)c->h_scratch)[0];
+  ATRY(zero(w->p2e_cnt, sizeof(int) * (n + 1)));
   hipLaunchKernelGGL(k_p2e_count, dim3(blocks_for(dp_total)), dim3(kT), 0, st, c->dp,
                      (int64_t)dp_total, w->p2e_cnt);
   ATRY(cd_scan_exclusive(c, w->p2e_cnt, w->p2e_ptr, n));
-  ATRY(hipMemsetAsync(w->p2e_cnt, 0, sizeof(int) * (n + 1), st));
+  ATRY(zero(w->p2e_cnt, sizeof(int) * (n + 1)));
   hipLaunchKernelGGL(k_p2e_fill, dim3(blocks_for(dp_total)), dim3(kT), 0, st, c->dp,
                      (int64_t)dp_total, w->p2e_ptr, w->p2e_cnt, w->p2e);
   hipLaunchKernelGGL(k_p2e_sort, dim3(blocks_for(n)), dim3(kT), 0, st, n, w->p2e_ptr, w->p2e);
@@ -716,9 +790,9 @@ int cd_adjoint(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv, do
     hipLaunchKernelGGL(k_dpb_base, dim3(blocks_for(E)), dim3(kT), 0, st, c->dp, c->dp_start, c->P,
                        E, r.v, r.w, n, c->dpb);
     ATRY(hipGetLastError());
-    ATRY(hipMemsetAsync(w->gv, 0, sizeof(double) * 3 * n, st));
-    ATRY(hipMemsetAsync(w->gn, 0, sizeof(double) * 2 * cap, st));
-    ATRY(hipMemsetAsync(w->ggdt, 0, sizeof(double) * cap, st));
+    ATRY(zero(w->gv, sizeof(double) * 3 * n));
+    ATRY(zero(w->gn, sizeof(double) * 2 * cap));
+    ATRY(zero(w->ggdt, sizeof(double) * cap));
     // the Euler update of step t (x, v, w of step t+1 depend on its forces)
     if (t < T - 1) {
       hipLaunchKernelGGL(k_euler_prep, dim3(blocks_for(n)), dim3(kT), 0, st, n, dt, w->gv_next,
@@ -735,7 +809,7 @@ int cd_adjoint(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv, do
       ATRY(hipMemcpyAsync(w->gx, w->gx_next, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice,
                           st));
     } else {
-      ATRY(hipMemsetAsync(w->gx, 0, sizeof(double) * 2 * n, st));
+      ATRY(zero(w->gx, sizeof(double) * 2 * n));
     }
     // the solve of step t, sweep by sweep from the last
     SweepArgs a = cd_sweep_args(c);
@@ -782,6 +856,53 @@ int cd_adjoint(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv, do
   ATRY(hipStreamSynchronize(st));
 #undef ATRY
   return CD_OK;
+}
+
+// The checks both entry points make before any work.
+static int adjoint_check(cd_ctx* c, const double* dL_dR) {
+  if (!c || !dL_dR) return CD_EINVAL;
+  if (c->dim != 2) return cd_fail(c, CD_EINVAL, "the adjoint is implemented for 2D");
+  if (!c->adj_valid || c->win.empty() || c->win.back().K < 1)
+    return cd_fail(c, CD_ENOTREADY,
+                   "cd_adjoint needs a solve recorded with cd_set_adjoint and fixed_iters");
+  if (c->sweep_global)
+    return cd_fail(c, CD_ECAPACITY, "the adjoint needs every domain in LDS");
+  const int np_max = std::max(c->st_ds.max_particles, 1);
+  const size_t lds = sizeof(double) * ((size_t)Layout<2>::PS * np_max +
+                                       6 * (size_t)c->st_ds.max_contacts + 3 * (size_t)np_max);
+  if (lds + 2048 > c->max_lds)
+    return cd_fail(c, CD_ECAPACITY, "a domain is too large for the adjoint");
+  return CD_OK;
+}
+
+extern "C" {
+
+int cd_adjoint(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv, double* dL_dw) {
+  const int st = adjoint_check(c, dL_dR);
+  if (st != CD_OK) return st;
+  if (!c->adj) c->adj = new AdjointWork();
+  return adjoint_run(c, c->adj, false, dL_dR, dL_dmu, dL_dv, dL_dw);
+}
+
+int cd_adjoint_static(cd_ctx* c, const double* dL_dR, double* dL_dmu, double* dL_dv,
+                      double* dL_dw) {
+  int st = adjoint_check(c, dL_dR);
+  if (st != CD_OK) return st;
+  AdjointWork w;
+  const size_t need = carve_work(&w, nullptr, c->cap, c->n, c->adj_every);
+  if (need > kScratchBytes)
+    return cd_fail(c, CD_ECAPACITY,
+                   "cd_adjoint_static: the workspace exceeds the 64 MiB static array "
+                   "(fewer contacts or particles, or a shorter checkpoint interval)");
+  // the prefix scan's status words belong to the context; the forward steps
+  // sized them for at least n + 1 entries, which is checked here
+  if (c->scan_tmp_cap < (c->n + 2048 - 1) / 2048 + 1)
+    return cd_fail(c, CD_ECAPACITY, "cd_adjoint_static: scan workspace not sized by a step");
+  unsigned char* base = nullptr;
+  st = scratch_address(c, &base);
+  if (st != CD_OK) return st;
+  carve_work(&w, base, c->cap, c->n, c->adj_every);
+  return adjoint_run(c, &w, true, dL_dR, dL_dmu, dL_dv, dL_dw);
 }
 
 }  // extern "C"
