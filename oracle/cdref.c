@@ -59,15 +59,33 @@ static void contact_frame(int dim, const double* normal, int64_t nc, int64_t c,
   }
 }
 
-/* gap between particle i and body j (particle or wall), Sec. 2.1 / Fig. 1 */
+/* Separation along a periodic axis of length L (the benchmark boxes of
+ * Sec. 4.1 are periodic in x): the nearest image, |d| <= L/2. */
+static double min_image(double d, double L) {
+  if (d > 0.5 * L) return d - L;
+  if (d < -0.5 * L) return d + L;
+  return d;
+}
+
+/* A coordinate back into [lo, lo + L) after it left by less than L. */
+static double wrap_into(double q, double lo, double L) {
+  if (q >= lo + L) return q - L;
+  if (q < lo) return q + L;
+  return q;
+}
+
+/* gap between particle i and body j (particle or wall), Sec. 2.1 / Fig. 1;
+ * period (NULL: none) holds the length of each periodic axis, 0 for open
+ * ones, and particle pairs are taken at their nearest image */
 static double pair_gap(int dim, int64_t n, const double* x, const double* r,
                        const double* wall_normal, const double* wall_offset,
-                       int64_t i, int64_t j, double nrm[3]) {
+                       int64_t i, int64_t j, double nrm[3], const double* period) {
   if (j < n) {
     double delta[3] = {0, 0, 0};
     double d2 = 0.0;
     for (int k = 0; k < dim; ++k) {
       delta[k] = x[k * n + j] - x[k * n + i];
+      if (period && period[k] > 0.0) delta[k] = min_image(delta[k], period[k]);
       d2 = d2 + delta[k] * delta[k];
     }
     double dist = sqrt(d2);
@@ -95,18 +113,26 @@ int cdref_detect(int dim, int64_t n, const double* x, const double* r,
                  int n_walls, const double* wall_normal, const double* wall_offset,
                  double skin, int use_cells, const double* box_lo, const double* box_hi,
                  int64_t cap, int32_t* ci, int32_t* cj, int64_t* nc) {
+  return cdref_detect_bc(dim, n, x, r, n_walls, wall_normal, wall_offset, skin, use_cells,
+                         box_lo, box_hi, NULL, cap, ci, cj, nc);
+}
+
+int cdref_detect_bc(int dim, int64_t n, const double* x, const double* r,
+                    int n_walls, const double* wall_normal, const double* wall_offset,
+                    double skin, int use_cells, const double* box_lo, const double* box_hi,
+                    const double* period, int64_t cap, int32_t* ci, int32_t* cj, int64_t* nc) {
   int64_t count = 0;
   if (dim != 2 && dim != 3) return CDREF_EINVAL;
   if (!use_cells) {
     for (int64_t i = 0; i < n; ++i) {
       for (int64_t j = i + 1; j < n; ++j) {
-        if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, j, NULL) <= skin) {
+        if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, j, NULL, period) <= skin) {
           if (count < cap) { ci[count] = (int32_t)i; cj[count] = (int32_t)j; }
           ++count;
         }
       }
       for (int w = 0; w < n_walls; ++w) {
-        if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, n + w, NULL) <= skin) {
+        if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, n + w, NULL, period) <= skin) {
           if (count < cap) { ci[count] = (int32_t)i; cj[count] = (int32_t)(n + w); }
           ++count;
         }
@@ -129,6 +155,9 @@ int cdref_detect(int dim, int64_t n, const double* x, const double* r,
     if (m > 4096) m = 4096;
     ncell[k] = m;
     width[k] = len / (double)m;
+    /* a periodic axis needs three cells so that the neighbour cells of a
+       cell are distinct and a pair is seen at one image only */
+    if (period && period[k] > 0.0 && m < 3) return CDREF_EINVAL;
   }
   int64_t total = ncell[0] * ncell[1] * ncell[2];
   int64_t* cell = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
@@ -163,13 +192,17 @@ int cdref_detect(int dim, int64_t n, const double* x, const double* r,
       for (int64_t dy = -1; dy <= 1; ++dy) {
         for (int64_t dx = -1; dx <= 1; ++dx) {
           int64_t qx = cx + dx, qy = cy + dy, qz = cz + dz;
+          /* periodic axes: the neighbour cells wrap around */
+          if (period && period[0] > 0.0) qx = (qx + ncell[0]) % ncell[0];
+          if (period && dim > 1 && period[1] > 0.0) qy = (qy + ncell[1]) % ncell[1];
+          if (period && dim > 2 && period[2] > 0.0) qz = (qz + ncell[2]) % ncell[2];
           if (qx < 0 || qy < 0 || qz < 0 || qx >= ncell[0] || qy >= ncell[1] || qz >= ncell[2])
             continue;
           int64_t q = (qz * ncell[1] + qy) * ncell[0] + qx;
           for (int64_t s = start[q]; s < start[q + 1]; ++s) {
             int64_t j = members[s];
             if (j <= i) continue;
-            if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, j, NULL) <= skin)
+            if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, j, NULL, period) <= skin)
               cand[ncand++] = (int32_t)j;
           }
         }
@@ -181,7 +214,7 @@ int cdref_detect(int dim, int64_t n, const double* x, const double* r,
       ++count;
     }
     for (int w = 0; w < n_walls; ++w) {
-      if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, n + w, NULL) <= skin) {
+      if (pair_gap(dim, n, x, r, wall_normal, wall_offset, i, n + w, NULL, period) <= skin) {
         if (count < cap) { ci[count] = (int32_t)i; cj[count] = (int32_t)(n + w); }
         ++count;
       }
@@ -196,16 +229,28 @@ void cdref_geometry(int dim, int64_t n, const double* x, const double* r,
                     int n_walls, const double* wall_normal, const double* wall_offset,
                     int64_t nc, const int32_t* ci, const int32_t* cj,
                     double* normal, double* gap, double* xmid) {
+  cdref_geometry_bc(dim, n, x, r, n_walls, wall_normal, wall_offset, NULL, NULL, nc, ci, cj,
+                    normal, gap, xmid);
+}
+
+void cdref_geometry_bc(int dim, int64_t n, const double* x, const double* r,
+                       int n_walls, const double* wall_normal, const double* wall_offset,
+                       const double* period, const double* box_lo, int64_t nc,
+                       const int32_t* ci, const int32_t* cj, double* normal, double* gap,
+                       double* xmid) {
   (void)n_walls;
   for (int64_t c = 0; c < nc; ++c) {
     double nrm[3];
     int64_t i = ci[c], j = cj[c];
-    double g = pair_gap(dim, n, x, r, wall_normal, wall_offset, i, j, nrm);
+    double g = pair_gap(dim, n, x, r, wall_normal, wall_offset, i, j, nrm, period);
     gap[c] = g;
     double lever = r[i] + 0.5 * g;   /* middle of the gap, Sec. 3.1 */
     for (int k = 0; k < dim; ++k) {
       normal[k * nc + c] = nrm[k];
       xmid[k * nc + c] = x[k * n + i] + lever * nrm[k];
+      /* on a periodic axis the position is taken back into the box */
+      if (period && period[k] > 0.0)
+        xmid[k * nc + c] = wrap_into(xmid[k * nc + c], box_lo[k], period[k]);
     }
   }
 }
@@ -810,8 +855,17 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
                       const double* normal, const double* gap, const double* mu_c,
                       const uint8_t* parallel, const uint64_t* step_key, int P,
                       const int64_t* dom_start, const int32_t* slot_contact, double* R,
-                      cdref_info* info, double* history) {
+                      cdref_info* info, double* history, const cdref_mobile_walls* mw) {
   int dim = p->dim, dr = dim == 2 ? 1 : 3;
+  /* walls whose normal motion follows from the forces (finite mass) */
+  const int W = p->n_walls;
+  double dtiM[CDREF_MAX_WALLS] = {0};
+  int any_mobile = 0;
+  if (mw && W > CDREF_MAX_WALLS) return CDREF_EINVAL;
+  for (int q = 0; q < W && mw; ++q) {
+    dtiM[q] = p->dt * mw->inv_mass[q];
+    if (mw->inv_mass[q] != 0.0) any_mobile = 1;
+  }
   int64_t nn = n > 0 ? n : 1, ncc = nc > 0 ? nc : 1;
   memset(info, 0, sizeof(*info));
   info->n_contacts = nc;
@@ -827,13 +881,19 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
   double* Wd = (double*)malloc(sizeof(double) * (size_t)(dr * nn) * (size_t)threads);
   double* dtim = (double*)malloc(sizeof(double) * (size_t)nn);
   double* dtii = (double*)malloc(sizeof(double) * (size_t)nn);
+  /* the walls' velocities: after the exchange (Uex) and each thread's
+     private copy (Ut) that its domain's contacts update */
+  double Uex[CDREF_MAX_WALLS * 3] = {0};
+  double* Ut = (double*)malloc(sizeof(double) * (size_t)(CDREF_MAX_WALLS * 3) * (size_t)threads);
   rand_slot* ord =
       step_key ? (rand_slot*)malloc(sizeof(rand_slot) * (size_t)ncc * (size_t)threads) : NULL;
-  if (!cc || !Rprev || !Vg || !Wg || !Vd || !Wd || !dtim || !dtii || (step_key && !ord)) {
+  if (!cc || !Rprev || !Vg || !Wg || !Vd || !Wd || !dtim || !dtii || !Ut ||
+      (step_key && !ord)) {
     free(cc); free(Rprev); free(Vg); free(Wg); free(Vd); free(Wd); free(dtim); free(dtii);
-    free(ord);
+    free(ord); free(Ut);
     return CDREF_ENOMEM;
   }
+  for (int q = 0; q < W * dim; ++q) Uex[q] = wall_velocity ? wall_velocity[q] : 0.0;
   for (int64_t i = 0; i < n; ++i) {
     dtim[i] = dt * (1.0 / m[i]);
     dtii[i] = dt * (1.0 / inertia[i]);
@@ -845,6 +905,12 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
     double wn = 1.0 / m[a] + (b < n ? 1.0 / m[b] : 0.0);
     double wt = wn + (r[a] * r[a]) * (1.0 / inertia[a]);
     wt = wt + (b < n ? (r[b] * r[b]) * (1.0 / inertia[b]) : 0.0);
+    if (b >= n && mw && mw->inv_mass[b - n] != 0.0) {
+      /* a wall of finite mass moves along its normal only: it adds 1/M to
+         the normal term and nothing to the tangential one */
+      wn = 1.0 / m[a] + mw->inv_mass[b - n];
+      wt = 1.0 / m[a] + (r[a] * r[a]) * (1.0 / inertia[a]);
+    }
     double ge = gap[c];
     if (p->overlap_mode == 0 && ge < 0.0) ge = 0.0;
     cc[c].gdt = ge / dt;
@@ -871,6 +937,8 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
     memcpy(Rprev, R, sizeof(double) * (size_t)(dim * nc));
     /* exchange: every particle's velocity from the forces of sweep j-1 */
     cdref_velocities(dim, n, dt, v, w, m, inertia, r, f, t, nc, ci, cj, normal, Rprev, Vg, Wg);
+    /* ... and every wall's of finite mass */
+    if (any_mobile) cdref_wall_velocities(dim, n, dt, W, wall_velocity, mw, nc, cj, Rprev, Uex);
     /* each domain sweeps its native contacts sequentially on a private copy
        of the velocities; other domains' contacts keep their sweep j-1 value.
        The domains of a sweep are independent: with threads > 1 they are
@@ -885,6 +953,9 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
 #endif
       double* Vt = Vd + (int64_t)tid * dim * nn;
       double* Wt = Wd + (int64_t)tid * dr * nn;
+      /* the domain's own copy of the walls' velocities */
+      double* Uw = Ut + (int64_t)tid * CDREF_MAX_WALLS * 3;
+      for (int q = 0; q < W * dim; ++q) Uw[q] = Uex[q];
       rand_slot* od = ord ? ord + (int64_t)tid * ncc : NULL;
       const int64_t len = dom_start[d + 1] - dom_start[d];
       /* the domain starts from the exchanged velocities of its bodies */
@@ -928,7 +999,7 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
           for (int k = 0; k < dr; ++k) Wb[k] = Wt[k * n + b];
           rb = r[b];
         } else {
-          for (int k = 0; k < dim; ++k) Vb[k] = wall_velocity[(b - n) * dim + k];
+          for (int k = 0; k < dim; ++k) Vb[k] = Uw[(b - n) * dim + k];
         }
         double Rold[3] = {0, 0, 0}, Rnew[3];
         for (int k = 0; k < dim; ++k) Rold[k] = R[k * nc + c];
@@ -950,6 +1021,10 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
         if (b < n) {
           for (int k = 0; k < dim; ++k) Vt[k * n + b] = Vt[k * n + b] + dtim[b] * dF[k];
           for (int k = 0; k < dr; ++k) Wt[k * n + b] = Wt[k * n + b] - dtii[b] * (r[b] * dq[k]);
+        } else if (dtiM[b - n] != 0.0) {
+          /* a wall of finite mass takes the normal part of the change */
+          for (int k = 0; k < dim; ++k)
+            Uw[(b - n) * dim + k] = Uw[(b - n) * dim + k] + dtiM[b - n] * (dRn * nv[k]);
         }
       }
     }
@@ -980,7 +1055,7 @@ static int solve_impl(const cdref_params* p, int64_t n, const double* v, const d
   }
   info->status = status;
   free(cc); free(Rprev); free(Vg); free(Wg); free(Vd); free(Wd); free(dtim); free(dtii);
-  free(ord);
+  free(ord); free(Ut);
   return status;
 }
 
@@ -993,7 +1068,7 @@ int cdref_solve_mixed(const cdref_params* p, int64_t n, const double* v, const d
                       const int32_t* slot_contact, double* R, cdref_info* info,
                       double* history) {
   return solve_impl(p, n, v, w, r, m, inertia, f, t, wall_velocity, nc, ci, cj, normal, gap,
-                    mu_c, parallel, NULL, P, dom_start, slot_contact, R, info, history);
+                    mu_c, parallel, NULL, P, dom_start, slot_contact, R, info, history, NULL);
 }
 
 int cdref_solve_random(const cdref_params* p, int64_t n, const double* v, const double* w,
@@ -1005,7 +1080,44 @@ int cdref_solve_random(const cdref_params* p, int64_t n, const double* v, const 
                        int64_t step, double* R, cdref_info* info, double* history) {
   const uint64_t key = cdref_random_step_key(seed, step);
   return solve_impl(p, n, v, w, r, m, inertia, f, t, wall_velocity, nc, ci, cj, normal, gap,
-                    mu_c, NULL, &key, P, dom_start, slot_contact, R, info, history);
+                    mu_c, NULL, &key, P, dom_start, slot_contact, R, info, history, NULL);
+}
+
+int cdref_solve_bc(const cdref_params* p, int64_t n, const double* v, const double* w,
+                   const double* r, const double* m, const double* inertia,
+                   const double* f, const double* t, const double* wall_velocity,
+                   int64_t nc, const int32_t* ci, const int32_t* cj,
+                   const double* normal, const double* gap, const double* mu_c,
+                   const uint8_t* parallel, int P, const int64_t* dom_start,
+                   const int32_t* slot_contact, const cdref_mobile_walls* mw, double* R,
+                   cdref_info* info, double* history) {
+  return solve_impl(p, n, v, w, r, m, inertia, f, t, wall_velocity, nc, ci, cj, normal, gap,
+                    mu_c, parallel, NULL, P, dom_start, slot_contact, R, info, history, mw);
+}
+
+/* Velocities of the walls after forces R (Eq. 1 for a wall body): a wall of
+ * finite mass M under the external force F along its normal nu has normal
+ * velocity u_n + dt/M (F - sum of R_n over its contacts, ascending contact
+ * id; the force on the wall along nu is -R_n since n = -nu), its tangential
+ * velocity stays prescribed; other walls keep their velocity. */
+void cdref_wall_velocities(int dim, int64_t n, double dt, int W, const double* wall_velocity,
+                           const cdref_mobile_walls* mw, int64_t nc, const int32_t* cj,
+                           const double* R, double* U) {
+  for (int q = 0; q < W; ++q) {
+    const double* u = wall_velocity + q * dim;
+    if (!mw || mw->inv_mass[q] == 0.0) {
+      for (int k = 0; k < dim; ++k) U[q * dim + k] = u[k];
+      continue;
+    }
+    const double* nu = mw->normal + q * dim;
+    double un = 0.0;
+    for (int k = 0; k < dim; ++k) un = un + nu[k] * u[k];
+    double acc = mw->force[q];
+    for (int64_t c = 0; c < nc; ++c)
+      if (cj[c] == n + q) acc = acc - R[c];
+    const double un1 = un + (dt * mw->inv_mass[q]) * acc;
+    for (int k = 0; k < dim; ++k) U[q * dim + k] = (u[k] - un * nu[k]) + un1 * nu[k];
+  }
 }
 
 /* ------------------------------------------------------------------ */
@@ -1029,6 +1141,11 @@ struct cdref_sim {
   uint64_t mixed_seed;
   int rand_on;        /* random sequential order (Sec. 2.1) */
   uint64_t rand_seed;
+  /* boundary conditions of the benchmark setups (Sec. 4.1, Sec. 4.4) */
+  double period[3];   /* > 0: periodic axis of this length */
+  int has_period;
+  double wall_inv_mass[CDREF_MAX_WALLS], wall_force[CDREF_MAX_WALLS];
+  int has_mobile;
   /* contacts of the last step */
   int64_t nc, cap;
   int32_t *ci, *cj, *dom, *color, *slot;
@@ -1086,6 +1203,35 @@ void cdref_sim_destroy(cdref_sim* s) {
   free(s->normal); free(s->gap); free(s->xmid); free(s->R);
   free(s->capacity);
   free(s);
+}
+
+int cdref_sim_set_bc(cdref_sim* s, int periodic_mask, const double* wall_inv_mass,
+                     const double* wall_force) {
+  const int dim = s->p.dim, W = s->p.n_walls;
+  if (W > CDREF_MAX_WALLS) return CDREF_EINVAL;
+  s->has_period = 0;
+  for (int k = 0; k < 3; ++k) {
+    s->period[k] = 0.0;
+    if (k < dim && (periodic_mask >> k) & 1) {
+      s->period[k] = s->hi[k] - s->lo[k];
+      s->has_period = 1;
+      /* no wall may bound a periodic axis */
+      for (int q = 0; q < W; ++q)
+        if (s->wn[q * dim + k] != 0.0) return CDREF_EINVAL;
+    }
+  }
+  s->has_mobile = 0;
+  for (int q = 0; q < CDREF_MAX_WALLS; ++q) {
+    s->wall_inv_mass[q] = (wall_inv_mass && q < W) ? wall_inv_mass[q] : 0.0;
+    s->wall_force[q] = (wall_force && q < W) ? wall_force[q] : 0.0;
+    if (s->wall_inv_mass[q] < 0.0) return CDREF_EINVAL;
+    if (s->wall_inv_mass[q] != 0.0) s->has_mobile = 1;
+  }
+  return CDREF_OK;
+}
+
+void cdref_sim_wall_velocities(const cdref_sim* s, double* U) {
+  for (int q = 0; q < s->p.n_walls * s->p.dim; ++q) U[q] = s->wu[q];
 }
 
 void cdref_sim_set_mixed(cdref_sim* s, double p, uint64_t seed) {
@@ -1175,14 +1321,15 @@ int cdref_sim_step(cdref_sim* s, cdref_info* info) {
     int64_t guess = s->cap > 0 ? s->cap : 4 * n + 64;
     int32_t* ci = (int32_t*)malloc(sizeof(int32_t) * (size_t)guess);
     int32_t* cj = (int32_t*)malloc(sizeof(int32_t) * (size_t)guess);
-    st = cdref_detect(dim, n, s->x, s->r, p->n_walls, s->wn, s->wo, skin, 1, s->lo, s->hi,
-                      guess, ci, cj, &nc);
+    const double* period = s->has_period ? s->period : NULL;
+    st = cdref_detect_bc(dim, n, s->x, s->r, p->n_walls, s->wn, s->wo, skin, 1, s->lo, s->hi,
+                         period, guess, ci, cj, &nc);
     if (st == CDREF_ECAPACITY) {
       free(ci); free(cj);
       ci = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
       cj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
-      st = cdref_detect(dim, n, s->x, s->r, p->n_walls, s->wn, s->wo, skin, 1, s->lo, s->hi,
-                        nc, ci, cj, &nc);
+      st = cdref_detect_bc(dim, n, s->x, s->r, p->n_walls, s->wn, s->wo, skin, 1, s->lo, s->hi,
+                           period, nc, ci, cj, &nc);
     }
     if (st != CDREF_OK) { free(ci); free(cj); free(old_ci); free(old_cj); free(old_R); return st; }
     int64_t keep_cap = s->cap;
@@ -1197,8 +1344,9 @@ int cdref_sim_step(cdref_sim* s, cdref_info* info) {
   }
   s->nc = nc;
   info->n_contacts = nc;
-  cdref_geometry(dim, n, s->x, s->r, p->n_walls, s->wn, s->wo, nc, s->ci, s->cj, s->normal,
-                 s->gap, s->xmid);
+  cdref_geometry_bc(dim, n, s->x, s->r, p->n_walls, s->wn, s->wo,
+                    s->has_period ? s->period : NULL, s->lo, nc, s->ci, s->cj, s->normal,
+                    s->gap, s->xmid);
   /* warm start: forces of the same pair in the previous step, else zero */
   s->R = (double*)calloc((size_t)(dim * (nc > 0 ? nc : 1)), sizeof(double));
   if (p->warm_start && old_R) {
@@ -1237,16 +1385,19 @@ int cdref_sim_step(cdref_sim* s, cdref_info* info) {
   }
   st = cdref_order_mixed(n, nc, s->ci, s->cj, P, s->dom, par, s->color, s->slot, dom_start);
   if (st != CDREF_OK) { free(dom_start); free(par); return st; }
+  cdref_mobile_walls mw = {s->wn, s->wall_inv_mass, s->wall_force};
+  const cdref_mobile_walls* mwp = s->has_mobile ? &mw : NULL;
   if (s->rand_on && par) {
     st = CDREF_EINVAL;   /* the random order has no parallel contacts */
   } else if (s->rand_on) {
-    st = cdref_solve_random(p, n, s->v, s->w, s->r, s->m, s->I, s->f, s->t, s->wu, nc, s->ci,
-                            s->cj, s->normal, s->gap, NULL, P, dom_start, s->slot,
-                            s->rand_seed, s->step, s->R, info, NULL);
+    const uint64_t key = cdref_random_step_key(s->rand_seed, s->step);
+    st = solve_impl(p, n, s->v, s->w, s->r, s->m, s->I, s->f, s->t, s->wu, nc, s->ci, s->cj,
+                    s->normal, s->gap, NULL, NULL, &key, P, dom_start, s->slot, s->R, info,
+                    NULL, mwp);
   } else {
-    st = cdref_solve_mixed(p, n, s->v, s->w, s->r, s->m, s->I, s->f, s->t, s->wu, nc, s->ci,
-                           s->cj, s->normal, s->gap, NULL, par, P, dom_start, s->slot, s->R,
-                           info, NULL);
+    st = solve_impl(p, n, s->v, s->w, s->r, s->m, s->I, s->f, s->t, s->wu, nc, s->ci, s->cj,
+                    s->normal, s->gap, NULL, par, NULL, P, dom_start, s->slot, s->R, info, NULL,
+                    mwp);
   }
   free(par);
   info->skin = skin;
@@ -1262,10 +1413,19 @@ int cdref_sim_step(cdref_sim* s, cdref_info* info) {
     for (int k = 0; k < dim; ++k) {
       s->v[k * n + i] = V[k * n + i];
       s->x[k * n + i] = s->x[k * n + i] + V[k * n + i] * p->dt;
+      /* a particle leaving a periodic box enters it on the other side */
+      if (s->has_period && s->period[k] > 0.0)
+        s->x[k * n + i] = wrap_into(s->x[k * n + i], s->lo[k], s->period[k]);
     }
     for (int k = 0; k < dr; ++k) s->w[k * n + i] = W[k * n + i];
   }
   free(V); free(W);
+  /* walls of finite mass: their velocity from the final forces (Eq. 1) */
+  if (s->has_mobile) {
+    double U[CDREF_MAX_WALLS * 3];
+    cdref_wall_velocities(dim, n, p->dt, p->n_walls, s->wu, mwp, nc, s->cj, s->R, U);
+    for (int q = 0; q < p->n_walls * dim; ++q) s->wu[q] = U[q];
+  }
   /* walls translate; a box face follows the wall lying on it */
   for (int wi = 0; wi < p->n_walls; ++wi) {
     double un = 0.0;

@@ -62,6 +62,22 @@ typedef struct {
   double skin;         /* < 0: 2 vmax dt */
 } cdref_params;
 
+#define CDREF_MAX_WALLS 8
+
+/* Walls whose motion along their normal follows from the contact forces: a
+ * wall of finite mass M under a constant external force F along its normal
+ * nu (the pressure-controlled confining walls of Sec. 4.1); its velocity
+ * along the wall stays prescribed (the shearing walls of Sec. 4.4).  In the
+ * solve such a wall is a body like a particle: each domain keeps its own
+ * copy of its velocity, updated by the domain's contacts with it, and the
+ * exchange recomputes it from all its contact forces of the previous sweep.
+ * inv_mass[w] = 0: the wall's motion is prescribed. */
+typedef struct {
+  const double* normal;     /* W x dim, unit, into the box */
+  const double* inv_mass;   /* W: 1/M */
+  const double* force;      /* W: F along nu */
+} cdref_mobile_walls;
+
 typedef struct {
   int status;
   int iterations;
@@ -84,12 +100,30 @@ int cdref_detect(int dim, int64_t n, const double* x, const double* r,
                  double skin, int use_cells, const double* box_lo, const double* box_hi,
                  int64_t cap, int32_t* ci, int32_t* cj, int64_t* nc);
 
+/* cdref_detect in a box with periodic axes (the benchmark boxes of Sec. 4.1
+ * are periodic in x): period[k] > 0 is the length of axis k, which must
+ * equal box_hi[k] - box_lo[k]; particle pairs are taken at their nearest
+ * image and the cells wrap around (at least three along a periodic axis,
+ * else CDREF_EINVAL).  period = NULL: as cdref_detect. */
+int cdref_detect_bc(int dim, int64_t n, const double* x, const double* r,
+                    int n_walls, const double* wall_normal, const double* wall_offset,
+                    double skin, int use_cells, const double* box_lo, const double* box_hi,
+                    const double* period, int64_t cap, int32_t* ci, int32_t* cj, int64_t* nc);
+
 /* Per-contact geometry (Sec. 2.1, Fig. 1): unit normal n (dim x nc), gap g
  * and the contact position at the middle of the gap (Sec. 3.1). */
 void cdref_geometry(int dim, int64_t n, const double* x, const double* r,
                     int n_walls, const double* wall_normal, const double* wall_offset,
                     int64_t nc, const int32_t* ci, const int32_t* cj,
                     double* normal, double* gap, double* xmid);
+
+/* cdref_geometry with periodic axes: the nearest image of each particle
+ * pair, the contact position taken back into [box_lo, box_lo + period). */
+void cdref_geometry_bc(int dim, int64_t n, const double* x, const double* r,
+                       int n_walls, const double* wall_normal, const double* wall_offset,
+                       const double* period, const double* box_lo, int64_t nc,
+                       const int32_t* ci, const int32_t* cj, double* normal, double* gap,
+                       double* xmid);
 
 /* Hierarchical bisection tree for P leaves (Sec. 3.2, Fig. 8), cuts placed
  * by contact count.  Node arrays have 2P-1 entries in creation order:
@@ -156,6 +190,25 @@ int cdref_solve_random(const cdref_params* p, int64_t n, const double* v, const 
                        const double* normal, const double* gap, const double* mu_c, int P,
                        const int64_t* dom_start, const int32_t* slot_contact, uint64_t seed,
                        int64_t step, double* R, cdref_info* info, double* history);
+
+/* The solve with walls of finite mass (mw, NULL: all prescribed) and the
+ * mixed update's parallel flags (NULL: none); otherwise as cdref_solve. */
+int cdref_solve_bc(const cdref_params* p, int64_t n, const double* v, const double* w,
+                   const double* r, const double* m, const double* inertia,
+                   const double* f, const double* t, const double* wall_velocity,
+                   int64_t nc, const int32_t* ci, const int32_t* cj,
+                   const double* normal, const double* gap, const double* mu_c,
+                   const uint8_t* parallel, int P, const int64_t* dom_start,
+                   const int32_t* slot_contact, const cdref_mobile_walls* mw, double* R,
+                   cdref_info* info, double* history);
+
+/* Wall velocities after forces R (Eq. 1 for the wall bodies): a wall of
+ * finite mass takes u_n + dt/M (F - sum of its contacts' R_n, ascending
+ * contact id) along its normal and keeps its tangential velocity; the
+ * others keep theirs.  U: W x dim. */
+void cdref_wall_velocities(int dim, int64_t n, double dt, int W, const double* wall_velocity,
+                           const cdref_mobile_walls* mw, int64_t nc, const int32_t* cj,
+                           const double* R, double* U);
 
 /* Load imbalance sigma_T = sqrt(<T^2> - <T>^2) / <T> over P times (Sec. 3.3). */
 double cdref_sigma_t(int P, const double* T);
@@ -230,7 +283,16 @@ int cdref_sim_set_random(cdref_sim* s, int on, uint64_t seed);
 /* capacities (P doubles, domain order) used by every later tree rebuild;
  * NULL: back to leaf counts */
 int cdref_sim_set_capacity(cdref_sim* s, const double* capacity);
-/* the current tree (2P-1 nodes) */
+/* Boundary conditions of the benchmark setups (Sec. 4.1, Sec. 4.4) from
+ * now on: periodic_mask bit k makes axis k periodic with the box's length
+ * (positions are kept in [lo, hi) on it, pairs taken at their nearest
+ * image); wall_inv_mass (W, NULL: all 0) and wall_force (W, NULL: all 0)
+ * give walls of finite mass 1/inv_mass pushed with the force along their
+ * normal.  CDREF_EINVAL for a wall lying on a periodic axis. */
+int cdref_sim_set_bc(cdref_sim* s, int periodic_mask, const double* wall_inv_mass,
+                     const double* wall_force);
+/* the walls' velocities after the steps so far (W x dim) */
+void cdref_sim_wall_velocities(const cdref_sim* s, double* U);
 /* The simulation box after the steps so far (dim entries each): a face
  * lying on an axis-aligned wall moves with that wall. */
 void cdref_sim_box(const cdref_sim* s, double* lo, double* hi);

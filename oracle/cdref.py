@@ -57,6 +57,19 @@ def lib():
         i64 = C.c_int64
         L.cdref_detect.argtypes = [C.c_int, i64, P, P, C.c_int, P, P, C.c_double, C.c_int, P, P,
                                    i64, P, P, C.POINTER(i64)]
+        L.cdref_detect_bc.argtypes = [C.c_int, i64, P, P, C.c_int, P, P, C.c_double, C.c_int, P,
+                                      P, P, i64, P, P, C.POINTER(i64)]
+        L.cdref_geometry_bc.argtypes = [C.c_int, i64, P, P, C.c_int, P, P, P, P, i64, P, P, P,
+                                        P, P]
+        L.cdref_geometry_bc.restype = None
+        L.cdref_wall_velocities.argtypes = [C.c_int, i64, C.c_double, C.c_int, P, P, i64, P, P,
+                                            P]
+        L.cdref_wall_velocities.restype = None
+        L.cdref_solve_bc.argtypes = [C.POINTER(Params), i64, P, P, P, P, P, P, P, P, i64, P, P,
+                                     P, P, P, P, C.c_int, P, P, P, P, C.POINTER(Info), P]
+        L.cdref_sim_set_bc.argtypes = [P, C.c_int, P, P]
+        L.cdref_sim_wall_velocities.argtypes = [P, P]
+        L.cdref_sim_wall_velocities.restype = None
         L.cdref_geometry.argtypes = [C.c_int, i64, P, P, C.c_int, P, P, i64, P, P, P, P, P]
         L.cdref_geometry.restype = None
         L.cdref_orb.argtypes = [C.c_int, C.c_int, P, P, i64, P, P, P, P, P, P, P]
@@ -132,18 +145,28 @@ def make_params(dim: int, n_walls: int, *, dt=1e-3, alpha=1e-6, mu=0.3, criterio
                   n_domains, repartition_every, warm_start, skin)
 
 
+def period_of(pk):
+    """Lengths of the periodic axes of a packing (0 for open axes), or None."""
+    mask = getattr(pk, "periodic", 0) or 0
+    if not mask:
+        return None
+    return np.array([(pk.box_hi[k] - pk.box_lo[k]) if (mask >> k) & 1 else 0.0
+                     for k in range(pk.dim)], dtype=np.float64)
+
+
 def detect(pk, skin: float, use_cells: bool = True):
     L = lib()
     x = _f64(pk.x)
     cap = max(16, 8 * pk.n)
+    period = period_of(pk)
     while True:
         ci = np.empty(cap, np.int32)
         cj = np.empty(cap, np.int32)
         nc = C.c_int64(0)
-        st = L.cdref_detect(pk.dim, pk.n, _p(x), _p(_f64(pk.r)), pk.n_walls,
-                            _p(_f64(pk.wall_normal)), _p(_f64(pk.wall_offset)), skin,
-                            1 if use_cells else 0, _p(_f64(pk.box_lo)), _p(_f64(pk.box_hi)), cap,
-                            _p(ci), _p(cj), C.byref(nc))
+        st = L.cdref_detect_bc(pk.dim, pk.n, _p(x), _p(_f64(pk.r)), pk.n_walls,
+                               _p(_f64(pk.wall_normal)), _p(_f64(pk.wall_offset)), skin,
+                               1 if use_cells else 0, _p(_f64(pk.box_lo)), _p(_f64(pk.box_hi)),
+                               _p(period), cap, _p(ci), _p(cj), C.byref(nc))
         if st == ECAPACITY:
             cap = int(nc.value)
             continue
@@ -158,10 +181,35 @@ def geometry(pk, ci, cj):
     normal = np.zeros((pk.dim, nc))
     gap = np.zeros(nc)
     xmid = np.zeros((pk.dim, nc))
-    L.cdref_geometry(pk.dim, pk.n, _p(_f64(pk.x)), _p(_f64(pk.r)), pk.n_walls,
-                     _p(_f64(pk.wall_normal)), _p(_f64(pk.wall_offset)), nc, _p(_i32(ci)),
-                     _p(_i32(cj)), _p(normal), _p(gap), _p(xmid))
+    L.cdref_geometry_bc(pk.dim, pk.n, _p(_f64(pk.x)), _p(_f64(pk.r)), pk.n_walls,
+                        _p(_f64(pk.wall_normal)), _p(_f64(pk.wall_offset)), _p(period_of(pk)),
+                        _p(_f64(pk.box_lo)), nc, _p(_i32(ci)), _p(_i32(cj)), _p(normal), _p(gap),
+                        _p(xmid))
     return normal, gap, xmid
+
+
+class MobileWalls(C.Structure):
+    _fields_ = [("normal", C.c_void_p), ("inv_mass", C.c_void_p), ("force", C.c_void_p)]
+
+
+def mobile_walls(pk):
+    """The cdref_mobile_walls of a packing with walls of finite mass (else
+    None), and the arrays it points to (kept alive by the caller)."""
+    if getattr(pk, "wall_inv_mass", None) is None or not np.any(pk.wall_inv_mass != 0):
+        return None, None
+    keep = (_f64(pk.wall_normal), _f64(pk.wall_inv_mass),
+            _f64(pk.wall_force if pk.wall_force is not None else np.zeros(pk.n_walls)))
+    return MobileWalls(*[a.ctypes.data for a in keep]), keep
+
+
+def wall_velocities(pk, dt, cj, R):
+    """Velocities of the walls after forces R (cdref_wall_velocities), W x dim."""
+    mw, keep = mobile_walls(pk)
+    U = np.zeros((max(pk.n_walls, 1), pk.dim))
+    lib().cdref_wall_velocities(pk.dim, pk.n, dt, pk.n_walls, _p(_f64(pk.wall_velocity)),
+                                C.byref(mw) if mw is not None else None, len(cj), _p(_i32(cj)),
+                                _p(_f64(R)), _p(U))
+    return U[:pk.n_walls]
 
 
 @dataclasses.dataclass
@@ -283,13 +331,15 @@ def solve(params: Params, pk, ci, cj, normal, gap, P: int, dom_start, slot, R0=N
         if st < 0:
             raise RuntimeError(f"cdref_solve_random failed: {st}")
         return R, info, (hist[:, :info.iterations] if hist is not None else None)
-    st = L.cdref_solve_mixed(C.byref(params), pk.n, _p(_f64(pk.v)), _p(_f64(pk.w)),
-                             _p(_f64(pk.r)), _p(_f64(pk.m)), _p(_f64(pk.inertia)),
-                             _p(_f64(pk.f)), _p(_f64(pk.t)), _p(_f64(pk.wall_velocity)), nc,
-                             _p(_i32(ci)), _p(_i32(cj)), _p(_f64(normal)), _p(_f64(gap)),
-                             None if mu_c is None else _p(_f64(mu_c)), _p(par), P,
-                             _p(np.ascontiguousarray(dom_start, np.int64)), _p(_i32(slot)),
-                             _p(R), C.byref(info), _p(hist))
+    mw, keep_mw = mobile_walls(pk)
+    st = L.cdref_solve_bc(C.byref(params), pk.n, _p(_f64(pk.v)), _p(_f64(pk.w)),
+                          _p(_f64(pk.r)), _p(_f64(pk.m)), _p(_f64(pk.inertia)),
+                          _p(_f64(pk.f)), _p(_f64(pk.t)), _p(_f64(pk.wall_velocity)), nc,
+                          _p(_i32(ci)), _p(_i32(cj)), _p(_f64(normal)), _p(_f64(gap)),
+                          None if mu_c is None else _p(_f64(mu_c)), _p(par), P,
+                          _p(np.ascontiguousarray(dom_start, np.int64)), _p(_i32(slot)),
+                          C.byref(mw) if mw is not None else None, _p(R), C.byref(info),
+                          _p(hist))
     if st < 0:
         raise RuntimeError(f"cdref_solve failed: {st}")
     if hist is not None:
@@ -354,6 +404,14 @@ class Sim:
         self.h = self.L.cdref_sim_create(C.byref(params), pk.n, *[_p(a) for a in self._keep])
         if not self.h:
             raise RuntimeError("cdref_sim_create failed")
+        mask = getattr(pk, "periodic", 0) or 0
+        im = getattr(pk, "wall_inv_mass", None)
+        if mask or im is not None:
+            self._bc = (None if im is None else _f64(im),
+                        None if getattr(pk, "wall_force", None) is None else _f64(pk.wall_force))
+            st = self.L.cdref_sim_set_bc(self.h, int(mask), _p(self._bc[0]), _p(self._bc[1]))
+            if st != OK:
+                raise RuntimeError(f"cdref_sim_set_bc failed: {st}")
 
     def close(self):
         if self.h:
@@ -381,6 +439,11 @@ class Sim:
         wo = np.zeros(max(self.params.n_walls, 1))
         self.L.cdref_sim_state(self.h, _p(x), _p(v), _p(w), _p(wo))
         return x, v, w, wo[:self.params.n_walls]
+
+    def wall_velocities(self):
+        U = np.zeros((max(self.params.n_walls, 1), self.dim))
+        self.L.cdref_sim_wall_velocities(self.h, _p(U))
+        return U[:self.params.n_walls]
 
     def box(self):
         lo = np.zeros(self.dim)

@@ -55,6 +55,12 @@ class Packing:
     wall_velocity: np.ndarray  # (W, dim) translation velocities
     box_lo: np.ndarray   # (dim,) simulation box, the root region of the partition
     box_hi: np.ndarray   # (dim,)
+    # benchmark boundary conditions (Sec. 4.1): bit k of `periodic` makes axis
+    # k periodic over [box_lo_k, box_hi_k); a wall with wall_inv_mass > 0 is a
+    # body of that inverse mass pushed with wall_force along its normal
+    periodic: int = 0
+    wall_inv_mass: Optional[np.ndarray] = None   # (W,)
+    wall_force: Optional[np.ndarray] = None      # (W,)
 
     @property
     def n(self) -> int:
@@ -117,6 +123,31 @@ def lattice_2d(nx: int, ny: int, seed: int, *, n: Optional[int] = None,
     wn, wo, wv = _box_walls(lo, hi, None)
     return Packing(2, np.ascontiguousarray(x), np.ascontiguousarray(v), np.zeros((1, n)),
                    r, m, inertia, f, np.zeros((1, n)), wn, wo, wv, lo, hi)
+
+
+def sheared_box_2d(nx: int, ny: int, seed: int, *, pressure: float = 0.25,
+                   shear_velocity: float = 0.0, sigma_v: float = 0.01) -> Packing:
+    """The setup of the paper's performance and physics tests (Sec. 4.1,
+    Fig. 10; Sec. 4.4): a jittered triangular lattice of nx*ny disks
+    (generator of lattice_2d, no gravity) periodic in x over nx spacings,
+    between a bottom and a top wall that each push with `pressure` times the
+    box width along their normal (walls of finite mass: one row of disks of
+    the mean radius, nx pi) and slide along x at -shear_velocity (bottom) and
+    +shear_velocity (top)."""
+    pk = lattice_2d(nx, ny, seed, gravity=0.0, sigma_v=sigma_v)
+    Lx = SPACING * nx
+    lo = np.array([0.0, pk.box_lo[1]])
+    hi = np.array([Lx, pk.box_hi[1]])
+    x = pk.x.copy()
+    x[0] = np.mod(x[0] - lo[0], Lx) + lo[0]     # the row offsets wrap into [0, Lx)
+    wn = np.array([[0.0, 1.0], [0.0, -1.0]])
+    wo = np.array([lo[1], -hi[1]])
+    wv = np.array([[-shear_velocity, 0.0], [shear_velocity, 0.0]])
+    mass = nx * math.pi
+    return Packing(2, np.ascontiguousarray(x), pk.v, pk.w, pk.r, pk.m, pk.inertia, pk.f, pk.t,
+                   wn, wo, wv, lo, hi, periodic=1,
+                   wall_inv_mass=np.array([1.0 / mass, 1.0 / mass]),
+                   wall_force=np.array([pressure * Lx, pressure * Lx]))
 
 
 def lattice_3d(nx: int, ny: int, nz: int, seed: int, *, gravity: float = 0.0,
