@@ -147,6 +147,30 @@ int cd_set_walls(cd_ctx* ctx, const double* normal, const double* offset, const 
  * CD_EINVAL unless hi > lo on every axis. */
 int cd_set_box(cd_ctx* ctx, const double* lo, const double* hi);
 
+/* Boundary conditions of the paper's benchmark setups (Sec. 4.1, Fig. 10:
+ * periodic in x between confining walls under pressure; Sec. 4.4: the same
+ * walls sliding in opposite directions), from the next step on.
+ *   periodic_mask: bit k makes axis k periodic with the box's length
+ *     (cd_set_box): particle pairs are taken at their nearest image, the
+ *     cell grid wraps (at least three cells of 2.2 r_max along the axis,
+ *     else the step returns CD_EINVAL), positions and contact positions are
+ *     kept in [lo, hi).  No wall may bound a periodic axis (CD_EINVAL).
+ *   wall_inv_mass (HOST, W, NULL = all 0): 1/M of each wall; a wall with
+ *     1/M > 0 is a body of the solve that moves along its normal only: its
+ *     contacts conflict in the colouring (distinct colours), each domain
+ *     touching it keeps its own copy of its velocity, recomputed in every
+ *     exchange as u_n + dt/M (F - sum of R_n over all its contacts, ascending
+ *     contact id) along its normal (Eq. 1 for the wall), its tangential
+ *     velocity (cd_set_walls) stays prescribed, and after the step it keeps
+ *     the velocity of the final forces.  1/M = 0: prescribed motion.
+ *   wall_force (HOST, W, NULL = all 0): the constant external force F on
+ *     each wall along its normal (pressure times area).
+ * Walls of finite mass exclude the mixed update, the random order, load
+ * measurement, the one-launch solve (mode 0), the batch and the adjoint
+ * (CD_EINVAL where they are set); periodic axes exclude the adjoint. */
+int cd_set_boundary(cd_ctx* ctx, int periodic_mask, const double* wall_inv_mass,
+                    const double* wall_force);
+
 /* One time step: detection, warm start, partition, order, force solve,
  * Euler update (Fig. 7).  Positions and velocities are updated in place in
  * the context.  out (host, may be NULL) receives the outcome.  Returns
@@ -191,6 +215,10 @@ int cd_get_state(cd_ctx* ctx, double* x, double* v, double* w);
 /* Wall offsets after the steps so far (HOST pointer, W entries): each wall
  * has moved by dt times its normal velocity per step (Sec. 2.1). */
 int cd_get_walls(cd_ctx* ctx, double* offset);
+
+/* Wall velocities after the steps so far (HOST pointer, W x dim): as set,
+ * with the normal part of walls of finite mass evolved (cd_set_boundary). */
+int cd_get_wall_velocities(cd_ctx* ctx, double* velocity);
 
 /* Number of contacts in the context's current list (Sec. 3.1: pairs within
  * the boundary width; host value, no device work). */

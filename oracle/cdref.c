@@ -597,9 +597,18 @@ int cdref_order(int64_t n, int64_t nc, const int32_t* ci, const int32_t* cj,
 int cdref_order_mixed(int64_t n, int64_t nc, const int32_t* ci, const int32_t* cj,
                       int P, const int32_t* dom, const uint8_t* parallel, int32_t* color,
                       int32_t* slot_contact, int64_t* dom_start) {
+  return cdref_order_bc(n, nc, ci, cj, P, dom, parallel, 0, color, slot_contact, dom_start);
+}
+
+int cdref_order_bc(int64_t n, int64_t nc, const int32_t* ci, const int32_t* cj, int P,
+                   const int32_t* dom, const uint8_t* parallel, int mobile_mask, int32_t* color,
+                   int32_t* slot_contact, int64_t* dom_start) {
   const int words = CDREF_MAX_COLORS / 64;
   const int first = parallel ? 1 : 0;   /* the first colour of a sequential contact */
-  uint64_t* used = (uint64_t*)calloc((size_t)(n > 0 ? n : 1) * words, sizeof(uint64_t));
+  /* colour sets of the particles, then of the walls (a wall of finite mass
+     is a body whose velocity the contacts change: its contacts conflict) */
+  uint64_t* used =
+      (uint64_t*)calloc((size_t)(n + CDREF_MAX_WALLS) * words, sizeof(uint64_t));
   int64_t* count = (int64_t*)calloc((size_t)P + 1, sizeof(int64_t));
   int64_t* members_start = (int64_t*)calloc((size_t)P + 1, sizeof(int64_t));
   int32_t* members = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
@@ -627,17 +636,18 @@ int cdref_order_mixed(int64_t n, int64_t nc, const int32_t* ci, const int32_t* c
         if (maxcol < 0) maxcol = 0;
         continue;
       }
+      const int b_body = b < n || ((mobile_mask >> (b - n)) & 1);
       int k = first;
       for (; k < CDREF_MAX_COLORS; ++k) {
         uint64_t bit = 1ull << (k % 64);
         int in_a = (used[a * words + k / 64] & bit) != 0;
-        int in_b = b < n ? (used[b * words + k / 64] & bit) != 0 : 0;
+        int in_b = b_body ? (used[b * words + k / 64] & bit) != 0 : 0;
         if (!in_a && !in_b) break;
       }
       if (k == CDREF_MAX_COLORS) { status = CDREF_ECAPACITY; k = CDREF_MAX_COLORS - 1; }
       color[c] = k;
       used[a * words + k / 64] |= 1ull << (k % 64);
-      if (b < n) used[b * words + k / 64] |= 1ull << (k % 64);
+      if (b_body) used[b * words + k / 64] |= 1ull << (k % 64);
       if (k > maxcol) maxcol = k;
     }
     /* order by (colour, canonical id) */
@@ -649,7 +659,7 @@ int cdref_order_mixed(int64_t n, int64_t nc, const int32_t* ci, const int32_t* c
       int32_t c = members[s];
       for (int w = 0; w < words; ++w) {
         used[(int64_t)ci[c] * words + w] = 0;
-        if (cj[c] < n) used[(int64_t)cj[c] * words + w] = 0;
+        used[(int64_t)cj[c] * words + w] = 0;
       }
     }
   }
@@ -1383,7 +1393,11 @@ int cdref_sim_step(cdref_sim* s, cdref_info* info) {
     if (!par) { free(dom_start); return CDREF_ENOMEM; }
     cdref_parallel_flags(nc, s->ci, s->cj, s->mixed_p, s->mixed_seed, par);
   }
-  st = cdref_order_mixed(n, nc, s->ci, s->cj, P, s->dom, par, s->color, s->slot, dom_start);
+  int mobile_mask = 0;
+  for (int q = 0; q < p->n_walls && s->has_mobile; ++q)
+    if (s->wall_inv_mass[q] != 0.0) mobile_mask |= 1 << q;
+  st = cdref_order_bc(n, nc, s->ci, s->cj, P, s->dom, par, mobile_mask, s->color, s->slot,
+                      dom_start);
   if (st != CDREF_OK) { free(dom_start); free(par); return st; }
   cdref_mobile_walls mw = {s->wn, s->wall_inv_mass, s->wall_force};
   const cdref_mobile_walls* mwp = s->has_mobile ? &mw : NULL;

@@ -222,6 +222,13 @@ void cdref_descend(int dim, int P, const int32_t* node_axis, const double* node_
  * 2P-1 entries in creation order.  Exposed for tests. */
 int cdref_tree_leaves(int P, int32_t* node_leaves);
 
+/* cdref_order_mixed where the walls in mobile_mask (bit w: wall w has
+ * finite mass) conflict like particles: their contacts take distinct
+ * colours, since each changes the wall's velocity. */
+int cdref_order_bc(int64_t n, int64_t nc, const int32_t* ci, const int32_t* cj, int P,
+                   const int32_t* dom, const uint8_t* parallel, int mobile_mask, int32_t* color,
+                   int32_t* slot_contact, int64_t* dom_start);
+
 /* Update order inside each domain: greedy first-fit colouring of the
  * domain's contacts in canonical order (two contacts conflict when they
  * share a particle; walls never conflict), then order by (colour, id).

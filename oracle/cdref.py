@@ -68,6 +68,7 @@ def lib():
         L.cdref_solve_bc.argtypes = [C.POINTER(Params), i64, P, P, P, P, P, P, P, P, i64, P, P,
                                      P, P, P, P, C.c_int, P, P, P, P, C.POINTER(Info), P]
         L.cdref_sim_set_bc.argtypes = [P, C.c_int, P, P]
+        L.cdref_order_bc.argtypes = [i64, i64, P, P, C.c_int, P, P, C.c_int, P, P, P]
         L.cdref_sim_wall_velocities.argtypes = [P, P]
         L.cdref_sim_wall_velocities.restype = None
         L.cdref_geometry.argtypes = [C.c_int, i64, P, P, C.c_int, P, P, i64, P, P, P, P, P]
@@ -290,15 +291,17 @@ def parallel_flags(ci, cj, p: float, seed: int) -> np.ndarray:
     return out[:nc]
 
 
-def order(n: int, ci, cj, P: int, dom, parallel=None):
+def order(n: int, ci, cj, P: int, dom, parallel=None, mobile_mask: int = 0):
+    """Colour-major order per domain; walls in mobile_mask (bit w) conflict
+    like particles (cdref_order_bc)."""
     L = lib()
     nc = len(ci)
     color = np.zeros(max(nc, 1), np.int32)
     slot = np.zeros(max(nc, 1), np.int32)
     dom_start = np.zeros(P + 1, np.int64)
     par = None if parallel is None else _u8(parallel)
-    st = L.cdref_order_mixed(n, nc, _p(_i32(ci)), _p(_i32(cj)), P, _p(_i32(dom)), _p(par),
-                             _p(color), _p(slot), _p(dom_start))
+    st = L.cdref_order_bc(n, nc, _p(_i32(ci)), _p(_i32(cj)), P, _p(_i32(dom)), _p(par),
+                          int(mobile_mask), _p(color), _p(slot), _p(dom_start))
     if st != OK:
         raise RuntimeError(f"cdref_order failed: {st}")
     return color[:nc], slot[:nc], dom_start

@@ -80,6 +80,8 @@ def lib():
         i64 = C.c_int64
         L.cd_create.argtypes = [C.POINTER(P), C.POINTER(Params), i64, i64, P]
         L.cd_solve_contacts.argtypes = [P, i64, P, P, P, P, P, C.POINTER(Result)]
+        L.cd_set_boundary.argtypes = [P, C.c_int, P, P]
+        L.cd_get_wall_velocities.argtypes = [P, P]
         L.cd_destroy.argtypes = [P]
         L.cd_set_particles.argtypes = [P, P, P, P, P, P, P]
         L.cd_set_external.argtypes = [P, P, P]
@@ -182,10 +184,30 @@ class Context:
             hi = np.ascontiguousarray(packing.box_hi, dtype=np.float64)
             self._check(self.L.cd_set_box(self.h, lo.ctypes.data_as(C.c_void_p),
                                           hi.ctypes.data_as(C.c_void_p)))
+            self._set_boundary(packing)
             self._check(self.L.cd_set_timing(self.h, int(timing)))
             self._check(self.L.cd_set_solve_mode(self.h, solve_mode))
             self._check(self.L.cd_set_launch(self.h, block_threads))
             torch.cuda.synchronize(self.device)
+
+    def _set_boundary(self, packing):
+        """Periodic axes and walls of finite mass of the packing (cd_set_boundary)."""
+        mask = int(getattr(packing, "periodic", 0) or 0)
+        im = getattr(packing, "wall_inv_mass", None)
+        wf = getattr(packing, "wall_force", None)
+        if not mask and im is None:
+            return
+        self._bc = tuple(None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+                         for a in (im, wf))
+        ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+        self._check(self.L.cd_set_boundary(self.h, mask, ptr(self._bc[0]), ptr(self._bc[1])))
+
+    def wall_velocities(self) -> np.ndarray:
+        """The walls' velocities after the steps so far (W x dim): as given,
+        with the normal part of walls of finite mass evolved."""
+        out = np.zeros(max(self.W, 1) * self.dim)
+        self._check(self.L.cd_get_wall_velocities(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out[:self.W * self.dim].reshape(self.W, self.dim)
 
     def _check(self, code: int, h="self"):
         if code < 0:

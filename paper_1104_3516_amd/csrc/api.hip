@@ -257,6 +257,10 @@ int setup_grid(cd_ctx* c) {
       int64_t m = (int64_t)floor(len / a);
       if (m < 1) m = 1;
       if (m > 4096) m = 4096;
+      // a periodic axis needs three cells so that a cell's neighbours are
+      // distinct and each pair is seen at one image
+      if (c->period[k] > 0.0 && m < 3)
+        return fail(c, CD_EINVAL, "a periodic axis must span at least three cells of 2.2 r_max");
       c->ncell[k] = (int)m;
       c->cwidth[k] = len / (double)m;
     } else {
@@ -284,8 +288,10 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 static_assert(sizeof(GridBar) <= 512 && sizeof(DomainStats) <= 512 && 6 * sizeof(double) <= 512,
               "pinned scratch holds every small readback");
-static_assert(sizeof(GridBar) <= 8 * kActiveSlot && sizeof(DomainStats) <= 8 * kActiveSlot,
-              "the active-contact count has a slot of its own in the pinned scratch");
+static_assert(sizeof(GridBar) <= 8 * kWallSlot && sizeof(DomainStats) <= 8 * kWallSlot &&
+                  kWallSlot + CD_MAX_WALLS * 3 <= kActiveSlot,
+              "the wall velocities and the active-contact count have slots of their own in "
+              "the pinned scratch");
 
 extern "C" {
 
@@ -354,7 +360,9 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles,
   alloc(&c->inv_I, n);
   alloc(&c->dtim, n);
   alloc(&c->dtii, n);
-  alloc(&c->d_wall, (int64_t)CD_WALL_MU + 1);
+  alloc(&c->d_wall, (int64_t)CD_WALL_WORDS);
+  alloc(&c->d_wall_new, (int64_t)CD_MAX_WALLS * 3);
+  alloci(&c->wall_cnt, CD_MAX_WALLS);
   alloci(&c->cell_of, n);
   alloci(&c->cell_members, n);
   alloci(&c->pair_count, n + 1);
@@ -390,7 +398,7 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles,
     st = CD_ENOMEM;
   if (st == CD_OK && hipHostMalloc((void**)&c->h_scratch, 512) != hipSuccess) st = CD_ENOMEM;
   if (st == CD_OK &&
-      hipHostMalloc((void**)&c->h_walls, sizeof(double) * CD_MAX_WALLS * 7) != hipSuccess)
+      hipHostMalloc((void**)&c->h_walls, sizeof(double) * CD_WALL_WORDS) != hipSuccess)
     st = CD_ENOMEM;
   if (st == CD_OK && hipHostMalloc((void**)&c->h_prog, sizeof(HostProg), hipHostMallocMapped) != hipSuccess)
     st = CD_ENOMEM;
@@ -404,6 +412,12 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles,
     if (hipEventCreate(&c->ev[k]) != hipSuccess) st = CD_EHIP;
   if (st == CD_OK && hipMemset(c->t, 0, sizeof(double) * c->dr * n) != hipSuccess) st = CD_EHIP;
   if (st == CD_OK && hipMemset(c->f, 0, sizeof(double) * c->dim * n) != hipSuccess) st = CD_EHIP;
+  // no wall of finite mass until cd_set_boundary
+  if (st == CD_OK && hipMemset(c->d_wall + CD_WALL_DTIM, 0,
+                               sizeof(double) * (CD_WALL_WORDS - CD_WALL_DTIM)) != hipSuccess)
+    st = CD_EHIP;
+  if (st == CD_OK && hipMemset(c->wall_cnt, 0, sizeof(int) * CD_MAX_WALLS) != hipSuccess)
+    st = CD_EHIP;
   if (st == CD_OK && contact_capacity > 0) {
     // contact arrays sized up front: both lists of the warm start and every
     // contact-sized workspace
@@ -462,6 +476,9 @@ int cd_destroy(cd_ctx* c) {
   cd_window_clear(c);
   release(&c->d_vmax);
   release(&c->d_active);
+  release(&c->d_wall_new);
+  release(&c->wall_cnt);
+  release(&c->wall_slot);
   release(&c->d_dtick);
   release(&c->par);
   release(&c->d_frac);
@@ -545,9 +562,18 @@ static int upload_walls(cd_ctx* c, bool sync = true) {
   for (int k = 0; k < W * dim; ++k) buf[k] = c->wn[k];
   for (int k = 0; k < W; ++k) buf[W * dim + k] = c->wo[k];
   for (int k = 0; k < W * dim; ++k) buf[W * dim + W + k] = c->wu[k];
-  if (W > 0)
+  // walls of finite mass: dt / M (the same product as in the oracle) and force
+  for (int k = 0; k < CD_MAX_WALLS; ++k) {
+    buf[CD_WALL_DTIM + k] = k < W ? c->p.dt * c->wim[k] : 0.0;
+    buf[CD_WALL_FORCE + k] = k < W ? c->wf[k] : 0.0;
+  }
+  if (W > 0) {
     CD_TRY(hipMemcpyAsync(c->d_wall, buf, sizeof(double) * (size_t)(W * (2 * dim + 1)),
                           hipMemcpyHostToDevice, c->stream));
+    CD_TRY(hipMemcpyAsync(c->d_wall + CD_WALL_DTIM, buf + CD_WALL_DTIM,
+                          sizeof(double) * (CD_WALL_WORDS - CD_WALL_DTIM), hipMemcpyHostToDevice,
+                          c->stream));
+  }
   if (sync) CD_TRY(hipStreamSynchronize(c->stream));
   return CD_OK;
 }
@@ -570,9 +596,46 @@ int cd_set_box(cd_ctx* c, const double* lo, const double* hi) {
     c->lo[k] = k < c->dim ? lo[k] : 0.0;
     c->hi[k] = k < c->dim ? hi[k] : 0.0;
     if (k < c->dim && !(hi[k] > lo[k])) return fail(c, CD_EINVAL, "box must have hi > lo");
+    // a periodic axis has the box's length
+    c->period[k] = (k < c->dim && ((c->periodic_mask >> k) & 1)) ? c->hi[k] - c->lo[k] : 0.0;
   }
   c->have_box = true;
   return CD_OK;
+}
+
+int cd_set_boundary(cd_ctx* c, int periodic_mask, const double* wall_inv_mass,
+                    const double* wall_force) {
+  if (!c || periodic_mask < 0 || periodic_mask >= (1 << c->dim)) return CD_EINVAL;
+  const int W = c->W, dim = c->dim;
+  for (int k = 0; k < dim; ++k)
+    if ((periodic_mask >> k) & 1)
+      for (int q = 0; q < W; ++q)
+        if (c->wn[q * dim + k] != 0.0)
+          return fail(c, CD_EINVAL, "a wall bounds an axis made periodic");
+  int mobile = 0;
+  for (int q = 0; q < W; ++q) {
+    const double im = wall_inv_mass ? wall_inv_mass[q] : 0.0;
+    const double fq = wall_force ? wall_force[q] : 0.0;
+    if (!(im >= 0.0) || !std::isfinite(im) || !std::isfinite(fq))
+      return fail(c, CD_EINVAL, "wall inverse masses must be >= 0, forces finite");
+    if (im != 0.0) mobile |= 1 << q;
+  }
+  if ((periodic_mask || mobile) && c->adj_every > 0)
+    return fail(c, CD_EINVAL, "the adjoint differentiates rigid boxes only");
+  if (mobile && (c->mixed_p >= 0.0 || c->order_random || c->lb_sigma_star >= 0.0))
+    return fail(c, CD_EINVAL,
+                "walls of finite mass go with the plain colour-major sweep only "
+                "(no mixed update, random order or load measurement)");
+  c->periodic_mask = periodic_mask;
+  for (int k = 0; k < 3; ++k)
+    c->period[k] = (k < dim && ((periodic_mask >> k) & 1)) ? c->hi[k] - c->lo[k] : 0.0;
+  for (int q = 0; q < CD_MAX_WALLS; ++q) {
+    c->wim[q] = (wall_inv_mass && q < W) ? wall_inv_mass[q] : 0.0;
+    c->wf[q] = (wall_force && q < W) ? wall_force[q] : 0.0;
+  }
+  c->mobile_mask = mobile;
+  c->have_tree = false;
+  return upload_walls(c);
 }
 
 int cd_set_timing(cd_ctx* c, int every) {
@@ -590,6 +653,8 @@ int cd_set_solve_mode(cd_ctx* c, int mode) {
 
 int cd_set_load_balance(cd_ctx* c, double sigma_star) {
   if (!c || !std::isfinite(sigma_star)) return CD_EINVAL;
+  if (sigma_star >= 0.0 && c->mobile_mask)
+    return fail(c, CD_EINVAL, "the load is measured on boxes without walls of finite mass");
   if (sigma_star >= 0.0 && c->order_random)
     return fail(c, CD_EINVAL, "the load is measured on the colour-major sweep only");
   if (sigma_star < 0.0) {
@@ -777,7 +842,9 @@ int prep_phase2(cd_ctx* c) {
   // the records in global memory
   const size_t rand_lds =
       c->order_random ? ((size_t)16 * std::max(ds.max_contacts, 1) + 31) / 32 * 32 : 0;
-  c->sweep_global = lds + rand_lds + 2048 > c->max_lds;
+  // walls of finite mass add their exchange buffer to the static LDS
+  const size_t mob_lds = c->mobile_mask ? sizeof(double) * (256 + CD_MAX_WALLS) : 0;
+  c->sweep_global = lds + rand_lds + mob_lds + 2048 > c->max_lds;
   c->sweep_lds = c->sweep_global ? 0 : lds;
   // one workgroup per domain, wide enough to stage its contacts and gather
   // its particles in one pass (the work is latency-bound)
@@ -876,6 +943,9 @@ int solve_single(cd_ctx* c) {
     return fail(c, CD_EINVAL, "the one-launch solve has no mixed update (solve modes 1 and 2 do)");
   if (c->persistent && c->order_random)
     return fail(c, CD_EINVAL, "the one-launch solve has no random order (solve modes 1 and 2 do)");
+  if (c->persistent && c->mobile_mask)
+    return fail(c, CD_EINVAL,
+                "the one-launch solve has no walls of finite mass (solve modes 1 and 2 do)");
   const int G = c->persistent ? cd_solve_grid(c) : 0;
   if (G < 8) cd_sweep_mode(c);
   if (c->order_random && nc > 0) {
@@ -1008,6 +1078,13 @@ int finish_enqueue(cd_ctx* c) {
   CD_TRY(cd_launch_count_active(c, c->d_active));
   CD_TRY(hipMemcpyAsync(c->h_scratch + kActiveSlot, c->d_active, sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, c->stream));
+  if (c->mobile_mask) {
+    // walls of finite mass: their velocity from the final forces
+    CD_TRY(cd_launch_wall_velocities(c));
+    CD_TRY(hipMemcpyAsync(c->h_scratch + kWallSlot, c->d_wall_new,
+                          sizeof(double) * (size_t)(c->W * c->dim), hipMemcpyDeviceToHost,
+                          c->stream));
+  }
   return CD_OK;
 }
 
@@ -1086,6 +1163,10 @@ static int collect_result(cd_ctx* c, cd_result* out) {
 int finish_complete(cd_ctx* c, cd_result* out) {
   const int dim = c->dim;
   const double dt = c->p.dt;
+  if (c->mobile_mask) {
+    const double* U = (const double*)(c->h_scratch + kWallSlot);
+    for (int k = 0; k < c->W * dim; ++k) c->wu[k] = U[k];
+  }
   // walls move; a box face follows the axis-aligned wall lying on it
   for (int wi = 0; wi < c->W; ++wi) {
     double un = 0.0;
@@ -1133,6 +1214,8 @@ int cd_solve(cd_ctx* c, cd_result* out) {
 
 int cd_set_mixed_update(cd_ctx* c, double p, unsigned long long seed) {
   if (!c || std::isnan(p)) return CD_EINVAL;
+  if (p >= 0.0 && c->mobile_mask)
+    return fail(c, CD_EINVAL, "walls of finite mass go with the plain sequential update only");
   if (p >= 0.0 && c->adj_every > 0)
     return fail(c, CD_EINVAL, "the adjoint differentiates the sequential update only");
   if (p >= 0.0 && c->order_random)
@@ -1144,6 +1227,8 @@ int cd_set_mixed_update(cd_ctx* c, double p, unsigned long long seed) {
 
 int cd_set_random_order(cd_ctx* c, int on, unsigned long long seed) {
   if (!c) return CD_EINVAL;
+  if (on && c->mobile_mask)
+    return fail(c, CD_EINVAL, "walls of finite mass go with the colour-major order only");
   if (on && c->adj_every > 0)
     return fail(c, CD_EINVAL, "the adjoint differentiates the colour-major order only");
   if (on && c->mixed_p >= 0.0)
@@ -1157,6 +1242,8 @@ int cd_set_random_order(cd_ctx* c, int on, unsigned long long seed) {
 
 int cd_set_adjoint(cd_ctx* c, int checkpoint_every) {
   if (!c || checkpoint_every < 0) return CD_EINVAL;
+  if (checkpoint_every > 0 && (c->mobile_mask || c->periodic_mask))
+    return fail(c, CD_EINVAL, "the adjoint differentiates rigid boxes only");
   if (checkpoint_every > 0 && c->mixed_p >= 0.0)
     return fail(c, CD_EINVAL, "the adjoint differentiates the sequential update only");
   if (checkpoint_every > 0 && c->order_random)
@@ -1278,6 +1365,12 @@ int cd_get_state(cd_ctx* c, double* x, double* v, double* w) {
   if (v) CD_TRY(hipMemcpyAsync(v, c->v, sizeof(double) * c->dim * n, hipMemcpyDeviceToDevice, c->stream));
   if (w) CD_TRY(hipMemcpyAsync(w, c->w, sizeof(double) * c->dr * n, hipMemcpyDeviceToDevice, c->stream));
   CD_TRY(hipStreamSynchronize(c->stream));
+  return CD_OK;
+}
+
+int cd_get_wall_velocities(cd_ctx* c, double* velocity) {
+  if (!c || (!velocity && c->W > 0)) return CD_EINVAL;
+  for (int k = 0; k < c->W * c->dim; ++k) velocity[k] = c->wu[k];
   return CD_OK;
 }
 

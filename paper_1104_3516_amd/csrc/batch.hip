@@ -146,7 +146,10 @@ int cd_batch_create(cd_batch** out, cd_ctx* const* ctxs, int count) {
   std::vector<int> blk;
   for (int p = 0; p < count; ++p) {
     cd_ctx* c = ctxs[p];
-    if (!c || c->stream != b->stream || c->dim != b->dim || c->device != ctxs[0]->device) {
+    // walls of finite mass need their own sweep instantiation, which the
+    // batched launch does not have
+    if (!c || c->stream != b->stream || c->dim != b->dim || c->device != ctxs[0]->device ||
+        c->mobile_mask) {
       delete b;
       return CD_EINVAL;
     }

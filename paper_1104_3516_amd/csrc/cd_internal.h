@@ -30,6 +30,11 @@
 #define CD_MAX_WALLS 8
 // index, in the device wall buffer, of the friction coefficient shared by all contacts
 #define CD_WALL_MU (CD_MAX_WALLS * 7)
+// then, per wall, dt / M of a wall of finite mass (0: prescribed motion) and
+// the external force along its normal
+#define CD_WALL_DTIM (CD_WALL_MU + 1)
+#define CD_WALL_FORCE (CD_WALL_DTIM + CD_MAX_WALLS)
+#define CD_WALL_WORDS (CD_WALL_FORCE + CD_MAX_WALLS)
 
 struct SolveState {
   int iter;           // sweeps completed
@@ -124,6 +129,15 @@ struct SweepArgs {
   int block;                // threads per block of a sweep launch
   unsigned long long* dtick;  // per-domain elapsed real-time ticks of the step, or null
   unsigned long long rkey;  // random sequential order: the step's key K (Sec. 2.1)
+  // walls of finite mass (Sec. 4.1): normals (W x dim), dt/M and force per
+  // wall (device), and each such wall's contact slots in ascending contact
+  // id (wall_slot + w * cap, wall_cnt[w] of them)
+  const double* walls_n;
+  const double* walls_dtim;
+  const double* walls_force;
+  const int* wall_slot;
+  const int* wall_cnt;
+  int mobile;               // bit w: wall w has finite mass
   int per_xcd;              // domains per XCD in the block -> domain map
   int wave_lds;             // LDS staging per wavefront (doubles)
   long long nc;
@@ -176,6 +190,16 @@ struct cd_ctx {
   double* d_wall = nullptr;     // normals (W x dim), offsets (W), velocities (W x dim)
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   bool have_box = false;
+  // benchmark boundary conditions (Sec. 4.1, 4.4): periodic axes and walls of
+  // finite mass pushed with a constant force
+  int periodic_mask = 0;
+  double period[3] = {0, 0, 0};   // > 0: periodic axis of this length
+  double wim[CD_MAX_WALLS] = {0}, wf[CD_MAX_WALLS] = {0};   // 1/M, force along the normal
+  int mobile_mask = 0;            // bit w: wall w has finite mass
+  int* wall_slot = nullptr;       // per mobile wall: its contact slots (cap each)
+  int* wall_cnt = nullptr;        // their counts (CD_MAX_WALLS)
+  int64_t wall_slot_cap = 0;
+  double* d_wall_new = nullptr;   // walls' velocities after a step (W x dim)
 
   // cells
   int ncell[3] = {1, 1, 1};
@@ -421,6 +445,11 @@ hipError_t cd_launch_solve(cd_ctx* c, int G, int limit);    // all sweeps in one
 hipError_t cd_launch_update(cd_ctx* c, int final_iter);
 // contacts with R_n > 0 in the canonical forces c->R, into *count (device)
 hipError_t cd_launch_count_active(cd_ctx* c, unsigned long long* count);
+// velocities of the walls of finite mass after the final forces c->R
+// (Eq. 1 for a wall body), into c->d_wall_new (W x dim)
+hipError_t cd_launch_wall_velocities(cd_ctx* c);
+// per wall of finite mass: its contacts' slots in ascending contact id
+hipError_t cd_launch_wall_lists(cd_ctx* c);
 hipError_t cd_launch_derived(cd_ctx* c);
 SweepArgs cd_sweep_args(cd_ctx* c);
 
@@ -433,6 +462,9 @@ __host__ __device__ constexpr int cd_stage_particle(int dim) { return dim == 2 ?
 // slot of the pinned 64-entry scratch (c->h_scratch) that receives the
 // active-contact count of a finished solve
 constexpr int kActiveSlot = 63;
+// first of the slots (CD_MAX_WALLS * 3 doubles) that receive the velocities
+// of the walls after a step with walls of finite mass
+constexpr int kWallSlot = 32;
 
 // helpers
 static inline int cd_blocks(int64_t n, int threads) {

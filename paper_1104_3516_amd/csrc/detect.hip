@@ -49,8 +49,23 @@ __global__ __launch_bounds__(kThreads) void k_vmax(const double* v, int64_t n,
 struct CellGrid {
   double lo[3];
   double width[3];
+  double period[3];   // > 0: periodic axis of this length (the box's)
   int ncell[3];
 };
+
+// Separation along a periodic axis of length L: the nearest image.
+__device__ inline double min_image(double d, double L) {
+  if (d > 0.5 * L) return d - L;
+  if (d < -0.5 * L) return d + L;
+  return d;
+}
+
+// A coordinate back into [lo, lo + L) after it left by less than L.
+__device__ inline double wrap_into(double q, double lo, double L) {
+  if (q >= lo + L) return q - L;
+  if (q < lo) return q + L;
+  return q;
+}
 
 template <int DIM>
 __device__ inline int cell_coord(double x, double lo, double width, int ncell) {
@@ -83,15 +98,20 @@ __global__ __launch_bounds__(kThreads) void k_cell_scatter(int64_t n, const int*
   members[cell_start[cell] + pos] = (int)i;
 }
 
-// gap of particles i < j: |x_j - x_i| - r_i - r_j (Sec. 2.1, Fig. 1)
+// gap of particles i < j: |x_j - x_i| - r_i - r_j (Sec. 2.1, Fig. 1), at
+// the nearest image along periodic axes
 template <int DIM>
-__device__ inline double pair_gap(const double* x, const double* r, int64_t n, int i, int j) {
+__device__ inline double pair_gap(const double* x, const double* r, int64_t n, int i, int j,
+                                  const CellGrid& g) {
   double d0 = x[j] - x[i];
+  if (g.period[0] > 0.0) d0 = min_image(d0, g.period[0]);
   double d1 = x[n + j] - x[n + i];
+  if (g.period[1] > 0.0) d1 = min_image(d1, g.period[1]);
   double d2 = d0 * d0;
   d2 = d2 + d1 * d1;
   if (DIM == 3) {
     double e = x[2 * n + j] - x[2 * n + i];
+    if (g.period[2] > 0.0) e = min_image(e, g.period[2]);
     d2 = d2 + e * e;
   }
   double dist = sqrt(d2);
@@ -140,20 +160,24 @@ __global__ __launch_bounds__(kThreads) void k_pairs(const double* x, const doubl
   int k = 0;
   int base = FILL ? off[i] : 0;
   const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+  // along a periodic axis (three cells at least) the neighbour cells wrap
   for (int dz = zlo; dz <= zhi; ++dz) {
     int qz = cz + dz;
+    if (DIM == 3 && g.period[2] > 0.0) qz = (qz + g.ncell[2]) % g.ncell[2];
     if (qz < 0 || qz >= g.ncell[2]) continue;
     for (int dy = -1; dy <= 1; ++dy) {
       int qy = cy + dy;
+      if (g.period[1] > 0.0) qy = (qy + g.ncell[1]) % g.ncell[1];
       if (qy < 0 || qy >= g.ncell[1]) continue;
       for (int dx = -1; dx <= 1; ++dx) {
         int qx = cx + dx;
+        if (g.period[0] > 0.0) qx = (qx + g.ncell[0]) % g.ncell[0];
         if (qx < 0 || qx >= g.ncell[0]) continue;
         int q = (qz * g.ncell[1] + qy) * g.ncell[0] + qx;
         for (int s = cell_start[q]; s < cell_start[q + 1]; ++s) {
           int j = members[s];
           if (j <= i) continue;
-          if (pair_gap<DIM>(x, r, n, i, j) <= skin) {
+          if (pair_gap<DIM>(x, r, n, i, j, g) <= skin) {
             if (FILL) {
               // insertion into the particle's sorted range
               int pos = k;
@@ -186,7 +210,7 @@ template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_geometry(const double* x, const double* r, int64_t n,
                                                       const double* wall, int W, int64_t nc,
                                                       const int* ci, const int* cj, double* nrm,
-                                                      double* gap, double* xmid) {
+                                                      double* gap, double* xmid, CellGrid gr) {
   int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (c >= nc) return;
   int i = ci[c], j = cj[c];
@@ -197,6 +221,7 @@ __global__ __launch_bounds__(kThreads) void k_geometry(const double* x, const do
     double d2 = 0.0;
     for (int k = 0; k < DIM; ++k) {
       d[k] = x[k * n + j] - x[k * n + i];
+      if (gr.period[k] > 0.0) d[k] = min_image(d[k], gr.period[k]);
       d2 = d2 + d[k] * d[k];
     }
     double dist = sqrt(d2);
@@ -215,7 +240,10 @@ __global__ __launch_bounds__(kThreads) void k_geometry(const double* x, const do
   double lever = r[i] + 0.5 * g;
   for (int k = 0; k < DIM; ++k) {
     nrm[k * nc + c] = nv[k];
-    xmid[k * nc + c] = x[k * n + i] + lever * nv[k];
+    double q = x[k * n + i] + lever * nv[k];
+    // on a periodic axis the contact position is taken back into the box
+    if (gr.period[k] > 0.0) q = wrap_into(q, gr.lo[k], gr.period[k]);
+    xmid[k * nc + c] = q;
   }
 }
 
@@ -257,6 +285,7 @@ static CellGrid make_grid(cd_ctx* c) {
     g.lo[k] = c->lo[k];
     g.width[k] = c->cwidth[k];
     g.ncell[k] = c->ncell[k];
+    g.period[k] = k < c->dim ? c->period[k] : 0.0;
   }
   return g;
 }
@@ -319,10 +348,12 @@ hipError_t cd_launch_geometry(cd_ctx* c) {
   int nb = cd_blocks(c->nc, kThreads);
   if (c->dim == 2)
     hipLaunchKernelGGL(k_geometry<2>, dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->r, c->n,
-                       c->d_wall, c->W, c->nc, c->ci, c->cj, c->nrm, c->gap, c->xmid);
+                       c->d_wall, c->W, c->nc, c->ci, c->cj, c->nrm, c->gap, c->xmid,
+                       make_grid(c));
   else
     hipLaunchKernelGGL(k_geometry<3>, dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->r, c->n,
-                       c->d_wall, c->W, c->nc, c->ci, c->cj, c->nrm, c->gap, c->xmid);
+                       c->d_wall, c->W, c->nc, c->ci, c->cj, c->nrm, c->gap, c->xmid,
+                       make_grid(c));
   return hipGetLastError();
 }
 

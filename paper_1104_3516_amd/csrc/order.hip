@@ -20,6 +20,8 @@
 //      domain fits, and writes the slot arrays: local body indices, contact
 //      frame, force-law constants and the initial force records;
 //   5. per-particle incidence lists in ascending contact id.
+#include <algorithm>
+
 #include "cd_internal.h"
 
 namespace {
@@ -175,6 +177,8 @@ struct BuildArgs {
   DomainStats* stats;
   const unsigned char* par;   // contacts updated in parallel (canonical order), or null
   int levels;                 // colours by level: the bucket order is the caller's order
+  int mobile;                 // bit w: wall w has finite mass (its contacts conflict)
+  double wim[CD_MAX_WALLS];   // 1/M of each wall (0: prescribed motion)
 };
 
 // Checks a caller's contact list (cd_solve_contacts) before any kernel
@@ -219,6 +223,21 @@ __global__ __launch_bounds__(kThreads) void k_check_inputs(const int* ci, const 
 }
 
 // The caller's order as the bucket, and its sorted domain keys
+// contacts of wall body `body` (flag 1) and, after a scan, their slots
+__global__ __launch_bounds__(kThreads) void k_wall_flags(const int* cj, int64_t nc, int body,
+                                                        int* flag) {
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c < nc) flag[c] = cj[c] == body ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_wall_scatter(const int* flag, const int* pos,
+                                                          int64_t nc, const int* contact_slot,
+                                                          int* out, int* count) {
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c < nc && flag[c]) out[pos[c]] = contact_slot[c];
+  if (c == 0) *count = pos[nc];
+}
+
 __global__ __launch_bounds__(kThreads) void k_order_keys(const int* order, const int* dom,
                                                         int64_t nc, unsigned long long* keys,
                                                         int* bucket) {
@@ -250,8 +269,12 @@ __device__ inline int colour_of(unsigned long long used, bool levels) {
 
 template <typename M, typename I, typename C, typename Par>
 __device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb_s, C* col_s,
-                                    C* rank_s, int* cnt, Par&& par, bool levels) {
+                                    C* rank_s, int* cnt, Par&& par, bool levels, int mobile,
+                                    unsigned long long wmask0) {
   int ncol = 0;
+  // colour sets of the walls of finite mass (bodies whose contacts conflict)
+  unsigned long long wmask[CD_MAX_WALLS];
+  for (int q = 0; q < CD_MAX_WALLS; ++q) wmask[q] = wmask0;
   for (int k = 0; k < nct; ++k) {
     if (par(k)) {
       col_s[k] = (C)0;
@@ -261,7 +284,9 @@ __device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb
       continue;
     }
     const int la = la_s[k], lb = lb_s[k];
-    const unsigned long long used = mask[la] | (lb >= 0 ? mask[lb] : 0ull);
+    const bool bw = lb < 0 && ((mobile >> (-1 - lb)) & 1);
+    const unsigned long long used =
+        mask[la] | (lb >= 0 ? (unsigned long long)mask[lb] : (bw ? wmask[-1 - lb] : 0ull));
     const int col = colour_of(used, levels);
     if (col >= CD_MAX_COLORS) return -1;
     col_s[k] = (C)col;
@@ -269,6 +294,7 @@ __device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb
     cnt[col] += 1;
     mask[la] |= 1ull << col;
     if (lb >= 0) mask[lb] |= 1ull << col;
+    else if (bw) wmask[-1 - lb] |= 1ull << col;
     if (col + 1 > ncol) ncol = col + 1;
   }
   return ncol;
@@ -280,7 +306,8 @@ __device__ inline int colour_serial(int nct, M* mask, const I* la_s, const I* lb
 // (the next contact's bodies are read one step ahead).
 __device__ inline int colour_wave(int nct, unsigned long long* mask, const int* la_s,
                                   const int* lb_s, short* col_s, short* rank_s, int* cnt_out,
-                                  const unsigned char* par, bool levels) {
+                                  const unsigned char* par, bool levels, int mobile,
+                                  unsigned long long* wmask) {
   static_assert(CD_MAX_COLORS == 64, "one lane per colour");
   const int lane = threadIdx.x & 63;
   int cnt = 0;   // contacts of colour `lane` so far
@@ -302,7 +329,10 @@ __device__ inline int colour_wave(int nct, unsigned long long* mask, const int* 
       lb = lb_n;
       continue;
     }
-    const unsigned long long ma = mask[la], mb = lb >= 0 ? mask[lb] : 0ull;
+    // a wall of finite mass is a body: its contacts conflict
+    const bool bw = lb < 0 && ((mobile >> (-1 - lb)) & 1);
+    const unsigned long long ma = mask[la],
+                             mb = lb >= 0 ? mask[lb] : (bw ? wmask[-1 - lb] : 0ull);
     const unsigned long long used = ma | mb;
     const int col = __builtin_amdgcn_readfirstlane(colour_of(used, levels));
     if (col >= CD_MAX_COLORS) return -1;
@@ -313,6 +343,7 @@ __device__ inline int colour_wave(int nct, unsigned long long* mask, const int* 
       rank_s[k] = (short)rank;
       mask[la] = ma | (1ull << col);
       if (lb >= 0) mask[lb] = mb | (1ull << col);
+      else if (bw) wmask[-1 - lb] = mb | (1ull << col);
     }
     if (col + 1 > ncol) ncol = col + 1;
     la = la_n;
@@ -395,6 +426,8 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   __shared__ int s_cnt[CD_MAX_COLORS];
   __shared__ int s_coloff[CD_MAX_COLORS + 1];
   __shared__ int s_ncol;
+  __shared__ unsigned long long s_wmask[CD_MAX_WALLS];
+  __shared__ int s_wtouch;
 
   const int d = blockIdx.x;
   const int cs = a.dom_start[d], nct = a.dom_start[d + 1] - cs;
@@ -408,6 +441,8 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   for (int q = threadIdx.x; q < CD_MAX_COLORS; q += blockDim.x) s_cnt[q] = 0;
   // mixed update: colour 0 is reserved for the contacts updated in parallel
   const unsigned long long mask0 = a.par ? 1ull : 0ull;
+  for (int q = threadIdx.x; q < CD_MAX_WALLS; q += blockDim.x) s_wmask[q] = mask0;
+  if (threadIdx.x == 0) s_wtouch = 0;
   if (small) {
     for (int k = threadIdx.x; k < np; k += blockDim.x) s_mask[k] = mask0;
     for (int k = threadIdx.x; k < nct; k += blockDim.x) {
@@ -421,7 +456,7 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   __syncthreads();
   int ncol_w = 0;
   if (small) ncol_w = colour_wave(nct, s_mask, s_la, s_lb, s_col, s_rank, s_cnt,
-                                  a.par ? s_par : nullptr, a.levels != 0);
+                                  a.par ? s_par : nullptr, a.levels != 0, a.mobile, s_wmask);
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned char* par = a.par;
@@ -430,7 +465,7 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     const int ncol = small ? ncol_w
                            : colour_serial(nct, a.gmask + ps, a.qla + cs, a.qlb + cs,
                                            a.qcol + cs, a.qpos + cs, s_cnt, is_par,
-                                           a.levels != 0);
+                                           a.levels != 0, a.mobile, mask0);
     s_coloff[0] = 0;
     for (int q = 0; q < ncol; ++q) s_coloff[q + 1] = s_coloff[q] + s_cnt[q];
     s_ncol = ncol;
@@ -439,6 +474,15 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   if (s_ncol < 0) {
     if (threadIdx.x == 0) atomicMax(&a.stats->overflow, 2);
     return;
+  }
+  // the walls of finite mass this domain touches (its sweep recomputes their
+  // velocity in the exchange)
+  if (a.mobile) {
+    for (int k = threadIdx.x; k < nct; k += blockDim.x) {
+      const int lb = small ? s_lb[k] : a.qlb[cs + k];
+      if (lb < 0 && ((a.mobile >> (-1 - lb)) & 1)) atomicOr(&s_wtouch, 1 << (-1 - lb));
+    }
+    __syncthreads();
   }
   // stable order by colour
   int* pos = a.qpos + cs;
@@ -458,7 +502,8 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     int widest = 0;   // the largest colour (of the sequential ones in the mixed update)
     for (int q = a.par ? 1 : 0; q < ncol; ++q) widest = max(widest, s_coloff[q + 1] - s_coloff[q]);
     dd[5] = widest;
-    dd[6] = dd[7] = 0;
+    dd[6] = s_wtouch;
+    dd[7] = 0;
     a.dncol[d] = ncol;
   }
   for (int q = threadIdx.x; q <= CD_MAX_COLORS; q += blockDim.x)
@@ -495,6 +540,12 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     double wn = a.inv_m[i] + (j < nn ? a.inv_m[j] : 0.0);
     double wt = wn + (a.r[i] * a.r[i]) * a.inv_I[i];
     wt = wt + (j < nn ? (a.r[j] * a.r[j]) * a.inv_I[j] : 0.0);
+    if (j >= nn && ((a.mobile >> (j - nn)) & 1)) {
+      // a wall of finite mass moves along its normal only: 1/M adds to the
+      // normal term, nothing to the tangential one
+      wn = a.inv_m[i] + a.wim[j - nn];
+      wt = a.inv_m[i] + (a.r[i] * a.r[i]) * a.inv_I[i];
+    }
     double ge = a.gap[c];
     if (a.clamp && ge < 0.0) ge = 0.0;
     double* g = a.geo;
@@ -761,6 +812,8 @@ hipError_t cd_launch_order(cd_ctx* c) {
   BuildArgs a;
   a.par = par;
   a.levels = c->given_order != nullptr;
+  a.mobile = c->mobile_mask;
+  for (int q = 0; q < CD_MAX_WALLS; ++q) a.wim[q] = c->wim[q];
   a.dom_start = c->dom_start;
   a.bucket = c->bucket;
   a.dp_start = c->dp_start;
@@ -804,6 +857,11 @@ hipError_t cd_launch_order(cd_ctx* c) {
   if (nc > 0)
     hipLaunchKernelGGL(k_inc_slots, dim3(cd_blocks(2 * nc, kThreads)), dim3(kThreads), 0,
                        c->stream, c->inc_ptr + n, 2 * nc, c->contact_slot, c->inc);
+  // 5b. walls of finite mass: each one's contact slots in ascending contact id
+  if (c->mobile_mask) {
+    e = cd_launch_wall_lists(c);
+    if (e != hipSuccess) return e;
+  }
   // 6. domain particle entries and their incidence counts
   const int64_t E = 2 * c->cap;
   if (c->dim == 2)
@@ -817,6 +875,36 @@ hipError_t cd_launch_order(cd_ctx* c) {
   e = cd_scan_exclusive(c, c->flag, c->dinc_ptr, E);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dinc_total, dim3(1), dim3(1), 0, c->stream, c->dinc_ptr, E, c->d_stats);
+  return hipGetLastError();
+}
+
+hipError_t cd_launch_wall_lists(cd_ctx* c) {
+  const int64_t nc = c->nc;
+  hipError_t e;
+  const int64_t need = (int64_t)c->W * c->cap;
+  if (c->wall_slot_cap < need || !c->wall_slot) {
+    if (c->wall_slot) (void)hipFree(c->wall_slot);
+    c->wall_slot = nullptr;
+    c->wall_slot_cap = 0;
+    e = hipMalloc((void**)&c->wall_slot, sizeof(int) * (size_t)std::max<int64_t>(need, 1));
+    if (e != hipSuccess) return e;
+    c->wall_slot_cap = need;
+  }
+  for (int w = 0; w < c->W; ++w) {
+    if (!((c->mobile_mask >> w) & 1)) continue;
+    if (nc == 0) {
+      e = hipMemsetAsync(c->wall_cnt + w, 0, sizeof(int), c->stream);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    hipLaunchKernelGGL(k_wall_flags, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0, c->stream,
+                       c->cj, nc, (int)(c->n + w), c->flag);
+    e = cd_scan_exclusive(c, c->flag, c->flag_scan, nc);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wall_scatter, dim3(cd_blocks(nc, kThreads)), dim3(kThreads), 0,
+                       c->stream, c->flag, c->flag_scan, nc, c->contact_slot,
+                       c->wall_slot + (int64_t)w * c->cap, c->wall_cnt + w);
+  }
   return hipGetLastError();
 }
 

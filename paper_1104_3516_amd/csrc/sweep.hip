@@ -207,14 +207,17 @@ __device__ inline void decide_wave(const SweepArgs& a, int jd) {
 // than a wavefront), so that a launch has one workgroup per domain.
 // TIMED: per-domain load measurement into a.dtick (single contexts with load
 // balancing on; a separate instantiation so that the plain sweep is unchanged).
+// MOBILE: the box has walls of finite mass (a separate instantiation).
 template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false,
-          bool RAND = false>
+          bool RAND = false, bool MOBILE = false>
 __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArgs& a, int b, int j,
                                                                   BatchProg* bp) {
   extern __shared__ double lds[];
   __shared__ BlockRed red;
   __shared__ int s_co[CD_MAX_COLORS + 1];
   __shared__ double s_wu[CD_MAX_WALLS * 3];
+  __shared__ double s_wm[MOBILE ? CD_MAX_WALLS : 1];
+  __shared__ double s_wtmp[MOBILE ? kMaxBlock : 1];
   __shared__ int s_flag;
   if (!FOLD && b == a.grid) {
     if (j >= 2) decide_block(a, j - 1, red, s_flag, bp, a.block);
@@ -240,9 +243,9 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
     // its domain (its wavefront runs the colours; a folded decision is
     // taken by another wavefront and not counted), summed over the step
     const unsigned long long t0 = TIMED ? __builtin_amdgcn_s_memrealtime() : 0ull;
-    sweep_domain<DIM, GLOB, STAGE, MIXED, RAND>(
+    sweep_domain<DIM, GLOB, STAGE, MIXED, RAND, MOBILE>(
         a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr,
-        RAND ? rand_mix(a.rkey ^ (unsigned long long)j) : 0ull, idle);
+        RAND ? rand_mix(a.rkey ^ (unsigned long long)j) : 0ull, idle, s_wm, s_wtmp);
     if (TIMED && threadIdx.x == 0) a.dtick[d] += __builtin_amdgcn_s_memrealtime() - t0;
   } else {
     idle();
@@ -260,9 +263,9 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
 // RAND: the random sequential order of Sec. 2.1 (thread 0 of each domain's
 // workgroup updates its contacts one at a time), a separate instantiation.
 template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false,
-          bool RAND = false>
+          bool RAND = false, bool MOBILE = false>
 __global__ __launch_bounds__(kMaxBlock, STAGE && DIM == 2 ? 5 : 1) void k_sweep(SweepArgs a, int j) {
-  sweep_block<DIM, GLOB, STAGE, FOLD, MIXED, TIMED, RAND>(a, blockIdx.x, j, nullptr);
+  sweep_block<DIM, GLOB, STAGE, FOLD, MIXED, TIMED, RAND, MOBILE>(a, blockIdx.x, j, nullptr);
 }
 
 // Sweep j of a batch of packings: workgroup b serves packing blk[2b] as its
@@ -501,6 +504,12 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.geo = c->geo;
   a.walls_u = c->d_wall + (size_t)c->W * c->dim + c->W;
   a.n_walls = c->W;
+  a.walls_n = c->d_wall;
+  a.walls_dtim = c->d_wall + CD_WALL_DTIM;
+  a.walls_force = c->d_wall + CD_WALL_FORCE;
+  a.wall_slot = c->wall_slot;
+  a.wall_cnt = c->wall_cnt;
+  a.mobile = c->mobile_mask;
   a.rec[0] = c->rec[0];
   a.rec[1] = c->rec[1];
   a.mu_slot = c->use_mu_slot ? c->mu_slot : c->d_wall + CD_WALL_MU;
@@ -614,7 +623,10 @@ void cd_sweep_mode(cd_ctx* c) {
   // separate decision workgroup runs alongside the domains and workgroup 0
   // would only become the slowest one.
   const int64_t domains = (int64_t)8 * ((c->P + 7) / 8);
-  const size_t extra = cd_random_lds(c);
+  // the random order's draws, and the exchange buffer of walls of finite mass
+  // (static LDS beyond the 2 KiB the checks allow for)
+  const size_t extra =
+      cd_random_lds(c) + (c->mobile_mask ? sizeof(double) * (kMaxBlock + CD_MAX_WALLS) : 0);
   c->sweep_stage = cd_stage_pick(c->dim, c->sweep_block, c->sweep_lds + extra,
                                  c->sweep_lds_stage + extra, domains + 1, domains + 1, c->num_cu,
                                  c->max_lds, false);
@@ -629,28 +641,32 @@ void cd_sweep_mode(cd_ctx* c) {
 
 // One sweep launch in the context's form (global records, staged with the
 // decision folded into workgroup 0, staged, register read-ahead).
-template <int DIM, bool MIXED, bool TIMED, bool RAND = false>
+template <int DIM, bool MIXED, bool TIMED, bool RAND = false, bool MOBILE = false>
 static void launch_sweep_form(cd_ctx* c, const SweepArgs& a, dim3 grid, dim3 block, size_t lds,
                               bool fold, int j) {
   if (c->sweep_global)
-    hipLaunchKernelGGL((k_sweep<DIM, true, false, false, MIXED, TIMED, RAND>), grid, block,
+    hipLaunchKernelGGL((k_sweep<DIM, true, false, false, MIXED, TIMED, RAND, MOBILE>), grid, block,
                        RAND ? lds : 0, c->stream, a, j);
   else if (fold)
-    hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED, TIMED, RAND>), grid, block, lds,
-                       c->stream, a, j);
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED, TIMED, RAND, MOBILE>), grid, block,
+                       lds, c->stream, a, j);
   else if (c->sweep_stage)
-    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED, TIMED, RAND>), grid, block, lds,
-                       c->stream, a, j);
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED, TIMED, RAND, MOBILE>), grid,
+                       block, lds, c->stream, a, j);
   else
-    hipLaunchKernelGGL((k_sweep<DIM, false, false, false, MIXED, TIMED, RAND>), grid, block, lds,
-                       c->stream, a, j);
+    hipLaunchKernelGGL((k_sweep<DIM, false, false, false, MIXED, TIMED, RAND, MOBILE>), grid,
+                       block, lds, c->stream, a, j);
 }
 
 template <int DIM>
 static void launch_sweep_dim(cd_ctx* c, const SweepArgs& a, dim3 grid, dim3 block, size_t lds,
                              bool fold, int j) {
   const bool timed = a.dtick != nullptr;
-  if (c->order_random) {
+  if (c->mobile_mask) {
+    // walls of finite mass: the plain colour-major sweep only (the setters
+    // refuse the mixed update, the random order and load timing with them)
+    launch_sweep_form<DIM, false, false, false, true>(c, a, grid, block, lds, fold, j);
+  } else if (c->order_random) {
     launch_sweep_form<DIM, false, false, true>(c, a, grid, block, lds, fold, j);
   } else if (c->order_mixed) {
     if (timed) launch_sweep_form<DIM, true, true>(c, a, grid, block, lds, fold, j);

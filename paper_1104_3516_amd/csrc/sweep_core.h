@@ -325,10 +325,13 @@ __device__ inline void account(const double* Rold, const double* Rn, double alph
 // and the contact's test values accounted.  APPLY = false (a contact
 // updated in parallel, Sec. 2.3): the change is not applied to the bodies,
 // which see it only through the next exchange.
-template <int DIM, bool APPLY = true>
-__device__ inline void update_contact(double* sp, const double* wu, const SlotPre<DIM>& c,
+// MOBILE: walls may have finite mass (wm: dt/M per wall, 0 for a wall of
+// prescribed motion); such a wall's domain copy of its velocity in `wu` takes
+// the normal part of the change, (dt/M) dR_n n (n = -nu).
+template <int DIM, bool APPLY = true, bool MOBILE = false>
+__device__ inline void update_contact(double* sp, double* wu, const SlotPre<DIM>& c,
                                       double alpha, double* ro, long long& npass,
-                                      double& maxd, double& sumr) {
+                                      double& maxd, double& sumr, const double* wm = nullptr) {
   constexpr int DR = Layout<DIM>::DR;
   const int la = c.ab.x, lb = c.ab.y;
   Body<DIM> A, B;
@@ -378,6 +381,11 @@ __device__ inline void update_contact(double* sp, const double* wu, const SlotPr
     for (int q = 0; q < DIM; ++q) Vb[q] = B.V[q] + B.dm * dF[q];
     for (int q = 0; q < DR; ++q) Wb[q] = B.W[q] - B.di * (B.r * dq[q]);
     write_velocities<DIM>(sp, lb, Vb, Wb);
+  } else if (MOBILE && APPLY) {
+    const int w = -1 - lb;
+    const double dtim = wm[w];
+    if (dtim != 0.0)
+      for (int q = 0; q < DIM; ++q) wu[w * DIM + q] = B.V[q] + dtim * (dRn * nv[q]);
   }
   // new record: frame force, world force, torque per unit lever (streamed
   // out: nothing in this launch reads it back)
@@ -553,6 +561,7 @@ __device__ inline void entry_finish_staged(const SweepArgs& a, const double* rin
 struct DomainHead {
   int cs, nct, ps, np, ncol;
   int widest;   // contacts of the domain's largest colour
+  int wmask;    // walls of finite mass the domain touches (bit w)
   int co;       // colour offset number threadIdx.x (threads 0..CD_MAX_COLORS)
   double wu;    // wall velocity component number threadIdx.x
 };
@@ -567,6 +576,7 @@ __device__ inline DomainHead load_head(const SweepArgs& a, int d) {
   h.np = dd[3];
   h.ncol = dd[4];
   h.widest = dd[5];
+  h.wmask = dd[6];
   const int tid = threadIdx.x;
   // every colour offset of a domain is written (unused ones hold the count)
   h.co = tid <= CD_MAX_COLORS ? a.dcol[(int64_t)d * (CD_MAX_COLORS + 1) + tid] : 0;
@@ -633,11 +643,19 @@ __host__ __device__ inline unsigned long long rand_mix(unsigned long long x) {
 // alongside the exchange (all its loads in flight at once) and the colours
 // read it from there; otherwise each thread reads its contact of the next
 // colour into registers one colour ahead.
-template <int DIM, bool GLOB, bool STAGE, bool MIXED = false, bool RAND = false, class Idle>
+// MOBILE: walls of finite mass (Sec. 4.1): a domain touching one takes its
+// velocity after the exchange from all its contacts' forces of the previous
+// sweep (read in parallel into s_wtmp, summed in ascending contact id by one
+// thread: u_n + dt/M (F - sum R_n) along nu, tangential part kept) and keeps
+// its own copy in s_wu, which the domain's contacts with it update (s_wm:
+// dt/M per wall).
+template <int DIM, bool GLOB, bool STAGE, bool MIXED = false, bool RAND = false,
+          bool MOBILE = false, class Idle>
 __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead& h,
                                     const double* rin, double* rout, double* lds, int* s_co,
                                     double* s_wu, long long& npass, double& maxd, double& sumr,
-                                    unsigned long long jkey, Idle&& idle) {
+                                    unsigned long long jkey, Idle&& idle,
+                                    double* s_wm = nullptr, double* s_wtmp = nullptr) {
   static_assert(!(GLOB && STAGE), "staged contact data needs the particles in LDS");
   using L = Layout<DIM>;
   constexpr int REC = L::REC, PS = L::PS;
@@ -652,6 +670,36 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
   if (tid <= CD_MAX_COLORS) s_co[tid] = h.co;
   for (int q = tid + nthr; q <= CD_MAX_COLORS; q += nthr) s_co[q] = dcol[q];
   if (tid < a.n_walls * DIM) s_wu[tid] = h.wu;
+  if (MOBILE) {
+    if (tid < a.n_walls) s_wm[tid] = a.walls_dtim[tid];
+    if (h.wmask) {
+      __syncthreads();
+      for (int w = 0; w < a.n_walls; ++w) {
+        if (!((h.wmask >> w) & 1)) continue;
+        const int cnt = a.wall_cnt[w];
+        const int* ls = a.wall_slot + (int64_t)w * a.cap;
+        double acc = a.walls_force[w];
+        for (int base = 0; base < cnt; base += nthr) {
+          const int k = base + tid;
+          if (k < cnt) s_wtmp[tid] = rin[(int64_t)ls[k] * REC];
+          __syncthreads();
+          if (tid == 0) {
+            const int m = cnt - base < nthr ? cnt - base : nthr;
+            for (int e = 0; e < m; ++e) acc = acc - s_wtmp[e];
+          }
+          __syncthreads();
+        }
+        if (tid == 0) {
+          const double* nu = a.walls_n + w * DIM;
+          const double* u = a.walls_u + w * DIM;
+          double un = 0.0;
+          for (int k = 0; k < DIM; ++k) un = un + nu[k] * u[k];
+          const double un1 = un + a.walls_dtim[w] * acc;
+          for (int k = 0; k < DIM; ++k) s_wu[w * DIM + k] = (u[k] - un * nu[k]) + un1 * nu[k];
+        }
+      }
+    }
+  }
   SlotPre<DIM> cur;
   int kc = -1;
   double* sl = lds + (int64_t)PS * np;
@@ -738,8 +786,8 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
         SlotPre<DIM> c;
         if (STAGE) get_slot<DIM>(sl, nct, k, mu0, mu_slot, c);
         else fetch_slot<DIM, true>(a, rin, cs + k, c);
-        update_contact<DIM>(sp, s_wu, c, a.alpha, rout + (int64_t)(cs + k) * REC, npass, maxd,
-                            sumr);
+        update_contact<DIM, true, MOBILE>(sp, s_wu, c, a.alpha, rout + (int64_t)(cs + k) * REC, npass, maxd,
+                            sumr, s_wm);
       }
     }
     idle();
@@ -770,8 +818,8 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
           if (k < s_co[col + 1]) {
             SlotPre<DIM> c;
             get_slot<DIM>(sl, nct, k, mu0, mu_slot, c);
-            update_contact<DIM>(sp, s_wu, c, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
-                                maxd, sumr);
+            update_contact<DIM, true, MOBILE>(sp, s_wu, c, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
+                                maxd, sumr, s_wm);
           }
           wave_lds_order();
         }
@@ -785,8 +833,8 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
       for (int k = k0 + tid; k < k1; k += nthr) {
         SlotPre<DIM> c;
         get_slot<DIM>(sl, nct, k, mu0, mu_slot, c);
-        update_contact<DIM>(sp, s_wu, c, a.alpha, rout + (int64_t)(cs + k) * REC, npass, maxd,
-                            sumr);
+        update_contact<DIM, true, MOBILE>(sp, s_wu, c, a.alpha, rout + (int64_t)(cs + k) * REC, npass, maxd,
+                            sumr, s_wm);
       }
       // the colour's velocity updates must be seen by the next colour; the
       // record stores stay in flight
@@ -808,8 +856,8 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
     fetch_slot<DIM, true>(a, rin, cs + (kp >= 0 ? kp : 0), pre);
     settle<DIM>(use);
     if (ku >= 0)
-      update_contact<DIM>(sp, s_wu, use, a.alpha, rout + (int64_t)(cs + ku) * REC, npass,
-                          maxd, sumr);
+      update_contact<DIM, true, MOBILE>(sp, s_wu, use, a.alpha, rout + (int64_t)(cs + ku) * REC, npass,
+                          maxd, sumr, s_wm);
     // colours wider than the workgroup (rare); the path ends with all its
     // memory accesses complete, so that it leaves no pending store whose
     // registers the common path would have to wait for
@@ -817,8 +865,8 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
       for (int k = k0 + tid + nthr; k < k1; k += nthr) {
         SlotPre<DIM> sd;
         fetch_slot<DIM, true>(a, rin, cs + k, sd);
-        update_contact<DIM>(sp, s_wu, sd, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
-                            maxd, sumr);
+        update_contact<DIM, true, MOBILE>(sp, s_wu, sd, a.alpha, rout + (int64_t)(cs + k) * REC, npass,
+                            maxd, sumr, s_wm);
       }
       __builtin_amdgcn_s_waitcnt(kWaitVm0);
     }

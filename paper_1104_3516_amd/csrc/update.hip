@@ -21,13 +21,18 @@ __global__ __launch_bounds__(kThreads) void k_derived(const double* m, const dou
   dtii[i] = dt * ii;
 }
 
+// periodic axes (length > 0) and the box's lower corner
+struct Period {
+  double lo[3], len[3];
+};
+
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_update(double* x, double* v, double* w,
                                                     const double* f, const double* t,
                                                     const double* r, const double* dtim,
                                                     const double* dtii, const int* inc_ptr,
                                                     const int* inc, const double* rec, int64_t n,
-                                                    double dt) {
+                                                    double dt, Period per) {
   constexpr int DR = DIM == 2 ? 1 : 3;
   constexpr int REC = DIM == 2 ? 4 : 12;
   int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -61,7 +66,14 @@ __global__ __launch_bounds__(kThreads) void k_update(double* x, double* v, doubl
   for (int k = 0; k < DIM; ++k) {
     double V = v[k * n + p] + dm * acc[k];
     v[k * n + p] = V;
-    x[k * n + p] = x[k * n + p] + V * dt;
+    double q = x[k * n + p] + V * dt;
+    // a particle leaving a periodic box enters it on the other side
+    if (per.len[k] > 0.0) {
+      const double L = per.len[k], lo = per.lo[k];
+      if (q >= lo + L) q = q - L;
+      else if (q < lo) q = q + L;
+    }
+    x[k * n + p] = q;
   }
   for (int k = 0; k < DR; ++k) w[k * n + p] = w[k * n + p] + di * tacc[k];
 }
@@ -83,7 +95,55 @@ __global__ __launch_bounds__(kThreads) void k_count_active(const double* R, int6
   }
 }
 
+// Velocity of each wall after the final forces (Eq. 1 for the wall body): a
+// wall of finite mass takes u_n + dt/M (F - sum of R_n over its contacts in
+// ascending contact id) along its normal nu and keeps its tangential
+// velocity; the others keep theirs.  One workgroup per wall: the forces are
+// read in parallel into LDS and summed in order by one thread.
+__global__ __launch_bounds__(kThreads) void k_wall_velocities(int dim, int W, int mobile,
+                                                             const double* wall,
+                                                             const double* rec, int REC,
+                                                             const int* wall_slot,
+                                                             const int* wall_cnt, int64_t cap,
+                                                             double* out) {
+  __shared__ double buf[kThreads];
+  const int q = blockIdx.x;
+  const double* nu = wall + q * dim;
+  const double* u = wall + W * dim + W + q * dim;
+  if (!((mobile >> q) & 1)) {
+    if (threadIdx.x < dim) out[q * dim + threadIdx.x] = u[threadIdx.x];
+    return;
+  }
+  const int cnt = wall_cnt[q];
+  const int* ls = wall_slot + (int64_t)q * cap;
+  double acc = wall[CD_WALL_FORCE + q];
+  for (int base = 0; base < cnt; base += kThreads) {
+    const int k = base + threadIdx.x;
+    if (k < cnt) buf[threadIdx.x] = rec[(int64_t)ls[k] * REC];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int m = cnt - base < kThreads ? cnt - base : kThreads;
+      for (int e = 0; e < m; ++e) acc = acc - buf[e];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double un = 0.0;
+    for (int k = 0; k < dim; ++k) un = un + nu[k] * u[k];
+    const double un1 = un + wall[CD_WALL_DTIM + q] * acc;
+    for (int k = 0; k < dim; ++k) out[q * dim + k] = (u[k] - un * nu[k]) + un1 * nu[k];
+  }
+}
+
 }  // namespace
+
+hipError_t cd_launch_wall_velocities(cd_ctx* c) {
+  if (c->W == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wall_velocities, dim3(c->W), dim3(kThreads), 0, c->stream, c->dim, c->W,
+                     c->mobile_mask, c->d_wall, c->rec[c->h_state->iter & 1],
+                     c->dim == 2 ? 4 : 12, c->wall_slot, c->wall_cnt, c->cap, c->d_wall_new);
+  return hipGetLastError();
+}
 
 hipError_t cd_launch_count_active(cd_ctx* c, unsigned long long* count) {
   hipError_t e = hipMemsetAsync(count, 0, sizeof(unsigned long long), c->stream);
@@ -102,11 +162,16 @@ hipError_t cd_launch_derived(cd_ctx* c) {
 hipError_t cd_launch_update(cd_ctx* c, int final_iter) {
   const double* rec = c->rec[final_iter & 1];
   int nb = cd_blocks(c->n, kThreads);
+  Period per;
+  for (int k = 0; k < 3; ++k) {
+    per.lo[k] = c->lo[k];
+    per.len[k] = k < c->dim ? c->period[k] : 0.0;
+  }
   if (c->dim == 2)
     hipLaunchKernelGGL(k_update<2>, dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->v, c->w, c->f,
-                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->n, c->p.dt);
+                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->n, c->p.dt, per);
   else
     hipLaunchKernelGGL(k_update<3>, dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->v, c->w, c->f,
-                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->n, c->p.dt);
+                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->n, c->p.dt, per);
   return hipGetLastError();
 }
