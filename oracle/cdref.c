@@ -1268,9 +1268,11 @@ int cdref_sim_set_capacity(cdref_sim* s, const double* capacity) {
   return CDREF_OK;
 }
 
-static int ensure_capacity(cdref_sim* s, int64_t need) {
+/* contact arrays for at least `need` contacts: a quarter more than needed
+ * when they grow, exactly `keep` (the previous capacity) otherwise */
+static int ensure_capacity(cdref_sim* s, int64_t need, int64_t keep) {
   if (need <= s->cap) return CDREF_OK;
-  int64_t cap = need + need / 4 + 64;
+  int64_t cap = need > keep ? need + need / 4 + 64 : keep;
   int dim = s->p.dim;
   free(s->ci); free(s->cj); free(s->dom); free(s->color); free(s->slot);
   free(s->normal); free(s->gap); free(s->xmid);
@@ -1346,7 +1348,7 @@ int cdref_sim_step(cdref_sim* s, cdref_info* info) {
     free(s->dom); free(s->color); free(s->slot); free(s->normal); free(s->gap); free(s->xmid);
     s->dom = NULL; s->color = NULL; s->slot = NULL; s->normal = NULL; s->gap = NULL; s->xmid = NULL;
     s->cap = 0;
-    st = ensure_capacity(s, nc > keep_cap ? nc : keep_cap);
+    st = ensure_capacity(s, nc, keep_cap);
     if (st != CDREF_OK) { free(ci); free(cj); return st; }
     memcpy(s->ci, ci, sizeof(int32_t) * (size_t)nc);
     memcpy(s->cj, cj, sizeof(int32_t) * (size_t)nc);
