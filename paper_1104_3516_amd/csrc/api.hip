@@ -200,7 +200,7 @@ int alloc_tree(cd_ctx* c) {
 int ensure_capacity(cd_ctx* c, int64_t need) {
   if (need <= c->cap && c->cap > 0) return CD_OK;
   int64_t cap = need + need / 4 + 1024;
-  const int rec = c->dim == 2 ? 4 : 12;
+  const int rec = kRec;
   CD_TRY(grow(&c->dom, cap));
   CD_TRY(grow(&c->color, cap));
   CD_TRY(grow(&c->nrm, c->dim * cap));
@@ -211,6 +211,7 @@ int ensure_capacity(cd_ctx* c, int64_t need) {
     CD_TRY(grow(&c->sort_vals[k], 2 * cap));
     CD_TRY(grow(&c->rec[k], rec * cap));
   }
+  if (c->dim == 3) CD_TRY(grow(&c->nrm4, 4 * cap));
   CD_TRY(grow(&c->q_la, cap));
   CD_TRY(grow(&c->q_lb, cap));
   CD_TRY(grow(&c->q_col, cap));
@@ -440,7 +441,7 @@ int cd_destroy(cd_ctx* c) {
   double** dbl[] = {&c->x, &c->v, &c->w, &c->r, &c->m, &c->I, &c->f, &c->t, &c->inv_m,
                     &c->inv_I, &c->dtim, &c->dtii, &c->d_wall, &c->nrm, &c->gap, &c->xmid,
                     &c->R, &c->R_prev, &c->d_cut, &c->d_region, &c->geo, &c->rec[0],
-                    &c->rec[1]};
+                    &c->rec[1], &c->nrm4};
   for (auto p : dbl) release(p);
   int** ints[] = {&c->cell_of, &c->cell_count, &c->cell_start, &c->cell_members,
                   &c->pair_count, &c->pair_off, &c->ci, &c->cj, &c->dom, &c->color,
@@ -539,6 +540,23 @@ int cd_set_particles(cd_ctx* c, const double* x, const double* v, const double* 
 int cd_set_external(cd_ctx* c, const double* force, const double* torque) {
   if (!c) return CD_EINVAL;
   const int64_t n = c->n;
+  // whether every component is +0.0 (then the sweeps need not read them)
+  bool zero = true;
+  for (int which = 0; which < 2 && zero; ++which) {
+    const double* src = which == 0 ? force : torque;
+    const int64_t count = (which == 0 ? c->dim : c->dr) * n;
+    if (!src) continue;
+    std::vector<unsigned long long> h((size_t)count);
+    CD_TRY(hipMemcpyAsync(h.data(), src, sizeof(double) * (size_t)count, hipMemcpyDeviceToHost,
+                          c->stream));
+    CD_TRY(hipStreamSynchronize(c->stream));
+    for (int64_t k = 0; k < count; ++k)
+      if (h[(size_t)k] != 0ull) {
+        zero = false;
+        break;
+      }
+  }
+  c->ext_zero = zero;
   if (force)
     CD_TRY(hipMemcpyAsync(c->f, force, sizeof(double) * c->dim * n, hipMemcpyDeviceToDevice,
                           c->stream));

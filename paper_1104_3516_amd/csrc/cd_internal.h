@@ -9,10 +9,11 @@
 //     slot range [dom_start[d], dom_start[d+1]) sorted by (colour, contact id);
 //     per slot: local body indices (a, b), frame (n, and t1, t2 in 3D) and the
 //     constants of the force law; forces live in two ping-pong record arrays
-//     rec[0], rec[1] of REC doubles per slot:
+//     rec[0], rec[1] of 4 doubles (32 bytes) per slot:
 //       2D: (R_n, R_t, F_x, F_y)  with F = R_n n + R_t t the world force,
-//       3D: (R_n, R_t1, R_t2, 0, F_x, F_y, F_z, 0, q_x, q_y, q_z, 0) with
-//           q = n x R (torque per unit lever);
+//       3D: (R_n, R_t1, R_t2, 0); the world force F and the torque per unit
+//           lever q = n x R follow from R and the slot's normal (nrm4: n_x,
+//           n_y, n_z, 0 per slot) with the tangents recomputed from n;
 //   per domain: its particles (ascending id) and colour offsets;
 //   per particle: incident slots in ascending contact id (sign bit = body 2).
 #pragma once
@@ -116,6 +117,8 @@ struct SweepArgs {
   const double* walls_u;    // W x dim wall velocities
   int n_walls;
   double* rec[2];
+  const double* nrm4;       // 3D: per slot (n_x, n_y, n_z, 0)
+  int ext_zero;             // every external force and torque is +0.0: not read
   const double* mu_slot;    // friction of slot s at mu_slot[s * mu_step]
   int mu_step;              // 1: per slot; 0: one coefficient for all
   // convergence
@@ -278,6 +281,8 @@ struct cd_ctx {
   int2* slot_ab = nullptr;
   double* geo = nullptr;
   double* rec[2] = {nullptr, nullptr};
+  double* nrm4 = nullptr;        // 3D: per slot normal, 4 doubles
+  bool ext_zero = true;          // every external force and torque is +0.0
   int *dcol = nullptr, *dncol = nullptr, *dp = nullptr, *dp_count = nullptr, *dp_start = nullptr;
   int *q_la = nullptr, *q_lb = nullptr, *q_col = nullptr, *q_pos = nullptr;
   unsigned long long* g_mask = nullptr;
@@ -465,6 +470,39 @@ constexpr int kActiveSlot = 63;
 // first of the slots (CD_MAX_WALLS * 3 doubles) that receive the velocities
 // of the walls after a step with walls of finite mass
 constexpr int kWallSlot = 32;
+
+// doubles per slot record (both dimensions)
+constexpr int kRec = 4;
+
+// 3D tangent basis (t1 = f[3..5], t2 = f[6..8]) of the unit normal f[0..2]:
+// the orthonormal basis of Duff et al. (JCGT 6(1), 2017), t1 x t2 = n.  Every
+// place that needs the tangents uses these operations, so the values agree.
+__device__ inline void cd_tangents(double* f) {
+  const double sign = copysign(1.0, f[2]);
+  const double aa = -1.0 / (sign + f[2]);
+  const double bb = f[0] * f[1] * aa;
+  f[3] = 1.0 + sign * f[0] * f[0] * aa;
+  f[4] = sign * bb;
+  f[5] = -sign * f[0];
+  f[6] = bb;
+  f[7] = sign + f[1] * f[1] * aa;
+  f[8] = -f[1];
+}
+
+// 3D: world force F = R_n n + R_t1 t1 + R_t2 t2 and torque factor
+// q = R_t1 t2 - R_t2 t1 (n x R) of slot s from its record and its normal
+__device__ inline void cd_record_force3(const double* rec, const double* nrm4, int64_t s,
+                                        double* F, double* Q) {
+  const double4 r4 = *(const double4*)(rec + s * kRec);
+  const double4 n4 = *(const double4*)(nrm4 + s * 4);
+  double f[9] = {n4.x, n4.y, n4.z, 0, 0, 0, 0, 0, 0};
+  cd_tangents(f);
+  for (int q = 0; q < 3; ++q) {
+    const double fk = r4.x * f[q] + r4.y * f[3 + q];
+    F[q] = fk + r4.z * f[6 + q];
+    Q[q] = r4.y * f[6 + q] - r4.z * f[3 + q];
+  }
+}
 
 // helpers
 static inline int cd_blocks(int64_t n, int threads) {

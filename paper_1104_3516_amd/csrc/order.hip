@@ -171,6 +171,7 @@ struct BuildArgs {
   int2* ab;
   double* geo;
   double* rec0;
+  double* nrm4;           // 3D: per slot normal (4 doubles)
   int* dcol;
   int* dncol;
   int* ddesc;             // per domain: cs, nct, ps, np, ncol, 0, 0, 0
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(kStats) void k_dom_stats(const int* ddesc, int P, i
 
 template <int DIM>
 __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
-  constexpr int REC = DIM == 2 ? 4 : 12;
+  constexpr int REC = kRec;
   __shared__ unsigned long long s_mask[kSmall];
   __shared__ int s_la[kSmall], s_lb[kSmall];
   __shared__ short s_col[kSmall], s_rank[kSmall];
@@ -571,17 +572,16 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
       rc[2] = rn * n3[0] + r1 * t1[0];
       rc[3] = rn * n3[1] + r1 * t1[1];
     } else {
+      // the frame force; F and n x R are rebuilt from it and the normal
       rc[0] = rn;
       rc[1] = r1;
       rc[2] = r2;
       rc[3] = 0.0;
-      for (int q = 0; q < 3; ++q) {
-        double fq = rn * n3[q] + r1 * t1[q];
-        rc[4 + q] = fq + r2 * t2[q];
-        rc[8 + q] = r1 * t2[q] - r2 * t1[q];
-      }
-      rc[7] = 0.0;
-      rc[11] = 0.0;
+      double* n4 = a.nrm4 + s * 4;
+      n4[0] = n3[0];
+      n4[1] = n3[1];
+      n4[2] = n3[2];
+      n4[3] = 0.0;
     }
   }
 }
@@ -841,6 +841,7 @@ hipError_t cd_launch_order(cd_ctx* c) {
   a.ab = c->slot_ab;
   a.geo = c->geo;
   a.rec0 = c->rec[0];
+  a.nrm4 = c->nrm4;
   a.dcol = c->dcol;
   a.dncol = c->dncol;
   a.ddesc = c->ddesc;

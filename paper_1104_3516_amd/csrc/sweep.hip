@@ -430,7 +430,7 @@ __device__ inline double block_sum_256(double s, double* sh) {
 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_rsum(const double* rec0, int64_t nc, double* part) {
-  constexpr int REC = DIM == 2 ? 4 : 12;
+  constexpr int REC = kRec;
   __shared__ double sh[4];
   const int64_t chunk = (nc + kInitBlocks - 1) / kInitBlocks;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(256) void k_solve_init(const double* part, int64_t 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_unslot(const double* rec, const int* contact_slot,
                                                int64_t nc, double* R) {
-  constexpr int REC = DIM == 2 ? 4 : 12;
+  constexpr int REC = kRec;
   int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= nc) return;
   const double* rc = rec + (int64_t)contact_slot[c] * REC;
@@ -512,6 +512,8 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.mobile = c->mobile_mask;
   a.rec[0] = c->rec[0];
   a.rec[1] = c->rec[1];
+  a.nrm4 = c->nrm4;
+  a.ext_zero = c->ext_zero ? 1 : 0;
   a.mu_slot = c->use_mu_slot ? c->mu_slot : c->d_wall + CD_WALL_MU;
   a.mu_step = c->use_mu_slot ? 1 : 0;
   a.state = c->d_state;

@@ -10,8 +10,9 @@ namespace {
 template <int DIM>
 struct Layout {
   static constexpr int DR = DIM == 2 ? 1 : 3;
-  static constexpr int REC = DIM == 2 ? 4 : 12;
+  static constexpr int REC = kRec;
   static constexpr int NG = DIM == 2 ? 2 : 9;      // frame doubles per slot
+  static constexpr int NGS = DIM == 2 ? 2 : 3;     // of which staged in LDS (the normal)
   // staged particle record (doubles): V [0, DIM), W [DIM, DIM+DR), dt/m, dt/I,
   // r, padded to an even count so that pairs load as 16-byte words
   static constexpr int PS = cd_stage_particle(DIM);
@@ -119,18 +120,16 @@ __device__ inline int domain_of(const SweepArgs& a, int b, int k, int G8) {
 // Accumulate the previous sweep's contact forces on one particle entry, in
 // ascending contact id: acc -= F (body 1) or += F (body 2), tacc -= r q.
 template <int DIM>
-__device__ inline void add_record(const double* rin, int ent, double rp, double* acc,
-                                  double* tacc) {
-  constexpr int REC = DIM == 2 ? 4 : 12;
-  const double* rc = rin + (int64_t)(ent >> 1) * REC;
+__device__ inline void add_record(const double* rin, const double* nrm4, int ent, double rp,
+                                  double* acc, double* tacc) {
   if (DIM == 2) {
-    const double4 r4 = *(const double4*)rc;
+    const double4 r4 = *(const double4*)(rin + (int64_t)(ent >> 1) * kRec);
     acc[0] = (ent & 1) ? acc[0] + r4.z : acc[0] - r4.z;
     acc[1] = (ent & 1) ? acc[1] + r4.w : acc[1] - r4.w;
     tacc[0] = tacc[0] - rp * r4.y;
   } else {
-    const double4 f4 = *(const double4*)(rc + 4), q4 = *(const double4*)(rc + 8);
-    const double F[3] = {f4.x, f4.y, f4.z}, Q[3] = {q4.x, q4.y, q4.z};
+    double F[3], Q[3];
+    cd_record_force3(rin, nrm4, ent >> 1, F, Q);
     for (int k = 0; k < 3; ++k) acc[k] = (ent & 1) ? acc[k] + F[k] : acc[k] - F[k];
     for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * Q[k];
   }
@@ -139,7 +138,7 @@ __device__ inline void add_record(const double* rin, int ent, double rp, double*
 template <int DIM>
 __device__ inline void gather_forces(const SweepArgs& a, const double* rin, int64_t e, int4 r4i,
                                      double rp, double* acc, double* tacc) {
-  constexpr int REC = DIM == 2 ? 4 : 12;
+  constexpr int REC = kRec;
   constexpr int KW = DIM == 2 ? 8 : 16;
   // incidence rows: KW/4 planes of int4 (plane q: entries 4q..4q+3); the
   // first plane (r4i) is read by the caller
@@ -148,7 +147,7 @@ __device__ inline void gather_forces(const SweepArgs& a, const double* rin, int6
   if (r4i.x == -2) {
     // more incidences than a row holds: the pointer list
     const int e1 = a.dinc_ptr[e + 1];
-    for (int x = a.dinc_ptr[e]; x < e1; ++x) add_record<DIM>(rin, a.dinc[x], rp, acc, tacc);
+    for (int x = a.dinc_ptr[e]; x < e1; ++x) add_record<DIM>(rin, a.nrm4, a.dinc[x], rp, acc, tacc);
     return;
   }
   // valid entries come first; the next plane is read only after a full one
@@ -165,19 +164,13 @@ __device__ inline void gather_forces(const SweepArgs& a, const double* rin, int6
         tacc[0] = tacc[0] - rp * rec[u].y;
       }
     } else {
-      double4 fq[4][2];
+      double F[4][3], Q[4][3];
       for (int u = 0; u < 4; ++u)
-        if (ent[u] >= 0) {
-          const double* rc = rin + (int64_t)(ent[u] >> 1) * REC;
-          fq[u][0] = *(const double4*)(rc + 4);
-          fq[u][1] = *(const double4*)(rc + 8);
-        }
+        if (ent[u] >= 0) cd_record_force3(rin, a.nrm4, ent[u] >> 1, F[u], Q[u]);
       for (int u = 0; u < 4; ++u) {
         if (ent[u] < 0) break;
-        const double F[3] = {fq[u][0].x, fq[u][0].y, fq[u][0].z};
-        const double Q[3] = {fq[u][1].x, fq[u][1].y, fq[u][1].z};
-        for (int k = 0; k < 3; ++k) acc[k] = (ent[u] & 1) ? acc[k] + F[k] : acc[k] - F[k];
-        for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * Q[k];
+        for (int k = 0; k < 3; ++k) acc[k] = (ent[u] & 1) ? acc[k] + F[u][k] : acc[k] - F[u][k];
+        for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * Q[u][k];
       }
     }
     if (ent[3] < 0 || q + 1 == KW / 4) break;
@@ -204,23 +197,14 @@ __device__ inline void fetch_slot(const SweepArgs& a, const double* rin, int64_t
   const double* g = a.geo;
   o.ab = a.ab[s];
   if (DIM == 3 && !RECIP) {
-    // staged 3D slots: the tangents follow from the normal (the basis of Duff
-    // et al., JCGT 6(1), 2017, with the operations of the domain build that
-    // stored them), 48 bytes per slot not read from memory
-    double n3[3];
-    for (int q = 0; q < 3; ++q) n3[q] = g[q * cap + s];
-    const double sign = copysign(1.0, n3[2]);
-    const double aa = -1.0 / (sign + n3[2]);
-    const double bb = n3[0] * n3[1] * aa;
-    o.f[0] = n3[0];
-    o.f[1] = n3[1];
-    o.f[2] = n3[2];
-    o.f[NG > 3 ? 3 : 0] = 1.0 + sign * n3[0] * n3[0] * aa;
-    o.f[NG > 4 ? 4 : 0] = sign * bb;
-    o.f[NG > 5 ? 5 : 0] = -sign * n3[0];
-    o.f[NG > 6 ? 6 : 0] = bb;
-    o.f[NG > 7 ? 7 : 0] = sign + n3[1] * n3[1] * aa;
-    o.f[NG > 8 ? 8 : 0] = -n3[1];
+    // staged 3D slots: the normal in one 32-byte load; the tangents follow
+    // from it (cd_tangents, the operations of the domain build), 48 bytes
+    // per slot not read from memory
+    const double4 n4 = *(const double4*)(a.nrm4 + s * 4);
+    o.f[0] = n4.x;
+    o.f[1] = n4.y;
+    o.f[2] = n4.z;
+    if (NG == 9) cd_tangents(o.f);
   } else {
     for (int q = 0; q < NG; ++q) o.f[q] = g[q * cap + s];
   }
@@ -241,7 +225,10 @@ __device__ inline void fetch_slot(const SweepArgs& a, const double* rin, int64_t
     o.Ro[0] = r2.x;
     o.Ro[1] = r2.y;
   } else {
-    for (int q = 0; q < DIM; ++q) o.Ro[q] = ri[q];
+    const double4 r4 = *(const double4*)ri;   // the whole 32-byte record
+    o.Ro[0] = r4.x;
+    o.Ro[1] = r4.y;
+    o.Ro[DIM - 1] = r4.z;
   }
 }
 
@@ -393,17 +380,9 @@ __device__ inline void update_contact(double* sp, double* wu, const SlotPre<DIM>
     const nt4 v4 = {Rn[0], Rn[1], Rn[0] * nv[0] + Rn[1] * t1[0], Rn[0] * nv[1] + Rn[1] * t1[1]};
     __builtin_nontemporal_store(v4, (nt4*)ro);
   } else {
-    double F[3], Q[3];
-    for (int q = 0; q < 3; ++q) {
-      double fk = Rn[0] * nv[q] + Rn[1] * t1[q];
-      F[q] = fk + Rn[2] * t2[q];
-      Q[q] = Rn[1] * t2[q] - Rn[2] * t1[q];
-    }
-    const nt4 v0 = {Rn[0], Rn[1], Rn[2], 0.0}, v1 = {F[0], F[1], F[2], 0.0},
-              v2 = {Q[0], Q[1], Q[2], 0.0};
+    // the frame force only: readers rebuild F and n x R from it and the normal
+    const nt4 v0 = {Rn[0], Rn[1], Rn[2], 0.0};
     __builtin_nontemporal_store(v0, (nt4*)ro);
-    __builtin_nontemporal_store(v1, (nt4*)(ro + 4));
-    __builtin_nontemporal_store(v2, (nt4*)(ro + 8));
   }
   account<DIM>(Rold, Rn, alpha, npass, maxd, sumr);
 }
@@ -424,10 +403,15 @@ __device__ inline void entry_load(const SweepArgs& a, int64_t e, EntryPre<DIM>& 
   for (int k = 0; k < DIM; ++k) o.v[k] = a.dpb[k * E + e];
   for (int k = 0; k < DR; ++k) o.w[k] = a.dpb[(DIM + k) * E + e];
   int q = DIM + DR;
-  for (int k = 0; k < DIM; ++k) o.f[k] = a.dpb[(q + k) * E + e];
-  q += DIM;
-  for (int k = 0; k < DR; ++k) o.t[k] = a.dpb[(q + k) * E + e];
-  q += DR;
+  if (a.ext_zero) {
+    // no external force or torque anywhere (all +0.0): nothing to read
+    for (int k = 0; k < DIM; ++k) o.f[k] = 0.0;
+    for (int k = 0; k < DR; ++k) o.t[k] = 0.0;
+  } else {
+    for (int k = 0; k < DIM; ++k) o.f[k] = a.dpb[(q + k) * E + e];
+    for (int k = 0; k < DR; ++k) o.t[k] = a.dpb[(q + DIM + k) * E + e];
+  }
+  q += DIM + DR;
   o.dm = a.dpb[q * E + e];
   o.di = a.dpb[(q + 1) * E + e];
   o.r = a.dpb[(q + 2) * E + e];
@@ -458,14 +442,16 @@ __device__ inline void entry_finish(const SweepArgs& a, const double* rin, int64
 // is one of the domain's own (the same products as the record's, so the
 // same values), else from the record.
 template <int DIM>
-__device__ inline void incidence_force(const double* rin, const double* sl, int cs, int nct,
-                                       int64_t s, double* F, double* Q) {
+__device__ inline void incidence_force(const double* rin, const double* nrm4, const double* sl,
+                                       int cs, int nct, int64_t s, double* F, double* Q) {
   constexpr int NG = Layout<DIM>::NG, REC = Layout<DIM>::REC;
+  constexpr int NGS = Layout<DIM>::NGS;
   const int64_t k = s - cs;
   if (k >= 0 && k < nct) {
     double f[NG], R[DIM];
-    for (int q = 0; q < NG; ++q) f[q] = sl[(1 + q) * nct + k];
-    for (int q = 0; q < DIM; ++q) R[q] = sl[(4 + NG + q) * nct + k];
+    for (int q = 0; q < NGS; ++q) f[q] = sl[(1 + q) * nct + k];
+    if (NG == 9) cd_tangents(f);
+    for (int q = 0; q < DIM; ++q) R[q] = sl[(4 + NGS + q) * nct + k];
     if (DIM == 2) {
       const double t0 = -f[1], t1 = f[0];
       F[0] = R[0] * f[0] + R[1] * t0;
@@ -478,22 +464,13 @@ __device__ inline void incidence_force(const double* rin, const double* sl, int 
         Q[q] = R[1] * f[6 + q] - R[2] * f[3 + q];
       }
     }
+  } else if (DIM == 2) {
+    const double4 r4 = *(const double4*)(rin + s * REC);
+    F[0] = r4.z;
+    F[1] = r4.w;
+    Q[0] = r4.y;
   } else {
-    const double* rc = rin + s * REC;
-    if (DIM == 2) {
-      const double4 r4 = *(const double4*)rc;
-      F[0] = r4.z;
-      F[1] = r4.w;
-      Q[0] = r4.y;
-    } else {
-      const double4 f4 = *(const double4*)(rc + 4), q4 = *(const double4*)(rc + 8);
-      F[0] = f4.x;
-      F[1] = f4.y;
-      F[2] = f4.z;
-      Q[0] = q4.x;
-      Q[1] = q4.y;
-      Q[2] = q4.z;
-    }
+    cd_record_force3(rin, nrm4, s, F, Q);
   }
 }
 
@@ -515,7 +492,7 @@ __device__ inline void gather_forces_staged(const SweepArgs& a, const double* ri
     for (int x = a.dinc_ptr[e]; x < e1; ++x) {
       const int ent = a.dinc[x];
       double F[DIM], Q[DR];
-      incidence_force<DIM>(rin, sl, cs, nct, ent >> 1, F, Q);
+      incidence_force<DIM>(rin, a.nrm4, sl, cs, nct, ent >> 1, F, Q);
       add(ent, F, Q);
     }
     return;
@@ -524,7 +501,7 @@ __device__ inline void gather_forces_staged(const SweepArgs& a, const double* ri
     const int ent[4] = {r4i.x, r4i.y, r4i.z, r4i.w};
     double F[4][DIM], Q[4][DR];
     for (int u = 0; u < 4; ++u)
-      if (ent[u] >= 0) incidence_force<DIM>(rin, sl, cs, nct, ent[u] >> 1, F[u], Q[u]);
+      if (ent[u] >= 0) incidence_force<DIM>(rin, a.nrm4, sl, cs, nct, ent[u] >> 1, F[u], Q[u]);
     for (int u = 0; u < 4; ++u) {
       if (ent[u] < 0) break;
       add(ent[u], F[u], Q[u]);
@@ -588,7 +565,7 @@ __device__ inline DomainHead load_head(const SweepArgs& a, int d) {
 // previous force, and the friction coefficient when it is per slot.
 template <int DIM>
 __host__ __device__ constexpr int slot_stage_doubles(bool mu_per_slot) {
-  return 1 + Layout<DIM>::NG + 3 + DIM + (mu_per_slot ? 1 : 0);
+  return 1 + Layout<DIM>::NGS + 3 + DIM + (mu_per_slot ? 1 : 0);
 }
 
 // The domain's contact data, slot k at column k of an LDS block of `nct`
@@ -596,7 +573,7 @@ __host__ __device__ constexpr int slot_stage_doubles(bool mu_per_slot) {
 // previous sweep's force, friction if per slot.
 template <int DIM>
 __device__ inline void put_slot(double* sl, int nct, int k, const SlotPre<DIM>& c, bool mu_slot) {
-  constexpr int NG = Layout<DIM>::NG;
+  constexpr int NG = Layout<DIM>::NGS;   // the normal only: 3D tangents are recomputed
   ((int2*)sl)[k] = c.ab;
   for (int q = 0; q < NG; ++q) sl[(1 + q) * nct + k] = c.f[q];
   sl[(1 + NG) * nct + k] = c.gdt;
@@ -611,9 +588,10 @@ __device__ inline void put_slot(double* sl, int nct, int k, const SlotPre<DIM>& 
 template <int DIM>
 __device__ inline void get_slot(const double* sl, int nct, int k, double mu0, bool mu_slot,
                                 SlotPre<DIM>& c) {
-  constexpr int NG = Layout<DIM>::NG;
+  constexpr int NG = Layout<DIM>::NGS;
   c.ab = ((const int2*)sl)[k];
   for (int q = 0; q < NG; ++q) c.f[q] = sl[(1 + q) * nct + k];
+  if (Layout<DIM>::NG == 9) cd_tangents(c.f);
   c.gdt = sl[(1 + NG) * nct + k];
   c.dwn = sl[(2 + NG) * nct + k];
   c.dwt = sl[(3 + NG) * nct + k];

@@ -31,10 +31,11 @@ __global__ __launch_bounds__(kThreads) void k_update(double* x, double* v, doubl
                                                     const double* f, const double* t,
                                                     const double* r, const double* dtim,
                                                     const double* dtii, const int* inc_ptr,
-                                                    const int* inc, const double* rec, int64_t n,
-                                                    double dt, Period per) {
+                                                    const int* inc, const double* rec,
+                                                    const double* nrm4, int64_t n, double dt,
+                                                    Period per) {
   constexpr int DR = DIM == 2 ? 1 : 3;
-  constexpr int REC = DIM == 2 ? 4 : 12;
+  constexpr int REC = kRec;
   int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
   double acc[DIM], tacc[DR];
@@ -55,11 +56,10 @@ __global__ __launch_bounds__(kThreads) void k_update(double* x, double* v, doubl
       }
       tacc[0] = tacc[0] - rp * q;
     } else {
-      for (int k = 0; k < 3; ++k) {
-        double F = rc[4 + k];
-        acc[k] = (ent & 1) ? acc[k] + F : acc[k] - F;
-      }
-      for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * rc[8 + k];
+      double F[3], Q[3];
+      cd_record_force3(rec, nrm4, ent >> 1, F, Q);
+      for (int k = 0; k < 3; ++k) acc[k] = (ent & 1) ? acc[k] + F[k] : acc[k] - F[k];
+      for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * Q[k];
     }
   }
   const double dm = dtim[p], di = dtii[p];
@@ -141,7 +141,7 @@ hipError_t cd_launch_wall_velocities(cd_ctx* c) {
   if (c->W == 0) return hipSuccess;
   hipLaunchKernelGGL(k_wall_velocities, dim3(c->W), dim3(kThreads), 0, c->stream, c->dim, c->W,
                      c->mobile_mask, c->d_wall, c->rec[c->h_state->iter & 1],
-                     c->dim == 2 ? 4 : 12, c->wall_slot, c->wall_cnt, c->cap, c->d_wall_new);
+                     kRec, c->wall_slot, c->wall_cnt, c->cap, c->d_wall_new);
   return hipGetLastError();
 }
 
@@ -169,9 +169,11 @@ hipError_t cd_launch_update(cd_ctx* c, int final_iter) {
   }
   if (c->dim == 2)
     hipLaunchKernelGGL(k_update<2>, dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->v, c->w, c->f,
-                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->n, c->p.dt, per);
+                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->nrm4, c->n,
+                       c->p.dt, per);
   else
     hipLaunchKernelGGL(k_update<3>, dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->v, c->w, c->f,
-                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->n, c->p.dt, per);
+                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->nrm4, c->n,
+                       c->p.dt, per);
   return hipGetLastError();
 }
