@@ -742,6 +742,7 @@ def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, 
         "solve_mode": args.solve_mode,
         "block_threads": tm.block_threads, "contact_data_in_lds": bool(tm.staged),
         "decision_in_workgroup0": tm.staged == 2,
+        "foreign_forces_in_lds": bool(tm.foreign_in_lds),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
                      "traffic": traffic,

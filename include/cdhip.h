@@ -108,6 +108,9 @@ typedef struct cd_timing {
                             2: and workgroup 0 also took each stop decision */
   int global_records;    /* 1: a domain's particle records did not fit in LDS and the
                             sweeps kept them in global memory */
+  int foreign_in_lds;    /* 1: with staged contact data, the previous sweep's forces of
+                            each domain's foreign incidences were staged in LDS as well,
+                            so that the exchange read no record from memory (Sec. 3.1) */
 } cd_timing;
 
 typedef struct cd_ctx cd_ctx;
@@ -359,7 +362,9 @@ int cd_solve(cd_ctx* ctx, cd_result* out);
 
 /* checkpoint_every > 0: solves with a fixed sweep count (params.fixed_iters)
  * record the forces before the first sweep and after every checkpoint_every
- * sweeps, for cd_adjoint (2D).  0 (default): no recording. */
+ * sweeps, for cd_adjoint (2D).  0 (default): no recording.  CD_EINVAL for
+ * checkpoint_every > 0 on a 3D context, with walls of finite mass or periodic
+ * axes, the mixed update or the random order. */
 int cd_set_adjoint(cd_ctx* ctx, int checkpoint_every);
 
 /* on != 0 (2D): the next step detects, partitions and orders as usual and

@@ -41,7 +41,8 @@ class Timing(C.Structure):
                 ("order_ms", C.c_double), ("solve_ms", C.c_double), ("update_ms", C.c_double),
                 ("sweep_kernel_ms", C.c_double), ("sweep_launches", C.c_int),
                 ("sweeps_executed", C.c_int), ("block_threads", C.c_int),
-                ("sweeps_timed", C.c_int), ("staged", C.c_int), ("global_records", C.c_int)]
+                ("sweeps_timed", C.c_int), ("staged", C.c_int), ("global_records", C.c_int),
+                ("foreign_in_lds", C.c_int)]
 
 
 class BatchTiming(C.Structure):

@@ -190,6 +190,7 @@ int alloc_tree(cd_ctx* c) {
   CD_TRY(grow(&c->dp_count, P + 1));
   CD_TRY(grow(&c->dp_start, P + 1));
   CD_TRY(grow(&c->ddesc, 8 * (int64_t)P));
+  CD_TRY(grow(&c->dhalo, (int64_t)P));
   int grid = 8 * ((P + 7) / 8);
   CD_TRY(grow(&c->partial, 2 * grid));   // double-buffered by sweep parity
   c->partial_cap = 2 * grid;
@@ -200,7 +201,7 @@ int alloc_tree(cd_ctx* c) {
 int ensure_capacity(cd_ctx* c, int64_t need) {
   if (need <= c->cap && c->cap > 0) return CD_OK;
   int64_t cap = need + need / 4 + 1024;
-  const int rec = kRec;
+  const int rec = cd_rec(c->dim);
   CD_TRY(grow(&c->dom, cap));
   CD_TRY(grow(&c->color, cap));
   CD_TRY(grow(&c->nrm, c->dim * cap));
@@ -211,7 +212,6 @@ int ensure_capacity(cd_ctx* c, int64_t need) {
     CD_TRY(grow(&c->sort_vals[k], 2 * cap));
     CD_TRY(grow(&c->rec[k], rec * cap));
   }
-  if (c->dim == 3) CD_TRY(grow(&c->nrm4, 4 * cap));
   CD_TRY(grow(&c->q_la, cap));
   CD_TRY(grow(&c->q_lb, cap));
   CD_TRY(grow(&c->q_col, cap));
@@ -219,6 +219,7 @@ int ensure_capacity(cd_ctx* c, int64_t need) {
   CD_TRY(grow(&c->g_mask, 2 * cap));
   CD_TRY(grow(&c->dpb, (int64_t)(2 * c->dim + 2 * c->dr + 3) * 2 * cap));
   CD_TRY(grow(&c->dinc_ptr, 2 * cap + 1));
+  CD_TRY(grow(&c->hoff, 2 * cap + 1));
   CD_TRY(grow(&c->drow, (int64_t)cd_row_width(c->dim) * 2 * cap));
   for (int k = 0; k < 3; ++k) {
     if (k < c->dim) CD_TRY(grow(&c->perm[k], cap));
@@ -441,7 +442,7 @@ int cd_destroy(cd_ctx* c) {
   double** dbl[] = {&c->x, &c->v, &c->w, &c->r, &c->m, &c->I, &c->f, &c->t, &c->inv_m,
                     &c->inv_I, &c->dtim, &c->dtii, &c->d_wall, &c->nrm, &c->gap, &c->xmid,
                     &c->R, &c->R_prev, &c->d_cut, &c->d_region, &c->geo, &c->rec[0],
-                    &c->rec[1], &c->nrm4};
+                    &c->rec[1]};
   for (auto p : dbl) release(p);
   int** ints[] = {&c->cell_of, &c->cell_count, &c->cell_start, &c->cell_members,
                   &c->pair_count, &c->pair_off, &c->ci, &c->cj, &c->dom, &c->color,
@@ -466,6 +467,9 @@ int cd_destroy(cd_ctx* c) {
   release(&c->dinc);
   release(&c->drow);
   release(&c->ddesc);
+  release(&c->halo);
+  release(&c->hoff);
+  release(&c->dhalo);
   release(&c->d_state);
   release(&c->d_stats);
   release(&c->d_bar);
@@ -849,6 +853,8 @@ int prep_phase2(cd_ctx* c) {
   if (ds.dinc_total > c->dinc_cap || !c->dinc) {
     int64_t cap = (int64_t)ds.dinc_total + ds.dinc_total / 4 + 1024;
     CD_TRY(grow(&c->dinc, cap));
+    // the foreign incidences are a subset of the entries' incidences
+    CD_TRY(grow(&c->halo, cap));
     c->dinc_cap = cap;
   }
   CD_TRY(cd_launch_order_entries(c));
@@ -1169,6 +1175,7 @@ static int collect_result(cd_ctx* c, cd_result* out) {
   }
   tm.sweep_kernel_ms = sk;
   tm.staged = c->sweep_stage ? (c->sweep_fold ? 2 : 1) : 0;
+  tm.foreign_in_lds = c->sweep_stage && c->sweep_halo ? 1 : 0;
   tm.global_records = c->sweep_global ? 1 : 0;
   c->timing = tm;
   if (c->block_override < 0 && tm.sweeps_timed > 0)
@@ -1260,6 +1267,8 @@ int cd_set_random_order(cd_ctx* c, int on, unsigned long long seed) {
 
 int cd_set_adjoint(cd_ctx* c, int checkpoint_every) {
   if (!c || checkpoint_every < 0) return CD_EINVAL;
+  if (checkpoint_every > 0 && c->dim != 2)
+    return fail(c, CD_EINVAL, "the adjoint is implemented for 2D");
   if (checkpoint_every > 0 && (c->mobile_mask || c->periodic_mask))
     return fail(c, CD_EINVAL, "the adjoint differentiates rigid boxes only");
   if (checkpoint_every > 0 && c->mixed_p >= 0.0)

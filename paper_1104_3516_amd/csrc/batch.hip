@@ -277,7 +277,8 @@ int cd_batch_step(cd_batch* b, cd_result* results) {
     b->h_tab[p].dtick = nullptr;   // batched sweeps do not measure the load
     block = std::max(block, c->sweep_block);
     lds = std::max(lds, c->sweep_lds);
-    lds_stage = std::max(lds_stage, cd_stage_lds(c, c->st_ds.max_particles, c->st_ds.max_contacts));
+    lds_stage = std::max(lds_stage, cd_stage_lds(c->st_ds.max_stage +
+                                                  (c->use_mu_slot ? 8 * c->st_ds.max_contacts : 0)));
     if (!b->failed[p] && c->nc > 0 && c->st_limit > 0) {
       ++open;
       limit = std::max(limit, c->st_limit);

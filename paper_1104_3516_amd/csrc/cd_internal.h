@@ -9,11 +9,11 @@
 //     slot range [dom_start[d], dom_start[d+1]) sorted by (colour, contact id);
 //     per slot: local body indices (a, b), frame (n, and t1, t2 in 3D) and the
 //     constants of the force law; forces live in two ping-pong record arrays
-//     rec[0], rec[1] of 4 doubles (32 bytes) per slot:
+//     rec[0], rec[1], per slot:
 //       2D: (R_n, R_t, F_x, F_y)  with F = R_n n + R_t t the world force,
-//       3D: (R_n, R_t1, R_t2, 0); the world force F and the torque per unit
-//           lever q = n x R follow from R and the slot's normal (nrm4: n_x,
-//           n_y, n_z, 0 per slot) with the tangents recomputed from n;
+//       3D: (R_n, R_t1, R_t2, 0, n_x, n_y, n_z, 0); the world force F and
+//           the torque per unit lever q = n x R follow from R and the
+//           normal with the tangents recomputed from n;
 //   per domain: its particles (ascending id) and colour offsets;
 //   per particle: incident slots in ascending contact id (sign bit = body 2).
 #pragma once
@@ -60,6 +60,10 @@ struct DomainStats {
   int dinc_total;     // incidences summed over all domain particle entries
   int dp_total;       // domain particle entries
   int input_fault;    // a caller's list, domains or order failed the checks (bits 1, 2, 4)
+  int max_halo;       // largest count of foreign incidences of a domain
+  int max_stage;      // largest staged sweep data of a domain (particles, slots, foreign
+                      // incidences), bytes
+  int max_stage0;     // the same without the foreign incidences
   int scan_fault;     // sticky: a prefix scan gave up waiting on a predecessor tile
                       // (never cleared by the per-step reset of the fields above)
 };
@@ -111,13 +115,18 @@ struct SweepArgs {
   const int* dinc;          // slot * 2 + (1 if body 2)
   const int* drow;          // per entry: the same in fixed-width rows (see k_dinc_rows)
   const int* ddesc;         // per domain: cs, nct, ps, np, ncol (8 ints)
+  // foreign incidences (contacts of other domains on the domain's particle
+  // entries), listed domain by domain, entry by entry in row order: their
+  // slots, each entry's first list index (hoff) and each domain's range
+  const int* halo;
+  const int* hoff;
+  const int2* dhalo;        // per domain: first list index, count
   // slots
   const int2* ab;           // local body indices; b < 0: wall -1-b
   const double* geo;        // per-slot constants, SoA with stride cap
   const double* walls_u;    // W x dim wall velocities
   int n_walls;
   double* rec[2];
-  const double* nrm4;       // 3D: per slot (n_x, n_y, n_z, 0)
   int ext_zero;             // every external force and torque is +0.0: not read
   const double* mu_slot;    // friction of slot s at mu_slot[s * mu_step]
   int mu_step;              // 1: per slot; 0: one coefficient for all
@@ -281,7 +290,6 @@ struct cd_ctx {
   int2* slot_ab = nullptr;
   double* geo = nullptr;
   double* rec[2] = {nullptr, nullptr};
-  double* nrm4 = nullptr;        // 3D: per slot normal, 4 doubles
   bool ext_zero = true;          // every external force and torque is +0.0
   int *dcol = nullptr, *dncol = nullptr, *dp = nullptr, *dp_count = nullptr, *dp_start = nullptr;
   int *q_la = nullptr, *q_lb = nullptr, *q_col = nullptr, *q_pos = nullptr;
@@ -294,6 +302,9 @@ struct cd_ctx {
   int64_t dinc_cap = 0;
   int* drow = nullptr;           // 2 cap x row width
   int* ddesc = nullptr;          // P x 8
+  int* halo = nullptr;           // foreign incidence slots (capacity dinc_cap)
+  int* hoff = nullptr;           // 2 cap + 1: per entry, first foreign incidence
+  int2* dhalo = nullptr;         // P: per domain, first foreign incidence and count
   int sweep_block = 64;          // threads per domain workgroup
   int block_override = 0;        // 0: chosen from the domain sizes; -1: tuned
   int tune_next = 0;             // next candidate width to try (4: tuning over)
@@ -330,6 +341,7 @@ struct cd_ctx {
   size_t sweep_lds_stage = 0;  // the same with the domain's contact data staged too
   bool sweep_stage = false;    // this solve stages contact data in LDS
   bool sweep_fold = false;     // ... and takes the stop decision in workgroup 0
+  bool sweep_halo = false;     // ... and stages the foreign incidences' forces too
   bool stage_off = false;      // never stage (the register read-ahead form only)
 
   // timing
@@ -421,7 +433,7 @@ hipError_t cd_launch_sweep_batch(hipStream_t stream, int dim, const SweepArgs* t
                                  BatchProg* bp);
 // LDS of the staged sweep for domains of these sizes (particle entries,
 // contacts), with the context's friction mode
-size_t cd_stage_lds(cd_ctx* c, int max_particles, int max_contacts);
+size_t cd_stage_lds(int max_stage_bytes);
 // LDS of the random order's draws and ranked slots per workgroup (0 without it)
 size_t cd_random_lds(cd_ctx* c);
 // whether a launch of `workgroups` should stage contact data: it must fit and
@@ -463,6 +475,14 @@ static inline int cd_row_width(int dim) { return dim == 2 ? 8 : 16; }
 // doubles the sweep stages per domain particle: V, W, dt/m, dt/I, r, padded
 // to an even count (2D: 6, 3D: 10)
 __host__ __device__ constexpr int cd_stage_particle(int dim) { return dim == 2 ? 6 : 10; }
+// doubles the staged sweep keeps per slot: body pair, normal, g_e/dt, dt w_n,
+// dt w_t, previous force, and the friction coefficient when it is per slot
+__host__ __device__ constexpr int cd_stage_slot(int dim, bool mu_per_slot) {
+  return 1 + (dim == 2 ? 2 : 3) + 3 + dim + (mu_per_slot ? 1 : 0);
+}
+// doubles per foreign incidence staged for the exchange: the world force F
+// and the torque factor (2D: R_t; 3D: n x R)
+__host__ __device__ constexpr int cd_stage_halo(int dim) { return dim == 2 ? 3 : 6; }
 
 // slot of the pinned 64-entry scratch (c->h_scratch) that receives the
 // active-contact count of a finished solve
@@ -471,8 +491,12 @@ constexpr int kActiveSlot = 63;
 // of the walls after a step with walls of finite mass
 constexpr int kWallSlot = 32;
 
-// doubles per slot record (both dimensions)
-constexpr int kRec = 4;
+// doubles per slot record.  2D: (R_n, R_t, F_x, F_y).  3D: the frame force
+// (R_n, R_t1, R_t2, 0) followed by the contact normal (n_x, n_y, n_z, 0),
+// one 64-byte block, so that a reader of a record finds the normal it needs
+// in the same cache line; the sweeps rewrite only the force half, both
+// record arrays carry the normal.
+__host__ __device__ constexpr int cd_rec(int dim) { return dim == 2 ? 4 : 8; }
 
 // 3D tangent basis (t1 = f[3..5], t2 = f[6..8]) of the unit normal f[0..2]:
 // the orthonormal basis of Duff et al. (JCGT 6(1), 2017), t1 x t2 = n.  Every
@@ -490,11 +514,10 @@ __device__ inline void cd_tangents(double* f) {
 }
 
 // 3D: world force F = R_n n + R_t1 t1 + R_t2 t2 and torque factor
-// q = R_t1 t2 - R_t2 t1 (n x R) of slot s from its record and its normal
-__device__ inline void cd_record_force3(const double* rec, const double* nrm4, int64_t s,
-                                        double* F, double* Q) {
-  const double4 r4 = *(const double4*)(rec + s * kRec);
-  const double4 n4 = *(const double4*)(nrm4 + s * 4);
+// q = R_t1 t2 - R_t2 t1 (n x R) of slot s from its record (force and normal)
+__device__ inline void cd_record_force3(const double* rec, int64_t s, double* F, double* Q) {
+  const double4 r4 = *(const double4*)(rec + s * cd_rec(3));
+  const double4 n4 = *(const double4*)(rec + s * cd_rec(3) + 4);
   double f[9] = {n4.x, n4.y, n4.z, 0, 0, 0, 0, 0, 0};
   cd_tangents(f);
   for (int q = 0; q < 3; ++q) {

@@ -171,7 +171,7 @@ struct BuildArgs {
   int2* ab;
   double* geo;
   double* rec0;
-  double* nrm4;           // 3D: per slot normal (4 doubles)
+  double* rec1;           // the other record array (3D: it carries the normals too)
   int* dcol;
   int* dncol;
   int* ddesc;             // per domain: cs, nct, ps, np, ncol, 0, 0, 0
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(kStats) void k_dom_stats(const int* ddesc, int P, i
 
 template <int DIM>
 __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
-  constexpr int REC = kRec;
+  constexpr int REC = cd_rec(DIM);
   __shared__ unsigned long long s_mask[kSmall];
   __shared__ int s_la[kSmall], s_lb[kSmall];
   __shared__ short s_col[kSmall], s_rank[kSmall];
@@ -577,11 +577,11 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
       rc[1] = r1;
       rc[2] = r2;
       rc[3] = 0.0;
-      double* n4 = a.nrm4 + s * 4;
-      n4[0] = n3[0];
-      n4[1] = n3[1];
-      n4[2] = n3[2];
-      n4[3] = 0.0;
+      // the normal half, in both record arrays
+      double* n4 = rc + 4;
+      double* m4 = a.rec1 + s * REC + 4;
+      for (int q = 0; q < 3; ++q) n4[q] = m4[q] = n3[q];
+      n4[3] = m4[3] = 0.0;
     }
   }
 }
@@ -697,6 +697,103 @@ __global__ __launch_bounds__(kThreads) void k_dinc_rows(const int* dp, const int
       v[k] = deg > KW ? (x == 0 ? -2 : -1) : (x < deg ? inc[s0 + x] : -1);
     }
     *(int4*)(rows + (q * E + e) * 4) = make_int4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// The domain of particle entry e < dp_start[P]: the d with
+// dp_start[d] <= e < dp_start[d + 1] (an empty domain has no entry).
+__device__ inline int entry_domain(const int* dp_start, int P, int e) {
+  int lo = 0, hi = P;
+  while (hi - lo > 1) {
+    const int m = (lo + hi) >> 1;
+    if (dp_start[m] <= e) lo = m;
+    else hi = m;
+  }
+  return lo;
+}
+
+// Foreign incidences of each domain particle entry: the incident slots that
+// belong to another domain (their forces come from the exchange).  The
+// incidence lists hold slots at this point.
+__global__ __launch_bounds__(kThreads) void k_halo_count(const int* dp, const int* dp_start, int P,
+                                                        int64_t E, const int* dom_start,
+                                                        const int* inc_ptr, const int* inc,
+                                                        int* count) {
+  int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= E) return;
+  if (e >= dp_start[P]) {
+    count[e] = 0;
+    return;
+  }
+  const int d = entry_domain(dp_start, P, (int)e);
+  const int cs = dom_start[d], ce = dom_start[d + 1];
+  const int p = dp[e];
+  int m = 0;
+  for (int x = inc_ptr[p]; x < inc_ptr[p + 1]; ++x) {
+    const int s = inc[x] >> 1;
+    m += (s < cs || s >= ce) ? 1 : 0;
+  }
+  count[e] = m;
+}
+
+// Per domain: the range of its foreign incidences in the list, and the
+// largest count and staged sweep size over all domains (one workgroup, as
+// k_dom_stats).  ps, sw, hw: doubles staged per particle entry, slot (without
+// a per-slot friction coefficient, which may be set later) and foreign
+// incidence.
+__global__ __launch_bounds__(kStats) void k_halo_dom(const int* dp_start, const int* ddesc, int P,
+                                                    const int* hoff, int ps, int sw, int hw,
+                                                    int2* dhalo, DomainStats* stats) {
+  __shared__ long long sh[3][kStats / 64];
+  long long mh = 0, mb = 0, m0 = 0;
+  for (int d = threadIdx.x; d < P; d += kStats) {
+    const int hs = hoff[dp_start[d]];
+    const int nh = hoff[dp_start[d + 1]] - hs;
+    dhalo[d] = make_int2(hs, nh);
+    const int* dd = ddesc + 8 * (int64_t)d;
+    const long long b0 = 8ll * ((long long)ps * dd[3] + (long long)sw * dd[1]);
+    mh = max(mh, (long long)nh);
+    mb = max(mb, b0 + 8ll * hw * nh);
+    m0 = max(m0, b0);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mh = max(mh, __shfl_xor(mh, off, 64));
+    mb = max(mb, __shfl_xor(mb, off, 64));
+    m0 = max(m0, __shfl_xor(m0, off, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = mh;
+    sh[1][w] = mb;
+    sh[2][w] = m0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kStats / 64; ++k) {
+      mh = max(mh, sh[0][k]);
+      mb = max(mb, sh[1][k]);
+      m0 = max(m0, sh[2][k]);
+    }
+    stats->max_halo = (int)mh;
+    stats->max_stage = (int)(mb < 0x7fffffffll ? mb : 0x7fffffffll);
+    stats->max_stage0 = (int)(m0 < 0x7fffffffll ? m0 : 0x7fffffffll);
+  }
+}
+
+// The foreign incidences' slots, entry by entry in incidence (row) order
+__global__ __launch_bounds__(kThreads) void k_halo_fill(const int* dp, const int* dp_start, int P,
+                                                       int64_t E, const int* dom_start,
+                                                       const int* inc_ptr, const int* inc,
+                                                       const int* hoff, int* halo) {
+  int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= E || e >= dp_start[P]) return;
+  const int d = entry_domain(dp_start, P, (int)e);
+  const int cs = dom_start[d], ce = dom_start[d + 1];
+  const int p = dp[e];
+  int o = hoff[e];
+  for (int x = inc_ptr[p]; x < inc_ptr[p + 1]; ++x) {
+    const int s = inc[x] >> 1;
+    if (s < cs || s >= ce) halo[o++] = s;
   }
 }
 
@@ -841,7 +938,7 @@ hipError_t cd_launch_order(cd_ctx* c) {
   a.ab = c->slot_ab;
   a.geo = c->geo;
   a.rec0 = c->rec[0];
-  a.nrm4 = c->nrm4;
+  a.rec1 = c->rec[1];
   a.dcol = c->dcol;
   a.dncol = c->dncol;
   a.ddesc = c->ddesc;
@@ -876,6 +973,15 @@ hipError_t cd_launch_order(cd_ctx* c) {
   e = cd_scan_exclusive(c, c->flag, c->dinc_ptr, E);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dinc_total, dim3(1), dim3(1), 0, c->stream, c->dinc_ptr, E, c->d_stats);
+  // 7. foreign incidences per entry and domain (their list follows once the
+  //    host has sized it)
+  hipLaunchKernelGGL(k_halo_count, dim3(cd_blocks(E, kThreads)), dim3(kThreads), 0, c->stream,
+                     c->dp, c->dp_start, P, E, c->dom_start, c->inc_ptr, c->inc, c->flag);
+  e = cd_scan_exclusive(c, c->flag, c->hoff, E);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_halo_dom, dim3(1), dim3(kStats), 0, c->stream, c->dp_start, c->ddesc, P,
+                     c->hoff, cd_stage_particle(c->dim), cd_stage_slot(c->dim, false),
+                     cd_stage_halo(c->dim), c->dhalo, c->d_stats);
   return hipGetLastError();
 }
 
@@ -930,5 +1036,8 @@ hipError_t cd_launch_order_entries(cd_ctx* c) {
   hipLaunchKernelGGL(k_dinc_rows, dim3(cd_blocks(E, kThreads)), dim3(kThreads), 0, c->stream,
                      c->dp, c->dp_start, c->P, E, cd_row_width(c->dim), c->inc_ptr, c->inc,
                      c->drow);
+  hipLaunchKernelGGL(k_halo_fill, dim3(cd_blocks(E, kThreads)), dim3(kThreads), 0, c->stream,
+                     c->dp, c->dp_start, c->P, E, c->dom_start, c->inc_ptr, c->inc, c->hoff,
+                     c->halo);
   return hipGetLastError();
 }

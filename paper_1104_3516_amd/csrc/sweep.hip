@@ -209,7 +209,7 @@ __device__ inline void decide_wave(const SweepArgs& a, int jd) {
 // balancing on; a separate instantiation so that the plain sweep is unchanged).
 // MOBILE: the box has walls of finite mass (a separate instantiation).
 template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false,
-          bool RAND = false, bool MOBILE = false>
+          bool RAND = false, bool MOBILE = false, bool HALO = true>
 __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArgs& a, int b, int j,
                                                                   BatchProg* bp) {
   extern __shared__ double lds[];
@@ -243,7 +243,7 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
     // its domain (its wavefront runs the colours; a folded decision is
     // taken by another wavefront and not counted), summed over the step
     const unsigned long long t0 = TIMED ? __builtin_amdgcn_s_memrealtime() : 0ull;
-    sweep_domain<DIM, GLOB, STAGE, MIXED, RAND, MOBILE>(
+    sweep_domain<DIM, GLOB, STAGE, MIXED, RAND, MOBILE, HALO>(
         a, d, h, rin, rout, lds, s_co, s_wu, npass, maxd, sumr,
         RAND ? rand_mix(a.rkey ^ (unsigned long long)j) : 0ull, idle, s_wm, s_wtmp);
     if (TIMED && threadIdx.x == 0) a.dtick[d] += __builtin_amdgcn_s_memrealtime() - t0;
@@ -263,9 +263,9 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
 // RAND: the random sequential order of Sec. 2.1 (thread 0 of each domain's
 // workgroup updates its contacts one at a time), a separate instantiation.
 template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false,
-          bool RAND = false, bool MOBILE = false>
+          bool RAND = false, bool MOBILE = false, bool HALO = true>
 __global__ __launch_bounds__(kMaxBlock, STAGE && DIM == 2 ? 5 : 1) void k_sweep(SweepArgs a, int j) {
-  sweep_block<DIM, GLOB, STAGE, FOLD, MIXED, TIMED, RAND, MOBILE>(a, blockIdx.x, j, nullptr);
+  sweep_block<DIM, GLOB, STAGE, FOLD, MIXED, TIMED, RAND, MOBILE, HALO>(a, blockIdx.x, j, nullptr);
 }
 
 // Sweep j of a batch of packings: workgroup b serves packing blk[2b] as its
@@ -430,7 +430,7 @@ __device__ inline double block_sum_256(double s, double* sh) {
 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_rsum(const double* rec0, int64_t nc, double* part) {
-  constexpr int REC = kRec;
+  constexpr int REC = cd_rec(DIM);
   __shared__ double sh[4];
   const int64_t chunk = (nc + kInitBlocks - 1) / kInitBlocks;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(256) void k_solve_init(const double* part, int64_t 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_unslot(const double* rec, const int* contact_slot,
                                                int64_t nc, double* R) {
-  constexpr int REC = kRec;
+  constexpr int REC = cd_rec(DIM);
   int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= nc) return;
   const double* rc = rec + (int64_t)contact_slot[c] * REC;
@@ -512,7 +512,6 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.mobile = c->mobile_mask;
   a.rec[0] = c->rec[0];
   a.rec[1] = c->rec[1];
-  a.nrm4 = c->nrm4;
   a.ext_zero = c->ext_zero ? 1 : 0;
   a.mu_slot = c->use_mu_slot ? c->mu_slot : c->d_wall + CD_WALL_MU;
   a.mu_step = c->use_mu_slot ? 1 : 0;
@@ -530,6 +529,9 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.rkey = c->order_random ? rand_mix(rand_mix(c->rand_seed) ^ (unsigned long long)c->step) : 0ull;
   a.drow = c->drow;
   a.ddesc = c->ddesc;
+  a.halo = c->halo;
+  a.hoff = c->hoff;
+  a.dhalo = c->dhalo;
   a.nc = c->nc;
   a.alpha = c->p.alpha;
   a.mu = c->p.mu;
@@ -583,12 +585,8 @@ static int resident_per_cu(const void* k, int block, size_t lds) {
   return n;
 }
 
-size_t cd_stage_lds(cd_ctx* c, int max_particles, int max_contacts) {
-  const int ps = cd_stage_particle(c->dim);
-  const int sw = c->dim == 2 ? slot_stage_doubles<2>(c->use_mu_slot)
-                             : slot_stage_doubles<3>(c->use_mu_slot);
-  const size_t b = 8 * ((size_t)ps * std::max(max_particles, 1) +
-                        (size_t)sw * std::max(max_contacts, 1));
+size_t cd_stage_lds(int max_stage_bytes) {
+  const size_t b = (size_t)std::max(max_stage_bytes, 8);
   return (b + 31) / 32 * 32;
 }
 
@@ -616,8 +614,11 @@ bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64
 void cd_sweep_mode(cd_ctx* c) {
   c->sweep_stage = false;
   c->sweep_fold = false;
+  c->sweep_halo = false;
   if (c->sweep_global || c->stage_off) return;
-  c->sweep_lds_stage = cd_stage_lds(c, c->st_ds.max_particles, c->st_ds.max_contacts);
+  const int mu_bytes = c->use_mu_slot ? 8 * c->st_ds.max_contacts : 0;
+  const size_t lds_halo = cd_stage_lds(c->st_ds.max_stage + mu_bytes);
+  const size_t lds_nohalo = cd_stage_lds(c->st_ds.max_stage0 + mu_bytes);
   // With two or more wavefronts per workgroup the decision can fold into
   // workgroup 0.  That pays when a launch runs in several rounds of
   // resident workgroups (a separate decision workgroup would be dispatched
@@ -629,12 +630,39 @@ void cd_sweep_mode(cd_ctx* c) {
   // (static LDS beyond the 2 KiB the checks allow for)
   const size_t extra =
       cd_random_lds(c) + (c->mobile_mask ? sizeof(double) * (kMaxBlock + CD_MAX_WALLS) : 0);
+  // the foreign incidences' forces staged as well when that saves a round
+  // of workgroups, or in 3D when it costs none (their LDS is the price of an
+  // exchange that reads nothing from memory; in 2D the plain staged form
+  // overlaps its record gathers with the slot staging and was measured
+  // faster at equal rounds)
+  {
+    const void* kh = c->dim == 2 ? (const void*)k_sweep<2, false, true, true>
+                                 : (const void*)k_sweep<3, false, true, true>;
+    const void* kn = c->dim == 2 ? (const void*)k_sweep<2, false, true, true, false, false, false, false, false>
+                                 : (const void*)k_sweep<3, false, true, true, false, false, false, false, false>;
+    const int64_t rh = lds_halo + extra + 2048 <= c->max_lds
+                           ? resident_per_cu(kh, c->sweep_block, lds_halo + extra) * c->num_cu
+                           : 0;
+    const int64_t rn = resident_per_cu(kn, c->sweep_block, lds_nohalo + extra) * c->num_cu;
+    // rounds of resident workgroups for the domain workgroups and the
+    // decision workgroup
+    const int64_t round_h = rh > 0 ? (domains + rh) / rh : 0;
+    const int64_t round_n = rn > 0 ? (domains + rn) / rn : 0;
+    c->sweep_halo = rh > 0 && (rn < 1 || round_h < round_n ||
+                               (round_h == round_n && c->dim == 3));
+  }
+  c->sweep_lds_stage = c->sweep_halo ? lds_halo : lds_nohalo;
   c->sweep_stage = cd_stage_pick(c->dim, c->sweep_block, c->sweep_lds + extra,
                                  c->sweep_lds_stage + extra, domains + 1, domains + 1, c->num_cu,
                                  c->max_lds, false);
+  if (!c->sweep_stage) c->sweep_halo = false;
   if (c->sweep_stage && c->sweep_block >= 128) {
-    const void* kf = c->dim == 2 ? (const void*)k_sweep<2, false, true, true>
-                                 : (const void*)k_sweep<3, false, true, true>;
+    const void* kf =
+        c->sweep_halo
+            ? (c->dim == 2 ? (const void*)k_sweep<2, false, true, true>
+                           : (const void*)k_sweep<3, false, true, true>)
+            : (c->dim == 2 ? (const void*)k_sweep<2, false, true, true, false, false, false, false, false>
+                           : (const void*)k_sweep<3, false, true, true, false, false, false, false, false>);
     const int64_t slots =
         (int64_t)resident_per_cu(kf, c->sweep_block, c->sweep_lds_stage + extra) * c->num_cu;
     c->sweep_fold = domains + 1 > slots;
@@ -649,11 +677,17 @@ static void launch_sweep_form(cd_ctx* c, const SweepArgs& a, dim3 grid, dim3 blo
   if (c->sweep_global)
     hipLaunchKernelGGL((k_sweep<DIM, true, false, false, MIXED, TIMED, RAND, MOBILE>), grid, block,
                        RAND ? lds : 0, c->stream, a, j);
+  else if (fold && c->sweep_halo)
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED, TIMED, RAND, MOBILE, true>), grid,
+                       block, lds, c->stream, a, j);
   else if (fold)
-    hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED, TIMED, RAND, MOBILE>), grid, block,
-                       lds, c->stream, a, j);
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED, TIMED, RAND, MOBILE, false>), grid,
+                       block, lds, c->stream, a, j);
+  else if (c->sweep_stage && c->sweep_halo)
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED, TIMED, RAND, MOBILE, true>), grid,
+                       block, lds, c->stream, a, j);
   else if (c->sweep_stage)
-    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED, TIMED, RAND, MOBILE>), grid,
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED, TIMED, RAND, MOBILE, false>), grid,
                        block, lds, c->stream, a, j);
   else
     hipLaunchKernelGGL((k_sweep<DIM, false, false, false, MIXED, TIMED, RAND, MOBILE>), grid,

@@ -10,7 +10,7 @@ namespace {
 template <int DIM>
 struct Layout {
   static constexpr int DR = DIM == 2 ? 1 : 3;
-  static constexpr int REC = kRec;
+  static constexpr int REC = cd_rec(DIM);
   static constexpr int NG = DIM == 2 ? 2 : 9;      // frame doubles per slot
   static constexpr int NGS = DIM == 2 ? 2 : 3;     // of which staged in LDS (the normal)
   // staged particle record (doubles): V [0, DIM), W [DIM, DIM+DR), dt/m, dt/I,
@@ -120,16 +120,16 @@ __device__ inline int domain_of(const SweepArgs& a, int b, int k, int G8) {
 // Accumulate the previous sweep's contact forces on one particle entry, in
 // ascending contact id: acc -= F (body 1) or += F (body 2), tacc -= r q.
 template <int DIM>
-__device__ inline void add_record(const double* rin, const double* nrm4, int ent, double rp,
+__device__ inline void add_record(const double* rin, int ent, double rp,
                                   double* acc, double* tacc) {
   if (DIM == 2) {
-    const double4 r4 = *(const double4*)(rin + (int64_t)(ent >> 1) * kRec);
+    const double4 r4 = *(const double4*)(rin + (int64_t)(ent >> 1) * cd_rec(2));
     acc[0] = (ent & 1) ? acc[0] + r4.z : acc[0] - r4.z;
     acc[1] = (ent & 1) ? acc[1] + r4.w : acc[1] - r4.w;
     tacc[0] = tacc[0] - rp * r4.y;
   } else {
     double F[3], Q[3];
-    cd_record_force3(rin, nrm4, ent >> 1, F, Q);
+    cd_record_force3(rin, ent >> 1, F, Q);
     for (int k = 0; k < 3; ++k) acc[k] = (ent & 1) ? acc[k] + F[k] : acc[k] - F[k];
     for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * Q[k];
   }
@@ -138,7 +138,7 @@ __device__ inline void add_record(const double* rin, const double* nrm4, int ent
 template <int DIM>
 __device__ inline void gather_forces(const SweepArgs& a, const double* rin, int64_t e, int4 r4i,
                                      double rp, double* acc, double* tacc) {
-  constexpr int REC = kRec;
+  constexpr int REC = cd_rec(DIM);
   constexpr int KW = DIM == 2 ? 8 : 16;
   // incidence rows: KW/4 planes of int4 (plane q: entries 4q..4q+3); the
   // first plane (r4i) is read by the caller
@@ -147,7 +147,7 @@ __device__ inline void gather_forces(const SweepArgs& a, const double* rin, int6
   if (r4i.x == -2) {
     // more incidences than a row holds: the pointer list
     const int e1 = a.dinc_ptr[e + 1];
-    for (int x = a.dinc_ptr[e]; x < e1; ++x) add_record<DIM>(rin, a.nrm4, a.dinc[x], rp, acc, tacc);
+    for (int x = a.dinc_ptr[e]; x < e1; ++x) add_record<DIM>(rin, a.dinc[x], rp, acc, tacc);
     return;
   }
   // valid entries come first; the next plane is read only after a full one
@@ -166,7 +166,7 @@ __device__ inline void gather_forces(const SweepArgs& a, const double* rin, int6
     } else {
       double F[4][3], Q[4][3];
       for (int u = 0; u < 4; ++u)
-        if (ent[u] >= 0) cd_record_force3(rin, a.nrm4, ent[u] >> 1, F[u], Q[u]);
+        if (ent[u] >= 0) cd_record_force3(rin, ent[u] >> 1, F[u], Q[u]);
       for (int u = 0; u < 4; ++u) {
         if (ent[u] < 0) break;
         for (int k = 0; k < 3; ++k) acc[k] = (ent[u] & 1) ? acc[k] + F[u][k] : acc[k] - F[u][k];
@@ -197,10 +197,10 @@ __device__ inline void fetch_slot(const SweepArgs& a, const double* rin, int64_t
   const double* g = a.geo;
   o.ab = a.ab[s];
   if (DIM == 3 && !RECIP) {
-    // staged 3D slots: the normal in one 32-byte load; the tangents follow
-    // from it (cd_tangents, the operations of the domain build), 48 bytes
-    // per slot not read from memory
-    const double4 n4 = *(const double4*)(a.nrm4 + s * 4);
+    // staged 3D slots: the normal from the record block (the same cache
+    // line as the force); the tangents follow from it (cd_tangents, the
+    // operations of the domain build), 48 bytes per slot not read
+    const double4 n4 = *(const double4*)(rin + s * REC + 4);
     o.f[0] = n4.x;
     o.f[1] = n4.y;
     o.f[2] = n4.z;
@@ -394,6 +394,8 @@ template <int DIM>
 struct EntryPre {
   double v[DIM], w[Layout<DIM>::DR], f[DIM], t[Layout<DIM>::DR], dm, di, r;
   int4 row;
+  int4 row1;   // the second plane when the first is full (staged form only)
+  int hb;      // list index of the first foreign incidence (staged form only)
 };
 
 template <int DIM>
@@ -416,6 +418,15 @@ __device__ inline void entry_load(const SweepArgs& a, int64_t e, EntryPre<DIM>& 
   o.di = a.dpb[(q + 1) * E + e];
   o.r = a.dpb[(q + 2) * E + e];
   o.row = ((const int4*)a.drow)[e];
+  o.hb = a.hoff[e];
+}
+
+// The second row plane of an entry whose first plane is full (read once
+// the first has arrived; most entries need only the first)
+template <int DIM>
+__device__ inline void entry_row1(const SweepArgs& a, int64_t e, EntryPre<DIM>& o) {
+  o.row1 = make_int4(-1, -1, -1, -1);
+  if (o.row.w >= 0) o.row1 = ((const int4*)a.drow)[a.dpe + e];
 }
 
 // The entry's velocities from its base data and the previous sweep's forces
@@ -437,40 +448,47 @@ __device__ inline void entry_finish(const SweepArgs& a, const double* rin, int64
   pr[L::P_R] = o.r;
 }
 
-// World force F and torque factor Q (2D: R_t; 3D: t2 R_1 - t1 R_2) of
-// the previous sweep's force of slot s: from the staged copy when the slot
+// World force F and torque factor Q (2D: R_t; 3D: t2 R_1 - t1 R_2) of the
+// domain's own slot k from its staged copy (the same products as the
+// record's, so the same values)
+template <int DIM>
+__device__ inline void own_force(const double* sl, int nct, int k, double* F, double* Q) {
+  constexpr int NG = Layout<DIM>::NG, NGS = Layout<DIM>::NGS;
+  double f[NG], R[DIM];
+  for (int q = 0; q < NGS; ++q) f[q] = sl[(1 + q) * nct + k];
+  if (NG == 9) cd_tangents(f);
+  for (int q = 0; q < DIM; ++q) R[q] = sl[(4 + NGS + q) * nct + k];
+  if (DIM == 2) {
+    const double t0 = -f[1], t1 = f[0];
+    F[0] = R[0] * f[0] + R[1] * t0;
+    F[1] = R[0] * f[1] + R[1] * t1;
+    Q[0] = R[1];
+  } else {
+    for (int q = 0; q < 3; ++q) {
+      const double fk = R[0] * f[q] + R[1] * f[3 + q];
+      F[q] = fk + R[2] * f[6 + q];
+      Q[q] = R[1] * f[6 + q] - R[2] * f[3 + q];
+    }
+  }
+}
+
+// F and Q of the previous sweep's force of slot s: from the staged copy when the slot
 // is one of the domain's own (the same products as the record's, so the
 // same values), else from the record.
 template <int DIM>
-__device__ inline void incidence_force(const double* rin, const double* nrm4, const double* sl,
+__device__ inline void incidence_force(const double* rin, const double* sl,
                                        int cs, int nct, int64_t s, double* F, double* Q) {
-  constexpr int NG = Layout<DIM>::NG, REC = Layout<DIM>::REC;
-  constexpr int NGS = Layout<DIM>::NGS;
+  constexpr int REC = Layout<DIM>::REC;
   const int64_t k = s - cs;
   if (k >= 0 && k < nct) {
-    double f[NG], R[DIM];
-    for (int q = 0; q < NGS; ++q) f[q] = sl[(1 + q) * nct + k];
-    if (NG == 9) cd_tangents(f);
-    for (int q = 0; q < DIM; ++q) R[q] = sl[(4 + NGS + q) * nct + k];
-    if (DIM == 2) {
-      const double t0 = -f[1], t1 = f[0];
-      F[0] = R[0] * f[0] + R[1] * t0;
-      F[1] = R[0] * f[1] + R[1] * t1;
-      Q[0] = R[1];
-    } else {
-      for (int q = 0; q < 3; ++q) {
-        const double fk = R[0] * f[q] + R[1] * f[3 + q];
-        F[q] = fk + R[2] * f[6 + q];
-        Q[q] = R[1] * f[6 + q] - R[2] * f[3 + q];
-      }
-    }
+    own_force<DIM>(sl, nct, (int)k, F, Q);
   } else if (DIM == 2) {
     const double4 r4 = *(const double4*)(rin + s * REC);
     F[0] = r4.z;
     F[1] = r4.w;
     Q[0] = r4.y;
   } else {
-    cd_record_force3(rin, nrm4, s, F, Q);
+    cd_record_force3(rin, s, F, Q);
   }
 }
 
@@ -492,7 +510,7 @@ __device__ inline void gather_forces_staged(const SweepArgs& a, const double* ri
     for (int x = a.dinc_ptr[e]; x < e1; ++x) {
       const int ent = a.dinc[x];
       double F[DIM], Q[DR];
-      incidence_force<DIM>(rin, a.nrm4, sl, cs, nct, ent >> 1, F, Q);
+      incidence_force<DIM>(rin, sl, cs, nct, ent >> 1, F, Q);
       add(ent, F, Q);
     }
     return;
@@ -501,7 +519,7 @@ __device__ inline void gather_forces_staged(const SweepArgs& a, const double* ri
     const int ent[4] = {r4i.x, r4i.y, r4i.z, r4i.w};
     double F[4][DIM], Q[4][DR];
     for (int u = 0; u < 4; ++u)
-      if (ent[u] >= 0) incidence_force<DIM>(rin, a.nrm4, sl, cs, nct, ent[u] >> 1, F[u], Q[u]);
+      if (ent[u] >= 0) incidence_force<DIM>(rin, sl, cs, nct, ent[u] >> 1, F[u], Q[u]);
     for (int u = 0; u < 4; ++u) {
       if (ent[u] < 0) break;
       add(ent[u], F[u], Q[u]);
@@ -530,6 +548,105 @@ __device__ inline void entry_finish_staged(const SweepArgs& a, const double* rin
   pr[L::P_R] = o.r;
 }
 
+// The previous sweep's force of foreign slot s in registers (2D: the whole
+// record; 3D: the frame force and the normal), issued before it is needed
+template <int DIM>
+struct HaloPre {
+  double4 r4, n4;
+};
+
+template <int DIM>
+__device__ inline void halo_load(const double* rin, int64_t s, HaloPre<DIM>& o) {
+  o.r4 = *(const double4*)(rin + s * cd_rec(DIM));
+  if (DIM == 3) o.n4 = *(const double4*)(rin + s * cd_rec(DIM) + 4);
+}
+
+// Stores F and Q of a foreign incidence as item h of the domain's LDS block
+// of nh items (column q at q nh): the values add_record computes from the
+// record.
+template <int DIM>
+__device__ inline void halo_put(const HaloPre<DIM>& o, double* hl, int nh, int h) {
+  if (DIM == 2) {
+    hl[h] = o.r4.z;
+    hl[nh + h] = o.r4.w;
+    hl[2 * nh + h] = o.r4.y;
+  } else {
+    double f[9] = {o.n4.x, o.n4.y, o.n4.z, 0, 0, 0, 0, 0, 0};
+    cd_tangents(f);
+    for (int q = 0; q < 3; ++q) {
+      const double fk = o.r4.x * f[q] + o.r4.y * f[3 + q];
+      hl[q * nh + h] = fk + o.r4.z * f[6 + q];
+      hl[(3 + q) * nh + h] = o.r4.y * f[6 + q] - o.r4.z * f[3 + q];
+    }
+  }
+}
+
+// The exchange of one particle entry entirely from LDS: its incidences in
+// row order (ascending contact id), the domain's own from the staged slots,
+// foreign ones as the next item of the entry's run in the staged block hl
+// (items hb - hs on).
+template <int DIM>
+__device__ inline void gather_lds(const SweepArgs& a, int64_t e, const EntryPre<DIM>& o,
+                                  const double* sl, int cs, int nct, const double* hl, int nh,
+                                  int hs, double* acc, double* tacc) {
+  constexpr int DR = Layout<DIM>::DR;
+  constexpr int KW = DIM == 2 ? 8 : 16;
+  int hk = o.hb - hs;
+  const double rp = o.r;
+  auto one = [&](int ent) {
+    const int k = (ent >> 1) - cs;
+    double F[DIM], Q[DR];
+    if (k >= 0 && k < nct) {
+      own_force<DIM>(sl, nct, k, F, Q);
+    } else {
+      for (int q = 0; q < DIM; ++q) F[q] = hl[q * nh + hk];
+      for (int q = 0; q < DR; ++q) Q[q] = hl[(DIM + q) * nh + hk];
+      ++hk;
+    }
+    for (int q = 0; q < DIM; ++q) acc[q] = (ent & 1) ? acc[q] + F[q] : acc[q] - F[q];
+    for (int q = 0; q < DR; ++q) tacc[q] = tacc[q] - rp * Q[q];
+  };
+  if (o.row.x == -2) {
+    // more incidences than a row holds: the pointer list
+    const int e1 = a.dinc_ptr[e + 1];
+    for (int x = a.dinc_ptr[e]; x < e1; ++x) one(a.dinc[x]);
+    return;
+  }
+  const int4* rows = (const int4*)a.drow;
+  int4 r = o.row;
+  for (int q = 0; q < KW / 4; ++q) {
+    if (q == 1) r = o.row1;
+    else if (q > 1) r = rows[q * a.dpe + e];
+    if (r.x < 0) break;
+    one(r.x);
+    if (r.y < 0) break;
+    one(r.y);
+    if (r.z < 0) break;
+    one(r.z);
+    if (r.w < 0) break;
+    one(r.w);
+  }
+}
+
+// entry_finish with the exchange from LDS (gather_lds)
+template <int DIM>
+__device__ inline void entry_finish_lds(const SweepArgs& a, int64_t e, const EntryPre<DIM>& o,
+                                        double* sp, int l, const double* sl, int cs, int nct,
+                                        const double* hl, int nh, int hs) {
+  using L = Layout<DIM>;
+  constexpr int DR = L::DR, PS = L::PS;
+  double acc[DIM], tacc[DR];
+  for (int k = 0; k < DIM; ++k) acc[k] = o.f[k];
+  for (int k = 0; k < DR; ++k) tacc[k] = o.t[k];
+  gather_lds<DIM>(a, e, o, sl, cs, nct, hl, nh, hs, acc, tacc);
+  double* pr = sp + (int64_t)PS * l;
+  for (int k = 0; k < DIM; ++k) pr[k] = o.v[k] + o.dm * acc[k];
+  for (int k = 0; k < DR; ++k) pr[L::P_W + k] = o.w[k] + o.di * tacc[k];
+  pr[L::P_DM] = o.dm;
+  pr[L::P_DI] = o.di;
+  pr[L::P_R] = o.r;
+}
+
 // Per-domain values a workgroup needs before its sweep: the descriptor
 // (first slot, slots, first particle entry, entries, colours, largest
 // colour), one colour
@@ -539,6 +656,7 @@ struct DomainHead {
   int cs, nct, ps, np, ncol;
   int widest;   // contacts of the domain's largest colour
   int wmask;    // walls of finite mass the domain touches (bit w)
+  int hs, nh;   // the domain's foreign incidences: first list index, count
   int co;       // colour offset number threadIdx.x (threads 0..CD_MAX_COLORS)
   double wu;    // wall velocity component number threadIdx.x
 };
@@ -554,6 +672,9 @@ __device__ inline DomainHead load_head(const SweepArgs& a, int d) {
   h.ncol = dd[4];
   h.widest = dd[5];
   h.wmask = dd[6];
+  const int2 hh = a.dhalo[d];
+  h.hs = hh.x;
+  h.nh = hh.y;
   const int tid = threadIdx.x;
   // every colour offset of a domain is written (unused ones hold the count)
   h.co = tid <= CD_MAX_COLORS ? a.dcol[(int64_t)d * (CD_MAX_COLORS + 1) + tid] : 0;
@@ -565,7 +686,8 @@ __device__ inline DomainHead load_head(const SweepArgs& a, int d) {
 // previous force, and the friction coefficient when it is per slot.
 template <int DIM>
 __host__ __device__ constexpr int slot_stage_doubles(bool mu_per_slot) {
-  return 1 + Layout<DIM>::NGS + 3 + DIM + (mu_per_slot ? 1 : 0);
+  static_assert(cd_stage_slot(DIM, false) == 1 + Layout<DIM>::NGS + 3 + DIM, "slot staging");
+  return cd_stage_slot(DIM, mu_per_slot);
 }
 
 // The domain's contact data, slot k at column k of an LDS block of `nct`
@@ -616,11 +738,15 @@ __host__ __device__ inline unsigned long long rand_mix(unsigned long long x) {
 // colours: slot s draws rand_mix(jkey ^ s), jkey = rand_mix(K ^ j) of sweep
 // j, and thread 0 updates the domain's contacts one at a time by increasing
 // draw (equal draws by slot); the draws and the ranked slots take 16 bytes
-// of LDS per contact after the form's own staging.  GLOB: the particle records live in global scratch (domains too
-// large for LDS).  STAGE: the domain's contact data is copied to LDS
-// alongside the exchange (all its loads in flight at once) and the colours
-// read it from there; otherwise each thread reads its contact of the next
-// colour into registers one colour ahead.
+// of LDS per contact after the form's own staging.  GLOB: the particle
+// records live in global scratch (domains too large for LDS).  STAGE: the
+// domain's contact data and the previous sweep's forces of its foreign
+// incidences are copied to LDS (all their loads in flight at once), the
+// exchange reads only LDS and the colours read the contact data from
+// there (HALO; without it the foreign forces are read from memory in the
+// exchange, which needs less LDS); otherwise the exchange reads the records
+// from memory and each thread reads its contact of the next colour into
+// registers one colour ahead.
 // MOBILE: walls of finite mass (Sec. 4.1): a domain touching one takes its
 // velocity after the exchange from all its contacts' forces of the previous
 // sweep (read in parallel into s_wtmp, summed in ascending contact id by one
@@ -628,7 +754,7 @@ __host__ __device__ inline unsigned long long rand_mix(unsigned long long x) {
 // its own copy in s_wu, which the domain's contacts with it update (s_wm:
 // dt/M per wall).
 template <int DIM, bool GLOB, bool STAGE, bool MIXED = false, bool RAND = false,
-          bool MOBILE = false, class Idle>
+          bool MOBILE = false, bool HALO = true, class Idle>
 __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead& h,
                                     const double* rin, double* rout, double* lds, int* s_co,
                                     double* s_wu, long long& npass, double& maxd, double& sumr,
@@ -682,7 +808,53 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
   int kc = -1;
   double* sl = lds + (int64_t)PS * np;
   const bool mu_slot = a.mu_step != 0;
-  if (STAGE) {
+  // foreign incidences staged after the slots (staged form with HALO)
+  double* hl = sl + (int64_t)slot_stage_doubles<DIM>(mu_slot) * nct;
+  const int nh = HALO ? h.nh : 0;
+  if (STAGE && HALO) {
+    // 1. this thread's first two contacts, first particle entry and first
+    //    foreign incidence: every read is issued before any is used
+    //    (indices clamped to valid ones so that the loads are
+    //    unconditional); the contact data goes to LDS while the foreign
+    //    incidences' forces are read, and those go to LDS as well, so that
+    //    the exchange below reads nothing from memory
+    {
+      const int k1 = tid, k2 = tid + nthr;
+      SlotPre<DIM> x, y;
+      EntryPre<DIM> ep;
+      const int64_t s0 = nct > 0 ? cs : 0;
+      fetch_slot<DIM, false>(a, rin, s0 + (k1 < nct ? k1 : 0), x);
+      fetch_slot<DIM, false>(a, rin, s0 + (k2 < nct ? k2 : 0), y);
+      const int64_t e1 = np > 0 ? ps + (tid < np ? tid : 0) : 0;
+      entry_load<DIM>(a, e1, ep);
+      const int hsl = nh > 0 ? a.halo[h.hs + (tid < nh ? tid : 0)] : 0;
+      if (k1 < nct) put_slot<DIM>(sl, nct, k1, x, mu_slot);
+      if (k2 < nct) put_slot<DIM>(sl, nct, k2, y, mu_slot);
+      HaloPre<DIM> hp;
+      if (tid < nh) halo_load<DIM>(rin, hsl, hp);
+      entry_row1<DIM>(a, e1, ep);
+      // the rest of the contacts (domains of more than two per thread)
+      for (int k = tid + 2 * nthr; k < nct; k += nthr) {
+        SlotPre<DIM> z;
+        fetch_slot<DIM, false>(a, rin, cs + k, z);
+        put_slot<DIM>(sl, nct, k, z, mu_slot);
+      }
+      if (tid < nh) halo_put<DIM>(hp, hl, nh, tid);
+      for (int q = tid + nthr; q < nh; q += nthr) {
+        HaloPre<DIM> hq;
+        halo_load<DIM>(rin, a.halo[h.hs + q], hq);
+        halo_put<DIM>(hq, hl, nh, q);
+      }
+      __syncthreads();
+      if (tid < np) entry_finish_lds<DIM>(a, e1, ep, sp, tid, sl, cs, nct, hl, nh, h.hs);
+    }
+    for (int l = tid + nthr; l < np; l += nthr) {
+      EntryPre<DIM> ep;
+      entry_load<DIM>(a, ps + l, ep);
+      entry_row1<DIM>(a, ps + l, ep);
+      entry_finish_lds<DIM>(a, ps + l, ep, sp, l, sl, cs, nct, hl, nh, h.hs);
+    }
+  } else if (STAGE) {
     // 1. this thread's first two contacts and first particle entry: every
     //    read is issued before any is used (indices clamped to valid ones
     //    so that the loads are unconditional), then the contact data goes
@@ -711,8 +883,8 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
       }
       if (DIM == 3) {
         // 3D: the gathers read the domain's own contacts (most of a
-        // particle's incidences) from the staged copy instead of 64 bytes
-        // of record each, and only foreign ones from memory
+        // particle's incidences) from the staged copy, only foreign ones
+        // from memory
         __syncthreads();
         if (tid < np) entry_finish_staged<DIM>(a, rin, e1, ep, sp, tid, sl, cs, nct);
       }
@@ -742,7 +914,7 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
   __syncthreads();
   if (RAND) {
     unsigned long long* key =
-        (unsigned long long*)(STAGE ? sl + (int64_t)slot_stage_doubles<DIM>(mu_slot) * nct
+        (unsigned long long*)(STAGE ? hl + (int64_t)cd_stage_halo(DIM) * nh
                                     : (GLOB ? lds : lds + (int64_t)PS * np));
     int* perm = (int*)(key + nct);
     for (int k = tid; k < nct; k += nthr) key[k] = rand_mix(jkey ^ (unsigned long long)(cs + k));

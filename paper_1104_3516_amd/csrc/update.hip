@@ -32,10 +32,10 @@ __global__ __launch_bounds__(kThreads) void k_update(double* x, double* v, doubl
                                                     const double* r, const double* dtim,
                                                     const double* dtii, const int* inc_ptr,
                                                     const int* inc, const double* rec,
-                                                    const double* nrm4, int64_t n, double dt,
+                                                    int64_t n, double dt,
                                                     Period per) {
   constexpr int DR = DIM == 2 ? 1 : 3;
-  constexpr int REC = kRec;
+  constexpr int REC = cd_rec(DIM);
   int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
   double acc[DIM], tacc[DR];
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kThreads) void k_update(double* x, double* v, doubl
       tacc[0] = tacc[0] - rp * q;
     } else {
       double F[3], Q[3];
-      cd_record_force3(rec, nrm4, ent >> 1, F, Q);
+      cd_record_force3(rec, ent >> 1, F, Q);
       for (int k = 0; k < 3; ++k) acc[k] = (ent & 1) ? acc[k] + F[k] : acc[k] - F[k];
       for (int k = 0; k < 3; ++k) tacc[k] = tacc[k] - rp * Q[k];
     }
@@ -141,7 +141,7 @@ hipError_t cd_launch_wall_velocities(cd_ctx* c) {
   if (c->W == 0) return hipSuccess;
   hipLaunchKernelGGL(k_wall_velocities, dim3(c->W), dim3(kThreads), 0, c->stream, c->dim, c->W,
                      c->mobile_mask, c->d_wall, c->rec[c->h_state->iter & 1],
-                     kRec, c->wall_slot, c->wall_cnt, c->cap, c->d_wall_new);
+                     cd_rec(c->dim), c->wall_slot, c->wall_cnt, c->cap, c->d_wall_new);
   return hipGetLastError();
 }
 
@@ -169,11 +169,11 @@ hipError_t cd_launch_update(cd_ctx* c, int final_iter) {
   }
   if (c->dim == 2)
     hipLaunchKernelGGL(k_update<2>, dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->v, c->w, c->f,
-                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->nrm4, c->n,
+                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->n,
                        c->p.dt, per);
   else
     hipLaunchKernelGGL(k_update<3>, dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->v, c->w, c->f,
-                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->nrm4, c->n,
+                       c->t, c->r, c->dtim, c->dtii, c->inc_ptr, c->inc, rec, c->n,
                        c->p.dt, per);
   return hipGetLastError();
 }

@@ -209,6 +209,8 @@ def test_full_size_disks_262k_2048_domains_both_forms(solve_mode):
                     fixed_iters=20)
     compare_step(sim, ctx, f"262k 2048 domains mode{solve_mode}")
     assert ctx.timing().staged == (1 if solve_mode == 1 else 0)
+    # one round of workgroups either way: 2D keeps the foreign records in memory
+    assert ctx.timing().foreign_in_lds == 0
 
 
 def test_full_size_disks_262k_300_sweeps_then_next_step():
@@ -254,6 +256,8 @@ def test_full_size_spheres_1m_16384_domains_fixed_sweeps():
     compare_step(sim, ctx, "1m spheres fixed10")
     compare_step(sim, ctx, "1m spheres step 2")
     assert ctx.timing().staged == 2
+    # the exchange reads the foreign incidences' forces from LDS
+    assert ctx.timing().foreign_in_lds == 1
 
 
 def test_full_size_spheres_tolerance_step_properties():
