@@ -58,14 +58,16 @@ BYTES = {2: (64, 48), 3: (88, 72)}
 WORKLOADS = {
     "disks_262k": dict(
         config="disks_262k", dim=2, mu=0.3, domains=2048, steps=100, cpu_sweeps=600,
-        traffic="sweep_disks_262k_traffic.json",
+        traffic="sweep_disks_262k_traffic.json", tune=(512, 1024, 2048, 4096), tune_use=True,
         text=("disks_262k: 2D disks N=262144 (512x512 jittered triangular lattice), mu=0.3, "
-              "dt=1e-3, gravity 1, 2048 contact-count-balanced bisection domains (4096 "
-              "diverges), repartition every 10 steps, alpha=1e-6 local test, max 2000 sweeps, "
-              "gravity settling")),
+              "dt=1e-3, gravity 1, contact-count-balanced bisection domains, their count "
+              "picked by the domain-count tuner among 512-4096 (the stated 4096 diverges; "
+              "2048 without tuning), repartition every 10 steps, alpha=1e-6 local test, max "
+              "2000 sweeps, gravity settling")),
     "spheres_1m": dict(
         config="spheres_1m", dim=3, mu=0.5, domains=16384, steps=50, cpu_sweeps=60,
-        traffic="sweep_spheres_1m_traffic.json",
+        traffic="sweep_spheres_1m_traffic.json", tune=(4096, 8192, 16384, 32768),
+        tune_use=False,
         text=("spheres_1m: 3D spheres N=1048576 (128x128x64 jittered simple-cubic lattice), "
               "mu=0.5, dt=1e-3, no gravity, top wall driven down at 1e-3, 16384 "
               "contact-count-balanced bisection domains, repartition every 10 steps, "
@@ -93,13 +95,16 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(path):
+def measured_traffic(path, n_domains=None):
     """HBM bytes per sweep launch from the committed counter measurement, or
-    None when the sweep kernel's sources changed since it was taken."""
+    None when the sweep kernel's sources changed since it was taken or it
+    was taken at another domain count."""
     import hashlib
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    if n_domains is not None and rec.get("n_domains") not in (None, n_domains):
+        return None
     h = hashlib.sha256()
     for f in ("sweep.hip", "sweep_core.h", "cd_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1104_3516_amd", "csrc", f), "rb").read())
@@ -118,19 +123,24 @@ def boundary_fraction(n, c):
     """Fraction of contacts with a body that also has contacts in another
     domain (walls excluded): the share of the update that sees frozen
     foreign forces, the parallel fraction p of Sec. 2.3."""
-    import numpy as np
-    ci, cj, dom = c["ci"].astype(np.int64), c["cj"].astype(np.int64), c["dom"].astype(np.int64)
-    if ci.size == 0:
-        return 0.0
-    body = np.concatenate([ci, cj[cj < n]])
-    d = np.concatenate([dom, dom[cj < n]])
-    lo = np.full(n, np.iinfo(np.int64).max)
-    hi = np.full(n, -1)
-    np.minimum.at(lo, body, d)
-    np.maximum.at(hi, body, d)
-    shared = lo != hi
-    shared_c = shared[ci] | np.where(cj < n, shared[np.minimum(cj, n - 1)], False)
-    return float(shared_c.mean())
+    from paper_1104_3516_amd import tune
+    return tune.boundary_fraction(c["ci"], c["cj"], c["dom"], n)
+
+
+def tuned_domains(wl, pk, binding, candidates):
+    """The domain-count tuner on this workload's parameters: candidates in
+    increasing order until one diverges, the fastest converging one kept
+    (three steps each on throwaway contexts, no cache)."""
+    from paper_1104_3516_amd import tune
+    mk = lambda P: binding.make_params(wl["dim"], pk.n_walls, mu=wl["mu"], dt=1e-3, alpha=1e-6,
+                                       criterion=0, max_iter=2000, n_domains=P,
+                                       repartition_every=10, warm_start=1)
+    out = tune.tune_domains(pk, mk, binding, candidates=candidates, steps=3, use_cache=False,
+                            log=log)
+    keep = ("n_domains", "ms_per_step", "sweeps", "boundary_fraction", "diverged")
+    return {"n_domains": out["n_domains"],
+            "critical_boundary_fraction": out["critical_boundary_fraction"],
+            "trials": [{k: t[k] for k in keep} for t in out["trials"]]}
 
 
 def mixed_experiment(torch, binding, inputs, cap=3000, settle=50, seed=2023):
@@ -539,6 +549,9 @@ def main() -> int:
                     help="after the timed steps, solve one step from scratch with the "
                          "workload's domains and with one domain (2D workloads)")
     ap.add_argument("--sequential-max-iter", type=int, default=20000)
+    ap.add_argument("--tune-domains", type=int, default=1,
+                    help="run the domain-count tuner (disks_262k uses its choice; spheres_1m "
+                         "keeps the stated 16384 and reports the tuner's trials)")
     ap.add_argument("--traffic-json", default=None,
                     help="counter record of the sweep kernel (default: the workload's)")
     args = ap.parse_args()
@@ -631,6 +644,13 @@ def main() -> int:
         print(json.dumps(out), flush=True)
         return 0
     pk = inputs.config(wl["config"])
+    tuning = None
+    if args.tune_domains and wl.get("tune"):
+        log(f"domain-count tuning on {args.workload} ...")
+        tuning = tuned_domains(wl, pk, binding, wl["tune"])
+        tuning["used"] = bool(wl["tune_use"])
+        if wl["tune_use"]:
+            wl = dict(wl, domains=tuning["n_domains"])
     out = run_single(args, wl, pk, torch, binding, inputs, steps=args.steps,
                      warmup=args.warmup, time_every=args.time_every,
                      traffic_json=args.traffic_json, random_order=args.random_order,
@@ -639,6 +659,8 @@ def main() -> int:
         out["mixed_parallelness"] = mixed_experiment(torch, binding, inputs)
     if args.order_experiment:
         out["update_orders"] = order_experiment(torch, binding, inputs)
+    if tuning is not None:
+        out["domain_count_tuning"] = tuning
     ctx = out.pop("_ctx")
     if args.sequential and wl["dim"] == 2:
         out["sequential_comparison"] = sequential_comparison(wl, pk, ctx, torch, binding,
@@ -715,7 +737,7 @@ def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, 
     # no per-sweep events (--time-every 0): no kernel duration, no roofline
     achieved = bytes_per_sweep / avg_sweep_s / 1e9 if sweeps and avg_sweep_s > 0 else None
     # the counters were taken on the colour-major sweep
-    traffic = measured_traffic(traffic_json) if random_order < 0 else None
+    traffic = measured_traffic(traffic_json, P) if random_order < 0 else None
     out = {
         "metric": METRIC,
         "value": updates / elapsed,
@@ -767,14 +789,19 @@ def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, 
 
 
 def extra_workloads(args, torch, binding, inputs) -> dict:
-    """Beside the 3D headline: the 2D 262,144-disk workload at 2,048 domains
-    (timed like the headline, fewer steps) and the same packing at the 4,096
-    domains of its stated configuration, which diverges (the step and the
-    status at which it fails are reported)."""
+    """Beside the 3D headline: the 2D 262,144-disk workload at the domain
+    count its tuner picks (timed like the headline, fewer steps); the
+    tuner's trials include the 4,096 domains of its stated configuration,
+    which diverge."""
     wl = WORKLOADS["disks_262k"]
     pk = inputs.config(wl["config"])
     res = {}
-    log("extra workload: disks_262k at 2,048 domains ...")
+    tuning = None
+    if args.tune_domains:
+        log("extra workload: disks_262k domain-count tuning ...")
+        tuning = tuned_domains(wl, pk, binding, wl["tune"])
+        wl = dict(wl, domains=tuning["n_domains"])
+    log(f"extra workload: disks_262k at {wl['domains']} domains ...")
     o = run_single(args, wl, pk, torch, binding, inputs, steps=args.extra_steps, warmup=2,
                    time_every=args.time_every,
                    traffic_json=os.path.join(ROOT, "profiles", wl["traffic"]))
@@ -782,24 +809,8 @@ def extra_workloads(args, torch, binding, inputs) -> dict:
     keep = ("value", "unit", "ms_per_step", "steps", "sweeps_per_step", "steps_at_sweep_cap",
             "sweep_kernel_us", "roofline", "config")
     res["disks_262k"] = {k: o[k] for k in keep}
-    log("extra workload: disks_262k at 4,096 domains (the stated configuration) ...")
-    ctx = make_ctx(wl, pk, binding, timing=0, n_domains=4096)
-    steps = []
-    failed = None
-    for s in range(10):
-        try:
-            r = ctx.step()
-            steps.append({"step": s, "sweeps": int(r.iterations), "status": int(r.status)})
-        except binding.CDError as err:
-            failed = {"step": s, "status": int(err.code), "error": str(err)}
-            break
-    torch.cuda.synchronize()
-    ctx.close()
-    res["disks_262k_4096_domains"] = {
-        "result": "fails" if failed else "runs", "steps_completed": steps, "failure": failed,
-        "note": ("the domain-wise update of this packing at 4,096 domains (about 74 contacts "
-                 "per domain) diverges; the CPU oracle with the same partition diverges "
-                 "identically, so the 2D line above uses 2,048 domains")}
+    if tuning is not None:
+        res["disks_262k"]["domain_count_tuning"] = tuning
     return res
 
 
