@@ -208,8 +208,8 @@ __device__ inline void decide_wave(const SweepArgs& a, int jd) {
 // TIMED: per-domain load measurement into a.dtick (single contexts with load
 // balancing on; a separate instantiation so that the plain sweep is unchanged).
 // MOBILE: the box has walls of finite mass (a separate instantiation).
-template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false,
-          bool RAND = false, bool MOBILE = false, bool HALO = true>
+template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED, bool TIMED, bool RAND,
+          bool MOBILE, bool HALO>
 __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArgs& a, int b, int j,
                                                                   BatchProg* bp) {
   extern __shared__ double lds[];
@@ -262,8 +262,10 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
 // (Sec. 2.3), a separate instantiation so that the plain sweep is unchanged.
 // RAND: the random sequential order of Sec. 2.1 (thread 0 of each domain's
 // workgroup updates its contacts one at a time), a separate instantiation.
-template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED = false, bool TIMED = false,
-          bool RAND = false, bool MOBILE = false, bool HALO = true>
+// HALO: the staged form with the foreign incidences' forces in LDS (the
+// dynamic LDS of the launch must be sized for it).
+template <int DIM, bool GLOB, bool STAGE, bool FOLD, bool MIXED, bool TIMED, bool RAND,
+          bool MOBILE, bool HALO>
 __global__ __launch_bounds__(kMaxBlock, STAGE && DIM == 2 ? 5 : 1) void k_sweep(SweepArgs a, int j) {
   sweep_block<DIM, GLOB, STAGE, FOLD, MIXED, TIMED, RAND, MOBILE, HALO>(a, blockIdx.x, j, nullptr);
 }
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep_batch(const SweepArgs* tab,
   const int2 pb = ((const int2*)blk)[blockIdx.x];
   // read in place: a local copy of the arguments would live in scratch
   const SweepArgs& a = tab[pb.x];
-  sweep_block<DIM, false, STAGE, false>(a, pb.y, j, bp);
+  sweep_block<DIM, false, STAGE, false, false, false, false, false, STAGE>(a, pb.y, j, bp);
 }
 
 // stop decision of sweep jd alone (after the last launched sweep)
@@ -599,8 +601,10 @@ bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64
     ks = dim == 2 ? (const void*)k_sweep_batch<2, true> : (const void*)k_sweep_batch<3, true>;
     kp = dim == 2 ? (const void*)k_sweep_batch<2, false> : (const void*)k_sweep_batch<3, false>;
   } else {
-    ks = dim == 2 ? (const void*)k_sweep<2, false, true, true> : (const void*)k_sweep<3, false, true, true>;
-    kp = dim == 2 ? (const void*)k_sweep<2, false, false, false> : (const void*)k_sweep<3, false, false, false>;
+    ks = dim == 2 ? (const void*)k_sweep<2, false, true, true, false, false, false, false, true>
+                  : (const void*)k_sweep<3, false, true, true, false, false, false, false, true>;
+    kp = dim == 2 ? (const void*)k_sweep<2, false, false, false, false, false, false, false, false>
+                  : (const void*)k_sweep<3, false, false, false, false, false, false, false, false>;
   }
   const int64_t rs = resident_per_cu(ks, block, lds_stage);
   const int64_t rp = resident_per_cu(kp, block, lds_plain);
@@ -609,6 +613,17 @@ bool cd_stage_pick(int dim, int block, size_t lds_plain, size_t lds_stage, int64
   // staging must not add a round of workgroups
   const int64_t slots_s = rs * num_cu, slots_p = rp * num_cu;
   return (wg_stage + slots_s - 1) / slots_s <= (wg_plain + slots_p - 1) / slots_p;
+}
+
+// The plain staged instantiation with the decision folded (no mixed update,
+// no load timing, colour-major order, rigid walls), with or without the
+// foreign incidences' forces in LDS, for occupancy queries.
+static const void* staged_kernel(int dim, bool halo) {
+  if (dim == 2)
+    return halo ? (const void*)k_sweep<2, false, true, true, false, false, false, false, true>
+                : (const void*)k_sweep<2, false, true, true, false, false, false, false, false>;
+  return halo ? (const void*)k_sweep<3, false, true, true, false, false, false, false, true>
+              : (const void*)k_sweep<3, false, true, true, false, false, false, false, false>;
 }
 
 void cd_sweep_mode(cd_ctx* c) {
@@ -636,10 +651,8 @@ void cd_sweep_mode(cd_ctx* c) {
   // overlaps its record gathers with the slot staging and was measured
   // faster at equal rounds)
   {
-    const void* kh = c->dim == 2 ? (const void*)k_sweep<2, false, true, true>
-                                 : (const void*)k_sweep<3, false, true, true>;
-    const void* kn = c->dim == 2 ? (const void*)k_sweep<2, false, true, true, false, false, false, false, false>
-                                 : (const void*)k_sweep<3, false, true, true, false, false, false, false, false>;
+    const void* kh = staged_kernel(c->dim, true);
+    const void* kn = staged_kernel(c->dim, false);
     const int64_t rh = lds_halo + extra + 2048 <= c->max_lds
                            ? resident_per_cu(kh, c->sweep_block, lds_halo + extra) * c->num_cu
                            : 0;
@@ -657,12 +670,7 @@ void cd_sweep_mode(cd_ctx* c) {
                                  c->max_lds, false);
   if (!c->sweep_stage) c->sweep_halo = false;
   if (c->sweep_stage && c->sweep_block >= 128) {
-    const void* kf =
-        c->sweep_halo
-            ? (c->dim == 2 ? (const void*)k_sweep<2, false, true, true>
-                           : (const void*)k_sweep<3, false, true, true>)
-            : (c->dim == 2 ? (const void*)k_sweep<2, false, true, true, false, false, false, false, false>
-                           : (const void*)k_sweep<3, false, true, true, false, false, false, false, false>);
+    const void* kf = staged_kernel(c->dim, c->sweep_halo);
     const int64_t slots =
         (int64_t)resident_per_cu(kf, c->sweep_block, c->sweep_lds_stage + extra) * c->num_cu;
     c->sweep_fold = domains + 1 > slots;
@@ -675,7 +683,7 @@ template <int DIM, bool MIXED, bool TIMED, bool RAND = false, bool MOBILE = fals
 static void launch_sweep_form(cd_ctx* c, const SweepArgs& a, dim3 grid, dim3 block, size_t lds,
                               bool fold, int j) {
   if (c->sweep_global)
-    hipLaunchKernelGGL((k_sweep<DIM, true, false, false, MIXED, TIMED, RAND, MOBILE>), grid, block,
+    hipLaunchKernelGGL((k_sweep<DIM, true, false, false, MIXED, TIMED, RAND, MOBILE, false>), grid, block,
                        RAND ? lds : 0, c->stream, a, j);
   else if (fold && c->sweep_halo)
     hipLaunchKernelGGL((k_sweep<DIM, false, true, true, MIXED, TIMED, RAND, MOBILE, true>), grid,
@@ -690,7 +698,7 @@ static void launch_sweep_form(cd_ctx* c, const SweepArgs& a, dim3 grid, dim3 blo
     hipLaunchKernelGGL((k_sweep<DIM, false, true, false, MIXED, TIMED, RAND, MOBILE, false>), grid,
                        block, lds, c->stream, a, j);
   else
-    hipLaunchKernelGGL((k_sweep<DIM, false, false, false, MIXED, TIMED, RAND, MOBILE>), grid,
+    hipLaunchKernelGGL((k_sweep<DIM, false, false, false, MIXED, TIMED, RAND, MOBILE, false>), grid,
                        block, lds, c->stream, a, j);
 }
 
@@ -761,23 +769,26 @@ hipError_t cd_launch_gather_states(hipStream_t stream, const SweepArgs* tab, int
   return hipGetLastError();
 }
 
+template <int DIM>
+static void launch_sweep_grid_dim(cd_ctx* c, const SweepArgs& a, int j, dim3 g, dim3 block) {
+  if (c->sweep_global)
+    hipLaunchKernelGGL((k_sweep<DIM, true, false, false, false, false, false, false, false>), g,
+                       block, 0, c->stream, a, j);
+  else if (c->sweep_stage && c->sweep_halo)
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, false, false, false, false, true>), g,
+                       block, block_lds(c), c->stream, a, j);
+  else if (c->sweep_stage)
+    hipLaunchKernelGGL((k_sweep<DIM, false, true, false, false, false, false, false, false>), g,
+                       block, block_lds(c), c->stream, a, j);
+  else
+    hipLaunchKernelGGL((k_sweep<DIM, false, false, false, false, false, false, false, false>), g,
+                       block, block_lds(c), c->stream, a, j);
+}
+
 hipError_t cd_launch_sweep_grid(cd_ctx* c, const SweepArgs& a, int j, int grid) {
   dim3 g(grid), block(c->sweep_block);
-  if (c->dim == 2) {
-    if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<2, true, false, false>), g, block, 0, c->stream, a, j);
-    else if (c->sweep_stage)
-      hipLaunchKernelGGL((k_sweep<2, false, true, false>), g, block, block_lds(c), c->stream, a, j);
-    else
-      hipLaunchKernelGGL((k_sweep<2, false, false, false>), g, block, block_lds(c), c->stream, a, j);
-  } else {
-    if (c->sweep_global)
-      hipLaunchKernelGGL((k_sweep<3, true, false, false>), g, block, 0, c->stream, a, j);
-    else if (c->sweep_stage)
-      hipLaunchKernelGGL((k_sweep<3, false, true, false>), g, block, block_lds(c), c->stream, a, j);
-    else
-      hipLaunchKernelGGL((k_sweep<3, false, false, false>), g, block, block_lds(c), c->stream, a, j);
-  }
+  if (c->dim == 2) launch_sweep_grid_dim<2>(c, a, j, g, block);
+  else launch_sweep_grid_dim<3>(c, a, j, g, block);
   return hipGetLastError();
 }
 

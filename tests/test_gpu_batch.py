@@ -99,3 +99,46 @@ def test_batch_rejects_mixed_dimensions():
     c3 = binding.Context(binding.make_params(3, p3.n_walls), p3)
     with pytest.raises(binding.CDError):
         binding.Batch([c2, c3])
+
+
+def test_full_size_batch512_one_step():
+    """The 512-packing workload (N log-uniform in [256, 65536], 5.58M disks,
+    mu uniform in [0.1, 0.6]) at about 300 contacts per domain, one step:
+    the batch against every packing stepped alone on the GPU, bit for bit;
+    and eight packings, the largest among them, against the oracle."""
+    import os
+    from oracle import cdref
+    from paper_1104_3516_amd import binding
+    _torch()
+    cdref.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    packs, mus = inputs.uneven_batch(512)
+    kw = lambda pk, mu: dict(mu=float(mu), alpha=1e-6, criterion=0, max_iter=2000,
+                             n_domains=domains_for(pk, 300), repartition_every=10, warm_start=1)
+    ctx_b = [binding.Context(binding.make_params(2, pk.n_walls, **kw(pk, mu)), pk, timing=0)
+             for pk, mu in zip(packs, mus)]
+    batch = binding.Batch(ctx_b, timing=0)
+    res = batch.step()
+    sizes = np.array([pk.n for pk in packs])
+    print(f"[batch512] N total {sizes.sum()}, contacts {sum(r.n_contacts for r in res)}, "
+          f"largest N {sizes.max()}, sweeps max {max(r.iterations for r in res)}, "
+          f"at the cap {sum(r.status == binding.MAXITER for r in res)}", flush=True)
+    for b, (pk, mu) in enumerate(zip(packs, mus)):
+        single = binding.Context(binding.make_params(2, pk.n_walls, **kw(pk, mu)), pk, timing=0)
+        r1 = single.step()
+        assert res[b].iterations == r1.iterations and res[b].status == r1.status, b
+        assert res[b].n_contacts == r1.n_contacts, b
+        cb = {k: v.cpu().numpy() for k, v in ctx_b[b].contacts().items()}
+        cs = {k: v.cpu().numpy() for k, v in single.contacts().items()}
+        for k in ("ci", "cj", "dom", "color", "slot", "R"):
+            np.testing.assert_array_equal(cb[k], cs[k], err_msg=f"packing {b} {k}")
+        for tb, ts in zip(ctx_b[b].state(), single.state()):
+            np.testing.assert_array_equal(tb.cpu().numpy(), ts.cpu().numpy())
+        single.close()
+    order = np.argsort(sizes)
+    pick = sorted(set([int(order[-1])] + [int(order[q]) for q in np.linspace(0, 510, 7).astype(int)]))
+    for b in pick:
+        pk, mu = packs[b], mus[b]
+        sim = cdref.Sim(cdref.make_params(2, pk.n_walls, **kw(pk, mu)), pk)
+        io = sim.step()
+        compare_results(sim, ctx_b[b], io, res[b], f"batch512 p{b} N={pk.n}")
+    batch.close()
