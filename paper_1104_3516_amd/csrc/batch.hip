@@ -36,8 +36,8 @@ struct cd_batch {
   std::vector<int> failed;      // per packing: 0, or the error that took it out
   std::vector<hipEvent_t> sweep_ev;
   hipEvent_t ev[4] = {};
-  // lanes: the per-packing preparation and update are spread over a few
-  // streams, each fed by its own host thread, so that the many small
+  // lanes: the per-packing preparation and update are spread over up to
+  // 16 streams, each fed by its own host thread, so that the many small
   // kernels of different packings run side by side
   std::vector<hipStream_t> lane;
   std::vector<hipEvent_t> lane_ev;
@@ -52,7 +52,10 @@ int bfail(cd_batch* b, int code, const std::string& msg) {
   return code;
 }
 
-constexpr int kLanes = 4;
+// Host threads (and streams) of the preparation: submission of the many
+// small launches scales up to about 16 (measured on 512 packings: 194 ms per
+// warm step with one, 100 with four, 78 with eight, 66 with sixteen).
+constexpr int kLanes = 16;
 
 // The packings' work on the lanes: packing p on lane p % lanes.
 void lanes_attach(cd_batch* b) {
@@ -180,7 +183,8 @@ int cd_batch_create(cd_batch** out, cd_ctx* const* ctxs, int count) {
     st = CD_EHIP;
   for (int k = 0; k < 4 && st == CD_OK; ++k)
     if (hipEventCreate(&b->ev[k]) != hipSuccess) st = CD_EHIP;
-  const int lanes = std::min(kLanes, (int)count);
+  const int hw = std::max(1u, std::thread::hardware_concurrency());
+  const int lanes = std::min({kLanes, (int)count, (int)hw});
   for (int t = 0; t < lanes && st == CD_OK; ++t) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) st = CD_EHIP;
