@@ -182,6 +182,61 @@ def mixed_experiment(torch, binding, inputs, cap=3000, settle=50, seed=2023):
             "rows": rows, "p_c": min(failing) if failing else None}
 
 
+def confined_pc_experiment(torch, binding, inputs, nx=40, steps=3000, dt=1e-2, pressure=1.0,
+                           cap=20000, seed=7):
+    """The protocol of Sec. 2.3 on a confined packing: nx x nx disks without
+    gravity compressed between two walls of finite mass pushed with
+    `pressure` per unit width (periodic in x) for `steps` steps, then the
+    walls held at their positions, the forces reset, and one step solved with
+    one domain and a share p of the contacts updated in parallel; N_I(p), the
+    closed-contact coordination Z of the compressed packing, and p_c, the
+    smallest p that does not converge within `cap` sweeps."""
+    import numpy as np
+    pk = inputs.sheared_box_2d(nx, nx, 2023, pressure=pressure)
+    prm = binding.make_params(2, pk.n_walls, mu=0.3, dt=dt, n_domains=1, max_iter=3000)
+    ctx = binding.Context(prm, pk, timing=0)
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ctx.step()
+    x, v, w = (t.cpu().numpy() for t in ctx.state())
+    wo = ctx.wall_offsets()
+    c = {k: t.cpu().numpy() for k, t in ctx.contacts().items()}
+    z = 2.0 * float((c["R"][0] > 0).sum()) / pk.n
+    vw = ctx.wall_velocities()
+    ctx.close()
+    log(f"confined packing: {steps} steps in {time.perf_counter() - t0:.1f} s, Z = {z:.2f}, "
+        f"wall speeds {np.abs(vw).max():.2e}")
+    q = pk.copy()
+    q.x, q.v, q.w = x, v, w
+    q.wall_offset = wo.copy()
+    q.wall_inv_mass = None
+    q.wall_force = None
+    q.wall_velocity = np.zeros_like(q.wall_velocity)
+    q.box_lo = np.array([pk.box_lo[0], wo[0]])
+    q.box_hi = np.array([pk.box_hi[0], -wo[1]])
+    rows = []
+    for p in (0.0, 0.02, 0.05, 0.1, 0.2, 0.3, 0.5, 0.65, 1.0):
+        prm = binding.make_params(2, q.n_walls, mu=0.3, dt=dt, n_domains=1, max_iter=cap,
+                                  warm_start=0)
+        cq = binding.Context(prm, q, timing=0)
+        cq.set_mixed_update(p, seed)
+        try:
+            r = cq.step()
+            status, sweeps = int(r.status), int(r.iterations)
+        except binding.CDError as err:
+            status, sweeps = int(err.code), None
+        cq.close()
+        rows.append({"p": p, "sweeps": sweeps, "status": status, "converged": status == 0})
+        log(f"confined mixed update p={p:.2f}: {sweeps} sweeps, status {status}")
+    failing = [row["p"] for row in rows if not row["converged"]]
+    return {"packing": f"{nx}x{nx} disks, no gravity, periodic in x, compressed for {steps} "
+                       f"steps (dt {dt}) between walls of finite mass under pressure {pressure}; "
+                       f"Z of closed contacts {z:.2f}",
+            "procedure": "walls then held, forces reset, one step with one domain, alpha=1e-6, "
+                         f"at most {cap} sweeps; parallel contacts by pair number (seed {seed})",
+            "rows": rows, "p_c": min(failing) if failing else None}
+
+
 def order_experiment(torch, binding, inputs, seeds=8):
     """Sweeps of one cold-started time step in three update orders (Sec. 2.1,
     Sec. 4.3): colour-major, random sequential (mean over `seeds` draws) and
@@ -657,6 +712,7 @@ def main() -> int:
                      balance=args.balance)
     if args.mixed_experiment:
         out["mixed_parallelness"] = mixed_experiment(torch, binding, inputs)
+        out["mixed_parallelness_confined"] = confined_pc_experiment(torch, binding, inputs)
     if args.order_experiment:
         out["update_orders"] = order_experiment(torch, binding, inputs)
     if tuning is not None:
