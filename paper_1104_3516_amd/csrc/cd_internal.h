@@ -64,6 +64,8 @@ struct DomainStats {
   int max_stage;      // largest staged sweep data of a domain (particles, slots, foreign
                       // incidences), bytes
   int max_stage0;     // the same without the foreign incidences
+  int max_stage_u;    // the same with the shared layout for domains of at most kUnionMax
+                      // entries
   int scan_fault;     // sticky: a prefix scan gave up waiting on a predecessor tile
                       // (never cleared by the per-step reset of the fields above)
 };
@@ -487,6 +489,10 @@ __host__ __device__ constexpr int cd_stage_halo(int dim) { return dim == 2 ? 3 :
 // slot of the pinned 64-entry scratch (c->h_scratch) that receives the
 // active-contact count of a finished solve
 constexpr int kActiveSlot = 63;
+// domains of at most this many particle entries (and workgroups at least
+// this wide) stage the foreign incidences' forces in the LDS of their
+// particle records (the staged sweep's shared layout)
+constexpr int kUnionMax = 128;
 // first of the slots (CD_MAX_WALLS * 3 doubles) that receive the velocities
 // of the walls after a step with walls of finite mass
 constexpr int kWallSlot = 32;

@@ -744,8 +744,8 @@ __global__ __launch_bounds__(kThreads) void k_halo_count(const int* dp, const in
 __global__ __launch_bounds__(kStats) void k_halo_dom(const int* dp_start, const int* ddesc, int P,
                                                     const int* hoff, int ps, int sw, int hw,
                                                     int2* dhalo, DomainStats* stats) {
-  __shared__ long long sh[3][kStats / 64];
-  long long mh = 0, mb = 0, m0 = 0;
+  __shared__ long long sh[4][kStats / 64];
+  long long mh = 0, mb = 0, m0 = 0, mu = 0;
   for (int d = threadIdx.x; d < P; d += kStats) {
     const int hs = hoff[dp_start[d]];
     const int nh = hoff[dp_start[d + 1]] - hs;
@@ -755,17 +755,23 @@ __global__ __launch_bounds__(kStats) void k_halo_dom(const int* dp_start, const 
     mh = max(mh, (long long)nh);
     mb = max(mb, b0 + 8ll * hw * nh);
     m0 = max(m0, b0);
+    // shared layout: particle records and foreign forces in one area
+    const long long pa = (long long)ps * dd[3], ha = (long long)hw * nh;
+    const long long bu = 8ll * ((long long)sw * dd[1] + (pa > ha ? pa : ha));
+    mu = max(mu, dd[3] <= kUnionMax ? bu : b0 + 8ll * hw * nh);
   }
   for (int off = 32; off > 0; off >>= 1) {
     mh = max(mh, __shfl_xor(mh, off, 64));
     mb = max(mb, __shfl_xor(mb, off, 64));
     m0 = max(m0, __shfl_xor(m0, off, 64));
+    mu = max(mu, __shfl_xor(mu, off, 64));
   }
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     sh[0][w] = mh;
     sh[1][w] = mb;
     sh[2][w] = m0;
+    sh[3][w] = mu;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -773,10 +779,12 @@ __global__ __launch_bounds__(kStats) void k_halo_dom(const int* dp_start, const 
       mh = max(mh, sh[0][k]);
       mb = max(mb, sh[1][k]);
       m0 = max(m0, sh[2][k]);
+      mu = max(mu, sh[3][k]);
     }
     stats->max_halo = (int)mh;
     stats->max_stage = (int)(mb < 0x7fffffffll ? mb : 0x7fffffffll);
     stats->max_stage0 = (int)(m0 < 0x7fffffffll ? m0 : 0x7fffffffll);
+    stats->max_stage_u = (int)(mu < 0x7fffffffll ? mu : 0x7fffffffll);
   }
 }
 

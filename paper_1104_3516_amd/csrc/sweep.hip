@@ -632,7 +632,9 @@ void cd_sweep_mode(cd_ctx* c) {
   c->sweep_halo = false;
   if (c->sweep_global || c->stage_off) return;
   const int mu_bytes = c->use_mu_slot ? 8 * c->st_ds.max_contacts : 0;
-  const size_t lds_halo = cd_stage_lds(c->st_ds.max_stage + mu_bytes);
+  // the shared layout needs workgroups at least kUnionMax wide
+  const size_t lds_halo = cd_stage_lds(
+      (c->sweep_block >= kUnionMax ? c->st_ds.max_stage_u : c->st_ds.max_stage) + mu_bytes);
   const size_t lds_nohalo = cd_stage_lds(c->st_ds.max_stage0 + mu_bytes);
   // With two or more wavefronts per workgroup the decision can fold into
   // workgroup 0.  That pays when a launch runs in several rounds of

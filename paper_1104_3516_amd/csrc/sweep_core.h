@@ -398,13 +398,13 @@ struct EntryPre {
   int hb;      // list index of the first foreign incidence (staged form only)
 };
 
+// The entry's external force and torque (+0.0 without reading when every
+// one is zero).
 template <int DIM>
-__device__ inline void entry_load(const SweepArgs& a, int64_t e, EntryPre<DIM>& o) {
+__device__ inline void entry_ext(const SweepArgs& a, int64_t e, EntryPre<DIM>& o) {
   constexpr int DR = Layout<DIM>::DR;
   const int64_t E = a.dpe;
-  for (int k = 0; k < DIM; ++k) o.v[k] = a.dpb[k * E + e];
-  for (int k = 0; k < DR; ++k) o.w[k] = a.dpb[(DIM + k) * E + e];
-  int q = DIM + DR;
+  const int q = DIM + DR;
   if (a.ext_zero) {
     // no external force or torque anywhere (all +0.0): nothing to read
     for (int k = 0; k < DIM; ++k) o.f[k] = 0.0;
@@ -413,6 +413,18 @@ __device__ inline void entry_load(const SweepArgs& a, int64_t e, EntryPre<DIM>& 
     for (int k = 0; k < DIM; ++k) o.f[k] = a.dpb[(q + k) * E + e];
     for (int k = 0; k < DR; ++k) o.t[k] = a.dpb[(q + DIM + k) * E + e];
   }
+}
+
+// EXT = false: the external force and torque are left for entry_ext (read
+// later, so that they do not occupy registers while the rest is in flight).
+template <int DIM, bool EXT = true>
+__device__ inline void entry_load(const SweepArgs& a, int64_t e, EntryPre<DIM>& o) {
+  constexpr int DR = Layout<DIM>::DR;
+  const int64_t E = a.dpe;
+  for (int k = 0; k < DIM; ++k) o.v[k] = a.dpb[k * E + e];
+  for (int k = 0; k < DR; ++k) o.w[k] = a.dpb[(DIM + k) * E + e];
+  int q = DIM + DR;
+  if (EXT) entry_ext<DIM>(a, e, o);
   q += DIM + DR;
   o.dm = a.dpb[q * E + e];
   o.di = a.dpb[(q + 1) * E + e];
@@ -628,23 +640,31 @@ __device__ inline void gather_lds(const SweepArgs& a, int64_t e, const EntryPre<
   }
 }
 
-// entry_finish with the exchange from LDS (gather_lds)
+// The entry's staged record from its base data and the summed forces
 template <int DIM>
-__device__ inline void entry_finish_lds(const SweepArgs& a, int64_t e, const EntryPre<DIM>& o,
-                                        double* sp, int l, const double* sl, int cs, int nct,
-                                        const double* hl, int nh, int hs) {
+__device__ inline void entry_write(const EntryPre<DIM>& o, const double* acc, const double* tacc,
+                                   double* sp, int l) {
   using L = Layout<DIM>;
   constexpr int DR = L::DR, PS = L::PS;
-  double acc[DIM], tacc[DR];
-  for (int k = 0; k < DIM; ++k) acc[k] = o.f[k];
-  for (int k = 0; k < DR; ++k) tacc[k] = o.t[k];
-  gather_lds<DIM>(a, e, o, sl, cs, nct, hl, nh, hs, acc, tacc);
   double* pr = sp + (int64_t)PS * l;
   for (int k = 0; k < DIM; ++k) pr[k] = o.v[k] + o.dm * acc[k];
   for (int k = 0; k < DR; ++k) pr[L::P_W + k] = o.w[k] + o.di * tacc[k];
   pr[L::P_DM] = o.dm;
   pr[L::P_DI] = o.di;
   pr[L::P_R] = o.r;
+}
+
+// entry_finish with the exchange from LDS (gather_lds)
+template <int DIM>
+__device__ inline void entry_finish_lds(const SweepArgs& a, int64_t e, const EntryPre<DIM>& o,
+                                        double* sp, int l, const double* sl, int cs, int nct,
+                                        const double* hl, int nh, int hs) {
+  constexpr int DR = Layout<DIM>::DR;
+  double acc[DIM], tacc[DR];
+  for (int k = 0; k < DIM; ++k) acc[k] = o.f[k];
+  for (int k = 0; k < DR; ++k) tacc[k] = o.t[k];
+  gather_lds<DIM>(a, e, o, sl, cs, nct, hl, nh, hs, acc, tacc);
+  entry_write<DIM>(o, acc, tacc, sp, l);
 }
 
 // Per-domain values a workgroup needs before its sweep: the descriptor
@@ -806,39 +826,46 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
   }
   SlotPre<DIM> cur;
   int kc = -1;
-  double* sl = lds + (int64_t)PS * np;
-  const bool mu_slot = a.mu_step != 0;
-  // foreign incidences staged after the slots (staged form with HALO)
-  double* hl = sl + (int64_t)slot_stage_doubles<DIM>(mu_slot) * nct;
+  // staged form with the foreign forces (HALO): when the domain's entries
+  // take one pass of the workgroup, the foreign forces share the LDS of the
+  // particle records (every thread gathers into registers and writes its
+  // record after a barrier); otherwise they follow the slots
   const int nh = HALO ? h.nh : 0;
+  const bool uni = HALO && np <= nthr && np <= kUnionMax;
+  constexpr int HW = cd_stage_halo(DIM);
+  const int64_t ua = (int64_t)PS * np > (int64_t)HW * nh ? (int64_t)PS * np : (int64_t)HW * nh;
+  double* sl = lds + (uni ? ua : (int64_t)PS * np);
+  const bool mu_slot = a.mu_step != 0;
+  double* hl = uni ? lds : sl + (int64_t)slot_stage_doubles<DIM>(mu_slot) * nct;
   if (STAGE && HALO) {
-    // 1. this thread's first two contacts, first particle entry and first
-    //    foreign incidence: every read is issued before any is used
-    //    (indices clamped to valid ones so that the loads are
-    //    unconditional); the contact data goes to LDS while the foreign
+    // 1. this thread's first contact, first particle entry (without its
+    //    external force) and first foreign incidence: every read is issued
+    //    before any is used (indices clamped to valid ones so that the loads
+    //    are unconditional); the contact data goes to LDS while the foreign
     //    incidences' forces are read, and those go to LDS as well, so that
     //    the exchange below reads nothing from memory
     {
-      const int k1 = tid, k2 = tid + nthr;
-      SlotPre<DIM> x, y;
-      EntryPre<DIM> ep;
       const int64_t s0 = nct > 0 ? cs : 0;
-      fetch_slot<DIM, false>(a, rin, s0 + (k1 < nct ? k1 : 0), x);
-      fetch_slot<DIM, false>(a, rin, s0 + (k2 < nct ? k2 : 0), y);
       const int64_t e1 = np > 0 ? ps + (tid < np ? tid : 0) : 0;
-      entry_load<DIM>(a, e1, ep);
-      const int hsl = nh > 0 ? a.halo[h.hs + (tid < nh ? tid : 0)] : 0;
-      if (k1 < nct) put_slot<DIM>(sl, nct, k1, x, mu_slot);
-      if (k2 < nct) put_slot<DIM>(sl, nct, k2, y, mu_slot);
+      EntryPre<DIM> ep;
+      int hsl = 0;
+      {
+        SlotPre<DIM> x;
+        fetch_slot<DIM, false>(a, rin, s0 + (tid < nct ? tid : 0), x);
+        entry_load<DIM, false>(a, e1, ep);
+        hsl = nh > 0 ? a.halo[h.hs + (tid < nh ? tid : 0)] : 0;
+        if (tid < nct) put_slot<DIM>(sl, nct, tid, x, mu_slot);
+      }
       HaloPre<DIM> hp;
       if (tid < nh) halo_load<DIM>(rin, hsl, hp);
       entry_row1<DIM>(a, e1, ep);
-      // the rest of the contacts (domains of more than two per thread)
-      for (int k = tid + 2 * nthr; k < nct; k += nthr) {
+      // the rest of the contacts (domains of more than one per thread)
+      for (int k = tid + nthr; k < nct; k += nthr) {
         SlotPre<DIM> z;
         fetch_slot<DIM, false>(a, rin, cs + k, z);
         put_slot<DIM>(sl, nct, k, z, mu_slot);
       }
+      entry_ext<DIM>(a, e1, ep);
       if (tid < nh) halo_put<DIM>(hp, hl, nh, tid);
       for (int q = tid + nthr; q < nh; q += nthr) {
         HaloPre<DIM> hq;
@@ -846,7 +873,19 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
         halo_put<DIM>(hq, hl, nh, q);
       }
       __syncthreads();
-      if (tid < np) entry_finish_lds<DIM>(a, e1, ep, sp, tid, sl, cs, nct, hl, nh, h.hs);
+      if (uni) {
+        constexpr int DR = Layout<DIM>::DR;
+        double acc[DIM], tacc[DR];
+        for (int k = 0; k < DIM; ++k) acc[k] = ep.f[k];
+        for (int k = 0; k < DR; ++k) tacc[k] = ep.t[k];
+        if (tid < np) gather_lds<DIM>(a, e1, ep, sl, cs, nct, hl, nh, h.hs, acc, tacc);
+        // every gather has read the foreign forces before the records
+        // overwrite them
+        __syncthreads();
+        if (tid < np) entry_write<DIM>(ep, acc, tacc, sp, tid);
+      } else if (tid < np) {
+        entry_finish_lds<DIM>(a, e1, ep, sp, tid, sl, cs, nct, hl, nh, h.hs);
+      }
     }
     for (int l = tid + nthr; l < np; l += nthr) {
       EntryPre<DIM> ep;
@@ -914,7 +953,8 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
   __syncthreads();
   if (RAND) {
     unsigned long long* key =
-        (unsigned long long*)(STAGE ? hl + (int64_t)cd_stage_halo(DIM) * nh
+        (unsigned long long*)(STAGE ? (uni ? sl + (int64_t)slot_stage_doubles<DIM>(mu_slot) * nct
+                                           : hl + (int64_t)cd_stage_halo(DIM) * nh)
                                     : (GLOB ? lds : lds + (int64_t)PS * np));
     int* perm = (int*)(key + nct);
     for (int k = tid; k < nct; k += nthr) key[k] = rand_mix(jkey ^ (unsigned long long)(cs + k));
