@@ -604,6 +604,8 @@ def main() -> int:
                     help="after the timed steps, solve one step from scratch with the "
                          "workload's domains and with one domain (2D workloads)")
     ap.add_argument("--sequential-max-iter", type=int, default=20000)
+    ap.add_argument("--domains", type=int, default=0,
+                    help="domain count of the workload (0: its own, or the tuner's where it tunes)")
     ap.add_argument("--tune-domains", type=int, default=1,
                     help="run the domain-count tuner (disks_262k uses its choice; spheres_1m "
                          "keeps the stated 16384 and reports the tuner's trials)")
@@ -700,7 +702,9 @@ def main() -> int:
         return 0
     pk = inputs.config(wl["config"])
     tuning = None
-    if args.tune_domains and wl.get("tune"):
+    if args.domains > 0:
+        wl = dict(wl, domains=args.domains)
+    elif args.tune_domains and wl.get("tune"):
         log(f"domain-count tuning on {args.workload} ...")
         tuning = tuned_domains(wl, pk, binding, wl["tune"])
         tuning["used"] = bool(wl["tune_use"])
