@@ -200,6 +200,9 @@ class Context:
             return
         self._bc = tuple(None if a is None else np.ascontiguousarray(a, dtype=np.float64)
                          for a in (im, wf))
+        for name, arr in zip(("wall_inv_mass", "wall_force"), self._bc):
+            if arr is not None and arr.shape != (self.W,):
+                raise ValueError(f"{name} needs one value per wall ({self.W})")
         ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
         self._check(self.L.cd_set_boundary(self.h, mask, ptr(self._bc[0]), ptr(self._bc[1])))
 

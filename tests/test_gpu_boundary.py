@@ -114,3 +114,8 @@ def test_boundary_refusals():
     c2 = binding.Context(binding.make_params(2, thin.n_walls), thin, timing=0)
     with pytest.raises(binding.CDError):
         c2.step()
+    # wall masses and forces need one value per wall
+    short = inputs.sheared_box_2d(16, 10, 89)
+    short.wall_inv_mass = short.wall_inv_mass[:1]
+    with pytest.raises(ValueError):
+        binding.Context(binding.make_params(2, short.n_walls), short, timing=0)
