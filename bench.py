@@ -39,6 +39,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import statistics
 import os
 import sys
 import time
@@ -111,8 +112,9 @@ def measured_traffic(path, n_domains=None):
     return rec.get("bytes_per_launch") if rec.get("kernel_sources_sha256") == h.hexdigest() else None
 
 
-def make_ctx(wl, pk, binding, timing=1, solve_mode=1, block=0, n_domains=None, max_iter=2000):
-    params = binding.make_params(wl["dim"], pk.n_walls, mu=wl["mu"], dt=1e-3, alpha=1e-6,
+def make_ctx(wl, pk, binding, timing=1, solve_mode=1, block=0, n_domains=None, max_iter=2000,
+             alpha=1e-6):
+    params = binding.make_params(wl["dim"], pk.n_walls, mu=wl["mu"], dt=1e-3, alpha=alpha,
                                  criterion=0, max_iter=max_iter,
                                  n_domains=wl["domains"] if n_domains is None else n_domains,
                                  repartition_every=10, warm_start=1)
@@ -180,6 +182,29 @@ def mixed_experiment(torch, binding, inputs, cap=3000, settle=50, seed=2023):
             "procedure": "one step from zero forces, one domain, alpha=1e-6, at most "
                          f"{cap} sweeps; parallel contacts by pair number (seed {seed})",
             "rows": rows, "p_c": min(failing) if failing else None}
+
+
+def strict_tolerance(wl, pk, torch, binding, steps):
+    """The same workload with alpha = 1e-12 instead of 1e-6: the tolerance
+    is applied to squared ratios (reading C12), so 1e-6 asks for about 1e-3
+    relative change per force and 1e-12 for about 1e-6; `steps` steps from
+    the initial state, timed as a whole."""
+    ctx = make_ctx(wl, pk, binding, timing=0, alpha=1e-12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweeps, capped, updates = [], 0, 0
+    for s in range(steps):
+        r = ctx.step()
+        sweeps.append(int(r.iterations))
+        capped += int(r.status == binding.MAXITER)
+        updates += r.iterations * r.n_contacts
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.close()
+    log(f"alpha 1e-12: sweeps per step {sweeps}")
+    return {"alpha": 1e-12, "steps": steps, "sweeps_per_step": sweeps,
+            "steps_at_sweep_cap": capped, "ms_per_step": 1e3 * el / steps,
+            "contact_updates_per_s": updates / el}
 
 
 def confined_pc_experiment(torch, binding, inputs, nx=40, steps=3000, dt=1e-2, pressure=1.0,
@@ -604,6 +629,8 @@ def main() -> int:
                     help="after the timed steps, solve one step from scratch with the "
                          "workload's domains and with one domain (2D workloads)")
     ap.add_argument("--sequential-max-iter", type=int, default=20000)
+    ap.add_argument("--strict-steps", type=int, default=5,
+                    help="steps of the workload at alpha = 1e-12 reported beside the line (0: none)")
     ap.add_argument("--domains", type=int, default=0,
                     help="domain count of the workload (0: its own, or the tuner's where it tunes)")
     ap.add_argument("--tune-domains", type=int, default=1,
@@ -721,6 +748,9 @@ def main() -> int:
         out["update_orders"] = order_experiment(torch, binding, inputs)
     if tuning is not None:
         out["domain_count_tuning"] = tuning
+    if args.strict_steps > 0:
+        log(f"{args.workload} at alpha 1e-12 ...")
+        out["strict_tolerance"] = strict_tolerance(wl, pk, torch, binding, args.strict_steps)
     ctx = out.pop("_ctx")
     if args.sequential and wl["dim"] == 2:
         out["sequential_comparison"] = sequential_comparison(wl, pk, ctx, torch, binding,
@@ -769,10 +799,14 @@ def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, 
     maxiter_steps = 0
     executed = 0
     timed = 0
+    step_ms, solve_ms_steps = [], []
     t0 = time.perf_counter()
     for s in range(steps):
         r = ctx.step()
         tm = ctx.timing()
+        # device time of the step's stages (events on the library's stream)
+        step_ms.append(tm.detect_ms + tm.partition_ms + tm.order_ms + tm.solve_ms + tm.update_ms)
+        solve_ms_steps.append(tm.solve_ms)
         sweeps += r.iterations
         updates += r.iterations * r.n_contacts
         sweep_kernel_ms += tm.sweep_kernel_ms
@@ -817,6 +851,8 @@ def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, 
         "sweeps_per_step": sweeps / steps,
         "steps_at_sweep_cap": maxiter_steps,
         "solve_ms_per_step": solve_ms / steps,
+        "median_step_ms": statistics.median(step_ms) if step_ms else None,
+        "median_solve_ms": statistics.median(solve_ms_steps) if solve_ms_steps else None,
         "solve_contact_updates_per_s": updates / (solve_ms / 1e3) if solve_ms > 0 else None,
         "sweep_kernel_us": 1e6 * avg_sweep_s if avg_sweep_s > 0 else None,
         "sweeps_executed": executed,
