@@ -544,9 +544,10 @@ int cd_set_particles(cd_ctx* c, const double* x, const double* v, const double* 
 int cd_set_external(cd_ctx* c, const double* force, const double* torque) {
   if (!c) return CD_EINVAL;
   const int64_t n = c->n;
-  // whether every component is +0.0 (then the sweeps need not read them)
-  bool zero = true;
-  for (int which = 0; which < 2 && zero; ++which) {
+  // whether every force, and every torque, is +0.0 (then the sweeps need not
+  // read that part)
+  bool zero[2] = {true, true};
+  for (int which = 0; which < 2; ++which) {
     const double* src = which == 0 ? force : torque;
     const int64_t count = (which == 0 ? c->dim : c->dr) * n;
     if (!src) continue;
@@ -556,11 +557,12 @@ int cd_set_external(cd_ctx* c, const double* force, const double* torque) {
     CD_TRY(hipStreamSynchronize(c->stream));
     for (int64_t k = 0; k < count; ++k)
       if (h[(size_t)k] != 0ull) {
-        zero = false;
+        zero[which] = false;
         break;
       }
   }
-  c->ext_zero = zero;
+  c->ext_fzero = zero[0];
+  c->ext_tzero = zero[1];
   if (force)
     CD_TRY(hipMemcpyAsync(c->f, force, sizeof(double) * c->dim * n, hipMemcpyDeviceToDevice,
                           c->stream));

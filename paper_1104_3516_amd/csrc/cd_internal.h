@@ -129,7 +129,8 @@ struct SweepArgs {
   const double* walls_u;    // W x dim wall velocities
   int n_walls;
   double* rec[2];
-  int ext_zero;             // every external force and torque is +0.0: not read
+  int ext_zero;             // bit 0: every external force is +0.0, bit 1: every
+                            // external torque is +0.0 (those are then not read)
   const double* mu_slot;    // friction of slot s at mu_slot[s * mu_step]
   int mu_step;              // 1: per slot; 0: one coefficient for all
   // convergence
@@ -292,7 +293,8 @@ struct cd_ctx {
   int2* slot_ab = nullptr;
   double* geo = nullptr;
   double* rec[2] = {nullptr, nullptr};
-  bool ext_zero = true;          // every external force and torque is +0.0
+  bool ext_fzero = true;         // every external force is +0.0
+  bool ext_tzero = true;         // every external torque is +0.0
   int *dcol = nullptr, *dncol = nullptr, *dp = nullptr, *dp_count = nullptr, *dp_start = nullptr;
   int *q_la = nullptr, *q_lb = nullptr, *q_col = nullptr, *q_pos = nullptr;
   unsigned long long* g_mask = nullptr;

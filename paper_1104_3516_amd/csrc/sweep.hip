@@ -514,7 +514,7 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.mobile = c->mobile_mask;
   a.rec[0] = c->rec[0];
   a.rec[1] = c->rec[1];
-  a.ext_zero = c->ext_zero ? 1 : 0;
+  a.ext_zero = (c->ext_fzero ? 1 : 0) | (c->ext_tzero ? 2 : 0);
   a.mu_slot = c->use_mu_slot ? c->mu_slot : c->d_wall + CD_WALL_MU;
   a.mu_step = c->use_mu_slot ? 1 : 0;
   a.state = c->d_state;

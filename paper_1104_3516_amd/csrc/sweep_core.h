@@ -398,19 +398,22 @@ struct EntryPre {
   int hb;      // list index of the first foreign incidence (staged form only)
 };
 
-// The entry's external force and torque (+0.0 without reading when every
-// one is zero).
+// The entry's external force and torque.  Forces and torques are flagged
+// apart (gravity comes without torques): a part that is +0.0 on every body
+// is set to +0.0 without reading, the same value the read would give.
 template <int DIM>
 __device__ inline void entry_ext(const SweepArgs& a, int64_t e, EntryPre<DIM>& o) {
   constexpr int DR = Layout<DIM>::DR;
   const int64_t E = a.dpe;
   const int q = DIM + DR;
-  if (a.ext_zero) {
-    // no external force or torque anywhere (all +0.0): nothing to read
+  if (a.ext_zero & 1) {
     for (int k = 0; k < DIM; ++k) o.f[k] = 0.0;
-    for (int k = 0; k < DR; ++k) o.t[k] = 0.0;
   } else {
     for (int k = 0; k < DIM; ++k) o.f[k] = a.dpb[(q + k) * E + e];
+  }
+  if (a.ext_zero & 2) {
+    for (int k = 0; k < DR; ++k) o.t[k] = 0.0;
+  } else {
     for (int k = 0; k < DR; ++k) o.t[k] = a.dpb[(q + DIM + k) * E + e];
   }
 }
