@@ -468,6 +468,7 @@ int cd_destroy(cd_ctx* c) {
   release(&c->drow);
   release(&c->ddesc);
   release(&c->halo);
+  release(&c->hpad);
   release(&c->hoff);
   release(&c->dhalo);
   release(&c->d_state);
@@ -858,6 +859,18 @@ int prep_phase2(cd_ctx* c) {
     // the foreign incidences are a subset of the entries' incidences
     CD_TRY(grow(&c->halo, cap));
     c->dinc_cap = cap;
+  }
+  {
+    // the foreign incidence slots once more at a fixed stride per domain, as
+    // many as a sweep workgroup's threads read with the domain's head
+    const int64_t stride = std::min<int64_t>(ds.max_halo, 256);
+    const int64_t need = stride * (int64_t)c->P;
+    if (need > c->hpad_cap || !c->hpad) {
+      const int64_t cap = need + need / 4 + 1024;
+      CD_TRY(grow(&c->hpad, cap));
+      c->hpad_cap = cap;
+    }
+    c->hstride = (int)stride;
   }
   CD_TRY(cd_launch_order_entries(c));
   // LDS staging per domain, 32-byte aligned; the static LDS of the sweep

@@ -123,6 +123,10 @@ struct SweepArgs {
   const int* halo;
   const int* hoff;
   const int2* dhalo;        // per domain: first list index, count
+  // the same slots domain by domain at a fixed stride (domain d's first
+  // min(count, hstride) of them at d * hstride): read with the head
+  const int* hpad;
+  int hstride;
   // slots
   const int2* ab;           // local body indices; b < 0: wall -1-b
   const double* geo;        // per-slot constants, SoA with stride cap
@@ -309,6 +313,9 @@ struct cd_ctx {
   int* halo = nullptr;           // foreign incidence slots (capacity dinc_cap)
   int* hoff = nullptr;           // 2 cap + 1: per entry, first foreign incidence
   int2* dhalo = nullptr;         // P: per domain, first foreign incidence and count
+  int* hpad = nullptr;           // P x hstride: each domain's first foreign incidence slots
+  int64_t hpad_cap = 0;
+  int hstride = 0;
   int sweep_block = 64;          // threads per domain workgroup
   int block_override = 0;        // 0: chosen from the domain sizes; -1: tuned
   int tune_next = 0;             // next candidate width to try (4: tuning over)

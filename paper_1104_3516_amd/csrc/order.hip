@@ -792,16 +792,22 @@ __global__ __launch_bounds__(kStats) void k_halo_dom(const int* dp_start, const 
 __global__ __launch_bounds__(kThreads) void k_halo_fill(const int* dp, const int* dp_start, int P,
                                                        int64_t E, const int* dom_start,
                                                        const int* inc_ptr, const int* inc,
-                                                       const int* hoff, int* halo) {
+                                                       const int* hoff, const int2* dhalo,
+                                                       int hstride, int* halo, int* hpad) {
   int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (e >= E || e >= dp_start[P]) return;
   const int d = entry_domain(dp_start, P, (int)e);
   const int cs = dom_start[d], ce = dom_start[d + 1];
   const int p = dp[e];
+  const int hs = dhalo[d].x;
   int o = hoff[e];
   for (int x = inc_ptr[p]; x < inc_ptr[p + 1]; ++x) {
     const int s = inc[x] >> 1;
-    if (s < cs || s >= ce) halo[o++] = s;
+    if (s < cs || s >= ce) {
+      // list index o is the domain's foreign incidence o - hs
+      if (o - hs < hstride) hpad[(int64_t)d * hstride + (o - hs)] = s;
+      halo[o++] = s;
+    }
   }
 }
 
@@ -1046,6 +1052,6 @@ hipError_t cd_launch_order_entries(cd_ctx* c) {
                      c->drow);
   hipLaunchKernelGGL(k_halo_fill, dim3(cd_blocks(E, kThreads)), dim3(kThreads), 0, c->stream,
                      c->dp, c->dp_start, c->P, E, c->dom_start, c->inc_ptr, c->inc, c->hoff,
-                     c->halo);
+                     c->dhalo, c->hstride, c->halo, c->hpad);
   return hipGetLastError();
 }

@@ -226,7 +226,7 @@ __device__ __attribute__((always_inline)) inline void sweep_block(const SweepArg
   // the domain's head is read together with the stop flag (one latency)
   const int d = domain_of(a, b, 0, a.grid / 8);
   DomainHead h{};
-  if (d >= 0) h = load_head<DIM>(a, d);
+  if (d >= 0) h = load_head<DIM, STAGE && HALO>(a, d);
   // the decision workgroup may set `done` during this launch: read it once
   if (threadIdx.x == 0) s_flag = *(volatile const int*)&a.state->done;
   __syncthreads();
@@ -534,6 +534,8 @@ SweepArgs cd_sweep_args(cd_ctx* c) {
   a.halo = c->halo;
   a.hoff = c->hoff;
   a.dhalo = c->dhalo;
+  a.hpad = c->hpad;
+  a.hstride = c->hstride;
   a.nc = c->nc;
   a.alpha = c->p.alpha;
   a.mu = c->p.mu;

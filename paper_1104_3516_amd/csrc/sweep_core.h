@@ -682,9 +682,13 @@ struct DomainHead {
   int hs, nh;   // the domain's foreign incidences: first list index, count
   int co;       // colour offset number threadIdx.x (threads 0..CD_MAX_COLORS)
   double wu;    // wall velocity component number threadIdx.x
+  int hsl;      // HSL: slot of foreign incidence number threadIdx.x (when
+                // threadIdx.x < hstride; meaningful below the count nh)
 };
 
-template <int DIM>
+// HSL: the domain's first foreign incidence slots too, so that their records
+// can be requested as soon as the head has arrived.
+template <int DIM, bool HSL = false>
 __device__ inline DomainHead load_head(const SweepArgs& a, int d) {
   DomainHead h;
   const int* dd = a.ddesc + 8 * (int64_t)d;
@@ -702,6 +706,7 @@ __device__ inline DomainHead load_head(const SweepArgs& a, int d) {
   // every colour offset of a domain is written (unused ones hold the count)
   h.co = tid <= CD_MAX_COLORS ? a.dcol[(int64_t)d * (CD_MAX_COLORS + 1) + tid] : 0;
   h.wu = tid < a.n_walls * DIM ? a.walls_u[tid] : 0.0;
+  h.hsl = HSL && tid < a.hstride ? a.hpad[(int64_t)d * a.hstride + tid] : 0;
   return h;
 }
 
@@ -851,16 +856,16 @@ __device__ inline void sweep_domain(const SweepArgs& a, int d, const DomainHead&
       const int64_t s0 = nct > 0 ? cs : 0;
       const int64_t e1 = np > 0 ? ps + (tid < np ? tid : 0) : 0;
       EntryPre<DIM> ep;
-      int hsl = 0;
+      // the foreign records first: their slots came with the head, so these
+      // reads are not a round after the others
+      HaloPre<DIM> hp;
+      if (tid < nh) halo_load<DIM>(rin, tid < a.hstride ? h.hsl : a.halo[h.hs + tid], hp);
       {
         SlotPre<DIM> x;
         fetch_slot<DIM, false>(a, rin, s0 + (tid < nct ? tid : 0), x);
         entry_load<DIM, false>(a, e1, ep);
-        hsl = nh > 0 ? a.halo[h.hs + (tid < nh ? tid : 0)] : 0;
         if (tid < nct) put_slot<DIM>(sl, nct, tid, x, mu_slot);
       }
-      HaloPre<DIM> hp;
-      if (tid < nh) halo_load<DIM>(rin, hsl, hp);
       entry_row1<DIM>(a, e1, ep);
       // the rest of the contacts (domains of more than one per thread)
       for (int k = tid + nthr; k < nct; k += nthr) {
