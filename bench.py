@@ -610,6 +610,9 @@ def main() -> int:
                     help="time sweep launches in event-bracketed groups of this size (0: none)")
     ap.add_argument("--block", type=int, default=0,
                     help="threads per domain workgroup (0: chosen from the domain sizes)")
+    ap.add_argument("--copy-mib", type=int, default=1024, metavar="MIB",
+                    help="size of the copy whose bandwidth the line reports beside the "
+                         "roofline (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), the reference "
                          "for scaling hardware byte counters, and exit")
@@ -758,12 +761,39 @@ def main() -> int:
     ctx.close()
     if args.workload == "spheres_1m" and args.extra:
         out["other_workloads"] = extra_workloads(args, torch, binding, inputs)
+    if args.copy_mib > 0:
+        out["copy_bandwidth"] = copy_bandwidth(torch, args.copy_mib)
     if args.cpu_sweeps > 0:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, pk, args.cpu_sweeps)
         out["cpu_parallel"] = cpu_parallel(wl, pk, args.cpu_sweeps)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def copy_bandwidth(torch, mib: int, reps: int = 10) -> dict:
+    """What the HBM gives a plain streaming kernel on this GPU: a
+    device-to-device copy of `mib` MiB, timed with events over `reps` copies
+    after two untimed ones (bytes read plus bytes written over the time),
+    beside the 8 TB/s peak the roofline fraction uses."""
+    n = mib * (1 << 20) // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    sec = t0.elapsed_time(t1) / 1e3
+    gbs = 2.0 * n * 8 * reps / sec / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GB/s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "bytes_per_copy": 2 * n * 8,
+            "copies": reps, "note": "device-to-device copy (torch copy_), read + written bytes"}
 
 
 def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, traffic_json,
