@@ -17,8 +17,16 @@ exact limit where the solution of the step is unique:
   count N_I(P)/N_I(1) of Sec. 4.3 is reported, and individual forces may
   differ by a few percent.
 
-The bounds were read off runs of the same cases; the domain-wise results
-themselves are pinned to the oracle elsewhere.
+The bounds of the benchmark-tolerance case were read off runs of the same
+cases, with margin; the domain-wise results themselves are pinned to the
+oracle elsewhere.  For scale: the local test stops when the last sweep
+changed each force by about sqrt(alpha) = 1e-3 relative, and a solve that
+needs N_I sweeps to go from order-one changes to that level shrinks them by
+about rho = sqrt(alpha)^(1/N_I) per sweep, so each solve may still be
+sqrt(alpha) rho / (1 - rho), about sqrt(alpha) N_I / ln(1/sqrt(alpha)) =
+0.04 relative (N_I = 270), from the converged forces; the 1e-3 and 1e-2
+bounds on the force-linear observables of two such solves are well inside
+what the tolerance allows.
 """
 import numpy as np
 import pytest
