@@ -110,3 +110,34 @@ def test_chain_sweeps_follow_the_diffusion_model():
         print(f"[chain P={P}] sweeps {run['it']} ratio {run['it'] / base:.3f} model {model:.3f}",
               flush=True)
         assert run["it"] / base == pytest.approx(model, rel=0.02)
+
+
+def test_sheared_box_observables_do_not_depend_on_the_decomposition():
+    """The paper's own setup (Sec. 4.1, 4.4): 48x32 disks periodic in x
+    between a bottom and a top wall of finite mass that press with 0.25 per
+    unit length and slide apart at 0.005.  At a tight tolerance one domain
+    and 16 domains give the same mean stress and sigma_yy strips to 1e-6
+    and the same wall velocities after the step (the pressure walls are
+    degrees of freedom of the solve, coupled to every wall contact)."""
+    from paper_1104_3516_amd import analysis, binding
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible ROCm GPU")
+    pk = inputs.sheared_box_2d(48, 32, 90, pressure=0.25, shear_velocity=0.005)
+    runs = {}
+    for P in (1, 16):
+        ctx = binding.Context(binding.make_params(2, pk.n_walls, mu=0.3, alpha=1e-18,
+                                                  max_iter=20000, n_domains=P), pk)
+        res = ctx.step()
+        runs[P] = dict(x=pk.x, c=analysis.host_contacts(ctx.contacts()),
+                       it=res.iterations, status=res.status, U=ctx.wall_velocities())
+        ctx.close()
+    ref, other = runs[1], runs[16]
+    assert ref["status"] == 0 and other["status"] == 0
+    d = _compare(pk, ref, other, "sheared box alpha=1e-18 P=16")
+    assert d["mean_stress"] <= 1e-6
+    assert d["strips"] <= 1e-6
+    # the lids' normal velocities from their contact forces, relative to the
+    # largest wall speed
+    scale = max(np.abs(ref["U"]).max(), 1e-300)
+    assert np.abs(other["U"] - ref["U"]).max() <= 1e-6 * scale
