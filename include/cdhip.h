@@ -242,6 +242,32 @@ int cd_get_contacts(cd_ctx* ctx, int64_t cap, int32_t* ci, int32_t* cj, double* 
  * id (-1 for inner nodes). */
 int cd_get_tree(cd_ctx* ctx, int32_t* axis, double* cut, int32_t* child, int32_t* leaf);
 
+/* Snapshots for checkpoint and resume.  A time step depends on the
+ * positions and velocities (Eq. 1), the walls' offsets and velocities, the
+ * step counter (tree rebuilds every repartition_every steps, Sec. 3.2; the
+ * random order's draws), the previous step's contact list and forces (the
+ * warm start) and the bisection tree the tree descent reuses (Sec. 3.2),
+ * plus the load-balancing capacities (Sec. 3.3) when set.  A snapshot holds
+ * exactly that, so that a context loaded from it steps bitwise as the one it
+ * was taken from would have.
+ *
+ * cd_snapshot_size: the bytes of a snapshot of the current state (host
+ * value).  cd_snapshot_save: writes it into the caller's HOST buffer of
+ * that many bytes (CD_EINVAL for another size).  cd_snapshot_load: restores
+ * one into a context created with the same parameters, particle count,
+ * walls and domain count, whose particles (radii, masses, inertia), box,
+ * boundary conditions and other settings the caller has set as in the
+ * original (the snapshot overwrites x, v, w, the walls' offsets and
+ * velocities, the box faces that follow walls, the step counter, the
+ * contact list and forces, the tree and the capacities).  Both run between
+ * steps only (CD_ENOTREADY after cd_prepare) and are refused with a kept
+ * contact list or the adjoint on (CD_EINVAL); a buffer that is not a
+ * snapshot of a matching context is CD_EINVAL.  No state changes on an
+ * error before the copies start. */
+int cd_snapshot_size(cd_ctx* ctx, int64_t* bytes);
+int cd_snapshot_save(cd_ctx* ctx, void* buf, int64_t bytes);
+int cd_snapshot_load(cd_ctx* ctx, const void* buf, int64_t bytes);
+
 /* every > 0: split sweep launches 2, 3, ... into consecutive groups of
  * `every` and bracket each group with one pair of HIP events;
  * cd_timing.sweep_kernel_ms is the mean launch duration over the complete

@@ -98,6 +98,9 @@ def lib():
         L.cd_num_contacts.restype = i64
         L.cd_get_contacts.argtypes = [P, i64, P, P, P, P, P, P, P, P]
         L.cd_get_tree.argtypes = [P, P, P, P, P]
+        L.cd_snapshot_size.argtypes = [P, C.POINTER(i64)]
+        L.cd_snapshot_save.argtypes = [P, P, i64]
+        L.cd_snapshot_load.argtypes = [P, P, i64]
         L.cd_get_timing.argtypes = [P, C.POINTER(Timing)]
         L.cd_status_string.argtypes = [C.c_int]
         L.cd_status_string.restype = C.c_char_p
@@ -317,6 +320,19 @@ class Context:
                                        child.ctypes.data_as(C.c_void_p),
                                        leaf.ctypes.data_as(C.c_void_p)))
         return dict(axis=axis, cut=cut, child=child, leaf=leaf)
+
+    def snapshot(self) -> bytes:
+        """The state the next step depends on, as bytes (cd_snapshot_save)."""
+        size = C.c_int64(0)
+        self._check(self.L.cd_snapshot_size(self.h, C.byref(size)))
+        buf = C.create_string_buffer(size.value)
+        self._check(self.L.cd_snapshot_save(self.h, C.cast(buf, C.c_void_p), size.value))
+        return buf.raw
+
+    def restore(self, snap: bytes) -> None:
+        """Loads a snapshot of a context set up as this one (cd_snapshot_load)."""
+        buf = C.create_string_buffer(bytes(snap), len(snap))
+        self._check(self.L.cd_snapshot_load(self.h, C.cast(buf, C.c_void_p), len(snap)))
 
     def timing(self) -> Timing:
         t = Timing()

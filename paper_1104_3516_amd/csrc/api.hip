@@ -1468,3 +1468,144 @@ int cd_get_timing(cd_ctx* c, cd_timing* out) {
 }
 
 }  // extern "C"
+
+// ---- snapshots: the state a step depends on, between steps
+namespace {
+
+struct SnapHeader {
+  char magic[8];
+  int32_t dim, W, P, flags;   // flags: 1 tree, 2 list of cd_solve_contacts, 4 capacities
+  int64_t n, nc, step;
+  double wo[CD_MAX_WALLS], wu[CD_MAX_WALLS * 3], lo[3], hi[3];
+};
+constexpr char kSnapMagic[8] = {'C', 'D', 'S', 'N', 'A', 'P', '1', 0};
+
+int64_t snap_bytes(const cd_ctx* c, int64_t nc, int flags) {
+  const int64_t n = c->n, nodes = 2 * (int64_t)c->P - 1;
+  int64_t b = (int64_t)sizeof(SnapHeader);
+  b += (int64_t)sizeof(double) * (2 * c->dim + c->dr) * n;               // x, v, w
+  b += (int64_t)(2 * sizeof(int) + sizeof(double) * c->dim) * nc;        // ci, cj, R
+  if (flags & 1) b += (int64_t)(sizeof(int) + sizeof(double)) * nodes;   // axis, cut
+  if (flags & 4) b += (int64_t)sizeof(double) * c->P;                    // capacities
+  return b;
+}
+
+int snap_flags(const cd_ctx* c) {
+  return (c->have_tree ? 1 : 0) | (c->list_solved ? 2 : 0) |
+         ((int64_t)c->lb_capacity.size() == c->P ? 4 : 0);
+}
+
+int snap_check_state(cd_ctx* c) {
+  if (c->prepared) return fail(c, CD_ENOTREADY, "snapshots are taken and loaded between steps");
+  if (c->frozen || c->adj_every > 0)
+    return fail(c, CD_EINVAL, "no snapshots with a kept contact list or the adjoint on");
+  return CD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cd_snapshot_size(cd_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return CD_EINVAL;
+  *bytes = snap_bytes(c, c->nc, snap_flags(c));
+  return CD_OK;
+}
+
+int cd_snapshot_save(cd_ctx* c, void* buf, int64_t bytes) {
+  if (!c || !buf) return CD_EINVAL;
+  int st = snap_check_state(c);
+  if (st != CD_OK) return st;
+  const int flags = snap_flags(c);
+  const int64_t n = c->n, nc = c->nc, nodes = 2 * (int64_t)c->P - 1;
+  if (bytes != snap_bytes(c, nc, flags)) return fail(c, CD_EINVAL, "snapshot buffer size");
+  SnapHeader hd{};
+  memcpy(hd.magic, kSnapMagic, sizeof(kSnapMagic));
+  hd.dim = c->dim;
+  hd.W = c->W;
+  hd.P = c->P;
+  hd.flags = flags;
+  hd.n = n;
+  hd.nc = nc;
+  hd.step = c->step;
+  memcpy(hd.wo, c->wo, sizeof(hd.wo));
+  memcpy(hd.wu, c->wu, sizeof(hd.wu));
+  memcpy(hd.lo, c->lo, sizeof(hd.lo));
+  memcpy(hd.hi, c->hi, sizeof(hd.hi));
+  char* p = (char*)buf;
+  memcpy(p, &hd, sizeof(hd));
+  p += sizeof(hd);
+  auto get = [&](const void* src, size_t nb) {
+    hipError_t e = nb ? hipMemcpyAsync(p, src, nb, hipMemcpyDeviceToHost, c->stream) : hipSuccess;
+    p += nb;
+    return e;
+  };
+  CD_TRY(get(c->x, sizeof(double) * c->dim * n));
+  CD_TRY(get(c->v, sizeof(double) * c->dim * n));
+  CD_TRY(get(c->w, sizeof(double) * c->dr * n));
+  CD_TRY(get(c->ci, sizeof(int) * nc));
+  CD_TRY(get(c->cj, sizeof(int) * nc));
+  CD_TRY(get(c->R, sizeof(double) * c->dim * nc));
+  if (flags & 1) {
+    CD_TRY(get(c->d_axis, sizeof(int) * nodes));
+    CD_TRY(get(c->d_cut, sizeof(double) * nodes));
+  }
+  CD_TRY(hipStreamSynchronize(c->stream));
+  if (flags & 4) memcpy(p, c->lb_capacity.data(), sizeof(double) * c->P);
+  return CD_OK;
+}
+
+int cd_snapshot_load(cd_ctx* c, const void* buf, int64_t bytes) {
+  if (!c || !buf) return CD_EINVAL;
+  int st = snap_check_state(c);
+  if (st != CD_OK) return st;
+  if (!c->have_particles || !c->have_box)
+    return fail(c, CD_ENOTREADY, "set the particles and the box before loading a snapshot");
+  SnapHeader hd;
+  if (bytes < (int64_t)sizeof(hd)) return fail(c, CD_EINVAL, "not a snapshot");
+  memcpy(&hd, buf, sizeof(hd));
+  if (memcmp(hd.magic, kSnapMagic, sizeof(kSnapMagic)) != 0)
+    return fail(c, CD_EINVAL, "not a snapshot");
+  if (hd.dim != c->dim || hd.W != c->W || hd.P != c->P || hd.n != c->n)
+    return fail(c, CD_EINVAL, "snapshot of a context with another dimension, wall, domain "
+                              "or particle count");
+  if (hd.nc < 0 || hd.step < 0 || bytes != snap_bytes(c, hd.nc, hd.flags))
+    return fail(c, CD_EINVAL, "snapshot size");
+  const int64_t n = c->n, nc = hd.nc, nodes = 2 * (int64_t)c->P - 1;
+  st = ensure_list(c, nc, &c->cap_list, &c->ci, &c->cj, &c->R);
+  if (st != CD_OK) return st;
+  const char* p = (const char*)buf + sizeof(hd);
+  auto put = [&](void* dst, size_t nb) {
+    hipError_t e = nb ? hipMemcpyAsync(dst, p, nb, hipMemcpyHostToDevice, c->stream) : hipSuccess;
+    p += nb;
+    return e;
+  };
+  CD_TRY(put(c->x, sizeof(double) * c->dim * n));
+  CD_TRY(put(c->v, sizeof(double) * c->dim * n));
+  CD_TRY(put(c->w, sizeof(double) * c->dr * n));
+  CD_TRY(put(c->ci, sizeof(int) * nc));
+  CD_TRY(put(c->cj, sizeof(int) * nc));
+  CD_TRY(put(c->R, sizeof(double) * c->dim * nc));
+  if (hd.flags & 1) {
+    CD_TRY(put(c->d_axis, sizeof(int) * nodes));
+    CD_TRY(put(c->d_cut, sizeof(double) * nodes));
+  }
+  CD_TRY(hipStreamSynchronize(c->stream));
+  if (hd.flags & 4) {
+    c->lb_capacity.assign((size_t)c->P, 0.0);
+    memcpy(c->lb_capacity.data(), p, sizeof(double) * c->P);
+  } else {
+    c->lb_capacity.clear();
+  }
+  c->nc = nc;
+  c->step = hd.step;
+  c->have_tree = (hd.flags & 1) != 0;
+  c->list_solved = (hd.flags & 2) != 0;
+  memcpy(c->wo, hd.wo, sizeof(hd.wo));
+  memcpy(c->wu, hd.wu, sizeof(hd.wu));
+  memcpy(c->lo, hd.lo, sizeof(hd.lo));
+  memcpy(c->hi, hd.hi, sizeof(hd.hi));
+  return upload_walls(c);
+}
+
+}  // extern "C"

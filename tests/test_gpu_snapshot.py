@@ -1,0 +1,88 @@
+"""Checkpoint and resume: a context loaded from a snapshot of another one
+steps bitwise as the other one does (the state a step depends on: positions,
+velocities, walls, step counter, previous contact list and forces for the
+warm start, bisection tree, Sec. 3.2)."""
+import numpy as np
+import pytest
+
+from paper_1104_3516_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _binding():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible ROCm GPU")
+    from paper_1104_3516_amd import binding
+    return binding
+
+
+def _ctx(binding, pk, **kw):
+    return binding.Context(binding.make_params(pk.dim, pk.n_walls, **kw), pk, timing=0)
+
+
+def _state(ctx):
+    x, v, w = (t.cpu().numpy() for t in ctx.state())
+    c = {k: t.cpu().numpy() for k, t in ctx.contacts().items()}
+    return dict(x=x, v=v, w=w, ci=c["ci"], cj=c["cj"], R=c["R"], dom=c["dom"],
+                off=ctx.wall_offsets(), U=ctx.wall_velocities())
+
+
+CASES = {
+    # periodic in x, pressure walls sliding apart (walls of finite mass)
+    "sheared_2d": (lambda: inputs.sheared_box_2d(24, 18, 91, pressure=0.25, shear_velocity=0.01),
+                   dict(mu=0.4, n_domains=7, repartition_every=3, max_iter=3000)),
+    # 3D, top wall driven down, staged sweeps with the foreign forces in LDS
+    "spheres_3d": (lambda: inputs.lattice_3d(16, 16, 12, 92, gravity=0.0, top_velocity=1e-3),
+                   dict(mu=0.5, n_domains=16, repartition_every=3)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_resumed_context_steps_bitwise(case):
+    binding = _binding()
+    make, kw = CASES[case]
+    pk = make()
+    a = _ctx(binding, pk, **kw)
+    b = _ctx(binding, pk, **kw)
+    for _ in range(3):
+        a.step()
+        b.step()
+    snap = b.snapshot()
+    b.close()
+    c = _ctx(binding, pk, **kw)
+    c.restore(snap)
+    # steps 3..6: a tree rebuild at 3 and 6, the tree descent at 4 and 5
+    for s in range(4):
+        ra, rc = a.step(), c.step()
+        assert (ra.iterations, ra.n_contacts, ra.status) == (rc.iterations, rc.n_contacts,
+                                                             rc.status), (case, s)
+        sa, sc = _state(a), _state(c)
+        for k in sa:
+            assert np.array_equal(sa[k], sc[k]), (case, s, k)
+    a.close()
+    c.close()
+
+
+def test_snapshot_refusals():
+    binding = _binding()
+    pk = inputs.lattice_2d(16, 16, 93)
+    a = _ctx(binding, pk, mu=0.3, n_domains=4)
+    a.step()
+    snap = a.snapshot()
+    # another domain count
+    other = _ctx(binding, pk, mu=0.3, n_domains=8)
+    with pytest.raises(binding.CDError):
+        other.restore(snap)
+    # not a snapshot, or cut short
+    with pytest.raises(binding.CDError):
+        a.restore(b"x" * len(snap))
+    with pytest.raises(binding.CDError):
+        a.restore(snap[:-8])
+    # between the phases of a step
+    a.prepare()
+    with pytest.raises(binding.CDError):
+        a.snapshot()
+    a.close()
+    other.close()
