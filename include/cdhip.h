@@ -49,7 +49,8 @@ enum {
   CD_ECAPACITY = -3,     /* a domain exceeds the per-domain limits (contacts, colours) */
   CD_ENONFINITE = -4,    /* non-finite input or force */
   CD_EHIP = -5,          /* HIP runtime error; cd_last_error() gives the detail */
-  CD_ENOTREADY = -6      /* particles not set yet */
+  CD_ENOTREADY = -6,     /* particles not set yet */
+  CD_ESHADOW = -7        /* the shadow run of a step differed from the first (cd_set_shadow) */
 };
 
 /* Solver parameters (host struct, copied at cd_create). */
@@ -267,6 +268,21 @@ int cd_get_tree(cd_ctx* ctx, int32_t* axis, double* cut, int32_t* child, int32_t
 int cd_snapshot_size(cd_ctx* ctx, int64_t* bytes);
 int cd_snapshot_save(cd_ctx* ctx, void* buf, int64_t bytes);
 int cd_snapshot_load(cd_ctx* ctx, const void* buf, int64_t bytes);
+
+/* Shadow mode, a check for nondeterminism (debugging; each step costs about
+ * twice as much).  mode 1: every cd_step takes a snapshot, steps, keeps the
+ * results (positions, velocities, contact list, forces, walls, sweep count
+ * and status), loads the snapshot, steps again and compares the two runs
+ * bitwise; a difference returns CD_ESHADOW with the first differing
+ * quantity in cd_last_error, else the second run's result.  The
+ * domain-wise solve is deterministic by construction (fixed-order
+ * reductions, no floating-point atomics), so any difference is a fault.
+ * mode 2 is the mode's own self-test: the second run starts with the first
+ * velocity component 1e-9 away from the snapshot's, which must be reported
+ * (the step's result is then the second run's).  mode 0 (the
+ * default) steps once.  Refused (CD_EINVAL) with a kept contact list or the
+ * adjoint on; cd_prepare / cd_solve and the batch step once regardless. */
+int cd_set_shadow(cd_ctx* ctx, int mode);
 
 /* every > 0: split sweep launches 2, 3, ... into consecutive groups of
  * `every` and bracket each group with one pair of HIP events;

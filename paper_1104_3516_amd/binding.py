@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcdhip.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "cdhip.h")
 
 OK, MAXITER, EINVAL, ENOMEM, ECAPACITY, ENONFINITE, EHIP, ENOTREADY = 0, 1, -1, -2, -3, -4, -5, -6
+ESHADOW = -7
 
 
 class Params(C.Structure):
@@ -113,6 +114,7 @@ def lib():
         L.cd_set_frozen_list.argtypes = [P, C.c_int]
         L.cd_set_mixed_update.argtypes = [P, C.c_double, C.c_ulonglong]
         L.cd_set_random_order.argtypes = [P, C.c_int, C.c_ulonglong]
+        L.cd_set_shadow.argtypes = [P, C.c_int]
         L.cd_set_load_balance.argtypes = [P, C.c_double]
         L.cd_set_domain_capacity.argtypes = [P, P]
         L.cd_get_domain_times.argtypes = [P, P, P]
@@ -386,6 +388,13 @@ class Context:
         """Mixed sequential/parallel update (Sec. 2.3): contacts with pair
         number below p are updated in parallel; p < 0 switches it off."""
         self._check(self.L.cd_set_mixed_update(self.h, float(p), int(seed)))
+
+    def set_shadow(self, mode: int = 1):
+        """Shadow mode (cd_set_shadow): 1 runs every step twice from a
+        snapshot and raises CDError(ESHADOW) if the runs differ; 2 is its
+        self-test (the second run starts 1e-9 away in one velocity); 0
+        steps once."""
+        self._check(self.L.cd_set_shadow(self.h, int(mode)))
 
     def set_random_order(self, on: bool = True, seed: int = 0):
         """Random sequential order (Sec. 2.1): every sweep, each domain's

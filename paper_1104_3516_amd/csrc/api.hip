@@ -307,6 +307,7 @@ const char* cd_status_string(int s) {
     case CD_ENONFINITE: return "non-finite value";
     case CD_EHIP: return "HIP runtime error";
     case CD_ENOTREADY: return "particles not set";
+    case CD_ESHADOW: return "shadow run differs";
     default: return "unknown status";
   }
 }
@@ -1304,13 +1305,262 @@ int cd_set_frozen_list(cd_ctx* c, int on) {
   return CD_OK;
 }
 
-int cd_step(cd_ctx* c, cd_result* out) {
+}  // extern "C"
+
+// ---- snapshots: the state a step depends on, between steps
+namespace {
+
+struct SnapHeader {
+  char magic[8];
+  int32_t dim, W, P, flags;   // flags: 1 tree, 2 list of cd_solve_contacts, 4 capacities
+  int64_t n, nc, step;
+  double wo[CD_MAX_WALLS], wu[CD_MAX_WALLS * 3], lo[3], hi[3];
+};
+constexpr char kSnapMagic[8] = {'C', 'D', 'S', 'N', 'A', 'P', '1', 0};
+
+int64_t snap_bytes(const cd_ctx* c, int64_t nc, int flags) {
+  const int64_t n = c->n, nodes = 2 * (int64_t)c->P - 1;
+  int64_t b = (int64_t)sizeof(SnapHeader);
+  b += (int64_t)sizeof(double) * (2 * c->dim + c->dr) * n;               // x, v, w
+  b += (int64_t)(2 * sizeof(int) + sizeof(double) * c->dim) * nc;        // ci, cj, R
+  if (flags & 1) b += (int64_t)(sizeof(int) + sizeof(double)) * nodes;   // axis, cut
+  if (flags & 4) b += (int64_t)sizeof(double) * c->P;                    // capacities
+  return b;
+}
+
+int snap_flags(const cd_ctx* c) {
+  return (c->have_tree ? 1 : 0) | (c->list_solved ? 2 : 0) |
+         ((int64_t)c->lb_capacity.size() == c->P ? 4 : 0);
+}
+
+int snap_check_state(cd_ctx* c) {
+  if (c->prepared) return fail(c, CD_ENOTREADY, "snapshots are taken and loaded between steps");
+  if (c->frozen || c->adj_every > 0)
+    return fail(c, CD_EINVAL, "no snapshots with a kept contact list or the adjoint on");
+  return CD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cd_snapshot_size(cd_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return CD_EINVAL;
+  *bytes = snap_bytes(c, c->nc, snap_flags(c));
+  return CD_OK;
+}
+
+int cd_snapshot_save(cd_ctx* c, void* buf, int64_t bytes) {
+  if (!c || !buf) return CD_EINVAL;
+  int st = snap_check_state(c);
+  if (st != CD_OK) return st;
+  const int flags = snap_flags(c);
+  const int64_t n = c->n, nc = c->nc, nodes = 2 * (int64_t)c->P - 1;
+  if (bytes != snap_bytes(c, nc, flags)) return fail(c, CD_EINVAL, "snapshot buffer size");
+  SnapHeader hd{};
+  memcpy(hd.magic, kSnapMagic, sizeof(kSnapMagic));
+  hd.dim = c->dim;
+  hd.W = c->W;
+  hd.P = c->P;
+  hd.flags = flags;
+  hd.n = n;
+  hd.nc = nc;
+  hd.step = c->step;
+  memcpy(hd.wo, c->wo, sizeof(hd.wo));
+  memcpy(hd.wu, c->wu, sizeof(hd.wu));
+  memcpy(hd.lo, c->lo, sizeof(hd.lo));
+  memcpy(hd.hi, c->hi, sizeof(hd.hi));
+  char* p = (char*)buf;
+  memcpy(p, &hd, sizeof(hd));
+  p += sizeof(hd);
+  auto get = [&](const void* src, size_t nb) {
+    hipError_t e = nb ? hipMemcpyAsync(p, src, nb, hipMemcpyDeviceToHost, c->stream) : hipSuccess;
+    p += nb;
+    return e;
+  };
+  CD_TRY(get(c->x, sizeof(double) * c->dim * n));
+  CD_TRY(get(c->v, sizeof(double) * c->dim * n));
+  CD_TRY(get(c->w, sizeof(double) * c->dr * n));
+  CD_TRY(get(c->ci, sizeof(int) * nc));
+  CD_TRY(get(c->cj, sizeof(int) * nc));
+  CD_TRY(get(c->R, sizeof(double) * c->dim * nc));
+  if (flags & 1) {
+    CD_TRY(get(c->d_axis, sizeof(int) * nodes));
+    CD_TRY(get(c->d_cut, sizeof(double) * nodes));
+  }
+  CD_TRY(hipStreamSynchronize(c->stream));
+  if (flags & 4) memcpy(p, c->lb_capacity.data(), sizeof(double) * c->P);
+  return CD_OK;
+}
+
+int cd_snapshot_load(cd_ctx* c, const void* buf, int64_t bytes) {
+  if (!c || !buf) return CD_EINVAL;
+  int st = snap_check_state(c);
+  if (st != CD_OK) return st;
+  if (!c->have_particles || !c->have_box)
+    return fail(c, CD_ENOTREADY, "set the particles and the box before loading a snapshot");
+  SnapHeader hd;
+  if (bytes < (int64_t)sizeof(hd)) return fail(c, CD_EINVAL, "not a snapshot");
+  memcpy(&hd, buf, sizeof(hd));
+  if (memcmp(hd.magic, kSnapMagic, sizeof(kSnapMagic)) != 0)
+    return fail(c, CD_EINVAL, "not a snapshot");
+  if (hd.dim != c->dim || hd.W != c->W || hd.P != c->P || hd.n != c->n)
+    return fail(c, CD_EINVAL, "snapshot of a context with another dimension, wall, domain "
+                              "or particle count");
+  if (hd.nc < 0 || hd.step < 0 || bytes != snap_bytes(c, hd.nc, hd.flags))
+    return fail(c, CD_EINVAL, "snapshot size");
+  const int64_t n = c->n, nc = hd.nc, nodes = 2 * (int64_t)c->P - 1;
+  st = ensure_list(c, nc, &c->cap_list, &c->ci, &c->cj, &c->R);
+  if (st != CD_OK) return st;
+  const char* p = (const char*)buf + sizeof(hd);
+  auto put = [&](void* dst, size_t nb) {
+    hipError_t e = nb ? hipMemcpyAsync(dst, p, nb, hipMemcpyHostToDevice, c->stream) : hipSuccess;
+    p += nb;
+    return e;
+  };
+  CD_TRY(put(c->x, sizeof(double) * c->dim * n));
+  CD_TRY(put(c->v, sizeof(double) * c->dim * n));
+  CD_TRY(put(c->w, sizeof(double) * c->dr * n));
+  CD_TRY(put(c->ci, sizeof(int) * nc));
+  CD_TRY(put(c->cj, sizeof(int) * nc));
+  CD_TRY(put(c->R, sizeof(double) * c->dim * nc));
+  if (hd.flags & 1) {
+    CD_TRY(put(c->d_axis, sizeof(int) * nodes));
+    CD_TRY(put(c->d_cut, sizeof(double) * nodes));
+  }
+  CD_TRY(hipStreamSynchronize(c->stream));
+  if (hd.flags & 4) {
+    c->lb_capacity.assign((size_t)c->P, 0.0);
+    memcpy(c->lb_capacity.data(), p, sizeof(double) * c->P);
+  } else {
+    c->lb_capacity.clear();
+  }
+  c->nc = nc;
+  c->step = hd.step;
+  c->have_tree = (hd.flags & 1) != 0;
+  c->list_solved = (hd.flags & 2) != 0;
+  memcpy(c->wo, hd.wo, sizeof(hd.wo));
+  memcpy(c->wu, hd.wu, sizeof(hd.wu));
+  memcpy(c->lo, hd.lo, sizeof(hd.lo));
+  memcpy(c->hi, hd.hi, sizeof(hd.hi));
+  return upload_walls(c);
+}
+
+
+}  // extern "C"
+
+static int plain_step(cd_ctx* c, cd_result* out) {
   int st = step_prepare(c);
   if (st != CD_OK) return st;
   c->prepared = false;
   st = solve_single(c);
   if (st != CD_OK) return st;
   return step_finish(c, out);
+}
+
+namespace {
+
+// The outputs of one step that the shadow run must reproduce.
+struct StepOut {
+  cd_result r{};
+  int64_t nc = 0;
+  std::vector<double> d;   // x, v, w, R
+  std::vector<int> ij;     // ci, cj
+  double wo[CD_MAX_WALLS], wu[CD_MAX_WALLS * 3];
+};
+
+int step_outputs(cd_ctx* c, const cd_result& r, StepOut& o) {
+  const int64_t n = c->n, nc = c->nc;
+  o.r = r;
+  o.nc = nc;
+  o.d.resize((size_t)((2 * c->dim + c->dr) * n + c->dim * nc));
+  o.ij.resize((size_t)(2 * nc));
+  double* p = o.d.data();
+  auto get = [&](double* dst, const double* src, int64_t k) {
+    return k ? hipMemcpyAsync(dst, src, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream)
+             : hipSuccess;
+  };
+  CD_TRY(get(p, c->x, c->dim * n));
+  CD_TRY(get(p + c->dim * n, c->v, c->dim * n));
+  CD_TRY(get(p + 2 * c->dim * n, c->w, c->dr * n));
+  CD_TRY(get(p + (2 * c->dim + c->dr) * n, c->R, c->dim * nc));
+  if (nc > 0) {
+    CD_TRY(hipMemcpyAsync(o.ij.data(), c->ci, sizeof(int) * nc, hipMemcpyDeviceToHost, c->stream));
+    CD_TRY(hipMemcpyAsync(o.ij.data() + nc, c->cj, sizeof(int) * nc, hipMemcpyDeviceToHost,
+                          c->stream));
+  }
+  CD_TRY(hipStreamSynchronize(c->stream));
+  memcpy(o.wo, c->wo, sizeof(o.wo));
+  memcpy(o.wu, c->wu, sizeof(o.wu));
+  return CD_OK;
+}
+
+// The first quantity in which two runs of a step differ, or null.
+const char* step_difference(const StepOut& a, const StepOut& b) {
+  if (a.r.status != b.r.status) return "status";
+  if (a.r.iterations != b.r.iterations) return "sweep count";
+  if (a.nc != b.nc || a.ij != b.ij) return "contact list";
+  const size_t nd = a.d.size();
+  if (b.d.size() != nd) return "sizes";
+  if (memcmp(a.d.data(), b.d.data(), sizeof(double) * nd) != 0) return "positions, velocities or forces";
+  if (memcmp(a.wo, b.wo, sizeof(a.wo)) != 0 || memcmp(a.wu, b.wu, sizeof(a.wu)) != 0) return "walls";
+  return nullptr;
+}
+
+int shadow_step(cd_ctx* c, cd_result* out) {
+  int64_t bytes = 0;
+  int st = cd_snapshot_size(c, &bytes);
+  if (st != CD_OK) return st;
+  std::vector<char> snap((size_t)bytes);
+  st = cd_snapshot_save(c, snap.data(), bytes);
+  if (st != CD_OK) return st;
+  cd_result r1{};
+  st = plain_step(c, &r1);
+  if (st < 0) return st;
+  StepOut first;
+  st = step_outputs(c, r1, first);
+  if (st != CD_OK) return st;
+  if (c->shadow == 2 && c->n > 0) {
+    // self-test: the first velocity component moved by 1e-9 (it follows the
+    // snapshot header and the positions), enough to survive the rounding of
+    // the step's updates
+    double v0;
+    char* at = snap.data() + sizeof(SnapHeader) + sizeof(double) * c->dim * c->n;
+    memcpy(&v0, at, sizeof(double));
+    v0 = v0 + 1e-9;
+    memcpy(at, &v0, sizeof(double));
+  }
+  st = cd_snapshot_load(c, snap.data(), bytes);
+  if (st != CD_OK) return st;
+  cd_result r2{};
+  const int st2 = plain_step(c, &r2);
+  if (st2 < 0) return st2;
+  StepOut second;
+  st = step_outputs(c, r2, second);
+  if (st != CD_OK) return st;
+  const char* diff = step_difference(first, second);
+  if (diff)
+    return fail(c, CD_ESHADOW, std::string("the shadow run of step ") +
+                                   std::to_string(c->step - 1) + " differs in its " + diff);
+  if (out) *out = r2;
+  return st2;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cd_set_shadow(cd_ctx* c, int mode) {
+  if (!c || mode < 0 || mode > 2) return CD_EINVAL;
+  if (mode && (c->frozen || c->adj_every > 0))
+    return fail(c, CD_EINVAL, "no shadow runs with a kept contact list or the adjoint on");
+  c->shadow = mode;
+  return CD_OK;
+}
+
+int cd_step(cd_ctx* c, cd_result* out) {
+  if (c && c->shadow) return shadow_step(c, out);
+  return plain_step(c, out);
 }
 
 int cd_solve_contacts(cd_ctx* c, int64_t n_c, const int32_t* ci, const int32_t* cj,
@@ -1469,143 +1719,3 @@ int cd_get_timing(cd_ctx* c, cd_timing* out) {
 
 }  // extern "C"
 
-// ---- snapshots: the state a step depends on, between steps
-namespace {
-
-struct SnapHeader {
-  char magic[8];
-  int32_t dim, W, P, flags;   // flags: 1 tree, 2 list of cd_solve_contacts, 4 capacities
-  int64_t n, nc, step;
-  double wo[CD_MAX_WALLS], wu[CD_MAX_WALLS * 3], lo[3], hi[3];
-};
-constexpr char kSnapMagic[8] = {'C', 'D', 'S', 'N', 'A', 'P', '1', 0};
-
-int64_t snap_bytes(const cd_ctx* c, int64_t nc, int flags) {
-  const int64_t n = c->n, nodes = 2 * (int64_t)c->P - 1;
-  int64_t b = (int64_t)sizeof(SnapHeader);
-  b += (int64_t)sizeof(double) * (2 * c->dim + c->dr) * n;               // x, v, w
-  b += (int64_t)(2 * sizeof(int) + sizeof(double) * c->dim) * nc;        // ci, cj, R
-  if (flags & 1) b += (int64_t)(sizeof(int) + sizeof(double)) * nodes;   // axis, cut
-  if (flags & 4) b += (int64_t)sizeof(double) * c->P;                    // capacities
-  return b;
-}
-
-int snap_flags(const cd_ctx* c) {
-  return (c->have_tree ? 1 : 0) | (c->list_solved ? 2 : 0) |
-         ((int64_t)c->lb_capacity.size() == c->P ? 4 : 0);
-}
-
-int snap_check_state(cd_ctx* c) {
-  if (c->prepared) return fail(c, CD_ENOTREADY, "snapshots are taken and loaded between steps");
-  if (c->frozen || c->adj_every > 0)
-    return fail(c, CD_EINVAL, "no snapshots with a kept contact list or the adjoint on");
-  return CD_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-int cd_snapshot_size(cd_ctx* c, int64_t* bytes) {
-  if (!c || !bytes) return CD_EINVAL;
-  *bytes = snap_bytes(c, c->nc, snap_flags(c));
-  return CD_OK;
-}
-
-int cd_snapshot_save(cd_ctx* c, void* buf, int64_t bytes) {
-  if (!c || !buf) return CD_EINVAL;
-  int st = snap_check_state(c);
-  if (st != CD_OK) return st;
-  const int flags = snap_flags(c);
-  const int64_t n = c->n, nc = c->nc, nodes = 2 * (int64_t)c->P - 1;
-  if (bytes != snap_bytes(c, nc, flags)) return fail(c, CD_EINVAL, "snapshot buffer size");
-  SnapHeader hd{};
-  memcpy(hd.magic, kSnapMagic, sizeof(kSnapMagic));
-  hd.dim = c->dim;
-  hd.W = c->W;
-  hd.P = c->P;
-  hd.flags = flags;
-  hd.n = n;
-  hd.nc = nc;
-  hd.step = c->step;
-  memcpy(hd.wo, c->wo, sizeof(hd.wo));
-  memcpy(hd.wu, c->wu, sizeof(hd.wu));
-  memcpy(hd.lo, c->lo, sizeof(hd.lo));
-  memcpy(hd.hi, c->hi, sizeof(hd.hi));
-  char* p = (char*)buf;
-  memcpy(p, &hd, sizeof(hd));
-  p += sizeof(hd);
-  auto get = [&](const void* src, size_t nb) {
-    hipError_t e = nb ? hipMemcpyAsync(p, src, nb, hipMemcpyDeviceToHost, c->stream) : hipSuccess;
-    p += nb;
-    return e;
-  };
-  CD_TRY(get(c->x, sizeof(double) * c->dim * n));
-  CD_TRY(get(c->v, sizeof(double) * c->dim * n));
-  CD_TRY(get(c->w, sizeof(double) * c->dr * n));
-  CD_TRY(get(c->ci, sizeof(int) * nc));
-  CD_TRY(get(c->cj, sizeof(int) * nc));
-  CD_TRY(get(c->R, sizeof(double) * c->dim * nc));
-  if (flags & 1) {
-    CD_TRY(get(c->d_axis, sizeof(int) * nodes));
-    CD_TRY(get(c->d_cut, sizeof(double) * nodes));
-  }
-  CD_TRY(hipStreamSynchronize(c->stream));
-  if (flags & 4) memcpy(p, c->lb_capacity.data(), sizeof(double) * c->P);
-  return CD_OK;
-}
-
-int cd_snapshot_load(cd_ctx* c, const void* buf, int64_t bytes) {
-  if (!c || !buf) return CD_EINVAL;
-  int st = snap_check_state(c);
-  if (st != CD_OK) return st;
-  if (!c->have_particles || !c->have_box)
-    return fail(c, CD_ENOTREADY, "set the particles and the box before loading a snapshot");
-  SnapHeader hd;
-  if (bytes < (int64_t)sizeof(hd)) return fail(c, CD_EINVAL, "not a snapshot");
-  memcpy(&hd, buf, sizeof(hd));
-  if (memcmp(hd.magic, kSnapMagic, sizeof(kSnapMagic)) != 0)
-    return fail(c, CD_EINVAL, "not a snapshot");
-  if (hd.dim != c->dim || hd.W != c->W || hd.P != c->P || hd.n != c->n)
-    return fail(c, CD_EINVAL, "snapshot of a context with another dimension, wall, domain "
-                              "or particle count");
-  if (hd.nc < 0 || hd.step < 0 || bytes != snap_bytes(c, hd.nc, hd.flags))
-    return fail(c, CD_EINVAL, "snapshot size");
-  const int64_t n = c->n, nc = hd.nc, nodes = 2 * (int64_t)c->P - 1;
-  st = ensure_list(c, nc, &c->cap_list, &c->ci, &c->cj, &c->R);
-  if (st != CD_OK) return st;
-  const char* p = (const char*)buf + sizeof(hd);
-  auto put = [&](void* dst, size_t nb) {
-    hipError_t e = nb ? hipMemcpyAsync(dst, p, nb, hipMemcpyHostToDevice, c->stream) : hipSuccess;
-    p += nb;
-    return e;
-  };
-  CD_TRY(put(c->x, sizeof(double) * c->dim * n));
-  CD_TRY(put(c->v, sizeof(double) * c->dim * n));
-  CD_TRY(put(c->w, sizeof(double) * c->dr * n));
-  CD_TRY(put(c->ci, sizeof(int) * nc));
-  CD_TRY(put(c->cj, sizeof(int) * nc));
-  CD_TRY(put(c->R, sizeof(double) * c->dim * nc));
-  if (hd.flags & 1) {
-    CD_TRY(put(c->d_axis, sizeof(int) * nodes));
-    CD_TRY(put(c->d_cut, sizeof(double) * nodes));
-  }
-  CD_TRY(hipStreamSynchronize(c->stream));
-  if (hd.flags & 4) {
-    c->lb_capacity.assign((size_t)c->P, 0.0);
-    memcpy(c->lb_capacity.data(), p, sizeof(double) * c->P);
-  } else {
-    c->lb_capacity.clear();
-  }
-  c->nc = nc;
-  c->step = hd.step;
-  c->have_tree = (hd.flags & 1) != 0;
-  c->list_solved = (hd.flags & 2) != 0;
-  memcpy(c->wo, hd.wo, sizeof(hd.wo));
-  memcpy(c->wu, hd.wu, sizeof(hd.wu));
-  memcpy(c->lo, hd.lo, sizeof(hd.lo));
-  memcpy(c->hi, hd.hi, sizeof(hd.hi));
-  return upload_walls(c);
-}
-
-}  // extern "C"

@@ -363,6 +363,7 @@ struct cd_ctx {
   // cd_solve_contacts: the caller's update order (device, during the call only)
   const int* given_order = nullptr;
   bool list_solved = false;    // the current list holds forces of cd_solve_contacts
+  int shadow = 0;              // cd_set_shadow mode
   unsigned long long* d_active = nullptr;   // closed contacts after the last solve
   // the current step, between its phases
   double st_skin = 0.0;

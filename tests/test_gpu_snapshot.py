@@ -86,3 +86,38 @@ def test_snapshot_refusals():
         a.snapshot()
     a.close()
     other.close()
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_shadow_mode_finds_the_step_deterministic(case):
+    """Shadow mode runs every step twice from a snapshot and compares the
+    runs bitwise; the results equal those of a context stepping once."""
+    binding = _binding()
+    make, kw = CASES[case]
+    pk = make()
+    a = _ctx(binding, pk, **kw)
+    s = _ctx(binding, pk, **kw)
+    s.set_shadow(1)
+    for step in range(4):
+        ra, rs = a.step(), s.step()
+        assert (ra.iterations, ra.n_contacts, ra.status) == (rs.iterations, rs.n_contacts,
+                                                             rs.status), (case, step)
+        sa, ss = _state(a), _state(s)
+        for k in sa:
+            assert np.array_equal(sa[k], ss[k]), (case, step, k)
+    a.close()
+    s.close()
+
+
+def test_shadow_mode_self_test_reports_a_difference():
+    """mode 2 starts the second run with one velocity 1e-9 away from the
+    snapshot's: the comparison must report it (the failure path, forced from
+    the host)."""
+    binding = _binding()
+    pk = inputs.lattice_2d(16, 16, 94)
+    s = _ctx(binding, pk, mu=0.3, n_domains=4)
+    s.set_shadow(2)
+    with pytest.raises(binding.CDError) as err:
+        s.step()
+    assert err.value.code == binding.ESHADOW
+    s.close()
