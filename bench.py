@@ -885,6 +885,9 @@ def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, 
         "median_solve_ms": statistics.median(solve_ms_steps) if solve_ms_steps else None,
         "solve_contact_updates_per_s": updates / (solve_ms / 1e3) if solve_ms > 0 else None,
         "sweep_kernel_us": 1e6 * avg_sweep_s if avg_sweep_s > 0 else None,
+        "contact_states_last_step": {"open": r.n_contacts - r.n_active,
+                                     "stick": r.n_active - r.n_sliding,
+                                     "slide": r.n_sliding},
         "sweeps_executed": executed,
         "sweeps_timed": timed,
         "solve_mode": args.solve_mode,

@@ -88,6 +88,10 @@ typedef struct cd_result {
   double rel_change_last;  /* relative change of the mean force in the last sweep, the
                               quantity of test (II): (dR_avg)^2 / (R_avg + R_avg_prev)^2
                               (0 when both are 0) */
+  int64_t n_sliding;     /* closed contacts at the Coulomb bound after the solve, sliding
+                            (Eqs. 8-9): 2D |R_t| = mu R_n, 3D |R_t|^2 >= (mu R_n)^2 (1 -
+                            1e-12); the other n_active - n_sliding stick, n_contacts -
+                            n_active are open */
 } cd_result;
 
 /* Time spent in each phase of the last step, milliseconds, from HIP events

@@ -34,7 +34,8 @@ class Result(C.Structure):
                 ("n_pass", C.c_int64), ("max_d_fail", C.c_double), ("r_avg", C.c_double),
                 ("r_avg_prev", C.c_double), ("skin", C.c_double), ("max_colors", C.c_int),
                 ("max_domain_contacts", C.c_int), ("n_active", C.c_int64),
-                ("crit_last", C.c_double), ("rel_change_last", C.c_double)]
+                ("crit_last", C.c_double), ("rel_change_last", C.c_double),
+                ("n_sliding", C.c_int64)]
 
 
 class Timing(C.Structure):

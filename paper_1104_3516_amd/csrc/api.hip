@@ -291,7 +291,7 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 static_assert(sizeof(GridBar) <= 512 && sizeof(DomainStats) <= 512 && 6 * sizeof(double) <= 512,
               "pinned scratch holds every small readback");
 static_assert(sizeof(GridBar) <= 8 * kWallSlot && sizeof(DomainStats) <= 8 * kWallSlot &&
-                  kWallSlot + CD_MAX_WALLS * 3 <= kActiveSlot,
+                  kWallSlot + CD_MAX_WALLS * 3 <= kSlideSlot && kSlideSlot + 1 == kActiveSlot,
               "the wall velocities and the active-contact count have slots of their own in "
               "the pinned scratch");
 
@@ -395,7 +395,7 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles,
     st = CD_EHIP;
   if (st == CD_OK && hipMalloc((void**)&c->d_vmax, sizeof(unsigned long long)) != hipSuccess)
     st = CD_ENOMEM;
-  if (st == CD_OK && hipMalloc((void**)&c->d_active, sizeof(unsigned long long)) != hipSuccess)
+  if (st == CD_OK && hipMalloc((void**)&c->d_active, 2 * sizeof(unsigned long long)) != hipSuccess)
     st = CD_ENOMEM;
   if (st == CD_OK && hipHostMalloc((void**)&c->h_state, sizeof(SolveState)) != hipSuccess)
     st = CD_ENOMEM;
@@ -1116,7 +1116,7 @@ int finish_enqueue(cd_ctx* c) {
   CD_TRY(cd_launch_update(c, s.iter));
   CD_TRY(hipEventRecord(c->ev[5], c->stream));
   CD_TRY(cd_launch_count_active(c, c->d_active));
-  CD_TRY(hipMemcpyAsync(c->h_scratch + kActiveSlot, c->d_active, sizeof(unsigned long long),
+  CD_TRY(hipMemcpyAsync(c->h_scratch + kSlideSlot, c->d_active, 2 * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, c->stream));
   if (c->mobile_mask) {
     // walls of finite mass: their velocity from the final forces
@@ -1157,6 +1157,7 @@ static int collect_result(cd_ctx* c, cd_result* out) {
   res.max_colors = ds.max_colors;
   res.max_domain_contacts = ds.max_contacts;
   res.n_active = nc > 0 ? (int64_t)c->h_scratch[kActiveSlot] : 0;
+  res.n_sliding = nc > 0 ? (int64_t)c->h_scratch[kSlideSlot] : 0;
   res.crit_last = nc > 0 ? (double)s.n_pass / (double)nc : 1.0;
   {
     const double dd = (s.r_avg - s.r_avg_prev) * (s.r_avg - s.r_avg_prev);
@@ -1640,7 +1641,7 @@ int cd_solve_contacts(cd_ctx* c, int64_t n_c, const int32_t* ci, const int32_t* 
   CD_TRY(cd_launch_unslot(c, s.iter));
   CD_TRY(hipEventRecord(c->ev[5], c->stream));
   CD_TRY(cd_launch_count_active(c, c->d_active));
-  CD_TRY(hipMemcpyAsync(c->h_scratch + kActiveSlot, c->d_active, sizeof(unsigned long long),
+  CD_TRY(hipMemcpyAsync(c->h_scratch + kSlideSlot, c->d_active, 2 * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, c->stream));
   if (n_c > 0)
     CD_TRY(hipMemcpyAsync(R_inout, c->R, sizeof(double) * c->dim * (size_t)n_c,

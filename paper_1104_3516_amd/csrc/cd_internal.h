@@ -364,7 +364,7 @@ struct cd_ctx {
   const int* given_order = nullptr;
   bool list_solved = false;    // the current list holds forces of cd_solve_contacts
   int shadow = 0;              // cd_set_shadow mode
-  unsigned long long* d_active = nullptr;   // closed contacts after the last solve
+  unsigned long long* d_active = nullptr;   // sliding, closed contacts after the last solve
   // the current step, between its phases
   double st_skin = 0.0;
   double st_wall_speed = 0.0;   // largest wall speed of the step (host)
@@ -496,8 +496,9 @@ __host__ __device__ constexpr int cd_stage_slot(int dim, bool mu_per_slot) {
 // and the torque factor (2D: R_t; 3D: n x R)
 __host__ __device__ constexpr int cd_stage_halo(int dim) { return dim == 2 ? 3 : 6; }
 
-// slot of the pinned 64-entry scratch (c->h_scratch) that receives the
-// active-contact count of a finished solve
+// slots of the pinned 64-entry scratch (c->h_scratch) that receive the
+// sliding and the closed (active) contact counts of a finished solve
+constexpr int kSlideSlot = 62;
 constexpr int kActiveSlot = 63;
 // domains of at most this many particle entries (and workgroups at least
 // this wide) stage the foreign incidences' forces in the LDS of their

@@ -78,20 +78,44 @@ __global__ __launch_bounds__(kThreads) void k_update(double* x, double* v, doubl
   for (int k = 0; k < DR; ++k) w[k * n + p] = w[k * n + p] + di * tacc[k];
 }
 
-// Contacts that carry a force after the solve (R_n > 0: closed contacts),
-// summed per block and added to *count.
-__global__ __launch_bounds__(kThreads) void k_count_active(const double* R, int64_t nc,
+// Contacts that carry a force after the solve (R_n > 0: closed contacts)
+// and those of them at the Coulomb bound (sliding, Eqs. 8-9: the projection
+// sets |R_t| to mu R_n, exactly in 2D and up to the rounding of the scaled
+// components in 3D), summed per block and added to count[1] and count[0].
+// mu_slot (per-slot friction of the solve) with contact_slot, or the shared
+// coefficient *mu.
+__global__ __launch_bounds__(kThreads) void k_count_active(int dim, const double* R, int64_t nc,
+                                                          const double* mu_slot,
+                                                          const int* contact_slot,
+                                                          const double* mu,
                                                           unsigned long long* count) {
-  __shared__ int part[kThreads / 64];
+  __shared__ int part[2][kThreads / 64];
   const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  int on = c < nc && R[c] > 0.0 ? 1 : 0;
-  for (int off = 32; off > 0; off >>= 1) on += __shfl_xor(on, off, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = on;
+  int on = 0, slide = 0;
+  if (c < nc && R[c] > 0.0) {
+    on = 1;
+    const double m = mu_slot ? mu_slot[contact_slot[c]] : *mu;
+    const double lim = m * R[c];
+    if (dim == 2) {
+      slide = fabs(R[nc + c]) == lim ? 1 : 0;
+    } else {
+      const double t1 = R[nc + c], t2 = R[2 * nc + c];
+      slide = t1 * t1 + t2 * t2 >= (lim * lim) * (1.0 - 1e-12) ? 1 : 0;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    on += __shfl_xor(on, off, 64);
+    slide += __shfl_xor(slide, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    part[0][threadIdx.x >> 6] = slide;
+    part[1][threadIdx.x >> 6] = on;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 2) {
     int s = 0;
-    for (int k = 0; k < kThreads / 64; ++k) s += part[k];
-    if (s) atomicAdd(count, (unsigned long long)s);
+    for (int k = 0; k < kThreads / 64; ++k) s += part[threadIdx.x][k];
+    if (s) atomicAdd(count + threadIdx.x, (unsigned long long)s);
   }
 }
 
@@ -146,10 +170,11 @@ hipError_t cd_launch_wall_velocities(cd_ctx* c) {
 }
 
 hipError_t cd_launch_count_active(cd_ctx* c, unsigned long long* count) {
-  hipError_t e = hipMemsetAsync(count, 0, sizeof(unsigned long long), c->stream);
+  hipError_t e = hipMemsetAsync(count, 0, 2 * sizeof(unsigned long long), c->stream);
   if (e != hipSuccess || c->nc == 0) return e;
   hipLaunchKernelGGL(k_count_active, dim3(cd_blocks(c->nc, kThreads)), dim3(kThreads), 0,
-                     c->stream, c->R, c->nc, count);
+                     c->stream, c->dim, c->R, c->nc, c->use_mu_slot ? c->mu_slot : nullptr,
+                     c->contact_slot, c->d_wall + CD_WALL_MU, count);
   return hipGetLastError();
 }
 

@@ -51,6 +51,20 @@ def margin_tiny(info, alpha):
     return abs(info.max_d_fail - thr) <= 1e-9 * thr
 
 
+def contact_states(R, mu):
+    """Closed contacts (R_n > 0) and those of them at the Coulomb bound
+    (Eqs. 8-9; 2D: |R_t| = mu R_n exactly as the projection sets it, 3D: up
+    to the rounding of its scaled components) of a canonical force array."""
+    R = np.asarray(R)
+    closed = R[0] > 0.0
+    lim = mu * R[0]
+    if R.shape[0] == 2:
+        slide = closed & (np.abs(R[1]) == lim)
+    else:
+        slide = closed & (R[1] * R[1] + R[2] * R[2] >= (lim * lim) * (1.0 - 1e-12))
+    return int(closed.sum()), int(slide.sum())
+
+
 def compare_step(sim, ctx, label, alpha=1e-6, check_tree=True):
     io = sim.step()
     ig = ctx.step()
@@ -87,6 +101,13 @@ def compare_results(sim, ctx, io, ig, label, alpha=1e-6, check_tree=True):
     nbit = int((cg["R"] != co["R"]).sum())
     print(f"[{label}] max rel |dR| = {err:.3e}  non-identical entries: {nbit}", flush=True)
     assert err <= RTOL
+    # closed and sliding counts: the library's against the same rule on its
+    # own forces, and on the oracle's when those are bit-identical
+    if cg["R"].size:
+        mu = ctx.params.mu
+        assert (ig.n_active, ig.n_sliding) == contact_states(cg["R"], mu)
+        if nbit == 0:
+            assert (ig.n_active, ig.n_sliding) == contact_states(co["R"], mu)
     xo, vo, wo, wallo = sim.state()
     xg, vg, wg = (t.cpu().numpy() for t in ctx.state())
     assert close_rel(vg, vo) <= RTOL
