@@ -1411,6 +1411,20 @@ int cd_snapshot_load(cd_ctx* c, const void* buf, int64_t bytes) {
   if (hd.nc < 0 || hd.step < 0 || bytes != snap_bytes(c, hd.nc, hd.flags))
     return fail(c, CD_EINVAL, "snapshot size");
   const int64_t n = c->n, nc = hd.nc, nodes = 2 * (int64_t)c->P - 1;
+  if (hd.flags & 1) {
+    // the tree descent indexes positions by the split axes: each inner node's
+    // axis must be a coordinate (leaves carry -1)
+    const char* ax = (const char*)buf + sizeof(hd) +
+                     sizeof(double) * (2 * c->dim + c->dr) * n +
+                     (2 * sizeof(int) + sizeof(double) * c->dim) * nc;
+    for (int64_t k = 0; k < nodes; ++k) {
+      int a;
+      memcpy(&a, ax + sizeof(int) * k, sizeof(int));
+      const bool inner = c->t_leaf[(size_t)k] < 0;
+      if (inner ? (a < 0 || a >= c->dim) : a != -1)
+        return fail(c, CD_EINVAL, "snapshot tree with an invalid split axis");
+    }
+  }
   st = ensure_list(c, nc, &c->cap_list, &c->ci, &c->cj, &c->R);
   if (st != CD_OK) return st;
   const char* p = (const char*)buf + sizeof(hd);

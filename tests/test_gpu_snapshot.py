@@ -80,6 +80,15 @@ def test_snapshot_refusals():
         a.restore(b"x" * len(snap))
     with pytest.raises(binding.CDError):
         a.restore(snap[:-8])
+    # a split axis that is no coordinate (the root's, the first of the 2P-1
+    # axes that precede the cuts at the end of the snapshot)
+    nodes = 2 * 4 - 1
+    bad = bytearray(snap)
+    at = len(bad) - 12 * nodes
+    bad[at:at + 4] = (7).to_bytes(4, "little", signed=True)
+    with pytest.raises(binding.CDError) as err:
+        a.restore(bytes(bad))
+    assert err.value.code == binding.EINVAL
     # between the phases of a step
     a.prepare()
     with pytest.raises(binding.CDError):
