@@ -264,7 +264,9 @@ int cd_get_tree(cd_ctx* ctx, int32_t* axis, double* cut, int32_t* child, int32_t
  * boundary conditions and other settings the caller has set as in the
  * original (the snapshot overwrites x, v, w, the walls' offsets and
  * velocities, the box faces that follow walls, the step counter, the
- * contact list and forces, the tree and the capacities).  Both run between
+ * contact list and forces, the tree and the capacities; until the next
+ * step, cd_get_contacts returns CD_ENOTREADY, the contacts' geometry,
+ * domains and colours being rebuilt by that step).  Both run between
  * steps only (CD_ENOTREADY after cd_prepare) and are refused with a kept
  * contact list or the adjoint on (CD_EINVAL); a buffer that is not a
  * snapshot of a matching context is CD_EINVAL.  No state changes on an

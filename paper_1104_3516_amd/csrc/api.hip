@@ -540,6 +540,7 @@ int cd_set_particles(cd_ctx* c, const double* x, const double* v, const double* 
   c->step = 0;
   c->nc_prev = 0;
   c->list_solved = false;
+  c->restored = false;
   return CD_OK;
 }
 
@@ -812,6 +813,7 @@ int prep_phase1(cd_ctx* c) {
   if (!(skin <= 0.2 * c->rmax))
     return fail(c, CD_EINVAL, "boundary width exceeds 0.2 r_max (displacement bound)");
   // ---- the previous step's list becomes the warm-start source
+  c->restored = false;
   std::swap(c->ci, c->ci_prev);
   std::swap(c->cj, c->cj_prev);
   std::swap(c->R, c->R_prev);
@@ -1426,6 +1428,7 @@ int cd_snapshot_load(cd_ctx* c, const void* buf, int64_t bytes) {
     }
   }
   st = ensure_list(c, nc, &c->cap_list, &c->ci, &c->cj, &c->R);
+  if (st == CD_OK) st = ensure_capacity(c, nc);
   if (st != CD_OK) return st;
   const char* p = (const char*)buf + sizeof(hd);
   auto put = [&](void* dst, size_t nb) {
@@ -1451,6 +1454,7 @@ int cd_snapshot_load(cd_ctx* c, const void* buf, int64_t bytes) {
     c->lb_capacity.clear();
   }
   c->nc = nc;
+  c->restored = true;
   c->step = hd.step;
   c->have_tree = (hd.flags & 1) != 0;
   c->list_solved = (hd.flags & 2) != 0;
@@ -1600,6 +1604,7 @@ int cd_solve_contacts(cd_ctx* c, int64_t n_c, const int32_t* ci, const int32_t* 
   st = ensure_list(c, n_c, &c->cap_list, &c->ci, &c->cj, &c->R);
   if (st != CD_OK) return st;
   c->nc = n_c;
+  c->restored = false;
   c->st_skin = 0.0;
   if (n_c > 0) {
     CD_TRY(hipMemcpyAsync(c->ci, ci, sizeof(int) * (size_t)n_c, hipMemcpyDeviceToDevice, c->stream));
@@ -1692,6 +1697,9 @@ int64_t cd_num_contacts(const cd_ctx* c) { return c ? c->nc : 0; }
 int cd_get_contacts(cd_ctx* c, int64_t cap, int32_t* ci, int32_t* cj, double* normal, double* gap,
                     double* R, int32_t* dom, int32_t* color, int32_t* slot_contact) {
   if (!c) return CD_EINVAL;
+  if (c->restored)
+    return fail(c, CD_ENOTREADY, "a loaded snapshot holds the warm-start list only: the "
+                                 "contacts' data comes with the next step");
   const int64_t nc = c->nc;
   if (cap < nc) return fail(c, CD_EINVAL, "output capacity below the contact count");
   if (nc == 0) return CD_OK;

@@ -364,6 +364,7 @@ struct cd_ctx {
   const int* given_order = nullptr;
   bool list_solved = false;    // the current list holds forces of cd_solve_contacts
   int shadow = 0;              // cd_set_shadow mode
+  bool restored = false;       // the list came from a snapshot: only ci, cj, R are its own
   unsigned long long* d_active = nullptr;   // sliding, closed contacts after the last solve
   // the current step, between its phases
   double st_skin = 0.0;

@@ -53,6 +53,10 @@ def test_resumed_context_steps_bitwise(case):
     b.close()
     c = _ctx(binding, pk, **kw)
     c.restore(snap)
+    # the list's geometry comes with the next step
+    with pytest.raises(binding.CDError) as err:
+        c.contacts()
+    assert err.value.code == binding.ENOTREADY
     # steps 3..6: a tree rebuild at 3 and 6, the tree descent at 4 and 5
     for s in range(4):
         ra, rc = a.step(), c.step()
