@@ -269,8 +269,8 @@ int cd_get_tree(cd_ctx* ctx, int32_t* axis, double* cut, int32_t* child, int32_t
  * domains and colours being rebuilt by that step).  Both run between
  * steps only (CD_ENOTREADY after cd_prepare) and are refused with a kept
  * contact list or the adjoint on (CD_EINVAL); a buffer that is not a
- * snapshot of a matching context is CD_EINVAL.  No state changes on an
- * error before the copies start. */
+ * snapshot of a matching context (header, size, split axes) is refused with
+ * CD_EINVAL before anything changes. */
 int cd_snapshot_size(cd_ctx* ctx, int64_t* bytes);
 int cd_snapshot_save(cd_ctx* ctx, void* buf, int64_t bytes);
 int cd_snapshot_load(cd_ctx* ctx, const void* buf, int64_t bytes);
