@@ -179,3 +179,22 @@ def test_chain_order_needing_many_colours_is_refused(oracle):
     with pytest.raises(binding.CDError) as e:
         ctx.solve_contacts(ci, cj, dom=np.zeros(nc, np.int32), order=order)
     assert e.value.code == binding.ECAPACITY
+
+
+def test_particle_in_more_than_32_domains_is_refused():
+    """A particle whose contacts lie in more than 32 domains (the per-particle
+    entry limit) is CD_ECAPACITY before any sweep: a star of 40 contacts
+    around particle 0, each in a domain of its own.  The context stays
+    usable."""
+    from paper_1104_3516_amd import binding
+    _torch()
+    pk = inputs.lattice_2d(8, 6, 95)
+    ci = np.zeros(40, np.int32)
+    cj = np.arange(1, 41, dtype=np.int32)
+    ctx = gpu_ctx(pk, 40)
+    with pytest.raises(binding.CDError) as e:
+        ctx.solve_contacts(ci, cj, dom=np.arange(40, dtype=np.int32))
+    assert e.value.code == binding.ECAPACITY
+    assert "32 domains" in str(e.value)
+    res = ctx.solve_contacts(ci, cj, dom=np.zeros(40, np.int32))
+    assert res.n_contacts == 40 and res.status in (binding.OK, binding.MAXITER)
