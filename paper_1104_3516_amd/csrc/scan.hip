@@ -1,5 +1,7 @@
 // scan.hip - exclusive prefix sum of nonnegative int32 counts (out has n+1
-// entries, out[n] = total), in one launch.
+// entries, out[n] = total), in one launch: the single-pass scan with
+// decoupled look-back of Merrill and Garland (NVIDIA technical report
+// NVR-2016-002), written here for 64-wide wavefronts.
 //
 // Tiles of kTile counts are scanned in the order of a ticket taken from a
 // device counter (not blockIdx), so every tile that a tile waits on has
@@ -17,7 +19,7 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 8;
+constexpr int kItems = 32;
 constexpr int kTile = kThreads * kItems;
 constexpr unsigned long long kPrefixBit = 1ull << 31;
 constexpr unsigned long long kValueMask = kPrefixBit - 1;
@@ -113,12 +115,29 @@ __global__ __launch_bounds__(kThreads) void k_scan(const int* in, int* out, int6
   __syncthreads();
   const int t = s_tile;
   const int64_t base = (int64_t)t * kTile + (int64_t)threadIdx.x * kItems;
+  // a thread's items are consecutive: 16-byte loads where they lie
+  // wholly inside the input and it is 16-byte aligned (a tile's first
+  // item is, whenever the input is), else one by one
+  const bool vec = ((uintptr_t)in & 15) == 0 && ((uintptr_t)out & 15) == 0 &&
+                   base + kItems <= n;
   int vals[kItems];
   int s = 0;
-  for (int k = 0; k < kItems; ++k) {
-    const int64_t i = base + k;
-    vals[k] = i < n ? in[i] : 0;
-    s += vals[k];
+  if (vec) {
+    static_assert(kItems % 4 == 0, "whole int4 per thread");
+    for (int q = 0; q < kItems / 4; ++q) {
+      const int4 a = *(const int4*)(in + base + 4 * q);
+      vals[4 * q] = a.x;
+      vals[4 * q + 1] = a.y;
+      vals[4 * q + 2] = a.z;
+      vals[4 * q + 3] = a.w;
+    }
+    for (int k = 0; k < kItems; ++k) s += vals[k];
+  } else {
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t i = base + k;
+      vals[k] = i < n ? in[i] : 0;
+      s += vals[k];
+    }
   }
   int total;
   const int inc = block_inclusive_scan(s, sh, &total);
@@ -137,10 +156,20 @@ __global__ __launch_bounds__(kThreads) void k_scan(const int* in, int* out, int6
   __syncthreads();
   const int excl = s_excl;
   int run = excl + inc - s;
-  for (int k = 0; k < kItems; ++k) {
-    const int64_t i = base + k;
-    if (i < n) out[i] = run;
-    run += vals[k];
+  if (vec) {
+    int o[kItems];
+    for (int k = 0; k < kItems; ++k) {
+      o[k] = run;
+      run += vals[k];
+    }
+    for (int q = 0; q < kItems / 4; ++q)
+      *(int4*)(out + base + 4 * q) = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+  } else {
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t i = base + k;
+      if (i < n) out[i] = run;
+      run += vals[k];
+    }
   }
   if (t == nb - 1 && threadIdx.x == 0) out[n] = excl + total;
 }
