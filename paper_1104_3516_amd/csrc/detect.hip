@@ -98,11 +98,10 @@ __global__ __launch_bounds__(kThreads) void k_cell_scatter(int64_t n, const int*
   members[cell_start[cell] + pos] = (int)i;
 }
 
-// gap of particles i < j: |x_j - x_i| - r_i - r_j (Sec. 2.1, Fig. 1), at
-// the nearest image along periodic axes
+// squared distance of particles i < j at the nearest image along periodic
+// axes; their gap (Sec. 2.1, Fig. 1) is its square root minus both radii
 template <int DIM>
-__device__ inline double pair_gap(const double* x, const double* r, int64_t n, int i, int j,
-                                  const CellGrid& g) {
+__device__ inline double pair_dist2(const double* x, int64_t n, int i, int j, const CellGrid& g) {
   double d0 = x[j] - x[i];
   if (g.period[0] > 0.0) d0 = min_image(d0, g.period[0]);
   double d1 = x[n + j] - x[n + i];
@@ -114,9 +113,9 @@ __device__ inline double pair_gap(const double* x, const double* r, int64_t n, i
     if (g.period[2] > 0.0) e = min_image(e, g.period[2]);
     d2 = d2 + e * e;
   }
-  double dist = sqrt(d2);
-  return (dist - r[i]) - r[j];
+  return d2;
 }
+
 
 // gap of particle i and wall w: (nu.x - o) - r_i
 template <int DIM>
@@ -153,6 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs(const double* x, const doubl
   if (ii >= n) return;
   const double skin = skin_of(sk);
   int i = (int)ii;
+  const double ri = r[i];
   int cell = cell_of[i];
   int cx = cell % g.ncell[0];
   int cy = (cell / g.ncell[0]) % g.ncell[1];
@@ -177,7 +177,13 @@ __global__ __launch_bounds__(kThreads) void k_pairs(const double* x, const doubl
         for (int s = cell_start[q]; s < cell_start[q + 1]; ++s) {
           int j = members[s];
           if (j <= i) continue;
-          if (pair_gap<DIM>(x, r, n, i, j, g) <= skin) {
+          // a pair whose squared distance exceeds (r_i + r_j + skin)^2 by a
+          // relative margin of 2e-9 cannot pass the test below, whatever the
+          // rounding (its errors are some 1e-15 relative): no square root
+          const double d2 = pair_dist2<DIM>(x, n, i, j, g);
+          const double reach = ((ri + r[j]) + skin) * (1.0 + 1e-9);
+          if (d2 > reach * reach) continue;
+          if ((sqrt(d2) - ri) - r[j] <= skin) {
             if (FILL) {
               // insertion into the particle's sorted range
               int pos = k;
