@@ -493,7 +493,9 @@ typedef struct cd_batch_timing {
 /* ctxs: `count` contexts (host array of handles), all of one dimension, on
  * one device and one stream; the batch keeps the handles (the caller keeps
  * ownership and must not destroy a context while the batch lives) and uses
- * their stream.  CD_EINVAL for mismatched contexts. */
+ * their stream.  While it belongs to a batch a context records no events
+ * around its phases (cd_get_timing's phase times read 0; the batch times
+ * its phases in cd_batch_timing).  CD_EINVAL for mismatched contexts. */
 int cd_batch_create(cd_batch** out, cd_ctx* const* ctxs, int count);
 int cd_batch_destroy(cd_batch* batch);
 

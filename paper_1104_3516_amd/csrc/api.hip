@@ -755,15 +755,15 @@ int prep_phase0(cd_ctx* c) {
     int st = cd_window_begin(c);
     if (st != CD_OK) return st;
   }
-  CD_TRY(hipEventRecord(c->ev[0], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[0], c->stream));
   if (c->frozen_now) {
     // the kept list: its geometry at the new positions, slot constants, the
     // previous step's forces as warm start, the new base velocities
     CD_TRY(cd_launch_geometry(c));
-    CD_TRY(hipEventRecord(c->ev[1], c->stream));
-    CD_TRY(hipEventRecord(c->ev[2], c->stream));
+    if (c->phase_events) CD_TRY(hipEventRecord(c->ev[1], c->stream));
+    if (c->phase_events) CD_TRY(hipEventRecord(c->ev[2], c->stream));
     CD_TRY(cd_launch_frozen_refresh(c));
-    CD_TRY(hipEventRecord(c->ev[3], c->stream));
+    if (c->phase_events) CD_TRY(hipEventRecord(c->ev[3], c->stream));
     c->st_limit = c->p.fixed_iters > 0 ? c->p.fixed_iters : c->p.max_iter;
     CD_TRY(cd_launch_solve_init(c, c->st_limit));
     c->run = SolveRun{};
@@ -829,7 +829,7 @@ int prep_phase1(cd_ctx* c) {
   CD_TRY(cd_launch_pair_fill(c));
   CD_TRY(cd_launch_geometry(c));
   CD_TRY(cd_launch_warm_start(c));
-  CD_TRY(hipEventRecord(c->ev[1], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[1], c->stream));
   // ---- partition (Sec. 3.2)
   if (!c->have_tree || c->step % c->p.repartition_every == 0) {
     CD_TRY(cd_launch_orb(c));
@@ -837,7 +837,7 @@ int prep_phase1(cd_ctx* c) {
   } else {
     CD_TRY(cd_launch_descend(c));
   }
-  CD_TRY(hipEventRecord(c->ev[2], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[2], c->stream));
   // ---- order
   CD_TRY(cd_launch_order(c));
   CD_TRY(hipMemcpyAsync(c->h_scratch, c->d_stats, sizeof(DomainStats), hipMemcpyDeviceToHost,
@@ -907,7 +907,7 @@ int prep_phase2(cd_ctx* c) {
       c->gscr_cap = need;
     }
   }
-  CD_TRY(hipEventRecord(c->ev[3], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[3], c->stream));
   // ---- iterative solve: set-up
   c->st_ds = ds;
   c->st_limit = c->p.fixed_iters > 0 ? c->p.fixed_iters : c->p.max_iter;
@@ -1112,11 +1112,11 @@ int solve_single(cd_ctx* c) {
 int finish_enqueue(cd_ctx* c) {
   SolveState s;
   memcpy(&s, c->h_state, sizeof(SolveState));
-  CD_TRY(hipEventRecord(c->ev[4], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[4], c->stream));
   // ---- Euler update and canonical forces
   CD_TRY(cd_launch_unslot(c, s.iter));
   CD_TRY(cd_launch_update(c, s.iter));
-  CD_TRY(hipEventRecord(c->ev[5], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[5], c->stream));
   CD_TRY(cd_launch_count_active(c, c->d_active));
   CD_TRY(hipMemcpyAsync(c->h_scratch + kSlideSlot, c->d_active, 2 * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, c->stream));
@@ -1168,11 +1168,13 @@ static int collect_result(cd_ctx* c, cd_result* out) {
   }
   c->last = res;
   cd_timing tm{};
-  tm.detect_ms = elapsed(c->ev[0], c->ev[1]);
-  tm.partition_ms = elapsed(c->ev[1], c->ev[2]);
-  tm.order_ms = elapsed(c->ev[2], c->ev[3]);
-  tm.solve_ms = elapsed(c->ev[3], c->ev[4]);
-  tm.update_ms = elapsed(c->ev[4], c->ev[5]);
+  if (c->phase_events) {
+    tm.detect_ms = elapsed(c->ev[0], c->ev[1]);
+    tm.partition_ms = elapsed(c->ev[1], c->ev[2]);
+    tm.order_ms = elapsed(c->ev[2], c->ev[3]);
+    tm.solve_ms = elapsed(c->ev[3], c->ev[4]);
+    tm.update_ms = elapsed(c->ev[4], c->ev[5]);
+  }
   tm.sweep_launches = launched;
   tm.block_threads = c->sweep_block;
   double sk = 0.0;
@@ -1597,7 +1599,7 @@ int cd_solve_contacts(cd_ctx* c, int64_t n_c, const int32_t* ci, const int32_t* 
   c->prepared = false;
   c->adj_valid = false;
   c->frozen_ready = false;
-  CD_TRY(hipEventRecord(c->ev[0], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[0], c->stream));
   // ---- the caller's list becomes the context's current list
   int st = ensure_capacity(c, n_c);
   if (st != CD_OK) return st;
@@ -1629,13 +1631,13 @@ int cd_solve_contacts(cd_ctx* c, int64_t n_c, const int32_t* ci, const int32_t* 
     }
   }
   CD_TRY(cd_launch_geometry(c));
-  CD_TRY(hipEventRecord(c->ev[1], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[1], c->stream));
   // ---- partition (Sec. 3.2) unless given
   if (!dom) {
     CD_TRY(cd_launch_orb(c));
     c->have_tree = true;
   }
-  CD_TRY(hipEventRecord(c->ev[2], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[2], c->stream));
   // ---- order: colour-major first fit, or the caller's order by levels
   c->given_order = order;
   hipError_t oe = cd_launch_order(c);
@@ -1656,9 +1658,9 @@ int cd_solve_contacts(cd_ctx* c, int64_t n_c, const int32_t* ci, const int32_t* 
   // ---- forces back in canonical order
   SolveState s;
   memcpy(&s, c->h_state, sizeof(SolveState));
-  CD_TRY(hipEventRecord(c->ev[4], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[4], c->stream));
   CD_TRY(cd_launch_unslot(c, s.iter));
-  CD_TRY(hipEventRecord(c->ev[5], c->stream));
+  if (c->phase_events) CD_TRY(hipEventRecord(c->ev[5], c->stream));
   CD_TRY(cd_launch_count_active(c, c->d_active));
   CD_TRY(hipMemcpyAsync(c->h_scratch + kSlideSlot, c->d_active, 2 * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, c->stream));

@@ -335,6 +335,7 @@ struct cd_ctx {
   HostProg* h_prog = nullptr;      // mapped pinned (host address)
   HostProg* d_prog = nullptr;      // its device address
   int time_every = 1;              // sweep launches timed with events: every k-th (0: none)
+  bool phase_events = true;        // events around the step's phases (off while in a batch)
   BlockPartial* partial = nullptr;
   double* init_part = nullptr;     // chunk sums of |R| at the start of a solve (256)
   int partial_cap = 0;
