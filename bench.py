@@ -650,9 +650,9 @@ def main() -> int:
     if args.traffic_json is None:
         args.traffic_json = os.path.join(ROOT, "profiles", wl["traffic"])
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              f"(the path shards by subtrees of the bisection tree, see the design notes)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the solver "
+              f"runs on one GPU (over several it would shard by subtrees of the bisection "
+              f"tree, exchanging boundary forces after every sweep)", file=sys.stderr)
         return 2
 
     import torch
