@@ -134,3 +134,30 @@ def test_shadow_mode_self_test_reports_a_difference():
         s.step()
     assert err.value.code == binding.ESHADOW
     s.close()
+
+
+@pytest.mark.parametrize("P", [16, 64])
+def test_workgroup_width_does_not_change_results_3d(P):
+    """The same 3D steps with 64-, 128- and 256-thread domain workgroups
+    (different passes over the staged data and the foreign incidences, and
+    the shared LDS layout only from 128 threads on) are bitwise equal."""
+    binding = _binding()
+    pk = inputs.lattice_3d(16, 16, 12, 96, gravity=0.0, top_velocity=1e-3)
+    ref = None
+    for width in (64, 128, 256):
+        ctx = binding.Context(binding.make_params(3, pk.n_walls, mu=0.5, n_domains=P,
+                                                  repartition_every=2), pk, timing=0,
+                              block_threads=width)
+        states = []
+        for _ in range(3):
+            r = ctx.step()
+            states.append((r.iterations, r.status, _state(ctx)))
+        assert ctx.timing().block_threads == width
+        ctx.close()
+        if ref is None:
+            ref = states
+            continue
+        for (ia, sa_, a), (ib, sb_, b) in zip(ref, states):
+            assert (ia, sa_) == (ib, sb_), (P, width)
+            for k in a:
+                assert np.array_equal(a[k], b[k]), (P, width, k)
