@@ -829,7 +829,7 @@ def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, 
     maxiter_steps = 0
     executed = 0
     timed = 0
-    step_ms, solve_ms_steps = [], []
+    step_ms, solve_ms_steps, phase_ms = [], [], []
     t0 = time.perf_counter()
     for s in range(steps):
         r = ctx.step()
@@ -837,6 +837,7 @@ def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, 
         # device time of the step's stages (events on the library's stream)
         step_ms.append(tm.detect_ms + tm.partition_ms + tm.order_ms + tm.solve_ms + tm.update_ms)
         solve_ms_steps.append(tm.solve_ms)
+        phase_ms.append((tm.detect_ms, tm.partition_ms, tm.order_ms, tm.solve_ms, tm.update_ms))
         sweeps += r.iterations
         updates += r.iterations * r.n_contacts
         sweep_kernel_ms += tm.sweep_kernel_ms
@@ -883,6 +884,10 @@ def run_single(args, wl, pk, torch, binding, inputs, steps, warmup, time_every, 
         "solve_ms_per_step": solve_ms / steps,
         "median_step_ms": statistics.median(step_ms) if step_ms else None,
         "median_solve_ms": statistics.median(solve_ms_steps) if solve_ms_steps else None,
+        # medians over the timed steps of each stage's device time (events)
+        "median_phase_ms": ({name: statistics.median(p[k] for p in phase_ms) for k, name in
+                             enumerate(("detect", "partition", "order", "solve", "update"))}
+                            if phase_ms else None),
         "solve_contact_updates_per_s": updates / (solve_ms / 1e3) if solve_ms > 0 else None,
         "sweep_kernel_us": 1e6 * avg_sweep_s if avg_sweep_s > 0 else None,
         "contact_states_last_step": {"open": r.n_contacts - r.n_active,
