@@ -417,13 +417,13 @@ __global__ __launch_bounds__(kStats) void k_dom_stats(const int* ddesc, int P, i
   }
 }
 
-template <int DIM>
+template <int DIM, int SMALL>
 __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
   constexpr int REC = cd_rec(DIM);
-  __shared__ unsigned long long s_mask[kSmall];
-  __shared__ int s_la[kSmall], s_lb[kSmall];
-  __shared__ short s_col[kSmall], s_rank[kSmall];
-  __shared__ unsigned char s_par[kSmall];
+  __shared__ unsigned long long s_mask[SMALL];
+  __shared__ int s_la[SMALL], s_lb[SMALL];
+  __shared__ short s_col[SMALL], s_rank[SMALL];
+  __shared__ unsigned char s_par[SMALL];
   __shared__ int s_cnt[CD_MAX_COLORS];
   __shared__ int s_coloff[CD_MAX_COLORS + 1];
   __shared__ int s_ncol;
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(kBuild) void k_dom_build(BuildArgs a) {
     if (threadIdx.x == 0) atomicMax(&a.stats->overflow, 3);
     return;
   }
-  const bool small = nct <= kSmall && np <= kSmall;
+  const bool small = nct <= SMALL && np <= SMALL;
   for (int q = threadIdx.x; q < CD_MAX_COLORS; q += blockDim.x) s_cnt[q] = 0;
   // mixed update: colour 0 is reserved for the contacts updated in parallel
   const unsigned long long mask0 = a.par ? 1ull : 0ull;
@@ -957,10 +957,18 @@ hipError_t cd_launch_order(cd_ctx* c) {
   a.dncol = c->dncol;
   a.ddesc = c->ddesc;
   a.stats = c->d_stats;
-  if (c->dim == 2)
-    hipLaunchKernelGGL(k_dom_build<2>, dim3(P), dim3(kBuild), 0, c->stream, a);
-  else
-    hipLaunchKernelGGL(k_dom_build<3>, dim3(P), dim3(kBuild), 0, c->stream, a);
+  // domains that fit colour in LDS; when they average at most 96 contacts
+  // and particles the LDS arrays hold 128 of each (2.8 KB instead of 11 KB,
+  // so that some 30 workgroups share a CU instead of 14), a larger domain
+  // then takes the global-memory colouring, which gives the same colours
+  const bool few = nc <= (int64_t)96 * P && n <= (int64_t)96 * P;
+  if (c->dim == 2) {
+    if (few) hipLaunchKernelGGL((k_dom_build<2, 128>), dim3(P), dim3(kBuild), 0, c->stream, a);
+    else hipLaunchKernelGGL((k_dom_build<2, kSmall>), dim3(P), dim3(kBuild), 0, c->stream, a);
+  } else {
+    if (few) hipLaunchKernelGGL((k_dom_build<3, 128>), dim3(P), dim3(kBuild), 0, c->stream, a);
+    else hipLaunchKernelGGL((k_dom_build<3, kSmall>), dim3(P), dim3(kBuild), 0, c->stream, a);
+  }
   hipLaunchKernelGGL(k_dom_stats, dim3(1), dim3(kStats), 0, c->stream, c->ddesc, P,
                      cd_stage_particle(c->dim), c->d_stats);
   e = hipGetLastError();
