@@ -368,6 +368,7 @@ int cd_create(cd_ctx** out, const cd_params* params, int64_t n_particles,
   alloci(&c->wall_cnt, CD_MAX_WALLS);
   alloci(&c->cell_of, n);
   alloci(&c->cell_members, n);
+  alloc(&c->cell_xr, (c->dim + 1) * n);
   alloci(&c->pair_count, n + 1);
   alloci(&c->pair_off, n + 1);
   alloci(&c->inc_count, n + 1);
@@ -443,7 +444,7 @@ int cd_destroy(cd_ctx* c) {
   double** dbl[] = {&c->x, &c->v, &c->w, &c->r, &c->m, &c->I, &c->f, &c->t, &c->inv_m,
                     &c->inv_I, &c->dtim, &c->dtii, &c->d_wall, &c->nrm, &c->gap, &c->xmid,
                     &c->R, &c->R_prev, &c->d_cut, &c->d_region, &c->geo, &c->rec[0],
-                    &c->rec[1]};
+                    &c->rec[1], &c->cell_xr};
   for (auto p : dbl) release(p);
   int** ints[] = {&c->cell_of, &c->cell_count, &c->cell_start, &c->cell_members,
                   &c->pair_count, &c->pair_off, &c->ci, &c->cj, &c->dom, &c->color,

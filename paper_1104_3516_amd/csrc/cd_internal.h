@@ -225,6 +225,7 @@ struct cd_ctx {
   double cwidth[3] = {1, 1, 1};
   int64_t ncells = 0, cells_cap = 0;
   int *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_members = nullptr;
+  double* cell_xr = nullptr;   // positions and radii in cell order ((dim + 1) x N), pair search
 
   // contacts (canonical)
   int64_t cap = 0, nc = 0;

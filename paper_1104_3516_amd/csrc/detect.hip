@@ -88,28 +88,37 @@ __global__ __launch_bounds__(kThreads) void k_cell_bin(const double* x, int64_t 
   atomicAdd(&cell_count[cell], 1);
 }
 
+// Each particle's place in its cell's member list, with a copy of its
+// position and radius at the same place (xr, (DIM + 1) x n), so that the
+// pair search reads its candidates' data in cell order, without going
+// through the member ids first.
+template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_cell_scatter(int64_t n, const int* cell_of,
                                                           const int* cell_start, int* cursor,
-                                                          int* members) {
+                                                          int* members, const double* x,
+                                                          const double* r, double* xr) {
   int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   int cell = cell_of[i];
   int pos = atomicAdd(&cursor[cell], 1);
-  members[cell_start[cell] + pos] = (int)i;
+  const int64_t s = cell_start[cell] + pos;
+  members[s] = (int)i;
+  for (int k = 0; k < DIM; ++k) xr[k * n + s] = x[k * n + i];
+  xr[DIM * n + s] = r[i];
 }
 
 // squared distance of particles i < j at the nearest image along periodic
 // axes; their gap (Sec. 2.1, Fig. 1) is its square root minus both radii
 template <int DIM>
-__device__ inline double pair_dist2(const double* x, int64_t n, int i, int j, const CellGrid& g) {
-  double d0 = x[j] - x[i];
+__device__ inline double pair_dist2(const double* xi, const double* xj, const CellGrid& g) {
+  double d0 = xj[0] - xi[0];
   if (g.period[0] > 0.0) d0 = min_image(d0, g.period[0]);
-  double d1 = x[n + j] - x[n + i];
+  double d1 = xj[1] - xi[1];
   if (g.period[1] > 0.0) d1 = min_image(d1, g.period[1]);
   double d2 = d0 * d0;
   d2 = d2 + d1 * d1;
   if (DIM == 3) {
-    double e = x[2 * n + j] - x[2 * n + i];
+    double e = xj[2] - xi[2];
     if (g.period[2] > 0.0) e = min_image(e, g.period[2]);
     d2 = d2 + e * e;
   }
@@ -146,13 +155,16 @@ template <int DIM, bool FILL>
 __global__ __launch_bounds__(kThreads) void k_pairs(const double* x, const double* r, int64_t n,
                                                    CellGrid g, const int* cell_of,
                                                    const int* cell_start, const int* members,
-                                                   const double* wall, int W, SkinArgs sk,
-                                                   int* count, const int* off, int* ci, int* cj) {
+                                                   const double* xr, const double* wall, int W,
+                                                   SkinArgs sk, int* count, const int* off,
+                                                   int* ci, int* cj) {
   int64_t ii = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (ii >= n) return;
   const double skin = skin_of(sk);
   int i = (int)ii;
   const double ri = r[i];
+  double xi[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < DIM; ++k) xi[k] = x[k * n + i];
   int cell = cell_of[i];
   int cx = cell % g.ncell[0];
   int cy = (cell / g.ncell[0]) % g.ncell[1];
@@ -175,15 +187,20 @@ __global__ __launch_bounds__(kThreads) void k_pairs(const double* x, const doubl
         if (qx < 0 || qx >= g.ncell[0]) continue;
         int q = (qz * g.ncell[1] + qy) * g.ncell[0] + qx;
         for (int s = cell_start[q]; s < cell_start[q + 1]; ++s) {
+          // the candidate's position and radius in cell order (the same
+          // values as x[j], r[j])
+          double xj[3] = {0.0, 0.0, 0.0};
+          for (int k = 0; k < DIM; ++k) xj[k] = xr[k * n + s];
+          const double rj = xr[DIM * n + s];
           int j = members[s];
           if (j <= i) continue;
           // a pair whose squared distance exceeds (r_i + r_j + skin)^2 by a
           // relative margin of 2e-9 cannot pass the test below, whatever the
           // rounding (its errors are some 1e-15 relative): no square root
-          const double d2 = pair_dist2<DIM>(x, n, i, j, g);
-          const double reach = ((ri + r[j]) + skin) * (1.0 + 1e-9);
+          const double d2 = pair_dist2<DIM>(xi, xj, g);
+          const double reach = ((ri + rj) + skin) * (1.0 + 1e-9);
           if (d2 > reach * reach) continue;
-          if ((sqrt(d2) - ri) - r[j] <= skin) {
+          if ((sqrt(d2) - ri) - rj <= skin) {
             if (FILL) {
               // insertion into the particle's sorted range
               int pos = k;
@@ -312,8 +329,14 @@ hipError_t cd_launch_cells(cd_ctx* c) {
   // reuse cell_count as the scatter cursor
   e = hipMemsetAsync(c->cell_count, 0, sizeof(int) * (size_t)(c->ncells + 1), c->stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cell_scatter, dim3(nb), dim3(kThreads), 0, c->stream, c->n, c->cell_of,
-                     c->cell_start, c->cell_count, c->cell_members);
+  if (c->dim == 2)
+    hipLaunchKernelGGL(k_cell_scatter<2>, dim3(nb), dim3(kThreads), 0, c->stream, c->n,
+                       c->cell_of, c->cell_start, c->cell_count, c->cell_members, c->x, c->r,
+                       c->cell_xr);
+  else
+    hipLaunchKernelGGL(k_cell_scatter<3>, dim3(nb), dim3(kThreads), 0, c->stream, c->n,
+                       c->cell_of, c->cell_start, c->cell_count, c->cell_members, c->x, c->r,
+                       c->cell_xr);
   return hipGetLastError();
 }
 
@@ -323,11 +346,13 @@ hipError_t cd_launch_pair_count(cd_ctx* c) {
   int nb = cd_blocks(c->n, kThreads);
   if (c->dim == 2)
     hipLaunchKernelGGL((k_pairs<2, false>), dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->r,
-                       c->n, g, c->cell_of, c->cell_start, c->cell_members, c->d_wall, c->W, skin,
+                       c->n, g, c->cell_of, c->cell_start, c->cell_members, c->cell_xr, c->d_wall, c->W,
+                       skin,
                        c->pair_count, nullptr, nullptr, nullptr);
   else
     hipLaunchKernelGGL((k_pairs<3, false>), dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->r,
-                       c->n, g, c->cell_of, c->cell_start, c->cell_members, c->d_wall, c->W, skin,
+                       c->n, g, c->cell_of, c->cell_start, c->cell_members, c->cell_xr, c->d_wall, c->W,
+                       skin,
                        c->pair_count, nullptr, nullptr, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -340,11 +365,13 @@ hipError_t cd_launch_pair_fill(cd_ctx* c) {
   int nb = cd_blocks(c->n, kThreads);
   if (c->dim == 2)
     hipLaunchKernelGGL((k_pairs<2, true>), dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->r,
-                       c->n, g, c->cell_of, c->cell_start, c->cell_members, c->d_wall, c->W, skin,
+                       c->n, g, c->cell_of, c->cell_start, c->cell_members, c->cell_xr, c->d_wall, c->W,
+                       skin,
                        nullptr, c->pair_off, c->ci, c->cj);
   else
     hipLaunchKernelGGL((k_pairs<3, true>), dim3(nb), dim3(kThreads), 0, c->stream, c->x, c->r,
-                       c->n, g, c->cell_of, c->cell_start, c->cell_members, c->d_wall, c->W, skin,
+                       c->n, g, c->cell_of, c->cell_start, c->cell_members, c->cell_xr, c->d_wall, c->W,
+                       skin,
                        nullptr, c->pair_off, c->ci, c->cj);
   return hipGetLastError();
 }
